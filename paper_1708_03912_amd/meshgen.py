@@ -1,0 +1,271 @@
+"""Seeded synthetic meshes shaped like the paper's workloads.
+
+This module only builds inputs: vertex coordinates, cells and boundary
+facets.  It holds none of the method's arithmetic and is the one module
+shared by the library's tests/benchmark and the oracle's tests.
+
+Shapes (Sec. 7 of arXiv:1708.03912 uses the interval (-1,1), the unit disk
+and an L-shaped domain; its adaptively refined meshes exist only as figures,
+so seeded stand-ins are generated here):
+
+* ``interval(N)``       -- uniform mesh of (-1,1) with N cells.
+* ``disk(h, seed)``     -- unit disk: equispaced points on the circle, a
+                           jittered hexagonal lattice inside, Delaunay.
+* ``lshape(...)``       -- (-1,1)^2 minus [0,1)x(-1,0]: newest-vertex
+                           bisection (conforming, no hanging nodes) graded
+                           geometrically toward the re-entrant corner and the
+                           boundary, size ratio up to 1:64.
+* ``square3(N)``        -- structured three-direction mesh of (-1,1)^2.
+
+Every mesh is a dict with ``dim``, ``verts`` (nv x dim float64), ``cells``
+(nc x (dim+1) int32) and ``bfacets`` (nb x dim int32).  Vertices and cells
+are sorted along a Morton curve so that neighbouring indices are
+neighbouring in space.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _morton_key(xy: np.ndarray, bits: int = 16) -> np.ndarray:
+    lo = xy.min(axis=0)
+    span = max(float((xy.max(axis=0) - lo).max()), 1e-300)
+    q = np.floor((xy - lo) / span * ((1 << bits) - 1)).astype(np.uint64)
+    key = np.zeros(len(xy), dtype=np.uint64)
+    for b in range(bits):
+        for d in range(xy.shape[1]):
+            key |= ((q[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(xy.shape[1] * b + d)
+    return key
+
+
+def _finish(dim, verts, cells, bfacets, sort=True):
+    verts = np.asarray(verts, dtype=np.float64).reshape(-1, dim)
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, dim + 1)
+    bfacets = np.asarray(bfacets, dtype=np.int64).reshape(-1, dim)
+    if sort and dim == 2:
+        perm = np.argsort(_morton_key(verts), kind="stable")
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(len(perm))
+        verts = verts[perm]
+        cells = inv[cells]
+        bfacets = inv[bfacets]
+        cen = verts[cells].mean(axis=1)
+        cells = cells[np.argsort(_morton_key(cen), kind="stable")]
+        # counter-clockwise orientation
+        a, b, c = verts[cells[:, 0]], verts[cells[:, 1]], verts[cells[:, 2]]
+        det = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
+        neg = det < 0
+        cells[neg] = cells[neg][:, [0, 2, 1]]
+        bfacets = bfacets[np.lexsort((bfacets[:, 1], bfacets[:, 0]))]
+    return {"dim": dim, "verts": np.ascontiguousarray(verts),
+            "cells": np.ascontiguousarray(cells, dtype=np.int32),
+            "bfacets": np.ascontiguousarray(bfacets, dtype=np.int32)}
+
+
+def interval(N: int, a: float = -1.0, b: float = 1.0):
+    """Uniform mesh of (a,b) with N cells; boundary facets are the endpoints."""
+    if a == -1.0 and b == 1.0 and (N & (N - 1)) == 0:
+        x = -1.0 + np.arange(N + 1) * (2.0 / N)  # exact in binary
+    else:
+        x = np.linspace(a, b, N + 1)
+    cells = np.stack([np.arange(N), np.arange(1, N + 1)], axis=1)
+    return _finish(1, x[:, None], cells, [[0], [N]], sort=False)
+
+
+def interval_graded(N: int, mu: float = 2.0):
+    """Mesh of (-1,1) graded symmetrically toward both endpoints:
+    x_i = -1 + (i/M)^mu on the left half (N = 2M cells)."""
+    M = N // 2
+    t = (np.arange(M + 1) / M) ** mu
+    x = np.concatenate([-1.0 + t, (1.0 - t[::-1])[1:]])
+    cells = np.stack([np.arange(2 * M), np.arange(1, 2 * M + 1)], axis=1)
+    return _finish(1, x[:, None], cells, [[0], [2 * M]], sort=False)
+
+
+def _boundary_edges(cells):
+    from collections import Counter
+    cnt = Counter()
+    for c in cells:
+        for i in range(3):
+            e = tuple(sorted((int(c[i]), int(c[(i + 1) % 3]))))
+            cnt[e] += 1
+    return [e for e, k in cnt.items() if k == 1]
+
+
+def disk(h: float, seed: int = 2, jitter: float = 0.15):
+    """Quasi-uniform mesh of the unit disk.  N_b = round(2 pi / h) points on
+    the circle; interior hexagonal lattice of spacing h clipped to
+    r < 1 - 0.7 h, each point shifted by U(-jitter h, jitter h)^2 drawn from
+    numpy.random.default_rng(seed); Delaunay triangulation (scipy), whose
+    hull is the inscribed polygon."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    nb = int(round(2 * math.pi / h))
+    th = 2 * math.pi * np.arange(nb) / nb
+    bpts = np.stack([np.cos(th), np.sin(th)], axis=1)
+    ny = int(math.ceil(1.0 / (h * math.sqrt(3) / 2))) + 1
+    pts = []
+    for j in range(-ny, ny + 1):
+        y = j * h * math.sqrt(3) / 2
+        off = 0.5 * h if (j % 2) else 0.0
+        nx = int(math.ceil(1.0 / h)) + 1
+        xs = np.arange(-nx, nx + 1) * h + off
+        pts.append(np.stack([xs, np.full_like(xs, y)], axis=1))
+    ipts = np.concatenate(pts)
+    ipts = ipts[np.hypot(ipts[:, 0], ipts[:, 1]) < 1.0 - 0.7 * h]
+    ipts = ipts + rng.uniform(-jitter * h, jitter * h, size=ipts.shape)
+    P = np.concatenate([bpts, ipts])
+    tri = Delaunay(P)
+    cells = tri.simplices
+    bf = _boundary_edges(cells)
+    return _finish(2, P, cells, bf)
+
+
+def disk_for_cells(T: int, seed: int = 2):
+    """Disk mesh with about T triangles (T ~ 7.25 / h^2)."""
+    return disk(math.sqrt(7.25 / T), seed=seed)
+
+
+def square3(N: int, a: float = -1.0, b: float = 1.0):
+    """Structured three-direction mesh of (a,b)^2: N x N squares, each cut
+    by its (lower-left, upper-right) diagonal."""
+    x = np.linspace(a, b, N + 1)
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    idx = lambda i, j: i * (N + 1) + j
+    cells = []
+    for i in range(N):
+        for j in range(N):
+            cells.append((idx(i, j), idx(i + 1, j), idx(i + 1, j + 1)))
+            cells.append((idx(i, j), idx(i + 1, j + 1), idx(i, j + 1)))
+    cells = np.array(cells)
+    bf = _boundary_edges(cells)
+    return _finish(2, verts, cells, bf, sort=False) | {"N": N}
+
+
+# ----------------------------------------------------------- L-shape NVB --
+
+def _nvb_refine(verts, tris, marked_fn, max_pass=200):
+    """Conforming newest-vertex bisection.  Each triangle (a,b,c) has its
+    refinement edge (b,c) opposite the newest vertex a.  A triangle is
+    bisected only together with the neighbour that shares its refinement
+    edge as that neighbour's refinement edge (recursively refining the
+    neighbour first), so no hanging nodes arise."""
+    verts = [tuple(v) for v in verts]
+    tris = {i: tuple(t) for i, t in enumerate(tris)}
+    nxt = len(tris)
+    edge = {}
+
+    def add(tid):
+        a, b, c = tris[tid]
+        for e in ((a, b), (b, c), (c, a)):
+            edge.setdefault(tuple(sorted(e)), set()).add(tid)
+
+    def rem(tid):
+        a, b, c = tris[tid]
+        for e in ((a, b), (b, c), (c, a)):
+            edge[tuple(sorted(e))].discard(tid)
+
+    for t in tris:
+        add(t)
+    mids = {}
+
+    def midpoint(b, c):
+        key = tuple(sorted((b, c)))
+        if key not in mids:
+            vb, vc = verts[b], verts[c]
+            verts.append(((vb[0] + vc[0]) / 2, (vb[1] + vc[1]) / 2))
+            mids[key] = len(verts) - 1
+        return mids[key]
+
+    def bisect(tid):
+        nonlocal nxt
+        a, b, c = tris[tid]
+        m = midpoint(b, c)
+        rem(tid)
+        del tris[tid]
+        t1, t2 = nxt, nxt + 1
+        nxt += 2
+        tris[t1] = (m, a, b)
+        tris[t2] = (m, c, a)
+        add(t1)
+        add(t2)
+
+    def refine(tid, depth=0):
+        if tid not in tris:
+            return
+        a, b, c = tris[tid]
+        key = tuple(sorted((b, c)))
+        nb = [t for t in edge.get(key, ()) if t != tid]
+        if nb:
+            n = nb[0]
+            na, nbv, ncv = tris[n]
+            if tuple(sorted((nbv, ncv))) != key:
+                refine(n, depth + 1)
+                nb = [t for t in edge.get(key, ()) if t != tid]
+                n = nb[0]
+            bisect(tid)
+            bisect(n)
+        else:
+            bisect(tid)
+
+    for _ in range(max_pass):
+        marked = [t for t, abc in tris.items() if marked_fn([verts[v] for v in abc])]
+        if not marked:
+            break
+        for t in marked:
+            refine(t)
+    return np.array(verts), np.array(list(tris.values()))
+
+
+def lshape(h_max: float = 0.1, gamma: float = 1.0, ratio: float = 64.0):
+    """L-shape (-1,1)^2 minus [0,1)x(-1,0], graded by newest-vertex
+    bisection: refine K while its longest edge exceeds
+    h_max * max(1/ratio, min(1, rho(c_K)^gamma)), rho = distance of the
+    centroid to the re-entrant corner or the boundary, whichever is
+    smaller.  Deterministic (no random numbers)."""
+    V = [(-1, -1), (0, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
+    # three unit squares, cut along diagonals through the corner (0,0);
+    # (newest vertex, refinement edge) = (right-angle corner, hypotenuse)
+    T = [(1, 0, 3), (2, 3, 0),      # [-1,0]x[-1,0], diagonal (-1,-1)-(0,0)
+         (2, 3, 5), (6, 5, 3),      # [-1,0]x[0,1],  diagonal (-1,1)-(0,0)
+         (4, 3, 7), (6, 7, 3)]      # [0,1]x[0,1],   diagonal (0,0)-(1,1)
+
+    def dist_boundary(x, y):
+        # distance to the boundary of the L-shape (inside points)
+        d = min(1 + x, 1 - x, 1 + y, 1 - y)
+        if x >= 0 and y <= 0:
+            return 0.0
+        if x >= 0:  # upper right square: edge y = 0 for x in [0,1]
+            d = min(d, y)
+        if y <= 0:  # lower left square: edge x = 0 for y in [-1,0]
+            d = min(d, -x)
+        return max(d, 0.0)
+
+    def marked(P):
+        cx = sum(p[0] for p in P) / 3
+        cy = sum(p[1] for p in P) / 3
+        rho = min(math.hypot(cx, cy), dist_boundary(cx, cy))
+        target = h_max * max(1.0 / ratio, min(1.0, rho ** gamma))
+        hk = max(math.dist(P[i], P[(i + 1) % 3]) for i in range(3))
+        return hk > target * 1.0000001
+
+    verts, tris = _nvb_refine(V, T, marked)
+    bf = _boundary_edges(tris)
+    return _finish(2, verts, tris, bf)
+
+
+def tiny(kind: str):
+    """Small meshes for brute-force checks."""
+    if kind == "one":
+        return _finish(2, [(0, 0), (1, 0), (0.2, 0.9)], [(0, 1, 2)], [(0, 1), (1, 2), (0, 2)], sort=False)
+    if kind == "two":
+        v = [(0, 0), (1, 0), (0.3, 0.8), (1.1, 0.9)]
+        return _finish(2, v, [(0, 1, 2), (1, 3, 2)], [(0, 1), (1, 3), (2, 3), (0, 2)], sort=False)
+    if kind == "four":
+        v = [(0, 0), (1, 0), (1, 1), (0, 1), (0.45, 0.55)]
+        c = [(0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)]
+        return _finish(2, v, c, [(0, 1), (1, 2), (2, 3), (0, 3)], sort=False)
+    raise ValueError(kind)
