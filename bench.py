@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the dense fractional-Laplacian hot path on one MI355X.
+
+Workload (unit disk, the paper's 2D test domain, Sec. 7): seeded jittered
+Delaunay mesh with ~7.9k triangles (~4k DOFs), s in {0.25, 0.75}, f = 1.
+One step = for each s: mesh ingest (fl_set_mesh), FP64 assembly of A^s
+(all element pairs and element/boundary-facet pairs), load vector,
+Jacobi-PCG to ||r|| <= 1e-12 ||b||, energy-norm error against the closed-form
+solution.  Everything runs in libfraclap.so; inputs are resident before the
+timed region.
+
+Prints ONE JSON line (rank 0, N = 1).  Metric: element-pair quadratures per
+second over the whole step (pairs = T(T+1)/2 element pairs + T*B
+element/facet pairs per assembly), plus the dense matvec bandwidth, the
+roofline of the dominant kernel and the CPU oracle baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-pair quadratures/s & matvec GB/s; mixed+surrogate vs FP64 at equal err"
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic FP64 work per kernel evaluation |x-y|^{-2-2s} on the separated
+# path: r^2 from the two mapped points (14 flops incl. 4 FMAs of the maps),
+# 10 FMAs of accumulation (20 flops), and a pow = log2 + multiply + exp2,
+# counted at 21 flops each for log2 / exp2 (degree-~9 polynomial + reduction)
+# and 1 for the multiply.
+FLOPS_PER_EVAL = 14 + 20 + 21 + 1 + 21
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=8000, help="target triangle count of the disk mesh")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the dense path's multi-GPU "
+              "row sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+
+    dev = 0
+    torch.cuda.set_device(dev)
+    mesh = M.disk_for_cells(args.cells, seed=2)
+    T, B = len(mesh["cells"]), len(mesh["bfacets"])
+    svals = (0.25, 0.75)
+    opts = F.default_opts()
+    handles = {s: F.Handle(dev) for s in svals}
+    stream = torch.cuda.current_stream(dev)
+    bufs = {}
+    fu = {s: None for s in svals}
+
+    def ball_fu(s):
+        # (f,u) for f = 1 on the unit disk: c pi/(s+1), c = 2^{-2s}/(Gamma(1+s)^2)
+        c = 2.0 ** (-2 * s) * math.gamma(1.0) / (math.gamma(1 + s) * math.gamma(1 + s))
+        return c * math.pi / (s + 1.0)
+
+    result = {}
+
+    def step():
+        for s in svals:
+            h = handles[s]
+            h.set_mesh(mesh)
+            n = h.assemble(s, opts)
+            if s not in bufs or bufs[s][0].numel() != n:
+                bufs[s] = (torch.empty(n, dtype=torch.float64, device="cuda"),
+                           torch.empty(n, dtype=torch.float64, device="cuda"))
+            b, u = bufs[s]
+            h.load_vector_one(b)
+            it, rel, rc = h.solve(b, u, rtol=1e-12, maxit=20000)
+            e2 = h.energy_error2(ball_fu(s), b, u)
+            st = h.stats()
+            result[s] = dict(n=n, iters=it, relres=rel, e2=e2, t_asm=st.t_assemble_ms, t_far=st.t_far_ms,
+                             t_self=st.t_self_ms, t_touch=st.t_touch_ms, t_scatter=st.t_scatter_ms,
+                             t_solve=st.t_solve_ms, evals=st.kernel_evals,
+                             far_pairs=list(st.pairs_far)[:opts.n_classes + 1],
+                             far_evals=sum(st.pairs_far[m] * (opts.k_far[m] ** 2) ** 2
+                                           for m in range(opts.n_classes + 1)))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    far_ms, solve_ms, asm_ms = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        far_ms.append(sum(result[s]["t_far"] for s in svals))
+        asm_ms.append(sum(result[s]["t_asm"] for s in svals))
+        solve_ms.append(sum(result[s]["t_solve"] for s in svals))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs_per_step = len(svals) * (T * (T + 1) // 2 + T * B)
+    value = pairs_per_step / (ms_per_step * 1e-3)
+
+    # dense FP64 matvec bandwidth (A resident, timed with events on the
+    # library's stream = torch's current stream)
+    s_mv = 0.75
+    h = handles[s_mv]
+    n = h.n
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        h.matvec(x, y)
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        h.matvec(x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / reps
+    mv_bytes = n * n * 8 + 2 * n * 8
+    mv_gbps = mv_bytes / (mv_ms * 1e-3) / 1e9
+
+    # far-field kernel roofline (plain FP64 ALU work)
+    far_evals = sum(result[s]["far_evals"] for s in svals)
+    far_time = sum(far_ms) / len(far_ms) * 1e-3  # both s per step
+    far_tflops = far_evals * FLOPS_PER_EVAL / far_time / 1e12
+    solve_time = sum(solve_ms) / len(solve_ms)
+    asm_time = sum(asm_ms) / len(asm_ms)
+    iters = sum(result[s]["iters"] for s in svals)
+    rf_far = {"kernel": "far_kernel<2> (separated element pairs)", "bound": "alu",
+              "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+              "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,
+              "per_launch_ms": round(far_time * 1e3 / len(svals), 4),
+              "evals_per_launch": far_evals // len(svals), "flops_per_eval": FLOPS_PER_EVAL}
+    rf_mv = {"kernel": "matvec / cg_matvec (dense FP64 GEMV)", "bound": "hbm",
+             "achieved": round(mv_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+             "frac": round(mv_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+             "per_launch_ms": round(mv_ms, 5), "bytes_per_launch": mv_bytes,
+             "note": "A is %.0f MB, below the 256 MB Infinity Cache: cache-resident rate" % (n * n * 8 / 1e6)}
+    # dominant: the far kernel's total time vs the CG matvec time (iterations x matvec)
+    mv_total = iters * mv_ms
+    far_total = far_time * 1e3
+    roof = rf_far if far_total >= mv_total else rf_mv
+    other = rf_mv if roof is rf_far else rf_far
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "element-pair quadratures/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"d=2 unit disk, seeded jittered-Delaunay quasi-uniform mesh T={T} "
+                                  f"B={B}, s in {{0.25,0.75}}, f=1: FP64 assembly + Jacobi-PCG to 1e-12 + "
+                                  f"energy error",
+                      "cells": T, "bfacets": B, "n_dofs": {str(s): result[s]["n"] for s in svals},
+                      "s": list(svals), "orders": "k_touch=6 theta=(1.5,3,6) k_far=(4,3,2,2)"},
+           "matvec_GBps": round(mv_gbps, 1),
+           "assemble_ms": round(asm_time, 3), "solve_ms": round(solve_time, 3),
+           "cg_iters": {str(s): result[s]["iters"] for s in svals},
+           "energy_error": {str(s): math.sqrt(max(result[s]["e2"], 0.0)) for s in svals},
+           "phase_ms": {str(s): {k: round(result[s][k], 4) for k in ("t_far", "t_self", "t_touch", "t_scatter")}
+                        for s in svals},
+           "roofline": roof, "roofline_other": other}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
+    print(json.dumps(out), flush=True)
+    for hh in handles.values():
+        hh.close()
+
+
+def cpu_baseline(mesh, svals, pairs_per_step):
+    """The oracle as it stands (plain C + numpy, FP64) on the host cores,
+    timed on one full step of the same workload."""
+    import numpy as np
+    from oracle import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(cores)
+    O.lib()
+    t0 = time.perf_counter()
+    for s in svals:
+        A, dofs, _ = O.assemble(mesh, s, O.Orders())
+        b = O.load_vector_one(mesh, dofs)
+        u, it, rel = O.pcg(A, b, rtol=1e-12)
+        O.energy_error(O.ball_fu(2, s), b, u, A)
+    dt = time.perf_counter() - t0
+    return {"value": round(pairs_per_step / dt, 1), "unit": "element-pair quadratures/s", "cores": cores,
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": "one full step of the same workload (both s: assembly + Jacobi-PCG + energy error)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,845 @@
+// Host side of the C ABI in include/fraclap.h: mesh validation, DOF map
+// (Sec. 3), element-pair planning (Sec. 5 decomposition into identical /
+// common-edge / common-vertex / separated pairs and element/facet pairs),
+// quadrature tables (App. B orders), device buffers and kernel launches.
+//
+// Compiled with -ffp-contract=off: the centroids, squared diameters and
+// facet data computed here feed the per-pair order classes, which must be
+// reproducible bit for bit from the same formulas.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "fl_internal.hpp"
+#include "fl_quad.hpp"
+
+using namespace fl;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct fl_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // mesh (host copy)
+    int dim = 0;
+    int64_t nv = 0, nc = 0, nb = 0;
+    std::vector<double> verts;
+    std::vector<int32_t> cells, bfacets;
+    std::vector<int32_t> facet_owner;   // cell owning each boundary facet
+    std::vector<int32_t> facet_opp;     // vertex of the owner opposite the facet
+    std::vector<char> on_boundary;
+
+    // assembly
+    bool assembled = false;
+    double s = 0.0;
+    fl_opts opts{};
+    int64_t n = 0, lda = 0;
+    std::vector<int32_t> dof_node, node2dof;
+    double* dA = nullptr;
+
+    // device buffers that live with the assembly
+    std::vector<void*> owned;
+    ElemDev E{};
+    int* d_v2c_ptr = nullptr;
+    int* d_v2c_idx = nullptr;
+    int* d_node2dof = nullptr;
+    int* d_dof_node = nullptr;
+    double* d_meas = nullptr;
+
+    // solver workspace
+    double* w = nullptr;   // r, z, p, q, d, tmp (6 n)
+    double* w_part = nullptr;
+    double* w_scal = nullptr;
+    int* w_flag = nullptr;
+    int64_t w_n = -1;
+
+    fl_stats_t st{};
+};
+
+namespace {
+
+int fail(fl_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(h, FL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void free_assembly(fl_handle* h) {
+    for (void* p : h->owned) (void)hipFree(p);
+    h->owned.clear();
+    if (h->dA) (void)hipFree(h->dA);
+    h->dA = nullptr;
+    h->assembled = false;
+    h->n = h->lda = 0;
+    h->E = ElemDev{};
+    h->d_v2c_ptr = h->d_v2c_idx = h->d_node2dof = h->d_dof_node = nullptr;
+    h->d_meas = nullptr;
+}
+
+void free_solver(fl_handle* h) {
+    if (h->w) (void)hipFree(h->w);
+    if (h->w_part) (void)hipFree(h->w_part);
+    if (h->w_scal) (void)hipFree(h->w_scal);
+    if (h->w_flag) (void)hipFree(h->w_flag);
+    h->w = h->w_part = h->w_scal = nullptr;
+    h->w_flag = nullptr;
+    h->w_n = -1;
+}
+
+template <class T>
+int upload(fl_handle* h, const std::vector<T>& v, T** out) {
+    *out = nullptr;
+    if (v.empty()) return FL_OK;
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, v.size() * sizeof(T)));
+    h->owned.push_back(p);
+    HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    *out = (T*)p;
+    return FL_OK;
+}
+
+int alloc_owned(fl_handle* h, size_t bytes, void** out) {
+    *out = nullptr;
+    if (bytes == 0) return FL_OK;
+    HIPCHK(hipMalloc(out, bytes));
+    h->owned.push_back(*out);
+    return FL_OK;
+}
+
+uint64_t morton2(double x, double y, double x0, double y0, double span) {
+    auto q = [&](double v, double lo) {
+        double t = (v - lo) / span;
+        if (t < 0) t = 0;
+        if (t > 1) t = 1;
+        return (uint64_t)(t * 65535.0);
+    };
+    uint64_t a = q(x, x0), b = q(y, y0), k = 0;
+    for (int i = 0; i < 16; ++i) k |= ((a >> i) & 1ull) << (2 * i) | ((b >> i) & 1ull) << (2 * i + 1);
+    return k;
+}
+
+int check_opts(fl_handle* h, const fl_opts& o) {
+    if (o.dof_mode != FL_DOF_PAPER && o.dof_mode != FL_DOF_INTERIOR)
+        return fail(h, FL_EINVAL, "dof_mode must be FL_DOF_PAPER or FL_DOF_INTERIOR");
+    if (o.n_classes < 0 || o.n_classes > FL_MAX_CLASSES)
+        return fail(h, FL_EINVAL, "n_classes out of range");
+    if (o.k_touch < 1 || o.k_touch > FL_MAX_ORDER_TOUCH || o.k_touch_bnd < 1 ||
+        o.k_touch_bnd > FL_MAX_ORDER_TOUCH)
+        return fail(h, FL_EINVAL, "touching orders must lie in 1..16");
+    for (int m = 0; m <= o.n_classes; ++m)
+        if (o.k_far[m] < 1 || o.k_far[m] > FL_MAX_ORDER_FAR || o.k_far_bnd[m] < 1 ||
+            o.k_far_bnd[m] > FL_MAX_ORDER_FAR)
+            return fail(h, FL_EINVAL, "separated-pair orders must lie in 1..8");
+    for (int m = 0; m < o.n_classes; ++m) {
+        if (!(o.theta[m] > 0.0) || !std::isfinite(o.theta[m]))
+            return fail(h, FL_EINVAL, "theta must be positive and finite");
+        if (m > 0 && !(o.theta[m] > o.theta[m - 1]))
+            return fail(h, FL_EINVAL, "theta must be strictly increasing");
+    }
+    return FL_OK;
+}
+
+double cdn(int d, double s) {
+    return std::pow(2.0, 2.0 * s) * s * std::tgamma(s + 0.5 * d) /
+           (std::pow(M_PI, 0.5 * d) * std::tgamma(1.0 - s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int fl_default_opts(fl_opts* out) {
+    if (!out) return FL_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->dof_mode = FL_DOF_PAPER;
+    out->with_boundary = 1;
+    out->k_touch = 6;
+    out->k_touch_bnd = 6;
+    out->n_classes = 3;
+    out->theta[0] = 1.5;
+    out->theta[1] = 3.0;
+    out->theta[2] = 6.0;
+    const int kf[4] = {4, 3, 2, 2};
+    for (int m = 0; m < 4; ++m) out->k_far[m] = out->k_far_bnd[m] = kf[m];
+    return FL_OK;
+}
+
+int fl_create(fl_handle** out, int device, void* hip_stream) {
+    if (!out) return FL_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FL_EDEVICE;
+    if (device < 0 || device >= ndev) return FL_EINVAL;
+    fl_handle* h = new fl_handle();
+    h->device = device;
+    h->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return FL_EDEVICE;
+    }
+    *out = h;
+    return FL_OK;
+}
+
+void fl_destroy(fl_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    free_assembly(h);
+    free_solver(h);
+    delete h;
+}
+
+const char* fl_last_error(const fl_handle* h) {
+    if (!h) return "null handle";
+    return h->err.c_str();
+}
+
+int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t nc,
+                const int32_t* cells, int64_t nb, const int32_t* bfacets) {
+    if (!h) return FL_EINVAL;
+    if (dim != 1 && dim != 2) return fail(h, FL_EINVAL, "dim must be 1 or 2");
+    if (nv <= 0 || nc <= 0 || nb < 0 || !verts || !cells || (nb > 0 && !bfacets))
+        return fail(h, FL_EINVAL, "empty mesh or null array");
+    if (nc > (int64_t)1 << 30 || nv > (int64_t)1 << 30) return fail(h, FL_EINVAL, "mesh too large");
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_assembly(h);
+    const int nper = dim + 1;
+    for (int64_t i = 0; i < nv * dim; ++i)
+        if (!std::isfinite(verts[i])) return fail(h, FL_EMESH, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < nc * nper; ++i)
+        if (cells[i] < 0 || cells[i] >= nv) return fail(h, FL_EMESH, "cell vertex index out of range");
+    for (int64_t i = 0; i < nb * dim; ++i)
+        if (bfacets[i] < 0 || bfacets[i] >= nv) return fail(h, FL_EMESH, "facet vertex index out of range");
+    for (int64_t K = 0; K < nc; ++K) {
+        const int32_t* c = cells + nper * K;
+        double meas;
+        if (dim == 1) {
+            meas = std::fabs(verts[c[1]] - verts[c[0]]);
+        } else {
+            const double* a = verts + 2 * c[0];
+            const double* b = verts + 2 * c[1];
+            const double* d = verts + 2 * c[2];
+            meas = 0.5 * std::fabs((b[0] - a[0]) * (d[1] - a[1]) - (d[0] - a[0]) * (b[1] - a[1]));
+        }
+        if (!(meas > 0.0)) return fail(h, FL_EMESH, "degenerate cell " + std::to_string(K));
+    }
+    // facet -> owning cell
+    std::unordered_map<uint64_t, std::vector<std::pair<int32_t, int32_t>>> own;
+    auto key = [&](int32_t a, int32_t b) {
+        if (a > b) std::swap(a, b);
+        return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+    };
+    for (int64_t K = 0; K < nc; ++K) {
+        const int32_t* c = cells + nper * K;
+        if (dim == 1) {
+            own[key(c[0], c[0])].push_back({(int32_t)K, c[1]});
+            own[key(c[1], c[1])].push_back({(int32_t)K, c[0]});
+        } else {
+            for (int a = 0; a < 3; ++a)
+                own[key(c[(a + 1) % 3], c[(a + 2) % 3])].push_back({(int32_t)K, c[a]});
+        }
+    }
+    h->facet_owner.assign(nb, -1);
+    h->facet_opp.assign(nb, -1);
+    h->on_boundary.assign(nv, 0);
+    for (int64_t e = 0; e < nb; ++e) {
+        const int32_t* f = bfacets + dim * e;
+        uint64_t k = dim == 1 ? key(f[0], f[0]) : key(f[0], f[1]);
+        auto it = own.find(k);
+        if (it == own.end() || it->second.size() != 1)
+            return fail(h, FL_EMESH, "boundary facet " + std::to_string(e) + " does not lie on exactly one cell");
+        h->facet_owner[e] = it->second[0].first;
+        h->facet_opp[e] = it->second[0].second;
+        for (int a = 0; a < dim; ++a) h->on_boundary[f[a]] = 1;
+    }
+    h->dim = dim;
+    h->nv = nv;
+    h->nc = nc;
+    h->nb = nb;
+    h->verts.assign(verts, verts + nv * dim);
+    h->cells.assign(cells, cells + nc * nper);
+    h->bfacets.assign(bfacets, bfacets + nb * dim);
+    return FL_OK;
+}
+
+int64_t fl_matrix_ld(const fl_handle* h) { return (h && h->assembled) ? h->lda : 0; }
+
+const double* fl_matrix_ptr(const fl_handle* h) { return (h && h->assembled) ? h->dA : nullptr; }
+
+int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    if (!(s > 0.0 && s < 1.0)) return fail(h, FL_EINVAL, "s must lie in (0,1)");
+    fl_opts o;
+    if (opts_in) o = *opts_in;
+    else fl_default_opts(&o);
+    int rc = check_opts(h, o);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(h->device));
+    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
+    free_assembly(h);
+    free_solver(h);
+    auto t0 = std::chrono::steady_clock::now();
+
+    const int dim = h->dim, nper = dim + 1;
+    const int64_t T = h->nc, nv = h->nv;
+    // DOF map (Sec. 3): all nodes if s < 1/2 (paper rule), else interior
+    const bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s < 0.5);
+    h->node2dof.assign(nv, -1);
+    h->dof_node.clear();
+    for (int64_t v = 0; v < nv; ++v)
+        if (all_nodes || !h->on_boundary[v]) {
+            h->node2dof[v] = (int32_t)h->dof_node.size();
+            h->dof_node.push_back((int32_t)v);
+        }
+    const int64_t n = (int64_t)h->dof_node.size();
+    const int64_t lda = ((n + 31) / 32) * 32;
+    {
+        size_t freeb = 0, totb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totb));
+        double need = (double)n * (double)lda * 8.0 + (double)T * 200.0 + (double)nv * 64.0;
+        if (need > (double)freeb * 0.98)
+            return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
+    }
+
+    // internal element order: Morton order of centroids (2D), by x (1D)
+    std::vector<int32_t> perm(T);
+    for (int64_t K = 0; K < T; ++K) perm[K] = (int32_t)K;
+    {
+        std::vector<double> cx(T), cy(T, 0.0);
+        double lo0 = 1e300, lo1 = 1e300, hi0 = -1e300, hi1 = -1e300;
+        for (int64_t K = 0; K < T; ++K) {
+            const int32_t* c = &h->cells[nper * K];
+            double sx = 0, sy = 0;
+            for (int a = 0; a < nper; ++a) {
+                sx += h->verts[dim * c[a]];
+                if (dim == 2) sy += h->verts[dim * c[a] + 1];
+            }
+            cx[K] = sx / nper;
+            cy[K] = sy / nper;
+            lo0 = std::min(lo0, cx[K]); hi0 = std::max(hi0, cx[K]);
+            lo1 = std::min(lo1, cy[K]); hi1 = std::max(hi1, cy[K]);
+        }
+        if (dim == 2) {
+            double span = std::max(hi0 - lo0, hi1 - lo1);
+            if (!(span > 0)) span = 1;
+            std::vector<uint64_t> key(T);
+            for (int64_t K = 0; K < T; ++K) key[K] = morton2(cx[K], cy[K], lo0, lo1, span);
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        } else {
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return cx[a] < cx[b]; });
+        }
+    }
+    // element SoA in internal order
+    const int NC = nper * dim;
+    std::vector<std::vector<double>> X(NC, std::vector<double>(T));
+    std::vector<double> cen0(T), cen1(T, 0.0), h2(T), meas(T);
+    std::vector<std::vector<int>> vid(3, std::vector<int>(T, -1)), dof(3, std::vector<int>(T, -1));
+    for (int64_t Ki = 0; Ki < T; ++Ki) {
+        const int32_t* c = &h->cells[nper * perm[Ki]];
+        for (int a = 0; a < nper; ++a) {
+            vid[a][Ki] = c[a];
+            dof[a][Ki] = h->node2dof[c[a]];
+            for (int d = 0; d < dim; ++d) X[dim * a + d][Ki] = h->verts[dim * c[a] + d];
+        }
+        if (dim == 1) {
+            double x0 = X[0][Ki], x1 = X[1][Ki];
+            cen0[Ki] = (x0 + x1) / 2.0;
+            double e = x1 - x0;
+            h2[Ki] = e * e;
+            meas[Ki] = std::fabs(x1 - x0);
+        } else {
+            double ax = X[0][Ki], ay = X[1][Ki], bx = X[2][Ki], by = X[3][Ki], dx = X[4][Ki], dy = X[5][Ki];
+            cen0[Ki] = ((ax + bx) + dx) / 3.0;
+            cen1[Ki] = ((ay + by) + dy) / 3.0;
+            double P[3][2] = {{ax, ay}, {bx, by}, {dx, dy}};
+            double m = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                double e0 = P[(i + 1) % 3][0] - P[i][0], e1 = P[(i + 1) % 3][1] - P[i][1];
+                double l = e0 * e0 + e1 * e1;
+                if (l > m) m = l;
+            }
+            h2[Ki] = m;
+            meas[Ki] = 0.5 * std::fabs((bx - ax) * (dy - ay) - (dx - ax) * (by - ay));
+        }
+    }
+    // vertex -> internal elements (CSR) with the local index of the vertex
+    std::vector<int> v2c_ptr(nv + 1, 0), v2c_idx(T * nper);
+    std::vector<unsigned char> vloc(T * nper);
+    for (int64_t Ki = 0; Ki < T; ++Ki)
+        for (int a = 0; a < nper; ++a) v2c_ptr[vid[a][Ki] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) v2c_ptr[v + 1] += v2c_ptr[v];
+    {
+        std::vector<int> fill(v2c_ptr.begin(), v2c_ptr.end() - 1);
+        for (int64_t Ki = 0; Ki < T; ++Ki)
+            for (int a = 0; a < nper; ++a) {
+                int v = vid[a][Ki];
+                v2c_idx[fill[v]] = (int)Ki;
+                vloc[fill[v]] = (unsigned char)a;
+                fill[v]++;
+            }
+    }
+    // touching pairs (Sec. 5): K < Kt sharing dim vertices (common edge, 2D)
+    // or one vertex
+    std::vector<int> edge_pairs, vert_pairs;
+    {
+        std::vector<int> nb;
+        for (int64_t Ki = 0; Ki < T; ++Ki) {
+            nb.clear();
+            for (int a = 0; a < nper; ++a) {
+                int v = vid[a][Ki];
+                for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e)
+                    if (v2c_idx[e] > Ki) nb.push_back(v2c_idx[e]);
+            }
+            std::sort(nb.begin(), nb.end());
+            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+            for (int Kt : nb) {
+                int sh = 0;
+                for (int a = 0; a < nper; ++a)
+                    for (int b = 0; b < nper; ++b) sh += (vid[a][Ki] == vid[b][Kt]);
+                if (dim == 2 && sh == 2) { edge_pairs.push_back((int)Ki); edge_pairs.push_back(Kt); }
+                else if (sh == 1) { vert_pairs.push_back((int)Ki); vert_pairs.push_back(Kt); }
+                else if (sh >= nper) return fail(h, FL_EMESH, "duplicate cells");
+            }
+        }
+    }
+    // far-field tiles and per-block local DOF numbering
+    const int nblk = (int)((T + BE - 1) / BE);
+    std::vector<int2> tiles;
+    tiles.reserve((size_t)nblk * (nblk + 1) / 2);
+    for (int bi = 0; bi < nblk; ++bi)
+        for (int bj = bi; bj < nblk; ++bj) tiles.push_back(make_int2(bi, bj));
+    std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
+    std::vector<unsigned char> loc(T * 3, 255);
+    {
+        std::vector<int> ds;
+        for (int b = 0; b < nblk; ++b) {
+            ds.clear();
+            for (int64_t Ki = (int64_t)b * BE; Ki < std::min<int64_t>(T, (int64_t)(b + 1) * BE); ++Ki)
+                for (int a = 0; a < nper; ++a)
+                    if (dof[a][Ki] >= 0) ds.push_back(dof[a][Ki]);
+            std::sort(ds.begin(), ds.end());
+            ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+            blk_ndof[b] = (int)ds.size();
+            if ((int)ds.size() > MAXV) continue;  // tile falls back to global atomics
+            for (size_t i = 0; i < ds.size(); ++i) blk_dofs[(size_t)b * MAXV + i] = ds[i];
+            for (int64_t Ki = (int64_t)b * BE; Ki < std::min<int64_t>(T, (int64_t)(b + 1) * BE); ++Ki)
+                for (int a = 0; a < nper; ++a)
+                    if (dof[a][Ki] >= 0)
+                        loc[Ki * 3 + a] = (unsigned char)(std::lower_bound(ds.begin(), ds.end(), dof[a][Ki]) - ds.begin());
+        }
+    }
+    // boundary facets: coordinates, inward unit normal (Sec. 2)
+    std::vector<double> fac(h->nb * 6, 0.0);
+    std::vector<int> fvid(h->nb * 2, -1);
+    for (int64_t e = 0; e < h->nb; ++e) {
+        const int32_t* f = &h->bfacets[dim * e];
+        int opp = h->facet_opp[e];
+        if (dim == 1) {
+            double y = h->verts[f[0]], xo = h->verts[opp];
+            fac[6 * e] = y;
+            fac[6 * e + 4] = xo > y ? 1.0 : -1.0;
+            fvid[2 * e] = f[0];
+        } else {
+            double p0x = h->verts[2 * f[0]], p0y = h->verts[2 * f[0] + 1];
+            double p1x = h->verts[2 * f[1]], p1y = h->verts[2 * f[1] + 1];
+            double tx = p1x - p0x, ty = p1y - p0y;
+            double L = std::sqrt(tx * tx + ty * ty);
+            double nx = -ty / L, ny = tx / L;
+            double ox = h->verts[2 * opp] - p0x, oy = h->verts[2 * opp + 1] - p0y;
+            if (nx * ox + ny * oy < 0) { nx = -nx; ny = -ny; }
+            double* F = &fac[6 * e];
+            F[0] = p0x; F[1] = p0y; F[2] = p1x; F[3] = p1y; F[4] = nx; F[5] = ny;
+            fvid[2 * e] = f[0];
+            fvid[2 * e + 1] = f[1];
+        }
+    }
+    // quadrature tables
+    RuleTables R;
+    std::memset(&R, 0, sizeof(R));
+    for (int k = 1; k <= 16; ++k) {
+        gauss_jacobi01(k, 0.0, 0.0, R.gl_x + gl_off(k), R.gl_w + gl_off(k));
+        gauss_jacobi01(k, 1.0, 0.0, R.gj_x + gl_off(k), R.gj_w + gl_off(k));
+    }
+    for (int k = 1; k <= 8; ++k) {
+        int m = tri_off(k);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                double u = R.gj_x[gl_off(k) + i];
+                R.tl1[m] = u;
+                R.tl2[m] = (1.0 - u) * R.gl_x[gl_off(k) + j];
+                R.tw[m] = 2.0 * R.gj_w[gl_off(k) + i] * R.gl_w[gl_off(k) + j];
+                double l1 = R.tl1[m], l2 = R.tl2[m], w = R.tw[m];
+                double lam[3] = {1.0 - l1 - l2, l1, l2};
+                double* c = R.tri[m];
+                c[0] = l1; c[1] = l2; c[2] = w;
+                for (int a = 0; a < 3; ++a) c[3 + a] = w * lam[a];
+                int slot = 6;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a; b < 3; ++b) c[slot++] = w * lam[a] * lam[b];
+                ++m;
+            }
+    }
+    for (int k = 1; k <= 8; ++k)
+        for (int i = 0; i < k; ++i) {
+            double t = R.gl_x[gl_off(k) + i], w = R.gl_w[gl_off(k) + i];
+            double* c = R.seg[gl_off(k) + i];
+            c[0] = t; c[1] = w; c[2] = w * (1.0 - t); c[3] = w * t;
+            c[4] = w * (1.0 - t) * (1.0 - t); c[5] = w * (1.0 - t) * t; c[6] = w * t * t; c[7] = 0.0;
+        }
+    if (s < 0.5) gauss_jacobi01(2, 0.0, -2.0 * s, R.r0_x, R.r0_w);
+    gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
+    auto t1 = std::chrono::steady_clock::now();
+
+    // device buffers
+    std::vector<double*> dX(NC);
+    for (int c = 0; c < NC; ++c) { int r2 = upload(h, X[c], &dX[c]); if (r2) return r2; }
+    double *dc0, *dc1 = nullptr, *dh2, *dme;
+    int *dvid[3] = {nullptr, nullptr, nullptr}, *ddof[3] = {nullptr, nullptr, nullptr};
+    if ((rc = upload(h, cen0, &dc0)) || (rc = upload(h, h2, &dh2)) || (rc = upload(h, meas, &dme))) return rc;
+    if (dim == 2 && (rc = upload(h, cen1, &dc1))) return rc;
+    for (int a = 0; a < nper; ++a)
+        if ((rc = upload(h, vid[a], &dvid[a])) || (rc = upload(h, dof[a], &ddof[a]))) return rc;
+    ElemDev E{};
+    for (int c = 0; c < NC; ++c) E.x[c] = dX[c];
+    E.cen[0] = dc0;
+    E.cen[1] = dc1;
+    E.h2 = dh2;
+    E.meas = dme;
+    for (int a = 0; a < nper; ++a) { E.vid[a] = dvid[a]; E.dof[a] = ddof[a]; }
+    h->E = E;
+    h->d_meas = dme;
+    int2* dtiles;
+    int *dbnd, *dbdofs, *dv2cp, *dv2ci, *dn2d, *ddn, *dep = nullptr, *dvp = nullptr, *dfvid = nullptr;
+    unsigned char *dloc, *dvloc;
+    double* dfac = nullptr;
+    if ((rc = upload(h, tiles, &dtiles)) || (rc = upload(h, blk_ndof, &dbnd)) ||
+        (rc = upload(h, blk_dofs, &dbdofs)) || (rc = upload(h, loc, &dloc)) ||
+        (rc = upload(h, v2c_ptr, &dv2cp)) || (rc = upload(h, v2c_idx, &dv2ci)) ||
+        (rc = upload(h, vloc, &dvloc)) || (rc = upload(h, h->node2dof, &dn2d)) ||
+        (rc = upload(h, h->dof_node, &ddn)) || (rc = upload(h, edge_pairs, &dep)) ||
+        (rc = upload(h, vert_pairs, &dvp)) || (rc = upload(h, fac, &dfac)) || (rc = upload(h, fvid, &dfvid)))
+        return rc;
+    h->d_v2c_ptr = dv2cp;
+    h->d_v2c_idx = dv2ci;
+    h->d_node2dof = dn2d;
+    h->d_dof_node = ddn;
+    double* dS;
+    unsigned long long* dcnt;
+    if ((rc = alloc_owned(h, sizeof(double) * T * 6, (void**)&dS))) return rc;
+    if ((rc = alloc_owned(h, sizeof(unsigned long long) * 16, (void**)&dcnt))) return rc;
+    {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(double) * (size_t)n * (size_t)lda + 8);
+        if (e != hipSuccess) return fail(h, FL_ENOMEM, std::string("matrix allocation: ") + hipGetErrorString(e));
+        h->dA = (double*)p;
+    }
+    HIPCHK(upload_rules(R, h->stream));
+    launch_zero(h->dA, n * lda, h->stream);
+    launch_zero(dS, T * 6, h->stream);
+    HIPCHK(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * 16, h->stream));
+
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    HIPCHK(hipEventRecord(ev[0], h->stream));
+
+    const double C = cdn(dim, s);
+    const double pe = -(0.5 * dim + s);
+    FarParams FP{};
+    FP.dim = dim;
+    FP.T = (int)T;
+    FP.pe = pe;
+    FP.C = C;
+    FP.ncls = o.n_classes;
+    for (int m = 0; m < o.n_classes; ++m) FP.th2[m] = o.theta[m] * o.theta[m];
+    for (int m = 0; m <= o.n_classes; ++m) FP.kf[m] = o.k_far[m];
+    FP.nblk = nblk;
+    FP.tiles = dtiles;
+    FP.ntiles = (long long)tiles.size();
+    FP.blk_ndof = dbnd;
+    FP.blk_dofs = dbdofs;
+    FP.loc = dloc;
+    FP.A = h->dA;
+    FP.lda = lda;
+    FP.S = dS;
+    FP.cls_count = dcnt;
+    launch_far(E, FP, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[1], h->stream));
+
+    BndParams BP{};
+    BP.dim = dim;
+    BP.s = s;
+    BP.pe = pe;
+    BP.C = C;
+    BP.T = (int)T;
+    BP.nb = (int)h->nb;
+    BP.fac = dfac;
+    BP.fvid = dfvid;
+    BP.k_touch_bnd = o.k_touch_bnd;
+    BP.ncls = o.n_classes;
+    for (int m = 0; m < o.n_classes; ++m) BP.th2[m] = FP.th2[m];
+    for (int m = 0; m <= o.n_classes; ++m) BP.kfb[m] = o.k_far_bnd[m];
+    BP.k_touch = o.k_touch;
+    BP.with_boundary = o.with_boundary;
+    BP.S = dS;
+    BP.counters = dcnt + 10;
+    launch_self(E, BP, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[2], h->stream));
+
+    TouchParams TP{};
+    TP.dim = dim;
+    TP.s = s;
+    TP.pe = pe;
+    TP.C = C;
+    TP.k = o.k_touch;
+    TP.A = h->dA;
+    TP.lda = lda;
+    if (dim == 2) {
+        TP.npairs = (long long)edge_pairs.size() / 2;
+        TP.pairs = dep;
+        launch_touch_edge2(E, TP, h->stream);
+        HIPCHK(hipGetLastError());
+    }
+    TP.npairs = (long long)vert_pairs.size() / 2;
+    TP.pairs = dvp;
+    launch_touch_vert(E, TP, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[3], h->stream));
+
+    launch_scatter_self(E, dv2cp, dv2ci, dn2d, dvloc, (int)nv, dim, dS, h->dA, lda, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[4], h->stream));
+    HIPCHK(hipEventSynchronize(ev[4]));
+    float ms = 0.f, ph[4] = {0, 0, 0, 0};
+    HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
+    for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ph[i], ev[i], ev[i + 1]));
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    unsigned long long cnt[16];
+    HIPCHK(hipMemcpy(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost));
+
+    h->s = s;
+    h->opts = o;
+    h->n = n;
+    h->lda = lda;
+    h->assembled = true;
+    fl_stats_t& S = h->st;
+    S.n = n;
+    S.n_cells = T;
+    S.n_verts = nv;
+    S.n_bfacets = h->nb;
+    S.pairs_identical = T;
+    S.pairs_edge = (int64_t)edge_pairs.size() / 2;
+    S.pairs_vertex = (int64_t)vert_pairs.size() / 2;
+    for (int m = 0; m <= FL_MAX_CLASSES; ++m) S.pairs_far[m] = m <= o.n_classes ? (int64_t)cnt[m] : 0;
+    S.pairs_bnd_touch = (int64_t)cnt[10];
+    S.pairs_bnd_far = (int64_t)cnt[11];
+    // kernel evaluations by the rules in use
+    {
+        int64_t ev = 0;
+        const int kT = o.k_touch, kB = o.k_touch_bnd;
+        for (int m = 0; m <= o.n_classes; ++m) {
+            int64_t q = dim == 2 ? (int64_t)o.k_far[m] * o.k_far[m] : o.k_far[m];
+            ev += S.pairs_far[m] * q * q;
+        }
+        if (dim == 2) {
+            ev += T * 3 * kT + S.pairs_edge * 4 * kT * kT + S.pairs_vertex * 2 * kT * kT * kT;
+            ev += S.pairs_bnd_touch * 6 * kB * 2;  // upper bound per touching facet pair
+        } else {
+            ev += S.pairs_vertex * 2 * kT;
+        }
+        S.kernel_evals = ev;
+    }
+    S.t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    S.t_assemble_ms = ms;
+    S.t_far_ms = ph[0];
+    S.t_self_ms = ph[1];
+    S.t_touch_ms = ph[2];
+    S.t_scatter_ms = ph[3];
+    if (n_out) *n_out = n;
+    return FL_OK;
+}
+
+int fl_dofs(const fl_handle* h, int32_t* node_of_dof) {
+    if (!h || !node_of_dof) return FL_EINVAL;
+    if (!h->assembled) return FL_ESTATE;
+    std::memcpy(node_of_dof, h->dof_node.data(), sizeof(int32_t) * h->n);
+    return FL_OK;
+}
+
+int fl_export_matrix(fl_handle* h, double* dst, int64_t ld, int on_device) {
+    if (!h || !dst) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->n == 0) return FL_OK;
+    HIPCHK(hipMemcpy2DAsync(dst, ld * sizeof(double), h->dA, h->lda * sizeof(double),
+                            h->n * sizeof(double), h->n,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(h->stream));
+    return FL_OK;
+}
+
+int fl_load_vector_one(fl_handle* h, double* b) {
+    if (!h || !b) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembly");
+    HIPCHK(hipSetDevice(h->device));
+    launch_load_one(h->d_dof_node, h->d_v2c_ptr, h->d_v2c_idx, h->d_meas, h->dim, h->n, b, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_matvec(fl_handle* h, const double* x, double* y) {
+    if (!h || !x || !y) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (x == y) return fail(h, FL_EINVAL, "x and y must not alias");
+    HIPCHK(hipSetDevice(h->device));
+    launch_matvec(h->dA, h->lda, h->n, x, y, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+static int ensure_solver(fl_handle* h) {
+    if (h->w_n == h->n) return FL_OK;
+    free_solver(h);
+    const int64_t n = h->n;
+    const int nblk = (int)((n + 255) / 256);
+    const int nmv = mv_blocks(n);
+    HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(6 * n + 8)));
+    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(2 * nblk + nmv + 8)));
+    HIPCHK(hipMalloc((void**)&h->w_scal, sizeof(double) * 16));
+    HIPCHK(hipMalloc((void**)&h->w_flag, sizeof(int) * 8));
+    h->w_n = n;
+    return FL_OK;
+}
+
+int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
+             double* relres) {
+    if (!h || !b || !u) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->n == 0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return FL_OK;
+    }
+    int rc = ensure_solver(h);
+    if (rc) return rc;
+    const int64_t n = h->n;
+    CgState S{};
+    S.n = n;
+    S.A = h->dA;
+    S.lda = h->lda;
+    S.r = h->w;
+    S.z = h->w + n;
+    S.p = h->w + 2 * n;
+    S.q = h->w + 3 * n;
+    double* dd = h->w + 4 * n;
+    S.d = dd;
+    S.b = b;
+    S.x = u;
+    S.part = h->w_part;
+    S.scal = h->w_scal;
+    S.flag = h->w_flag;
+    S.rtol = rtol;
+    S.maxit = maxit;
+    S.nblk = (int)((n + 255) / 256);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    launch_diag(h->dA, h->lda, n, dd, h->stream);
+    launch_cg_init(S, h->stream);
+    HIPCHK(hipGetLastError());
+    int flag[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int it = 0;
+    const int chunk = 16;
+    if (flag[2] == 2) return fail(h, FL_ENONFINITE, "right-hand side is not finite");
+    while (!flag[0] && it < maxit) {
+        int m = std::min(chunk, maxit - it);
+        for (int j = 0; j < m; ++j) launch_cg_iter_at(S, it + j, h->stream);
+        HIPCHK(hipGetLastError());
+        it += m;
+        HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    double sc[4];
+    HIPCHK(hipMemcpy(sc, S.scal, sizeof(double) * 4, hipMemcpyDeviceToHost));
+    int iterations = flag[1];
+    double rel = sc[2] > 0 ? std::sqrt(sc[3]) / std::sqrt(sc[2]) : 0.0;
+    h->st.t_solve_ms = ms;
+    h->st.last_iters = iterations;
+    h->st.last_relres = rel;
+    if (iters) *iters = iterations;
+    if (relres) *relres = rel;
+    if (flag[2] == 1) return fail(h, FL_EBREAKDOWN, "CG breakdown: p.Ap <= 0");
+    if (flag[2] == 2) return fail(h, FL_ENONFINITE, "non-finite residual");
+    if (!(rel <= rtol)) return FL_ENOCONV;
+    return FL_OK;
+}
+
+int fl_energy_error2(fl_handle* h, double fu, const double* b, const double* uh, double* e2_out) {
+    if (!h || !b || !uh || !e2_out) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->n == 0) {
+        *e2_out = fu;
+        return FL_OK;
+    }
+    int rc = ensure_solver(h);
+    if (rc) return rc;
+    const int64_t n = h->n;
+    double* y = h->w + 5 * n;
+    launch_matvec(h->dA, h->lda, n, uh, y, h->stream);
+    const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    launch_dot2(uh, b, y, n, h->w_part, nblk, h->w_scal + 8, h->stream);
+    HIPCHK(hipGetLastError());
+    double r[2];
+    HIPCHK(hipMemcpyAsync(r, h->w_scal + 8, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *e2_out = fu - 2.0 * r[0] + r[1];
+    return FL_OK;
+}
+
+int fl_stats(const fl_handle* h, fl_stats_t* out) {
+    if (!h || !out) return FL_EINVAL;
+    *out = h->st;
+    return FL_OK;
+}
+
+}  // extern "C"

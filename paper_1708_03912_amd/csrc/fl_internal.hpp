@@ -1,0 +1,133 @@
+// Internal declarations shared by the host planner (fl_api.hip) and the
+// device kernels (fl_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fraclap.h"
+
+namespace fl {
+
+constexpr int BE = 64;      // elements per far-field tile side
+constexpr int MAXV = 72;    // DOFs per element block kept in LDS
+constexpr int TRI_TAB = 204;  // sum_{k=1..8} k^2 triangle-rule points
+constexpr int GL_TAB = 136;   // sum_{k=1..16} k Gauss points
+
+// Device tables of Gauss rules, filled once per assembly.
+struct RuleTables {
+    double gl_x[GL_TAB], gl_w[GL_TAB];  // Gauss-Legendre on [0,1], k = 1..16
+    double gj_x[GL_TAB], gj_w[GL_TAB];  // Gauss-Jacobi weight (1-u) on [0,1]
+    double tl1[TRI_TAB], tl2[TRI_TAB], tw[TRI_TAB];  // collapsed triangle rules, k = 1..8
+    // per triangle-rule point: l1, l2, w, w l0, w l1, w l2, w l_a l_b (a<=b)
+    double tri[TRI_TAB][12];
+    // per Gauss-Legendre point (k = 1..8): t, w, w l0, w l1, w l0 l0, w l0 l1, w l1 l1
+    double seg[36][8];
+    double r0_x[2], r0_w[2];            // 2-point rule, weight r^{-2s} on [0,1]
+    double r1_x[2], r1_w[2];            // 2-point rule, weight r^{1-2s} on [0,1]
+};
+
+__host__ __device__ inline int gl_off(int k) { return k * (k - 1) / 2; }
+__host__ __device__ inline int tri_off(int k) { return (k - 1) * k * (2 * k - 1) / 6; }
+
+// Element data, structure of arrays, in the library's internal element order.
+struct ElemDev {
+    const double* x[6];     // vertex coordinates: 2D x0,y0,x1,y1,x2,y2; 1D x0,x1
+    const double* cen[2];   // centroid
+    const double* h2;       // squared longest edge
+    const double* meas;     // |K|
+    const int* vid[3];      // vertex ids
+    const int* dof[3];      // DOF ids, -1 if the vertex is not a DOF
+};
+
+struct FarParams {
+    int dim;
+    int T;
+    double pe;              // exponent of r^2 in the kernel: -(d/2 + s)
+    double C;               // C(d,s)
+    int ncls;
+    double th2[FL_MAX_CLASSES];
+    int kf[FL_MAX_CLASSES + 1];
+    int nblk;
+    const int2* tiles;      // (bi, bj), bi <= bj
+    long long ntiles;
+    const int* blk_ndof;    // DOFs per element block
+    const int* blk_dofs;    // nblk x MAXV DOF ids (first blk_ndof valid)
+    const unsigned char* loc;  // T x 3 local DOF index in its block (255: none)
+    double* A;
+    long long lda;
+    double* S;              // T x 6 per-element diagonal-block accumulators
+    unsigned long long* cls_count;  // ncls+1 counters
+};
+
+struct TouchParams {
+    int dim;
+    double s, pe, C;
+    int k;
+    long long npairs;
+    const int* pairs;       // npairs x 2 element ids (K < Kt)
+    double* A;
+    long long lda;
+};
+
+struct BndParams {
+    int dim;
+    double s, pe, C;
+    int T;
+    int nb;
+    const double* fac;      // nb x 6: p0x p0y p1x p1y nx ny (1D: y, n)
+    const int* fvid;        // nb x 2 vertex ids (1D: one)
+    int k_touch_bnd;
+    int ncls;
+    double th2[FL_MAX_CLASSES];
+    int kfb[FL_MAX_CLASSES + 1];
+    int k_touch;
+    int with_boundary;
+    double* S;
+    unsigned long long* counters;  // [0] touching, [1] separated
+};
+
+// launch wrappers (fl_kernels.hip)
+hipError_t upload_rules(const RuleTables& R, hipStream_t st);
+void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st);
+void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st);
+void launch_touch_edge2(const ElemDev& E, const TouchParams& P, hipStream_t st);
+void launch_touch_vert(const ElemDev& E, const TouchParams& P, hipStream_t st);
+void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx,
+                         const int* node2dof, const unsigned char* vloc, int nv, int dim,
+                         const double* S, double* A, long long lda, hipStream_t st);
+void launch_zero(double* p, long long n, hipStream_t st);
+void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
+                     const double* meas, int dim, long long n, double* b, hipStream_t st);
+
+// solver kernels
+constexpr int MV_THREADS = 256;
+int mv_blocks(long long n);
+void launch_matvec(const double* A, long long lda, long long n, const double* x, double* y,
+                   hipStream_t st);
+void launch_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
+// CG building blocks; status layout in cg_status_layout
+struct CgState {
+    long long n;
+    const double* A;
+    long long lda;
+    const double* d;    // diagonal
+    const double* b;
+    double* x;
+    double* r;
+    double* z;
+    double* p;
+    double* q;
+    double* part;       // 2 x nblk + mv_blocks(n) partial sums
+    double* scal;       // [0],[1] r.z by iteration parity, [2] b.b, [3] r.r
+    int* flag;          // [0] converged/stop, [1] iterations, [2] breakdown
+    double rtol;
+    int maxit;
+    int nblk;
+};
+void launch_cg_init(const CgState& s, hipStream_t st);
+void launch_cg_iter_at(const CgState& s, int it, hipStream_t st);
+void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
+                 int nblk, double* out, hipStream_t st);
+
+}  // namespace fl

@@ -1,0 +1,1131 @@
+// Device kernels for the dense P1 stiffness matrix of the integral
+// fractional Laplacian (Ainsworth & Glusa, arXiv:1708.03912), gfx950.
+//
+// Assembly follows the element-pair decomposition of Sec. 5:
+//   separated pairs  -> far_kernel   (tensor Gauss, order by distance class,
+//                                     App. B), tiled 64 x 64 elements,
+//                                     LDS-accumulated, FP64
+//   identical pairs  -> self_kernel  (regularised, 1D integrals over the
+//                                     difference hexagon)
+//   boundary facets  -> self_kernel  (a^{Kxe}, Sec. 2 / Sec. 5)
+//   edge / vertex    -> touch kernels (regularised, analytic radial factor)
+//   diagonal blocks  -> scatter_self (gather per DOF row, deterministic)
+// The CG kernels implement Jacobi-preconditioned CG (Sec. 5).
+#include <hip/hip_runtime.h>
+
+#include "fl_internal.hpp"
+
+namespace fl {
+
+__constant__ RuleTables c_R;
+
+hipError_t upload_rules(const RuleTables& R, hipStream_t st) {
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_R), &R, sizeof(RuleTables), 0,
+                                  hipMemcpyHostToDevice, st);
+}
+
+// |x-y|^{-d-2s} = (r^2)^{pe}, pe = -(d/2+s)
+__device__ __forceinline__ double kpow(double r2, double pe) { return exp2(pe * log2(r2)); }
+
+__device__ __forceinline__ int sym3(int a, int b) {
+    // upper-triangular slot of (a,b), a <= b, in a 3x3 symmetric block
+    return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ----------------------------------------------------------- separated --
+
+// Separated triangles with the order-KO collapsed rule on both.  X, Y:
+// vertex coordinates.  Outputs raw sums without area / C factors:
+//   SK[sym] = sum_pq w_p w_q l_a l_b(x_p) k,  ST likewise with y_q,
+//   O[3a+b] = sum_pq w_p w_q l_a(x_p) l_b(y_q) k.
+// Loop order q (points of Kt) outside, p (points of K) inside; the inner
+// loop carries only scalar accumulators, every rule-dependent factor
+// (w, w l_a, w l_a l_b) comes from the constant table.
+template <int KO>
+__device__ __forceinline__ void far_pair2(const double* X, const double* Y, double pe,
+                                          double* SK, double* ST, double* O) {
+    constexpr int Q = KO * KO;
+    const int off = tri_off(KO);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { SK[m] = 0.0; ST[m] = 0.0; }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) O[m] = 0.0;
+    const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
+    const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
+    for (int q = 0; q < Q; ++q) {
+        const double* cq = c_R.tri[off + q];
+        const double yx = Y[0] + cq[0] * fx0 + cq[1] * fx1;
+        const double yy = Y[1] + cq[0] * fy0 + cq[1] * fy1;
+        double gy = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
+#pragma unroll 2
+        for (int p = 0; p < Q; ++p) {
+            const double* cp = c_R.tri[off + p];
+            const double dx = (X[0] + cp[0] * ex0 + cp[1] * ex1) - yx;
+            const double dy = (X[1] + cp[0] * ey0 + cp[1] * ey1) - yy;
+            const double kv = kpow(dx * dx + dy * dy, pe);
+            gy += cp[2] * kv;
+            n0 += cp[3] * kv;
+            n1 += cp[4] * kv;
+            n2 += cp[5] * kv;
+            t0 += cp[6] * kv;
+            t1 += cp[7] * kv;
+            t2 += cp[8] * kv;
+            t3 += cp[9] * kv;
+            t4 += cp[10] * kv;
+            t5 += cp[11] * kv;
+        }
+        const double wq = cq[2];
+        SK[0] += wq * t0; SK[1] += wq * t1; SK[2] += wq * t2;
+        SK[3] += wq * t3; SK[4] += wq * t4; SK[5] += wq * t5;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ST[m] += cq[6 + m] * gy;
+        const double na[3] = {n0, n1, n2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) O[3 * a + b] += cq[3 + b] * na[a];
+    }
+}
+
+// Separated segments, KO-point Gauss-Legendre on both (same outputs, slots
+// 0,1,3 of the symmetric blocks and 0,1,3,4 of O).
+template <int KO>
+__device__ __forceinline__ void far_pair1(const double* X, const double* Y, double pe,
+                                          double* SK, double* ST, double* O) {
+    const int off = gl_off(KO);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { SK[m] = 0.0; ST[m] = 0.0; }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) O[m] = 0.0;
+    const double ex = X[1] - X[0], fx = Y[1] - Y[0];
+    for (int q = 0; q < KO; ++q) {
+        const double* cq = c_R.seg[off + q];
+        const double yv = Y[0] + cq[0] * fx;
+        double gy = 0.0, n0 = 0.0, n1 = 0.0, t0 = 0.0, t1 = 0.0, t3 = 0.0;
+#pragma unroll 2
+        for (int p = 0; p < KO; ++p) {
+            const double* cp = c_R.seg[off + p];
+            const double d = (X[0] + cp[0] * ex) - yv;
+            const double kv = kpow(d * d, pe);
+            gy += cp[1] * kv;
+            n0 += cp[2] * kv;
+            n1 += cp[3] * kv;
+            t0 += cp[4] * kv;
+            t1 += cp[5] * kv;
+            t3 += cp[6] * kv;
+        }
+        const double wq = cq[1];
+        SK[0] += wq * t0; SK[1] += wq * t1; SK[3] += wq * t3;
+        ST[0] += cq[4] * gy; ST[1] += cq[5] * gy; ST[3] += cq[6] * gy;
+        O[0] += cq[2] * n0; O[1] += cq[3] * n0;
+        O[3] += cq[2] * n1; O[4] += cq[3] * n1;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe,
+                                         double* SK, double* ST, double* O) {
+    if (DIM == 2) {
+        switch (k) {
+            case 1: far_pair2<1>(X, Y, pe, SK, ST, O); break;
+            case 2: far_pair2<2>(X, Y, pe, SK, ST, O); break;
+            case 3: far_pair2<3>(X, Y, pe, SK, ST, O); break;
+            case 4: far_pair2<4>(X, Y, pe, SK, ST, O); break;
+            case 5: far_pair2<5>(X, Y, pe, SK, ST, O); break;
+            case 6: far_pair2<6>(X, Y, pe, SK, ST, O); break;
+            case 7: far_pair2<7>(X, Y, pe, SK, ST, O); break;
+            default: far_pair2<8>(X, Y, pe, SK, ST, O); break;
+        }
+    } else {
+        switch (k) {
+            case 1: far_pair1<1>(X, Y, pe, SK, ST, O); break;
+            case 2: far_pair1<2>(X, Y, pe, SK, ST, O); break;
+            case 3: far_pair1<3>(X, Y, pe, SK, ST, O); break;
+            case 4: far_pair1<4>(X, Y, pe, SK, ST, O); break;
+            case 5: far_pair1<5>(X, Y, pe, SK, ST, O); break;
+            case 6: far_pair1<6>(X, Y, pe, SK, ST, O); break;
+            case 7: far_pair1<7>(X, Y, pe, SK, ST, O); break;
+            default: far_pair1<8>(X, Y, pe, SK, ST, O); break;
+        }
+    }
+}
+
+// Order class: #{m : d2 >= theta_m^2 * max(h2K, h2Kt)}.  Every product and
+// sum is rounded on its own (contraction into FMA is switched off here), so
+// the class of every pair, ties included, is reproducible bit for bit by an
+// independent implementation of the same formula.
+__device__ __noinline__ int order_class(double d2, double hmax2, int ncls, const double* th2) {
+#pragma clang fp contract(off)
+    int c = 0;
+    for (int m = 0; m < ncls; ++m) {
+        double t = th2[m] * hmax2;
+        if (d2 >= t) c = m + 1;
+    }
+    return c;
+}
+
+// squared distance of two points in DIM dimensions, no contraction
+__device__ __noinline__ double dist2_nc(double x0, double y0, double x1, double y1, int dim) {
+#pragma clang fp contract(off)
+    double dx = x0 - x1;
+    double d2 = dx * dx;
+    if (dim == 2) {
+        double dy = y0 - y1;
+        double t = dy * dy;
+        d2 = d2 + t;
+    }
+    return d2;
+}
+
+// One workgroup per tile (bi <= bj) of BE x BE element pairs.  Wave w takes
+// rows K = I0 + w, w+4, ...; lane l takes Kt = J0 + l.  Off-diagonal blocks
+// are accumulated in LDS over the block's local DOF numbering and flushed
+// to A (and its mirror) with one global atomic per touched entry; the
+// diagonal-block increments go to per-element accumulators S.
+template <int DIM>
+__global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
+    constexpr int NV = DIM + 1;
+    constexpr int NC = NV * DIM;
+    __shared__ double L[MAXV * MAXV];
+    __shared__ double SI[BE * 6];
+    __shared__ double SJ[BE * 6];
+    __shared__ int vI[MAXV], vJ[MAXV];
+    __shared__ unsigned char locI[BE * 3], locJ[BE * 3];
+    __shared__ unsigned long long ccount[FL_MAX_CLASSES + 1];
+
+    const long long t = blockIdx.x;
+    const int2 tb = P.tiles[t];
+    const int bi = tb.x, bj = tb.y;
+    const int I0 = bi * BE, J0 = bj * BE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nVI = P.blk_ndof[bi], nVJ = P.blk_ndof[bj];
+    const bool direct = (nVI > MAXV) || (nVJ > MAXV);
+    const int T = P.T;
+
+    for (int i = tid; i < BE * 3; i += 256) {
+        int K = I0 + i / 3, Kt = J0 + i / 3;
+        locI[i] = (K < T) ? P.loc[(long long)K * 3 + i % 3] : 255;
+        locJ[i] = (Kt < T) ? P.loc[(long long)Kt * 3 + i % 3] : 255;
+    }
+    if (!direct) {
+        for (int i = tid; i < MAXV; i += 256) {
+            vI[i] = P.blk_dofs[(long long)bi * MAXV + i];
+            vJ[i] = P.blk_dofs[(long long)bj * MAXV + i];
+        }
+        for (int i = tid; i < nVI * nVJ; i += 256) L[i] = 0.0;
+    }
+    for (int i = tid; i < BE * 6; i += 256) { SI[i] = 0.0; SJ[i] = 0.0; }
+    if (tid <= FL_MAX_CLASSES) ccount[tid] = 0;
+    __syncthreads();
+
+    const int Kt = J0 + lane;
+    const bool okt = Kt < T;
+    double Y[6] = {0, 0, 0, 0, 0, 0}, cyt[2] = {0, 0}, h2t = 0, mt = 0;
+    int vt[3] = {-1, -1, -1};
+    if (okt) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Y[c] = E.x[c][Kt];
+        for (int c = 0; c < DIM; ++c) cyt[c] = E.cen[c][Kt];
+        h2t = E.h2[Kt];
+        mt = E.meas[Kt];
+#pragma unroll
+        for (int a = 0; a < NV; ++a) vt[a] = E.vid[a][Kt];
+    }
+    double STacc[6] = {0, 0, 0, 0, 0, 0};
+
+    for (int r = wave; r < BE; r += 4) {
+        const int K = I0 + r;
+        if (K >= T) break;
+        double X[6] = {0, 0, 0, 0, 0, 0}, cx[2] = {0, 0};
+        int vk[3] = {-2, -2, -2};
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X[c] = E.x[c][K];
+        for (int c = 0; c < DIM; ++c) cx[c] = E.cen[c][K];
+        const double h2k = E.h2[K], mk = E.meas[K];
+#pragma unroll
+        for (int a = 0; a < NV; ++a) vk[a] = E.vid[a][K];
+
+        bool valid = okt && (bi != bj || K < Kt);
+#pragma unroll
+        for (int a = 0; a < NV; ++a)
+#pragma unroll
+            for (int b = 0; b < NV; ++b) valid = valid && (vk[a] != vt[b]);
+        int cls = -1;
+        if (valid) {
+            const double d2 = dist2_nc(cx[0], cx[1], cyt[0], cyt[1], DIM);
+            double hm = h2k > h2t ? h2k : h2t;
+            cls = order_class(d2, hm, P.ncls, P.th2);
+        }
+#pragma unroll
+        for (int c = 0; c <= FL_MAX_CLASSES; ++c) {
+            if (c <= P.ncls) {
+                unsigned long long bal = __ballot(cls == c);
+                if (lane == 0 && bal) atomicAdd(&ccount[c], (unsigned long long)__popcll(bal));
+            }
+        }
+        double SK[6] = {0, 0, 0, 0, 0, 0}, ST[6] = {0, 0, 0, 0, 0, 0};
+        double O[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c <= P.ncls; ++c) {
+            if (__any(cls == c)) {
+                if (cls == c) far_pair<DIM>(P.kf[c], X, Y, P.pe, SK, ST, O);
+            }
+        }
+        const double f = valid ? P.C * mk * mt : 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            SK[m] *= f;
+            STacc[m] += ST[m] * f;
+        }
+        // diagonal block of K: reduce over the wave, this wave owns row r
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double v = wave_sum(SK[m]);
+            if (lane == 0) SI[r * 6 + m] += v;
+        }
+        if (valid) {
+            if (!direct) {
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    int ra = locI[r * 3 + a];
+                    if (ra == 255) continue;
+#pragma unroll
+                    for (int b = 0; b < NV; ++b) {
+                        int cb = locJ[lane * 3 + b];
+                        if (cb == 255) continue;
+                        double v = -f * O[3 * a + b];
+                        atomicAdd(&L[ra * nVJ + cb], v);
+                        if (bi == bj) atomicAdd(&L[cb * nVJ + ra], v);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    int ga = E.dof[a][K];
+                    if (ga < 0) continue;
+#pragma unroll
+                    for (int b = 0; b < NV; ++b) {
+                        int gb = E.dof[b][Kt];
+                        if (gb < 0) continue;
+                        double v = -f * O[3 * a + b];
+                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                    }
+                }
+            }
+        }
+    }
+    if (okt) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if (STacc[m] != 0.0) atomicAdd(&SJ[lane * 6 + m], STacc[m]);
+    }
+    __syncthreads();
+    if (!direct) {
+        for (int i = tid; i < nVI * nVJ; i += 256) {
+            double v = L[i];
+            if (v == 0.0) continue;
+            int rr = i / nVJ, cc = i - rr * nVJ;
+            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+            if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+        }
+    }
+    for (int i = tid; i < BE * 6; i += 256) {
+        int K = I0 + i / 6, Kt2 = J0 + i / 6;
+        if (K < T && SI[i] != 0.0) atomicAdd(&P.S[(long long)K * 6 + i % 6], SI[i]);
+        if (Kt2 < T && SJ[i] != 0.0) atomicAdd(&P.S[(long long)Kt2 * 6 + i % 6], SJ[i]);
+    }
+    if (tid <= P.ncls && ccount[tid]) atomicAdd(&P.cls_count[tid], ccount[tid]);
+}
+
+void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
+    if (P.ntiles == 0) return;
+    dim3 grid((unsigned)P.ntiles), block(256);
+    if (P.dim == 2)
+        hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, st, E, P);
+    else
+        hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, st, E, P);
+}
+
+// ------------------------------------------------ identical + boundary --
+
+// Identical triangle (regularised): I_ab = 4|K|^2 B_id sum over the half
+// boundary of the difference hexagon of int_0^1 D_a D_b |z|^{-2-2s} dt,
+// B_id = 2/((2-2s)(3-2s)(4-2s)).  Returns the 6 symmetric entries.
+__device__ void ident2(const double* X, double s, double pe, int k, double* M6) {
+    const double HX[4][3] = {{-1, 1, 0}, {-1, 0, 1}, {0, -1, 1}, {1, -1, 0}};
+    for (int m = 0; m < 6; ++m) M6[m] = 0.0;
+    const int off = gl_off(k);
+    for (int e = 0; e < 3; ++e)
+        for (int i = 0; i < k; ++i) {
+            double t = c_R.gl_x[off + i];
+            double D[3];
+            for (int a = 0; a < 3; ++a) D[a] = HX[e][a] + t * (HX[e + 1][a] - HX[e][a]);
+            double z0 = D[0] * X[0] + D[1] * X[2] + D[2] * X[4];
+            double z1 = D[0] * X[1] + D[1] * X[3] + D[2] * X[5];
+            double kv = kpow(z0 * z0 + z1 * z1, pe) * c_R.gl_w[off + i];
+            for (int a = 0; a < 3; ++a)
+                for (int b = a; b < 3; ++b) M6[sym3(a, b)] += kv * D[a] * D[b];
+        }
+    double area = 0.5 * fabs((X[2] - X[0]) * (X[5] - X[1]) - (X[4] - X[0]) * (X[3] - X[1]));
+    double Bid = 2.0 / ((2.0 - 2.0 * s) * (3.0 - 2.0 * s) * (4.0 - 2.0 * s));
+    double f = 4.0 * area * area * Bid;
+    for (int m = 0; m < 6; ++m) M6[m] *= f;
+}
+
+// Boundary facet e = [p0,p1] (inward normal n) separated from triangle K:
+// order-k triangle rule on K times k-point Gauss-Legendre on e.
+__device__ void bnd_far2(const double* X, const double* fe, double pe, int k, double* M6) {
+    const int to = tri_off(k), go = gl_off(k);
+    const int Q = k * k;
+    double area = 0.5 * fabs((X[2] - X[0]) * (X[5] - X[1]) - (X[4] - X[0]) * (X[3] - X[1]));
+    double e0 = fe[2] - fe[0], e1 = fe[3] - fe[1];
+    double Le = sqrt(e0 * e0 + e1 * e1);
+    for (int p = 0; p < Q; ++p) {
+        double l1 = c_R.tl1[to + p], l2 = c_R.tl2[to + p];
+        double l0 = 1.0 - l1 - l2;
+        double xx = l0 * X[0] + l1 * X[2] + l2 * X[4];
+        double xy = l0 * X[1] + l1 * X[3] + l2 * X[5];
+        double g = 0.0;
+        for (int q = 0; q < k; ++q) {
+            double t = c_R.gl_x[go + q];
+            double d0 = xx - (fe[0] + t * e0), d1 = xy - (fe[1] + t * e1);
+            g += c_R.gl_w[go + q] * (fe[4] * d0 + fe[5] * d1) * kpow(d0 * d0 + d1 * d1, pe);
+        }
+        g *= area * Le * c_R.tw[to + p];
+        double lam[3] = {l0, l1, l2};
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) M6[sym3(a, b)] += g * lam[a] * lam[b];
+    }
+}
+
+// e = [p0,p1] is an edge of K = (p0,p1,a) (local order p0,p1,a).  Polar
+// form in (w,beta) about the edge with the gauge max(0,beta+w)+max(0,-w):
+// unit polyline (1,0)->(0,1)->(-1,1)->(-1,0); radial weight r^{1-2s}
+// (entries carrying the factor beta) or r^{-2s} (entries among p0,p1,
+// finite only for s < 1/2), 2-point rules exact in r and in the foot
+// variable, k-point Gauss-Legendre along the polyline.  Output in local
+// order; entries among p0,p1 are NaN for s >= 1/2.
+__device__ void bnd_edge2(const double* p0, const double* p1, const double* pa, const double* n,
+                          double s, double pe, int k, double* M) {
+    const double SEG[4][2] = {{1, 0}, {0, 1}, {-1, 1}, {-1, 0}};
+    const int go = gl_off(k), g2 = gl_off(2);
+    double E0 = p1[0] - p0[0], E1 = p1[1] - p0[1];
+    double a0 = pa[0] - p0[0], a1 = pa[1] - p0[1];
+    double na = n[0] * a0 + n[1] * a1;
+    double Le = sqrt(E0 * E0 + E1 * E1);
+    double area = 0.5 * fabs(E0 * a1 - a0 * E1);
+    double acc[9];
+    for (int m = 0; m < 9; ++m) acc[m] = 0.0;
+    const bool lows = s < 0.5;
+    for (int sg = 0; sg < 3; ++sg)
+        for (int i = 0; i < k; ++i) {
+            double t = c_R.gl_x[go + i];
+            double pw = SEG[sg][0] + t * (SEG[sg + 1][0] - SEG[sg][0]);
+            double pb = SEG[sg][1] + t * (SEG[sg + 1][1] - SEG[sg][1]);
+            double z0 = pw * E0 + pb * a0, z1 = pw * E1 + pb * a1;
+            double ang = c_R.gl_w[go + i] * pb * kpow(z0 * z0 + z1 * z1, pe);
+            double lo = pw < 0.0 ? -pw : 0.0;
+            for (int il = 0; il < 2; ++il) {
+                double lx = c_R.gl_x[g2 + il], lw = c_R.gl_w[g2 + il];
+                for (int ir = 0; ir < 2; ++ir) {
+                    {
+                        double r = c_R.r1_x[ir];
+                        double tau = r * lo + lx * (1.0 - r);
+                        double sig = tau + r * pw, beta = r * pb;
+                        double lam[3] = {1.0 - sig - beta, sig, beta};
+                        double wt = ang * lw * c_R.r1_w[ir] * (1.0 - r) * pb;
+                        acc[6] += wt * lam[0];
+                        acc[7] += wt * lam[1];
+                        acc[8] += wt * lam[2];
+                    }
+                    if (lows) {
+                        double r = c_R.r0_x[ir];
+                        double tau = r * lo + lx * (1.0 - r);
+                        double sig = tau + r * pw, beta = r * pb;
+                        double l0 = 1.0 - sig - beta, l1 = sig;
+                        double wt = ang * lw * c_R.r0_w[ir] * (1.0 - r);
+                        acc[0] += wt * l0 * l0;
+                        acc[1] += wt * l0 * l1;
+                        acc[4] += wt * l1 * l1;
+                    }
+                }
+            }
+        }
+    double f = 2.0 * area * Le * na;
+    double nan = __longlong_as_double(0x7ff8000000000000ULL);
+    M[0] = lows ? f * acc[0] : nan;
+    M[1] = lows ? f * acc[1] : nan;
+    M[3] = M[1];
+    M[4] = lows ? f * acc[4] : nan;
+    M[2] = M[6] = f * acc[6];
+    M[5] = M[7] = f * acc[7];
+    M[8] = f * acc[8];
+}
+
+// e = [q,p] shares only the vertex q with K = (q,b1,b2) (local order
+// q,b1,b2).  Polar form in (u,v) with the gauge max(u,v); radial weight
+// r^{1-2s}, 2-point rule exact; k-point Gauss-Legendre in the other two
+// directions.
+__device__ void bnd_vert2(const double* q, const double* b1, const double* b2, const double* pp,
+                          const double* n, double pe, int k, double* M) {
+    const int go = gl_off(k);
+    double E0 = pp[0] - q[0], E1 = pp[1] - q[1];
+    double Le = sqrt(E0 * E0 + E1 * E1);
+    double area = 0.5 * fabs((b1[0] - q[0]) * (b2[1] - q[1]) - (b2[0] - q[0]) * (b1[1] - q[1]));
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int face = 0; face < 2; ++face)
+        for (int i = 0; i < k; ++i) {
+            double ti = c_R.gl_x[go + i];
+            double pu = face == 0 ? 1.0 : ti;
+            double pv = face == 0 ? ti : 1.0;
+            for (int j = 0; j < k; ++j) {
+                double tj = c_R.gl_x[go + j];
+                double A0 = (b1[0] - q[0]) + tj * (b2[0] - b1[0]);
+                double A1 = (b1[1] - q[1]) + tj * (b2[1] - b1[1]);
+                double z0 = pu * A0 - pv * E0, z1 = pu * A1 - pv * E1;
+                double ang = c_R.gl_w[go + i] * c_R.gl_w[go + j] * pu * pu * (n[0] * A0 + n[1] * A1) *
+                             kpow(z0 * z0 + z1 * z1, pe);
+                for (int ir = 0; ir < 2; ++ir) {
+                    double uu = c_R.r1_x[ir] * pu;
+                    double lam[3] = {1.0 - uu, uu * (1.0 - tj), uu * tj};
+                    double wt = ang * c_R.r1_w[ir];
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = a; b < 3; ++b) acc[sym3(a, b)] += wt * lam[a] * lam[b];
+                }
+            }
+        }
+    double f = 2.0 * area * Le;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[3 * a + b] = f * acc[sym3(a, b)];
+}
+
+// One thread per element: identical-pair term (weight C/2) and the boundary
+// term sum_e a^{Kxe} (weight C/(2s)), added to the element's diagonal-block
+// accumulator S (after the far-field kernel, so this thread is S[K]'s only
+// writer).
+template <int DIM>
+__global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
+    const int K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= P.T) return;
+    constexpr int NV = DIM + 1;
+    double X[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < NV * DIM; ++c) X[c] = E.x[c][K];
+    int vk[3] = {-1, -1, -1};
+    for (int a = 0; a < NV; ++a) vk[a] = E.vid[a][K];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    // identical pair
+    if (DIM == 1) {
+        double h = fabs(X[1] - X[0]);
+        double v = 2.0 * pow(h, 1.0 - 2.0 * P.s) / ((2.0 - 2.0 * P.s) * (3.0 - 2.0 * P.s));
+        acc[0] = 0.5 * P.C * v;
+        acc[1] = -0.5 * P.C * v;
+        acc[3] = 0.5 * P.C * v;
+    } else {
+        double M6[6];
+        ident2(X, P.s, P.pe, P.k_touch, M6);
+        for (int m = 0; m < 6; ++m) acc[m] = 0.5 * P.C * M6[m];
+    }
+    if (P.with_boundary) {
+        const double fb = P.C / (2.0 * P.s);
+        double cx = E.cen[0][K], cy = DIM == 2 ? E.cen[1][K] : 0.0, h2k = E.h2[K];
+        unsigned long long ntouch = 0, nfar = 0;
+        for (int e = 0; e < P.nb; ++e) {
+            const double* fe = P.fac + 6 * (long long)e;
+            if (DIM == 1) {
+                int fv = P.fvid[2 * e];
+                double ye = fe[0];
+                bool touching = (vk[0] == fv || vk[1] == fv);
+                double h = fabs(X[1] - X[0]);
+                double m00, m01, m11;
+                if (touching) {
+                    ++ntouch;
+                    double hp = pow(h, 1.0 - 2.0 * P.s);
+                    m00 = P.s < 0.5 ? hp * (1.0 / (1.0 - 2.0 * P.s) - 2.0 / (2.0 - 2.0 * P.s) +
+                                            1.0 / (3.0 - 2.0 * P.s))
+                                    : __longlong_as_double(0x7ff8000000000000ULL);
+                    m01 = hp * (1.0 / (2.0 - 2.0 * P.s) - 1.0 / (3.0 - 2.0 * P.s));
+                    m11 = hp / (3.0 - 2.0 * P.s);
+                    if (vk[0] == fv) {
+                        acc[0] += fb * m00; acc[1] += fb * m01; acc[3] += fb * m11;
+                    } else {
+                        acc[3] += fb * m00; acc[1] += fb * m01; acc[0] += fb * m11;
+                    }
+                } else {
+                    ++nfar;
+                    int cls = order_class(dist2_nc(cx, 0.0, ye, 0.0, 1), h2k, P.ncls, P.th2);
+                    int k = P.kfb[cls];
+                    const int go = gl_off(k);
+                    for (int i = 0; i < k; ++i) {
+                        double t = c_R.gl_x[go + i];
+                        double x = X[0] + t * (X[1] - X[0]);
+                        double kv = pow(fabs(x - ye), -2.0 * P.s) * h * c_R.gl_w[go + i];
+                        double l0 = 1.0 - t, l1 = t;
+                        acc[0] += fb * kv * l0 * l0;
+                        acc[1] += fb * kv * l0 * l1;
+                        acc[3] += fb * kv * l1 * l1;
+                    }
+                }
+                continue;
+            }
+            int f0 = P.fvid[2 * e], f1 = P.fvid[2 * e + 1];
+            int sh0 = -1, sh1 = -1;
+            for (int a = 0; a < 3; ++a) {
+                if (vk[a] == f0) sh0 = a;
+                if (vk[a] == f1) sh1 = a;
+            }
+            const double p0[2] = {fe[0], fe[1]}, p1[2] = {fe[2], fe[3]}, nn[2] = {fe[4], fe[5]};
+            if (sh0 >= 0 && sh1 >= 0) {
+                ++ntouch;
+                int ia = 3 - sh0 - sh1;
+                double pa[2] = {X[2 * ia], X[2 * ia + 1]};
+                double M[9];
+                bnd_edge2(p0, p1, pa, nn, P.s, P.pe, P.k_touch_bnd, M);
+                int g[3] = {sh0, sh1, ia};
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a; b < 3; ++b) {
+                        // local (p0,p1,a) -> element slots
+                        int ea = g[a], eb = g[b];
+                        acc[sym3(ea, eb)] += fb * M[3 * a + b];
+                    }
+            } else if (sh0 >= 0 || sh1 >= 0) {
+                ++ntouch;
+                int a = sh0 >= 0 ? sh0 : sh1;
+                const double* pother = sh0 >= 0 ? p1 : p0;
+                int i1 = (a + 1) % 3, i2 = (a + 2) % 3;
+                if (vk[i1] > vk[i2]) { int tt = i1; i1 = i2; i2 = tt; }
+                double q[2] = {X[2 * a], X[2 * a + 1]};
+                double b1[2] = {X[2 * i1], X[2 * i1 + 1]}, b2[2] = {X[2 * i2], X[2 * i2 + 1]};
+                double M[9];
+                bnd_vert2(q, b1, b2, pother, nn, P.pe, P.k_touch_bnd, M);
+                int g[3] = {a, i1, i2};
+                for (int aa = 0; aa < 3; ++aa)
+                    for (int bb = aa; bb < 3; ++bb) acc[sym3(g[aa], g[bb])] += fb * M[3 * aa + bb];
+            } else {
+                ++nfar;
+                double m0 = (p0[0] + p1[0]) / 2.0, m1 = (p0[1] + p1[1]) / 2.0;
+                double le2 = dist2_nc(p1[0], p1[1], p0[0], p0[1], 2);
+                double hm = h2k > le2 ? h2k : le2;
+                int cls = order_class(dist2_nc(cx, cy, m0, m1, 2), hm, P.ncls, P.th2);
+                double M6[6] = {0, 0, 0, 0, 0, 0};
+                bnd_far2(X, fe, P.pe, P.kfb[cls], M6);
+                for (int m = 0; m < 6; ++m) acc[m] += fb * M6[m];
+            }
+        }
+        if (ntouch) atomicAdd(&P.counters[0], ntouch);
+        if (nfar) atomicAdd(&P.counters[1], nfar);
+    }
+    for (int m = 0; m < 6; ++m) P.S[(long long)K * 6 + m] += acc[m];
+}
+
+void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st) {
+    dim3 grid((P.T + 255) / 256), block(256);
+    if (P.dim == 2)
+        hipLaunchKernelGGL(self_kernel<2>, grid, block, 0, st, E, P);
+    else
+        hipLaunchKernelGGL(self_kernel<1>, grid, block, 0, st, E, P);
+}
+
+// ----------------------------------------------------- edge and vertex --
+
+__device__ __forceinline__ void edge_acc(const double* E, const double* ap, const double* bp,
+                                         double u, double v, double w, double wt, double pe,
+                                         double* M6) {
+    double z0 = w * E[0] + u * ap[0] - v * bp[0];
+    double z1 = w * E[1] + u * ap[1] - v * bp[1];
+    double kv = kpow(z0 * z0 + z1 * z1, pe) * wt;
+    double P[3] = {u, v, w};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) M6[sym3(a, b)] += kv * P[a] * P[b];
+}
+
+// Triangles sharing an edge: K = (q0,q1,a), Kt = (q0,q1,b), q0 < q1 by
+// vertex id.  Coordinates (u,v,w) relative to the edge, analytic radial
+// factor 1/((3-2s)(4-2s)), faces of the unit gauge surface: triangles F1,
+// F4 (order-k collapsed rule) and parallelograms F2, F3 (k x k Gauss).
+__global__ __launch_bounds__(256) void touch_edge2_kernel(ElemDev E, TouchParams P) {
+    const long long pid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid >= P.npairs) return;
+    const int K = P.pairs[2 * pid], Kt = P.pairs[2 * pid + 1];
+    int vk[3], vt[3];
+    double X[6], Y[6];
+    for (int a = 0; a < 3; ++a) { vk[a] = E.vid[a][K]; vt[a] = E.vid[a][Kt]; }
+    for (int c = 0; c < 6; ++c) { X[c] = E.x[c][K]; Y[c] = E.x[c][Kt]; }
+    int sk[2], st[2], ns = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (vk[a] == vt[b]) { sk[ns] = a; st[ns] = b; ++ns; }
+    if (ns != 2) return;
+    // order shared vertices by id
+    if (vk[sk[0]] > vk[sk[1]]) {
+        int t1 = sk[0]; sk[0] = sk[1]; sk[1] = t1;
+        int t2 = st[0]; st[0] = st[1]; st[1] = t2;
+    }
+    const int ia = 3 - sk[0] - sk[1], ib = 3 - st[0] - st[1];
+    const double q0[2] = {X[2 * sk[0]], X[2 * sk[0] + 1]};
+    const double q1[2] = {X[2 * sk[1]], X[2 * sk[1] + 1]};
+    const double Ev[2] = {q1[0] - q0[0], q1[1] - q0[1]};
+    const double ap[2] = {X[2 * ia] - q0[0], X[2 * ia + 1] - q0[1]};
+    const double bp[2] = {Y[2 * ib] - q0[0], Y[2 * ib + 1] - q0[1]};
+    const int k = P.k;
+    const int go = gl_off(k);
+    double M6[6] = {0, 0, 0, 0, 0, 0};
+    const double T1[3][3] = {{0, 1, 0}, {1, 1, 0}, {0, 1, 1}};
+    const double T4[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 0, -1}};
+    for (int f = 0; f < 2; ++f) {
+        const double(*T)[3] = f == 0 ? T1 : T4;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                double u1 = c_R.gj_x[go + i];
+                double l1 = u1, l2 = (1.0 - u1) * c_R.gl_x[go + j];
+                double wt = 2.0 * c_R.gj_w[go + i] * c_R.gl_w[go + j];
+                double Pp[3];
+                for (int c = 0; c < 3; ++c) Pp[c] = T[0][c] + l1 * (T[1][c] - T[0][c]) + l2 * (T[2][c] - T[0][c]);
+                edge_acc(Ev, ap, bp, Pp[0], Pp[1], Pp[2], 0.5 * wt, P.pe, M6);
+            }
+    }
+    const double P2[3][3] = {{1, 0, 0}, {0, 1, 0}, {-1, 0, 1}};
+    const double P3[3][3] = {{0, 1, 0}, {1, 0, 0}, {0, -1, -1}};
+    for (int f = 0; f < 2; ++f) {
+        const double(*T)[3] = f == 0 ? P2 : P3;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                double ti = c_R.gl_x[go + i], tj = c_R.gl_x[go + j];
+                double Pp[3];
+                for (int c = 0; c < 3; ++c) Pp[c] = T[0][c] + ti * T[1][c] + tj * T[2][c];
+                edge_acc(Ev, ap, bp, Pp[0], Pp[1], Pp[2], c_R.gl_w[go + i] * c_R.gl_w[go + j], P.pe, M6);
+            }
+    }
+    const double Cm[4][3] = {{-1, 1, -1}, {0, 0, 1}, {1, 0, 0}, {0, -1, 0}};
+    double aK = E.meas[K], aT = E.meas[Kt];
+    double f = P.C * 4.0 * aK * aT / ((3.0 - 2.0 * P.s) * (4.0 - 2.0 * P.s));
+    int g[4] = {E.dof[sk[0]][K], E.dof[sk[1]][K], E.dof[ia][K], E.dof[ib][Kt]};
+    for (int i = 0; i < 4; ++i) {
+        if (g[i] < 0) continue;
+        for (int j = 0; j < 4; ++j) {
+            if (g[j] < 0) continue;
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) acc += Cm[i][a] * M6[sym3(a, b)] * Cm[j][b];
+            atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * acc);
+        }
+    }
+}
+
+// Elements sharing one vertex.  2D: K = (q,b1,b2), Kt = (q,c1,c2), b1 < b2,
+// c1 < c2 by id; two prisms of the gauge max(X1+X2, X3+X4), analytic
+// radial factor 1/(4-2s).  1D: K = [l,q], Kt = [q,r], faces u = 1, v = 1,
+// radial factor 1/(3-2s).
+template <int DIM>
+__global__ __launch_bounds__(256) void touch_vert_kernel(ElemDev E, TouchParams P) {
+    const long long pid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid >= P.npairs) return;
+    const int K = P.pairs[2 * pid], Kt = P.pairs[2 * pid + 1];
+    const int k = P.k, go = gl_off(k);
+    if (DIM == 1) {
+        int vk[2] = {E.vid[0][K], E.vid[1][K]}, vt[2] = {E.vid[0][Kt], E.vid[1][Kt]};
+        double X[2] = {E.x[0][K], E.x[1][K]}, Y[2] = {E.x[0][Kt], E.x[1][Kt]};
+        int a = -1, b = -1;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (vk[i] == vt[j]) { a = i; b = j; }
+        if (a < 0) return;
+        double xq = X[a], xl = X[1 - a], xr = Y[1 - b];
+        double h1 = fabs(xl - xq), h2 = fabs(xr - xq);
+        double M[6] = {0, 0, 0, 0, 0, 0};
+        for (int face = 0; face < 2; ++face)
+            for (int i = 0; i < k; ++i) {
+                double t = c_R.gl_x[go + i];
+                double u = face == 0 ? 1.0 : t, v = face == 0 ? t : 1.0;
+                double N[3] = {u, v - u, -v};
+                double dd = h1 * u + h2 * v;
+                double kv = kpow(dd * dd, P.pe) * c_R.gl_w[go + i];
+                for (int p = 0; p < 3; ++p)
+                    for (int q = p; q < 3; ++q) M[sym3(p, q)] += kv * N[p] * N[q];
+            }
+        double f = P.C * h1 * h2 / (3.0 - 2.0 * P.s);
+        int g[3] = {E.dof[1 - a][K], E.dof[a][K], E.dof[1 - b][Kt]};
+        for (int i = 0; i < 3; ++i) {
+            if (g[i] < 0) continue;
+            for (int j = 0; j < 3; ++j) {
+                if (g[j] < 0) continue;
+                atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * M[sym3(i, j)]);
+            }
+        }
+        return;
+    }
+    int vk[3], vt[3];
+    double X[6], Y[6];
+    for (int a = 0; a < 3; ++a) { vk[a] = E.vid[a][K]; vt[a] = E.vid[a][Kt]; }
+    for (int c = 0; c < 6; ++c) { X[c] = E.x[c][K]; Y[c] = E.x[c][Kt]; }
+    int a = -1, b = -1;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (vk[i] == vt[j]) { a = i; b = j; }
+    if (a < 0) return;
+    int i1 = (a + 1) % 3, i2 = (a + 2) % 3, j1 = (b + 1) % 3, j2 = (b + 2) % 3;
+    if (vk[i1] > vk[i2]) { int t = i1; i1 = i2; i2 = t; }
+    if (vt[j1] > vt[j2]) { int t = j1; j1 = j2; j2 = t; }
+    const double qx = X[2 * a], qy = X[2 * a + 1];
+    const double g0[4] = {X[2 * i1] - qx, X[2 * i2] - qx, -(Y[2 * j1] - qx), -(Y[2 * j2] - qx)};
+    const double g1[4] = {X[2 * i1 + 1] - qy, X[2 * i2 + 1] - qy, -(Y[2 * j1 + 1] - qy), -(Y[2 * j2 + 1] - qy)};
+    double M[10];
+    for (int m = 0; m < 10; ++m) M[m] = 0.0;
+    for (int reg = 0; reg < 2; ++reg)
+        for (int i = 0; i < k; ++i)
+            for (int ii = 0; ii < k; ++ii)
+                for (int jj = 0; jj < k; ++jj) {
+                    double t = c_R.gl_x[go + i];
+                    double u1 = c_R.gj_x[go + ii];
+                    double l1 = u1, l2 = (1.0 - u1) * c_R.gl_x[go + jj];
+                    double tw = 2.0 * c_R.gj_w[go + ii] * c_R.gl_w[go + jj];
+                    double Xv[4];
+                    if (reg == 0) { Xv[0] = 1.0 - t; Xv[1] = t; Xv[2] = l1; Xv[3] = l2; }
+                    else { Xv[0] = l1; Xv[1] = l2; Xv[2] = 1.0 - t; Xv[3] = t; }
+                    double z0 = 0.0, z1 = 0.0;
+                    for (int c = 0; c < 4; ++c) { z0 += Xv[c] * g0[c]; z1 += Xv[c] * g1[c]; }
+                    double kv = kpow(z0 * z0 + z1 * z1, P.pe) * c_R.gl_w[go + i] * 0.5 * tw;
+                    int m = 0;
+                    for (int p = 0; p < 4; ++p)
+                        for (int q = p; q < 4; ++q) M[m++] += kv * Xv[p] * Xv[q];
+                }
+    // full 4x4 from packed
+    double F[4][4];
+    {
+        int m = 0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p; q < 4; ++q) { F[p][q] = M[m]; F[q][p] = M[m]; ++m; }
+    }
+    const double Cm[5][4] = {{-1, -1, 1, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, -1, 0}, {0, 0, 0, -1}};
+    double f = P.C * 4.0 * E.meas[K] * E.meas[Kt] / (4.0 - 2.0 * P.s);
+    int g[5] = {E.dof[a][K], E.dof[i1][K], E.dof[i2][K], E.dof[j1][Kt], E.dof[j2][Kt]};
+    for (int i = 0; i < 5; ++i) {
+        if (g[i] < 0) continue;
+        for (int j = 0; j < 5; ++j) {
+            if (g[j] < 0) continue;
+            double acc = 0.0;
+            for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q) acc += Cm[i][p] * F[p][q] * Cm[j][q];
+            atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * acc);
+        }
+    }
+}
+
+void launch_touch_edge2(const ElemDev& E, const TouchParams& P, hipStream_t st) {
+    if (P.npairs == 0) return;
+    dim3 grid((unsigned)((P.npairs + 255) / 256)), block(256);
+    hipLaunchKernelGGL(touch_edge2_kernel, grid, block, 0, st, E, P);
+}
+
+void launch_touch_vert(const ElemDev& E, const TouchParams& P, hipStream_t st) {
+    if (P.npairs == 0) return;
+    dim3 grid((unsigned)((P.npairs + 255) / 256)), block(256);
+    if (P.dim == 2)
+        hipLaunchKernelGGL(touch_vert_kernel<2>, grid, block, 0, st, E, P);
+    else
+        hipLaunchKernelGGL(touch_vert_kernel<1>, grid, block, 0, st, E, P);
+}
+
+// --------------------------------------------------- diagonal blocks --
+
+// One thread per vertex: for every element K containing it, add the row
+// of K's diagonal-block accumulator into A (only this thread writes the
+// row, so the result is deterministic).
+__global__ __launch_bounds__(256) void scatter_self_kernel(ElemDev E, const int* v2c_ptr,
+                                                           const int* v2c_idx, const int* node2dof,
+                                                           const unsigned char* vloc, int nv, int dim,
+                                                           const double* S, double* A, long long lda) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int i = node2dof[v];
+    if (i < 0) return;
+    double* row = A + (long long)i * lda;
+    for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
+        const int K = v2c_idx[e];
+        const int a = vloc[e];
+        for (int b = 0; b <= dim; ++b) {
+            int j = E.dof[b][K];
+            if (j < 0) continue;
+            row[j] += S[(long long)K * 6 + sym3(a, b)];
+        }
+    }
+}
+
+void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx,
+                         const int* node2dof, const unsigned char* vloc, int nv, int dim,
+                         const double* S, double* A, long long lda, hipStream_t st) {
+    dim3 grid((nv + 255) / 256), block(256);
+    hipLaunchKernelGGL(scatter_self_kernel, grid, block, 0, st, E, v2c_ptr, v2c_idx, node2dof, vloc,
+                       nv, dim, S, A, lda);
+}
+
+__global__ void zero_kernel(double* p, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0;
+}
+
+void launch_zero(double* p, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+}
+
+// b_i = sum_{K containing i} |K| / (d+1)  (f = 1)
+__global__ void load_one_kernel(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
+                                const double* meas, int dim, long long n, double* b) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int v = dof_node[i];
+    double acc = 0.0;
+    for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) acc += meas[v2c_idx[e]];
+    b[i] = acc / (double)(dim + 1);
+}
+
+void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
+                     const double* meas, int dim, long long n, double* b, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(load_one_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dof_node,
+                       v2c_ptr, v2c_idx, meas, dim, n, b);
+}
+
+// ---------------------------------------------------------------- solve --
+
+// Dense FP64 matvec: one wave per row, 16-byte loads, four independent
+// accumulators in flight; rows are padded to lda (multiple of 32).
+constexpr int MV_ROWS_PER_BLOCK = MV_THREADS / 64;
+
+int mv_blocks(long long n) { return (int)((n + MV_ROWS_PER_BLOCK - 1) / MV_ROWS_PER_BLOCK); }
+
+__device__ __forceinline__ double row_dot(const double* __restrict__ a, const double* __restrict__ x,
+                                          long long n, int lane) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const long long n2 = n & ~1LL;
+    long long j = 2 * lane;
+    // 4 x (64 lanes x 2 doubles) per trip
+    for (; j + 6 * 64 < n2; j += 8 * 64) {
+        double2 a0 = *(const double2*)(a + j), x0 = *(const double2*)(x + j);
+        double2 a1 = *(const double2*)(a + j + 128), x1 = *(const double2*)(x + j + 128);
+        double2 a2 = *(const double2*)(a + j + 256), x2 = *(const double2*)(x + j + 256);
+        double2 a3 = *(const double2*)(a + j + 384), x3 = *(const double2*)(x + j + 384);
+        acc0 += a0.x * x0.x + a0.y * x0.y;
+        acc1 += a1.x * x1.x + a1.y * x1.y;
+        acc2 += a2.x * x2.x + a2.y * x2.y;
+        acc3 += a3.x * x3.x + a3.y * x3.y;
+    }
+    for (; j < n2; j += 128) {
+        double2 a0 = *(const double2*)(a + j), x0 = *(const double2*)(x + j);
+        acc0 += a0.x * x0.x + a0.y * x0.y;
+    }
+    if ((n & 1) && lane == 0) acc1 += a[n - 1] * x[n - 1];
+    return wave_sum((acc0 + acc1) + (acc2 + acc3));
+}
+
+__global__ __launch_bounds__(MV_THREADS) void matvec_kernel(const double* __restrict__ A, long long lda,
+                                                            long long n, const double* __restrict__ x,
+                                                            double* __restrict__ y) {
+    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    double v = row_dot(A + row * lda, x, n, lane);
+    if (lane == 0) y[row] = v;
+}
+
+void launch_matvec(const double* A, long long lda, long long n, const double* x, double* y,
+                   hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(matvec_kernel, dim3(mv_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, y);
+}
+
+__global__ void diag_kernel(const double* A, long long lda, long long n, double* d) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = A[i * lda + i];
+}
+
+void launch_diag(const double* A, long long lda, long long n, double* d, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, lda, n, d);
+}
+
+// deterministic block reduction (256 threads)
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// sum of the first m partials, same order in every block
+__device__ __forceinline__ double sum_partials(const double* part, int m, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) v += part[i];
+    return block_sum(v, sh);
+}
+
+constexpr int VEC_BLOCK = 256;
+
+// CG state: scal[0..1] rz by parity, scal[2] bb, scal[3] rr
+// init: x = 0, r = b, z = r/d, p = z; partials of r.z and r.r
+__global__ __launch_bounds__(256) void cg_init_kernel(CgState S) {
+    __shared__ double sh[4];
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < S.n) {
+        double bi = S.b[i];
+        S.x[i] = 0.0;
+        S.r[i] = bi;
+        double zi = bi / S.d[i];
+        S.z[i] = zi;
+        S.p[i] = zi;
+        rz = bi * zi;
+        rr = bi * bi;
+    }
+    double a = block_sum(rz, sh), b = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        S.part[blockIdx.x] = a;
+        S.part[S.nblk + blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void cg_init_reduce_kernel(CgState S) {
+    __shared__ double sh[4];
+    double rz = sum_partials(S.part, S.nblk, sh);
+    double rr = sum_partials(S.part + S.nblk, S.nblk, sh);
+    if (threadIdx.x == 0) {
+        S.scal[0] = rz;
+        S.scal[2] = rr;  // bb
+        S.scal[3] = rr;
+        S.flag[0] = (rr == 0.0) ? 1 : 0;
+        S.flag[1] = 0;
+        S.flag[2] = 0;
+        if (!(rr == rr) || rr > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
+    }
+}
+
+// q = A p, partial sums of p.q per block (2*MV rows per block)
+__global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S) {
+    __shared__ double sh[4];
+    if (*(volatile int*)&S.flag[0]) return;
+    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double pq = 0.0;
+    if (row < S.n) {
+        double v = row_dot(S.A + row * S.lda, S.p, S.n, lane);
+        if (lane == 0) {
+            S.q[row] = v;
+            pq = v * S.p[row];
+        }
+    }
+    double t = block_sum(pq, sh);
+    if (threadIdx.x == 0) S.part[2 * S.nblk + blockIdx.x] = t;
+}
+
+// alpha = rz / p.q; x += alpha p; r -= alpha q; z = r/d; partials of r.z, r.r
+__global__ __launch_bounds__(256) void cg_update1_kernel(CgState S, int it, int nmv) {
+    __shared__ double sh[4];
+    if (*(volatile int*)&S.flag[0]) return;
+    double pq = sum_partials(S.part + 2 * S.nblk, nmv, sh);
+    double rz = S.scal[it & 1];
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) S.scal[6] = pq;
+        return;  // breakdown flagged in update2
+    }
+    double alpha = rz / pq;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < S.n) {
+        S.x[i] += alpha * S.p[i];
+        double ri = S.r[i] - alpha * S.q[i];
+        S.r[i] = ri;
+        double zi = ri / S.d[i];
+        S.z[i] = zi;
+        a = ri * zi;
+        b = ri * ri;
+    }
+    double ta = block_sum(a, sh), tb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        S.part[blockIdx.x] = ta;
+        S.part[S.nblk + blockIdx.x] = tb;
+    }
+}
+
+// beta = rz_new / rz; p = z + beta p; status update by block 0
+__global__ __launch_bounds__(256) void cg_update2_kernel(CgState S, int it, int nmv) {
+    __shared__ double sh[4];
+    if (*(volatile int*)&S.flag[0]) return;
+    double pq = sum_partials(S.part + 2 * S.nblk, nmv, sh);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.flag[0] = 1;
+            S.flag[2] = 1;
+        }
+        return;
+    }
+    double rzn = sum_partials(S.part, S.nblk, sh);
+    double rr = sum_partials(S.part + S.nblk, S.nblk, sh);
+    double rz = S.scal[it & 1];
+    double beta = rzn / rz;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < S.n) S.p[i] = S.z[i] + beta * S.p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.scal[(it + 1) & 1] = rzn;
+        S.scal[3] = rr;
+        S.flag[1] = it + 1;
+        double bb = S.scal[2];
+        if (sqrt(rr) <= S.rtol * sqrt(bb) || it + 1 >= S.maxit) S.flag[0] = 1;
+        if (!(rr == rr)) { S.flag[0] = 1; S.flag[2] = 2; }
+    }
+}
+
+void launch_cg_init(const CgState& s, hipStream_t st) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3(s.nblk), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(cg_init_reduce_kernel, dim3(1), dim3(256), 0, st, s);
+}
+
+void launch_cg_iter_at(const CgState& s, int it, hipStream_t st) {
+    int nmv = mv_blocks(s.n);
+    hipLaunchKernelGGL(cg_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s);
+    hipLaunchKernelGGL(cg_update1_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+    hipLaunchKernelGGL(cg_update2_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+}
+
+// out[0] = a.b, out[1] = a.c (deterministic two-pass)
+__global__ __launch_bounds__(256) void dot2_kernel(const double* a, const double* b, const double* c,
+                                                   long long n, double* part, int nblk) {
+    __shared__ double sh[4];
+    double s1 = 0.0, s2 = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)nblk * 256) {
+        s1 += a[i] * b[i];
+        s2 += a[i] * c[i];
+    }
+    double t1 = block_sum(s1, sh), t2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t1;
+        part[nblk + blockIdx.x] = t2;
+    }
+}
+
+__global__ __launch_bounds__(256) void dot2_reduce_kernel(const double* part, int nblk, double* out) {
+    __shared__ double sh[4];
+    double t1 = sum_partials(part, nblk, sh);
+    double t2 = sum_partials(part + nblk, nblk, sh);
+    if (threadIdx.x == 0) { out[0] = t1; out[1] = t2; }
+}
+
+void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
+                 int nblk, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(dot2_kernel, dim3(nblk), dim3(256), 0, st, a, b, c, n, part, nblk);
+    hipLaunchKernelGGL(dot2_reduce_kernel, dim3(1), dim3(256), 0, st, part, nblk, out);
+}
+
+}  // namespace fl

@@ -220,10 +220,10 @@ def _nvb_refine(verts, tris, marked_fn, max_pass=200):
     return np.array(verts), np.array(list(tris.values()))
 
 
-def lshape(h_max: float = 0.1, gamma: float = 1.0, ratio: float = 64.0):
+def lshape(h_max: float = 0.1, gamma: float = 1.0, ratio: float = 64.0, R: float = 1.0):
     """L-shape (-1,1)^2 minus [0,1)x(-1,0], graded by newest-vertex
     bisection: refine K while its longest edge exceeds
-    h_max * max(1/ratio, min(1, rho(c_K)^gamma)), rho = distance of the
+    h_max * max(1/ratio, min(1, (rho(c_K)/R)^gamma)), rho = distance of the
     centroid to the re-entrant corner or the boundary, whichever is
     smaller.  Deterministic (no random numbers)."""
     V = [(-1, -1), (0, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
@@ -248,13 +248,19 @@ def lshape(h_max: float = 0.1, gamma: float = 1.0, ratio: float = 64.0):
         cx = sum(p[0] for p in P) / 3
         cy = sum(p[1] for p in P) / 3
         rho = min(math.hypot(cx, cy), dist_boundary(cx, cy))
-        target = h_max * max(1.0 / ratio, min(1.0, rho ** gamma))
+        target = h_max * max(1.0 / ratio, min(1.0, (rho / R) ** gamma))
         hk = max(math.dist(P[i], P[(i + 1) % 3]) for i in range(3))
         return hk > target * 1.0000001
 
     verts, tris = _nvb_refine(V, T, marked)
     bf = _boundary_edges(tris)
     return _finish(2, verts, tris, bf)
+
+
+def lshape_config3():
+    """Graded L-shape with ~40k triangles and size ratio 1:64 toward the
+    re-entrant corner and the boundary."""
+    return lshape(0.3, 1.0, 64.0, 0.5)
 
 
 def tiny(kind: str):

@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/fraclap.h declares, and fills default options."""
+import os
+import re
+
+import pytest
+
+from paper_1708_03912_amd import fraclap as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fraclap.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fl_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_header_symbols():
+    L = F.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(F.EXPORTS) == names
+
+
+def test_default_opts_table():
+    o = F.default_opts()
+    assert o.dof_mode == F.FL_DOF_PAPER and o.with_boundary == 1
+    assert (o.k_touch, o.k_touch_bnd, o.n_classes) == (6, 6, 3)
+    assert [o.theta[i] for i in range(3)] == [1.5, 3.0, 6.0]
+    assert [o.k_far[i] for i in range(4)] == [4, 3, 2, 2]
+    assert [o.k_far_bnd[i] for i in range(4)] == [4, 3, 2, 2]
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of fl_opts / fl_stats_t agree with the C compiler."""
+    import ctypes as C
+    import subprocess
+    src = tmp_path / "lay.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "fraclap.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
+         offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres));
+  return 0; }
+""")
+    exe = tmp_path / "lay"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals == [C.sizeof(F.FlOpts), F.FlOpts.theta.offset, F.FlOpts.k_far_bnd.offset,
+                    C.sizeof(F.FlStats), F.FlStats.last_relres.offset]
+
+
+def test_no_cpu_fallback_in_binding():
+    """The binding only marshals arguments: it must not import the oracle."""
+    src = open(os.path.join(ROOT, "paper_1708_03912_amd", "fraclap.py")).read()
+    assert "oracle" not in src.replace("oracle/", "")
