@@ -30,7 +30,9 @@
  *     enqueued on the stream given to fl_create (in order, asynchronous
  *     unless a host output is returned, in which case the call
  *     synchronises that stream);
- *   - one handle per stream; a handle is not thread safe.
+ *   - one handle per stream; a handle is not thread safe;
+ *   - when the assembly has no degrees of freedom (n = 0) every vector /
+ *     matrix argument may be NULL and the calls succeed without work.
  */
 #ifndef FRACLAP_H
 #define FRACLAP_H

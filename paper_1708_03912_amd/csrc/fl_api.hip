@@ -430,10 +430,37 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     }
     // far-field tiles and per-block local DOF numbering
     const int nblk = (int)((T + BE - 1) / BE);
-    std::vector<int2> tiles;
-    tiles.reserve((size_t)nblk * (nblk + 1) / 2);
-    for (int bi = 0; bi < nblk; ++bi)
-        for (int bj = bi; bj < nblk; ++bj) tiles.push_back(make_int2(bi, bj));
+    // Tiles of block pairs bi <= bj.  A tile is "far" when the bounding boxes
+    // of the two blocks' centroids are so far apart that every pair is
+    // separated (centroid distance > 2 h_max excludes a common vertex) and in
+    // the last distance class; such tiles skip the per-pair classification.
+    std::vector<int2> tiles, far_tiles;
+    {
+        std::vector<double> bx0(nblk, 1e300), bx1(nblk, -1e300), by0(nblk, 1e300), by1(nblk, -1e300),
+            bh(nblk, 0.0);
+        for (int64_t Ki = 0; Ki < T; ++Ki) {
+            int b = (int)(Ki / BE);
+            bx0[b] = std::min(bx0[b], cen0[Ki]);
+            bx1[b] = std::max(bx1[b], cen0[Ki]);
+            by0[b] = std::min(by0[b], cen1[Ki]);
+            by1[b] = std::max(by1[b], cen1[Ki]);
+            bh[b] = std::max(bh[b], h2[Ki]);
+        }
+        double th_last2 = 4.0;
+        if (o.n_classes > 0) th_last2 = std::max(4.0, o.theta[o.n_classes - 1] * o.theta[o.n_classes - 1]);
+        const bool use_far = o.k_far[o.n_classes] <= 4;
+        for (int bi = 0; bi < nblk; ++bi)
+            for (int bj = bi; bj < nblk; ++bj) {
+                bool far = false;
+                if (use_far && bi != bj) {
+                    double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
+                    double dy = std::max(0.0, std::max(by0[bj] - by1[bi], by0[bi] - by1[bj]));
+                    double d2 = dx * dx + dy * dy;
+                    far = d2 > th_last2 * std::max(bh[bi], bh[bj]) * (1.0 + 1e-9);
+                }
+                (far ? far_tiles : tiles).push_back(make_int2(bi, bj));
+            }
+    }
     std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
     std::vector<unsigned char> loc(T * 3, 255);
     {
@@ -535,9 +562,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     h->E = E;
     h->d_meas = dme;
     int2* dtiles;
+    int2* dftiles = nullptr;
     int *dbnd, *dbdofs, *dv2cp, *dv2ci, *dn2d, *ddn, *dep = nullptr, *dvp = nullptr, *dfvid = nullptr;
     unsigned char *dloc, *dvloc;
     double* dfac = nullptr;
+    if ((rc = upload(h, far_tiles, &dftiles))) return rc;
     if ((rc = upload(h, tiles, &dtiles)) || (rc = upload(h, blk_ndof, &dbnd)) ||
         (rc = upload(h, blk_dofs, &dbdofs)) || (rc = upload(h, loc, &dloc)) ||
         (rc = upload(h, v2c_ptr, &dv2cp)) || (rc = upload(h, v2c_idx, &dv2ci)) ||
@@ -578,6 +607,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     FP.ncls = o.n_classes;
     for (int m = 0; m < o.n_classes; ++m) FP.th2[m] = o.theta[m] * o.theta[m];
     for (int m = 0; m <= o.n_classes; ++m) FP.kf[m] = o.k_far[m];
+    for (int m = 0; m <= o.n_classes; ++m) {
+        FP.kfirst[m] = 1;
+        for (int j = 0; j < m; ++j)
+            if (o.k_far[j] == o.k_far[m]) FP.kfirst[m] = 0;
+    }
     FP.nblk = nblk;
     FP.tiles = dtiles;
     FP.ntiles = (long long)tiles.size();
@@ -590,6 +624,13 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     FP.cls_count = dcnt;
     launch_far(E, FP, h->stream);
     HIPCHK(hipGetLastError());
+    {
+        FarParams FF = FP;
+        FF.tiles = dftiles;
+        FF.ntiles = (long long)far_tiles.size();
+        launch_far_tiles(E, FF, o.k_far[o.n_classes], h->stream);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipEventRecord(ev[1], h->stream));
 
     BndParams BP{};
@@ -687,15 +728,19 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
 }
 
 int fl_dofs(const fl_handle* h, int32_t* node_of_dof) {
-    if (!h || !node_of_dof) return FL_EINVAL;
+    if (!h) return FL_EINVAL;
     if (!h->assembled) return FL_ESTATE;
+    if (h->n == 0) return FL_OK;
+    if (!node_of_dof) return FL_EINVAL;
     std::memcpy(node_of_dof, h->dof_node.data(), sizeof(int32_t) * h->n);
     return FL_OK;
 }
 
 int fl_export_matrix(fl_handle* h, double* dst, int64_t ld, int on_device) {
-    if (!h || !dst) return FL_EINVAL;
+    if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (h->n == 0) return FL_OK;
+    if (!dst) return fail(h, FL_EINVAL, "null destination");
     if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
     HIPCHK(hipSetDevice(h->device));
     if (h->n == 0) return FL_OK;
@@ -707,8 +752,10 @@ int fl_export_matrix(fl_handle* h, double* dst, int64_t ld, int on_device) {
 }
 
 int fl_load_vector_one(fl_handle* h, double* b) {
-    if (!h || !b) return FL_EINVAL;
+    if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembly");
+    if (h->n == 0) return FL_OK;
+    if (!b) return fail(h, FL_EINVAL, "null vector");
     HIPCHK(hipSetDevice(h->device));
     launch_load_one(h->d_dof_node, h->d_v2c_ptr, h->d_v2c_idx, h->d_meas, h->dim, h->n, b, h->stream);
     HIPCHK(hipGetLastError());
@@ -716,8 +763,10 @@ int fl_load_vector_one(fl_handle* h, double* b) {
 }
 
 int fl_matvec(fl_handle* h, const double* x, double* y) {
-    if (!h || !x || !y) return FL_EINVAL;
+    if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (h->n == 0) return FL_OK;
+    if (!x || !y) return fail(h, FL_EINVAL, "null vector");
     if (x == y) return fail(h, FL_EINVAL, "x and y must not alias");
     HIPCHK(hipSetDevice(h->device));
     launch_matvec(h->dA, h->lda, h->n, x, y, h->stream);
@@ -741,15 +790,16 @@ static int ensure_solver(fl_handle* h) {
 
 int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
              double* relres) {
-    if (!h || !b || !u) return FL_EINVAL;
+    if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
     if (!(rtol >= 0.0) || maxit < 0) return fail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
-    HIPCHK(hipSetDevice(h->device));
     if (h->n == 0) {
         if (iters) *iters = 0;
         if (relres) *relres = 0.0;
         return FL_OK;
     }
+    if (!b || !u) return fail(h, FL_EINVAL, "null vector");
+    HIPCHK(hipSetDevice(h->device));
     int rc = ensure_solver(h);
     if (rc) return rc;
     const int64_t n = h->n;
@@ -814,13 +864,14 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
 }
 
 int fl_energy_error2(fl_handle* h, double fu, const double* b, const double* uh, double* e2_out) {
-    if (!h || !b || !uh || !e2_out) return FL_EINVAL;
+    if (!h || !e2_out) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
-    HIPCHK(hipSetDevice(h->device));
     if (h->n == 0) {
         *e2_out = fu;
         return FL_OK;
     }
+    if (!b || !uh) return fail(h, FL_EINVAL, "null vector");
+    HIPCHK(hipSetDevice(h->device));
     int rc = ensure_solver(h);
     if (rc) return rc;
     const int64_t n = h->n;

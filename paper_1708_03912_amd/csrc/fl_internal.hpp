@@ -48,6 +48,7 @@ struct FarParams {
     int ncls;
     double th2[FL_MAX_CLASSES];
     int kf[FL_MAX_CLASSES + 1];
+    int kfirst[FL_MAX_CLASSES + 1];  // 1 if no lower class has the same order
     int nblk;
     const int2* tiles;      // (bi, bj), bi <= bj
     long long ntiles;
@@ -89,7 +90,10 @@ struct BndParams {
 
 // launch wrappers (fl_kernels.hip)
 hipError_t upload_rules(const RuleTables& R, hipStream_t st);
+// General tiles (per-pair classification) and far tiles (every pair of the
+// block pair provably in the last class: fixed order fark, no touching).
 void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st);
+void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_t st);
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st);
 void launch_touch_edge2(const ElemDev& E, const TouchParams& P, hipStream_t st);
 void launch_touch_vert(const ElemDev& E, const TouchParams& P, hipStream_t st);

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fl_internal.hpp"
+#include "fl_math.hpp"
 
 namespace fl {
 
@@ -23,9 +24,6 @@ hipError_t upload_rules(const RuleTables& R, hipStream_t st) {
     return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_R), &R, sizeof(RuleTables), 0,
                                   hipMemcpyHostToDevice, st);
 }
-
-// |x-y|^{-d-2s} = (r^2)^{pe}, pe = -(d/2+s)
-__device__ __forceinline__ double kpow(double r2, double pe) { return exp2(pe * log2(r2)); }
 
 __device__ __forceinline__ int sym3(int a, int b) {
     // upper-triangular slot of (a,b), a <= b, in a 3x3 symmetric block
@@ -40,32 +38,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ----------------------------------------------------------- separated --
 
-// Separated triangles with the order-KO collapsed rule on both.  X, Y:
+// Separated triangles with the order-k collapsed rule on both.  X, Y:
 // vertex coordinates.  Outputs raw sums without area / C factors:
 //   SK[sym] = sum_pq w_p w_q l_a l_b(x_p) k,  ST likewise with y_q,
 //   O[3a+b] = sum_pq w_p w_q l_a(x_p) l_b(y_q) k.
 // Loop order q (points of Kt) outside, p (points of K) inside; the inner
 // loop carries only scalar accumulators, every rule-dependent factor
-// (w, w l_a, w l_a l_b) comes from the constant table.
+// (w, w l_a, w l_a l_b) comes from the constant table.  k is uniform across
+// the wave, so the table reads are scalar loads.  KO > 0 fixes k = KO at
+// compile time (inner loop unrolled: its KO^2 kernel evaluations are
+// independent); KO = 0 takes k at run time.
 template <int KO>
-__device__ __forceinline__ void far_pair2(const double* X, const double* Y, double pe,
+__device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, double pe,
                                           double* SK, double* ST, double* O) {
-    constexpr int Q = KO * KO;
-    const int off = tri_off(KO);
+    if (KO > 0) k = KO;
+    const int Q = k * k;
+    const int off = tri_off(k);
 #pragma unroll
     for (int m = 0; m < 6; ++m) { SK[m] = 0.0; ST[m] = 0.0; }
 #pragma unroll
     for (int m = 0; m < 9; ++m) O[m] = 0.0;
     const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
     const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
         const double* cq = c_R.tri[off + q];
         const double yx = Y[0] + cq[0] * fx0 + cq[1] * fx1;
         const double yy = Y[1] + cq[0] * fy0 + cq[1] * fy1;
         double gy = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
-#pragma unroll 2
-        for (int p = 0; p < Q; ++p) {
+        auto body = [&](int p) {
             const double* cp = c_R.tri[off + p];
             const double dx = (X[0] + cp[0] * ex0 + cp[1] * ex1) - yx;
             const double dy = (X[1] + cp[0] * ey0 + cp[1] * ey1) - yy;
@@ -80,6 +82,13 @@ __device__ __forceinline__ void far_pair2(const double* X, const double* Y, doub
             t3 += cp[9] * kv;
             t4 += cp[10] * kv;
             t5 += cp[11] * kv;
+        };
+        if constexpr (KO > 0) {
+#pragma unroll
+            for (int p = 0; p < KO * KO; ++p) body(p);
+        } else {
+#pragma unroll 1
+            for (int p = 0; p < Q; ++p) body(p);
         }
         const double wq = cq[2];
         SK[0] += wq * t0; SK[1] += wq * t1; SK[2] += wq * t2;
@@ -94,23 +103,23 @@ __device__ __forceinline__ void far_pair2(const double* X, const double* Y, doub
     }
 }
 
-// Separated segments, KO-point Gauss-Legendre on both (same outputs, slots
+// Separated segments, k-point Gauss-Legendre on both (same outputs, slots
 // 0,1,3 of the symmetric blocks and 0,1,3,4 of O).
-template <int KO>
-__device__ __forceinline__ void far_pair1(const double* X, const double* Y, double pe,
+__device__ __forceinline__ void far_pair1(int k, const double* X, const double* Y, double pe,
                                           double* SK, double* ST, double* O) {
-    const int off = gl_off(KO);
+    const int off = gl_off(k);
 #pragma unroll
     for (int m = 0; m < 6; ++m) { SK[m] = 0.0; ST[m] = 0.0; }
 #pragma unroll
     for (int m = 0; m < 9; ++m) O[m] = 0.0;
     const double ex = X[1] - X[0], fx = Y[1] - Y[0];
-    for (int q = 0; q < KO; ++q) {
+#pragma unroll 1
+    for (int q = 0; q < k; ++q) {
         const double* cq = c_R.seg[off + q];
         const double yv = Y[0] + cq[0] * fx;
         double gy = 0.0, n0 = 0.0, n1 = 0.0, t0 = 0.0, t1 = 0.0, t3 = 0.0;
-#pragma unroll 2
-        for (int p = 0; p < KO; ++p) {
+#pragma unroll 1
+        for (int p = 0; p < k; ++p) {
             const double* cp = c_R.seg[off + p];
             const double d = (X[0] + cp[0] * ex) - yv;
             const double kv = kpow(d * d, pe);
@@ -133,27 +142,9 @@ template <int DIM>
 __device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe,
                                          double* SK, double* ST, double* O) {
     if (DIM == 2) {
-        switch (k) {
-            case 1: far_pair2<1>(X, Y, pe, SK, ST, O); break;
-            case 2: far_pair2<2>(X, Y, pe, SK, ST, O); break;
-            case 3: far_pair2<3>(X, Y, pe, SK, ST, O); break;
-            case 4: far_pair2<4>(X, Y, pe, SK, ST, O); break;
-            case 5: far_pair2<5>(X, Y, pe, SK, ST, O); break;
-            case 6: far_pair2<6>(X, Y, pe, SK, ST, O); break;
-            case 7: far_pair2<7>(X, Y, pe, SK, ST, O); break;
-            default: far_pair2<8>(X, Y, pe, SK, ST, O); break;
-        }
+        far_pair2<0>(k, X, Y, pe, SK, ST, O);
     } else {
-        switch (k) {
-            case 1: far_pair1<1>(X, Y, pe, SK, ST, O); break;
-            case 2: far_pair1<2>(X, Y, pe, SK, ST, O); break;
-            case 3: far_pair1<3>(X, Y, pe, SK, ST, O); break;
-            case 4: far_pair1<4>(X, Y, pe, SK, ST, O); break;
-            case 5: far_pair1<5>(X, Y, pe, SK, ST, O); break;
-            case 6: far_pair1<6>(X, Y, pe, SK, ST, O); break;
-            case 7: far_pair1<7>(X, Y, pe, SK, ST, O); break;
-            default: far_pair1<8>(X, Y, pe, SK, ST, O); break;
-        }
+        far_pair1(k, X, Y, pe, SK, ST, O);
     }
 }
 
@@ -161,7 +152,7 @@ __device__ __forceinline__ void far_pair(int k, const double* X, const double* Y
 // sum is rounded on its own (contraction into FMA is switched off here), so
 // the class of every pair, ties included, is reproducible bit for bit by an
 // independent implementation of the same formula.
-__device__ __noinline__ int order_class(double d2, double hmax2, int ncls, const double* th2) {
+__device__ __forceinline__ int order_class(double d2, double hmax2, int ncls, const double* th2) {
 #pragma clang fp contract(off)
     int c = 0;
     for (int m = 0; m < ncls; ++m) {
@@ -172,7 +163,7 @@ __device__ __noinline__ int order_class(double d2, double hmax2, int ncls, const
 }
 
 // squared distance of two points in DIM dimensions, no contraction
-__device__ __noinline__ double dist2_nc(double x0, double y0, double x1, double y1, int dim) {
+__device__ __forceinline__ double dist2_nc(double x0, double y0, double x1, double y1, int dim) {
 #pragma clang fp contract(off)
     double dx = x0 - x1;
     double d2 = dx * dx;
@@ -189,7 +180,7 @@ __device__ __noinline__ double dist2_nc(double x0, double y0, double x1, double 
 // are accumulated in LDS over the block's local DOF numbering and flushed
 // to A (and its mirror) with one global atomic per touched entry; the
 // diagonal-block increments go to per-element accumulators S.
-template <int DIM>
+template <int DIM, int FARK>
 __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
@@ -199,6 +190,8 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     __shared__ int vI[MAXV], vJ[MAXV];
     __shared__ unsigned char locI[BE * 3], locJ[BE * 3];
     __shared__ unsigned long long ccount[FL_MAX_CLASSES + 1];
+    __shared__ double sI[10][BE];  // row elements: coordinates, centroid, h^2, |K|
+    __shared__ int sV[3][BE];      // row elements: vertex ids
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -223,6 +216,23 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     }
     for (int i = tid; i < BE * 6; i += 256) { SI[i] = 0.0; SJ[i] = 0.0; }
     if (tid <= FL_MAX_CLASSES) ccount[tid] = 0;
+    for (int i = tid; i < 13 * BE; i += 256) {
+        const int f = i / BE, r = i - f * BE, K = I0 + r;
+        if (f < 10) {
+            double v = 0.0;
+            if (K < T) {
+                if (f < NC) v = E.x[f][K];
+                else if (f == 6) v = E.cen[0][K];
+                else if (f == 7 && DIM == 2) v = E.cen[1][K];
+                else if (f == 8) v = E.h2[K];
+                else if (f == 9) v = E.meas[K];
+            }
+            sI[f][r] = v;
+        } else {
+            const int a = f - 10;
+            sV[a][r] = (K < T && a < NV) ? E.vid[a][K] : -2;
+        }
+    }
     __syncthreads();
 
     const int Kt = J0 + lane;
@@ -243,25 +253,30 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     for (int r = wave; r < BE; r += 4) {
         const int K = I0 + r;
         if (K >= T) break;
-        double X[6] = {0, 0, 0, 0, 0, 0}, cx[2] = {0, 0};
+        double X[6] = {0, 0, 0, 0, 0, 0};
         int vk[3] = {-2, -2, -2};
 #pragma unroll
-        for (int c = 0; c < NC; ++c) X[c] = E.x[c][K];
-        for (int c = 0; c < DIM; ++c) cx[c] = E.cen[c][K];
-        const double h2k = E.h2[K], mk = E.meas[K];
+        for (int c = 0; c < NC; ++c) X[c] = sI[c][r];
+        const double cx[2] = {sI[6][r], sI[7][r]};
+        const double h2k = sI[8][r], mk = sI[9][r];
 #pragma unroll
-        for (int a = 0; a < NV; ++a) vk[a] = E.vid[a][K];
+        for (int a = 0; a < NV; ++a) vk[a] = sV[a][r];
 
         bool valid = okt && (bi != bj || K < Kt);
-#pragma unroll
-        for (int a = 0; a < NV; ++a)
-#pragma unroll
-            for (int b = 0; b < NV; ++b) valid = valid && (vk[a] != vt[b]);
         int cls = -1;
-        if (valid) {
-            const double d2 = dist2_nc(cx[0], cx[1], cyt[0], cyt[1], DIM);
-            double hm = h2k > h2t ? h2k : h2t;
-            cls = order_class(d2, hm, P.ncls, P.th2);
+        if (FARK > 0) {
+            // far tile: the host proved every pair separated and in the last class
+            if (valid) cls = P.ncls;
+        } else {
+#pragma unroll
+            for (int a = 0; a < NV; ++a)
+#pragma unroll
+                for (int b = 0; b < NV; ++b) valid = valid && (vk[a] != vt[b]);
+            if (valid) {
+                const double d2 = dist2_nc(cx[0], cx[1], cyt[0], cyt[1], DIM);
+                double hm = h2k > h2t ? h2k : h2t;
+                cls = order_class(d2, hm, P.ncls, P.th2);
+            }
         }
 #pragma unroll
         for (int c = 0; c <= FL_MAX_CLASSES; ++c) {
@@ -272,9 +287,25 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
         }
         double SK[6] = {0, 0, 0, 0, 0, 0}, ST[6] = {0, 0, 0, 0, 0, 0};
         double O[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int c = 0; c <= P.ncls; ++c) {
-            if (__any(cls == c)) {
-                if (cls == c) far_pair<DIM>(P.kf[c], X, Y, P.pe, SK, ST, O);
+        if (FARK > 0) {
+            if (valid) {
+                if (DIM == 2)
+                    far_pair2<FARK>(FARK, X, Y, P.pe, SK, ST, O);
+                else
+                    far_pair1(FARK, X, Y, P.pe, SK, ST, O);
+            }
+        } else {
+            // one pass per distinct order present in the wave
+            int myk = 0;
+#pragma unroll
+            for (int m = 0; m <= FL_MAX_CLASSES; ++m)
+                if (m <= P.ncls && cls == m) myk = P.kf[m];
+            for (int c = 0; c <= P.ncls; ++c) {
+                if (!P.kfirst[c]) continue;
+                const int kc = P.kf[c];
+                if (__any(myk == kc)) {
+                    if (myk == kc) far_pair<DIM>(kc, X, Y, P.pe, SK, ST, O);
+                }
             }
         }
         const double f = valid ? P.C * mk * mt : 0.0;
@@ -344,13 +375,209 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     if (tid <= P.ncls && ccount[tid]) atomicAdd(&P.cls_count[tid], ccount[tid]);
 }
 
+// Near tiles: the pairs of the tile are classified first and bucketed by
+// class (counting sort in LDS), then every thread takes one pair of a
+// bucket at a time, so all lanes of a wave run the same order.  Diagonal
+// blocks, self terms and off-diagonal blocks are accumulated in LDS as in
+// far_kernel and flushed once per tile.
+template <int DIM>
+__global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
+    constexpr int NV = DIM + 1;
+    constexpr int NC = NV * DIM;
+    __shared__ double L[MAXV * MAXV];
+    __shared__ double SI[BE * 6];
+    __shared__ double SJ[BE * 6];
+    __shared__ double sI[10][BE], sJ[10][BE];
+    __shared__ int sVI[3][BE], sVJ[3][BE];
+    __shared__ int vI[MAXV], vJ[MAXV];
+    __shared__ unsigned char locI[BE * 3], locJ[BE * 3];
+    __shared__ unsigned char pcls[BE * BE];
+    __shared__ unsigned short plist[BE * BE];
+    __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
+
+    const long long t = blockIdx.x;
+    const int2 tb = P.tiles[t];
+    const int bi = tb.x, bj = tb.y;
+    const int I0 = bi * BE, J0 = bj * BE;
+    const int tid = threadIdx.x;
+    const int nVI = P.blk_ndof[bi], nVJ = P.blk_ndof[bj];
+    const bool direct = (nVI > MAXV) || (nVJ > MAXV);
+    const int T = P.T;
+
+    for (int i = tid; i < BE * 3; i += 256) {
+        int K = I0 + i / 3, Kt = J0 + i / 3;
+        locI[i] = (K < T) ? P.loc[(long long)K * 3 + i % 3] : 255;
+        locJ[i] = (Kt < T) ? P.loc[(long long)Kt * 3 + i % 3] : 255;
+    }
+    if (!direct) {
+        for (int i = tid; i < MAXV; i += 256) {
+            vI[i] = P.blk_dofs[(long long)bi * MAXV + i];
+            vJ[i] = P.blk_dofs[(long long)bj * MAXV + i];
+        }
+        for (int i = tid; i < nVI * nVJ; i += 256) L[i] = 0.0;
+    }
+    for (int i = tid; i < BE * 6; i += 256) { SI[i] = 0.0; SJ[i] = 0.0; }
+    if (tid <= FL_MAX_CLASSES) { ccnt[tid] = 0; cfill[tid] = 0; }
+    for (int i = tid; i < 13 * BE; i += 256) {
+        const int f = i / BE, r = i - f * BE;
+        const int K = I0 + r, Kt = J0 + r;
+        if (f < 10) {
+            double a = 0.0, b = 0.0;
+            if (f < NC) {
+                if (K < T) a = E.x[f][K];
+                if (Kt < T) b = E.x[f][Kt];
+            } else if (f == 6) {
+                if (K < T) a = E.cen[0][K];
+                if (Kt < T) b = E.cen[0][Kt];
+            } else if (f == 7 && DIM == 2) {
+                if (K < T) a = E.cen[1][K];
+                if (Kt < T) b = E.cen[1][Kt];
+            } else if (f == 8) {
+                if (K < T) a = E.h2[K];
+                if (Kt < T) b = E.h2[Kt];
+            } else if (f == 9) {
+                if (K < T) a = E.meas[K];
+                if (Kt < T) b = E.meas[Kt];
+            }
+            sI[f][r] = a;
+            sJ[f][r] = b;
+        } else {
+            const int a = f - 10;
+            sVI[a][r] = (K < T && a < NV) ? E.vid[a][K] : -2;
+            sVJ[a][r] = (Kt < T && a < NV) ? E.vid[a][Kt] : -3;
+        }
+    }
+    __syncthreads();
+    // classify
+    for (int pidx = tid; pidx < BE * BE; pidx += 256) {
+        const int r = pidx / BE, l = pidx - r * BE;
+        const int K = I0 + r, Kt = J0 + l;
+        bool valid = K < T && Kt < T && (bi != bj || K < Kt);
+#pragma unroll
+        for (int a = 0; a < NV; ++a)
+#pragma unroll
+            for (int b = 0; b < NV; ++b) valid = valid && (sVI[a][r] != sVJ[b][l]);
+        unsigned char c = 255;
+        if (valid) {
+            const double d2 = dist2_nc(sI[6][r], sI[7][r], sJ[6][l], sJ[7][l], DIM);
+            const double hm = sI[8][r] > sJ[8][l] ? sI[8][r] : sJ[8][l];
+            c = (unsigned char)order_class(d2, hm, P.ncls, P.th2);
+            atomicAdd(&ccnt[c], 1);
+        }
+        pcls[pidx] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int c = 0; c <= P.ncls; ++c) { coff[c] = acc; acc += ccnt[c]; }
+        coff[P.ncls + 1] = acc;
+    }
+    __syncthreads();
+    for (int pidx = tid; pidx < BE * BE; pidx += 256) {
+        const unsigned char c = pcls[pidx];
+        if (c == 255) continue;
+        const int slot = coff[c] + atomicAdd(&cfill[c], 1);
+        plist[slot] = (unsigned short)pidx;
+    }
+    __syncthreads();
+    // one class at a time, one pair per thread
+    for (int c = 0; c <= P.ncls; ++c) {
+        const int k = P.kf[c];
+        for (int base = coff[c]; base < coff[c + 1]; base += 256) {
+            const int slot = base + tid;
+            if (slot >= coff[c + 1]) continue;
+            const int pidx = plist[slot];
+            const int r = pidx / BE, l = pidx - r * BE;
+            double X[6] = {0, 0, 0, 0, 0, 0}, Y[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NC; ++q) { X[q] = sI[q][r]; Y[q] = sJ[q][l]; }
+            double SK[6], ST[6], O[9];
+            far_pair<DIM>(k, X, Y, P.pe, SK, ST, O);
+            const double f = P.C * sI[9][r] * sJ[9][l];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                if (SK[m] != 0.0) atomicAdd(&SI[r * 6 + m], f * SK[m]);
+                if (ST[m] != 0.0) atomicAdd(&SJ[l * 6 + m], f * ST[m]);
+            }
+            if (!direct) {
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    int ra = locI[r * 3 + a];
+                    if (ra == 255) continue;
+#pragma unroll
+                    for (int b = 0; b < NV; ++b) {
+                        int cb = locJ[l * 3 + b];
+                        if (cb == 255) continue;
+                        double v = -f * O[3 * a + b];
+                        atomicAdd(&L[ra * nVJ + cb], v);
+                        if (bi == bj) atomicAdd(&L[cb * nVJ + ra], v);
+                    }
+                }
+            } else {
+                const int K = I0 + r, Kt = J0 + l;
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    int ga = E.dof[a][K];
+                    if (ga < 0) continue;
+#pragma unroll
+                    for (int b = 0; b < NV; ++b) {
+                        int gb = E.dof[b][Kt];
+                        if (gb < 0) continue;
+                        double v = -f * O[3 * a + b];
+                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!direct) {
+        for (int i = tid; i < nVI * nVJ; i += 256) {
+            double v = L[i];
+            if (v == 0.0) continue;
+            int rr = i / nVJ, cc = i - rr * nVJ;
+            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+            if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+        }
+    }
+    for (int i = tid; i < BE * 6; i += 256) {
+        int K = I0 + i / 6, Kt2 = J0 + i / 6;
+        if (K < T && SI[i] != 0.0) atomicAdd(&P.S[(long long)K * 6 + i % 6], SI[i]);
+        if (Kt2 < T && SJ[i] != 0.0) atomicAdd(&P.S[(long long)Kt2 * 6 + i % 6], SJ[i]);
+    }
+    if (tid <= P.ncls && ccnt[tid]) atomicAdd(&P.cls_count[tid], (unsigned long long)ccnt[tid]);
+}
+
 void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
     if (P.dim == 2)
-        hipLaunchKernelGGL(far_kernel<2>, grid, block, 0, st, E, P);
+        hipLaunchKernelGGL((near_kernel<2>), grid, block, 0, st, E, P);
     else
-        hipLaunchKernelGGL(far_kernel<1>, grid, block, 0, st, E, P);
+        hipLaunchKernelGGL((near_kernel<1>), grid, block, 0, st, E, P);
+}
+
+void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_t st) {
+    if (P.ntiles == 0) return;
+    dim3 grid((unsigned)P.ntiles), block(256);
+#define FL_FAR_CASE(D, K) hipLaunchKernelGGL((far_kernel<D, K>), grid, block, 0, st, E, P)
+    if (P.dim == 2) {
+        switch (fark) {
+            case 1: FL_FAR_CASE(2, 1); break;
+            case 2: FL_FAR_CASE(2, 2); break;
+            case 3: FL_FAR_CASE(2, 3); break;
+            default: FL_FAR_CASE(2, 4); break;
+        }
+    } else {
+        switch (fark) {
+            case 1: FL_FAR_CASE(1, 1); break;
+            case 2: FL_FAR_CASE(1, 2); break;
+            case 3: FL_FAR_CASE(1, 3); break;
+            default: FL_FAR_CASE(1, 4); break;
+        }
+    }
+#undef FL_FAR_CASE
 }
 
 // ------------------------------------------------ identical + boundary --
@@ -506,14 +733,18 @@ __device__ void bnd_vert2(const double* q, const double* b1, const double* b2, c
         for (int b = 0; b < 3; ++b) M[3 * a + b] = f * acc[sym3(a, b)];
 }
 
-// One thread per element: identical-pair term (weight C/2) and the boundary
-// term sum_e a^{Kxe} (weight C/(2s)), added to the element's diagonal-block
-// accumulator S (after the far-field kernel, so this thread is S[K]'s only
-// writer).
+constexpr int FACET_CHUNK = 4;
+
+// One thread per (element, chunk of FACET_CHUNK boundary facets): the
+// boundary term sum_e a^{Kxe} over the chunk (weight C/(2s)); the thread of
+// chunk 0 adds the identical-pair term (weight C/2).  The partial 3x3 block
+// is added to the element's diagonal-block accumulator S atomically.
 template <int DIM>
 __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
     const int K = blockIdx.x * blockDim.x + threadIdx.x;
     if (K >= P.T) return;
+    const int e_lo = blockIdx.y * FACET_CHUNK;
+    const int e_hi = min(P.nb, e_lo + FACET_CHUNK);
     constexpr int NV = DIM + 1;
     double X[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < NV * DIM; ++c) X[c] = E.x[c][K];
@@ -521,7 +752,8 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
     for (int a = 0; a < NV; ++a) vk[a] = E.vid[a][K];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     // identical pair
-    if (DIM == 1) {
+    if (blockIdx.y != 0) {
+    } else if (DIM == 1) {
         double h = fabs(X[1] - X[0]);
         double v = 2.0 * pow(h, 1.0 - 2.0 * P.s) / ((2.0 - 2.0 * P.s) * (3.0 - 2.0 * P.s));
         acc[0] = 0.5 * P.C * v;
@@ -536,7 +768,7 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
         const double fb = P.C / (2.0 * P.s);
         double cx = E.cen[0][K], cy = DIM == 2 ? E.cen[1][K] : 0.0, h2k = E.h2[K];
         unsigned long long ntouch = 0, nfar = 0;
-        for (int e = 0; e < P.nb; ++e) {
+        for (int e = e_lo; e < e_hi; ++e) {
             const double* fe = P.fac + 6 * (long long)e;
             if (DIM == 1) {
                 int fv = P.fvid[2 * e];
@@ -621,11 +853,13 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
         if (ntouch) atomicAdd(&P.counters[0], ntouch);
         if (nfar) atomicAdd(&P.counters[1], nfar);
     }
-    for (int m = 0; m < 6; ++m) P.S[(long long)K * 6 + m] += acc[m];
+    for (int m = 0; m < 6; ++m)
+        if (acc[m] != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], acc[m]);
 }
 
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st) {
-    dim3 grid((P.T + 255) / 256), block(256);
+    const int chunks = P.with_boundary ? max(1, (P.nb + FACET_CHUNK - 1) / FACET_CHUNK) : 1;
+    dim3 grid((P.T + 255) / 256, chunks), block(256);
     if (P.dim == 2)
         hipLaunchKernelGGL(self_kernel<2>, grid, block, 0, st, E, P);
     else
