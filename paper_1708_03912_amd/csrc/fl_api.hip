@@ -6,6 +6,11 @@
 // Compiled with -ffp-contract=off: the centroids, squared diameters and
 // facet data computed here feed the per-pair order classes, which must be
 // reproducible bit for bit from the same formulas.
+//
+// Every per-assembly input of the kernels is packed into one pinned host
+// staging buffer and sent with a single asynchronous copy into one device
+// "plan" buffer; device buffers (plan, matrix, scratch) grow on demand and
+// are reused by later assemblies on the same handle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,22 +19,12 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "fl_internal.hpp"
 #include "fl_quad.hpp"
 
 using namespace fl;
-
-namespace {
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
 
 struct fl_handle {
     int device = 0;
@@ -41,8 +36,7 @@ struct fl_handle {
     int64_t nv = 0, nc = 0, nb = 0;
     std::vector<double> verts;
     std::vector<int32_t> cells, bfacets;
-    std::vector<int32_t> facet_owner;   // cell owning each boundary facet
-    std::vector<int32_t> facet_opp;     // vertex of the owner opposite the facet
+    std::vector<int32_t> facet_opp;     // vertex of the owning cell opposite the facet
     std::vector<char> on_boundary;
 
     // assembly
@@ -51,10 +45,19 @@ struct fl_handle {
     fl_opts opts{};
     int64_t n = 0, lda = 0;
     std::vector<int32_t> dof_node, node2dof;
-    double* dA = nullptr;
 
-    // device buffers that live with the assembly
-    std::vector<void*> owned;
+    // device / pinned buffers, grown on demand and reused
+    char* plan = nullptr;
+    size_t plan_cap = 0;
+    char* pin = nullptr;
+    size_t pin_cap = 0;
+    double* dA = nullptr;
+    size_t A_cap = 0;
+    double* dS = nullptr;
+    size_t S_cap = 0;
+    unsigned long long* dcnt = nullptr;
+
+    // views into the plan buffer used after assembly
     ElemDev E{};
     int* d_v2c_ptr = nullptr;
     int* d_v2c_idx = nullptr;
@@ -86,16 +89,25 @@ int fail(fl_handle* h, int code, const std::string& msg) {
             return fail(h, FL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-void free_assembly(fl_handle* h) {
-    for (void* p : h->owned) (void)hipFree(p);
-    h->owned.clear();
-    if (h->dA) (void)hipFree(h->dA);
-    h->dA = nullptr;
+void reset_assembly(fl_handle* h) {
     h->assembled = false;
     h->n = h->lda = 0;
     h->E = ElemDev{};
     h->d_v2c_ptr = h->d_v2c_idx = h->d_node2dof = h->d_dof_node = nullptr;
     h->d_meas = nullptr;
+}
+
+void free_buffers(fl_handle* h) {
+    reset_assembly(h);
+    if (h->plan) (void)hipFree(h->plan);
+    if (h->pin) (void)hipHostFree(h->pin);
+    if (h->dA) (void)hipFree(h->dA);
+    if (h->dS) (void)hipFree(h->dS);
+    if (h->dcnt) (void)hipFree(h->dcnt);
+    h->plan = h->pin = nullptr;
+    h->dA = h->dS = nullptr;
+    h->dcnt = nullptr;
+    h->plan_cap = h->pin_cap = h->A_cap = h->S_cap = 0;
 }
 
 void free_solver(fl_handle* h) {
@@ -108,25 +120,37 @@ void free_solver(fl_handle* h) {
     h->w_n = -1;
 }
 
+// grow a device buffer (contents are not preserved)
 template <class T>
-int upload(fl_handle* h, const std::vector<T>& v, T** out) {
-    *out = nullptr;
-    if (v.empty()) return FL_OK;
-    void* p = nullptr;
-    HIPCHK(hipMalloc(&p, v.size() * sizeof(T)));
-    h->owned.push_back(p);
-    HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-    *out = (T*)p;
+int ensure_dev(fl_handle* h, T** p, size_t* cap, size_t bytes) {
+    if (*cap >= bytes && *p) return FL_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) return fail(h, FL_ENOMEM, std::string("device allocation: ") + hipGetErrorString(e));
+    *p = (T*)q;
+    *cap = std::max<size_t>(bytes, 256);
     return FL_OK;
 }
 
-int alloc_owned(fl_handle* h, size_t bytes, void** out) {
-    *out = nullptr;
-    if (bytes == 0) return FL_OK;
-    HIPCHK(hipMalloc(out, bytes));
-    h->owned.push_back(*out);
-    return FL_OK;
-}
+// Layout of the packed plan: each part is 256-byte aligned.
+struct Packer {
+    struct Part {
+        const void* src;
+        size_t bytes, off;
+    };
+    std::vector<Part> parts;
+    size_t total = 0;
+    template <class T>
+    size_t add(const std::vector<T>& v) {
+        size_t off = total;
+        parts.push_back({v.data(), v.size() * sizeof(T), off});
+        total += ((v.size() * sizeof(T) + 255) / 256) * 256;
+        return off;
+    }
+};
 
 uint64_t morton2(double x, double y, double x0, double y0, double span) {
     auto q = [&](double v, double lo) {
@@ -164,6 +188,55 @@ int check_opts(fl_handle* h, const fl_opts& o) {
 double cdn(int d, double s) {
     return std::pow(2.0, 2.0 * s) * s * std::tgamma(s + 0.5 * d) /
            (std::pow(M_PI, 0.5 * d) * std::tgamma(1.0 - s));
+}
+
+// Gauss-Legendre / Gauss-Jacobi(1,0) tables (k = 1..16), collapsed triangle
+// rules and segment rules (k = 1..8); independent of s, built once.
+const RuleTables& base_rules() {
+    static RuleTables R = [] {
+        RuleTables T;
+        std::memset(&T, 0, sizeof(T));
+        for (int k = 1; k <= 16; ++k) {
+            gauss_jacobi01(k, 0.0, 0.0, T.gl_x + gl_off(k), T.gl_w + gl_off(k));
+            gauss_jacobi01(k, 1.0, 0.0, T.gj_x + gl_off(k), T.gj_w + gl_off(k));
+        }
+        for (int k = 1; k <= 8; ++k) {
+            int m = tri_off(k);
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j) {
+                    double u = T.gj_x[gl_off(k) + i];
+                    T.tl1[m] = u;
+                    T.tl2[m] = (1.0 - u) * T.gl_x[gl_off(k) + j];
+                    T.tw[m] = 2.0 * T.gj_w[gl_off(k) + i] * T.gl_w[gl_off(k) + j];
+                    double l1 = T.tl1[m], l2 = T.tl2[m], w = T.tw[m];
+                    double lam[3] = {1.0 - l1 - l2, l1, l2};
+                    double* c = T.tri[m];
+                    c[0] = l1;
+                    c[1] = l2;
+                    c[2] = w;
+                    for (int a = 0; a < 3; ++a) c[3 + a] = w * lam[a];
+                    int slot = 6;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = a; b < 3; ++b) c[slot++] = w * lam[a] * lam[b];
+                    ++m;
+                }
+        }
+        for (int k = 1; k <= 8; ++k)
+            for (int i = 0; i < k; ++i) {
+                double t = T.gl_x[gl_off(k) + i], w = T.gl_w[gl_off(k) + i];
+                double* c = T.seg[gl_off(k) + i];
+                c[0] = t;
+                c[1] = w;
+                c[2] = w * (1.0 - t);
+                c[3] = w * t;
+                c[4] = w * (1.0 - t) * (1.0 - t);
+                c[5] = w * (1.0 - t) * t;
+                c[6] = w * t * t;
+                c[7] = 0.0;
+            }
+        return T;
+    }();
+    return R;
 }
 
 }  // namespace
@@ -208,7 +281,7 @@ void fl_destroy(fl_handle* h) {
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
-    free_assembly(h);
+    free_buffers(h);
     free_solver(h);
     delete h;
 }
@@ -227,7 +300,8 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     if (nc > (int64_t)1 << 30 || nv > (int64_t)1 << 30) return fail(h, FL_EINVAL, "mesh too large");
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    free_assembly(h);
+    reset_assembly(h);
+    h->dim = 0;
     const int nper = dim + 1;
     for (int64_t i = 0; i < nv * dim; ++i)
         if (!std::isfinite(verts[i])) return fail(h, FL_EMESH, "non-finite vertex coordinate");
@@ -248,33 +322,32 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
         }
         if (!(meas > 0.0)) return fail(h, FL_EMESH, "degenerate cell " + std::to_string(K));
     }
-    // facet -> owning cell
-    std::unordered_map<uint64_t, std::vector<std::pair<int32_t, int32_t>>> own;
-    auto key = [&](int32_t a, int32_t b) {
-        if (a > b) std::swap(a, b);
-        return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-    };
-    for (int64_t K = 0; K < nc; ++K) {
-        const int32_t* c = cells + nper * K;
-        if (dim == 1) {
-            own[key(c[0], c[0])].push_back({(int32_t)K, c[1]});
-            own[key(c[1], c[1])].push_back({(int32_t)K, c[0]});
-        } else {
-            for (int a = 0; a < 3; ++a)
-                own[key(c[(a + 1) % 3], c[(a + 2) % 3])].push_back({(int32_t)K, c[a]});
-        }
+    // vertex -> cells (CSR) to find the cell owning each boundary facet
+    std::vector<int32_t> ptr(nv + 1, 0), idx(nc * nper);
+    for (int64_t i = 0; i < nc * nper; ++i) ptr[cells[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) ptr[v + 1] += ptr[v];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t K = 0; K < nc; ++K)
+            for (int a = 0; a < nper; ++a) idx[fill[cells[nper * K + a]]++] = (int32_t)K;
     }
-    h->facet_owner.assign(nb, -1);
     h->facet_opp.assign(nb, -1);
     h->on_boundary.assign(nv, 0);
     for (int64_t e = 0; e < nb; ++e) {
         const int32_t* f = bfacets + dim * e;
-        uint64_t k = dim == 1 ? key(f[0], f[0]) : key(f[0], f[1]);
-        auto it = own.find(k);
-        if (it == own.end() || it->second.size() != 1)
+        int owners = 0, opp = -1;
+        for (int32_t j = ptr[f[0]]; j < ptr[f[0] + 1]; ++j) {
+            const int32_t* c = cells + nper * idx[j];
+            bool has = true;
+            if (dim == 2) has = (c[0] == f[1] || c[1] == f[1] || c[2] == f[1]) && f[0] != f[1];
+            if (!has) continue;
+            ++owners;
+            for (int a = 0; a < nper; ++a)
+                if (c[a] != f[0] && (dim == 1 || c[a] != f[1])) opp = c[a];
+        }
+        if (owners != 1)
             return fail(h, FL_EMESH, "boundary facet " + std::to_string(e) + " does not lie on exactly one cell");
-        h->facet_owner[e] = it->second[0].first;
-        h->facet_opp[e] = it->second[0].second;
+        h->facet_opp[e] = opp;
         for (int a = 0; a < dim; ++a) h->on_boundary[f[a]] = 1;
     }
     h->dim = dim;
@@ -302,8 +375,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     if (rc) return rc;
     HIPCHK(hipSetDevice(h->device));
     if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
-    free_assembly(h);
-    free_solver(h);
+    reset_assembly(h);
     auto t0 = std::chrono::steady_clock::now();
 
     const int dim = h->dim, nper = dim + 1;
@@ -319,17 +391,19 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
         }
     const int64_t n = (int64_t)h->dof_node.size();
     const int64_t lda = ((n + 31) / 32) * 32;
-    {
+    const size_t A_bytes = sizeof(double) * (size_t)n * (size_t)lda + 8;
+    if (A_bytes > h->A_cap) {
+        if (h->dA) (void)hipFree(h->dA);
+        h->dA = nullptr;
+        h->A_cap = 0;
         size_t freeb = 0, totb = 0;
         HIPCHK(hipMemGetInfo(&freeb, &totb));
-        double need = (double)n * (double)lda * 8.0 + (double)T * 200.0 + (double)nv * 64.0;
-        if (need > (double)freeb * 0.98)
+        if ((double)A_bytes + (double)T * 512.0 > (double)freeb * 0.98)
             return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
     }
 
     // internal element order: Morton order of centroids (2D), by x (1D)
     std::vector<int32_t> perm(T);
-    for (int64_t K = 0; K < T; ++K) perm[K] = (int32_t)K;
     {
         std::vector<double> cx(T), cy(T, 0.0);
         double lo0 = 1e300, lo1 = 1e300, hi0 = -1e300, hi1 = -1e300;
@@ -345,21 +419,25 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             lo0 = std::min(lo0, cx[K]); hi0 = std::max(hi0, cx[K]);
             lo1 = std::min(lo1, cy[K]); hi1 = std::max(hi1, cy[K]);
         }
+        std::vector<uint64_t> key(T);
         if (dim == 2) {
             double span = std::max(hi0 - lo0, hi1 - lo1);
             if (!(span > 0)) span = 1;
-            std::vector<uint64_t> key(T);
-            for (int64_t K = 0; K < T; ++K) key[K] = morton2(cx[K], cy[K], lo0, lo1, span);
-            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+            for (int64_t K = 0; K < T; ++K) key[K] = (morton2(cx[K], cy[K], lo0, lo1, span) << 32) | (uint64_t)K;
         } else {
-            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return cx[a] < cx[b]; });
+            double span = hi0 - lo0;
+            if (!(span > 0)) span = 1;
+            for (int64_t K = 0; K < T; ++K)
+                key[K] = ((uint64_t)((cx[K] - lo0) / span * 4294967295.0) << 32) | (uint64_t)K;
         }
+        std::sort(key.begin(), key.end());
+        for (int64_t K = 0; K < T; ++K) perm[K] = (int32_t)(key[K] & 0xffffffffu);
     }
     // element SoA in internal order
     const int NC = nper * dim;
     std::vector<std::vector<double>> X(NC, std::vector<double>(T));
     std::vector<double> cen0(T), cen1(T, 0.0), h2(T), meas(T);
-    std::vector<std::vector<int>> vid(3, std::vector<int>(T, -1)), dof(3, std::vector<int>(T, -1));
+    std::vector<std::vector<int>> vid(nper, std::vector<int>(T, -1)), dof(nper, std::vector<int>(T, -1));
     for (int64_t Ki = 0; Ki < T; ++Ki) {
         const int32_t* c = &h->cells[nper * perm[Ki]];
         for (int a = 0; a < nper; ++a) {
@@ -405,35 +483,36 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             }
     }
     // touching pairs (Sec. 5): K < Kt sharing dim vertices (common edge, 2D)
-    // or one vertex
+    // or one vertex; shared-vertex counts through a marker array
     std::vector<int> edge_pairs, vert_pairs;
     {
-        std::vector<int> nb;
+        std::vector<int> mark(T, -1), cnt(T, 0), seen;
         for (int64_t Ki = 0; Ki < T; ++Ki) {
-            nb.clear();
+            seen.clear();
             for (int a = 0; a < nper; ++a) {
                 int v = vid[a][Ki];
-                for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e)
-                    if (v2c_idx[e] > Ki) nb.push_back(v2c_idx[e]);
+                for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
+                    int Kt = v2c_idx[e];
+                    if (Kt <= Ki) continue;
+                    if (mark[Kt] != (int)Ki) {
+                        mark[Kt] = (int)Ki;
+                        cnt[Kt] = 0;
+                        seen.push_back(Kt);
+                    }
+                    cnt[Kt]++;
+                }
             }
-            std::sort(nb.begin(), nb.end());
-            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
-            for (int Kt : nb) {
-                int sh = 0;
-                for (int a = 0; a < nper; ++a)
-                    for (int b = 0; b < nper; ++b) sh += (vid[a][Ki] == vid[b][Kt]);
+            std::sort(seen.begin(), seen.end());
+            for (int Kt : seen) {
+                int sh = cnt[Kt];
                 if (dim == 2 && sh == 2) { edge_pairs.push_back((int)Ki); edge_pairs.push_back(Kt); }
                 else if (sh == 1) { vert_pairs.push_back((int)Ki); vert_pairs.push_back(Kt); }
-                else if (sh >= nper) return fail(h, FL_EMESH, "duplicate cells");
+                else return fail(h, FL_EMESH, "duplicate cells");
             }
         }
     }
-    // far-field tiles and per-block local DOF numbering
+    // far-field tiles, see launch_far_tiles
     const int nblk = (int)((T + BE - 1) / BE);
-    // Tiles of block pairs bi <= bj.  A tile is "far" when the bounding boxes
-    // of the two blocks' centroids are so far apart that every pair is
-    // separated (centroid distance > 2 h_max excludes a common vertex) and in
-    // the last distance class; such tiles skip the per-pair classification.
     std::vector<int2> tiles, far_tiles;
     {
         std::vector<double> bx0(nblk, 1e300), bx1(nblk, -1e300), by0(nblk, 1e300), by1(nblk, -1e300),
@@ -446,6 +525,9 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             by1[b] = std::max(by1[b], cen1[Ki]);
             bh[b] = std::max(bh[b], h2[Ki]);
         }
+        // a tile is "far" when the centroid boxes of the two blocks are so
+        // far apart that every pair is separated (centroid distance > 2 h
+        // excludes a common vertex) and falls in the last distance class
         double th_last2 = 4.0;
         if (o.n_classes > 0) th_last2 = std::max(4.0, o.theta[o.n_classes - 1] * o.theta[o.n_classes - 1]);
         const bool use_far = o.k_far[o.n_classes] <= 4;
@@ -467,7 +549,8 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
         std::vector<int> ds;
         for (int b = 0; b < nblk; ++b) {
             ds.clear();
-            for (int64_t Ki = (int64_t)b * BE; Ki < std::min<int64_t>(T, (int64_t)(b + 1) * BE); ++Ki)
+            const int64_t k0 = (int64_t)b * BE, k1 = std::min<int64_t>(T, (int64_t)(b + 1) * BE);
+            for (int64_t Ki = k0; Ki < k1; ++Ki)
                 for (int a = 0; a < nper; ++a)
                     if (dof[a][Ki] >= 0) ds.push_back(dof[a][Ki]);
             std::sort(ds.begin(), ds.end());
@@ -475,15 +558,15 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             blk_ndof[b] = (int)ds.size();
             if ((int)ds.size() > MAXV) continue;  // tile falls back to global atomics
             for (size_t i = 0; i < ds.size(); ++i) blk_dofs[(size_t)b * MAXV + i] = ds[i];
-            for (int64_t Ki = (int64_t)b * BE; Ki < std::min<int64_t>(T, (int64_t)(b + 1) * BE); ++Ki)
+            for (int64_t Ki = k0; Ki < k1; ++Ki)
                 for (int a = 0; a < nper; ++a)
                     if (dof[a][Ki] >= 0)
                         loc[Ki * 3 + a] = (unsigned char)(std::lower_bound(ds.begin(), ds.end(), dof[a][Ki]) - ds.begin());
         }
     }
     // boundary facets: coordinates, inward unit normal (Sec. 2)
-    std::vector<double> fac(h->nb * 6, 0.0);
-    std::vector<int> fvid(h->nb * 2, -1);
+    std::vector<double> fac(std::max<int64_t>(h->nb, 1) * 6, 0.0);
+    std::vector<int> fvid(std::max<int64_t>(h->nb, 1) * 2, -1);
     for (int64_t e = 0; e < h->nb; ++e) {
         const int32_t* f = &h->bfacets[dim * e];
         int opp = h->facet_opp[e];
@@ -506,92 +589,62 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             fvid[2 * e + 1] = f[1];
         }
     }
-    // quadrature tables
-    RuleTables R;
-    std::memset(&R, 0, sizeof(R));
-    for (int k = 1; k <= 16; ++k) {
-        gauss_jacobi01(k, 0.0, 0.0, R.gl_x + gl_off(k), R.gl_w + gl_off(k));
-        gauss_jacobi01(k, 1.0, 0.0, R.gj_x + gl_off(k), R.gj_w + gl_off(k));
-    }
-    for (int k = 1; k <= 8; ++k) {
-        int m = tri_off(k);
-        for (int i = 0; i < k; ++i)
-            for (int j = 0; j < k; ++j) {
-                double u = R.gj_x[gl_off(k) + i];
-                R.tl1[m] = u;
-                R.tl2[m] = (1.0 - u) * R.gl_x[gl_off(k) + j];
-                R.tw[m] = 2.0 * R.gj_w[gl_off(k) + i] * R.gl_w[gl_off(k) + j];
-                double l1 = R.tl1[m], l2 = R.tl2[m], w = R.tw[m];
-                double lam[3] = {1.0 - l1 - l2, l1, l2};
-                double* c = R.tri[m];
-                c[0] = l1; c[1] = l2; c[2] = w;
-                for (int a = 0; a < 3; ++a) c[3 + a] = w * lam[a];
-                int slot = 6;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = a; b < 3; ++b) c[slot++] = w * lam[a] * lam[b];
-                ++m;
-            }
-    }
-    for (int k = 1; k <= 8; ++k)
-        for (int i = 0; i < k; ++i) {
-            double t = R.gl_x[gl_off(k) + i], w = R.gl_w[gl_off(k) + i];
-            double* c = R.seg[gl_off(k) + i];
-            c[0] = t; c[1] = w; c[2] = w * (1.0 - t); c[3] = w * t;
-            c[4] = w * (1.0 - t) * (1.0 - t); c[5] = w * (1.0 - t) * t; c[6] = w * t * t; c[7] = 0.0;
-        }
+    // quadrature tables: cached base rules + the two s-dependent radial rules
+    RuleTables R = base_rules();
     if (s < 0.5) gauss_jacobi01(2, 0.0, -2.0 * s, R.r0_x, R.r0_w);
     gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
     auto t1 = std::chrono::steady_clock::now();
 
-    // device buffers
-    std::vector<double*> dX(NC);
-    for (int c = 0; c < NC; ++c) { int r2 = upload(h, X[c], &dX[c]); if (r2) return r2; }
-    double *dc0, *dc1 = nullptr, *dh2, *dme;
-    int *dvid[3] = {nullptr, nullptr, nullptr}, *ddof[3] = {nullptr, nullptr, nullptr};
-    if ((rc = upload(h, cen0, &dc0)) || (rc = upload(h, h2, &dh2)) || (rc = upload(h, meas, &dme))) return rc;
-    if (dim == 2 && (rc = upload(h, cen1, &dc1))) return rc;
-    for (int a = 0; a < nper; ++a)
-        if ((rc = upload(h, vid[a], &dvid[a])) || (rc = upload(h, dof[a], &ddof[a]))) return rc;
-    ElemDev E{};
-    for (int c = 0; c < NC; ++c) E.x[c] = dX[c];
-    E.cen[0] = dc0;
-    E.cen[1] = dc1;
-    E.h2 = dh2;
-    E.meas = dme;
-    for (int a = 0; a < nper; ++a) { E.vid[a] = dvid[a]; E.dof[a] = ddof[a]; }
-    h->E = E;
-    h->d_meas = dme;
-    int2* dtiles;
-    int2* dftiles = nullptr;
-    int *dbnd, *dbdofs, *dv2cp, *dv2ci, *dn2d, *ddn, *dep = nullptr, *dvp = nullptr, *dfvid = nullptr;
-    unsigned char *dloc, *dvloc;
-    double* dfac = nullptr;
-    if ((rc = upload(h, far_tiles, &dftiles))) return rc;
-    if ((rc = upload(h, tiles, &dtiles)) || (rc = upload(h, blk_ndof, &dbnd)) ||
-        (rc = upload(h, blk_dofs, &dbdofs)) || (rc = upload(h, loc, &dloc)) ||
-        (rc = upload(h, v2c_ptr, &dv2cp)) || (rc = upload(h, v2c_idx, &dv2ci)) ||
-        (rc = upload(h, vloc, &dvloc)) || (rc = upload(h, h->node2dof, &dn2d)) ||
-        (rc = upload(h, h->dof_node, &ddn)) || (rc = upload(h, edge_pairs, &dep)) ||
-        (rc = upload(h, vert_pairs, &dvp)) || (rc = upload(h, fac, &dfac)) || (rc = upload(h, fvid, &dfvid)))
-        return rc;
-    h->d_v2c_ptr = dv2cp;
-    h->d_v2c_idx = dv2ci;
-    h->d_node2dof = dn2d;
-    h->d_dof_node = ddn;
-    double* dS;
-    unsigned long long* dcnt;
-    if ((rc = alloc_owned(h, sizeof(double) * T * 6, (void**)&dS))) return rc;
-    if ((rc = alloc_owned(h, sizeof(unsigned long long) * 16, (void**)&dcnt))) return rc;
-    {
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, sizeof(double) * (size_t)n * (size_t)lda + 8);
-        if (e != hipSuccess) return fail(h, FL_ENOMEM, std::string("matrix allocation: ") + hipGetErrorString(e));
-        h->dA = (double*)p;
+    // pack everything into the pinned staging buffer, one copy to the device
+    Packer pk;
+    std::vector<size_t> offX(NC);
+    for (int c = 0; c < NC; ++c) offX[c] = pk.add(X[c]);
+    const size_t o_c0 = pk.add(cen0), o_c1 = pk.add(cen1), o_h2 = pk.add(h2), o_me = pk.add(meas);
+    std::vector<size_t> o_vid(nper), o_dof(nper);
+    for (int a = 0; a < nper; ++a) { o_vid[a] = pk.add(vid[a]); o_dof[a] = pk.add(dof[a]); }
+    const size_t o_ft = pk.add(far_tiles), o_nt = pk.add(tiles), o_bnd = pk.add(blk_ndof),
+                 o_bdofs = pk.add(blk_dofs), o_loc = pk.add(loc), o_v2cp = pk.add(v2c_ptr),
+                 o_v2ci = pk.add(v2c_idx), o_vloc = pk.add(vloc), o_n2d = pk.add(h->node2dof),
+                 o_dn = pk.add(h->dof_node), o_ep = pk.add(edge_pairs), o_vp = pk.add(vert_pairs),
+                 o_fac = pk.add(fac), o_fvid = pk.add(fvid);
+    if (pk.total > h->pin_cap) {
+        if (h->pin) (void)hipHostFree(h->pin);
+        h->pin = nullptr;
+        h->pin_cap = 0;
+        HIPCHK(hipHostMalloc((void**)&h->pin, pk.total, 0));
+        h->pin_cap = pk.total;
     }
+    for (const auto& p : pk.parts)
+        if (p.bytes) std::memcpy(h->pin + p.off, p.src, p.bytes);
+    if ((rc = ensure_dev(h, &h->plan, &h->plan_cap, pk.total))) return rc;
+    if ((rc = ensure_dev(h, &h->dA, &h->A_cap, A_bytes))) return rc;
+    if ((rc = ensure_dev(h, &h->dS, &h->S_cap, sizeof(double) * (size_t)T * 6))) return rc;
+    if (!h->dcnt) HIPCHK(hipMalloc((void**)&h->dcnt, sizeof(unsigned long long) * 16));
+    HIPCHK(hipMemcpyAsync(h->plan, h->pin, pk.total, hipMemcpyHostToDevice, h->stream));
+    char* base = h->plan;
+    auto dv = [&](size_t off) { return (void*)(base + off); };
+    ElemDev E{};
+    for (int c = 0; c < NC; ++c) E.x[c] = (const double*)dv(offX[c]);
+    E.cen[0] = (const double*)dv(o_c0);
+    E.cen[1] = dim == 2 ? (const double*)dv(o_c1) : nullptr;
+    E.h2 = (const double*)dv(o_h2);
+    E.meas = (const double*)dv(o_me);
+    for (int a = 0; a < nper; ++a) {
+        E.vid[a] = (const int*)dv(o_vid[a]);
+        E.dof[a] = (const int*)dv(o_dof[a]);
+    }
+    h->E = E;
+    h->d_meas = (double*)dv(o_me);
+    h->d_v2c_ptr = (int*)dv(o_v2cp);
+    h->d_v2c_idx = (int*)dv(o_v2ci);
+    h->d_node2dof = (int*)dv(o_n2d);
+    h->d_dof_node = (int*)dv(o_dn);
+    double* dS = h->dS;
+    unsigned long long* dcnt = h->dcnt;
     HIPCHK(upload_rules(R, h->stream));
     launch_zero(h->dA, n * lda, h->stream);
     launch_zero(dS, T * 6, h->stream);
-    HIPCHK(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long) * 16, h->stream));
+    launch_zero((double*)dcnt, 16, h->stream);
 
     hipEvent_t ev[5];
     for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -613,11 +666,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             if (o.k_far[j] == o.k_far[m]) FP.kfirst[m] = 0;
     }
     FP.nblk = nblk;
-    FP.tiles = dtiles;
+    FP.tiles = (const int2*)dv(o_nt);
     FP.ntiles = (long long)tiles.size();
-    FP.blk_ndof = dbnd;
-    FP.blk_dofs = dbdofs;
-    FP.loc = dloc;
+    FP.blk_ndof = (const int*)dv(o_bnd);
+    FP.blk_dofs = (const int*)dv(o_bdofs);
+    FP.loc = (const unsigned char*)dv(o_loc);
     FP.A = h->dA;
     FP.lda = lda;
     FP.S = dS;
@@ -626,7 +679,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     HIPCHK(hipGetLastError());
     {
         FarParams FF = FP;
-        FF.tiles = dftiles;
+        FF.tiles = (const int2*)dv(o_ft);
         FF.ntiles = (long long)far_tiles.size();
         launch_far_tiles(E, FF, o.k_far[o.n_classes], h->stream);
         HIPCHK(hipGetLastError());
@@ -640,8 +693,8 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     BP.C = C;
     BP.T = (int)T;
     BP.nb = (int)h->nb;
-    BP.fac = dfac;
-    BP.fvid = dfvid;
+    BP.fac = (const double*)dv(o_fac);
+    BP.fvid = (const int*)dv(o_fvid);
     BP.k_touch_bnd = o.k_touch_bnd;
     BP.ncls = o.n_classes;
     for (int m = 0; m < o.n_classes; ++m) BP.th2[m] = FP.th2[m];
@@ -664,26 +717,28 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     TP.lda = lda;
     if (dim == 2) {
         TP.npairs = (long long)edge_pairs.size() / 2;
-        TP.pairs = dep;
+        TP.pairs = (const int*)dv(o_ep);
         launch_touch_edge2(E, TP, h->stream);
         HIPCHK(hipGetLastError());
     }
     TP.npairs = (long long)vert_pairs.size() / 2;
-    TP.pairs = dvp;
+    TP.pairs = (const int*)dv(o_vp);
     launch_touch_vert(E, TP, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
-    launch_scatter_self(E, dv2cp, dv2ci, dn2d, dvloc, (int)nv, dim, dS, h->dA, lda, h->stream);
+    launch_scatter_self(E, h->d_v2c_ptr, h->d_v2c_idx, h->d_node2dof, (const unsigned char*)dv(o_vloc),
+                        (int)nv, dim, dS, h->dA, lda, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[4], h->stream));
+    unsigned long long cnt[16];
+    HIPCHK(hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipEventSynchronize(ev[4]));
+    HIPCHK(hipStreamSynchronize(h->stream));
     float ms = 0.f, ph[4] = {0, 0, 0, 0};
     HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ph[i], ev[i], ev[i + 1]));
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
-    unsigned long long cnt[16];
-    HIPCHK(hipMemcpy(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost));
 
     h->s = s;
     h->opts = o;
@@ -703,19 +758,19 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     S.pairs_bnd_far = (int64_t)cnt[11];
     // kernel evaluations by the rules in use
     {
-        int64_t ev = 0;
+        int64_t ev2 = 0;
         const int kT = o.k_touch, kB = o.k_touch_bnd;
         for (int m = 0; m <= o.n_classes; ++m) {
             int64_t q = dim == 2 ? (int64_t)o.k_far[m] * o.k_far[m] : o.k_far[m];
-            ev += S.pairs_far[m] * q * q;
+            ev2 += S.pairs_far[m] * q * q;
         }
         if (dim == 2) {
-            ev += T * 3 * kT + S.pairs_edge * 4 * kT * kT + S.pairs_vertex * 2 * kT * kT * kT;
-            ev += S.pairs_bnd_touch * 6 * kB * 2;  // upper bound per touching facet pair
+            ev2 += T * 3 * kT + S.pairs_edge * 4 * kT * kT + S.pairs_vertex * 2 * kT * kT * kT;
+            ev2 += S.pairs_bnd_touch * 6 * kB * 2;  // upper bound per touching facet pair
         } else {
-            ev += S.pairs_vertex * 2 * kT;
+            ev2 += S.pairs_vertex * 2 * kT;
         }
-        S.kernel_evals = ev;
+        S.kernel_evals = ev2;
     }
     S.t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     S.t_assemble_ms = ms;
@@ -780,8 +835,8 @@ static int ensure_solver(fl_handle* h) {
     const int64_t n = h->n;
     const int nblk = (int)((n + 255) / 256);
     const int nmv = mv_blocks(n);
-    HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(6 * n + 8)));
-    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(2 * nblk + nmv + 8)));
+    HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(7 * n + 8)));
+    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * nblk + nmv + 8)));
     HIPCHK(hipMalloc((void**)&h->w_scal, sizeof(double) * 16));
     HIPCHK(hipMalloc((void**)&h->w_flag, sizeof(int) * 8));
     h->w_n = n;
@@ -809,9 +864,9 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     S.lda = h->lda;
     S.r = h->w;
     S.z = h->w + n;
-    S.p = h->w + 2 * n;
-    S.q = h->w + 3 * n;
-    double* dd = h->w + 4 * n;
+    S.p = h->w + 2 * n;  // two buffers
+    S.q = h->w + 4 * n;
+    double* dd = h->w + 5 * n;
     S.d = dd;
     S.b = b;
     S.x = u;
@@ -831,9 +886,9 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     int flag[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (flag[2] == 2) return fail(h, FL_ENONFINITE, "right-hand side is not finite");
     int it = 0;
     const int chunk = 16;
-    if (flag[2] == 2) return fail(h, FL_ENONFINITE, "right-hand side is not finite");
     while (!flag[0] && it < maxit) {
         int m = std::min(chunk, maxit - it);
         for (int j = 0; j < m; ++j) launch_cg_iter_at(S, it + j, h->stream);
@@ -842,16 +897,19 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
         HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
     }
+    // residual of the final iterate (when the loop ended at maxit)
+    launch_cg_final(S, it, h->stream);
     HIPCHK(hipEventRecord(e1, h->stream));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    double sc[4];
-    HIPCHK(hipMemcpy(sc, S.scal, sizeof(double) * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost));
+    double sc[2];
+    HIPCHK(hipMemcpy(sc, S.scal, sizeof(double) * 2, hipMemcpyDeviceToHost));
     int iterations = flag[1];
-    double rel = sc[2] > 0 ? std::sqrt(sc[3]) / std::sqrt(sc[2]) : 0.0;
+    double rel = sc[0] > 0 ? std::sqrt(sc[1]) / std::sqrt(sc[0]) : 0.0;
     h->st.t_solve_ms = ms;
     h->st.last_iters = iterations;
     h->st.last_relres = rel;
@@ -875,7 +933,7 @@ int fl_energy_error2(fl_handle* h, double fu, const double* b, const double* uh,
     int rc = ensure_solver(h);
     if (rc) return rc;
     const int64_t n = h->n;
-    double* y = h->w + 5 * n;
+    double* y = h->w + 6 * n;
     launch_matvec(h->dA, h->lda, n, uh, y, h->stream);
     const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
     launch_dot2(uh, b, y, n, h->w_part, nblk, h->w_scal + 8, h->stream);

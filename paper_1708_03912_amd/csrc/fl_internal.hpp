@@ -120,17 +120,18 @@ struct CgState {
     double* x;
     double* r;
     double* z;
-    double* p;
+    double* p;          // 2 x n (double-buffered by iteration parity)
     double* q;
-    double* part;       // 2 x nblk + mv_blocks(n) partial sums
-    double* scal;       // [0],[1] r.z by iteration parity, [2] b.b, [3] r.r
-    int* flag;          // [0] converged/stop, [1] iterations, [2] breakdown
+    double* part;       // 4 x nblk (r.z, r.r by parity) + mv_blocks(n) partial sums
+    double* scal;       // [0] b.b, [1] last r.r
+    int* flag;          // [0] stop, [1] iterations, [2] 1 breakdown / 2 non-finite
     double rtol;
     int maxit;
     int nblk;
 };
 void launch_cg_init(const CgState& s, hipStream_t st);
 void launch_cg_iter_at(const CgState& s, int it, hipStream_t st);
+void launch_cg_final(const CgState& s, int it, hipStream_t st);
 void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
                  int nblk, double* out, hipStream_t st);
 

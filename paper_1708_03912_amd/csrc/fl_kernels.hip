@@ -1206,10 +1206,18 @@ __device__ __forceinline__ double sum_partials(const double* part, int m, double
     return block_sum(v, sh);
 }
 
-constexpr int VEC_BLOCK = 256;
-
-// CG state: scal[0..1] rz by parity, scal[2] bb, scal[3] rr
-// init: x = 0, r = b, z = r/d, p = z; partials of r.z and r.r
+// Jacobi-PCG (Sec. 5), two kernels per iteration.  Partial sums are kept
+// per block and reduced in a fixed order by every block that needs them
+// (deterministic); r.z and r.r partials are double-buffered by iteration
+// parity, the search direction p too.
+//   cg_matvec(it):  check ||r_it|| against rtol ||b||; beta = rz_it/rz_{it-1};
+//                   p_it = z + beta p_{it-1} (computed on the fly for the
+//                   product, stored for the block's own rows); q = A p_it;
+//                   partials of p_it.q
+//   cg_update(it):  alpha = rz_it / p.q; x += alpha p; r -= alpha q; z = r/d;
+//                   partials of r.z and r.r for iteration it+1
+// status: flag[0] stop, flag[1] iterations done, flag[2] 1 breakdown /
+// 2 non-finite; scal[0] = b.b, scal[1] = last r.r.
 __global__ __launch_bounds__(256) void cg_init_kernel(CgState S) {
     __shared__ double sh[4];
     long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -1220,65 +1228,112 @@ __global__ __launch_bounds__(256) void cg_init_kernel(CgState S) {
         S.r[i] = bi;
         double zi = bi / S.d[i];
         S.z[i] = zi;
-        S.p[i] = zi;
+        S.p[S.n + i] = 0.0;  // p_{-1}
         rz = bi * zi;
         rr = bi * bi;
     }
     double a = block_sum(rz, sh), b = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        S.part[blockIdx.x] = a;
-        S.part[S.nblk + blockIdx.x] = b;
+        S.part[blockIdx.x] = a;              // rz, parity 0
+        S.part[2 * S.nblk + blockIdx.x] = b; // rr, parity 0
     }
 }
 
 __global__ __launch_bounds__(256) void cg_init_reduce_kernel(CgState S) {
     __shared__ double sh[4];
-    double rz = sum_partials(S.part, S.nblk, sh);
-    double rr = sum_partials(S.part + S.nblk, S.nblk, sh);
+    double bb = sum_partials(S.part + 2 * S.nblk, S.nblk, sh);
     if (threadIdx.x == 0) {
-        S.scal[0] = rz;
-        S.scal[2] = rr;  // bb
-        S.scal[3] = rr;
-        S.flag[0] = (rr == 0.0) ? 1 : 0;
+        S.scal[0] = bb;
+        S.scal[1] = bb;
+        S.flag[0] = (bb == 0.0) ? 1 : 0;
         S.flag[1] = 0;
         S.flag[2] = 0;
-        if (!(rr == rr) || rr > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
+        if (!(bb == bb) || bb > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
     }
 }
 
-// q = A p, partial sums of p.q per block (2*MV rows per block)
-__global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S) {
+__device__ __forceinline__ double row_dot_comb(const double* __restrict__ a, const double* __restrict__ z,
+                                               const double* __restrict__ pp, double beta, long long n,
+                                               int lane) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const long long n2 = n & ~1LL;
+    long long j = 2 * lane;
+    for (; j + 6 * 64 < n2; j += 8 * 64) {
+        double2 a0 = *(const double2*)(a + j), a1 = *(const double2*)(a + j + 128);
+        double2 a2 = *(const double2*)(a + j + 256), a3 = *(const double2*)(a + j + 384);
+        double2 z0 = *(const double2*)(z + j), z1 = *(const double2*)(z + j + 128);
+        double2 z2 = *(const double2*)(z + j + 256), z3 = *(const double2*)(z + j + 384);
+        double2 p0 = *(const double2*)(pp + j), p1 = *(const double2*)(pp + j + 128);
+        double2 p2 = *(const double2*)(pp + j + 256), p3 = *(const double2*)(pp + j + 384);
+        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y);
+        acc1 += a1.x * (z1.x + beta * p1.x) + a1.y * (z1.y + beta * p1.y);
+        acc2 += a2.x * (z2.x + beta * p2.x) + a2.y * (z2.y + beta * p2.y);
+        acc3 += a3.x * (z3.x + beta * p3.x) + a3.y * (z3.y + beta * p3.y);
+    }
+    for (; j < n2; j += 128) {
+        double2 a0 = *(const double2*)(a + j), z0 = *(const double2*)(z + j), p0 = *(const double2*)(pp + j);
+        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y);
+    }
+    if ((n & 1) && lane == 0) acc1 += a[n - 1] * (z[n - 1] + beta * pp[n - 1]);
+    return wave_sum((acc0 + acc1) + (acc2 + acc3));
+}
+
+__global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S, int it, int nmv) {
     __shared__ double sh[4];
     if (*(volatile int*)&S.flag[0]) return;
+    const int par = it & 1;
+    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
+    const double rr = sum_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk, sh);
+    const double bb = S.scal[0];
+    if (sqrt(rr) <= S.rtol * sqrt(bb) || !(rr == rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.flag[0] = 1;
+            S.flag[1] = it;
+            S.scal[1] = rr;
+            if (!(rr == rr)) S.flag[2] = 2;
+        }
+        return;
+    }
+    double beta = 0.0;
+    if (it > 0) beta = rz / sum_partials(S.part + (1 - par) * S.nblk, S.nblk, sh);
+    const double* pprev = S.p + (long long)(1 - par) * S.n;
+    double* pcur = S.p + (long long)par * S.n;
     const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     double pq = 0.0;
     if (row < S.n) {
-        double v = row_dot(S.A + row * S.lda, S.p, S.n, lane);
+        double v = row_dot_comb(S.A + row * S.lda, S.z, pprev, beta, S.n, lane);
         if (lane == 0) {
+            const double pr = S.z[row] + beta * pprev[row];
+            pcur[row] = pr;
             S.q[row] = v;
-            pq = v * S.p[row];
+            pq = v * pr;
         }
     }
     double t = block_sum(pq, sh);
-    if (threadIdx.x == 0) S.part[2 * S.nblk + blockIdx.x] = t;
+    if (threadIdx.x == 0) S.part[4 * S.nblk + blockIdx.x] = t;
 }
 
-// alpha = rz / p.q; x += alpha p; r -= alpha q; z = r/d; partials of r.z, r.r
-__global__ __launch_bounds__(256) void cg_update1_kernel(CgState S, int it, int nmv) {
+__global__ __launch_bounds__(256) void cg_update_kernel(CgState S, int it, int nmv) {
     __shared__ double sh[4];
     if (*(volatile int*)&S.flag[0]) return;
-    double pq = sum_partials(S.part + 2 * S.nblk, nmv, sh);
-    double rz = S.scal[it & 1];
+    const int par = it & 1;
+    const double pq = sum_partials(S.part + 4 * S.nblk, nmv, sh);
     if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) S.scal[6] = pq;
-        return;  // breakdown flagged in update2
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.flag[0] = 1;
+            S.flag[1] = it;
+            S.flag[2] = 1;
+        }
+        return;
     }
-    double alpha = rz / pq;
+    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
+    const double alpha = rz / pq;
+    const double* pcur = S.p + (long long)par * S.n;
     long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     double a = 0.0, b = 0.0;
     if (i < S.n) {
-        S.x[i] += alpha * S.p[i];
+        S.x[i] += alpha * pcur[i];
         double ri = S.r[i] - alpha * S.q[i];
         S.r[i] = ri;
         double zi = ri / S.d[i];
@@ -1288,37 +1343,17 @@ __global__ __launch_bounds__(256) void cg_update1_kernel(CgState S, int it, int 
     }
     double ta = block_sum(a, sh), tb = block_sum(b, sh);
     if (threadIdx.x == 0) {
-        S.part[blockIdx.x] = ta;
-        S.part[S.nblk + blockIdx.x] = tb;
+        S.part[(1 - par) * S.nblk + blockIdx.x] = ta;
+        S.part[2 * S.nblk + (1 - par) * S.nblk + blockIdx.x] = tb;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.flag[1] = it + 1;
 }
 
-// beta = rz_new / rz; p = z + beta p; status update by block 0
-__global__ __launch_bounds__(256) void cg_update2_kernel(CgState S, int it, int nmv) {
+// after the last launched iteration: residual of iteration `it`
+__global__ __launch_bounds__(256) void cg_final_kernel(CgState S, int it) {
     __shared__ double sh[4];
-    if (*(volatile int*)&S.flag[0]) return;
-    double pq = sum_partials(S.part + 2 * S.nblk, nmv, sh);
-    if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            S.flag[0] = 1;
-            S.flag[2] = 1;
-        }
-        return;
-    }
-    double rzn = sum_partials(S.part, S.nblk, sh);
-    double rr = sum_partials(S.part + S.nblk, S.nblk, sh);
-    double rz = S.scal[it & 1];
-    double beta = rzn / rz;
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i < S.n) S.p[i] = S.z[i] + beta * S.p[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        S.scal[(it + 1) & 1] = rzn;
-        S.scal[3] = rr;
-        S.flag[1] = it + 1;
-        double bb = S.scal[2];
-        if (sqrt(rr) <= S.rtol * sqrt(bb) || it + 1 >= S.maxit) S.flag[0] = 1;
-        if (!(rr == rr)) { S.flag[0] = 1; S.flag[2] = 2; }
-    }
+    const double rr = sum_partials(S.part + 2 * S.nblk + (it & 1) * S.nblk, S.nblk, sh);
+    if (threadIdx.x == 0 && !S.flag[0]) S.scal[1] = rr;
 }
 
 void launch_cg_init(const CgState& s, hipStream_t st) {
@@ -1328,9 +1363,12 @@ void launch_cg_init(const CgState& s, hipStream_t st) {
 
 void launch_cg_iter_at(const CgState& s, int it, hipStream_t st) {
     int nmv = mv_blocks(s.n);
-    hipLaunchKernelGGL(cg_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s);
-    hipLaunchKernelGGL(cg_update1_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
-    hipLaunchKernelGGL(cg_update2_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+    hipLaunchKernelGGL(cg_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s, it, nmv);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+}
+
+void launch_cg_final(const CgState& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL(cg_final_kernel, dim3(1), dim3(256), 0, st, s, it);
 }
 
 // out[0] = a.b, out[1] = a.c (deterministic two-pass)
