@@ -57,6 +57,9 @@ extern "C" {
 #define FL_DOF_PAPER 0      /* Sec. 3 rule: all nodes if s < 1/2             */
 #define FL_DOF_INTERIOR 1   /* interior nodes only                           */
 
+#define FL_FP64 0           /* every step in FP64                            */
+#define FL_MIXED 1          /* separated pairs and the inner CG in FP32      */
+
 #define FL_MAX_CLASSES 8    /* distance classes for separated pairs          */
 #define FL_MAX_ORDER_FAR 8  /* largest order for separated pairs             */
 #define FL_MAX_ORDER_TOUCH 16 /* largest order for touching pairs            */
@@ -83,6 +86,15 @@ typedef struct {
     double theta[FL_MAX_CLASSES];        /* centroid-distance thresholds    */
     int k_far[FL_MAX_CLASSES + 1];       /* 1..FL_MAX_ORDER_FAR             */
     int k_far_bnd[FL_MAX_CLASSES + 1];   /* 1..FL_MAX_ORDER_FAR             */
+    int precision;                       /* FL_FP64 (default) or FL_MIXED:
+                                            separated pairs evaluated in
+                                            FP32 (hardware log2/exp2, FP32
+                                            sums within a pair; tile and
+                                            cross-tile sums, touching pairs
+                                            and the boundary term in FP64);
+                                            an FP32 copy of A drives an
+                                            inner FP32 Jacobi-PCG inside
+                                            FP64 iterative refinement     */
 } fl_opts;
 
 typedef struct {
@@ -99,8 +111,10 @@ typedef struct {
     double t_touch_ms;        /* ... common-edge / common-vertex pairs      */
     double t_scatter_ms;      /* ... diagonal blocks into A                 */
     double t_solve_ms;        /* device time of the last solve              */
-    int32_t last_iters;       /* iterations of the last solve               */
+    int32_t last_iters;       /* iterations of the last solve (mixed: inner
+                                 FP32 iterations summed over refinements)  */
     double last_relres;
+    int32_t last_outer;       /* FP64 refinement steps of the last solve    */
 } fl_stats_t;
 
 /* Default orders (the calibrated table: k_touch = k_touch_bnd = 6,
@@ -169,6 +183,10 @@ int fl_matvec(fl_handle *h, const double *x, double *y);
 /* Jacobi-preconditioned CG on A u = b (Sec. 5).  b, u: device, length n;
  * u is overwritten (initial guess 0).  Stops when ||r||_2 <= rtol ||b||_2
  * or after maxit iterations (then FL_ENOCONV with the last iterate).
+ * After an FL_MIXED assembly: FP64 iterative refinement u += e with the
+ * residual r = b - A u in FP64, each correction from FP32 Jacobi-PCG on the
+ * FP32 copy of A to a relative residual 1e-4 (maxit bounds the total inner
+ * iterations).
  * FL_EBREAKDOWN if p.Ap <= 0; FL_ENONFINITE if b is not finite.  Host
  * outputs iters / relres (may be NULL).  Synchronises the stream. */
 int fl_solve(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,

@@ -55,6 +55,8 @@ struct fl_handle {
     size_t A_cap = 0;
     double* dS = nullptr;
     size_t S_cap = 0;
+    float* dA32 = nullptr;
+    size_t A32_cap = 0;
     unsigned long long* dcnt = nullptr;
 
     // views into the plan buffer used after assembly
@@ -66,7 +68,8 @@ struct fl_handle {
     double* d_meas = nullptr;
 
     // solver workspace
-    double* w = nullptr;   // r, z, p, q, d, tmp (6 n)
+    double* w = nullptr;   // r, z, p (2n), q, d, tmp (7 n)
+    float* w32 = nullptr;  // FP32 refinement workspace (8 n)
     double* w_part = nullptr;
     double* w_scal = nullptr;
     int* w_flag = nullptr;
@@ -104,6 +107,9 @@ void free_buffers(fl_handle* h) {
     if (h->dA) (void)hipFree(h->dA);
     if (h->dS) (void)hipFree(h->dS);
     if (h->dcnt) (void)hipFree(h->dcnt);
+    if (h->dA32) (void)hipFree(h->dA32);
+    h->dA32 = nullptr;
+    h->A32_cap = 0;
     h->plan = h->pin = nullptr;
     h->dA = h->dS = nullptr;
     h->dcnt = nullptr;
@@ -115,6 +121,8 @@ void free_solver(fl_handle* h) {
     if (h->w_part) (void)hipFree(h->w_part);
     if (h->w_scal) (void)hipFree(h->w_scal);
     if (h->w_flag) (void)hipFree(h->w_flag);
+    if (h->w32) (void)hipFree(h->w32);
+    h->w32 = nullptr;
     h->w = h->w_part = h->w_scal = nullptr;
     h->w_flag = nullptr;
     h->w_n = -1;
@@ -169,6 +177,8 @@ int check_opts(fl_handle* h, const fl_opts& o) {
         return fail(h, FL_EINVAL, "dof_mode must be FL_DOF_PAPER or FL_DOF_INTERIOR");
     if (o.n_classes < 0 || o.n_classes > FL_MAX_CLASSES)
         return fail(h, FL_EINVAL, "n_classes out of range");
+    if (o.precision != FL_FP64 && o.precision != FL_MIXED)
+        return fail(h, FL_EINVAL, "precision must be FL_FP64 or FL_MIXED");
     if (o.k_touch < 1 || o.k_touch > FL_MAX_ORDER_TOUCH || o.k_touch_bnd < 1 ||
         o.k_touch_bnd > FL_MAX_ORDER_TOUCH)
         return fail(h, FL_EINVAL, "touching orders must lie in 1..16");
@@ -234,6 +244,10 @@ const RuleTables& base_rules() {
                 c[6] = w * t * t;
                 c[7] = 0.0;
             }
+        for (int m = 0; m < TRI_TAB; ++m)
+            for (int c = 0; c < 12; ++c) T.trif[m][c] = (float)T.tri[m][c];
+        for (int m = 0; m < 36; ++m)
+            for (int c = 0; c < 8; ++c) T.segf[m][c] = (float)T.seg[m][c];
         return T;
     }();
     return R;
@@ -675,6 +689,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     FP.lda = lda;
     FP.S = dS;
     FP.cls_count = dcnt;
+    FP.mixed = o.precision == FL_MIXED ? 1 : 0;
     launch_far(E, FP, h->stream);
     HIPCHK(hipGetLastError());
     {
@@ -730,6 +745,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     launch_scatter_self(E, h->d_v2c_ptr, h->d_v2c_idx, h->d_node2dof, (const unsigned char*)dv(o_vloc),
                         (int)nv, dim, dS, h->dA, lda, h->stream);
     HIPCHK(hipGetLastError());
+    if (o.precision == FL_MIXED) {
+        if ((rc = ensure_dev(h, &h->dA32, &h->A32_cap, sizeof(float) * (size_t)n * (size_t)lda + 16))) return rc;
+        launch_to_f32(h->dA, lda, n, h->dA32, h->stream);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipEventRecord(ev[4], h->stream));
     unsigned long long cnt[16];
     HIPCHK(hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
@@ -830,7 +850,7 @@ int fl_matvec(fl_handle* h, const double* x, double* y) {
 }
 
 static int ensure_solver(fl_handle* h) {
-    if (h->w_n == h->n) return FL_OK;
+    if (h->w_n == h->n && (h->opts.precision != FL_MIXED || h->w32)) return FL_OK;
     free_solver(h);
     const int64_t n = h->n;
     const int nblk = (int)((n + 255) / 256);
@@ -839,7 +859,90 @@ static int ensure_solver(fl_handle* h) {
     HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * nblk + nmv + 8)));
     HIPCHK(hipMalloc((void**)&h->w_scal, sizeof(double) * 16));
     HIPCHK(hipMalloc((void**)&h->w_flag, sizeof(int) * 8));
+    if (h->opts.precision == FL_MIXED) HIPCHK(hipMalloc((void**)&h->w32, sizeof(float) * (size_t)(9 * n + 16)));
     h->w_n = n;
+    return FL_OK;
+}
+
+// FP64 iterative refinement around FP32 Jacobi-PCG (FL_MIXED).
+static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit,
+                       int32_t* iters, double* relres) {
+    const int64_t n = h->n;
+    const int nblk = (int)((n + 255) / 256);
+    double* r = h->w;                 // FP64 residual
+    float* W = h->w32;
+    CgState32 S{};
+    S.n = n;
+    S.A = h->dA32;
+    S.lda = h->lda;
+    S.d = W;
+    S.b = W + n;                      // FP32 copy of the residual
+    S.x = W + 2 * n;                  // FP32 correction
+    S.r = W + 3 * n;
+    S.z = W + 4 * n;
+    S.p = W + 5 * n;                  // 2 n
+    S.q = W + 7 * n;
+    S.part = h->w_part;
+    S.scal = h->w_scal;
+    S.flag = h->w_flag;
+    S.nblk = nblk;
+    const double rtol_in = 1e-4;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    launch_diag32(h->dA32, h->lda, n, (float*)S.d, h->stream);
+    launch_zero(u, n, h->stream);
+    double bb = -1.0, rr = 0.0;
+    int total_inner = 0, outer = 0, status = FL_OK;
+    for (;;) {
+        launch_residual(h->dA, h->lda, n, u, b, r, (float*)S.b, h->w_part, nblk, h->stream);
+        launch_dot2(r, r, r, n, h->w_part, nblk, h->w_scal + 8, h->stream);
+        HIPCHK(hipGetLastError());
+        double rs[2];
+        HIPCHK(hipMemcpyAsync(rs, h->w_scal + 8, sizeof(rs), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        rr = rs[0];
+        if (bb < 0) bb = rr;
+        if (!(rr == rr) || rr > 1.79e308) { status = FL_ENONFINITE; break; }
+        if (std::sqrt(rr) <= rtol * std::sqrt(bb) || total_inner >= maxit || outer >= 60) break;
+        // inner FP32 solve A32 e = r32
+        S.rtol = rtol_in;
+        S.maxit = maxit - total_inner;
+        launch_cg32_init(S, h->stream);
+        int flag[3] = {0, 0, 0};
+        int it = 0;
+        HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        while (!flag[0] && it < S.maxit) {
+            int m = std::min(16, S.maxit - it);
+            for (int j = 0; j < m; ++j) launch_cg32_iter_at(S, it + j, h->stream);
+            HIPCHK(hipGetLastError());
+            it += m;
+            HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+        if (flag[2] == 1) { status = FL_EBREAKDOWN; break; }
+        total_inner += flag[1];
+        launch_add_correction(u, S.x, n, h->stream);
+        ++outer;
+    }
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    double rel = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
+    h->st.t_solve_ms = ms;
+    h->st.last_iters = total_inner;
+    h->st.last_relres = rel;
+    h->st.last_outer = outer;
+    if (iters) *iters = total_inner;
+    if (relres) *relres = rel;
+    if (status == FL_EBREAKDOWN) return fail(h, FL_EBREAKDOWN, "CG breakdown: p.Ap <= 0");
+    if (status == FL_ENONFINITE) return fail(h, FL_ENONFINITE, "non-finite residual");
+    if (!(rel <= rtol)) return FL_ENOCONV;
     return FL_OK;
 }
 
@@ -857,6 +960,7 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     HIPCHK(hipSetDevice(h->device));
     int rc = ensure_solver(h);
     if (rc) return rc;
+    if (h->opts.precision == FL_MIXED) return solve_mixed(h, b, u, rtol, maxit, iters, relres);
     const int64_t n = h->n;
     CgState S{};
     S.n = n;
@@ -913,6 +1017,7 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     h->st.t_solve_ms = ms;
     h->st.last_iters = iterations;
     h->st.last_relres = rel;
+    h->st.last_outer = 0;
     if (iters) *iters = iterations;
     if (relres) *relres = rel;
     if (flag[2] == 1) return fail(h, FL_EBREAKDOWN, "CG breakdown: p.Ap <= 0");

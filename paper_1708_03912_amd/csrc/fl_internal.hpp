@@ -25,6 +25,8 @@ struct RuleTables {
     double seg[36][8];
     double r0_x[2], r0_w[2];            // 2-point rule, weight r^{-2s} on [0,1]
     double r1_x[2], r1_w[2];            // 2-point rule, weight r^{1-2s} on [0,1]
+    float trif[TRI_TAB][12];            // FP32 copies for the mixed-precision path
+    float segf[36][8];
 };
 
 __host__ __device__ inline int gl_off(int k) { return k * (k - 1) / 2; }
@@ -59,6 +61,7 @@ struct FarParams {
     long long lda;
     double* S;              // T x 6 per-element diagonal-block accumulators
     unsigned long long* cls_count;  // ncls+1 counters
+    int mixed;              // 1: separated pairs evaluated in FP32
 };
 
 struct TouchParams {
@@ -101,6 +104,7 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
                          const double* S, double* A, long long lda, hipStream_t st);
 void launch_zero(double* p, long long n, hipStream_t st);
+void launch_to_f32(const double* A, long long lda, long long n, float* A32, hipStream_t st);
 void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
                      const double* meas, int dim, long long n, double* b, hipStream_t st);
 
@@ -132,6 +136,36 @@ struct CgState {
 void launch_cg_init(const CgState& s, hipStream_t st);
 void launch_cg_iter_at(const CgState& s, int it, hipStream_t st);
 void launch_cg_final(const CgState& s, int it, hipStream_t st);
+
+// FP32 Jacobi-PCG (inner solver of the mixed-precision refinement); same
+// algorithm and status layout as CgState, vectors and matrix in FP32, dot
+// products accumulated in FP64.
+struct CgState32 {
+    long long n;
+    const float* A;
+    long long lda;
+    const float* d;
+    const float* b;
+    float* x;
+    float* r;
+    float* z;
+    float* p;           // 2 x n
+    float* q;
+    double* part;
+    double* scal;
+    int* flag;
+    double rtol;
+    int maxit;
+    int nblk;
+};
+void launch_cg32_init(const CgState32& s, hipStream_t st);
+void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st);
+void launch_cg32_final(const CgState32& s, int it, hipStream_t st);
+// y = b - A x (FP64 residual), x += e (FP32 correction)
+void launch_residual(const double* A, long long lda, long long n, const double* x, const double* b,
+                     double* r, float* r32, double* part, int nblk, hipStream_t st);
+void launch_diag32(const float* A, long long lda, long long n, float* d, hipStream_t st);
+void launch_add_correction(double* u, const float* e, long long n, hipStream_t st);
 void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
                  int nblk, double* out, hipStream_t st);
 

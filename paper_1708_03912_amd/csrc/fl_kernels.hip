@@ -138,13 +138,120 @@ __device__ __forceinline__ void far_pair1(int k, const double* X, const double* 
     }
 }
 
-template <int DIM>
+// FP32 variants for the mixed-precision assembly: kernel power with the
+// hardware base-2 log / exp (v_log_f32, v_exp_f32), FP32 sums within the
+// pair.  The offset between the two elements' first vertices is formed in
+// FP64 before rounding, so coordinates far from the origin lose nothing.
+__device__ __forceinline__ float kpow32(float r2, float pe) {
+    return __builtin_amdgcn_exp2f(pe * __builtin_amdgcn_logf(r2));
+}
+
+template <int KO>
+__device__ __forceinline__ void far_pair2_f32(int k, const double* X, const double* Y, double pe64,
+                                              double* SK, double* ST, double* O) {
+    if (KO > 0) k = KO;
+    const int Q = k * k;
+    const int off = tri_off(k);
+    const float pe = (float)pe64;
+    const float ox = (float)(X[0] - Y[0]), oy = (float)(X[1] - Y[1]);
+    const float ex0 = (float)(X[2] - X[0]), ey0 = (float)(X[3] - X[1]);
+    const float ex1 = (float)(X[4] - X[0]), ey1 = (float)(X[5] - X[1]);
+    const float fx0 = (float)(Y[2] - Y[0]), fy0 = (float)(Y[3] - Y[1]);
+    const float fx1 = (float)(Y[4] - Y[0]), fy1 = (float)(Y[5] - Y[1]);
+    float sk[6] = {0, 0, 0, 0, 0, 0}, st[6] = {0, 0, 0, 0, 0, 0}, oo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        const float* cq = c_R.trif[off + q];
+        const float yx = cq[0] * fx0 + cq[1] * fx1 - ox;
+        const float yy = cq[0] * fy0 + cq[1] * fy1 - oy;
+        float gy = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f, t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f, t4 = 0.f,
+              t5 = 0.f;
+        auto body = [&](int p) {
+            const float* cp = c_R.trif[off + p];
+            const float dx = (cp[0] * ex0 + cp[1] * ex1) - yx;
+            const float dy = (cp[0] * ey0 + cp[1] * ey1) - yy;
+            const float kv = kpow32(dx * dx + dy * dy, pe);
+            gy += cp[2] * kv;
+            n0 += cp[3] * kv;
+            n1 += cp[4] * kv;
+            n2 += cp[5] * kv;
+            t0 += cp[6] * kv;
+            t1 += cp[7] * kv;
+            t2 += cp[8] * kv;
+            t3 += cp[9] * kv;
+            t4 += cp[10] * kv;
+            t5 += cp[11] * kv;
+        };
+        if constexpr (KO > 0) {
+#pragma unroll
+            for (int p = 0; p < KO * KO; ++p) body(p);
+        } else {
+#pragma unroll 1
+            for (int p = 0; p < Q; ++p) body(p);
+        }
+        const float wq = cq[2];
+        sk[0] += wq * t0; sk[1] += wq * t1; sk[2] += wq * t2;
+        sk[3] += wq * t3; sk[4] += wq * t4; sk[5] += wq * t5;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) st[m] += cq[6 + m] * gy;
+        const float na[3] = {n0, n1, n2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) oo[3 * a + b] += cq[3 + b] * na[a];
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { SK[m] = sk[m]; ST[m] = st[m]; }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) O[m] = oo[m];
+}
+
+__device__ __forceinline__ void far_pair1_f32(int k, const double* X, const double* Y, double pe64,
+                                              double* SK, double* ST, double* O) {
+    const int off = gl_off(k);
+    const float pe = (float)pe64;
+    const float ox = (float)(X[0] - Y[0]);
+    const float ex = (float)(X[1] - X[0]), fx = (float)(Y[1] - Y[0]);
+    float sk0 = 0.f, sk1 = 0.f, sk3 = 0.f, st0 = 0.f, st1 = 0.f, st3 = 0.f, o0 = 0.f, o1 = 0.f, o3 = 0.f,
+          o4 = 0.f;
+#pragma unroll 1
+    for (int q = 0; q < k; ++q) {
+        const float* cq = c_R.segf[off + q];
+        const float yv = cq[0] * fx - ox;
+        float gy = 0.f, n0 = 0.f, n1 = 0.f, t0 = 0.f, t1 = 0.f, t3 = 0.f;
+#pragma unroll 1
+        for (int p = 0; p < k; ++p) {
+            const float* cp = c_R.segf[off + p];
+            const float d = cp[0] * ex - yv;
+            const float kv = kpow32(d * d, pe);
+            gy += cp[1] * kv;
+            n0 += cp[2] * kv;
+            n1 += cp[3] * kv;
+            t0 += cp[4] * kv;
+            t1 += cp[5] * kv;
+            t3 += cp[6] * kv;
+        }
+        const float wq = cq[1];
+        sk0 += wq * t0; sk1 += wq * t1; sk3 += wq * t3;
+        st0 += cq[4] * gy; st1 += cq[5] * gy; st3 += cq[6] * gy;
+        o0 += cq[2] * n0; o1 += cq[3] * n0; o3 += cq[2] * n1; o4 += cq[3] * n1;
+    }
+    for (int m = 0; m < 6; ++m) { SK[m] = 0.0; ST[m] = 0.0; }
+    for (int m = 0; m < 9; ++m) O[m] = 0.0;
+    SK[0] = sk0; SK[1] = sk1; SK[3] = sk3;
+    ST[0] = st0; ST[1] = st1; ST[3] = st3;
+    O[0] = o0; O[1] = o1; O[3] = o3; O[4] = o4;
+}
+
+template <int DIM, int MIX>
 __device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe,
                                          double* SK, double* ST, double* O) {
     if (DIM == 2) {
-        far_pair2<0>(k, X, Y, pe, SK, ST, O);
+        if (MIX) far_pair2_f32<0>(k, X, Y, pe, SK, ST, O);
+        else far_pair2<0>(k, X, Y, pe, SK, ST, O);
     } else {
-        far_pair1(k, X, Y, pe, SK, ST, O);
+        if (MIX) far_pair1_f32(k, X, Y, pe, SK, ST, O);
+        else far_pair1(k, X, Y, pe, SK, ST, O);
     }
 }
 
@@ -180,7 +287,7 @@ __device__ __forceinline__ double dist2_nc(double x0, double y0, double x1, doub
 // are accumulated in LDS over the block's local DOF numbering and flushed
 // to A (and its mirror) with one global atomic per touched entry; the
 // diagonal-block increments go to per-element accumulators S.
-template <int DIM, int FARK>
+template <int DIM, int FARK, int MIX>
 __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
@@ -289,10 +396,13 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
         double O[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (FARK > 0) {
             if (valid) {
-                if (DIM == 2)
-                    far_pair2<FARK>(FARK, X, Y, P.pe, SK, ST, O);
-                else
-                    far_pair1(FARK, X, Y, P.pe, SK, ST, O);
+                if (DIM == 2) {
+                    if (MIX) far_pair2_f32<FARK>(FARK, X, Y, P.pe, SK, ST, O);
+                    else far_pair2<FARK>(FARK, X, Y, P.pe, SK, ST, O);
+                } else {
+                    if (MIX) far_pair1_f32(FARK, X, Y, P.pe, SK, ST, O);
+                    else far_pair1(FARK, X, Y, P.pe, SK, ST, O);
+                }
             }
         } else {
             // one pass per distinct order present in the wave
@@ -304,7 +414,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 if (!P.kfirst[c]) continue;
                 const int kc = P.kf[c];
                 if (__any(myk == kc)) {
-                    if (myk == kc) far_pair<DIM>(kc, X, Y, P.pe, SK, ST, O);
+                    if (myk == kc) far_pair<DIM, MIX>(kc, X, Y, P.pe, SK, ST, O);
                 }
             }
         }
@@ -380,7 +490,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
 // bucket at a time, so all lanes of a wave run the same order.  Diagonal
 // blocks, self terms and off-diagonal blocks are accumulated in LDS as in
 // far_kernel and flushed once per tile.
-template <int DIM>
+template <int DIM, int MIX>
 __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
@@ -492,7 +602,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 #pragma unroll
             for (int q = 0; q < NC; ++q) { X[q] = sI[q][r]; Y[q] = sJ[q][l]; }
             double SK[6], ST[6], O[9];
-            far_pair<DIM>(k, X, Y, P.pe, SK, ST, O);
+            far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
             const double f = P.C * sI[9][r] * sJ[9][l];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
@@ -552,16 +662,23 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
-    if (P.dim == 2)
-        hipLaunchKernelGGL((near_kernel<2>), grid, block, 0, st, E, P);
-    else
-        hipLaunchKernelGGL((near_kernel<1>), grid, block, 0, st, E, P);
+    if (P.dim == 2) {
+        if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1>), grid, block, 0, st, E, P);
+        else hipLaunchKernelGGL((near_kernel<2, 0>), grid, block, 0, st, E, P);
+    } else {
+        if (P.mixed) hipLaunchKernelGGL((near_kernel<1, 1>), grid, block, 0, st, E, P);
+        else hipLaunchKernelGGL((near_kernel<1, 0>), grid, block, 0, st, E, P);
+    }
 }
 
 void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
-#define FL_FAR_CASE(D, K) hipLaunchKernelGGL((far_kernel<D, K>), grid, block, 0, st, E, P)
+#define FL_FAR_CASE(D, K)                                                          \
+    do {                                                                           \
+        if (P.mixed) hipLaunchKernelGGL((far_kernel<D, K, 1>), grid, block, 0, st, E, P); \
+        else hipLaunchKernelGGL((far_kernel<D, K, 0>), grid, block, 0, st, E, P);         \
+    } while (0)
     if (P.dim == 2) {
         switch (fark) {
             case 1: FL_FAR_CASE(2, 1); break;
@@ -1398,6 +1515,234 @@ void launch_dot2(const double* a, const double* b, const double* c, long long n,
                  int nblk, double* out, hipStream_t st) {
     hipLaunchKernelGGL(dot2_kernel, dim3(nblk), dim3(256), 0, st, a, b, c, n, part, nblk);
     hipLaunchKernelGGL(dot2_reduce_kernel, dim3(1), dim3(256), 0, st, part, nblk, out);
+}
+
+// ------------------------------------------------ mixed precision --
+
+__global__ void to_f32_kernel(const double* A, long long lda, long long n, float* A32) {
+    const long long total = n * lda;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x)
+        A32[i] = (float)A[i];
+}
+
+void launch_to_f32(const double* A, long long lda, long long n, float* A32, hipStream_t st) {
+    if (n == 0) return;
+    long long blocks = (n * lda + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, lda, n, A32);
+}
+
+__global__ void diag32_kernel(const float* A, long long lda, long long n, float* d) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = A[i * lda + i];
+}
+
+void launch_diag32(const float* A, long long lda, long long n, float* d, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(diag32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, lda, n, d);
+}
+
+// r = b - A x in FP64 (one wave per row), also r32 = (float) r and
+// per-block partials of r.r
+__global__ __launch_bounds__(MV_THREADS) void residual_kernel(const double* __restrict__ A, long long lda,
+                                                              long long n, const double* __restrict__ x,
+                                                              const double* __restrict__ b, double* r,
+                                                              float* r32, double* part) {
+    __shared__ double sh[4];
+    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double rr = 0.0;
+    if (row < n) {
+        double v = row_dot(A + row * lda, x, n, lane);
+        if (lane == 0) {
+            const double ri = b[row] - v;
+            r[row] = ri;
+            r32[row] = (float)ri;
+            rr = ri * ri;
+        }
+    }
+    double t = block_sum(rr, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+void launch_residual(const double* A, long long lda, long long n, const double* x, const double* b,
+                     double* r, float* r32, double* part, int nblk, hipStream_t st) {
+    (void)nblk;
+    if (n == 0) return;
+    hipLaunchKernelGGL(residual_kernel, dim3(mv_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, b, r,
+                       r32, part);
+}
+
+__global__ void add_correction_kernel(double* u, const float* e, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += (double)e[i];
+}
+
+void launch_add_correction(double* u, const float* e, long long n, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(add_correction_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, e, n);
+}
+
+// FP32 row . (z + beta p) with 16-byte loads (4 floats), FP32 products
+// summed in FP32 per lane and in FP64 across the wave
+__device__ __forceinline__ double row_dot_comb32(const float* __restrict__ a, const float* __restrict__ z,
+                                                 const float* __restrict__ pp, float beta, long long n,
+                                                 int lane) {
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    const long long n4 = n & ~3LL;
+    long long j = 4 * lane;
+    for (; j + 3 * 256 < n4; j += 4 * 256) {
+        float4 a0 = *(const float4*)(a + j), a1 = *(const float4*)(a + j + 256);
+        float4 a2 = *(const float4*)(a + j + 512), a3 = *(const float4*)(a + j + 768);
+        float4 z0 = *(const float4*)(z + j), z1 = *(const float4*)(z + j + 256);
+        float4 z2 = *(const float4*)(z + j + 512), z3 = *(const float4*)(z + j + 768);
+        float4 p0 = *(const float4*)(pp + j), p1 = *(const float4*)(pp + j + 256);
+        float4 p2 = *(const float4*)(pp + j + 512), p3 = *(const float4*)(pp + j + 768);
+        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y) + a0.z * (z0.z + beta * p0.z) +
+                a0.w * (z0.w + beta * p0.w);
+        acc1 += a1.x * (z1.x + beta * p1.x) + a1.y * (z1.y + beta * p1.y) + a1.z * (z1.z + beta * p1.z) +
+                a1.w * (z1.w + beta * p1.w);
+        acc2 += a2.x * (z2.x + beta * p2.x) + a2.y * (z2.y + beta * p2.y) + a2.z * (z2.z + beta * p2.z) +
+                a2.w * (z2.w + beta * p2.w);
+        acc3 += a3.x * (z3.x + beta * p3.x) + a3.y * (z3.y + beta * p3.y) + a3.z * (z3.z + beta * p3.z) +
+                a3.w * (z3.w + beta * p3.w);
+    }
+    for (; j < n4; j += 256) {
+        float4 a0 = *(const float4*)(a + j), z0 = *(const float4*)(z + j), p0 = *(const float4*)(pp + j);
+        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y) + a0.z * (z0.z + beta * p0.z) +
+                a0.w * (z0.w + beta * p0.w);
+    }
+    if (lane == 0)
+        for (long long jj = n4; jj < n; ++jj) acc1 += a[jj] * (z[jj] + beta * pp[jj]);
+    return wave_sum((double)((acc0 + acc1) + (acc2 + acc3)));
+}
+
+__global__ __launch_bounds__(256) void cg32_init_kernel(CgState32 S) {
+    __shared__ double sh[4];
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < S.n) {
+        float bi = S.b[i];
+        S.x[i] = 0.f;
+        S.r[i] = bi;
+        float zi = bi / S.d[i];
+        S.z[i] = zi;
+        S.p[S.n + i] = 0.f;
+        rz = (double)bi * zi;
+        rr = (double)bi * bi;
+    }
+    double a = block_sum(rz, sh), b = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        S.part[blockIdx.x] = a;
+        S.part[2 * S.nblk + blockIdx.x] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void cg32_init_reduce_kernel(CgState32 S) {
+    __shared__ double sh[4];
+    double bb = sum_partials(S.part + 2 * S.nblk, S.nblk, sh);
+    if (threadIdx.x == 0) {
+        S.scal[0] = bb;
+        S.scal[1] = bb;
+        S.flag[0] = (bb == 0.0) ? 1 : 0;
+        S.flag[1] = 0;
+        S.flag[2] = 0;
+        if (!(bb == bb) || bb > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
+    }
+}
+
+__global__ __launch_bounds__(MV_THREADS) void cg32_matvec_kernel(CgState32 S, int it, int nmv) {
+    __shared__ double sh[4];
+    if (*(volatile int*)&S.flag[0]) return;
+    const int par = it & 1;
+    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
+    const double rr = sum_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk, sh);
+    const double bb = S.scal[0];
+    if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.flag[0] = 1;
+            S.flag[1] = it;
+            S.scal[1] = rr;
+            if (!(rr == rr)) S.flag[2] = 2;
+        }
+        return;
+    }
+    double beta = 0.0;
+    if (it > 0) beta = rz / sum_partials(S.part + (1 - par) * S.nblk, S.nblk, sh);
+    const float fb = (float)beta;
+    const float* pprev = S.p + (long long)(1 - par) * S.n;
+    float* pcur = S.p + (long long)par * S.n;
+    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double pq = 0.0;
+    if (row < S.n) {
+        double v = row_dot_comb32(S.A + row * S.lda, S.z, pprev, fb, S.n, lane);
+        if (lane == 0) {
+            const float pr = S.z[row] + fb * pprev[row];
+            pcur[row] = pr;
+            S.q[row] = (float)v;
+            pq = v * pr;
+        }
+    }
+    double t = block_sum(pq, sh);
+    if (threadIdx.x == 0) S.part[4 * S.nblk + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void cg32_update_kernel(CgState32 S, int it, int nmv) {
+    __shared__ double sh[4];
+    if (*(volatile int*)&S.flag[0]) return;
+    const int par = it & 1;
+    const double pq = sum_partials(S.part + 4 * S.nblk, nmv, sh);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.flag[0] = 1;
+            S.flag[1] = it;
+            S.flag[2] = 1;
+        }
+        return;
+    }
+    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
+    const float alpha = (float)(rz / pq);
+    const float* pcur = S.p + (long long)par * S.n;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < S.n) {
+        S.x[i] += alpha * pcur[i];
+        float ri = S.r[i] - alpha * S.q[i];
+        S.r[i] = ri;
+        float zi = ri / S.d[i];
+        S.z[i] = zi;
+        a = (double)ri * zi;
+        b = (double)ri * ri;
+    }
+    double ta = block_sum(a, sh), tb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        S.part[(1 - par) * S.nblk + blockIdx.x] = ta;
+        S.part[2 * S.nblk + (1 - par) * S.nblk + blockIdx.x] = tb;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.flag[1] = it + 1;
+}
+
+__global__ __launch_bounds__(256) void cg32_final_kernel(CgState32 S, int it) {
+    __shared__ double sh[4];
+    const double rr = sum_partials(S.part + 2 * S.nblk + (it & 1) * S.nblk, S.nblk, sh);
+    if (threadIdx.x == 0 && !S.flag[0]) S.scal[1] = rr;
+}
+
+void launch_cg32_init(const CgState32& s, hipStream_t st) {
+    hipLaunchKernelGGL(cg32_init_kernel, dim3(s.nblk), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(cg32_init_reduce_kernel, dim3(1), dim3(256), 0, st, s);
+}
+
+void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) {
+    int nmv = mv_blocks(s.n);
+    hipLaunchKernelGGL(cg32_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s, it, nmv);
+    hipLaunchKernelGGL(cg32_update_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+}
+
+void launch_cg32_final(const CgState32& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL(cg32_final_kernel, dim3(1), dim3(256), 0, st, s, it);
 }
 
 }  // namespace fl

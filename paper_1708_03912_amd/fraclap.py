@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfraclap.so")
 FL_OK, FL_EINVAL, FL_EMESH, FL_ENOMEM, FL_EDEVICE = 0, -1, -2, -3, -4
 FL_ESTATE, FL_ENONFINITE, FL_EBREAKDOWN, FL_ENOCONV = -5, -6, -7, 1
 FL_DOF_PAPER, FL_DOF_INTERIOR = 0, 1
+FL_FP64, FL_MIXED = 0, 1
 FL_MAX_CLASSES = 8
 
 ERROR_NAMES = {0: "FL_OK", -1: "FL_EINVAL", -2: "FL_EMESH", -3: "FL_ENOMEM", -4: "FL_EDEVICE",
@@ -34,7 +35,7 @@ class FlOpts(C.Structure):
                 ("k_touch_bnd", C.c_int), ("n_classes", C.c_int),
                 ("theta", C.c_double * FL_MAX_CLASSES),
                 ("k_far", C.c_int * (FL_MAX_CLASSES + 1)),
-                ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1))]
+                ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1)), ("precision", C.c_int)]
 
 
 class FlStats(C.Structure):
@@ -46,7 +47,7 @@ class FlStats(C.Structure):
                 ("kernel_evals", C.c_int64), ("t_plan_ms", C.c_double),
                 ("t_assemble_ms", C.c_double), ("t_far_ms", C.c_double), ("t_self_ms", C.c_double),
                 ("t_touch_ms", C.c_double), ("t_scatter_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("last_iters", C.c_int32), ("last_relres", C.c_double)]
+                ("last_iters", C.c_int32), ("last_relres", C.c_double), ("last_outer", C.c_int32)]
 
 
 class FraclapError(RuntimeError):
@@ -96,8 +97,10 @@ def default_opts() -> FlOpts:
 
 
 def make_opts(k_touch=None, k_touch_bnd=None, theta=None, k_far=None, k_far_bnd=None,
-              dof_mode=None, with_boundary=None) -> FlOpts:
+              dof_mode=None, with_boundary=None, precision=None) -> FlOpts:
     o = default_opts()
+    if precision is not None:
+        o.precision = {"fp64": FL_FP64, "mixed": FL_MIXED}.get(precision, precision)
     if dof_mode is not None:
         o.dof_mode = {"paper": FL_DOF_PAPER, "interior": FL_DOF_INTERIOR}.get(dof_mode, dof_mode)
     if with_boundary is not None:

@@ -242,3 +242,35 @@ def test_repeatable():
     assert np.abs(A1 - A2).max() <= 1e-14 * np.abs(A1).max()
     h1.close()
     h2.close()
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_mixed_precision_assembly_and_refined_solve(s):
+    """FL_MIXED: separated pairs in FP32, FP64 everywhere else; the matrix
+    stays within FP32 rounding of the FP64 one, and the refined solve reaches
+    rtol on it with an energy-norm gap to the FP64 solution far below the
+    discretisation error (equal error: gap <= 0.1 E)."""
+    mesh = M.disk_for_cells(1500, seed=5)
+    h64 = gpu_assemble(mesh, s, F.default_opts())
+    hmx = gpu_assemble(mesh, s, F.make_opts(precision="mixed"))
+    A64, Amx = h64.export_matrix(), hmx.export_matrix()
+    assert np.abs(Amx - A64).max() <= 2e-6 * np.abs(A64).max()
+    n = h64.n
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    h64.load_vector_one(b)
+    u64, umx = torch.zeros_like(b), torch.zeros_like(b)
+    h64.solve(b, u64, rtol=1e-12)
+    it, rel, rc = hmx.solve(b, umx, rtol=1e-12)
+    assert rc == F.FL_OK and rel <= 1e-12
+    st = hmx.stats()
+    assert st.last_outer >= 2
+    fu = O.ball_fu(2, s)
+    E = math.sqrt(h64.energy_error2(fu, b, u64))
+    du = (umx - u64).cpu().numpy()
+    gap = math.sqrt(du @ A64 @ du)
+    assert gap <= 1e-3 * E
+    # refined solution solves the mixed matrix to rtol
+    r = b.cpu().numpy() - Amx @ umx.cpu().numpy()
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(b.cpu().numpy())
+    h64.close()
+    hmx.close()
