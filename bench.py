@@ -42,7 +42,38 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cells", type=int, default=8000, help="target triangle count of the disk mesh")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
+                         "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_disk8k.json")) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, "paper_1708_03912_amd", "csrc", "fl_kernels.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return t if t.get("source_sha256") == sha else None
+
+
+def copy_calib(mib):
+    """Plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE of one launch
+    should read mib * 1024 KiB each; the ratio scales the kernels' counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_KiB_per_launch": mib * 1024, "launches": 3}), flush=True)
 
 
 def main():
@@ -51,6 +82,9 @@ def main():
         print("bench.py: this build runs on one GPU only; the dense path's multi-GPU "
               "row sharding is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        copy_calib(args.copy_calib)
+        return
     import numpy as np
     import torch
     from paper_1708_03912_amd import fraclap as F, meshgen as M
@@ -136,14 +170,17 @@ def main():
     solve_time = sum(solve_ms) / len(solve_ms)
     asm_time = sum(asm_ms) / len(asm_ms)
     iters = sum(result[s]["iters"] for s in svals)
-    rf_far = {"kernel": "far_kernel<2> (separated element pairs)", "bound": "alu",
+    traffic = measured_traffic()
+    rf_far = {"kernel": "near_kernel<2> + far_kernel<2> (separated element pairs)", "bound": "alu",
               "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-              "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4), "traffic": None,
+              "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4),
+              "traffic": traffic and traffic["separated_pairs_bytes_per_assembly"],
               "per_launch_ms": round(far_time * 1e3 / len(svals), 4),
               "evals_per_launch": far_evals // len(svals), "flops_per_eval": FLOPS_PER_EVAL}
     rf_mv = {"kernel": "matvec / cg_matvec (dense FP64 GEMV)", "bound": "hbm",
              "achieved": round(mv_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-             "frac": round(mv_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+             "frac": round(mv_gbps / HBM_PEAK_GBPS, 4),
+             "traffic": traffic and traffic["matvec_bytes_per_launch"],
              "per_launch_ms": round(mv_ms, 5), "bytes_per_launch": mv_bytes,
              "note": "A is %.0f MB, below the 256 MB Infinity Cache: cache-resident rate" % (n * n * 8 / 1e6)}
     # dominant: the far kernel's total time vs the CG matvec time (iterations x matvec)
