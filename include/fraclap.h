@@ -60,6 +60,17 @@ extern "C" {
 #define FL_FP64 0           /* every step in FP64                            */
 #define FL_MIXED 1          /* separated pairs and the inner CG in FP32      */
 
+#define FL_F64 0            /* element types of fl_matmul / fl_solve_batch    */
+#define FL_F32 1            /* FP32 matrix copy, FP32 vectors                 */
+#define FL_BF16 2           /* bf16 matrix (one plane), FP32 vectors split
+                               into bf16 hi + lo, FP32 accumulation         */
+#define FL_BF16X2 3         /* bf16 hi + lo matrix planes, as FL_BF16 else   */
+
+#define FL_RHS_ONE 0        /* f = 1                                          */
+#define FL_RHS_FOURIER16 1  /* f = sum of 16 cosine modes (coefficients)      */
+#define FL_RHS_P1_NODAL 2   /* f = P1 interpolant of nodal values             */
+
+#define FL_MAX_BATCH 16     /* s values per fl_assemble_batch                 */
 #define FL_MAX_CLASSES 8    /* distance classes for separated pairs          */
 #define FL_MAX_ORDER_FAR 8  /* largest order for separated pairs             */
 #define FL_MAX_ORDER_TOUCH 16 /* largest order for touching pairs            */
@@ -198,8 +209,89 @@ int fl_solve(fl_handle *h, const double *b, double *u, double rtol, int32_t maxi
  * b, uh: device, length n.  *e2_out: host.  Synchronises the stream. */
 int fl_energy_error2(fl_handle *h, double fu, const double *b, const double *uh, double *e2_out);
 
-/* Counters and timings of the last assembly / solve. */
+/* Counters and timings of the last assembly / solve (after a batch call:
+ * pair counts of one s, times summed over the batch). */
 int fl_stats(const fl_handle *h, fl_stats_t *out);
+
+/* Replace the assembled FP64 matrix by src (n x n, leading dimension
+ * ld >= n, device pointer if on_device else host), e.g. to restore a saved
+ * matrix; n and the DOF map are those of the last fl_assemble.  FL_ESTATE
+ * before fl_assemble.  Synchronises the stream when src is on the host. */
+int fl_import_matrix(fl_handle *h, const double *src, int64_t ld, int on_device);
+
+/* Load vectors b_i = <f, phi_i> (Sec. 2) for nrhs right-hand sides, after
+ * fl_assemble or fl_assemble_batch (same DOFs).  b: device, n x nrhs,
+ * column-major with leading dimension n, owned by the caller.
+ *   FL_RHS_ONE        f = 1, exact (coeffs unused, may be NULL);
+ *   FL_RHS_FOURIER16  host coeffs[16 c + m], f_c = sum_m coeffs psi_m with
+ *                     2D psi_m(x) = cos(pi (k1 x1 + k2 x2)), m = 4 k1 + k2,
+ *                     k1, k2 in 0..3 (1D: psi_m(x) = cos(pi m x));
+ *                     order-4 collapsed Gauss rule per cell (4-point Gauss
+ *                     per segment);
+ *   FL_RHS_P1_NODAL   host coeffs, nv x nrhs column-major nodal values of
+ *                     f (all vertices); b = mass matrix times f, exact. */
+int fl_load_vector(fl_handle *h, int kind, const double *coeffs, int64_t nrhs, double *b);
+
+/* Batch of fractional orders on the current mesh (Sec. 2 operator for each
+ * s_j, same pair decomposition and orders as fl_assemble): assembles
+ * A^{s_j}, j < ns <= FL_MAX_BATCH, in FP64 into handle-owned device
+ * memory.  All s_j must give the same DOF set: dof_mode FL_DOF_INTERIOR,
+ * or every s_j on the same side of 1/2 (else FL_EINVAL).  *n_out receives
+ * n.  Lower-precision copies (FP32 / bf16 planes) are made on first use by
+ * fl_matmul / fl_solve_batch and kept until the next assembly.
+ * Synchronises the stream. */
+int fl_assemble_batch(fl_handle *h, const double *s, int ns, const fl_opts *opts, int64_t *n_out);
+
+/* Export matrix j of the batch (as fl_export_matrix). */
+int fl_export_batch_matrix(fl_handle *h, int j, double *dst, int64_t ld, int on_device);
+
+/* Y = A^{s_j} X for nrhs columns (Sec. 5 dense product; nrhs > 1 runs on
+ * the matrix cores).  Needs fl_assemble_batch.  s_index = j, or -1 for
+ * every matrix of the batch (then X and Y hold ns blocks, block j at
+ * j * ld * nrhs elements).  X: n x nrhs column-major, leading dimension
+ * ldx >= n; Y likewise with ldy.  dtype FL_F64: X, Y double, FP64 matrix;
+ * FL_F32 / FL_BF16 / FL_BF16X2: X, Y float, the matrix in that storage,
+ * FP32 accumulation.  Device pointers owned by the caller, not aliased. */
+int fl_matmul(fl_handle *h, int s_index, int dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
+              int64_t nrhs);
+
+/* Solve A^{s_j} U_j = B_j for every j of the batch and nrhs columns
+ * (Sec. 5 Jacobi-PCG, x0 = 0, stop at ||r|| <= rtol ||b|| per column).
+ * B: device, n x nrhs column-major (leading dimension ldb), block j at
+ * B + j * strideB (strideB = 0: the same right-hand sides for every j);
+ * U likewise (ldu, strideU > 0 unless ns = 1), overwritten.
+ *   inner = FL_F64   plain FP64 batched CG on the FP64 matrices;
+ *   inner = FL_F32 / FL_BF16 / FL_BF16X2   FP64 iterative refinement: the
+ *           residual b - A u is formed with the FP64 matrix, each
+ *           correction comes from the batched CG in FP32 arithmetic on the
+ *           matrix in that storage, to a relative residual of 1e-4 (1e-2
+ *           for FL_BF16); maxit bounds each column's inner iterations.
+ * Converged columns drop out of the products.  iters / relres: host
+ * arrays of ns x nrhs (index j * nrhs + c; may be NULL): CG iterations
+ * (refinement: inner iterations summed) and the final relative residual.
+ * Returns FL_ENOCONV if a column did not converge, FL_EBREAKDOWN if p.Ap
+ * <= 0 occurred, FL_ENONFINITE for non-finite data.  Synchronises the
+ * stream. */
+int fl_solve_batch(fl_handle *h, const double *B, int64_t ldb, int64_t strideB, double *U, int64_t ldu,
+                   int64_t strideU, int64_t nrhs, double rtol, int32_t maxit, int inner, int32_t *iters,
+                   double *relres);
+
+/* One timed kernel configuration of the batched product. */
+typedef struct {
+    int wm, waves, bk, planes; /* rows per wave, waves per workgroup, K stage,
+                                  bf16 matrix planes                       */
+    double ms;                 /* time of one product over the whole batch */
+    double tflops;             /* 2 n^2 * 64 * ns / time                   */
+    double gbps;               /* matrix bytes / time                      */
+} fl_tune_entry;
+
+/* Autotuner: times every GEMM configuration of `dtype` on the current
+ * batch (64 columns per matrix, all matrices) and keeps the fastest for
+ * later fl_matmul / fl_solve_batch calls; without this call the tuner runs
+ * on first use.  out (host, may be NULL): up to max_out entries in
+ * configuration order; *n_out receives the count, *best the index of the
+ * chosen one. */
+int fl_autotune(fl_handle *h, int dtype, fl_tune_entry *out, int max_out, int *n_out, int *best);
 
 #ifdef __cplusplus
 }

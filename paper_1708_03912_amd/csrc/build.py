@@ -1,8 +1,10 @@
 """Build libfraclap.so (gfx950) in-tree with hipcc.
 
-Two translation units: the kernels (default floating-point contraction) and
-the host planner (no contraction, see fl_api.hip).  Packed FP32 instructions
-are disabled for all device code.
+Translation units: the assembly / single-system solver kernels and the
+batched product / solver kernels (default floating-point contraction), the
+host planner (no contraction, see fl_api.hip) and the batched host calls.
+Packed FP32 instructions are disabled for all device code.  Units are built
+in parallel.
 """
 import os
 import subprocess
@@ -15,12 +17,13 @@ ARCH = os.environ.get("FRACLAP_ARCH", "gfx950")
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-UNITS = [("fl_kernels.hip", []), ("fl_api.hip", ["-ffp-contract=off"])]
+UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_api.hip", ["-ffp-contract=off"]),
+         ("fl_batch_api.hip", [])]
 
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, procs = [], []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src, extra in UNITS:
@@ -28,8 +31,11 @@ def build(verbose=False):
         cmd = [hipcc, "-c", os.path.join(HERE, src), "-o", obj] + COMMON + extra
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

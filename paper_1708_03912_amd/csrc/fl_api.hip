@@ -21,62 +21,11 @@
 #include <string>
 #include <vector>
 
+#include "fl_handle.hpp"
 #include "fl_internal.hpp"
 #include "fl_quad.hpp"
 
 using namespace fl;
-
-struct fl_handle {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-
-    // mesh (host copy)
-    int dim = 0;
-    int64_t nv = 0, nc = 0, nb = 0;
-    std::vector<double> verts;
-    std::vector<int32_t> cells, bfacets;
-    std::vector<int32_t> facet_opp;     // vertex of the owning cell opposite the facet
-    std::vector<char> on_boundary;
-
-    // assembly
-    bool assembled = false;
-    double s = 0.0;
-    fl_opts opts{};
-    int64_t n = 0, lda = 0;
-    std::vector<int32_t> dof_node, node2dof;
-
-    // device / pinned buffers, grown on demand and reused
-    char* plan = nullptr;
-    size_t plan_cap = 0;
-    char* pin = nullptr;
-    size_t pin_cap = 0;
-    double* dA = nullptr;
-    size_t A_cap = 0;
-    double* dS = nullptr;
-    size_t S_cap = 0;
-    float* dA32 = nullptr;
-    size_t A32_cap = 0;
-    unsigned long long* dcnt = nullptr;
-
-    // views into the plan buffer used after assembly
-    ElemDev E{};
-    int* d_v2c_ptr = nullptr;
-    int* d_v2c_idx = nullptr;
-    int* d_node2dof = nullptr;
-    int* d_dof_node = nullptr;
-    double* d_meas = nullptr;
-
-    // solver workspace
-    double* w = nullptr;   // r, z, p (2n), q, d, tmp (7 n)
-    float* w32 = nullptr;  // FP32 refinement workspace (8 n)
-    double* w_part = nullptr;
-    double* w_scal = nullptr;
-    int* w_flag = nullptr;
-    int64_t w_n = -1;
-
-    fl_stats_t st{};
-};
 
 namespace {
 
@@ -94,9 +43,12 @@ int fail(fl_handle* h, int code, const std::string& msg) {
 
 void reset_assembly(fl_handle* h) {
     h->assembled = false;
+    h->planned = false;
+    h->B.ns = 0;
     h->n = h->lda = 0;
     h->E = ElemDev{};
     h->d_v2c_ptr = h->d_v2c_idx = h->d_node2dof = h->d_dof_node = nullptr;
+    h->d_vloc = nullptr;
     h->d_meas = nullptr;
 }
 
@@ -110,6 +62,14 @@ void free_buffers(fl_handle* h) {
     if (h->dA32) (void)hipFree(h->dA32);
     h->dA32 = nullptr;
     h->A32_cap = 0;
+    fl_batch& B = h->B;
+    if (B.A64) (void)hipFree(B.A64);
+    if (B.A32) (void)hipFree(B.A32);
+    if (B.Ahi) (void)hipFree(B.Ahi);
+    if (B.Alo) (void)hipFree(B.Alo);
+    if (B.ws) (void)hipFree(B.ws);
+    if (B.hflag) (void)hipHostFree(B.hflag);
+    h->B = fl_batch{};
     h->plan = h->pin = nullptr;
     h->dA = h->dS = nullptr;
     h->dcnt = nullptr;
@@ -378,24 +338,28 @@ int64_t fl_matrix_ld(const fl_handle* h) { return (h && h->assembled) ? h->lda :
 
 const double* fl_matrix_ptr(const fl_handle* h) { return (h && h->assembled) ? h->dA : nullptr; }
 
-int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) {
-    if (!h) return FL_EINVAL;
-    if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
-    if (!(s > 0.0 && s < 1.0)) return fail(h, FL_EINVAL, "s must lie in (0,1)");
-    fl_opts o;
-    if (opts_in) o = *opts_in;
-    else fl_default_opts(&o);
-    int rc = check_opts(h, o);
-    if (rc) return rc;
-    HIPCHK(hipSetDevice(h->device));
-    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
-    reset_assembly(h);
-    auto t0 = std::chrono::steady_clock::now();
+}  // extern "C"
 
+namespace {
+
+// Result of the s-independent planning of an assembly: device views live in
+// the handle (plan buffer), the offsets of the per-launch lists here.
+struct Plan {
+    int64_t T = 0, nv = 0, n = 0;
+    int dim = 0, nper = 0, nblk = 0;
+    size_t o_ft = 0, o_nt = 0, o_bnd = 0, o_bdofs = 0, o_loc = 0, o_vloc = 0, o_ep = 0, o_vp = 0,
+           o_fac = 0, o_fvid = 0;
+    long long n_tiles = 0, n_far_tiles = 0, n_edge = 0, n_vert = 0;
+    double t_plan_ms = 0.0;
+};
+
+// DOF map (Sec. 3), element order, touching-pair lists, tiles, facet data;
+// everything packed and sent to the device plan buffer.
+int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = FL_OK;
     const int dim = h->dim, nper = dim + 1;
     const int64_t T = h->nc, nv = h->nv;
-    // DOF map (Sec. 3): all nodes if s < 1/2 (paper rule), else interior
-    const bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s < 0.5);
     h->node2dof.assign(nv, -1);
     h->dof_node.clear();
     for (int64_t v = 0; v < nv; ++v)
@@ -404,17 +368,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             h->dof_node.push_back((int32_t)v);
         }
     const int64_t n = (int64_t)h->dof_node.size();
-    const int64_t lda = ((n + 31) / 32) * 32;
-    const size_t A_bytes = sizeof(double) * (size_t)n * (size_t)lda + 8;
-    if (A_bytes > h->A_cap) {
-        if (h->dA) (void)hipFree(h->dA);
-        h->dA = nullptr;
-        h->A_cap = 0;
-        size_t freeb = 0, totb = 0;
-        HIPCHK(hipMemGetInfo(&freeb, &totb));
-        if ((double)A_bytes + (double)T * 512.0 > (double)freeb * 0.98)
-            return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
-    }
+    P.T = T;
+    P.nv = nv;
+    P.n = n;
+    P.dim = dim;
+    P.nper = nper;
 
     // internal element order: Morton order of centroids (2D), by x (1D)
     std::vector<int32_t> perm(T);
@@ -527,6 +485,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     }
     // far-field tiles, see launch_far_tiles
     const int nblk = (int)((T + BE - 1) / BE);
+    P.nblk = nblk;
     std::vector<int2> tiles, far_tiles;
     {
         std::vector<double> bx0(nblk, 1e300), bx1(nblk, -1e300), by0(nblk, 1e300), by1(nblk, -1e300),
@@ -603,12 +562,6 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             fvid[2 * e + 1] = f[1];
         }
     }
-    // quadrature tables: cached base rules + the two s-dependent radial rules
-    RuleTables R = base_rules();
-    if (s < 0.5) gauss_jacobi01(2, 0.0, -2.0 * s, R.r0_x, R.r0_w);
-    gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
-    auto t1 = std::chrono::steady_clock::now();
-
     // pack everything into the pinned staging buffer, one copy to the device
     Packer pk;
     std::vector<size_t> offX(NC);
@@ -616,7 +569,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     const size_t o_c0 = pk.add(cen0), o_c1 = pk.add(cen1), o_h2 = pk.add(h2), o_me = pk.add(meas);
     std::vector<size_t> o_vid(nper), o_dof(nper);
     for (int a = 0; a < nper; ++a) { o_vid[a] = pk.add(vid[a]); o_dof[a] = pk.add(dof[a]); }
-    const size_t o_ft = pk.add(far_tiles), o_nt = pk.add(tiles), o_bnd = pk.add(blk_ndof),
+    size_t o_ft = pk.add(far_tiles), o_nt = pk.add(tiles), o_bnd = pk.add(blk_ndof),
                  o_bdofs = pk.add(blk_dofs), o_loc = pk.add(loc), o_v2cp = pk.add(v2c_ptr),
                  o_v2ci = pk.add(v2c_idx), o_vloc = pk.add(vloc), o_n2d = pk.add(h->node2dof),
                  o_dn = pk.add(h->dof_node), o_ep = pk.add(edge_pairs), o_vp = pk.add(vert_pairs),
@@ -631,7 +584,6 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     for (const auto& p : pk.parts)
         if (p.bytes) std::memcpy(h->pin + p.off, p.src, p.bytes);
     if ((rc = ensure_dev(h, &h->plan, &h->plan_cap, pk.total))) return rc;
-    if ((rc = ensure_dev(h, &h->dA, &h->A_cap, A_bytes))) return rc;
     if ((rc = ensure_dev(h, &h->dS, &h->S_cap, sizeof(double) * (size_t)T * 6))) return rc;
     if (!h->dcnt) HIPCHK(hipMalloc((void**)&h->dcnt, sizeof(unsigned long long) * 16));
     HIPCHK(hipMemcpyAsync(h->plan, h->pin, pk.total, hipMemcpyHostToDevice, h->stream));
@@ -653,10 +605,41 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     h->d_v2c_idx = (int*)dv(o_v2ci);
     h->d_node2dof = (int*)dv(o_n2d);
     h->d_dof_node = (int*)dv(o_dn);
+    h->d_vloc = (const unsigned char*)dv(o_vloc);
+    P.o_ft = o_ft; P.o_nt = o_nt; P.o_bnd = o_bnd; P.o_bdofs = o_bdofs; P.o_loc = o_loc;
+    P.o_vloc = o_vloc; P.o_ep = o_ep; P.o_vp = o_vp; P.o_fac = o_fac; P.o_fvid = o_fvid;
+    P.n_tiles = (long long)tiles.size();
+    P.n_far_tiles = (long long)far_tiles.size();
+    P.n_edge = (long long)edge_pairs.size() / 2;
+    P.n_vert = (long long)vert_pairs.size() / 2;
+    P.t_plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return FL_OK;
+}
+
+// One assembly of A^s (Sec. 5 pair decomposition) into A (row-major, lda;
+// a_elems elements zeroed first), optional FP32 copy A32 (same lda).
+// Adds the phase times to *st and fills its pair counts.
+int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double* A, int64_t lda,
+                 long long a_elems, float* A32, fl_stats_t* st) {
+    int rc = FL_OK;
+    const int dim = P.dim;
+    const int64_t T = P.T, nv = P.nv, n = P.n;
+    const int nblk = P.nblk;
+    char* base = h->plan;
+    auto dv = [&](size_t off) { return (void*)(base + off); };
+    const ElemDev E = h->E;
     double* dS = h->dS;
     unsigned long long* dcnt = h->dcnt;
+    const size_t o_ft = P.o_ft, o_nt = P.o_nt, o_bnd = P.o_bnd, o_bdofs = P.o_bdofs, o_loc = P.o_loc,
+                 o_vloc = P.o_vloc, o_ep = P.o_ep, o_vp = P.o_vp, o_fac = P.o_fac, o_fvid = P.o_fvid;
+    (void)nblk;
+    (void)rc;
+    // quadrature tables: cached base rules + the two s-dependent radial rules
+    RuleTables R = base_rules();
+    if (s < 0.5) gauss_jacobi01(2, 0.0, -2.0 * s, R.r0_x, R.r0_w);
+    gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
     HIPCHK(upload_rules(R, h->stream));
-    launch_zero(h->dA, n * lda, h->stream);
+    launch_zero(A, a_elems, h->stream);
     launch_zero(dS, T * 6, h->stream);
     launch_zero((double*)dcnt, 16, h->stream);
 
@@ -681,11 +664,11 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     }
     FP.nblk = nblk;
     FP.tiles = (const int2*)dv(o_nt);
-    FP.ntiles = (long long)tiles.size();
+    FP.ntiles = P.n_tiles;
     FP.blk_ndof = (const int*)dv(o_bnd);
     FP.blk_dofs = (const int*)dv(o_bdofs);
     FP.loc = (const unsigned char*)dv(o_loc);
-    FP.A = h->dA;
+    FP.A = A;
     FP.lda = lda;
     FP.S = dS;
     FP.cls_count = dcnt;
@@ -695,7 +678,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     {
         FarParams FF = FP;
         FF.tiles = (const int2*)dv(o_ft);
-        FF.ntiles = (long long)far_tiles.size();
+        FF.ntiles = P.n_far_tiles;
         launch_far_tiles(E, FF, o.k_far[o.n_classes], h->stream);
         HIPCHK(hipGetLastError());
     }
@@ -728,26 +711,25 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     TP.pe = pe;
     TP.C = C;
     TP.k = o.k_touch;
-    TP.A = h->dA;
+    TP.A = A;
     TP.lda = lda;
     if (dim == 2) {
-        TP.npairs = (long long)edge_pairs.size() / 2;
+        TP.npairs = P.n_edge;
         TP.pairs = (const int*)dv(o_ep);
         launch_touch_edge2(E, TP, h->stream);
         HIPCHK(hipGetLastError());
     }
-    TP.npairs = (long long)vert_pairs.size() / 2;
+    TP.npairs = P.n_vert;
     TP.pairs = (const int*)dv(o_vp);
     launch_touch_vert(E, TP, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
     launch_scatter_self(E, h->d_v2c_ptr, h->d_v2c_idx, h->d_node2dof, (const unsigned char*)dv(o_vloc),
-                        (int)nv, dim, dS, h->dA, lda, h->stream);
+                        (int)nv, dim, dS, A, lda, h->stream);
     HIPCHK(hipGetLastError());
-    if (o.precision == FL_MIXED) {
-        if ((rc = ensure_dev(h, &h->dA32, &h->A32_cap, sizeof(float) * (size_t)n * (size_t)lda + 16))) return rc;
-        launch_to_f32(h->dA, lda, n, h->dA32, h->stream);
+    if (A32) {
+        launch_to_f32(A, lda, n, A32, h->stream);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipEventRecord(ev[4], h->stream));
@@ -760,19 +742,14 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ph[i], ev[i], ev[i + 1]));
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
 
-    h->s = s;
-    h->opts = o;
-    h->n = n;
-    h->lda = lda;
-    h->assembled = true;
-    fl_stats_t& S = h->st;
+    fl_stats_t& S = *st;
     S.n = n;
     S.n_cells = T;
     S.n_verts = nv;
     S.n_bfacets = h->nb;
     S.pairs_identical = T;
-    S.pairs_edge = (int64_t)edge_pairs.size() / 2;
-    S.pairs_vertex = (int64_t)vert_pairs.size() / 2;
+    S.pairs_edge = P.n_edge;
+    S.pairs_vertex = P.n_vert;
     for (int m = 0; m <= FL_MAX_CLASSES; ++m) S.pairs_far[m] = m <= o.n_classes ? (int64_t)cnt[m] : 0;
     S.pairs_bnd_touch = (int64_t)cnt[10];
     S.pairs_bnd_far = (int64_t)cnt[11];
@@ -792,19 +769,131 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
         }
         S.kernel_evals = ev2;
     }
-    S.t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    S.t_assemble_ms = ms;
-    S.t_far_ms = ph[0];
-    S.t_self_ms = ph[1];
-    S.t_touch_ms = ph[2];
-    S.t_scatter_ms = ph[3];
+    S.t_plan_ms = P.t_plan_ms;
+    S.t_assemble_ms += ms;
+    S.t_far_ms += ph[0];
+    S.t_self_ms += ph[1];
+    S.t_touch_ms += ph[2];
+    S.t_scatter_ms += ph[3];
+    return FL_OK;
+}
+
+
+int check_s_opts(fl_handle* h, double s, const fl_opts* opts_in, fl_opts* o) {
+    if (!(s > 0.0 && s < 1.0)) return fail(h, FL_EINVAL, "s must lie in (0,1)");
+    if (opts_in) *o = *opts_in;
+    else fl_default_opts(o);
+    return check_opts(h, *o);
+}
+
+bool fits(fl_handle* h, double bytes) {
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) != hipSuccess) return false;
+    return bytes + (double)h->nc * 512.0 <= (double)freeb * 0.98;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    fl_opts o;
+    int rc = check_s_opts(h, s, opts_in, &o);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(h->device));
+    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
+    reset_assembly(h);
+    // DOF map (Sec. 3): all nodes if s < 1/2 (paper rule), else interior
+    const bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s < 0.5);
+    int64_t n = 0;
+    for (int64_t v = 0; v < h->nv; ++v) n += (all_nodes || !h->on_boundary[v]) ? 1 : 0;
+    const int64_t lda = ((n + 31) / 32) * 32;
+    const size_t A_bytes = sizeof(double) * (size_t)n * (size_t)lda + 8;
+    if (A_bytes > h->A_cap) {
+        if (h->dA) (void)hipFree(h->dA);
+        h->dA = nullptr;
+        h->A_cap = 0;
+        if (!fits(h, (double)A_bytes))
+            return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
+    }
+    Plan P;
+    if ((rc = plan_assembly(h, all_nodes, o, P))) return rc;
+    if ((rc = ensure_dev(h, &h->dA, &h->A_cap, A_bytes))) return rc;
+    float* A32 = nullptr;
+    if (o.precision == FL_MIXED) {
+        if ((rc = ensure_dev(h, &h->dA32, &h->A32_cap, sizeof(float) * (size_t)n * (size_t)lda + 16))) return rc;
+        A32 = h->dA32;
+    }
+    fl_stats_t S{};
+    if ((rc = run_assembly(h, P, s, o, h->dA, lda, (long long)n * lda, A32, &S))) return rc;
+    h->st = S;
+    h->s = s;
+    h->opts = o;
+    h->n = n;
+    h->lda = lda;
+    h->assembled = true;
+    h->planned = true;
+    if (n_out) *n_out = n;
+    return FL_OK;
+}
+
+int fl_assemble_batch(fl_handle* h, const double* s, int ns, const fl_opts* opts_in, int64_t* n_out) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    if (!s || ns < 1 || ns > FL_MAX_BATCH) return fail(h, FL_EINVAL, "need 1 <= ns <= FL_MAX_BATCH values of s");
+    fl_opts o;
+    int rc = FL_OK;
+    for (int j = 0; j < ns; ++j)
+        if ((rc = check_s_opts(h, s[j], opts_in, &o))) return rc;
+    bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s[0] < 0.5);
+    for (int j = 1; j < ns; ++j)
+        if (((o.dof_mode == FL_DOF_PAPER) && (s[j] < 0.5)) != all_nodes)
+            return fail(h, FL_EINVAL, "the s values give different DOF sets; use FL_DOF_INTERIOR");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
+    reset_assembly(h);
+    fl_batch& B = h->B;
+    B.ns = 0;
+    B.have32 = B.havehi = B.havelo = false;
+    int64_t n = 0;
+    for (int64_t v = 0; v < h->nv; ++v) n += (all_nodes || !h->on_boundary[v]) ? 1 : 0;
+    const int64_t n_pad = std::max<int64_t>(256, ((n + 255) / 256) * 256);
+    const size_t bytes = sizeof(double) * (size_t)ns * (size_t)n_pad * (size_t)n_pad;
+    if (bytes > B.A64_cap) {
+        if (B.A64) (void)hipFree(B.A64);
+        B.A64 = nullptr;
+        B.A64_cap = 0;
+        if (!fits(h, (double)bytes))
+            return fail(h, FL_ENOMEM, "batch of " + std::to_string(ns) + " matrices does not fit in device memory");
+    }
+    Plan P;
+    if ((rc = plan_assembly(h, all_nodes, o, P))) return rc;
+    if ((rc = ensure_dev(h, &B.A64, &B.A64_cap, bytes))) return rc;
+    fl_stats_t S{};
+    for (int j = 0; j < ns; ++j) {
+        double* Aj = B.A64 + (size_t)j * n_pad * n_pad;
+        if ((rc = run_assembly(h, P, s[j], o, Aj, n_pad, (long long)n_pad * n_pad, nullptr, &S))) return rc;
+        B.s[j] = s[j];
+    }
+    B.ns = ns;
+    B.n = n;
+    B.n_pad = n_pad;
+    B.ld = n_pad;
+    for (int d = 0; d < 4; ++d) B.best[d] = -1;
+    h->st = S;
+    h->opts = o;
+    h->s = s[0];
+    h->n = n;
+    h->planned = true;
     if (n_out) *n_out = n;
     return FL_OK;
 }
 
 int fl_dofs(const fl_handle* h, int32_t* node_of_dof) {
     if (!h) return FL_EINVAL;
-    if (!h->assembled) return FL_ESTATE;
+    if (!h->planned) return FL_ESTATE;
     if (h->n == 0) return FL_OK;
     if (!node_of_dof) return FL_EINVAL;
     std::memcpy(node_of_dof, h->dof_node.data(), sizeof(int32_t) * h->n);
@@ -826,9 +915,23 @@ int fl_export_matrix(fl_handle* h, double* dst, int64_t ld, int on_device) {
     return FL_OK;
 }
 
+int fl_import_matrix(fl_handle* h, const double* src, int64_t ld, int on_device) {
+    if (!h) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix to replace");
+    if (h->n == 0) return FL_OK;
+    if (!src) return fail(h, FL_EINVAL, "null source");
+    if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipMemcpy2DAsync(h->dA, h->lda * sizeof(double), src, ld * sizeof(double), h->n * sizeof(double),
+                            h->n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+    if (h->opts.precision == FL_MIXED && h->dA32) launch_to_f32(h->dA, h->lda, h->n, h->dA32, h->stream);
+    if (!on_device) HIPCHK(hipStreamSynchronize(h->stream));
+    return FL_OK;
+}
+
 int fl_load_vector_one(fl_handle* h, double* b) {
     if (!h) return FL_EINVAL;
-    if (!h->assembled) return fail(h, FL_ESTATE, "no assembly");
+    if (!h->planned) return fail(h, FL_ESTATE, "no assembly");
     if (h->n == 0) return FL_OK;
     if (!b) return fail(h, FL_EINVAL, "null vector");
     HIPCHK(hipSetDevice(h->device));

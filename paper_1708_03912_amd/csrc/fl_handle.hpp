@@ -1,0 +1,85 @@
+// Private definition of the library handle (shared by the host units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "fl_internal.hpp"
+
+// Matrices of one fl_assemble_batch call and the buffers of the batched
+// products / solves.
+struct fl_batch {
+    int ns = 0;
+    double s[FL_MAX_BATCH] = {};
+    int64_t n = 0, n_pad = 0, ld = 0;       // FP64 and low-precision planes share ld = n_pad
+    double* A64 = nullptr;                  // ns x n_pad x ld
+    size_t A64_cap = 0;
+    float* A32 = nullptr;
+    size_t A32_cap = 0;
+    void* Ahi = nullptr;                    // bf16 planes
+    size_t Ahi_cap = 0;
+    void* Alo = nullptr;
+    size_t Alo_cap = 0;
+    bool have32 = false, havehi = false, havelo = false;
+    int best[4] = {-1, -1, -1, -1};         // tuned GEMM entry per element type
+    char* ws = nullptr;                     // solver / product workspace
+    size_t ws_cap = 0;
+    int* hflag = nullptr;                   // pinned host word (active count)
+};
+
+struct fl_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // mesh (host copy)
+    int dim = 0;
+    int64_t nv = 0, nc = 0, nb = 0;
+    std::vector<double> verts;
+    std::vector<int32_t> cells, bfacets;
+    std::vector<int32_t> facet_opp;     // vertex of the owning cell opposite the facet
+    std::vector<char> on_boundary;
+
+    // assembly
+    bool assembled = false;   // single matrix (fl_assemble) present
+    bool planned = false;     // DOF map and device geometry present
+    double s = 0.0;
+    fl_opts opts{};
+    int64_t n = 0, lda = 0;
+    std::vector<int32_t> dof_node, node2dof;
+
+    // device / pinned buffers, grown on demand and reused
+    char* plan = nullptr;
+    size_t plan_cap = 0;
+    char* pin = nullptr;
+    size_t pin_cap = 0;
+    double* dA = nullptr;
+    size_t A_cap = 0;
+    double* dS = nullptr;
+    size_t S_cap = 0;
+    float* dA32 = nullptr;
+    size_t A32_cap = 0;
+    unsigned long long* dcnt = nullptr;
+
+    // views into the plan buffer used after assembly
+    fl::ElemDev E{};
+    int* d_v2c_ptr = nullptr;
+    int* d_v2c_idx = nullptr;
+    int* d_node2dof = nullptr;
+    int* d_dof_node = nullptr;
+    const unsigned char* d_vloc = nullptr;  // local index of the vertex in each v2c entry
+    double* d_meas = nullptr;
+
+    // solver workspace
+    double* w = nullptr;   // r, z, p (2n), q, d, tmp (7 n)
+    float* w32 = nullptr;  // FP32 refinement workspace (8 n)
+    double* w_part = nullptr;
+    double* w_scal = nullptr;
+    int* w_flag = nullptr;
+    int64_t w_n = -1;
+
+    fl_stats_t st{};
+    fl_batch B;
+};

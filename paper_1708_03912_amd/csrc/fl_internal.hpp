@@ -169,4 +169,114 @@ void launch_add_correction(double* u, const float* e, long long n, hipStream_t s
 void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
                  int nblk, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------- batch --
+// Element types of the batched GEMM (fl_batch.hip).
+enum { GD_F64 = 0, GD_F32 = 1, GD_BF16 = 2 };
+
+struct GemmArgs {
+    int ns;                 // systems in the batch
+    long long n_pad;        // rows = K extent; multiple of 256
+    const void* A;          // plane 0: ns blocks of n_pad x lda (row-major), block stride sA
+    const void* A2;         // bf16 low plane (two-plane variants)
+    long long lda, sA;
+    const void* X;          // plane 0 of X: ns blocks of 64 columns x n_pad (column-major)
+    const void* X2;         // bf16 low plane of X
+    long long sX;           // elements between systems (64 n_pad)
+    void* Y;                // accumulator type (double for GD_F64, else float), layout of X
+    const void* V;          // epilogue vector, accumulator type, layout of X
+    double* part;           // ns x nrb x 64 epilogue partial sums
+    const int* act;         // ns x 64 activity (null: every system)
+    int epi;                // 0: Y = A X; 1: also part = sum V.Y; 2: Y = V - A X, part = sum Y.Y
+};
+
+struct GemmInfo {
+    int dt, npa, wm, waves, bk, bm;
+};
+int gemm_count();
+GemmInfo gemm_info(int id);
+hipError_t launch_gemm(int id, const GemmArgs& g, hipStream_t st);
+
+void launch_mat_lo(const double* A, long long ld64, long long n, long long n_pad, long long ldl, int dt,
+                   int npa, void* P0, void* P1, hipStream_t st);
+void launch_bdiag(const double* A, long long lda, long long sA, long long n, long long n_pad, int ns,
+                  double* dinv64, float* dinv32, hipStream_t st);
+void launch_pack_f64(const double* src, long long ld, long long sstride, long long n, int nrhs,
+                     long long n_pad, int ns, double* dst, hipStream_t st);
+void launch_pack_f32(const float* src, long long ld, long long sstride, long long n, int nrhs,
+                     long long n_pad, int ns, float* dst, hipStream_t st);
+void launch_unpack_f64(const double* src, long long n_pad, long long n, int nrhs, int ns, double* dst,
+                       long long ld, long long dstride, hipStream_t st);
+void launch_unpack_f32(const float* src, long long n_pad, long long n, int nrhs, int ns, float* dst,
+                       long long ld, long long dstride, hipStream_t st);
+void launch_split_bf16(const float* x, long long m, void* hi, void* lo, hipStream_t st);
+void launch_fill_f64(double* x, long long m, hipStream_t st);
+void launch_fill_f32(float* x, long long m, hipStream_t st);
+
+// Batched Jacobi-PCG state; vectors in the padded batch layout, per-system
+// scalars indexed j * 64 + c.
+template <class T>
+struct BcgState {
+    long long n_pad;
+    T* x;
+    T* r;
+    T* p;
+    T* q;                   // GEMM output A p
+    void* ph;               // bf16 hi / lo planes of p (null: not needed)
+    void* pl;
+    const T* b;
+    const T* dinv;          // ns x n_pad reciprocal diagonal (0 in padding)
+    const int* want;        // columns that take part
+    int* act;
+    int* iters;
+    int* status;            // 0 ok, 1 breakdown (p.Ap <= 0), 2 non-finite
+    double* rz;
+    double* bb;
+    double* rel;            // ||r|| / ||b|| of the last iterate
+    const double* partq;    // GEMM epilogue partials of p.q
+    int nrbq;
+    double rtol2;
+    int maxit;
+};
+template <class T>
+void launch_bcg_init(const BcgState<T>& S, int ns, hipStream_t st);
+template <class T>
+void launch_bcg_step(const BcgState<T>& S, int ns, hipStream_t st);
+void launch_count(const int* act, int m, int* out, hipStream_t st);
+
+struct RefineState {
+    long long n_pad;
+    const double* b64;
+    double* u64;
+    const double* r64;      // residual GEMM output
+    float* r32;             // inner right-hand side
+    const double* part;     // residual GEMM partials |r|^2
+    int nrb;
+    double* bb;
+    int* oact;              // outer activity
+    int* want;              // inner participation
+    int* status;
+    double* rel;
+    double rtol2;
+};
+void launch_refine_init(const RefineState& R, int ns, int nrhs, hipStream_t st);
+void launch_refine_check(const RefineState& R, int ns, hipStream_t st);
+void launch_add_corr(double* u, const float* e, long long m, hipStream_t st);
+
+struct LoadArgs {
+    ElemDev E;
+    int dim;
+    long long n, nv;
+    const int* dof_node;
+    const int* v2c_ptr;
+    const int* v2c_idx;
+    const unsigned char* vloc;
+    const double* meas;
+    int nq;
+    const double* q;        // nq x 4: l1 (1D: t), l2, w
+    const double* coef;     // FOURIER: nrhs x 16; NODAL: nv x nrhs (column-major)
+    int nrhs;
+    double* b;              // n x nrhs column-major
+};
+void launch_load(const LoadArgs& a, int kind, hipStream_t st);
+
 }  // namespace fl

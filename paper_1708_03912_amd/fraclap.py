@@ -19,7 +19,11 @@ FL_OK, FL_EINVAL, FL_EMESH, FL_ENOMEM, FL_EDEVICE = 0, -1, -2, -3, -4
 FL_ESTATE, FL_ENONFINITE, FL_EBREAKDOWN, FL_ENOCONV = -5, -6, -7, 1
 FL_DOF_PAPER, FL_DOF_INTERIOR = 0, 1
 FL_FP64, FL_MIXED = 0, 1
+FL_F64, FL_F32, FL_BF16, FL_BF16X2 = 0, 1, 2, 3
+FL_RHS_ONE, FL_RHS_FOURIER16, FL_RHS_P1_NODAL = 0, 1, 2
+FL_MAX_BATCH = 16
 FL_MAX_CLASSES = 8
+DTYPES = {"f64": FL_F64, "f32": FL_F32, "bf16": FL_BF16, "bf16x2": FL_BF16X2}
 
 ERROR_NAMES = {0: "FL_OK", -1: "FL_EINVAL", -2: "FL_EMESH", -3: "FL_ENOMEM", -4: "FL_EDEVICE",
                -5: "FL_ESTATE", -6: "FL_ENONFINITE", -7: "FL_EBREAKDOWN", 1: "FL_ENOCONV"}
@@ -27,7 +31,9 @@ ERROR_NAMES = {0: "FL_OK", -1: "FL_EINVAL", -2: "FL_EMESH", -3: "FL_ENOMEM", -4:
 # every symbol include/fraclap.h declares
 EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_set_mesh",
            "fl_assemble", "fl_matrix_ld", "fl_matrix_ptr", "fl_dofs", "fl_export_matrix",
-           "fl_load_vector_one", "fl_matvec", "fl_solve", "fl_energy_error2", "fl_stats"]
+           "fl_load_vector_one", "fl_matvec", "fl_solve", "fl_energy_error2", "fl_stats",
+           "fl_import_matrix", "fl_load_vector", "fl_assemble_batch", "fl_export_batch_matrix",
+           "fl_matmul", "fl_solve_batch", "fl_autotune"]
 
 
 class FlOpts(C.Structure):
@@ -48,6 +54,11 @@ class FlStats(C.Structure):
                 ("t_assemble_ms", C.c_double), ("t_far_ms", C.c_double), ("t_self_ms", C.c_double),
                 ("t_touch_ms", C.c_double), ("t_scatter_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("last_iters", C.c_int32), ("last_relres", C.c_double), ("last_outer", C.c_int32)]
+
+
+class FlTuneEntry(C.Structure):
+    _fields_ = [("wm", C.c_int), ("waves", C.c_int), ("bk", C.c_int), ("planes", C.c_int),
+                ("ms", C.c_double), ("tflops", C.c_double), ("gbps", C.c_double)]
 
 
 class FraclapError(RuntimeError):
@@ -86,6 +97,14 @@ def lib():
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_energy_error2.argtypes = [vp, dp, vp, vp, C.POINTER(dp)]
         L.fl_stats.argtypes = [vp, C.POINTER(FlStats)]
+        L.fl_import_matrix.argtypes = [vp, vp, i64, C.c_int]
+        L.fl_load_vector.argtypes = [vp, C.c_int, vp, i64, vp]
+        L.fl_assemble_batch.argtypes = [vp, vp, C.c_int, C.POINTER(FlOpts), C.POINTER(i64)]
+        L.fl_export_batch_matrix.argtypes = [vp, C.c_int, vp, i64, C.c_int]
+        L.fl_matmul.argtypes = [vp, C.c_int, C.c_int, vp, i64, vp, i64, i64]
+        L.fl_solve_batch.argtypes = [vp, vp, i64, i64, vp, i64, i64, i64, dp, C.c_int32, C.c_int, vp, vp]
+        L.fl_autotune.argtypes = [vp, C.c_int, C.POINTER(FlTuneEntry), C.c_int, C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -221,6 +240,68 @@ class Handle:
         st = FlStats()
         self._check(lib().fl_stats(self.h, C.byref(st)))
         return st
+
+    def import_matrix(self, A):
+        """A: host numpy (n x n) or device torch tensor (n x n, row stride)."""
+        if isinstance(A, np.ndarray):
+            a = np.ascontiguousarray(A, dtype=np.float64)
+            self._check(lib().fl_import_matrix(self.h, a.ctypes.data_as(C.c_void_p), a.shape[1], 0))
+        else:
+            self._check(lib().fl_import_matrix(self.h, _ptr(A), A.stride(0), 1))
+
+    # ---- many right-hand sides / several s ----
+    def load_vector(self, kind, b, coeffs=None):
+        """b: device tensor (nrhs, n) float64 (= column-major n x nrhs).
+        kind: "one" | "fourier16" (coeffs (nrhs, 16)) | "nodal" (coeffs (nrhs, nv))."""
+        k = {"one": FL_RHS_ONE, "fourier16": FL_RHS_FOURIER16, "nodal": FL_RHS_P1_NODAL}.get(kind, kind)
+        nrhs = b.shape[0] if b.dim() == 2 else 1
+        cp = None
+        if coeffs is not None:
+            c = np.ascontiguousarray(coeffs, dtype=np.float64)
+            cp = c.ctypes.data_as(C.c_void_p)
+        self._check(lib().fl_load_vector(self.h, k, cp, nrhs, _ptr(b)))
+
+    def assemble_batch(self, svals, opts: FlOpts | None = None) -> int:
+        sv = np.ascontiguousarray(svals, dtype=np.float64)
+        n = C.c_int64()
+        self._check(lib().fl_assemble_batch(self.h, sv.ctypes.data_as(C.c_void_p), sv.size,
+                                            None if opts is None else C.byref(opts), C.byref(n)))
+        self.n = n.value
+        self.ns = sv.size
+        return self.n
+
+    def export_batch_matrix(self, j) -> np.ndarray:
+        out = np.zeros((self.n, self.n), dtype=np.float64)
+        self._check(lib().fl_export_batch_matrix(self.h, j, out.ctypes.data_as(C.c_void_p), self.n, 0))
+        return out
+
+    def matmul(self, X, Y, dtype="f64", s_index=-1):
+        """X, Y: device tensors (ns, nrhs, n) for s_index = -1, else (nrhs, n)
+        (each row a column of the column-major operand)."""
+        dt = DTYPES.get(dtype, dtype)
+        nrhs = X.shape[-2]
+        self._check(lib().fl_matmul(self.h, s_index, dt, _ptr(X), X.stride(-2), _ptr(Y), Y.stride(-2), nrhs))
+
+    def solve_batch(self, Bt, U, rtol=1e-12, maxit=20000, inner="f64"):
+        """Bt: device (ns, nrhs, n) or (nrhs, n) shared by every s; U: (ns, nrhs, n).
+        Returns (iters (ns, nrhs), relres (ns, nrhs), rc)."""
+        ns, nrhs = U.shape[0], U.shape[1]
+        sb = Bt.stride(0) if Bt.dim() == 3 else 0
+        it = np.zeros(ns * nrhs, dtype=np.int32)
+        rel = np.zeros(ns * nrhs, dtype=np.float64)
+        rc = self._check(lib().fl_solve_batch(self.h, _ptr(Bt), Bt.stride(-2), sb, _ptr(U), U.stride(-2),
+                                              U.stride(0), nrhs, rtol, maxit, DTYPES.get(inner, inner),
+                                              it.ctypes.data_as(C.c_void_p), rel.ctypes.data_as(C.c_void_p)),
+                         allow=(FL_OK, FL_ENOCONV))
+        return it.reshape(ns, nrhs), rel.reshape(ns, nrhs), rc
+
+    def autotune(self, dtype="f64"):
+        out = (FlTuneEntry * 64)()
+        cnt, best = C.c_int(), C.c_int()
+        self._check(lib().fl_autotune(self.h, DTYPES.get(dtype, dtype), out, 64, C.byref(cnt), C.byref(best)))
+        rows = [dict(wm=e.wm, waves=e.waves, bk=e.bk, planes=e.planes, ms=e.ms, tflops=e.tflops, gbps=e.gbps)
+                for e in out[:cnt.value]]
+        return rows, best.value
 
 
 def _device_view(torch, ptr, n, ld, device):

@@ -35,7 +35,7 @@ def test_default_opts_table():
 
 
 def test_struct_layouts_match_header(tmp_path):
-    """ctypes mirrors of fl_opts / fl_stats_t agree with the C compiler."""
+    """ctypes mirrors of fl_opts / fl_stats_t / fl_tune_entry agree with the C compiler."""
     import ctypes as C
     import subprocess
     src = tmp_path / "lay.c"
@@ -44,15 +44,17 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "fraclap.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
-         offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
+         offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres),
+         sizeof(fl_tune_entry), offsetof(fl_tune_entry, gbps));
   return 0; }
 """)
     exe = tmp_path / "lay"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [C.sizeof(F.FlOpts), F.FlOpts.theta.offset, F.FlOpts.k_far_bnd.offset,
-                    C.sizeof(F.FlStats), F.FlStats.last_relres.offset]
+                    C.sizeof(F.FlStats), F.FlStats.last_relres.offset,
+                    C.sizeof(F.FlTuneEntry), F.FlTuneEntry.gbps.offset]
 
 
 def test_no_cpu_fallback_in_binding():
