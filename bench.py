@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cells", type=int, default=8000, help="target triangle count of the disk mesh")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched leg (disk ~16k DOFs, 8 values of s, 64 right-hand sides)")
+    ap.add_argument("--batch-cells", type=int, default=32000)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -207,6 +210,8 @@ def main():
            "roofline": roof, "roofline_other": other}
 
     out["mixed"] = mixed_leg(args, mesh, svals, handles, bufs, ball_fu, pairs_per_step)
+    if not args.no_batch:
+        out["batch"] = batch_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -265,6 +270,89 @@ def mixed_leg(args, mesh, svals, handles64, bufs64, ball_fu, pairs_per_step):
     return out
 
 
+def batch_leg(args):
+    """Many right-hand sides and several s (unit disk, ~32k triangles, ~16k
+    interior DOFs; s = linspace(0.1, 0.9, 8); 64 right-hand sides f =
+    sum of 16 cosine modes with N(0,1) coefficients, seeds 1000..1063).
+    One step: batched FP64 assembly of the 8 matrices, then the batched
+    Jacobi-PCG to ||r|| <= 1e-10 ||b|| for all 512 systems, plain FP64 and
+    FP64 refinement around an FP32-arithmetic inner CG on FP32 / bf16 hi+lo /
+    bf16 matrix storage.  The gap of each low-precision solution to the FP64
+    one is measured in the FP64 energy norm."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    mesh = M.disk_for_cells(args.batch_cells, seed=2)
+    T, Bf = len(mesh["cells"]), len(mesh["bfacets"])
+    svals = np.linspace(0.1, 0.9, 8)
+    ns = len(svals)
+    nrhs = 64
+    coef = np.stack([np.random.default_rng(1000 + m).standard_normal(16) for m in range(nrhs)])
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    opts = F.make_opts(dof_mode="interior")
+    n = h.assemble_batch(svals, opts)
+    tune = {}
+    for dt in ("f64", "f32", "bf16x2", "bf16"):
+        rows, best = h.autotune(dt)
+        tune[dt] = dict(best=rows[best], configs=len(rows))
+    b = torch.zeros(nrhs, n, dtype=torch.float64, device="cuda")
+    h.load_vector("fourier16", b, coef)
+    inners = ("f64", "f32", "bf16x2", "bf16")
+    U = {k: torch.zeros(ns, nrhs, n, dtype=torch.float64, device="cuda") for k in inners}
+    rtol = 1e-10
+    res = {}
+    steps = max(1, min(args.steps, 2))
+    for rep in range(steps + 1):           # first pass untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.assemble_batch(svals, opts)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        st = h.stats()
+        res["assemble_ms"] = t_asm
+        res["assemble_device_ms"] = st.t_assemble_ms
+        res["far_ms"] = st.t_far_ms
+        h.load_vector("fourier16", b, coef)
+        for k in inners:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, rel, rc = h.solve_batch(b, U[k], rtol=rtol, maxit=20000, inner=k)
+            torch.cuda.synchronize()
+            res[k] = dict(ms=(time.perf_counter() - t0) * 1e3, rc=rc, iters=it, rel=rel,
+                          outer=h.stats().last_outer)
+    # energy-norm gaps to the FP64 solutions (FP64 matrices)
+    Y = torch.empty_like(U["f64"])
+    h.matmul(U["f64"], Y, "f64")
+    norm2 = (U["f64"] * Y).sum(dim=2)
+    gaps = {}
+    for k in inners[1:]:
+        D = U[k] - U["f64"]
+        h.matmul(D, Y, "f64")
+        g2 = (D * Y).sum(dim=2).clamp(min=0)
+        gaps[k] = float((g2 / norm2).sqrt().max())
+    pairs = ns * (T * (T + 1) // 2 + T * Bf)
+    out = {"workload": f"d=2 unit disk T={T} B={Bf} n={n} (interior DOFs), s=linspace(0.1,0.9,8), "
+                       f"64 right-hand sides (16 cosine modes, N(0,1) coefficients), CG to 1e-10",
+           "cells": T, "n": n, "ns": ns, "nrhs": nrhs,
+           "assemble_ms": round(res["assemble_ms"], 2), "assemble_device_ms": round(res["assemble_device_ms"], 2),
+           "far_ms": round(res["far_ms"], 2),
+           "assembly_pairs_per_s": round(pairs / (res["assemble_ms"] * 1e-3), 1),
+           "gemm_tuned": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v["best"].items()}
+                          for k, v in tune.items()}}
+    for k in inners:
+        r = res[k]
+        it = r["iters"]
+        out["solve_" + k] = {"ms": round(r["ms"], 2), "converged": bool(np.all(r["rel"] <= rtol)),
+                             "iters_mean_per_s": [round(float(x), 1) for x in it.mean(axis=1)],
+                             "iters_max": int(it.max()), "refinements": r["outer"],
+                             "max_relres": float(r["rel"].max())}
+        if k != "f64":
+            out["solve_" + k]["energy_gap_rel_max"] = gaps[k]
+    h.close()
+    return out
+
+
 def cpu_baseline(mesh, svals, pairs_per_step):
     """The oracle as it stands (plain C + numpy, FP64) on the host cores,
     timed on one full step of the same workload."""
@@ -275,7 +363,8 @@ def cpu_baseline(mesh, svals, pairs_per_step):
     O.lib()
     t0 = time.perf_counter()
     for s in svals:
-        A, dofs, _ = O.assemble(mesh, s, O.Orders())
+        A, dofs, _ = O.assemble(mesh, s, O.Orders(k_touch=6, k_touch_bnd=6, theta=[1.5, 3.0, 6.0],
+                                                  k_far=[4, 3, 2, 2], k_far_bnd=[4, 3, 2, 2]))
         b = O.load_vector_one(mesh, dofs)
         u, it, rel = O.pcg(A, b, rtol=1e-12)
         O.energy_error(O.ball_fu(2, s), b, u, A)
