@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (disk ~16k DOFs, 8 values of s, 64 right-hand sides)")
     ap.add_argument("--batch-cells", type=int, default=32000)
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the batched leg and print its object (profiling)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -87,6 +89,11 @@ def main():
         sys.exit(2)
     if args.copy_calib:
         copy_calib(args.copy_calib)
+        return
+    if args.only_batch:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"batch": batch_leg(args)}), flush=True)
         return
     import numpy as np
     import torch

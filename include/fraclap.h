@@ -125,7 +125,8 @@ typedef struct {
     int32_t last_iters;       /* iterations of the last solve (mixed: inner
                                  FP32 iterations summed over refinements)  */
     double last_relres;
-    int32_t last_outer;       /* FP64 refinement steps of the last solve    */
+    int32_t last_outer;       /* FP64 refinement steps of the last solve
+                                 (fl_solve_batch: residual replacements)   */
 } fl_stats_t;
 
 /* Default orders (the calibrated table: k_touch = k_touch_bnd = 6,
@@ -261,14 +262,18 @@ int fl_matmul(fl_handle *h, int s_index, int dtype, const void *X, int64_t ldx, 
  * B + j * strideB (strideB = 0: the same right-hand sides for every j);
  * U likewise (ldu, strideU > 0 unless ns = 1), overwritten.
  *   inner = FL_F64   plain FP64 batched CG on the FP64 matrices;
- *   inner = FL_F32 / FL_BF16 / FL_BF16X2   FP64 iterative refinement: the
- *           residual b - A u is formed with the FP64 matrix, each
- *           correction comes from the batched CG in FP32 arithmetic on the
- *           matrix in that storage, to a relative residual of 1e-4 (1e-2
- *           for FL_BF16); maxit bounds each column's inner iterations.
+ *   inner = FL_F32 / FL_BF16 / FL_BF16X2   mixed-precision CG with
+ *           reliable updates: the CG recurrence runs in FP32 arithmetic with
+ *           the matrix in that storage and the solution accumulates in FP64;
+ *           when a column's residual has fallen 10x since the last
+ *           replacement, or it claims convergence, it pauses, u += x is
+ *           formed in FP64 and the residual is replaced by the FP64 residual
+ *           b - A u (FP64 matrix); the column resumes with its search
+ *           direction and an exact line search for that step, and stops
+ *           only when the FP64 residual meets rtol (or at maxit).
  * Converged columns drop out of the products.  iters / relres: host
- * arrays of ns x nrhs (index j * nrhs + c; may be NULL): CG iterations
- * (refinement: inner iterations summed) and the final relative residual.
+ * arrays of ns x nrhs (index j * nrhs + c; may be NULL): CG iterations and
+ * the final relative residual (mixed precision: of the FP64 residual).
  * Returns FL_ENOCONV if a column did not converge, FL_EBREAKDOWN if p.Ap
  * <= 0 occurred, FL_ENONFINITE for non-finite data.  Synchronises the
  * stream. */

@@ -115,14 +115,19 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_kernel(GemmArgs g) {
     __shared__ __align__(16) char lds[2][NPX * PLANEB];
     __shared__ double red[WAVES][64];
 
+    // work item w = (tile, split); tiles = (active system, row block); a
+    // contiguous range of work items per XCD (workgroups are dealt to the
+    // XCDs round-robin)
     const long long nrb = g.n_pad / BM;
-    const long long ntiles = nrb * g.ns;
-    const long long per = (ntiles + 7) / 8;
+    const long long nwork = (long long)g.nsys * nrb * g.ksplit;
+    const long long per = (nwork + 7) / 8;
     const long long L = blockIdx.x;
-    const long long tile = (L & 7) * per + (L >> 3);
-    if (tile >= ntiles) return;
-    const int j = (int)(tile / nrb);
-    const long long rb = tile - (long long)j * nrb;
+    const long long w = (L & 7) * per + (L >> 3);
+    if (w >= nwork) return;
+    const int split = (int)(w % g.ksplit);
+    const long long t = w / g.ksplit;
+    const int j = g.sys[t / nrb];
+    const long long rb = t % nrb;
     if (g.act) {
         const int a = g.act[j * 64 + (threadIdx.x & 63)];
         if (!__syncthreads_or(a)) return;
@@ -161,11 +166,14 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_kernel(GemmArgs g) {
         }
     };
 
-    const long long nk = g.n_pad / BK;
-    gload(0);
-    lstore(0);
+    const long long nkt = g.n_pad / BK, kchunk = (nkt + g.ksplit - 1) / g.ksplit;
+    const long long kb = split * kchunk, nk = kb + kchunk < nkt ? kb + kchunk : nkt;
+    if (kb < nk) {
+        gload(kb * BK);
+        lstore((int)(kb & 1));
+    }
     __syncthreads();
-    for (long long kc = 0; kc < nk; ++kc) {
+    for (long long kc = kb; kc < nk; ++kc) {
         const int buf = (int)(kc & 1);
         if (kc + 1 < nk) gload((kc + 1) * BK);
         Seg a[NKS][MB][NPA];
@@ -202,7 +210,7 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_kernel(GemmArgs g) {
 
     // epilogue.  Lane (r16, gq) holds column cb*16 + r16 of the 16-row block
     // m; item v is row 4*gq + v (f32 / bf16 MFMA) or row gq + 4*v (f64 MFMA).
-    acc_t* Y = (acc_t*)g.Y + (long long)j * g.sX;
+    acc_t* Y = (acc_t*)g.Y + (long long)split * g.ysplit + (long long)j * g.sX;
     const acc_t* V = (const acc_t*)g.V + (long long)j * g.sX;
     double dsum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -297,8 +305,10 @@ hipError_t launch_gemm(int id, const GemmArgs& g, hipStream_t st) {
     if (id < 0 || id >= gemm_count()) return hipErrorInvalidValue;
     const GemmEntry& e = kGemm[id];
     const long long bm = (long long)e.wm * e.waves;
-    if (g.n_pad % 256 != 0 || g.n_pad % e.bk != 0 || g.ns <= 0) return hipErrorInvalidValue;
-    const long long ntiles = (g.n_pad / bm) * g.ns;
+    if (g.n_pad % 256 != 0 || g.n_pad % e.bk != 0 || g.nsys <= 0 || g.nsys > FL_MAX_BATCH || g.ksplit < 1 ||
+        (g.ksplit > 1 && g.epi != 0))
+        return hipErrorInvalidValue;
+    const long long ntiles = (g.n_pad / bm) * g.nsys * g.ksplit;
     const long long per = (ntiles + 7) / 8;
     hipLaunchKernelGGL(e.fn, dim3((unsigned)(8 * per)), dim3(e.waves * 64), 0, st, g);
     return hipGetLastError();
@@ -497,6 +507,8 @@ __global__ __launch_bounds__(BCG_T) void bcg_init_kernel(BcgState<T> S) {
             S.rz[idx] = 0.0;
             S.bb[idx] = 0.0;
             S.rel[idx] = 0.0;
+            if (S.upd) S.upd[idx] = 0;
+            if (S.lsf) S.lsf[idx] = 0;
         }
         return;
     }
@@ -520,6 +532,11 @@ __global__ __launch_bounds__(BCG_T) void bcg_init_kernel(BcgState<T> S) {
         S.status[idx] = fin ? 0 : 2;
         S.act[idx] = (fin && bb > 0.0 && S.maxit > 0) ? 1 : 0;
         S.rel[idx] = bb > 0.0 ? 1.0 : 0.0;
+        if (S.upd) {
+            S.upd[idx] = 0;
+            S.rupd2[idx] = bb;
+        }
+        if (S.lsf) S.lsf[idx] = 0;
     }
 }
 
@@ -531,11 +548,22 @@ __global__ __launch_bounds__(BCG_T) void bcg_step_kernel(BcgState<T> S) {
     if (!S.act[idx]) return;
     const long long col = ((long long)j * 64 + c) * S.n_pad;
     const T* dinv = S.dinv + (long long)j * S.n_pad;
-    // p.q from the GEMM epilogue partials
+    // p.q from the GEMM epilogue partials, or q = sum of the K-split partial
+    // products and p.q formed here
     double pq = 0.0, dummy = 0.0;
-    for (int rb = threadIdx.x; rb < S.nrbq; rb += BCG_T) pq += S.partq[((long long)j * S.nrbq + rb) * 64 + c];
+    if (S.ksplit == 1) {
+        for (int rb = threadIdx.x; rb < S.nrbq; rb += BCG_T) pq += S.partq[((long long)j * S.nrbq + rb) * 64 + c];
+    } else {
+        for (long long i = threadIdx.x; i < S.n_pad; i += BCG_T) {
+            T qs = S.q[col + i];
+            for (int k = 1; k < S.ksplit; ++k) qs += S.q[k * S.ysplit + col + i];
+            S.q[col + i] = qs;
+            pq += (double)S.p[col + i] * (double)qs;
+        }
+    }
     block_sum2<T>(pq, dummy, sh);
     const double rz_old = S.rz[idx];
+    const double num = (S.lsf && S.lsf[idx]) ? S.pr[idx] : rz_old;
     if (!(pq > 0.0) || !(pq < 1.79e308)) {
         if (threadIdx.x == 0) {
             S.status[idx] = (pq == pq) ? 1 : 2;
@@ -543,7 +571,7 @@ __global__ __launch_bounds__(BCG_T) void bcg_step_kernel(BcgState<T> S) {
         }
         return;
     }
-    const double alpha = rz_old / pq;
+    const double alpha = num / pq;
     const T a = (T)alpha;
     double rz = 0.0, rr = 0.0;
     for (long long i = threadIdx.x; i < S.n_pad; i += BCG_T) {
@@ -559,11 +587,14 @@ __global__ __launch_bounds__(BCG_T) void bcg_step_kernel(BcgState<T> S) {
     const bool fin = rr == rr && rr < 1.79e308;
     const bool conv = rr <= S.rtol2 * bb;
     const bool stop = conv || !fin || it >= S.maxit;
+    // with residual replacement p stays current even at a stop: the
+    // replacement may find the column unconverged and resume it
+    const bool newp = !stop || (S.upd && fin);
     const T beta = (T)(rz_old > 0.0 ? rz / rz_old : 0.0);
     for (long long i = threadIdx.x; i < S.n_pad; i += BCG_T) {
         const T p = S.p[col + i];
         S.x[col + i] += a * p;
-        if (!stop) {
+        if (newp) {
             const T pn = S.r[col + i] * dinv[i] + beta * p;
             S.p[col + i] = pn;
             write_planes(S, col + i, pn);
@@ -575,6 +606,11 @@ __global__ __launch_bounds__(BCG_T) void bcg_step_kernel(BcgState<T> S) {
         S.rel[idx] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         if (!fin) S.status[idx] = 2;
         if (stop) S.act[idx] = 0;
+        if (S.upd && fin && (stop || rr < S.delta2 * S.rupd2[idx])) {
+            S.upd[idx] = 1;
+            S.act[idx] = 0;
+        }
+        if (S.lsf) S.lsf[idx] = 0;
     }
 }
 
@@ -591,60 +627,104 @@ template void launch_bcg_init<double>(const BcgState<double>&, int, hipStream_t)
 template void launch_bcg_step<float>(const BcgState<float>&, int, hipStream_t);
 template void launch_bcg_step<double>(const BcgState<double>&, int, hipStream_t);
 
-// number of active systems -> *out
-__global__ void count_kernel(const int* act, int m, int* out) {
-    __shared__ int sh[256];
-    int s = 0;
-    for (int i = threadIdx.x; i < m; i += 256) s += act[i] != 0;
-    sh[threadIdx.x] = s;
+// active columns: out[0] total, out[1 + j] of system j (one wave per system)
+__global__ __launch_bounds__(1024) void count_kernel(const int* act, int ns, int* out) {
+    __shared__ int sh[16];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int c = 0;
+    if (w < ns) c = __popcll(__ballot(act[w * 64 + l] != 0));
+    if (l == 0) sh[w] = w < ns ? c : 0;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int i = 0; i < 16; ++i) tot += sh[i];
+        out[0] = tot;
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (l == 0 && w < ns) out[1 + w] = c;
 }
-void launch_count(const int* act, int m, int* out, hipStream_t st) {
-    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, act, m, out);
+void launch_count(const int* act, int ns, int* out, hipStream_t st) {
+    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1024), 0, st, act, ns, out);
 }
 
 // ------------------------------------------------------------------------
-// FP64 iterative refinement around the low-precision batched CG.
-// After the residual GEMM (R = B - A U, part = per-row-block |R|^2):
-// per column: rr = sum part; done if rr <= rtol^2 bb; otherwise the inner
-// right-hand side is R in FP32 and the column takes part in the inner solve.
-__global__ __launch_bounds__(256) void refine_check_kernel(RefineState R) {
+// Mixed-precision batched CG: FP64 solution and true residuals around the
+// FP32-arithmetic CG recurrence on the low-precision matrix.
+
+// u += x, x = 0 on the columns with upd set
+__global__ void corr_masked_kernel(double* u, float* x, const int* upd, long long n_pad) {
+    const int c = blockIdx.y, j = blockIdx.z;
+    if (!upd[j * 64 + c]) return;
+    const long long col = ((long long)j * 64 + c) * n_pad;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
+         i += (long long)gridDim.x * blockDim.x) {
+        u[col + i] += (double)x[col + i];
+        x[col + i] = 0.f;
+    }
+}
+void launch_corr_masked(double* u, float* x, const int* upd, long long n_pad, int ns, hipStream_t st) {
+    const unsigned gx = (unsigned)std::min<long long>((n_pad + 255) / 256, 16);
+    hipLaunchKernelGGL(corr_masked_kernel, dim3(gx, 64, ns), dim3(256), 0, st, u, x, upd, n_pad);
+}
+
+__global__ __launch_bounds__(256) void reliable_kernel(ReliableState R) {
     __shared__ double sh[8];
     const int c = blockIdx.x, j = blockIdx.y;
     const int idx = j * 64 + c;
+    if (!R.upd[idx]) return;
     const long long col = ((long long)j * 64 + c) * R.n_pad;
-    if (!R.oact[idx]) {
-        for (long long i = threadIdx.x; i < R.n_pad; i += 256) R.r32[col + i] = 0.f;
-        if (threadIdx.x == 0) R.want[idx] = 0;
-        return;
-    }
+    const float* dinv = R.dinv + (long long)j * R.n_pad;
     double rr = 0.0;
     for (int rb = threadIdx.x; rb < R.nrb; rb += 256) rr += R.part[((long long)j * R.nrb + rb) * 64 + c];
     for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rr;
     __syncthreads();
     rr = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
     const double bb = R.bb[idx];
     const bool fin = rr == rr && rr < 1.79e308;
-    const bool done = !fin || rr <= R.rtol2 * bb;
-    for (long long i = threadIdx.x; i < R.n_pad; i += 256) R.r32[col + i] = done ? 0.f : (float)R.r64[col + i];
+    const bool done = !fin || rr <= R.rtol2 * bb || R.iters[idx] >= R.maxit;
+    double rz = 0.0, pr = 0.0;
+    if (!done) {
+        for (long long i = threadIdx.x; i < R.n_pad; i += 256) {
+            const float r = (float)R.r64[col + i];
+            R.r[col + i] = r;
+            rz += (double)r * (double)(r * dinv[i]);
+            pr += (double)R.p[col + i] * (double)r;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            rz += __shfl_xor(rz, o);
+            pr += __shfl_xor(pr, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            sh[threadIdx.x >> 6] = rz;
+            sh[4 + (threadIdx.x >> 6)] = pr;
+        }
+        __syncthreads();
+        rz = sh[0] + sh[1] + sh[2] + sh[3];
+        pr = sh[4] + sh[5] + sh[6] + sh[7];
+    }
     if (threadIdx.x == 0) {
         R.rel[idx] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         if (!fin) R.status[idx] = 2;
-        if (done) R.oact[idx] = 0;
-        R.want[idx] = done ? 0 : 1;
+        if (done) {
+            R.act[idx] = 0;
+        } else {
+            R.rz[idx] = rz;
+            R.rupd2[idx] = rr;
+            R.pr[idx] = pr;
+            R.lsf[idx] = 1;
+            R.act[idx] = 1;
+        }
+        R.upd[idx] = 0;
     }
 }
-void launch_refine_check(const RefineState& R, int ns, hipStream_t st) {
-    hipLaunchKernelGGL(refine_check_kernel, dim3(64, ns), dim3(256), 0, st, R);
+void launch_reliable(const ReliableState& R, int ns, hipStream_t st) {
+    hipLaunchKernelGGL(reliable_kernel, dim3(64, ns), dim3(256), 0, st, R);
 }
 
-// b.b per column of the padded FP64 right-hand sides; outer activity
+// b.b per column of the padded FP64 right-hand sides; activity (columns
+// c < nrhs with a finite, nonzero b); u = 0; r32 = fp32(b) for the
+// low-precision CG
 __global__ __launch_bounds__(256) void refine_init_kernel(RefineState R, int nrhs) {
     __shared__ double sh[8];
     const int c = blockIdx.x, j = blockIdx.y;
@@ -660,28 +740,20 @@ __global__ __launch_bounds__(256) void refine_init_kernel(RefineState R, int nrh
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = bb;
     __syncthreads();
     bb = sh[0] + sh[1] + sh[2] + sh[3];
+    const bool fin = bb == bb && bb < 1.79e308;
+    const bool on = c < nrhs && fin && bb > 0.0;
+    if (R.r32)
+        for (long long i = threadIdx.x; i < R.n_pad; i += 256) R.r32[col + i] = on ? (float)R.b64[col + i] : 0.f;
     if (threadIdx.x == 0) {
-        const bool fin = bb == bb && bb < 1.79e308;
         R.bb[idx] = bb;
         R.status[idx] = fin ? 0 : 2;
-        R.oact[idx] = (c < nrhs && fin && bb > 0.0) ? 1 : 0;
+        R.oact[idx] = on ? 1 : 0;
+        if (R.want) R.want[idx] = on ? 1 : 0;
         R.rel[idx] = bb > 0.0 ? 1.0 : 0.0;
     }
 }
 void launch_refine_init(const RefineState& R, int ns, int nrhs, hipStream_t st) {
     hipLaunchKernelGGL(refine_init_kernel, dim3(64, ns), dim3(256), 0, st, R, nrhs);
-}
-
-// u += e for every element (e is zero where the column sat out)
-__global__ void add_corr_kernel(double* u, const float* e, long long m) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (long long)gridDim.x * blockDim.x)
-        u[i] += (double)e[i];
-}
-void launch_add_corr(double* u, const float* e, long long m, hipStream_t st) {
-    if (m <= 0) return;
-    const unsigned g = (unsigned)std::min<long long>((m + 255) / 256, 8192);
-    hipLaunchKernelGGL(add_corr_kernel, dim3(g), dim3(256), 0, st, u, e, m);
 }
 
 // ------------------------------------------------------------------------

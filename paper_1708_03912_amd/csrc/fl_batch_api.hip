@@ -43,6 +43,8 @@ int grow(fl_handle* h, T** p, size_t* cap, size_t bytes) {
     return FL_OK;
 }
 
+constexpr int KSPLIT_MAX = 8;
+
 // bump allocator over the batch workspace (256-byte aligned parts)
 struct Bump {
     size_t off = 0;
@@ -90,7 +92,9 @@ int ensure_planes(fl_handle* h, int dtype) {
 // GEMM arguments for systems j0 .. j0+nsys-1 of the batch in `dtype`
 GemmArgs gemm_args(const fl_batch& B, int dtype, int j0, int nsys) {
     GemmArgs g{};
-    g.ns = nsys;
+    g.nsys = nsys;
+    for (int i = 0; i < nsys; ++i) g.sys[i] = i;
+    g.ksplit = 1;
     g.n_pad = B.n_pad;
     g.lda = B.ld;
     g.sA = B.n_pad * B.ld;
@@ -200,15 +204,33 @@ int need_batch(fl_handle* h) {
     return FL_OK;
 }
 
-int count_active(fl_handle* h, const int* act, int m, int* out) {
+// active columns in total (*out) and the systems that still have one
+// (written as the launch list of g, if given)
+int count_active(fl_handle* h, const int* act, int ns, int* out, GemmArgs* g = nullptr) {
     fl_batch& B = h->B;
-    if (!B.hflag) HIPCHK(hipHostMalloc((void**)&B.hflag, 64, 0));
+    if (!B.hflag) HIPCHK(hipHostMalloc((void**)&B.hflag, 256, 0));
     int* dcount = (int*)(B.ws + B.ws_cap - 256);  // last 256 bytes of the workspace
-    launch_count(act, m, dcount, h->stream);
-    HIPCHK(hipMemcpyAsync(B.hflag, dcount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    launch_count(act, ns, dcount, h->stream);
+    HIPCHK(hipMemcpyAsync(B.hflag, dcount, sizeof(int) * (1 + ns), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    *out = *B.hflag;
+    *out = B.hflag[0];
+    if (g) {
+        g->nsys = 0;
+        for (int j = 0; j < ns; ++j)
+            if (B.hflag[1 + j] > 0) g->sys[g->nsys++] = j;
+    }
     return FL_OK;
+}
+
+// K split for a CG product over the active systems of g: aim at >= 1024
+// workgroups, keep >= 4 K stages per split, at most `cap` splits
+int choose_ksplit(const fl_batch& B, int id, int nsys, int cap) {
+    const GemmInfo gi = gemm_info(id);
+    const long long work = (long long)nsys * (B.n_pad / gi.bm);
+    const long long nk = B.n_pad / gi.bk;
+    int k = 1;
+    while (k < cap && work * k < 1024 && nk / (2 * k) >= 4) k *= 2;
+    return k;
 }
 
 }  // namespace
@@ -414,14 +436,14 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
     const size_t V = (size_t)ns * 64 * B.n_pad, NS = (size_t)ns * 64;
     Bump bp;
     const size_t o_b64 = bp.take(V * 8), o_u64 = bp.take(V * 8), o_r64 = bp.take(V * 8), o_p64 = bp.take(V * 8),
-                 o_q64 = bp.take(mixed ? 0 : V * 8), o_d64 = bp.take((size_t)ns * B.n_pad * 8),
+                 o_q64 = bp.take(mixed ? 0 : V * 8 * KSPLIT_MAX), o_d64 = bp.take((size_t)ns * B.n_pad * 8),
                  o_d32 = bp.take((size_t)ns * B.n_pad * 4), o_r32 = bp.take(mixed ? V * 4 : 0),
                  o_x32 = bp.take(mixed ? V * 4 : 0), o_rr32 = bp.take(mixed ? V * 4 : 0),
-                 o_p32 = bp.take(mixed ? V * 4 : 0), o_q32 = bp.take(mixed ? V * 4 : 0),
+                 o_p32 = bp.take(mixed ? V * 4 : 0), o_q32 = bp.take(mixed ? V * 4 * KSPLIT_MAX : 0),
                  o_ph = bp.take(mixed && inner >= FL_BF16 ? V * 2 : 0),
                  o_pl = bp.take(mixed && inner >= FL_BF16 ? V * 2 : 0),
                  o_part = bp.take(NS * (size_t)std::max(nrb64, nrbin) * 8), o_partr = bp.take(NS * nrb64 * 8),
-                 o_ints = bp.take(NS * 4 * 8), o_dbl = bp.take(NS * 6 * 8), o_tail = bp.take(256);
+                 o_ints = bp.take(NS * 8 * 4), o_dbl = bp.take(NS * 8 * 8), o_tail = bp.take(256);
     (void)o_tail;
     if ((rc = ensure_ws(h, bp.off))) return rc;
     char* ws = B.ws;
@@ -434,9 +456,10 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
     float* d32 = (float*)(ws + o_d32);
     int* I = (int*)(ws + o_ints);
     int *oact = I, *want = I + NS, *act = I + 2 * NS, *its = I + 3 * NS, *st_in = I + 4 * NS,
-        *st_out = I + 5 * NS;
+        *st_out = I + 5 * NS, *upd = I + 6 * NS, *lsf = I + 7 * NS;
     double* D = (double*)(ws + o_dbl);
-    double *bb = D, *rel = D + NS, *rz = D + 2 * NS, *ibb = D + 3 * NS, *irel = D + 4 * NS;
+    double *bb = D, *rel = D + NS, *rz = D + 2 * NS, *ibb = D + 3 * NS, *irel = D + 4 * NS,
+           *rupd2 = D + 5 * NS, *prv = D + 6 * NS;
 
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -455,16 +478,12 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
         R.n_pad = B.n_pad;
         R.b64 = b64;
         R.u64 = u64;
-        R.r64 = r64;
-        R.r32 = (float*)(ws + o_r32);
-        R.part = (double*)(ws + o_partr);
-        R.nrb = nrb64;
+        R.r32 = mixed ? (float*)(ws + o_r32) : nullptr;
         R.bb = bb;
         R.oact = oact;
         R.want = want;
         R.status = st_out;
         R.rel = rel;
-        R.rtol2 = rtol * rtol;
         launch_refine_init(R, ns, nc, h->stream);  // b.b, outer activity, u = 0
         HIPCHK(hipGetLastError());
         std::fill(h_tot.begin(), h_tot.end(), 0);
@@ -498,13 +517,20 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
             g.act = act;
             g.epi = 1;
             int nact = 1;
+            if ((rc = count_active(h, act, ns, &nact, &g))) return rc;
             for (int it = 0; nact > 0 && it < maxit; it += chunk) {
+                const int ks = choose_ksplit(B, id64, g.nsys, KSPLIT_MAX);
+                g.ksplit = ks;
+                g.epi = ks > 1 ? 0 : 1;
+                g.ysplit = (long long)V;
+                S.ksplit = ks;
+                S.ysplit = (long long)V;
                 for (int k = 0; k < chunk; ++k) {
                     HIPCHK(launch_gemm(id64, g, h->stream));
                     launch_bcg_step(S, ns, h->stream);
                 }
                 HIPCHK(hipGetLastError());
-                if ((rc = count_active(h, act, ns * 64, &nact))) return rc;
+                if ((rc = count_active(h, act, ns, &nact, &g))) return rc;
             }
             HIPCHK(hipMemcpy(h_its.data(), its, sizeof(int) * NS, hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(h_st.data(), st_in, sizeof(int) * NS, hipMemcpyDeviceToHost));
@@ -530,15 +556,19 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
             S.rel = irel;
             S.partq = (double*)(ws + o_part);
             S.nrbq = nrbin;
-            const double tin = inner == FL_BF16 ? 1e-2 : 1e-4;
-            S.rtol2 = tin * tin;
+            S.rtol2 = rtol * rtol;
             S.maxit = maxit;
+            S.upd = upd;
+            S.rupd2 = rupd2;
+            S.lsf = lsf;
+            S.pr = prv;
+            S.delta2 = 1e-2;                         // replace when |r| fell 10x
             GemmArgs gr = gemm_args(B, FL_F64, 0, ns);  // r = b - A u, |r|^2 partials
             gr.X = u64;
             gr.Y = r64;
             gr.V = b64;
             gr.part = (double*)(ws + o_partr);
-            gr.act = oact;
+            gr.act = upd;
             gr.epi = 2;
             GemmArgs gi = gemm_args(B, inner, 0, ns);   // q = A p, p.q partials
             gi.X = inner >= FL_BF16 ? S.ph : (const void*)S.p;
@@ -548,38 +578,64 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
             gi.part = (double*)(ws + o_part);
             gi.act = act;
             gi.epi = 1;
-            int outer = 0;
-            for (;; ++outer) {
-                HIPCHK(launch_gemm(id64, gr, h->stream));
-                launch_refine_check(R, ns, h->stream);
-                HIPCHK(hipGetLastError());
-                int nout = 0;
-                if ((rc = count_active(h, oact, ns * 64, &nout))) return rc;
-                if (nout == 0 || outer >= 30) break;
-                launch_bcg_init(S, ns, h->stream);
-                int nact = 1;
-                for (int it = 0; nact > 0 && it < maxit; it += chunk) {
+            ReliableState RS{};
+            RS.n_pad = B.n_pad;
+            RS.r64 = r64;
+            RS.part = (double*)(ws + o_partr);
+            RS.nrb = nrb64;
+            RS.r = S.r;
+            RS.dinv = d32;
+            RS.rz = rz;
+            RS.rupd2 = rupd2;
+            RS.bb = bb;
+            RS.p = S.p;
+            RS.pr = prv;
+            RS.lsf = lsf;
+            RS.act = act;
+            RS.upd = upd;
+            RS.iters = its;
+            RS.status = st_out;
+            RS.rel = rel;
+            RS.rtol2 = rtol * rtol;
+            RS.maxit = maxit;
+            launch_bcg_init(S, ns, h->stream);       // r = fp32(b), x = 0, p = D^-1 r
+            int nact = 0, nupd = 0, replacements = 0;
+            if ((rc = count_active(h, act, ns, &nact, &gi))) return rc;
+            for (long long guard = 0; (nact > 0 || nupd > 0) && guard <= (long long)maxit + 64; guard += chunk) {
+                if (nact > 0) {
+                    const int ks = choose_ksplit(B, idin, gi.nsys, KSPLIT_MAX);
+                    gi.ksplit = ks;
+                    gi.epi = ks > 1 ? 0 : 1;
+                    gi.ysplit = (long long)V;
+                    S.ksplit = ks;
+                    S.ysplit = (long long)V;
                     for (int k = 0; k < chunk; ++k) {
                         HIPCHK(launch_gemm(idin, gi, h->stream));
                         launch_bcg_step(S, ns, h->stream);
                     }
                     HIPCHK(hipGetLastError());
-                    if ((rc = count_active(h, act, ns * 64, &nact))) return rc;
                 }
-                launch_add_corr(u64, S.x, (long long)V, h->stream);
-                HIPCHK(hipGetLastError());
-                HIPCHK(hipMemcpy(h_its.data(), its, sizeof(int) * NS, hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(h_st2.data(), st_in, sizeof(int) * NS, hipMemcpyDeviceToHost));
-                for (size_t i = 0; i < NS; ++i) {
-                    h_tot[i] += h_its[i];
-                    if (h_st2[i]) h_st[i] = h_st2[i];
+                if ((rc = count_active(h, upd, ns, &nupd, &gr))) return rc;
+                if (nupd > 0) {
+                    // u += x in FP64, r = b - A u with the FP64 matrix
+                    launch_corr_masked(u64, S.x, upd, B.n_pad, ns, h->stream);
+                    HIPCHK(launch_gemm(id64, gr, h->stream));
+                    launch_reliable(RS, ns, h->stream);
+                    HIPCHK(hipGetLastError());
+                    ++replacements;
+                    nupd = 0;
                 }
+                if ((rc = count_active(h, act, ns, &nact, &gi))) return rc;
             }
-            outer_max = std::max(outer_max, outer);
+            outer_max = std::max(outer_max, replacements);
+            HIPCHK(hipMemcpy(h_its.data(), its, sizeof(int) * NS, hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(h_rel.data(), rel, sizeof(double) * NS, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(h_st.data(), st_in, sizeof(int) * NS, hipMemcpyDeviceToHost));
             HIPCHK(hipMemcpy(h_st2.data(), st_out, sizeof(int) * NS, hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < NS; ++i)
+            for (size_t i = 0; i < NS; ++i) {
+                h_tot[i] = h_its[i];
                 if (h_st2[i]) h_st[i] = h_st2[i];
+            }
         }
         launch_unpack_f64(u64, B.n_pad, B.n, nc, ns, U + c0 * ldu, ldu, strideU, h->stream);
         HIPCHK(hipGetLastError());

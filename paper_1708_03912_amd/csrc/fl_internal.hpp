@@ -174,7 +174,10 @@ void launch_dot2(const double* a, const double* b, const double* c, long long n,
 enum { GD_F64 = 0, GD_F32 = 1, GD_BF16 = 2 };
 
 struct GemmArgs {
-    int ns;                 // systems in the batch
+    int nsys;               // systems in this launch
+    int sys[FL_MAX_BATCH];  // their indices in the batch
+    int ksplit;             // K split: split k writes Y + k * ysplit (epi 0 only)
+    long long ysplit;
     long long n_pad;        // rows = K extent; multiple of 256
     const void* A;          // plane 0: ns blocks of n_pad x lda (row-major), block stride sA
     const void* A2;         // bf16 low plane (two-plane variants)
@@ -232,35 +235,73 @@ struct BcgState {
     double* rz;
     double* bb;
     double* rel;            // ||r|| / ||b|| of the last iterate
-    const double* partq;    // GEMM epilogue partials of p.q
+    const double* partq;    // GEMM epilogue partials of p.q (ksplit == 1)
     int nrbq;
+    int ksplit;             // > 1: q is the sum of ksplit partial products
+    long long ysplit;       // elements between the partial products
     double rtol2;
     int maxit;
+    // reliable updates (mixed precision): a column asks for a residual
+    // replacement (upd = 1) and pauses (act = 0) when rr < delta2 * rupd2 or
+    // when it claims convergence / reaches maxit; p is kept up to date so it
+    // can go on.  The first step after a replacement takes the exact line
+    // search alpha = p.r / p.Ap (lsf set, numerator in pr).
+    int* upd;               // null: plain CG
+    double* rupd2;          // |r|^2 at the last replacement
+    double delta2;
+    int* lsf;
+    const double* pr;
 };
 template <class T>
 void launch_bcg_init(const BcgState<T>& S, int ns, hipStream_t st);
 template <class T>
 void launch_bcg_step(const BcgState<T>& S, int ns, hipStream_t st);
-void launch_count(const int* act, int m, int* out, hipStream_t st);
+// out[0] = active columns, out[1 + j] = active columns of system j
+void launch_count(const int* act, int ns, int* out, hipStream_t st);
 
+// Right-hand-side set-up of the batched solve: |b|^2, activity, u = 0,
+// r32 = fp32(b) for mixed precision.
 struct RefineState {
     long long n_pad;
     const double* b64;
     double* u64;
-    const double* r64;      // residual GEMM output
-    float* r32;             // inner right-hand side
-    const double* part;     // residual GEMM partials |r|^2
-    int nrb;
+    float* r32;             // null: not needed
     double* bb;
-    int* oact;              // outer activity
-    int* want;              // inner participation
+    int* oact;              // columns with a finite nonzero b
+    int* want;              // CG participation (may be null)
+    int* status;
+    double* rel;
+};
+void launch_refine_init(const RefineState& R, int ns, int nrhs, hipStream_t st);
+
+
+// Residual replacement of the mixed-precision CG: after u += x (x = 0) and the
+// FP64 residual GEMM r64 = b - A u on the columns with upd set, either the
+// column has converged (act = 0, final relres) or r = fp32(r64), rz, rupd2
+// are refreshed and the column goes on (act = 1).
+struct ReliableState {
+    long long n_pad;
+    const double* r64;
+    const double* part;     // |r64|^2 partials of the residual GEMM
+    int nrb;
+    float* r;
+    const float* dinv;
+    double* rz;
+    double* rupd2;
+    const double* bb;       // |b|^2 of the FP64 right-hand side
+    const float* p;         // current search directions
+    double* pr;             // p.r after the replacement
+    int* lsf;
+    int* act;
+    int* upd;
+    const int* iters;
     int* status;
     double* rel;
     double rtol2;
+    int maxit;
 };
-void launch_refine_init(const RefineState& R, int ns, int nrhs, hipStream_t st);
-void launch_refine_check(const RefineState& R, int ns, hipStream_t st);
-void launch_add_corr(double* u, const float* e, long long m, hipStream_t st);
+void launch_corr_masked(double* u, float* x, const int* upd, long long n_pad, int ns, hipStream_t st);
+void launch_reliable(const ReliableState& R, int ns, hipStream_t st);
 
 struct LoadArgs {
     ElemDev E;

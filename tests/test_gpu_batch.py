@@ -16,9 +16,10 @@ the CPU oracle.
             |x - hi| <= 2^-8 |x|, lo rounds that to 2^-8 relative) + n 2^-24
     bf16x2  g = 2^-16 (A as hi + lo) + 2^-24 + 2^-16 (X split) + 2^-16 (the
             dropped A_lo X_lo product) + n 2^-24
-* fl_solve_batch at rtol 1e-13 (FP64 CG, or FP64 refinement around an
-  FP32 / bf16 inner CG): ||u - u_oracle||_A <= 1e-10 ||u_oracle||_A, the
-  oracle solving its own matrix and load vector by Cholesky.
+* fl_solve_batch at rtol 1e-13 (FP64 CG, or CG in FP32 arithmetic on the
+  FP32 / bf16 matrix with FP64 solution and FP64 residual replacement):
+  ||u - u_oracle||_A <= 1e-10 ||u_oracle||_A, the oracle solving its own
+  matrix and load vector by Cholesky.
 """
 import numpy as np
 import pytest
