@@ -265,8 +265,8 @@ int fl_matmul(fl_handle *h, int s_index, int dtype, const void *X, int64_t ldx, 
  *   inner = FL_F32 / FL_BF16 / FL_BF16X2   mixed-precision CG with
  *           reliable updates: the CG recurrence runs in FP32 arithmetic with
  *           the matrix in that storage and the solution accumulates in FP64;
- *           when a column's residual has fallen 10x since the last
- *           replacement, or it claims convergence, it pauses, u += x is
+ *           when a column's residual has fallen 100x (FL_BF16: 10x) since
+ *           the last replacement, or it claims convergence, it pauses, u += x is
  *           formed in FP64 and the residual is replaced by the FP64 residual
  *           b - A u (FP64 matrix); the column resumes with its search
  *           direction and an exact line search for that step, and stops

@@ -667,42 +667,42 @@ void launch_corr_masked(double* u, float* x, const int* upd, long long n_pad, in
 }
 
 __global__ __launch_bounds__(256) void reliable_kernel(ReliableState R) {
-    __shared__ double sh[8];
+    __shared__ double sh[12];
     const int c = blockIdx.x, j = blockIdx.y;
     const int idx = j * 64 + c;
     if (!R.upd[idx]) return;
     const long long col = ((long long)j * 64 + c) * R.n_pad;
     const float* dinv = R.dinv + (long long)j * R.n_pad;
-    double rr = 0.0;
-    for (int rb = threadIdx.x; rb < R.nrb; rb += 256) rr += R.part[((long long)j * R.nrb + rb) * 64 + c];
-    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rr;
+    // r64 = b - sum of the partial products; rr, and (used only if the
+    // column goes on) r, rz, p.r
+    double rr = 0.0, rz = 0.0, pr = 0.0;
+    for (long long i = threadIdx.x; i < R.n_pad; i += 256) {
+        double y = R.y64[col + i];
+        for (int k = 1; k < R.ksplit; ++k) y += R.y64[k * R.ysplit + col + i];
+        const double r64 = R.b64[col + i] - y;
+        rr += r64 * r64;
+        const float r = (float)r64;
+        R.r[col + i] = r;
+        rz += (double)r * (double)(r * dinv[i]);
+        pr += (double)R.p[col + i] * (double)r;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        rr += __shfl_xor(rr, o);
+        rz += __shfl_xor(rz, o);
+        pr += __shfl_xor(pr, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = rr;
+        sh[4 + (threadIdx.x >> 6)] = rz;
+        sh[8 + (threadIdx.x >> 6)] = pr;
+    }
     __syncthreads();
     rr = sh[0] + sh[1] + sh[2] + sh[3];
-    __syncthreads();
+    rz = sh[4] + sh[5] + sh[6] + sh[7];
+    pr = sh[8] + sh[9] + sh[10] + sh[11];
     const double bb = R.bb[idx];
     const bool fin = rr == rr && rr < 1.79e308;
     const bool done = !fin || rr <= R.rtol2 * bb || R.iters[idx] >= R.maxit;
-    double rz = 0.0, pr = 0.0;
-    if (!done) {
-        for (long long i = threadIdx.x; i < R.n_pad; i += 256) {
-            const float r = (float)R.r64[col + i];
-            R.r[col + i] = r;
-            rz += (double)r * (double)(r * dinv[i]);
-            pr += (double)R.p[col + i] * (double)r;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            rz += __shfl_xor(rz, o);
-            pr += __shfl_xor(pr, o);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            sh[threadIdx.x >> 6] = rz;
-            sh[4 + (threadIdx.x >> 6)] = pr;
-        }
-        __syncthreads();
-        rz = sh[0] + sh[1] + sh[2] + sh[3];
-        pr = sh[4] + sh[5] + sh[6] + sh[7];
-    }
     if (threadIdx.x == 0) {
         R.rel[idx] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         if (!fin) R.status[idx] = 2;

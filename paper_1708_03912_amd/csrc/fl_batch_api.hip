@@ -435,14 +435,15 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
     // workspace
     const size_t V = (size_t)ns * 64 * B.n_pad, NS = (size_t)ns * 64;
     Bump bp;
-    const size_t o_b64 = bp.take(V * 8), o_u64 = bp.take(V * 8), o_r64 = bp.take(V * 8), o_p64 = bp.take(V * 8),
+    const size_t o_b64 = bp.take(V * 8), o_u64 = bp.take(V * 8), o_r64 = bp.take(V * 8 * (mixed ? KSPLIT_MAX : 1)),
+                 o_p64 = bp.take(V * 8),
                  o_q64 = bp.take(mixed ? 0 : V * 8 * KSPLIT_MAX), o_d64 = bp.take((size_t)ns * B.n_pad * 8),
                  o_d32 = bp.take((size_t)ns * B.n_pad * 4), o_r32 = bp.take(mixed ? V * 4 : 0),
                  o_x32 = bp.take(mixed ? V * 4 : 0), o_rr32 = bp.take(mixed ? V * 4 : 0),
                  o_p32 = bp.take(mixed ? V * 4 : 0), o_q32 = bp.take(mixed ? V * 4 * KSPLIT_MAX : 0),
                  o_ph = bp.take(mixed && inner >= FL_BF16 ? V * 2 : 0),
                  o_pl = bp.take(mixed && inner >= FL_BF16 ? V * 2 : 0),
-                 o_part = bp.take(NS * (size_t)std::max(nrb64, nrbin) * 8), o_partr = bp.take(NS * nrb64 * 8),
+                 o_part = bp.take(NS * (size_t)std::max(nrb64, nrbin) * 8),
                  o_ints = bp.take(NS * 8 * 4), o_dbl = bp.take(NS * 8 * 8), o_tail = bp.take(256);
     (void)o_tail;
     if ((rc = ensure_ws(h, bp.off))) return rc;
@@ -562,14 +563,15 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
             S.rupd2 = rupd2;
             S.lsf = lsf;
             S.pr = prv;
-            S.delta2 = 1e-2;                         // replace when |r| fell 10x
-            GemmArgs gr = gemm_args(B, FL_F64, 0, ns);  // r = b - A u, |r|^2 partials
+            // replace when |r| fell 100x (10x for the one-plane bf16 matrix,
+            // whose products drift faster)
+            S.delta2 = inner == FL_BF16 ? 1e-2 : 1e-4;
+            GemmArgs gr = gemm_args(B, FL_F64, 0, ns);  // A u (K-split partial products)
             gr.X = u64;
             gr.Y = r64;
-            gr.V = b64;
-            gr.part = (double*)(ws + o_partr);
             gr.act = upd;
-            gr.epi = 2;
+            gr.epi = 0;
+            gr.ysplit = (long long)V;
             GemmArgs gi = gemm_args(B, inner, 0, ns);   // q = A p, p.q partials
             gi.X = inner >= FL_BF16 ? S.ph : (const void*)S.p;
             gi.X2 = S.pl;
@@ -580,9 +582,9 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
             gi.epi = 1;
             ReliableState RS{};
             RS.n_pad = B.n_pad;
-            RS.r64 = r64;
-            RS.part = (double*)(ws + o_partr);
-            RS.nrb = nrb64;
+            RS.b64 = b64;
+            RS.y64 = r64;
+            RS.ysplit = (long long)V;
             RS.r = S.r;
             RS.dinv = d32;
             RS.rz = rz;
@@ -619,6 +621,7 @@ int fl_solve_batch(fl_handle* h, const double* Bm, int64_t ldb, int64_t strideB,
                 if (nupd > 0) {
                     // u += x in FP64, r = b - A u with the FP64 matrix
                     launch_corr_masked(u64, S.x, upd, B.n_pad, ns, h->stream);
+                    gr.ksplit = RS.ksplit = choose_ksplit(B, id64, gr.nsys, KSPLIT_MAX);
                     HIPCHK(launch_gemm(id64, gr, h->stream));
                     launch_reliable(RS, ns, h->stream);
                     HIPCHK(hipGetLastError());

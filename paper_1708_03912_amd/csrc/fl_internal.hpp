@@ -276,14 +276,16 @@ void launch_refine_init(const RefineState& R, int ns, int nrhs, hipStream_t st);
 
 
 // Residual replacement of the mixed-precision CG: after u += x (x = 0) and the
-// FP64 residual GEMM r64 = b - A u on the columns with upd set, either the
-// column has converged (act = 0, final relres) or r = fp32(r64), rz, rupd2
-// are refreshed and the column goes on (act = 1).
+// FP64 product A u (possibly as K-split partial products) on the columns
+// with upd set, r64 = b - A u; either the column has converged (act = 0,
+// final relres) or r = fp32(r64), rz, rupd2 are refreshed and the column
+// goes on (act = 1).
 struct ReliableState {
     long long n_pad;
-    const double* r64;
-    const double* part;     // |r64|^2 partials of the residual GEMM
-    int nrb;
+    const double* b64;
+    const double* y64;      // partial products of A u (ksplit of them)
+    int ksplit;
+    long long ysplit;
     float* r;
     const float* dinv;
     double* rz;
