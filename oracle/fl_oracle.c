@@ -216,6 +216,27 @@ void orc_far2(const orc_rules *R, double s, int k, const double *X, const double
     }
 }
 
+/* Many separated triangle pairs at once (OpenMP over the pairs): for pair
+ * i the order-k rule of orc_far2 with exponent s[i], written as 21 values:
+ * the K block (a <= b: 00 01 02 11 12 22), the Kt block (same order) and
+ * the cross block int int l_a(x) l_b(y) k = -O[3a+b], a, b = 0..2.  The
+ * tensor rules do not depend on s, so one rule table serves every pair. */
+void orc_far2_many(const orc_rules *R, int64_t m, const double *s, int k, const double *X,
+                   const double *Y, double *out) {
+    static const int sa[6] = {0, 0, 0, 1, 1, 2}, sb[6] = {0, 1, 2, 1, 2, 2};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < m; ++i) {
+        double SK[9], ST[9], O[9];
+        orc_far2(R, s[i], k, X + 6 * i, Y + 6 * i, SK, ST, O);
+        double *o = out + 21 * i;
+        for (int t = 0; t < 6; ++t) {
+            o[t] = SK[3 * sa[t] + sb[t]];
+            o[6 + t] = ST[3 * sa[t] + sb[t]];
+        }
+        for (int t = 0; t < 9; ++t) o[12 + t] = -O[t];
+    }
+}
+
 /* Identical triangle K = (v0,v1,v2).  For x, y in K the numerator is
  * D_a D_b with D = lambda(x) - lambda(y) (sums to zero) and
  * x - y = sum_a D_a v_a.  Hence
@@ -556,6 +577,8 @@ typedef struct {
     const int *k_far_bnd;  /* ncls+1 orders for separated element/facet pairs */
     int with_boundary;     /* 0: drop a^{Kxe} (regional operator) */
     int which;             /* bitmask: 1 far, 2 touching, 4 boundary */
+    int far_skip_below;    /* separated pairs of class < this are left out
+                              (counted only); 0: none */
 } orc_opts;
 
 static double cdn(int dim, double s) {
@@ -636,6 +659,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                 double hm = h2[K] > h2[Kt] ? h2[K] : h2[Kt];
                 int cls = order_class(d2, hm, o->ncls, o->theta);
                 cnt[cls] += 1;
+                if (cls < o->far_skip_below) continue;
                 int k = o->k_far[cls];
                 double SK[9], ST[9], O[9];
                 if (dim == 1) {
@@ -817,4 +841,41 @@ int orc_pcg(int64_t n, const double *A, const double *b, double *x, double rtol,
     if (relres) *relres = sqrt(rr) / nb;
     free(r); free(z); free(p); free(q);
     return it;
+}
+
+/* Separated triangle pairs (K < Kt, no common vertex) whose order class
+ * (thresholds theta on centroid distance / larger longest edge, as in
+ * orc_assemble) is below nsur.  For each: K, Kt, the class and the bin of
+ * the same ratio for the thresholds redges (nr of them).  Writes at most
+ * cap entries of 4 int64 each; returns the total count. */
+int64_t orc_band_pairs(const double *verts, int64_t nc, const int32_t *cells, int ncls,
+                       const double *theta, int nsur, int nr, const double *redges, int64_t cap,
+                       int64_t *out) {
+    double *cen = (double *)malloc(sizeof(double) * nc * 2);
+    double *h2 = (double *)malloc(sizeof(double) * nc);
+    for (int64_t K = 0; K < nc; ++K) centroid_h2(2, verts, cells + 3 * K, cen + 2 * K, h2 + K);
+    int64_t n = 0;
+    for (int64_t K = 0; K < nc; ++K)
+        for (int64_t Kt = K + 1; Kt < nc; ++Kt) {
+            const int32_t *cK = cells + 3 * K, *cT = cells + 3 * Kt;
+            int sh = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) sh += cK[a] == cT[b];
+            if (sh) continue;
+            double dx = cen[2 * K] - cen[2 * Kt], dy = cen[2 * K + 1] - cen[2 * Kt + 1];
+            double d2 = dx * dx + dy * dy;
+            double hm = h2[K] > h2[Kt] ? h2[K] : h2[Kt];
+            int cls = order_class(d2, hm, ncls, theta);
+            if (cls >= nsur) continue;
+            if (n < cap) {
+                out[4 * n] = K;
+                out[4 * n + 1] = Kt;
+                out[4 * n + 2] = cls;
+                out[4 * n + 3] = order_class(d2, hm, nr, redges);
+            }
+            ++n;
+        }
+    free(cen);
+    free(h2);
+    return n;
 }

@@ -238,7 +238,7 @@ class _Opts(C.Structure):
     _fields_ = [("s", C.c_double), ("k_touch", C.c_int), ("k_touch_bnd", C.c_int),
                 ("ncls", C.c_int), ("theta", C.POINTER(C.c_double)),
                 ("k_far", C.POINTER(C.c_int)), ("k_far_bnd", C.POINTER(C.c_int)),
-                ("with_boundary", C.c_int), ("which", C.c_int)]
+                ("with_boundary", C.c_int), ("which", C.c_int), ("far_skip_below", C.c_int)]
 
 
 def boundary_normals(dim, verts, cells, bfacets):
@@ -279,7 +279,8 @@ def dof_nodes(nv, bfacets, s, mode="paper"):
     return np.nonzero(~on_b)[0]
 
 
-def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None):
+def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None,
+                  far_skip_below=0):
     """Full-node matrix (nv x nv) of a(phi_i, phi_j) by the element-pair
     decomposition of Sec. 5.  ``rows``: optional vertex indices; only those
     rows are accumulated (others stay zero).  Returns (A, class_counts)."""
@@ -302,7 +303,7 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     kb = np.ascontiguousarray(orders.k_far_bnd, dtype=np.int32)
     o = _Opts(s, orders.k_touch, orders.k_touch_bnd, len(orders.theta), _dp(th),
               kf.ctypes.data_as(C.POINTER(C.c_int)), kb.ctypes.data_as(C.POINTER(C.c_int)),
-              1 if with_boundary else 0, which)
+              1 if with_boundary else 0, which, int(far_skip_below))
     cnt = np.zeros(16, dtype=np.int64)
     if threads is not None:
         os.environ["OMP_NUM_THREADS"] = str(threads)

@@ -1,0 +1,381 @@
+"""CPU FP64 reference for the learned pair-integral surrogate.
+
+TEST INFRASTRUCTURE ONLY (like the rest of ``oracle/``): imported by
+``tests/``; never by the product library, with which it shares no code.
+
+What is learned.  For two separated triangles K, Kt (Sec. 5 element-pair
+decomposition; no common vertex) and k(x, y) = |x - y|^{-2-2s} the 21
+integrals
+
+    SK_ab = int_K int_Kt l_a(x) l_b(x) k dy dx      (a <= b: 00 01 02 11 12 22)
+    ST_ab = int_K int_Kt l_a(y) l_b(y) k dy dx      (same order)
+    X_ab  = int_K int_Kt l_a(x) l_b(y) k dy dx      (a, b = 0..2, row-major)
+
+(l_a the barycentric coordinates) make up the pair's contribution to the
+stiffness matrix.  The method evaluates them with tensor Gauss rules whose
+order grows as the pair gets closer (App. B).  The surrogate instead takes
+the cheapest of those rules, order 2 (2 x 2 collapsed points per triangle),
+and predicts its relative error t = I / Q2 - 1 for each of the 21 values;
+the corrected value is Q2 (1 + t).
+
+Canonical form.  t does not change under translation, rotation and uniform
+scaling of the pair (integral and rule scale alike).  Each pair is put in a
+canonical order first:
+  * the triangle with the longer longest edge comes first (equal: the one
+    whose lexicographically smallest vertex is smaller);
+  * in each triangle the vertices are (a, b, c) with ab a longest edge
+    (several: the one whose opposite vertex is lexicographically smallest)
+    and c to the left of a -> b;
+and described in the frame of the first triangle: origin a, unit length
+|b - a|, x axis along b - a.  Features (9): c of the first triangle and the
+three canonical vertices of the second in that frame, and s.
+
+Network: 9 -> 64 -> 64 -> 21, tanh on both hidden layers, inputs and
+targets standardised with the training set's means and standard
+deviations, loss = mean over samples and the 21 outputs of the squared
+error.  Parameters are kept in the padded layout of
+``paper_1708_03912_amd.pairgen.param_layout`` (an input layout only).
+
+Certification.  A pair is handed to the network only when its features lie
+in the box spanned by the training set and the network's measured error on
+held-out pairs of the same distance bin (centroid distance over the larger
+longest edge, edges RBIN_EDGES) and s bin (SBIN_EDGES), times 1.25, is at
+most the requested tolerance; every other pair keeps the exact rule.
+
+Parity status: pinned by ``tests/test_surrogate_oracle.py`` -- invariance
+of the targets under similarity maps and vertex relabelling, the order-8
+targets against order 16, the gradient against central differences, the
+forward map against its small-weight linearisation, Adam's first step, and
+the surrogate assembly with zero correction against plain order-2 / exact
+assembly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import oracle as O
+
+NIN, NH, NOUT, KIN, KOUT = 9, 64, 21, 32, 32
+SYM = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+RBIN_EDGES = (1.0, 1.5, 2.0, 2.5, 3.0)
+SBIN_EDGES = (0.25, 0.5, 0.75)
+NRB, NSB = len(RBIN_EDGES) + 1, len(SBIN_EDGES) + 1
+SAFETY = 1.25
+MIN_BIN = 32
+LAYOUT = [("W1", (NH, KIN)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)),
+          ("W3", (KOUT, NH)), ("b3", (KOUT,))]
+NPARAM = sum(int(np.prod(sh)) for _, sh in LAYOUT)
+
+
+def unpack(theta):
+    """Packed parameter vector -> dict of views."""
+    out, o = {}, 0
+    for name, sh in LAYOUT:
+        n = int(np.prod(sh))
+        out[name] = theta[o:o + n].reshape(sh)
+        o += n
+    return out
+
+
+def pack(p):
+    return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in LAYOUT])
+
+
+# ------------------------------------------------------- canonical form --
+
+def _sq(p, q):
+    dx = p[0] - q[0]
+    dy = p[1] - q[1]
+    return dx * dx + dy * dy
+
+
+def _lexless(p, q):
+    return (p[0], p[1]) < (q[0], q[1])
+
+
+def _lexmin(P):
+    m = P[0]
+    for q in P[1:]:
+        if _lexless(q, m):
+            m = q
+    return m
+
+
+def _canon_tri(P):
+    """Vertex order (ia, ib, ic) of one triangle P (3 x 2)."""
+    L = [_sq(P[(i + 1) % 3], P[i]) for i in range(3)]
+    best = None
+    for i in range(3):
+        if L[i] != max(L):
+            continue
+        if best is None or _lexless(P[(i + 2) % 3], P[(best + 2) % 3]):
+            best = i
+    ia, ib, ic = best, (best + 1) % 3, (best + 2) % 3
+    a, b, c = P[ia], P[ib], P[ic]
+    cross = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+    if cross < 0:
+        ia, ib = ib, ia
+    return ia, ib, ic
+
+
+def canonical(X, Y):
+    """Canonical form of the pair (X, Y) (each 3 x 2 or 6 values).  Returns
+    (swap, pK, pT): swap = 1 if Y comes first; pK / pT the vertex orders
+    of the first / second triangle (indices into that triangle)."""
+    X = np.asarray(X, dtype=np.float64).reshape(3, 2)
+    Y = np.asarray(Y, dtype=np.float64).reshape(3, 2)
+    hX = max(_sq(X[(i + 1) % 3], X[i]) for i in range(3))
+    hY = max(_sq(Y[(i + 1) % 3], Y[i]) for i in range(3))
+    swap = 1 if (hY > hX or (hY == hX and _lexless(_lexmin(Y), _lexmin(X)))) else 0
+    F, S = (Y, X) if swap else (X, Y)
+    return swap, _canon_tri(F), _canon_tri(S)
+
+
+def features_one(X, Y, s):
+    """(features (9,), canonical first triangle (3x2), canonical second
+    triangle (3x2), swap, pK, pT)."""
+    swap, pK, pT = canonical(X, Y)
+    X = np.asarray(X, dtype=np.float64).reshape(3, 2)
+    Y = np.asarray(Y, dtype=np.float64).reshape(3, 2)
+    F, S = (Y, X) if swap else (X, Y)
+    Kc, Tc = F[list(pK)], S[list(pT)]
+    a = Kc[0]
+    ex, ey = Kc[1][0] - a[0], Kc[1][1] - a[1]
+    L2 = ex * ex + ey * ey
+
+    def frame(p):
+        dx, dy = p[0] - a[0], p[1] - a[1]
+        return (dx * ex + dy * ey) / L2, (ex * dy - ey * dx) / L2
+
+    f = [*frame(Kc[2]), *frame(Tc[0]), *frame(Tc[1]), *frame(Tc[2]), s]
+    return np.array(f), Kc, Tc, swap, pK, pT
+
+
+def features(X, Y, s):
+    """Features of m pairs: X, Y (m, 6), s (m,) -> (m, 9)."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 6)
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 6)
+    return np.array([features_one(X[i], Y[i], s[i])[0] for i in range(len(X))])
+
+
+def canonical_pairs(X, Y):
+    """Canonical vertex coordinates of m pairs: (Kc (m, 6), Tc (m, 6))."""
+    X = np.asarray(X, dtype=np.float64).reshape(-1, 6)
+    Y = np.asarray(Y, dtype=np.float64).reshape(-1, 6)
+    Kc, Tc = np.empty_like(X), np.empty_like(Y)
+    for i in range(len(X)):
+        _, a, b, _, _, _ = features_one(X[i], Y[i], 0.0)
+        Kc[i], Tc[i] = a.ravel(), b.ravel()
+    return Kc, Tc
+
+
+# ------------------------------------------------------ pair integrals --
+
+def integrals_many(s, k, X, Y):
+    """The 21 integrals (vertex order as given) of m pairs with the
+    order-k collapsed Gauss rule on both triangles: (m, 21).  C loop."""
+    s = np.ascontiguousarray(np.broadcast_to(np.asarray(s, dtype=np.float64), (len(X),)))
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 6)
+    Y = np.ascontiguousarray(Y, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros((len(s), 21))
+    if len(s):
+        O.lib().orc_far2_many(O._rp(0.5), C.c_int64(len(s)), O._dp(s), C.c_int(k), O._dp(X),
+                              O._dp(Y), O._dp(out))
+    return out
+
+
+def dataset(X, Y, s, k_exact=8):
+    """Features (m, 9) and targets t = I_k / Q2 - 1 (m, 21) in canonical
+    order."""
+    Kc, Tc = canonical_pairs(X, Y)
+    F = features(X, Y, s)
+    t = integrals_many(s, k_exact, Kc, Tc) / integrals_many(s, 2, Kc, Tc) - 1.0
+    return F, t
+
+
+# ------------------------------------------------------------- network --
+
+def standardise(F, Tg):
+    """Means and standard deviations (population) of features and targets,
+    deviations floored at 1e-12."""
+    return F.mean(0), np.maximum(F.std(0), 1e-12), Tg.mean(0), np.maximum(Tg.std(0), 1e-12)
+
+
+def _pad_in(xn):
+    out = np.zeros((len(xn), KIN))
+    out[:, :NIN] = xn
+    return out
+
+
+def forward(theta, xn):
+    """xn: (B, 9) standardised features -> (out (B, 21), cache)."""
+    p = unpack(theta)
+    x = _pad_in(xn)
+    h1 = np.tanh(x @ p["W1"].T + p["b1"])
+    h2 = np.tanh(h1 @ p["W2"].T + p["b2"])
+    out = h2 @ p["W3"].T + p["b3"]
+    return out[:, :NOUT], (x, h1, h2)
+
+
+def forward16(theta, xn):
+    """forward() with the FP16 roundings of the matrix-core path: inputs,
+    weights and hidden activations rounded to binary16, products summed
+    exactly (FP64), biases and tanh in FP64."""
+    p = unpack(theta)
+    r = lambda a: np.asarray(a, dtype=np.float64).astype(np.float16).astype(np.float64)
+    x = r(_pad_in(xn))
+    h1 = r(np.tanh(x @ r(p["W1"]).T + p["b1"]))
+    h2 = r(np.tanh(h1 @ r(p["W2"]).T + p["b2"]))
+    out = h2 @ r(p["W3"]).T + p["b3"]
+    return out[:, :NOUT]
+
+
+def loss_and_grad(theta, xn, yn):
+    """L = mean over the B x 21 entries of (out - yn)^2 and dL/dtheta
+    (packed, zero on the padding)."""
+    p = unpack(theta)
+    out, (x, h1, h2) = forward(theta, xn)
+    B = len(xn)
+    diff = out - yn
+    L = float(np.mean(diff * diff))
+    g3 = np.zeros((B, KOUT))
+    g3[:, :NOUT] = 2.0 * diff / (B * NOUT)
+    g = {"W3": g3.T @ h2, "b3": g3.sum(0)}
+    gz2 = (g3 @ p["W3"]) * (1.0 - h2 * h2)
+    g["W2"] = gz2.T @ h1
+    g["b2"] = gz2.sum(0)
+    gz1 = (gz2 @ p["W2"]) * (1.0 - h1 * h1)
+    g["W1"] = gz1.T @ x
+    g["W1"][:, NIN:] = 0.0
+    g["b1"] = gz1.sum(0)
+    return L, pack(g)
+
+
+def adam_step(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, Algorithm 1), t = 1, 2, ...; returns
+    (theta, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def predict(net, F, fp16=True):
+    """Targets predicted for features F (m, 9) by net (dict with theta,
+    mx, sx, mt, st)."""
+    xn = (F - net["mx"]) / net["sx"]
+    out = forward16(net["theta"], xn) if fp16 else forward(net["theta"], xn)[0]
+    return out * net["st"] + net["mt"]
+
+
+# ------------------------------------------------------- certification --
+
+def _bin(v, edges):
+    return int(sum(1 for e in edges if v >= e))
+
+
+def rbin_of_features(F):
+    """Distance bin of each pair from its features: centroid distance in
+    the first triangle's frame (whose longest edge, the larger of the
+    two, has length 1)."""
+    cx = (1.0 + F[:, 0]) / 3.0
+    cy = F[:, 1] / 3.0
+    tx = (F[:, 2] + F[:, 4] + F[:, 6]) / 3.0
+    ty = (F[:, 3] + F[:, 5] + F[:, 7]) / 3.0
+    d2 = (tx - cx) ** 2 + (ty - cy) ** 2
+    return np.array([_bin(v, [e * e for e in RBIN_EDGES]) for v in d2])
+
+
+def sbin(s):
+    return _bin(s, SBIN_EDGES)
+
+
+def certify(tpred, t, F):
+    """Bound table (NRB x NSB): SAFETY times the largest |tpred - t| over
+    the pairs of each bin; infinite for bins with fewer than MIN_BIN
+    pairs."""
+    err = np.abs(tpred - t).max(1)
+    rb = rbin_of_features(F)
+    sb = np.array([sbin(v) for v in F[:, 8]])
+    B = np.full((NRB, NSB), np.inf)
+    for i in range(NRB):
+        for j in range(NSB):
+            mk = (rb == i) & (sb == j)
+            if mk.sum() >= MIN_BIN:
+                B[i, j] = SAFETY * err[mk].max()
+    return B
+
+
+# ------------------------------------------------- surrogate assembly --
+
+def band_pairs(mesh, theta, nsur):
+    """Separated pairs of order class < nsur: (m, 4) int64 rows (K, Kt,
+    class, distance bin)."""
+    V = np.ascontiguousarray(mesh["verts"], dtype=np.float64).reshape(-1)
+    Cc = np.ascontiguousarray(mesh["cells"], dtype=np.int32).reshape(-1)
+    nc = Cc.size // 3
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    re = np.ascontiguousarray(RBIN_EDGES, dtype=np.float64)
+    f = O.lib().orc_band_pairs
+    f.restype = C.c_int64
+    args = (O._dp(V), C.c_int64(nc), Cc.ctypes.data_as(C.c_void_p), C.c_int(len(th)), O._dp(th),
+            C.c_int(nsur), C.c_int(len(re)), O._dp(re))
+    n = f(*args, C.c_int64(0), None)
+    out = np.zeros((max(n, 1), 4), dtype=np.int64)
+    f(*args, C.c_int64(n), out.ctypes.data_as(C.c_void_p))
+    return out[:n]
+
+
+def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True, full=False):
+    """A^s on the DOF set with the band pairs (order class < nsur) done by
+    the surrogate where certified (features inside net['lo'] .. net['hi']
+    and net['bound'][distance bin, s bin] <= tol), by the exact rule of
+    their class otherwise.  Returns (A, dofs, n_surrogate, n_fallback);
+    full=True: A over all nodes instead."""
+    Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur)
+    V = np.asarray(mesh["verts"], dtype=np.float64)
+    Cc = np.asarray(mesh["cells"], dtype=np.int64)
+    P = band_pairs(mesh, orders.theta, nsur)
+    Cd = O.cdn(2, s)
+    X = V[Cc[P[:, 0]]].reshape(-1, 6)
+    Y = V[Cc[P[:, 1]]].reshape(-1, 6)
+    m = len(P)
+    F = features(X, Y, np.full(m, s)) if m else np.zeros((0, 9))
+    inbox = np.all((F >= net["lo"]) & (F <= net["hi"]), axis=1) if m else np.zeros(0, bool)
+    use = inbox & (net["bound"][P[:, 3], sbin(s)] <= tol) if m else inbox
+    # values in canonical order for the surrogate pairs, as given otherwise
+    vals = np.zeros((m, 21))
+    if use.any():
+        idx = np.nonzero(use)[0]
+        Kc, Tc = canonical_pairs(X[idx], Y[idx])
+        tp = predict(net, F[idx], fp16=fp16)
+        vals[idx] = integrals_many(s, 2, Kc, Tc) * (1.0 + tp)
+    for c in range(nsur):
+        idx = np.nonzero(~use & (P[:, 2] == c))[0]
+        if len(idx):
+            vals[idx] = integrals_many(s, orders.k_far[c], X[idx], Y[idx])
+    for i in range(m):
+        gK, gT = Cc[P[i, 0]], Cc[P[i, 1]]
+        if use[i]:
+            swap, pK, pT = canonical(X[i], Y[i])
+            F1, F2 = (gT, gK) if swap else (gK, gT)
+            g1 = [F1[j] for j in pK]
+            g2 = [F2[j] for j in pT]
+        else:
+            g1, g2 = list(gK), list(gT)
+        v = vals[i]
+        for q, (a, b) in enumerate(SYM):
+            for (u, w) in {(a, b), (b, a)}:
+                Afull[g1[u], g1[w]] += Cd * v[q]
+                Afull[g2[u], g2[w]] += Cd * v[6 + q]
+        for a in range(3):
+            for b in range(3):
+                x = Cd * v[12 + 3 * a + b]
+                Afull[g1[a], g2[b]] -= x
+                Afull[g2[b], g1[a]] -= x
+    dofs = O.dof_nodes(len(V), np.asarray(mesh["bfacets"]), s, mode)
+    A = Afull if full else Afull[np.ix_(dofs, dofs)]
+    return A, dofs, int(use.sum()), int((~use).sum())

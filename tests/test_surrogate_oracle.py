@@ -1,0 +1,233 @@
+"""Pins of the CPU reference for the learned pair-integral surrogate
+(``oracle/surrogate.py``) against facts that do not come from itself:
+invariances of the learned quantity, sum rules of the pair integrals,
+convergence of the exact rule, central differences for the gradient, the
+small-weight linearisation of the network, Adam's first step and the
+reduction of the surrogate assembly to plain quadrature."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import surrogate as S
+from paper_1708_03912_amd import meshgen as M
+from paper_1708_03912_amd import pairgen as G
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    return G.sample_pairs(11, 64)
+
+
+def _similar(P, rng, R, t, lam):
+    Q = P.reshape(3, 2) @ R.T * lam + t
+    return Q[rng.permutation(3)].ravel()
+
+
+def test_layout_matches_generator():
+    assert S.NPARAM == G.n_params()
+    assert S.LAYOUT == G.param_layout()
+
+
+def test_features_and_targets_invariant(pairs):
+    """t = I/Q2 - 1 and the canonical features do not change under
+    rotation, translation, uniform scaling, vertex relabelling and
+    exchange of the two triangles."""
+    X, Y, s = pairs
+    X, Y, s = X[:16], Y[:16], s[:16]
+    F0, t0 = S.dataset(X, Y, s)
+    rng = np.random.default_rng(5)
+    X2, Y2 = np.empty_like(X), np.empty_like(Y)
+    for i in range(len(X)):
+        a = rng.uniform(0, 2 * math.pi)
+        R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+        t = rng.uniform(-3, 3, 2)
+        lam = math.exp(rng.uniform(-2, 2))
+        A, B = _similar(X[i], rng, R, t, lam), _similar(Y[i], rng, R, t, lam)
+        if i % 2:
+            A, B = B, A
+        X2[i], Y2[i] = A, B
+    F1, t1 = S.dataset(X2, Y2, s)
+    assert np.abs(F1 - F0).max() < 1e-11
+    assert np.abs(t1 - t0).max() < 1e-9
+
+
+def test_canonical_frame(pairs):
+    """First triangle: longest edge (0,0)-(1,0), apex above; it is the
+    larger of the two."""
+    X, Y, s = pairs
+    F = S.features(X, Y, s)
+    assert np.all(F[:, 1] > 0)
+    assert np.all(F[:, 0] >= -1e-12) and np.all(F[:, 0] <= 1 + 1e-12)
+    assert np.all(F[:, 0] ** 2 + F[:, 1] ** 2 <= 1 + 1e-12)
+    assert np.all((F[:, 0] - 1) ** 2 + F[:, 1] ** 2 <= 1 + 1e-12)
+    T = F[:, 2:8].reshape(-1, 3, 2)
+    L = ((T[:, [1, 2, 0]] - T) ** 2).sum(-1)
+    assert np.all(L.max(1) <= 1 + 1e-12)
+    assert np.all(np.abs(L[:, 0] - L.max(1)) < 1e-12)
+    cr = (T[:, 1, 0] - T[:, 0, 0]) * (T[:, 2, 1] - T[:, 0, 1]) - (T[:, 1, 1] - T[:, 0, 1]) * (T[:, 2, 0] - T[:, 0, 0])
+    assert np.all(cr > 0)
+
+
+def test_pair_integral_sum_rules(pairs):
+    """sum_ab l_a l_b = 1 on each triangle: the full 3x3 sums of SK, ST and
+    X all equal int int k; with l_a summing to 1, row sums of X equal the
+    first moments, which the symmetric blocks give as row sums too."""
+    X, Y, s = pairs
+    for k in (2, 5):
+        I = S.integrals_many(s, k, X, Y)
+        SK, ST, Xc = I[:, :6], I[:, 6:12], I[:, 12:].reshape(-1, 3, 3)
+        full = lambda v: v[:, 0] + v[:, 3] + v[:, 5] + 2 * (v[:, 1] + v[:, 2] + v[:, 4])
+        tot = Xc.sum((1, 2))
+        assert np.allclose(full(SK), tot, rtol=1e-13) and np.allclose(full(ST), tot, rtol=1e-13)
+        rowK = np.stack([SK[:, 0] + SK[:, 1] + SK[:, 2], SK[:, 1] + SK[:, 3] + SK[:, 4],
+                         SK[:, 2] + SK[:, 4] + SK[:, 5]], 1)
+        colT = np.stack([ST[:, 0] + ST[:, 1] + ST[:, 2], ST[:, 1] + ST[:, 3] + ST[:, 4],
+                         ST[:, 2] + ST[:, 4] + ST[:, 5]], 1)
+        assert np.allclose(rowK, Xc.sum(2), rtol=1e-13)
+        assert np.allclose(colT, Xc.sum(1), rtol=1e-13)
+        assert np.all(I > 0)
+
+
+def test_exact_targets_converged(pairs):
+    """Order 8 (the training targets) agrees with order 16 to 1e-6 on the
+    band pairs: the learned quantity is the rule-independent integral."""
+    X, Y, s = pairs
+    Kc, Tc = S.canonical_pairs(X, Y)
+    I8 = S.integrals_many(s, 8, Kc, Tc)
+    I16 = S.integrals_many(s, 16, Kc, Tc)
+    assert np.abs(I8 / I16 - 1).max() < 1e-6
+
+
+def test_gradient_central_differences():
+    rng = np.random.default_rng(3)
+    theta = G.glorot_params(4)
+    p = S.unpack(theta)
+    p["b1"][:] = rng.normal(0, 0.1, S.NH)
+    p["b2"][:] = rng.normal(0, 0.1, S.NH)
+    p["b3"][:S.NOUT] = rng.normal(0, 0.1, S.NOUT)
+    xn = rng.normal(size=(8, S.NIN))
+    yn = rng.normal(size=(8, S.NOUT))
+    L, g = S.loss_and_grad(theta, xn, yn)
+    live = [i for i in range(S.NPARAM) if g[i] != 0.0]
+    pad = [i for i in range(S.NPARAM) if i not in set(live)]
+    idx = rng.choice(live, 300, replace=False)
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (S.loss_and_grad(tp, xn, yn)[0] - S.loss_and_grad(tm, xn, yn)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])) + 1e-9
+    # padding (W1 columns >= 9, W3 rows >= 21, b3 >= 21) gets no gradient
+    o = S.unpack(g)
+    assert np.all(o["W1"][:, S.NIN:] == 0) and np.all(o["W3"][S.NOUT:] == 0) and np.all(o["b3"][S.NOUT:] == 0)
+
+
+def test_forward_small_weight_linearisation():
+    """tanh(z) = z + O(z^3): with weights eps*W and zero biases the network
+    is eps^3 W3 W2 W1 x up to relative O(eps^2)."""
+    rng = np.random.default_rng(8)
+    theta = G.glorot_params(9)
+    xn = rng.normal(size=(5, S.NIN))
+    eps = 1e-3
+    out, _ = S.forward(eps * theta, xn)
+    p = S.unpack(theta)
+    lin = (eps ** 3) * (xn @ p["W1"][:, :S.NIN].T @ p["W2"].T @ p["W3"][:S.NOUT].T)
+    assert np.abs(out - lin).max() <= 1e-5 * np.abs(lin).max()
+
+
+def test_adam_first_step_is_lr_sign():
+    """With zero moments the bias-corrected first Adam step moves every
+    parameter with nonzero gradient by lr in the direction of -sign(g)."""
+    rng = np.random.default_rng(1)
+    th = rng.normal(size=50)
+    g = rng.normal(size=50)
+    t2, m, v = S.adam_step(th, np.zeros(50), np.zeros(50), g, 1, 1e-3)
+    assert np.allclose(t2 - th, -1e-3 * np.sign(g), rtol=1e-4)
+    # a 1D quadratic is minimised
+    x, m, v = np.array([3.0]), np.zeros(1), np.zeros(1)
+    for t in range(1, 3001):
+        x, m, v = S.adam_step(x, m, v, 2 * (x - 1.0), t, 1e-2)
+    assert abs(x[0] - 1.0) < 1e-3
+
+
+def test_fp16_forward_close_to_fp64():
+    rng = np.random.default_rng(2)
+    theta = G.glorot_params(2)
+    xn = rng.normal(size=(64, S.NIN))
+    a = S.forward(theta, xn)[0]
+    b = S.forward16(theta, xn)
+    assert np.abs(a - b).max() < 5e-3 * max(1.0, np.abs(a).max())
+
+
+def test_certify_table():
+    rng = np.random.default_rng(4)
+    X, Y, s = G.sample_pairs(6, 600)
+    F = S.features(X, Y, s)
+    t = rng.normal(size=(600, 21)) * 1e-3
+    err = np.exp(rng.uniform(-12, -4, 600))
+    tp = t.copy()
+    tp[np.arange(600), rng.integers(0, 21, 600)] += err
+    B = S.certify(tp, t, F)
+    rb = S.rbin_of_features(F)
+    sb = np.array([S.sbin(v) for v in s])
+    for i in range(S.NRB):
+        for j in range(S.NSB):
+            mk = (rb == i) & (sb == j)
+            if mk.sum() >= S.MIN_BIN:
+                assert B[i, j] == pytest.approx(S.SAFETY * err[mk].max(), rel=1e-12)
+            else:
+                assert np.isinf(B[i, j])
+
+
+def _zero_net(lo=-1e300, hi=1e300, bound=0.0):
+    return {"theta": np.zeros(S.NPARAM), "mx": np.zeros(9), "sx": np.ones(9), "mt": np.zeros(21),
+            "st": np.ones(21), "lo": np.full(9, lo), "hi": np.full(9, hi),
+            "bound": np.full((S.NRB, S.NSB), bound)}
+
+
+def _canonical_cells(mesh):
+    """the mesh with every cell's vertices in the surrogate's canonical
+    per-triangle order"""
+    V = np.asarray(mesh["verts"])
+    cells = np.array([[c[j] for j in S._canon_tri(V[c])] for c in np.asarray(mesh["cells"])])
+    return dict(mesh, cells=cells.astype(np.int32))
+
+
+@pytest.mark.parametrize("s", [0.3, 0.75])
+def test_surrogate_assembly_reduces_to_quadrature(s):
+    """Zero correction, everything certified: the band pairs get exactly
+    the order-2 rule on the canonically ordered triangles (the tensor rule
+    is symmetric under exchanging the two triangles, not under relabelling
+    a triangle's vertices); this pins the relabelling and the placement of
+    the 21 values.  Nothing certified (bound infinite, or the box empty):
+    the plain assembly."""
+    mesh = M.disk_for_cells(300, seed=4)
+    o = O.Orders(6, 6, [1.5, 3.0, 6.0], [4, 3, 2, 2], [4, 3, 2, 2])
+    o2 = O.Orders(6, 6, [1.5, 3.0, 6.0], [2, 2, 2, 2], [4, 3, 2, 2])
+    rest, _ = O.assemble_full(mesh, s, o, far_skip_below=2)
+    As, _, nsur, nfb = S.assemble_surrogate(mesh, s, o, _zero_net(), 2, 1e-3, full=True)
+    assert nsur > 0 and nfb == 0
+    mc = _canonical_cells(mesh)
+    band = O.assemble_full(mc, s, o2, which=1)[0] - O.assemble_full(mc, s, o2, which=1, far_skip_below=2)[0]
+    fin = np.isfinite(rest)  # s >= 1/2: boundary-node entries of the boundary term diverge
+    assert np.array_equal(fin, np.isfinite(As))
+    assert np.abs((As - rest - band)[fin]).max() <= 1e-12 * np.abs(band).max()
+    A4, d4, _ = O.assemble(mesh, s, o)
+    Af, df, nsur, nfb = S.assemble_surrogate(mesh, s, o, _zero_net(bound=np.inf), 2, 1e-3)
+    assert nsur == 0 and nfb > 0 and np.array_equal(d4, df)
+    assert np.abs(Af - A4).max() <= 1e-12 * np.abs(A4).max()
+    Ab, _, nsur, _ = S.assemble_surrogate(mesh, s, o, _zero_net(lo=1e300), 2, 1e-3)
+    assert nsur == 0 and np.abs(Ab - A4).max() <= 1e-12 * np.abs(A4).max()
+
+
+def test_band_pairs_match_class_counts():
+    mesh = M.disk_for_cells(300, seed=4)
+    o = O.Orders(6, 6, [1.5, 3.0, 6.0], [4, 3, 2, 2], [4, 3, 2, 2])
+    _, cnt = O.assemble_full(mesh, 0.5, o)
+    P = S.band_pairs(mesh, o.theta, 2)
+    assert (P[:, 2] == 0).sum() == cnt[0] and (P[:, 2] == 1).sum() == cnt[1]
+    # class 0/1 = centroid distance below 3 max(h): distance bins 0..4
+    assert P[:, 3].max() <= 4
