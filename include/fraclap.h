@@ -75,6 +75,13 @@ extern "C" {
 #define FL_MAX_ORDER_FAR 8  /* largest order for separated pairs             */
 #define FL_MAX_ORDER_TOUCH 16 /* largest order for touching pairs            */
 
+#define FL_SUR_NIN 9        /* surrogate features                             */
+#define FL_SUR_NOUT 21      /* surrogate outputs (pair integrals)             */
+#define FL_SUR_NPARAM 8352  /* packed network parameters                      */
+#define FL_SUR_NRB 6        /* certification distance bins                    */
+#define FL_SUR_NSB 4        /* certification s bins                           */
+#define FL_SUR_BLOB 8454    /* doubles in a parameter blob                    */
+
 typedef struct fl_handle fl_handle;
 
 /* Quadrature orders (App. B).  A separated pair (K,Kt) -- no common vertex --
@@ -106,6 +113,19 @@ typedef struct {
                                             an FP32 copy of A drives an
                                             inner FP32 Jacobi-PCG inside
                                             FP64 iterative refinement     */
+    int surrogate;                       /* 0 (default): off.  0 < c <=
+                                            n_classes (2D only): separated
+                                            pairs of the classes
+                                            0 .. c-1 go to the learned
+                                            surrogate (fl_surrogate_*):
+                                            order-2 rule times the
+                                            network's correction where the
+                                            pair is certified, the exact
+                                            rule of its class elsewhere  */
+    double sur_tol;                      /* certified bound (relative error
+                                            of each pair integral) a
+                                            distance bin must meet to use
+                                            the network (default 1e-2)     */
 } fl_opts;
 
 typedef struct {
@@ -127,6 +147,8 @@ typedef struct {
     double last_relres;
     int32_t last_outer;       /* FP64 refinement steps of the last solve
                                  (fl_solve_batch: residual replacements)   */
+    int64_t pairs_surrogate;  /* band pairs done by the network             */
+    int64_t pairs_fallback;   /* band pairs that kept the exact rule        */
 } fl_stats_t;
 
 /* Default orders (the calibrated table: k_touch = k_touch_bnd = 6,
@@ -297,6 +319,103 @@ typedef struct {
  * configuration order; *n_out receives the count, *best the index of the
  * chosen one. */
 int fl_autotune(fl_handle *h, int dtype, fl_tune_entry *out, int max_out, int *n_out, int *best);
+
+/* ------------------------------------------------------------------------
+ * Learned pair-integral surrogate.
+ *
+ * For a separated pair of triangles (Sec. 5 decomposition, no common
+ * vertex) the assembly needs 21 integrals over K x Kt of l_a(x) l_b(x) k,
+ * l_a(y) l_b(y) k (a <= b, order 00 01 02 11 12 22) and l_a(x) l_b(y) k
+ * (row-major), k = |x - y|^{-2-2s}, l the barycentric coordinates.  App. B
+ * raises the Gauss order as pairs get closer; the surrogate keeps the
+ * cheapest rule, order 2, and a 9-64-64-21 tanh network predicts its
+ * relative error t = I / Q2 - 1 of each integral from the pair's canonical
+ * form:
+ *   * the triangle with the larger squared longest edge comes first (equal:
+ *     the one whose lexicographically smallest vertex is smaller);
+ *   * each triangle is ordered (a, b, c) with ab a longest edge (several:
+ *     the one whose opposite vertex is lexicographically smallest) and c
+ *     to the left of a -> b;
+ *   * features: c of the first triangle and the three vertices of the
+ *     second in the first's frame (origin a, x axis b - a, unit |b - a|),
+ *     then s.
+ * Network: inputs and targets standardised (means mx, mt; deviations sx,
+ * st); W1 64x32 (columns >= 9 zero), b1, W2 64x64, b2, W3 32x64 (rows >= 21
+ * zero), b3 (32, entries >= 21 zero), packed in that order (row-major);
+ * tanh after layers 1 and 2.  Inference and training run on the FP16
+ * matrix cores with FP32 accumulation; master weights FP32, Adam.
+ * Certification: bound[rb][sb] = 1.25 x the largest |t_pred - t| over
+ * held-out pairs in distance bin rb (centroid distance over the larger
+ * longest edge, edges 1, 1.5, 2, 2.5, 3) and s bin sb (edges 0.25, 0.5,
+ * 0.75), infinite below 32 pairs; a pair uses the network only if its
+ * features lie in the box of the training features and its bin's bound at
+ * the assembly's s is <= fl_opts.sur_tol.
+ *
+ * Parameter blob (FL_SUR_BLOB doubles): packed parameters, mx[9], sx[9],
+ * mt[21], st[21], box lo[9], hi[9], bound[FL_SUR_NRB][FL_SUR_NSB].
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    int steps;            /* Adam steps                                     */
+    int batch;            /* samples per step, multiple of 64               */
+    double lr, lr_min;    /* cosine schedule from lr to lr_min              */
+    double beta1, beta2, eps;
+    uint64_t seed;        /* minibatch sampling                             */
+} fl_train_opts;
+
+/* steps 20000, batch 1024, lr 3e-3, lr_min 1e-5, beta 0.9 / 0.999, eps
+ * 1e-8, seed 1. */
+int fl_default_train_opts(fl_train_opts *out);
+
+/* The 21 integrals of m separated triangle pairs with the order-k collapsed
+ * Gauss rule on both triangles (k in 1..8), vertex order as given.  X, Y:
+ * device m x 6 (x0 y0 x1 y1 x2 y2), s: device m, out: device m x 21.
+ * Caller-owned; asynchronous on the handle's stream. */
+int fl_pair_integrals(fl_handle *h, int64_t m, const double *X, const double *Y, const double *s, int k,
+                      double *out);
+
+/* Training data: canonical features (device m x 9) and targets t = I_k /
+ * Q2 - 1 (device m x 21, canonical order, I_k with the order-k rule, k in
+ * 3..8) of m separated pairs (device X, Y, s as fl_pair_integrals). */
+int fl_surrogate_dataset(fl_handle *h, int64_t m, const double *X, const double *Y, const double *s,
+                         int k_exact, double *feats, double *targets);
+
+/* Fresh network: Glorot-uniform weights from a splitmix64 stream seeded by
+ * seed, zero biases, zero Adam state; no scaling (fl_surrogate_fit_scaling
+ * or fl_surrogate_set_params must follow) and no certified bin. */
+int fl_surrogate_init(fl_handle *h, uint64_t seed);
+
+/* Standardisation and box from training data (device feats m x 9, targets
+ * m x 21): means, population deviations (floored at 1e-12), feature
+ * minima / maxima.  Synchronises the stream. */
+int fl_surrogate_fit_scaling(fl_handle *h, const double *feats, const double *targets, int64_t m);
+
+/* Parameter blob in / out (host, FL_SUR_BLOB doubles).  set_params
+ * resets the Adam state; parameters are held in FP32. */
+int fl_surrogate_set_params(fl_handle *h, const double *blob);
+int fl_surrogate_get_params(fl_handle *h, double *blob);
+
+/* Full-batch loss L = mean over the m x 21 standardised entries of
+ * (out - y)^2 and its gradient (host grad: FL_SUR_NPARAM floats, may be
+ * NULL; host loss, may be NULL), computed by the FP16 forward / backward
+ * kernels.  Synchronises the stream. */
+int fl_surrogate_grad(fl_handle *h, const double *feats, const double *targets, int64_t m, float *grad,
+                      double *loss);
+
+/* Adam training on m samples (device feats / targets) with random
+ * minibatches; loss_hist (host, opts->steps doubles, may be NULL) receives
+ * each step's minibatch loss.  Needs scaling.  Synchronises the stream. */
+int fl_surrogate_train(fl_handle *h, const double *feats, const double *targets, int64_t m,
+                       const fl_train_opts *opts, double *loss_hist);
+
+/* Predicted targets t (device out m x 21) for device features m x 9. */
+int fl_surrogate_predict(fl_handle *h, const double *feats, int64_t m, double *out);
+
+/* Certification table from held-out data (device feats / targets):
+ * replaces the handle's bound table; bound (host, FL_SUR_NRB x FL_SUR_NSB,
+ * may be NULL) receives it.  Synchronises the stream. */
+int fl_surrogate_certify(fl_handle *h, const double *feats, const double *targets, int64_t m,
+                         double *bound);
 
 #ifdef __cplusplus
 }

@@ -146,6 +146,10 @@ int check_opts(fl_handle* h, const fl_opts& o) {
         if (o.k_far[m] < 1 || o.k_far[m] > FL_MAX_ORDER_FAR || o.k_far_bnd[m] < 1 ||
             o.k_far_bnd[m] > FL_MAX_ORDER_FAR)
             return fail(h, FL_EINVAL, "separated-pair orders must lie in 1..8");
+    if (o.surrogate < 0 || o.surrogate > o.n_classes)
+        return fail(h, FL_EINVAL, "surrogate must lie in 0..n_classes (the last class stays exact)");
+    if (o.surrogate > 0 && h->dim != 2) return fail(h, FL_EINVAL, "the surrogate is for triangle meshes (dim 2)");
+    if (!(o.sur_tol >= 0.0)) return fail(h, FL_EINVAL, "sur_tol must be >= 0");
     for (int m = 0; m < o.n_classes; ++m) {
         if (!(o.theta[m] > 0.0) || !std::isfinite(o.theta[m]))
             return fail(h, FL_EINVAL, "theta must be positive and finite");
@@ -224,6 +228,7 @@ int fl_default_opts(fl_opts* out) {
     out->with_boundary = 1;
     out->k_touch = 6;
     out->k_touch_bnd = 6;
+    out->sur_tol = 1e-2;
     out->n_classes = 3;
     out->theta[0] = 1.5;
     out->theta[1] = 3.0;
@@ -257,6 +262,7 @@ void fl_destroy(fl_handle* h) {
     else (void)hipDeviceSynchronize();
     free_buffers(h);
     free_solver(h);
+    fl_sur_free(h);
     delete h;
 }
 
@@ -585,7 +591,7 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         if (p.bytes) std::memcpy(h->pin + p.off, p.src, p.bytes);
     if ((rc = ensure_dev(h, &h->plan, &h->plan_cap, pk.total))) return rc;
     if ((rc = ensure_dev(h, &h->dS, &h->S_cap, sizeof(double) * (size_t)T * 6))) return rc;
-    if (!h->dcnt) HIPCHK(hipMalloc((void**)&h->dcnt, sizeof(unsigned long long) * 16));
+    if (!h->dcnt) HIPCHK(hipMalloc((void**)&h->dcnt, sizeof(unsigned long long) * 32));
     HIPCHK(hipMemcpyAsync(h->plan, h->pin, pk.total, hipMemcpyHostToDevice, h->stream));
     char* base = h->plan;
     auto dv = [&](size_t off) { return (void*)(base + off); };
@@ -641,7 +647,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(upload_rules(R, h->stream));
     launch_zero(A, a_elems, h->stream);
     launch_zero(dS, T * 6, h->stream);
-    launch_zero((double*)dcnt, 16, h->stream);
+    launch_zero((double*)dcnt, 32, h->stream);
 
     hipEvent_t ev[5];
     for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -673,8 +679,37 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     FP.S = dS;
     FP.cls_count = dcnt;
     FP.mixed = o.precision == FL_MIXED ? 1 : 0;
+    // surrogate band: near tiles list the pairs of classes < o.surrogate
+    long long band_cap = 0;
+    BandParams BDP{};
+    if (o.surrogate > 0) {
+        if ((rc = fl_sur_band_params(h, s, o, &BDP))) return rc;
+        if (h->sur.band_cap < sizeof(int2) * (size_t)std::max<int64_t>(1 << 20, 160 * T)) {
+            if ((rc = ensure_dev(h, &h->sur.band, &h->sur.band_cap,
+                                 sizeof(int2) * (size_t)std::max<int64_t>(1 << 20, 160 * T))))
+                return rc;
+        }
+        band_cap = (long long)(h->sur.band_cap / sizeof(int2));
+        FP.nsur = o.surrogate;
+        FP.band = h->sur.band;
+        FP.band_count = dcnt + 14;
+        FP.band_cap = band_cap;
+    }
     launch_far(E, FP, h->stream);
     HIPCHK(hipGetLastError());
+    if (o.surrogate > 0) {
+        BDP.list = h->sur.band;
+        BDP.count = dcnt + 14;
+        BDP.cap = band_cap;
+        BDP.pe = pe;
+        BDP.C = C;
+        BDP.A = A;
+        BDP.lda = lda;
+        BDP.S = dS;
+        BDP.counters = dcnt + 12;
+        launch_band(E, BDP, FP.mixed, h->stream);
+        HIPCHK(hipGetLastError());
+    }
     {
         FarParams FF = FP;
         FF.tiles = (const int2*)dv(o_ft);
@@ -741,6 +776,14 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ph[i], ev[i], ev[i + 1]));
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    unsigned long long cnt2[16];
+    HIPCHK(hipMemcpy(cnt2, dcnt + 16, sizeof(cnt2), hipMemcpyDeviceToHost));
+    if (o.surrogate > 0 && (long long)cnt[14] > band_cap) {
+        // the band list overflowed: grow it to fit and assemble again
+        if ((rc = ensure_dev(h, &h->sur.band, &h->sur.band_cap, sizeof(int2) * (size_t)(cnt[14] + cnt[14] / 4 + 1024))))
+            return rc;
+        return run_assembly(h, P, s, o, A, lda, a_elems, A32, st);
+    }
 
     fl_stats_t& S = *st;
     S.n = n;
@@ -753,14 +796,20 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     for (int m = 0; m <= FL_MAX_CLASSES; ++m) S.pairs_far[m] = m <= o.n_classes ? (int64_t)cnt[m] : 0;
     S.pairs_bnd_touch = (int64_t)cnt[10];
     S.pairs_bnd_far = (int64_t)cnt[11];
+    S.pairs_surrogate = o.surrogate > 0 ? (int64_t)cnt[12] : 0;
+    S.pairs_fallback = o.surrogate > 0 ? (int64_t)cnt[13] : 0;
     // kernel evaluations by the rules in use
     {
         int64_t ev2 = 0;
         const int kT = o.k_touch, kB = o.k_touch_bnd;
         for (int m = 0; m <= o.n_classes; ++m) {
             int64_t q = dim == 2 ? (int64_t)o.k_far[m] * o.k_far[m] : o.k_far[m];
-            ev2 += S.pairs_far[m] * q * q;
+            // band classes: order 2 for the surrogate pairs, the class order
+            // for the fallbacks (counted per class by the band kernel)
+            int64_t np = m < o.surrogate ? (int64_t)cnt2[m] : S.pairs_far[m];
+            ev2 += np * q * q;
         }
+        if (o.surrogate > 0) ev2 += S.pairs_surrogate * 16 * 16;
         if (dim == 2) {
             ev2 += T * 3 * kT + S.pairs_edge * 4 * kT * kT + S.pairs_vertex * 2 * kT * kT * kT;
             ev2 += S.pairs_bnd_touch * 6 * kB * 2;  // upper bound per touching facet pair
@@ -793,6 +842,8 @@ bool fits(fl_handle* h, double bytes) {
 }
 
 }  // namespace
+
+const fl::RuleTables& fl_base_rules() { return base_rules(); }
 
 extern "C" {
 

@@ -29,6 +29,29 @@ struct fl_batch {
     int* hflag = nullptr;                   // pinned host word (active count)
 };
 
+// Pair-integral surrogate: network, scaling, certification table and the
+// band-pair list of the assembly.
+struct fl_sur {
+    bool have = false;                      // parameters present
+    bool have_scaling = false;              // standardisation and box present
+    float* theta = nullptr;                 // FP32 master parameters (device)
+    float* m = nullptr;                     // Adam moments
+    float* v = nullptr;
+    long long adam_t = 0;
+    _Float16* half = nullptr;               // W1, W2, W3, W2T, W3T (device)
+    float* scal = nullptr;                  // mx, isx (9 each), mt, st (21 each) (device)
+    double mx[fl::SUR_NIN] = {}, sx[fl::SUR_NIN] = {}, mt[fl::SUR_NOUT] = {}, st[fl::SUR_NOUT] = {};
+    double lo[fl::SUR_NIN] = {}, hi[fl::SUR_NIN] = {};
+    double bound[fl::SUR_NRB * fl::SUR_NSB] = {};
+    float* part = nullptr;                  // training partial gradients
+    size_t part_cap = 0;
+    double* loss = nullptr;                 // per-step workgroup squared errors
+    size_t loss_cap = 0;
+    double* ws = nullptr;                   // statistics / certification scratch
+    int2* band = nullptr;                   // band pairs listed by the near tiles
+    size_t band_cap = 0;                    // bytes
+};
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -82,4 +105,12 @@ struct fl_handle {
 
     fl_stats_t st{};
     fl_batch B;
+    fl_sur sur;
 };
+
+// Band-kernel parameters for an assembly at s with options o (classes below
+// o.surrogate); FL_ESTATE without a network and scaling.  Defined with the
+// surrogate calls.
+const fl::RuleTables& fl_base_rules();
+int fl_sur_band_params(fl_handle* h, double s, const fl_opts& o, fl::BandParams* bp);
+void fl_sur_free(fl_handle* h);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/fraclap.h"
+#include "fl_sur.hpp"
 
 namespace fl {
 
@@ -62,6 +63,10 @@ struct FarParams {
     double* S;              // T x 6 per-element diagonal-block accumulators
     unsigned long long* cls_count;  // ncls+1 counters
     int mixed;              // 1: separated pairs evaluated in FP32
+    int nsur;               // > 0: pairs of class < nsur are listed, not computed
+    int2* band;             // the list (cap entries)
+    unsigned long long* band_count;
+    long long band_cap;
 };
 
 struct TouchParams {
@@ -321,5 +326,87 @@ struct LoadArgs {
     double* b;              // n x nrhs column-major
 };
 void launch_load(const LoadArgs& a, int kind, hipStream_t st);
+
+// ------------------------------------------------------------ surrogate --
+// FP16 weight copies written after every update
+struct SurHalves {
+    _Float16* W1;   // 64 x 32
+    _Float16* W2;   // 64 x 64
+    _Float16* W3;   // 32 x 64
+    _Float16* W2T;  // 64 x 64, W2T[j][k] = W2[k][j]
+    _Float16* W3T;  // 64 x 32, W3T[j][k] = W3[k][j]
+};
+
+struct SurTrain {
+    const double* F;        // m x 9 features
+    const double* T;        // m x 21 targets
+    long long m;
+    int mode;               // 0: 64 random samples per workgroup (seed, step); 1: samples base + ...
+    int batch;              // samples per step (mode 0)
+    unsigned long long seed;
+    long long step;
+    long long base;
+    SurNet N;
+    const _Float16* W2T;
+    const _Float16* W3T;
+    float* part;            // gridDim x SUR_NPARAM gradient partials
+    double* loss;           // gridDim partial sums of squared errors
+};
+void launch_sur_train(const SurTrain& A, int nwg, hipStream_t st);
+
+struct SurAdam {
+    float* theta;           // FP32 master parameters
+    float* m;
+    float* v;
+    const float* part;
+    int nwg;
+    float gscale;           // factor from the partial sums to dL/dtheta
+    int update;             // 0: only the gradient
+    float lr, b1, b2, eps, bc1, bc2;  // bc: 1 - beta^t
+    float* grad_out;        // optional FP32 gradient
+    SurHalves H;
+};
+void launch_sur_adam(const SurAdam& S, hipStream_t st);
+void launch_sur_halves(const float* theta, const SurHalves& H, hipStream_t st);
+
+struct SurPredict {
+    const double* F;
+    long long m;
+    SurNet N;
+    double* out;            // m x 21 predicted t (optional)
+    const double* T;        // optional targets: per-bin error maxima
+    unsigned int* emax_bits;  // SUR_NRB x SUR_NSB
+    unsigned int* count;
+};
+void launch_sur_predict(const SurPredict& P, hipStream_t st);
+// column sums (or, with mean, sums of squared deviations), minima, maxima
+void launch_sur_colstat(const double* X, long long m, int ncol, const double* mean, double* part, int nblk,
+                        double* out, hipStream_t st);
+
+// pair integrals (21 values, order k, vertex order as given) and the
+// training set (canonical features, t = I_k / Q2 - 1) of m separated pairs
+void launch_pair_integrals(const double* X, const double* Y, const double* s, long long m, int k,
+                           int canonical, double* out, double* feats, hipStream_t st);
+
+// Band pairs listed by the near-tile kernel, handled by the surrogate
+// where certified and by the exact rule of their class otherwise.
+struct BandParams {
+    const int2* list;       // (K, Kt) library element indices
+    const unsigned long long* count;  // entries written (may exceed cap)
+    long long cap;
+    double s, pe, C;
+    int ncls;
+    double th2[FL_MAX_CLASSES];
+    int kf[FL_MAX_CLASSES + 1];
+    int enabled;            // network usable
+    SurNet N;
+    double lo[SUR_NIN], hi[SUR_NIN];  // box of the training features
+    int use_rbin[SUR_NRB];  // distance bins certified at this s
+    double* A;
+    long long lda;
+    double* S;
+    unsigned long long* counters;  // [0] surrogate pairs, [1] fallback pairs
+};
+void launch_band(const ElemDev& E, const BandParams& P, int mixed, hipStream_t st);
 
 }  // namespace fl

@@ -504,6 +504,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ unsigned char pcls[BE * BE];
     __shared__ unsigned short plist[BE * BE];
     __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
+    __shared__ unsigned long long bbase;
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -590,8 +591,24 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
         plist[slot] = (unsigned short)pidx;
     }
     __syncthreads();
+    // classes below nsur (surrogate band): only listed for band_kernel
+    int c0 = 0;
+    if (P.nsur > 0) {
+        c0 = P.nsur < P.ncls + 1 ? P.nsur : P.ncls + 1;
+        const int nb = coff[c0];
+        if (tid == 0) bbase = nb ? atomicAdd(P.band_count, (unsigned long long)nb) : 0ull;
+        __syncthreads();
+        for (int sl = tid; sl < nb; sl += 256) {
+            const unsigned long long slot = bbase + (unsigned long long)sl;
+            if (slot < (unsigned long long)P.band_cap) {
+                const int pidx = plist[sl];
+                const int r = pidx / BE, l = pidx - r * BE;
+                P.band[slot] = make_int2(I0 + r, J0 + l);
+            }
+        }
+    }
     // one class at a time, one pair per thread
-    for (int c = 0; c <= P.ncls; ++c) {
+    for (int c = c0; c <= P.ncls; ++c) {
         const int k = P.kf[c];
         for (int base = coff[c]; base < coff[c + 1]; base += 256) {
             const int slot = base + tid;
@@ -1743,6 +1760,214 @@ void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) {
 
 void launch_cg32_final(const CgState32& s, int it, hipStream_t st) {
     hipLaunchKernelGGL(cg32_final_kernel, dim3(1), dim3(256), 0, st, s, it);
+}
+
+// ------------------------------------------------- surrogate band pairs --
+
+// Separated pairs of the band classes, one per thread (grid-stride over
+// chunks of 256 so every wave runs the network together).  Certified
+// pairs (features inside the training box, distance bin certified at this
+// s): order-2 rule on the canonical pair times (1 + t) from the network;
+// the others: the exact rule of their class.  Diagonal-block increments go
+// to the per-element accumulators S, off-diagonal blocks straight to A and
+// its mirror, all with atomics.
+template <int MIX>
+__global__ __launch_bounds__(256) void band_kernel(ElemDev E, BandParams P) {
+    __shared__ float outs[4][64 * 33];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+    long long n = (long long)*P.count;
+    if (n > P.cap) n = P.cap;
+    const double rb_e2[5] = {1.0, 2.25, 4.0, 6.25, 9.0};
+    unsigned long long nsur = 0, nfb = 0;
+    for (long long base = (long long)blockIdx.x * 256; base < n; base += (long long)gridDim.x * 256) {
+        const long long i = base + tid;
+        const bool valid = i < n;
+        int K = 0, Kt = 0, cls = 0, rb = 0;
+        double X[6] = {0, 0, 0, 0, 0, 0}, Y[6] = {0, 0, 0, 0, 0, 0};
+        if (valid) {
+            const int2 pr = P.list[i];
+            K = pr.x;
+            Kt = pr.y;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                X[c] = E.x[c][K];
+                Y[c] = E.x[c][Kt];
+            }
+            const double d2 = dist2_nc(E.cen[0][K], E.cen[1][K], E.cen[0][Kt], E.cen[1][Kt], 2);
+            const double hm = E.h2[K] > E.h2[Kt] ? E.h2[K] : E.h2[Kt];
+            cls = order_class(d2, hm, P.ncls, P.th2);
+            rb = order_class(d2, hm, 5, rb_e2);
+        }
+        // o1 / o2: vertex slots of the first / second element in the order
+        // of the computed blocks (canonical for the network, as stored for
+        // the exact rule)
+        int o1[3] = {0, 1, 2}, o2[3] = {0, 1, 2}, swap = 0;
+        double C1[6], C2[6], f[SUR_NIN];
+        bool sur = false;
+        if (valid && P.enabled) {
+            int c1[3], c2[3];
+            const int sw = sur_canon(X, Y, c1, c2, C1, C2);
+            sur_features(C1, C2, P.s, f);
+            bool in = true;
+#pragma unroll
+            for (int k = 0; k < SUR_NIN; ++k) in = in && f[k] >= P.lo[k] && f[k] <= P.hi[k];
+            sur = in && P.use_rbin[rb];
+            if (sur) {
+                swap = sw;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    o1[a] = c1[a];
+                    o2[a] = c2[a];
+                }
+            }
+        }
+        float xn[SUR_NIN];
+#pragma unroll
+        for (int k = 0; k < SUR_NIN; ++k) xn[k] = 0.f;
+        double SK[6], ST[6], O[9];
+        if (sur) {
+            sur_std_features(P.N, f, xn);
+            if (MIX) far_pair2_f32<2>(2, C1, C2, P.pe, SK, ST, O);
+            else far_pair2<2>(2, C1, C2, P.pe, SK, ST, O);
+        }
+        if (__any(sur)) {
+            unsigned int pk[5];
+            sur_pack_x(xn, pk);
+            float* ow = outs[wave];
+            for (int q = 0; q < 4; ++q) {
+                const h8 xb = sur_gather_x(pk, q);
+                SurAct a;
+                sur_forward16(P.N, xb, a);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) ow[(16 * q + r) * 33 + 16 * t + 4 * g + v] = a.out[t][v];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (sur) {
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    SK[j] *= 1.0 + ((double)ow[lane * 33 + j] * (double)P.N.st[j] + (double)P.N.mt[j]);
+                    ST[j] *= 1.0 + ((double)ow[lane * 33 + 6 + j] * (double)P.N.st[6 + j] + (double)P.N.mt[6 + j]);
+                }
+#pragma unroll
+                for (int j = 0; j < 9; ++j)
+                    O[j] *= 1.0 + ((double)ow[lane * 33 + 12 + j] * (double)P.N.st[12 + j] + (double)P.N.mt[12 + j]);
+            }
+        }
+        for (int c = 0; c < P.ncls + 1 && c < 12; ++c) {
+            const unsigned long long bal = __ballot(valid && !sur && cls == c);
+            if (lane == 0 && bal) atomicAdd(P.counters + 4 + c, (unsigned long long)__popcll(bal));
+        }
+        if (!valid) continue;
+        if (!sur) {
+            far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, SK, ST, O);
+            ++nfb;
+        } else {
+            ++nsur;
+        }
+        const int e1 = sur ? (swap ? Kt : K) : K, e2 = sur ? (swap ? K : Kt) : Kt;
+        const double fct = P.C * E.meas[K] * E.meas[Kt];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) {
+                const int q = sym3(a, b);
+                atomicAdd(&P.S[(long long)e1 * 6 + sym3(o1[a], o1[b])], fct * SK[q]);
+                atomicAdd(&P.S[(long long)e2 * 6 + sym3(o2[a], o2[b])], fct * ST[q]);
+            }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ga = E.dof[o1[a]][e1];
+            if (ga < 0) continue;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int gb = E.dof[o2[b]][e2];
+                if (gb < 0) continue;
+                const double v = -fct * O[3 * a + b];
+                atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+            }
+        }
+    }
+    // counters
+    for (int m = 32; m >= 1; m >>= 1) {
+        nsur += __shfl_xor(nsur, m, 64);
+        nfb += __shfl_xor(nfb, m, 64);
+    }
+    if (lane == 0) {
+        if (nsur) atomicAdd(P.counters, nsur);
+        if (nfb) atomicAdd(P.counters + 1, nfb);
+    }
+}
+
+void launch_band(const ElemDev& E, const BandParams& P, int mixed, hipStream_t st) {
+    if (P.cap <= 0) return;
+    long long blocks = (P.cap + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (mixed) hipLaunchKernelGGL(band_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, E, P);
+    else hipLaunchKernelGGL(band_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, E, P);
+}
+
+// Pair integrals of m separated triangle pairs with the order-k rule.
+// canonical = 0: the 21 integrals (areas included) in the given vertex
+// order; canonical = 1: features of the canonical form (feats) and the
+// relative error t = I_k / Q2 - 1 of the order-2 rule (out), both on the
+// canonical pair.
+__global__ __launch_bounds__(256) void pair_integrals_kernel(const double* X, const double* Y,
+                                                             const double* s, long long m, int k,
+                                                             int canonical, double* out, double* feats) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double x[6], y[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        x[c] = X[i * 6 + c];
+        y[c] = Y[i * 6 + c];
+    }
+    const double sv = s[i], pe = -(1.0 + sv);
+    double SK[6], ST[6], O[9];
+    double* o = out + i * 21;
+    if (!canonical) {
+        far_pair2<0>(k, x, y, pe, SK, ST, O);
+        auto area = [](const double* P) {
+            return 0.5 * fabs((P[2] - P[0]) * (P[5] - P[1]) - (P[3] - P[1]) * (P[4] - P[0]));
+        };
+        const double f = area(x) * area(y);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            o[j] = f * SK[j];
+            o[6 + j] = f * ST[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) o[12 + j] = f * O[j];
+        return;
+    }
+    int o1[3], o2[3];
+    double C1[6], C2[6], fe[SUR_NIN];
+    sur_canon(x, y, o1, o2, C1, C2);
+    sur_features(C1, C2, sv, fe);
+#pragma unroll
+    for (int j = 0; j < SUR_NIN; ++j) feats[i * SUR_NIN + j] = fe[j];
+    double SK2[6], ST2[6], O2[9];
+    far_pair2<0>(k, C1, C2, pe, SK, ST, O);
+    far_pair2<2>(2, C1, C2, pe, SK2, ST2, O2);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        o[j] = SK[j] / SK2[j] - 1.0;
+        o[6 + j] = ST[j] / ST2[j] - 1.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) o[12 + j] = O[j] / O2[j] - 1.0;
+}
+
+void launch_pair_integrals(const double* X, const double* Y, const double* s, long long m, int k,
+                           int canonical, double* out, double* feats, hipStream_t st) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(pair_integrals_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, X, Y, s,
+                       m, k, canonical, out, feats);
 }
 
 }  // namespace fl

@@ -33,7 +33,11 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_assemble", "fl_matrix_ld", "fl_matrix_ptr", "fl_dofs", "fl_export_matrix",
            "fl_load_vector_one", "fl_matvec", "fl_solve", "fl_energy_error2", "fl_stats",
            "fl_import_matrix", "fl_load_vector", "fl_assemble_batch", "fl_export_batch_matrix",
-           "fl_matmul", "fl_solve_batch", "fl_autotune"]
+           "fl_matmul", "fl_solve_batch", "fl_autotune", "fl_default_train_opts", "fl_pair_integrals",
+           "fl_surrogate_dataset", "fl_surrogate_init", "fl_surrogate_fit_scaling",
+           "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
+           "fl_surrogate_predict", "fl_surrogate_certify"]
+SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
 class FlOpts(C.Structure):
@@ -41,7 +45,8 @@ class FlOpts(C.Structure):
                 ("k_touch_bnd", C.c_int), ("n_classes", C.c_int),
                 ("theta", C.c_double * FL_MAX_CLASSES),
                 ("k_far", C.c_int * (FL_MAX_CLASSES + 1)),
-                ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1)), ("precision", C.c_int)]
+                ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1)), ("precision", C.c_int),
+                ("surrogate", C.c_int), ("sur_tol", C.c_double)]
 
 
 class FlStats(C.Structure):
@@ -53,7 +58,13 @@ class FlStats(C.Structure):
                 ("kernel_evals", C.c_int64), ("t_plan_ms", C.c_double),
                 ("t_assemble_ms", C.c_double), ("t_far_ms", C.c_double), ("t_self_ms", C.c_double),
                 ("t_touch_ms", C.c_double), ("t_scatter_ms", C.c_double), ("t_solve_ms", C.c_double),
-                ("last_iters", C.c_int32), ("last_relres", C.c_double), ("last_outer", C.c_int32)]
+                ("last_iters", C.c_int32), ("last_relres", C.c_double), ("last_outer", C.c_int32),
+                ("pairs_surrogate", C.c_int64), ("pairs_fallback", C.c_int64)]
+
+
+class FlTrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("lr_min", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("seed", C.c_uint64)]
 
 
 class FlTuneEntry(C.Structure):
@@ -105,6 +116,17 @@ def lib():
         L.fl_solve_batch.argtypes = [vp, vp, i64, i64, vp, i64, i64, i64, dp, C.c_int32, C.c_int, vp, vp]
         L.fl_autotune.argtypes = [vp, C.c_int, C.POINTER(FlTuneEntry), C.c_int, C.POINTER(C.c_int),
                                   C.POINTER(C.c_int)]
+        L.fl_default_train_opts.argtypes = [C.POINTER(FlTrainOpts)]
+        L.fl_pair_integrals.argtypes = [vp, i64, vp, vp, vp, C.c_int, vp]
+        L.fl_surrogate_dataset.argtypes = [vp, i64, vp, vp, vp, C.c_int, vp, vp]
+        L.fl_surrogate_init.argtypes = [vp, C.c_uint64]
+        L.fl_surrogate_fit_scaling.argtypes = [vp, vp, vp, i64]
+        L.fl_surrogate_set_params.argtypes = [vp, vp]
+        L.fl_surrogate_get_params.argtypes = [vp, vp]
+        L.fl_surrogate_grad.argtypes = [vp, vp, vp, i64, vp, C.POINTER(dp)]
+        L.fl_surrogate_train.argtypes = [vp, vp, vp, i64, C.POINTER(FlTrainOpts), vp]
+        L.fl_surrogate_predict.argtypes = [vp, vp, i64, vp]
+        L.fl_surrogate_certify.argtypes = [vp, vp, vp, i64, vp]
         _lib = L
     return _lib
 
@@ -115,9 +137,21 @@ def default_opts() -> FlOpts:
     return o
 
 
+def default_train_opts(**kw) -> FlTrainOpts:
+    o = FlTrainOpts()
+    lib().fl_default_train_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
 def make_opts(k_touch=None, k_touch_bnd=None, theta=None, k_far=None, k_far_bnd=None,
-              dof_mode=None, with_boundary=None, precision=None) -> FlOpts:
+              dof_mode=None, with_boundary=None, precision=None, surrogate=None, sur_tol=None) -> FlOpts:
     o = default_opts()
+    if surrogate is not None:
+        o.surrogate = int(surrogate)
+    if sur_tol is not None:
+        o.sur_tol = float(sur_tol)
     if precision is not None:
         o.precision = {"fp64": FL_FP64, "mixed": FL_MIXED}.get(precision, precision)
     if dof_mode is not None:
@@ -302,6 +336,55 @@ class Handle:
         rows = [dict(wm=e.wm, waves=e.waves, bk=e.bk, planes=e.planes, ms=e.ms, tflops=e.tflops, gbps=e.gbps)
                 for e in out[:cnt.value]]
         return rows, best.value
+
+    # ---- learned pair-integral surrogate ----
+    def pair_integrals(self, X, Y, s, k, out):
+        """X, Y: device (m, 6) float64; s: device (m,); out: device (m, 21)."""
+        self._check(lib().fl_pair_integrals(self.h, X.shape[0], _ptr(X), _ptr(Y), _ptr(s), k, _ptr(out)))
+
+    def surrogate_dataset(self, X, Y, s, feats, targets, k_exact=8):
+        self._check(lib().fl_surrogate_dataset(self.h, X.shape[0], _ptr(X), _ptr(Y), _ptr(s), k_exact,
+                                               _ptr(feats), _ptr(targets)))
+
+    def surrogate_init(self, seed=1):
+        self._check(lib().fl_surrogate_init(self.h, seed))
+
+    def surrogate_fit_scaling(self, feats, targets):
+        self._check(lib().fl_surrogate_fit_scaling(self.h, _ptr(feats), _ptr(targets), feats.shape[0]))
+
+    def surrogate_set_params(self, blob):
+        b = np.ascontiguousarray(blob, dtype=np.float64)
+        if b.size != SUR_BLOB:
+            raise ValueError("blob must hold %d doubles" % SUR_BLOB)
+        self._check(lib().fl_surrogate_set_params(self.h, b.ctypes.data_as(C.c_void_p)))
+
+    def surrogate_get_params(self) -> np.ndarray:
+        b = np.zeros(SUR_BLOB)
+        self._check(lib().fl_surrogate_get_params(self.h, b.ctypes.data_as(C.c_void_p)))
+        return b
+
+    def surrogate_grad(self, feats, targets):
+        g = np.zeros(SUR_NPARAM, dtype=np.float32)
+        L = C.c_double()
+        self._check(lib().fl_surrogate_grad(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
+                                            g.ctypes.data_as(C.c_void_p), C.byref(L)))
+        return L.value, g
+
+    def surrogate_train(self, feats, targets, opts: FlTrainOpts | None = None):
+        o = opts if opts is not None else default_train_opts()
+        hist = np.zeros(max(o.steps, 1))
+        self._check(lib().fl_surrogate_train(self.h, _ptr(feats), _ptr(targets), feats.shape[0], C.byref(o),
+                                             hist.ctypes.data_as(C.c_void_p)))
+        return hist[:o.steps]
+
+    def surrogate_predict(self, feats, out):
+        self._check(lib().fl_surrogate_predict(self.h, _ptr(feats), feats.shape[0], _ptr(out)))
+
+    def surrogate_certify(self, feats, targets) -> np.ndarray:
+        b = np.zeros(SUR_NRB * SUR_NSB)
+        self._check(lib().fl_surrogate_certify(self.h, _ptr(feats), _ptr(targets), feats.shape[0],
+                                               b.ctypes.data_as(C.c_void_p)))
+        return b.reshape(SUR_NRB, SUR_NSB)
 
 
 def _device_view(torch, ptr, n, ld, device):

@@ -44,9 +44,11 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "fraclap.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
          offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres),
-         sizeof(fl_tune_entry), offsetof(fl_tune_entry, gbps));
+         sizeof(fl_tune_entry), offsetof(fl_tune_entry, gbps), offsetof(fl_opts, sur_tol),
+         offsetof(fl_stats_t, pairs_fallback), sizeof(fl_train_opts), offsetof(fl_train_opts, seed),
+         (size_t)FL_SUR_BLOB);
   return 0; }
 """)
     exe = tmp_path / "lay"
@@ -54,7 +56,18 @@ int main(void) {
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [C.sizeof(F.FlOpts), F.FlOpts.theta.offset, F.FlOpts.k_far_bnd.offset,
                     C.sizeof(F.FlStats), F.FlStats.last_relres.offset,
-                    C.sizeof(F.FlTuneEntry), F.FlTuneEntry.gbps.offset]
+                    C.sizeof(F.FlTuneEntry), F.FlTuneEntry.gbps.offset, F.FlOpts.sur_tol.offset,
+                    C.sizeof(F.FlStats) - 8, C.sizeof(F.FlTrainOpts), F.FlTrainOpts.seed.offset, F.SUR_BLOB]
+
+
+def test_surrogate_constants_match_generator():
+    from paper_1708_03912_amd import pairgen as G
+    assert F.SUR_NPARAM == G.n_params()
+    assert F.SUR_BLOB == G.n_params() + 2 * 9 + 2 * 21 + 2 * 9 + F.SUR_NRB * F.SUR_NSB
+    o = F.default_opts()
+    assert o.surrogate == 0 and o.sur_tol == 1e-2
+    t = F.default_train_opts()
+    assert (t.steps, t.batch, t.seed) == (20000, 1024, 1)
 
 
 def test_no_cpu_fallback_in_binding():
