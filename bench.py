@@ -47,6 +47,16 @@ def parse():
     ap.add_argument("--batch-cells", type=int, default=32000)
     ap.add_argument("--only-batch", action="store_true",
                     help="run only the batched leg and print its object (profiling)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate leg (graded L-shape, ~37.7k triangles, s = 0.5)")
+    ap.add_argument("--only-surrogate", action="store_true",
+                    help="run only the surrogate leg and print its object (profiling)")
+    ap.add_argument("--sur-train", type=int, default=65536, help="training pairs of the surrogate")
+    ap.add_argument("--sur-steps", type=int, default=20000, help="Adam steps of the surrogate")
+    ap.add_argument("--sur-tol", type=float, default=0.02, help="certified bound for the surrogate")
+    ap.add_argument("--c5", action="store_true",
+                    help="run only the large-disk leg (~2e5 triangles, ~1e5 DOFs, 80 GB FP64 matrix): plain "
+                         "FP64 vs FL_MIXED + surrogate, s in {0.25, 0.75}, and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -94,6 +104,16 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"batch": batch_leg(args)}), flush=True)
+        return
+    if args.c5:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"c5": c5_leg(args)}), flush=True)
+        return
+    if args.only_surrogate:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
         return
     import numpy as np
     import torch
@@ -219,6 +239,8 @@ def main():
     out["mixed"] = mixed_leg(args, mesh, svals, handles, bufs, ball_fu, pairs_per_step)
     if not args.no_batch:
         out["batch"] = batch_leg(args)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -357,6 +379,256 @@ def batch_leg(args):
         if k != "f64":
             out["solve_" + k]["energy_gap_rel_max"] = gaps[k]
     h.close()
+    return out
+
+
+def surrogate_leg(args):
+    """Learned surrogate on the graded L-shape ((-1,1)^2 minus [0,1)x(-1,0],
+    newest-vertex bisection graded 1:64 toward the re-entrant corner and the
+    boundary, 37,692 triangles), s = 0.5, f = 1.
+
+    Training set: separated element pairs of this mesh drawn from the two
+    closest distance classes (centroid distance < 3 larger longest edges),
+    s uniform in [0.05, 0.95]; targets by the library's order-8 rule.  The
+    network (9-64-64-21, FP16 matrix cores) is trained on the GPU with Adam
+    and certified on held-out pairs of the same kind.  Then four FP64-matrix
+    assemblies of A^0.5 are compared: exact orders (4,3,2,2) (the plain
+    path), the surrogate in classes 0-1 (exact fallback where not
+    certified), the surrogate with FP32 separated pairs (FL_MIXED), and the
+    plain order-2 rule in classes 0-1 (and FL_MIXED alone).  Each is solved
+    by Jacobi-PCG to 1e-10; energy-norm distances ||u_X - u_ref||_A /
+    ||u_ref||_A are measured against a reference assembled with orders 8 / 6
+    in classes 0-1."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M, pairgen as G
+    mesh = M.lshape_config3()
+    T, Bf = len(mesh["cells"]), len(mesh["bfacets"])
+    s = 0.5
+    pairs = T * (T + 1) // 2 + T * Bf
+    out = {"workload": f"d=2 graded L-shape T={T} B={Bf} (size ratio 1:64), s=0.5, f=1: exact-order FP64 "
+                       f"assembly vs learned surrogate (classes 0-1) + Jacobi-PCG to 1e-10",
+           "cells": T, "bfacets": Bf, "s": s}
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    h = F.Handle(0)
+    Xt, Yt, st_ = G.mesh_band_pairs(mesh, 101, args.sur_train)  # same draws as train_surrogate_for
+    Xv, Yv, sv = G.mesh_band_pairs(mesh, 102, 16384)
+    ft = torch.zeros(len(st_), 9, dtype=torch.float64, device="cuda")
+    tt = torch.zeros(len(st_), 21, dtype=torch.float64, device="cuda")
+    fv = torch.zeros(len(sv), 9, dtype=torch.float64, device="cuda")
+    tv = torch.zeros(len(sv), 21, dtype=torch.float64, device="cuda")
+    Xt, Yt, st_, Xv, Yv, sv = (dev(a) for a in (Xt, Yt, st_, Xv, Yv, sv))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.surrogate_dataset(Xt, Yt, st_, ft, tt, k_exact=8)
+    h.surrogate_dataset(Xv, Yv, sv, fv, tv, k_exact=8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.surrogate_init(7)
+    h.surrogate_fit_scaling(ft, tt)
+    topt = F.default_train_opts(steps=args.sur_steps, batch=1024)
+    hist = h.surrogate_train(ft, tt, topt)
+    t2 = time.perf_counter()
+    bound = h.surrogate_certify(fv, tv)
+    pred = torch.zeros_like(tv)
+    h.surrogate_predict(fv, pred)
+    err = (pred - tv).abs()
+    t3 = time.perf_counter()
+    out["train"] = {"pairs": int(ft.shape[0]), "heldout_pairs": int(fv.shape[0]), "steps": topt.steps,
+                    "batch": topt.batch, "dataset_ms": round((t1 - t0) * 1e3, 2),
+                    "train_ms": round((t2 - t1) * 1e3, 2), "certify_ms": round((t3 - t2) * 1e3, 2),
+                    "loss_first": float(np.mean(hist[:20])), "loss_last": float(np.mean(hist[-200:])),
+                    "heldout_abs_err": {"median": float(err.median()), "p99": float(torch.quantile(err.flatten()[:1 << 20], 0.99)),
+                                        "max": float(err.max())},
+                    "heldout_order2_rel_err": {"median": float(tv.abs().median()), "max": float(tv.abs().max())},
+                    "bound_at_s": [float(b) for b in bound[:, 2]], "sur_tol": args.sur_tol}
+    legs = {"plain": F.make_opts(),
+            "surrogate": F.make_opts(surrogate=2, sur_tol=args.sur_tol),
+            "mixed": F.make_opts(precision="mixed"),
+            "surrogate_mixed": F.make_opts(surrogate=2, sur_tol=args.sur_tol, precision="mixed"),
+            "order2_band": F.make_opts(k_far=[2, 2, 2, 2]),
+            "reference": F.make_opts(k_far=[8, 6, 2, 2])}
+    hs = {"plain": F.Handle(0)}
+    for k in legs:
+        if k != "plain":
+            hs[k] = h if k == "surrogate" else F.Handle(0)
+    # the mixed leg needs the same network: copy the parameters over
+    blob = h.surrogate_get_params()
+    hs["surrogate_mixed"].surrogate_set_params(blob)
+    sol = {}
+    for k, o in legs.items():
+        hk = hs[k]
+        hk.set_mesh(mesh)
+        for rep in range(2):                     # first assembly untimed
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            n = hk.assemble(s, o)
+            torch.cuda.synchronize()
+            a_ms = (time.perf_counter() - a0) * 1e3
+        stt = hk.stats()
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        u = torch.zeros(n, dtype=torch.float64, device="cuda")
+        hk.load_vector_one(b)
+        it, rel, rc = hk.solve(b, u, rtol=1e-10, maxit=20000)
+        t_solve = hk.stats().t_solve_ms
+        sol[k] = (b, u)
+        out[k] = {"assemble_ms": round(a_ms, 3), "assemble_device_ms": round(stt.t_assemble_ms, 3),
+                  "separated_ms": round(stt.t_far_ms, 3), "pairs_per_s": round(pairs / (a_ms * 1e-3), 1),
+                  "pairs_far": [int(x) for x in list(stt.pairs_far)[:4]],
+                  "pairs_surrogate": int(stt.pairs_surrogate), "pairs_fallback": int(stt.pairs_fallback),
+                  "kernel_evals": int(stt.kernel_evals), "cg_iters": it, "relres": rel,
+                  "solve_ms": round(t_solve, 3)}
+    # energy-norm distances in the reference matrix (band classes with
+    # orders 8 / 6: quadrature error of the band far below every leg's)
+    hr = hs["reference"]
+    ur = sol["reference"][1]
+    y = torch.empty_like(ur)
+    hr.matvec(ur, y)
+    unorm = math.sqrt(float(torch.dot(ur, y)))
+    out["n"] = int(ur.numel())
+    out["u_energy_norm"] = unorm
+    for k in legs:
+        if k == "reference":
+            continue
+        du = sol[k][1] - ur
+        hr.matvec(du, y)
+        out[k]["energy_gap_to_reference_rel"] = math.sqrt(max(float(torch.dot(du, y)), 0.0)) / unorm
+        out[k]["speedup_vs_plain"] = round(out["plain"]["assemble_ms"] / out[k]["assemble_ms"], 3)
+    for hk in set(hs.values()):
+        hk.close()
+    return out
+
+
+def train_surrogate_for(mesh, args, h):
+    """Train h's network on band pairs of mesh (library dataset, library
+    kernels) and certify it on held-out pairs; returns timings."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, pairgen as G
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    Xt, Yt, st_ = (dev(a) for a in G.mesh_band_pairs(mesh, 101, args.sur_train))
+    Xv, Yv, sv = (dev(a) for a in G.mesh_band_pairs(mesh, 102, 16384))
+    ft = torch.zeros(Xt.shape[0], 9, dtype=torch.float64, device="cuda")
+    tt = torch.zeros(Xt.shape[0], 21, dtype=torch.float64, device="cuda")
+    fv = torch.zeros(Xv.shape[0], 9, dtype=torch.float64, device="cuda")
+    tv = torch.zeros(Xv.shape[0], 21, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.surrogate_dataset(Xt, Yt, st_, ft, tt, k_exact=8)
+    h.surrogate_dataset(Xv, Yv, sv, fv, tv, k_exact=8)
+    h.surrogate_init(7)
+    h.surrogate_fit_scaling(ft, tt)
+    hist = h.surrogate_train(ft, tt, F.default_train_opts(steps=args.sur_steps, batch=1024))
+    bound = h.surrogate_certify(fv, tv)
+    torch.cuda.synchronize()
+    return {"train_total_ms": round((time.perf_counter() - t0) * 1e3, 1), "loss_last": float(np.mean(hist[-200:])),
+            "bound_at_s": {"0.25": [float(b) for b in bound[:, 1]], "0.75": [float(b) for b in bound[:, 3]]}}
+
+
+def c5_leg(args):
+    """Unit disk, ~2e5 triangles, ~1e5 interior DOFs: the FP64 matrix takes
+    80 GB, its FP32 copy 40 GB.  For s in {0.25, 0.75}, f = 1, interior
+    DOFs: (a) plain FP64 assembly + Jacobi-PCG to 1e-10; (b) FL_MIXED
+    assembly with the learned surrogate in classes 0-1 (trained on this
+    mesh's band pairs) + FP32 inner CG inside FP64 refinement.  Energy-norm
+    errors against the closed-form solution, and the gap of (b) to (a) in
+    the FP64 matrix."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    mesh = M.disk_for_cells(200000, seed=2)
+    T, Bf = len(mesh["cells"]), len(mesh["bfacets"])
+    pairs = T * (T + 1) // 2 + T * Bf
+    out = {"workload": f"d=2 unit disk T={T} B={Bf}, interior DOFs, s in {{0.25,0.75}}, f=1: plain FP64 vs "
+                       f"FL_MIXED + learned surrogate, Jacobi-PCG to 1e-10", "cells": T}
+    hs = F.Handle(0)
+    hs.set_mesh(mesh)
+    out["surrogate_training"] = train_surrogate_for(mesh, args, hs)
+
+    def ball_fu(s):
+        c = 2.0 ** (-2 * s) / (math.gamma(1 + s) * math.gamma(1 + s))
+        return c * math.pi / (s + 1.0)
+
+    for s in (0.25, 0.75):
+        res = {}
+        h64 = F.Handle(0)
+        h64.set_mesh(mesh)
+        # (a) plain FP64: fl_assemble + fl_solve
+        o64 = F.make_opts(dof_mode="interior")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = h64.assemble(s, o64)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        st = h64.stats()
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        u = torch.zeros(n, dtype=torch.float64, device="cuda")
+        h64.load_vector_one(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rel, rc = h64.solve(b, u, rtol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+        t_sol = (time.perf_counter() - t0) * 1e3
+        res["fp64"] = {"n": n, "assemble_ms": round(t_asm, 1), "assemble_device_ms": round(st.t_assemble_ms, 1),
+                       "separated_ms": round(st.t_far_ms, 1), "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
+                       "solve_ms": round(t_sol, 1), "cg_iters": it, "relres": rel, "u": u, "b": b}
+        # (b) FL_MIXED + surrogate assembly (batch call, one s) and the
+        # batched Jacobi-PCG with FP32 matrix storage and reliable updates
+        om = F.make_opts(dof_mode="interior", precision="mixed", surrogate=2, sur_tol=args.sur_tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nm = hs.assemble_batch([s], om)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        st = hs.stats()
+        bm = torch.zeros(1, nm, dtype=torch.float64, device="cuda")
+        hs.load_vector("one", bm)
+        Um = torch.zeros(1, 1, nm, dtype=torch.float64, device="cuda")
+        hs.solve_batch(bm, Um, rtol=1e-10, maxit=20000, inner="f32")   # converts A to FP32 (first use)
+        Um.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        itm, relm, rcm = hs.solve_batch(bm, Um, rtol=1e-10, maxit=20000, inner="f32")
+        torch.cuda.synchronize()
+        t_sol = (time.perf_counter() - t0) * 1e3
+        res["mixed_surrogate"] = {"n": nm, "assemble_ms": round(t_asm, 1),
+                                  "assemble_device_ms": round(st.t_assemble_ms, 1),
+                                  "separated_ms": round(st.t_far_ms, 1),
+                                  "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
+                                  "pairs_surrogate": int(st.pairs_surrogate), "pairs_fallback": int(st.pairs_fallback),
+                                  "solve_ms": round(t_sol, 1), "cg_iters": int(itm.max()),
+                                  "residual_replacements": hs.stats().last_outer, "relres": float(relm.max()),
+                                  "u": Um[0, 0].clone(), "b": bm[0]}
+        e2 = h64.energy_error2(ball_fu(s), res["fp64"]["b"], res["fp64"]["u"])
+        E = math.sqrt(max(e2, 0.0))
+        du = res["mixed_surrogate"]["u"] - res["fp64"]["u"]
+        y = torch.empty_like(du)
+        h64.matvec(du, y)
+        gap = math.sqrt(max(float(torch.dot(du, y)), 0.0))
+        e2m = h64.energy_error2(ball_fu(s), res["fp64"]["b"], res["mixed_surrogate"]["u"])
+        # dense FP64 matvec rate on the 80 GB matrix (HBM-bound, not cache-resident)
+        x = torch.rand(res["fp64"]["n"], dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            h64.matvec(x, y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            h64.matvec(x, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        mv_ms = ev0.elapsed_time(ev1) / 5
+        n = res["fp64"]["n"]
+        for r in res.values():
+            r.pop("u")
+            r.pop("b")
+        res["energy_error_fp64"] = E
+        res["energy_error_mixed_surrogate"] = math.sqrt(max(e2m, 0.0))
+        res["gap_over_E"] = gap / E if E > 0 else None
+        res["matvec_ms"] = round(mv_ms, 3)
+        res["matvec_GBps"] = round(n * n * 8 / (mv_ms * 1e-3) / 1e9, 1)
+        out[str(s)] = res
+        h64.close()
+    hs.close()
     return out
 
 

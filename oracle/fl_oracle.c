@@ -588,26 +588,28 @@ static double cdn(int dim, double s) {
 
 double orc_cdn(int dim, double s) { return cdn(dim, s); }
 
-static void add_block(double *A, int64_t nv, const char *rowmask, const int *gi, int na,
+static void add_block(double *A, int64_t nv, const int32_t *rowmask, const int *gi, int na,
                       const int *gj, int nb, const double *B, int ldb, double f) {
     for (int a = 0; a < na; ++a) {
-        if (rowmask && !rowmask[gi[a]]) continue;
+        if (rowmask && rowmask[gi[a]] < 0) continue;
+        const int64_t row = rowmask ? rowmask[gi[a]] : gi[a];
         for (int b = 0; b < nb; ++b) {
             double v = f * B[ldb * a + b];
 #pragma omp atomic
-            A[(int64_t)gi[a] * nv + gj[b]] += v;
+            A[row * nv + gj[b]] += v;
         }
     }
 }
 
 /* Assemble the full-node matrix (nv x nv, row-major, accumulated into A)
- * for the mesh.  rowmask (nv bytes, may be NULL) restricts accumulation
- * to the rows whose vertex is set; pairs that cannot reach such a row are
- * skipped.  bnd_normals: nb x dim inward unit normals of the facets.
+ * for the mesh.  rowmask (nv ints, may be NULL) restricts accumulation to
+ * the rows of the vertices v with rowmask[v] >= 0, stored as row
+ * rowmask[v] of A (then A has that many rows of nv); pairs that cannot
+ * reach such a row are skipped.  bnd_normals: nb x dim inward unit normals of the facets.
  * Returns the number of separated pairs per class in cls_count. */
 void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, const double *verts,
                   int64_t nc, const int32_t *cells, int64_t nb, const int32_t *bfacets,
-                  const double *bnormals, const char *rowmask, double *A, int64_t *cls_count) {
+                  const double *bnormals, const int32_t *rowmask, double *A, int64_t *cls_count) {
     const int nper = dim + 1;
     const double s = o->s;
     const double C = cdn(dim, s);
@@ -618,7 +620,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
         centroid_h2(dim, verts, cells + nper * K, cen + dim * K, h2 + K);
         hit[K] = 0;
         for (int a = 0; a < nper; ++a)
-            if (!rowmask || rowmask[cells[nper * K + a]]) hit[K] = 1;
+            if (!rowmask || rowmask[cells[nper * K + a]] >= 0) hit[K] = 1;
     }
     int64_t cnt[16] = {0};
 

@@ -280,10 +280,13 @@ def dof_nodes(nv, bfacets, s, mode="paper"):
 
 
 def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None,
-                  far_skip_below=0):
+                  far_skip_below=0, compact=False):
     """Full-node matrix (nv x nv) of a(phi_i, phi_j) by the element-pair
     decomposition of Sec. 5.  ``rows``: optional vertex indices; only those
-    rows are accumulated (others stay zero).  Returns (A, class_counts)."""
+    rows are accumulated (others stay zero); with ``compact`` the result is
+    just those rows (len(rows) x nv, in the order given).
+    ``far_skip_below``: separated pairs of a lower order class are left out
+    (still counted).  Returns (A, class_counts)."""
     orders.check()
     dim = mesh["dim"]
     verts = np.ascontiguousarray(mesh["verts"], dtype=np.float64).reshape(-1)
@@ -293,11 +296,12 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     nc = cells.size // (dim + 1)
     nb = bf.size // dim
     normals = np.ascontiguousarray(boundary_normals(dim, verts, cells, bf), dtype=np.float64).reshape(-1)
-    A = np.zeros((nv, nv))
     mask = None
     if rows is not None:
-        mask = np.zeros(nv, dtype=np.int8)
-        mask[np.asarray(rows)] = 1
+        rows = np.asarray(rows, dtype=np.int64)
+        mask = np.full(nv, -1, dtype=np.int32)
+        mask[rows] = np.arange(len(rows)) if compact else rows
+    A = np.zeros((len(rows) if (compact and rows is not None) else nv, nv))
     th = np.ascontiguousarray(orders.theta, dtype=np.float64)
     kf = np.ascontiguousarray(orders.k_far, dtype=np.int32)
     kb = np.ascontiguousarray(orders.k_far_bnd, dtype=np.int32)

@@ -16,7 +16,9 @@ stiffness matrix.  The method evaluates them with tensor Gauss rules whose
 order grows as the pair gets closer (App. B).  The surrogate instead takes
 the cheapest of those rules, order 2 (2 x 2 collapsed points per triangle),
 and predicts its relative error t = I / Q2 - 1 for each of the 21 values;
-the corrected value is Q2 (1 + t).
+the corrected value is Q2 (1 + t), after which the six diagonal values are
+recomputed from the sum rules (enforce_sum_rules) so that the assembled
+matrix keeps the zero row sums of its Omega x Omega part.
 
 Canonical form.  t does not change under translation, rotation and uniform
 scaling of the pair (integral and rule scale alike).  Each pair is put in a
@@ -263,6 +265,26 @@ def adam_step(theta, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def enforce_sum_rules(v):
+    """Make 21 corrected pair integrals (rows of v, canonical order)
+    satisfy the sum rules every quadrature of the pair satisfies, because
+    the barycentric coordinates sum to 1: sum_b SK_ab = sum_b X_ab (row sums
+    of X) and sum_a ST_ab = sum_a X_ab (column sums).  The six diagonal
+    entries SK_aa, ST_bb are recomputed from the other values, so the
+    assembled matrix keeps the zero row sums of its Omega x Omega part (the
+    constants stay in its kernel) whatever the network's errors."""
+    v = np.array(v, dtype=np.float64, copy=True)
+    X = v[:, 12:].reshape(-1, 3, 3)
+    rs, cs = X.sum(2), X.sum(1)
+    v[:, 0] = rs[:, 0] - v[:, 1] - v[:, 2]
+    v[:, 3] = rs[:, 1] - v[:, 1] - v[:, 4]
+    v[:, 5] = rs[:, 2] - v[:, 2] - v[:, 4]
+    v[:, 6] = cs[:, 0] - v[:, 7] - v[:, 8]
+    v[:, 9] = cs[:, 1] - v[:, 7] - v[:, 10]
+    v[:, 11] = cs[:, 2] - v[:, 8] - v[:, 10]
+    return v
+
+
 def predict(net, F, fp16=True):
     """Targets predicted for features F (m, 9) by net (dict with theta,
     mx, sx, mt, st)."""
@@ -329,13 +351,14 @@ def band_pairs(mesh, theta, nsur):
     return out[:n]
 
 
-def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True, full=False):
+def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True, full=False,
+                       with_boundary=True):
     """A^s on the DOF set with the band pairs (order class < nsur) done by
     the surrogate where certified (features inside net['lo'] .. net['hi']
     and net['bound'][distance bin, s bin] <= tol), by the exact rule of
     their class otherwise.  Returns (A, dofs, n_surrogate, n_fallback);
     full=True: A over all nodes instead."""
-    Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur)
+    Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur, with_boundary=with_boundary)
     V = np.asarray(mesh["verts"], dtype=np.float64)
     Cc = np.asarray(mesh["cells"], dtype=np.int64)
     P = band_pairs(mesh, orders.theta, nsur)
@@ -352,7 +375,7 @@ def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True,
         idx = np.nonzero(use)[0]
         Kc, Tc = canonical_pairs(X[idx], Y[idx])
         tp = predict(net, F[idx], fp16=fp16)
-        vals[idx] = integrals_many(s, 2, Kc, Tc) * (1.0 + tp)
+        vals[idx] = enforce_sum_rules(integrals_many(s, 2, Kc, Tc) * (1.0 + tp))
     for c in range(nsur):
         idx = np.nonzero(~use & (P[:, 2] == c))[0]
         if len(idx):

@@ -679,37 +679,12 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     FP.S = dS;
     FP.cls_count = dcnt;
     FP.mixed = o.precision == FL_MIXED ? 1 : 0;
-    // surrogate band: near tiles list the pairs of classes < o.surrogate
-    long long band_cap = 0;
-    BandParams BDP{};
     if (o.surrogate > 0) {
-        if ((rc = fl_sur_band_params(h, s, o, &BDP))) return rc;
-        if (h->sur.band_cap < sizeof(int2) * (size_t)std::max<int64_t>(1 << 20, 160 * T)) {
-            if ((rc = ensure_dev(h, &h->sur.band, &h->sur.band_cap,
-                                 sizeof(int2) * (size_t)std::max<int64_t>(1 << 20, 160 * T))))
-                return rc;
-        }
-        band_cap = (long long)(h->sur.band_cap / sizeof(int2));
-        FP.nsur = o.surrogate;
-        FP.band = h->sur.band;
-        FP.band_count = dcnt + 14;
-        FP.band_cap = band_cap;
+        if ((rc = fl_sur_params(h, s, o, &FP.sur))) return rc;
+        FP.sur.counters = dcnt + 12;
     }
     launch_far(E, FP, h->stream);
     HIPCHK(hipGetLastError());
-    if (o.surrogate > 0) {
-        BDP.list = h->sur.band;
-        BDP.count = dcnt + 14;
-        BDP.cap = band_cap;
-        BDP.pe = pe;
-        BDP.C = C;
-        BDP.A = A;
-        BDP.lda = lda;
-        BDP.S = dS;
-        BDP.counters = dcnt + 12;
-        launch_band(E, BDP, FP.mixed, h->stream);
-        HIPCHK(hipGetLastError());
-    }
     {
         FarParams FF = FP;
         FF.tiles = (const int2*)dv(o_ft);
@@ -778,12 +753,6 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
     unsigned long long cnt2[16];
     HIPCHK(hipMemcpy(cnt2, dcnt + 16, sizeof(cnt2), hipMemcpyDeviceToHost));
-    if (o.surrogate > 0 && (long long)cnt[14] > band_cap) {
-        // the band list overflowed: grow it to fit and assemble again
-        if ((rc = ensure_dev(h, &h->sur.band, &h->sur.band_cap, sizeof(int2) * (size_t)(cnt[14] + cnt[14] / 4 + 1024))))
-            return rc;
-        return run_assembly(h, P, s, o, A, lda, a_elems, A32, st);
-    }
 
     fl_stats_t& S = *st;
     S.n = n;
@@ -805,11 +774,11 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
         for (int m = 0; m <= o.n_classes; ++m) {
             int64_t q = dim == 2 ? (int64_t)o.k_far[m] * o.k_far[m] : o.k_far[m];
             // band classes: order 2 for the surrogate pairs, the class order
-            // for the fallbacks (counted per class by the band kernel)
+            // for the fallbacks (counted per class by the near-tile kernel)
             int64_t np = m < o.surrogate ? (int64_t)cnt2[m] : S.pairs_far[m];
             ev2 += np * q * q;
         }
-        if (o.surrogate > 0) ev2 += S.pairs_surrogate * 16 * 16;
+        if (o.surrogate > 0) ev2 += S.pairs_surrogate * 16;  // order 2: 4 x 4 points
         if (dim == 2) {
             ev2 += T * 3 * kT + S.pairs_edge * 4 * kT * kT + S.pairs_vertex * 2 * kT * kT * kT;
             ev2 += S.pairs_bnd_touch * 6 * kB * 2;  // upper bound per touching facet pair

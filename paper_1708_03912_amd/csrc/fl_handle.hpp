@@ -29,8 +29,7 @@ struct fl_batch {
     int* hflag = nullptr;                   // pinned host word (active count)
 };
 
-// Pair-integral surrogate: network, scaling, certification table and the
-// band-pair list of the assembly.
+// Pair-integral surrogate: network, scaling and certification table.
 struct fl_sur {
     bool have = false;                      // parameters present
     bool have_scaling = false;              // standardisation and box present
@@ -48,8 +47,6 @@ struct fl_sur {
     double* loss = nullptr;                 // per-step workgroup squared errors
     size_t loss_cap = 0;
     double* ws = nullptr;                   // statistics / certification scratch
-    int2* band = nullptr;                   // band pairs listed by the near tiles
-    size_t band_cap = 0;                    // bytes
 };
 
 struct fl_handle {
@@ -108,9 +105,10 @@ struct fl_handle {
     fl_sur sur;
 };
 
-// Band-kernel parameters for an assembly at s with options o (classes below
+// Quadrature tables independent of s (defined with the assembly driver).
+const fl::RuleTables& fl_base_rules();
+// Surrogate parameters of an assembly at s with options o (classes below
 // o.surrogate); FL_ESTATE without a network and scaling.  Defined with the
 // surrogate calls.
-const fl::RuleTables& fl_base_rules();
-int fl_sur_band_params(fl_handle* h, double s, const fl_opts& o, fl::BandParams* bp);
+int fl_sur_params(fl_handle* h, double s, const fl_opts& o, fl::SurParams* sp);
 void fl_sur_free(fl_handle* h);

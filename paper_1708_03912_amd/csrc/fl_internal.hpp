@@ -43,6 +43,19 @@ struct ElemDev {
     const int* dof[3];      // DOF ids, -1 if the vertex is not a DOF
 };
 
+// Learned surrogate for the separated pairs of the closest classes: the
+// near-tile kernel gives pairs of class < nsur whose features lie in the
+// training box and whose distance bin is certified at this s the order-2
+// rule times the network's correction, the others the exact rule.
+struct SurParams {
+    int nsur;               // 0: off
+    double s;
+    SurNet N;
+    double lo[SUR_NIN], hi[SUR_NIN];  // box of the training features
+    int use_rbin[SUR_NRB];  // distance bins certified at this s
+    unsigned long long* counters;  // [0] surrogate pairs, [1] fallback pairs, [4 + c] fallback of class c
+};
+
 struct FarParams {
     int dim;
     int T;
@@ -63,10 +76,7 @@ struct FarParams {
     double* S;              // T x 6 per-element diagonal-block accumulators
     unsigned long long* cls_count;  // ncls+1 counters
     int mixed;              // 1: separated pairs evaluated in FP32
-    int nsur;               // > 0: pairs of class < nsur are listed, not computed
-    int2* band;             // the list (cap entries)
-    unsigned long long* band_count;
-    long long band_cap;
+    SurParams sur;          // learned surrogate for the closest classes
 };
 
 struct TouchParams {
@@ -388,25 +398,5 @@ void launch_sur_colstat(const double* X, long long m, int ncol, const double* me
 void launch_pair_integrals(const double* X, const double* Y, const double* s, long long m, int k,
                            int canonical, double* out, double* feats, hipStream_t st);
 
-// Band pairs listed by the near-tile kernel, handled by the surrogate
-// where certified and by the exact rule of their class otherwise.
-struct BandParams {
-    const int2* list;       // (K, Kt) library element indices
-    const unsigned long long* count;  // entries written (may exceed cap)
-    long long cap;
-    double s, pe, C;
-    int ncls;
-    double th2[FL_MAX_CLASSES];
-    int kf[FL_MAX_CLASSES + 1];
-    int enabled;            // network usable
-    SurNet N;
-    double lo[SUR_NIN], hi[SUR_NIN];  // box of the training features
-    int use_rbin[SUR_NRB];  // distance bins certified at this s
-    double* A;
-    long long lda;
-    double* S;
-    unsigned long long* counters;  // [0] surrogate pairs, [1] fallback pairs
-};
-void launch_band(const ElemDev& E, const BandParams& P, int mixed, hipStream_t st);
 
 }  // namespace fl

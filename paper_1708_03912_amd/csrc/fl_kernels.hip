@@ -490,7 +490,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
 // bucket at a time, so all lanes of a wave run the same order.  Diagonal
 // blocks, self terms and off-diagonal blocks are accumulated in LDS as in
 // far_kernel and flushed once per tile.
-template <int DIM, int MIX>
+template <int DIM, int MIX, int SUR>
 __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ unsigned char pcls[BE * BE];
     __shared__ unsigned short plist[BE * BE];
     __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
-    __shared__ unsigned long long bbase;
+    __shared__ float souts[SUR ? 4 * 16 * 24 : 1];  // network outputs, 16 samples per wave
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -591,20 +591,172 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
         plist[slot] = (unsigned short)pidx;
     }
     __syncthreads();
-    // classes below nsur (surrogate band): only listed for band_kernel
+    // classes below nsur: the learned surrogate where certified (order-2
+    // rule on the canonical pair times 1 + t), the exact rule otherwise
     int c0 = 0;
-    if (P.nsur > 0) {
-        c0 = P.nsur < P.ncls + 1 ? P.nsur : P.ncls + 1;
+    if constexpr (SUR) {
+        const SurParams& SP = P.sur;
+        c0 = SP.nsur < P.ncls + 1 ? SP.nsur : P.ncls + 1;
         const int nb = coff[c0];
-        if (tid == 0) bbase = nb ? atomicAdd(P.band_count, (unsigned long long)nb) : 0ull;
-        __syncthreads();
-        for (int sl = tid; sl < nb; sl += 256) {
-            const unsigned long long slot = bbase + (unsigned long long)sl;
-            if (slot < (unsigned long long)P.band_cap) {
-                const int pidx = plist[sl];
-                const int r = pidx / BE, l = pidx - r * BE;
-                P.band[slot] = make_int2(I0 + r, J0 + l);
+        const int lane = tid & 63, wave = tid >> 6, r16 = lane & 15, g = lane >> 4;
+        const double rb_e2[5] = {1.0, 2.25, 4.0, 6.25, 9.0};
+        unsigned long long n_sur = 0, n_fb = 0;
+        for (int base = 0; base < nb; base += 256) {
+            const int slot = base + tid;
+            const bool valid = slot < nb;
+            int r = 0, l = 0, cls = 0;
+            // phase 1: canonical form, features, certification.  o1 / o2:
+            // vertex slots, in the order of the computed blocks, of the first /
+            // second element (canonical for the network, stored order for the
+            // exact rule); swap: the first element is Kt
+            int o1[3] = {0, 1, 2}, o2[3] = {0, 1, 2}, swap = 0;
+            bool sur = false;
+            float xn[SUR_NIN];
+#pragma unroll
+            for (int k = 0; k < SUR_NIN; ++k) xn[k] = 0.f;
+            if (valid) {
+                const int pidx = plist[slot];
+                r = pidx / BE;
+                l = pidx - r * BE;
+                cls = pcls[pidx];
+                double X[6], Y[6], C1[6], C2[6], f[SUR_NIN];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    X[q] = sI[q][r];
+                    Y[q] = sJ[q][l];
+                }
+                const double d2 = dist2_nc(sI[6][r], sI[7][r], sJ[6][l], sJ[7][l], 2);
+                const double hm = sI[8][r] > sJ[8][l] ? sI[8][r] : sJ[8][l];
+                const int rb = order_class(d2, hm, 5, rb_e2);
+                int c1[3], c2[3];
+                const int sw = sur_canon(X, Y, c1, c2, C1, C2);
+                sur_features(C1, C2, SP.s, f);
+                bool in = true;
+#pragma unroll
+                for (int k = 0; k < SUR_NIN; ++k) in = in && f[k] >= SP.lo[k] && f[k] <= SP.hi[k];
+                sur = in && SP.use_rbin[rb];
+                if (sur) {
+                    swap = sw;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        o1[a] = c1[a];
+                        o2[a] = c2[a];
+                    }
+                    sur_std_features(SP.N, f, xn);
+                }
             }
+            // phase 2: the network for the wave's 64 pairs, 16 at a time
+            float tv[SUR_NOUT];
+            const bool any_sur = __any(sur);
+            if (any_sur) {
+                unsigned int pk[5];
+                sur_pack_x(xn, pk);
+                float* ow = souts + wave * 16 * 24;
+                for (int q = 0; q < 4; ++q) {
+                    const h8 xb = sur_gather_x(pk, q);
+                    SurAct a;
+                    sur_forward16(SP.N, xb, a);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (16 * t + 4 * g + v < 24) ow[r16 * 24 + 16 * t + 4 * g + v] = a.out[t][v];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (g == q) {
+#pragma unroll
+                        for (int j = 0; j < SUR_NOUT; ++j) tv[j] = ow[r16 * 24 + j];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+            // phase 3: the pair's blocks
+            double SK[6], ST[6], O[9];
+            if (valid) {
+                double X[6], Y[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    X[q] = sI[q][r];
+                    Y[q] = sJ[q][l];
+                }
+                if (sur) {
+                    const double* Fp = swap ? Y : X;
+                    const double* Sp = swap ? X : Y;
+                    double C1[6], C2[6];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        C1[2 * a] = Fp[2 * o1[a]];
+                        C1[2 * a + 1] = Fp[2 * o1[a] + 1];
+                        C2[2 * a] = Sp[2 * o2[a]];
+                        C2[2 * a + 1] = Sp[2 * o2[a] + 1];
+                    }
+                    if (MIX) far_pair2_f32<2>(2, C1, C2, P.pe, SK, ST, O);
+                    else far_pair2<2>(2, C1, C2, P.pe, SK, ST, O);
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        SK[j] *= 1.0 + ((double)tv[j] * (double)SP.N.st[j] + (double)SP.N.mt[j]);
+                        ST[j] *= 1.0 + ((double)tv[6 + j] * (double)SP.N.st[6 + j] + (double)SP.N.mt[6 + j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 9; ++j)
+                        O[j] *= 1.0 + ((double)tv[12 + j] * (double)SP.N.st[12 + j] + (double)SP.N.mt[12 + j]);
+                    sur_sum_rules(SK, ST, O);
+                } else {
+                    far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, SK, ST, O);
+                }
+            }
+            for (int c = 0; c < c0; ++c) {
+                const unsigned long long bal = __ballot(valid && !sur && cls == c);
+                if ((tid & 63) == 0 && bal) atomicAdd(SP.counters + 4 + c, (unsigned long long)__popcll(bal));
+            }
+            if (!valid) continue;
+            if (sur) ++n_sur;
+            else ++n_fb;
+            // blocks of the row element K (r) and the column element Kt (l)
+            const double* BK = swap ? ST : SK;
+            const double* BT = swap ? SK : ST;
+            const int* pK = swap ? o2 : o1;
+            const int* pT = swap ? o1 : o2;
+            const double fct = P.C * sI[9][r] * sJ[9][l];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = a; b < 3; ++b) {
+                    const int q = sym3(a, b);
+                    atomicAdd(&SI[r * 6 + sym3(pK[a], pK[b])], fct * BK[q]);
+                    atomicAdd(&SJ[l * 6 + sym3(pT[a], pT[b])], fct * BT[q]);
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    // O[3a+b]: vertex a of the first element, b of the second
+                    const int sk = swap ? o2[b] : o1[a], sl = swap ? o1[a] : o2[b];
+                    const double v = -fct * O[3 * a + b];
+                    if (!direct) {
+                        const int ra = locI[r * 3 + sk], cb = locJ[l * 3 + sl];
+                        if (ra == 255 || cb == 255) continue;
+                        atomicAdd(&L[ra * nVJ + cb], v);
+                        if (bi == bj) atomicAdd(&L[cb * nVJ + ra], v);
+                    } else {
+                        const int ga = E.dof[sk][I0 + r], gb = E.dof[sl][J0 + l];
+                        if (ga < 0 || gb < 0) continue;
+                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                    }
+                }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            n_sur += __shfl_xor(n_sur, m, 64);
+            n_fb += __shfl_xor(n_fb, m, 64);
+        }
+        if ((tid & 63) == 0) {
+            if (n_sur) atomicAdd(SP.counters, n_sur);
+            if (n_fb) atomicAdd(SP.counters + 1, n_fb);
         }
     }
     // one class at a time, one pair per thread
@@ -680,11 +832,16 @@ void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
     if (P.dim == 2) {
-        if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1>), grid, block, 0, st, E, P);
-        else hipLaunchKernelGGL((near_kernel<2, 0>), grid, block, 0, st, E, P);
+        if (P.sur.nsur > 0) {
+            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 1>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((near_kernel<2, 0, 1>), grid, block, 0, st, E, P);
+        } else {
+            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 0>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((near_kernel<2, 0, 0>), grid, block, 0, st, E, P);
+        }
     } else {
-        if (P.mixed) hipLaunchKernelGGL((near_kernel<1, 1>), grid, block, 0, st, E, P);
-        else hipLaunchKernelGGL((near_kernel<1, 0>), grid, block, 0, st, E, P);
+        if (P.mixed) hipLaunchKernelGGL((near_kernel<1, 1, 0>), grid, block, 0, st, E, P);
+        else hipLaunchKernelGGL((near_kernel<1, 0, 0>), grid, block, 0, st, E, P);
     }
 }
 
@@ -1760,155 +1917,6 @@ void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) {
 
 void launch_cg32_final(const CgState32& s, int it, hipStream_t st) {
     hipLaunchKernelGGL(cg32_final_kernel, dim3(1), dim3(256), 0, st, s, it);
-}
-
-// ------------------------------------------------- surrogate band pairs --
-
-// Separated pairs of the band classes, one per thread (grid-stride over
-// chunks of 256 so every wave runs the network together).  Certified
-// pairs (features inside the training box, distance bin certified at this
-// s): order-2 rule on the canonical pair times (1 + t) from the network;
-// the others: the exact rule of their class.  Diagonal-block increments go
-// to the per-element accumulators S, off-diagonal blocks straight to A and
-// its mirror, all with atomics.
-template <int MIX>
-__global__ __launch_bounds__(256) void band_kernel(ElemDev E, BandParams P) {
-    __shared__ float outs[4][64 * 33];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
-    long long n = (long long)*P.count;
-    if (n > P.cap) n = P.cap;
-    const double rb_e2[5] = {1.0, 2.25, 4.0, 6.25, 9.0};
-    unsigned long long nsur = 0, nfb = 0;
-    for (long long base = (long long)blockIdx.x * 256; base < n; base += (long long)gridDim.x * 256) {
-        const long long i = base + tid;
-        const bool valid = i < n;
-        int K = 0, Kt = 0, cls = 0, rb = 0;
-        double X[6] = {0, 0, 0, 0, 0, 0}, Y[6] = {0, 0, 0, 0, 0, 0};
-        if (valid) {
-            const int2 pr = P.list[i];
-            K = pr.x;
-            Kt = pr.y;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                X[c] = E.x[c][K];
-                Y[c] = E.x[c][Kt];
-            }
-            const double d2 = dist2_nc(E.cen[0][K], E.cen[1][K], E.cen[0][Kt], E.cen[1][Kt], 2);
-            const double hm = E.h2[K] > E.h2[Kt] ? E.h2[K] : E.h2[Kt];
-            cls = order_class(d2, hm, P.ncls, P.th2);
-            rb = order_class(d2, hm, 5, rb_e2);
-        }
-        // o1 / o2: vertex slots of the first / second element in the order
-        // of the computed blocks (canonical for the network, as stored for
-        // the exact rule)
-        int o1[3] = {0, 1, 2}, o2[3] = {0, 1, 2}, swap = 0;
-        double C1[6], C2[6], f[SUR_NIN];
-        bool sur = false;
-        if (valid && P.enabled) {
-            int c1[3], c2[3];
-            const int sw = sur_canon(X, Y, c1, c2, C1, C2);
-            sur_features(C1, C2, P.s, f);
-            bool in = true;
-#pragma unroll
-            for (int k = 0; k < SUR_NIN; ++k) in = in && f[k] >= P.lo[k] && f[k] <= P.hi[k];
-            sur = in && P.use_rbin[rb];
-            if (sur) {
-                swap = sw;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    o1[a] = c1[a];
-                    o2[a] = c2[a];
-                }
-            }
-        }
-        float xn[SUR_NIN];
-#pragma unroll
-        for (int k = 0; k < SUR_NIN; ++k) xn[k] = 0.f;
-        double SK[6], ST[6], O[9];
-        if (sur) {
-            sur_std_features(P.N, f, xn);
-            if (MIX) far_pair2_f32<2>(2, C1, C2, P.pe, SK, ST, O);
-            else far_pair2<2>(2, C1, C2, P.pe, SK, ST, O);
-        }
-        if (__any(sur)) {
-            unsigned int pk[5];
-            sur_pack_x(xn, pk);
-            float* ow = outs[wave];
-            for (int q = 0; q < 4; ++q) {
-                const h8 xb = sur_gather_x(pk, q);
-                SurAct a;
-                sur_forward16(P.N, xb, a);
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) ow[(16 * q + r) * 33 + 16 * t + 4 * g + v] = a.out[t][v];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (sur) {
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    SK[j] *= 1.0 + ((double)ow[lane * 33 + j] * (double)P.N.st[j] + (double)P.N.mt[j]);
-                    ST[j] *= 1.0 + ((double)ow[lane * 33 + 6 + j] * (double)P.N.st[6 + j] + (double)P.N.mt[6 + j]);
-                }
-#pragma unroll
-                for (int j = 0; j < 9; ++j)
-                    O[j] *= 1.0 + ((double)ow[lane * 33 + 12 + j] * (double)P.N.st[12 + j] + (double)P.N.mt[12 + j]);
-            }
-        }
-        for (int c = 0; c < P.ncls + 1 && c < 12; ++c) {
-            const unsigned long long bal = __ballot(valid && !sur && cls == c);
-            if (lane == 0 && bal) atomicAdd(P.counters + 4 + c, (unsigned long long)__popcll(bal));
-        }
-        if (!valid) continue;
-        if (!sur) {
-            far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, SK, ST, O);
-            ++nfb;
-        } else {
-            ++nsur;
-        }
-        const int e1 = sur ? (swap ? Kt : K) : K, e2 = sur ? (swap ? K : Kt) : Kt;
-        const double fct = P.C * E.meas[K] * E.meas[Kt];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = a; b < 3; ++b) {
-                const int q = sym3(a, b);
-                atomicAdd(&P.S[(long long)e1 * 6 + sym3(o1[a], o1[b])], fct * SK[q]);
-                atomicAdd(&P.S[(long long)e2 * 6 + sym3(o2[a], o2[b])], fct * ST[q]);
-            }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int ga = E.dof[o1[a]][e1];
-            if (ga < 0) continue;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const int gb = E.dof[o2[b]][e2];
-                if (gb < 0) continue;
-                const double v = -fct * O[3 * a + b];
-                atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
-            }
-        }
-    }
-    // counters
-    for (int m = 32; m >= 1; m >>= 1) {
-        nsur += __shfl_xor(nsur, m, 64);
-        nfb += __shfl_xor(nfb, m, 64);
-    }
-    if (lane == 0) {
-        if (nsur) atomicAdd(P.counters, nsur);
-        if (nfb) atomicAdd(P.counters + 1, nfb);
-    }
-}
-
-void launch_band(const ElemDev& E, const BandParams& P, int mixed, hipStream_t st) {
-    if (P.cap <= 0) return;
-    long long blocks = (P.cap + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (mixed) hipLaunchKernelGGL(band_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, E, P);
-    else hipLaunchKernelGGL(band_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, E, P);
 }
 
 // Pair integrals of m separated triangle pairs with the order-k rule.

@@ -14,7 +14,9 @@
 // Features: c of the first triangle and the canonical vertices of the
 // second in the first's frame (origin a, x axis b - a, unit |b - a|), and
 // s.  Outputs: relative errors t = I / Q2 - 1 of the order-2 rule for the
-// 21 integrals SK (a <= b), ST (a <= b), X (row-major) in canonical order.
+// 21 integrals SK (a <= b), ST (a <= b), X (row-major) in canonical order;
+// the corrected values Q2 (1 + t) are then made consistent with the sum
+// rules (sur_sum_rules).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -187,6 +189,21 @@ __device__ __forceinline__ int sur_rbin_features(const double* f) {
 
 __device__ __forceinline__ int sur_sbin(double s) {
     return (s >= 0.25) + (s >= 0.5) + (s >= 0.75);
+}
+
+// The barycentric coordinates sum to 1 on each element, so every
+// quadrature of a separated pair satisfies sum_b SK_ab = sum_b X_ab and
+// sum_a ST_ab = sum_a X_ab; the network's corrections do not.  Recomputing
+// the six diagonal values from the others restores both, so the assembled
+// matrix keeps the zero row sums of its Omega x Omega part (constants stay
+// in its kernel).  SK, ST: symmetric slots 00 01 02 11 12 22; O row-major.
+__device__ __forceinline__ void sur_sum_rules(double* SK, double* ST, const double* O) {
+    SK[0] = (O[0] + O[1] + O[2]) - SK[1] - SK[2];
+    SK[3] = (O[3] + O[4] + O[5]) - SK[1] - SK[4];
+    SK[5] = (O[6] + O[7] + O[8]) - SK[2] - SK[4];
+    ST[0] = (O[0] + O[3] + O[6]) - ST[1] - ST[2];
+    ST[3] = (O[1] + O[4] + O[7]) - ST[1] - ST[4];
+    ST[5] = (O[2] + O[5] + O[8]) - ST[2] - ST[4];
 }
 
 // ------------------------------------------------------------- network --

@@ -1,6 +1,6 @@
 // Host side of the learned pair-integral surrogate (include/fraclap.h):
 // data generation, initialisation, scaling, training, inference,
-// certification and the parameters the assembly's band kernel needs.
+// certification and the surrogate parameters of an assembly.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -141,16 +141,13 @@ int need_net(fl_handle* h, bool scaling) {
 
 }  // namespace
 
-int fl_sur_band_params(fl_handle* h, double s, const fl_opts& o, BandParams* bp) {
+int fl_sur_params(fl_handle* h, double s, const fl_opts& o, SurParams* sp) {
     fl_sur& S = h->sur;
     if (!S.have || !S.have_scaling)
         return sfail(h, FL_ESTATE, "surrogate assembly needs a network with scaling (fl_surrogate_*)");
-    BandParams& B = *bp;
+    SurParams& B = *sp;
+    B.nsur = o.surrogate;
     B.s = s;
-    B.ncls = o.n_classes;
-    for (int m = 0; m < o.n_classes; ++m) B.th2[m] = o.theta[m] * o.theta[m];
-    for (int m = 0; m <= o.n_classes; ++m) B.kf[m] = o.k_far[m];
-    B.enabled = 1;
     B.N = net(h);
     for (int k = 0; k < SUR_NIN; ++k) {
         B.lo[k] = S.lo[k];
@@ -164,7 +161,7 @@ int fl_sur_band_params(fl_handle* h, double s, const fl_opts& o, BandParams* bp)
 void fl_sur_free(fl_handle* h) {
     fl_sur& S = h->sur;
     for (void* p : {(void*)S.theta, (void*)S.m, (void*)S.v, (void*)S.half, (void*)S.scal, (void*)S.part,
-                    (void*)S.loss, (void*)S.ws, (void*)S.band})
+                    (void*)S.loss, (void*)S.ws})
         if (p) (void)hipFree(p);
     S = fl_sur{};
 }

@@ -137,3 +137,36 @@ def sample_pairs(seed: int, m: int, r_range=(0.75, 3.0), size_ratio=(0.25, 4.0),
     Y = np.concatenate(Ys)[:m]
     s = rng.uniform(s_range[0], s_range[1], m)
     return np.ascontiguousarray(X), np.ascontiguousarray(Y), s
+
+
+def mesh_band_pairs(mesh, seed: int, m: int, r_max: float = 3.0, s_range=(0.05, 0.95)):
+    """m separated element pairs of a triangle mesh (no common vertex) whose
+    centroid distance is below r_max times the larger longest edge -- the
+    pairs the closest classes of the order rule hold.  Each draw takes a
+    random element K and a random such partner no larger than K.  Returns
+    X (m, 6), Y (m, 6) vertex coordinates and s (m,) uniform in s_range."""
+    from scipy.spatial import cKDTree
+    V = np.asarray(mesh["verts"], dtype=np.float64)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    P = V[C]
+    cen = P.mean(1)
+    h = np.sqrt(((P[:, [1, 2, 0]] - P) ** 2).sum(-1)).max(1)
+    rng = np.random.default_rng(seed)
+    tree = cKDTree(cen)
+    Xs, Ys = [], []
+    while len(Xs) < m:
+        K = int(rng.integers(len(C)))
+        idx = np.asarray(tree.query_ball_point(cen[K], r_max * h[K]), dtype=np.int64)
+        idx = idx[(h[idx] <= h[K]) & (idx != K)]
+        if len(idx):
+            shared = (C[idx][:, :, None] == C[K][None, None, :]).any(-1).any(-1)
+            idx = idx[~shared]
+        if len(idx) == 0:
+            continue
+        j = int(idx[rng.integers(len(idx))])
+        if ((cen[K] - cen[j]) ** 2).sum() >= (r_max * h[K]) ** 2:
+            continue
+        Xs.append(P[K].ravel())
+        Ys.append(P[j].ravel())
+    s = rng.uniform(s_range[0], s_range[1], m)
+    return np.ascontiguousarray(Xs), np.ascontiguousarray(Ys), s

@@ -111,6 +111,30 @@ def test_config2_full_size_sampled_rows(s):
     sampled_rows_parity(M.disk_for_cells(8000, seed=2), s, 10, 11)
 
 
+def test_config5_disk_100k_sampled_rows():
+    """d=2 unit disk with ~2e5 triangles: ~1e5 interior DOFs, an 80 GB FP64
+    matrix on one device.  The oracle computes 8 sampled rows (all element
+    pairs that reach them) without forming the matrix."""
+    mesh = M.disk_for_cells(200000, seed=2)
+    o = F.default_opts()
+    o.dof_mode = F.FL_DOF_INTERIOR
+    s = 0.75
+    h = gpu_assemble(mesh, s, o)
+    dofs = h.dofs()
+    n = len(dofs)
+    assert 95000 < n < 105000
+    rng = np.random.default_rng(13)
+    rows = np.unique(np.concatenate([rng.choice(n, 6, replace=False), [0, n - 1]]))
+    A = h.matrix_view()
+    Ag = A[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    Ar, _ = O.assemble_full(mesh, s, oracle_orders(o), rows=dofs[rows], compact=True)
+    Ao = Ar[:, dofs]
+    scale = np.abs(Ao).max()
+    assert np.abs(Ag - Ao).max() <= TOL * scale
+    assert np.linalg.norm(Ag - Ao) <= TOL * np.linalg.norm(Ao)
+    h.close()
+
+
 def test_config3_lshape_full_size_sampled_rows():
     """d=2 graded L-shape, ~40k triangles, size ratio up to 1:64, s = 1/2."""
     mesh = M.lshape_config3()

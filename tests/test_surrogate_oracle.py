@@ -223,6 +223,42 @@ def test_surrogate_assembly_reduces_to_quadrature(s):
     assert nsur == 0 and np.abs(Ab - A4).max() <= 1e-12 * np.abs(A4).max()
 
 
+def test_sum_rules_projection(pairs):
+    """enforce_sum_rules leaves exact (or any quadrature's) values alone and
+    makes perturbed ones consistent again."""
+    X, Y, s = pairs
+    I = S.integrals_many(s, 3, X, Y)
+    assert np.abs(S.enforce_sum_rules(I) / I - 1).max() < 1e-12
+    rng = np.random.default_rng(2)
+    P = S.enforce_sum_rules(I * (1 + 1e-2 * rng.normal(size=I.shape)))
+    Xc = P[:, 12:].reshape(-1, 3, 3)
+    rowK = np.stack([P[:, 0] + P[:, 1] + P[:, 2], P[:, 1] + P[:, 3] + P[:, 4], P[:, 2] + P[:, 4] + P[:, 5]], 1)
+    colT = np.stack([P[:, 6] + P[:, 7] + P[:, 8], P[:, 7] + P[:, 9] + P[:, 10], P[:, 8] + P[:, 10] + P[:, 11]], 1)
+    assert np.allclose(rowK, Xc.sum(2), rtol=1e-13) and np.allclose(colT, Xc.sum(1), rtol=1e-13)
+
+
+@pytest.mark.parametrize("s", [0.4, 0.8])
+def test_surrogate_assembly_zero_row_sums(s):
+    """P3: the Omega x Omega part of the matrix over all nodes has zero row
+    sums for any rule; with a random (untrained) network correcting the
+    band pairs it still does."""
+    mesh = M.disk_for_cells(300, seed=4)
+    o = O.Orders(6, 6, [1.5, 3.0, 6.0], [4, 3, 2, 2], [4, 3, 2, 2])
+    rng = np.random.default_rng(1)
+    net = _zero_net()
+    p = S.unpack(net["theta"])
+    p.update({k: v for k, v in S.unpack(G.glorot_params(3)).items() if k.startswith("W")})
+    net["theta"] = S.pack(p)
+    net["st"] = np.full(21, 0.05)
+    A, _, nsur, _ = S.assemble_surrogate(mesh, s, o, net, 2, 1e-3, full=True, with_boundary=False)
+    assert nsur > 0
+    Afull, _ = O.assemble_full(mesh, s, o, with_boundary=False)
+    assert np.abs(Afull.sum(1)).max() <= 1e-12 * np.abs(Afull).max()
+    Aomega = A
+    assert np.abs(Aomega.sum(1)).max() <= 1e-12 * np.abs(Afull).max()
+    assert np.abs(Aomega - Afull).max() > 1e-6 * np.abs(Afull).max()  # the network did change it
+
+
 def test_band_pairs_match_class_counts():
     mesh = M.disk_for_cells(300, seed=4)
     o = O.Orders(6, 6, [1.5, 3.0, 6.0], [4, 3, 2, 2], [4, 3, 2, 2])
