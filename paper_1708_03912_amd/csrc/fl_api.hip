@@ -170,6 +170,7 @@ const RuleTables& base_rules() {
     static RuleTables R = [] {
         RuleTables T;
         std::memset(&T, 0, sizeof(T));
+        for (int i = 0; i < 256; ++i) T.pw_inv[i] = (double)exp2l(-(long double)i / 256.0L);
         for (int k = 1; k <= 16; ++k) {
             gauss_jacobi01(k, 0.0, 0.0, T.gl_x + gl_off(k), T.gl_w + gl_off(k));
             gauss_jacobi01(k, 1.0, 0.0, T.gj_x + gl_off(k), T.gj_w + gl_off(k));
@@ -644,6 +645,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     RuleTables R = base_rules();
     if (s < 0.5) gauss_jacobi01(2, 0.0, -2.0 * s, R.r0_x, R.r0_w);
     gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
+    set_pow_tables(R, -(0.5 * dim + s));
     HIPCHK(upload_rules(R, h->stream));
     launch_zero(A, a_elems, h->stream);
     launch_zero(dS, T * 6, h->stream);
@@ -813,6 +815,24 @@ bool fits(fl_handle* h, double bytes) {
 }  // namespace
 
 const fl::RuleTables& fl_base_rules() { return base_rules(); }
+
+namespace fl {
+// r2^pe = 2^(pe (n + i/256)) (1 + t)^pe with 2^(n + i/256) the nearest
+// multiple of 1/256 in the exponent: tables of 2^(pe i/256) and 2^(pe n)
+// (long double, rounded once) and the Taylor coefficients C(pe, k) of
+// (1 + t)^pe, |t| < 1.4e-3 (degree 5: truncation below 5e-17).
+void set_pow_tables(RuleTables& R, double pe) {
+    const long double P = pe;
+    for (int i = 0; i < 256; ++i) R.pw_fr[i] = (double)exp2l(P * (long double)i / 256.0L);
+    for (int n = -128; n < 128; ++n) R.pw_ex[n + 128] = (double)exp2l(P * (long double)n);
+    long double c = 1.0L;
+    R.pw_c[0] = 1.0;
+    for (int k = 1; k < 8; ++k) {
+        c = c * (P - (long double)(k - 1)) / (long double)k;
+        R.pw_c[k] = (double)c;
+    }
+}
+}  // namespace fl
 
 extern "C" {
 

@@ -11,7 +11,7 @@
 namespace fl {
 
 constexpr int BE = 64;      // elements per far-field tile side
-constexpr int MAXV = 72;    // DOFs per element block kept in LDS
+constexpr int MAXV = 64;    // DOFs per element block kept in LDS
 constexpr int TRI_TAB = 204;  // sum_{k=1..8} k^2 triangle-rule points
 constexpr int GL_TAB = 136;   // sum_{k=1..16} k Gauss points
 
@@ -28,7 +28,13 @@ struct RuleTables {
     double r1_x[2], r1_w[2];            // 2-point rule, weight r^{1-2s} on [0,1]
     float trif[TRI_TAB][12];            // FP32 copies for the mixed-precision path
     float segf[36][8];
+    // kernel power r2^pe by tables (kpow_tab): 2^(-i/256), 2^(pe i/256),
+    // 2^(pe n) for n = -128..127, and the binomial coefficients C(pe, k),
+    // k = 0..5 (pe of the current assembly)
+    double pw_inv[256], pw_fr[256], pw_ex[256], pw_c[8];
 };
+// fill the pe-dependent parts of the kernel-power tables
+void set_pow_tables(RuleTables& R, double pe);
 
 __host__ __device__ inline int gl_off(int k) { return k * (k - 1) / 2; }
 __host__ __device__ inline int tri_off(int k) { return (k - 1) * k * (2 * k - 1) / 6; }

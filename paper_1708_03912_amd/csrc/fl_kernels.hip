@@ -48,8 +48,48 @@ __device__ __forceinline__ double wave_sum(double v) {
 // the wave, so the table reads are scalar loads.  KO > 0 fixes k = KO at
 // compile time (inner loop unrolled: its KO^2 kernel evaluations are
 // independent); KO = 0 takes k at run time.
-template <int KO>
-__device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, double pe,
+// Kernel power r2^pe: the series routine of fl_math.hpp ...
+struct KPow {
+    double pe;
+    __device__ __forceinline__ double operator()(double r2) const { return kpow(r2, pe); }
+};
+
+// ... or by tables held in LDS (pw: 2^(-i/256), 2^(pe i/256), 2^(pe n),
+// n = -128..127, 768 doubles) with the coefficients C(pe, k): the hardware
+// FP32 log2 picks the nearest 2^(n + i/256), the remaining factor 1 + t
+// (|t| < 1.4e-3) is raised to pe by its degree-5 Taylor polynomial.  10
+// FP64 operations instead of ~38; relative error ~5e-15 for r2 in
+// [2^-128, 2^127) (exponents outside are clamped to the table).
+struct KPowTab {
+    const double* pw;
+    double c1, c2, c3, c4, c5;
+    __device__ __forceinline__ double operator()(double r2) const {
+        const float l = __builtin_amdgcn_logf((float)r2);
+        int q = (int)__builtin_rintf(l * 256.f);
+        q = q < -32768 ? -32768 : (q > 32767 ? 32767 : q);
+        const int n = q >> 8, i = q & 255;
+        const double t = ldexp(r2, -n) * pw[i] - 1.0;
+        double p = fma(c5, t, c4);
+        p = fma(p, t, c3);
+        p = fma(p, t, c2);
+        p = fma(p, t, c1);
+        p = fma(p, t, 1.0);
+        return (p * pw[256 + i]) * pw[512 + 128 + n];
+    }
+};
+
+__device__ __forceinline__ KPowTab make_kpow_tab(const double* pw_lds) {
+    return KPowTab{pw_lds, c_R.pw_c[1], c_R.pw_c[2], c_R.pw_c[3], c_R.pw_c[4], c_R.pw_c[5]};
+}
+
+// copy the table part of c_R into LDS (768 doubles; caller synchronises)
+__device__ __forceinline__ void load_pow_tables(double* pw) {
+    for (int i = threadIdx.x; i < 768; i += blockDim.x)
+        pw[i] = i < 256 ? c_R.pw_inv[i] : (i < 512 ? c_R.pw_fr[i - 256] : c_R.pw_ex[i - 512]);
+}
+
+template <int KO, class KP>
+__device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, const KP& kp,
                                           double* SK, double* ST, double* O) {
     if (KO > 0) k = KO;
     const int Q = k * k;
@@ -60,6 +100,17 @@ __device__ __forceinline__ void far_pair2(int k, const double* X, const double* 
     for (int m = 0; m < 9; ++m) O[m] = 0.0;
     const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
     const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
+    // fixed order: K's points once, outside the loop over Kt's points
+    constexpr int QP = KO > 0 ? KO * KO : 1;
+    double px[QP], py[QP];
+    if constexpr (KO > 0) {
+#pragma unroll
+        for (int p = 0; p < QP; ++p) {
+            const double* cp = c_R.tri[off + p];
+            px[p] = X[0] + cp[0] * ex0 + cp[1] * ex1;
+            py[p] = X[1] + cp[0] * ey0 + cp[1] * ey1;
+        }
+    }
 #pragma unroll 1
     for (int q = 0; q < Q; ++q) {
         const double* cq = c_R.tri[off + q];
@@ -69,9 +120,15 @@ __device__ __forceinline__ void far_pair2(int k, const double* X, const double* 
         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
         auto body = [&](int p) {
             const double* cp = c_R.tri[off + p];
-            const double dx = (X[0] + cp[0] * ex0 + cp[1] * ex1) - yx;
-            const double dy = (X[1] + cp[0] * ey0 + cp[1] * ey1) - yy;
-            const double kv = kpow(dx * dx + dy * dy, pe);
+            double dx, dy;
+            if constexpr (KO > 0) {
+                dx = px[p] - yx;
+                dy = py[p] - yy;
+            } else {
+                dx = (X[0] + cp[0] * ex0 + cp[1] * ex1) - yx;
+                dy = (X[1] + cp[0] * ey0 + cp[1] * ey1) - yy;
+            }
+            const double kv = kp(dx * dx + dy * dy);
             gy += cp[2] * kv;
             n0 += cp[3] * kv;
             n1 += cp[4] * kv;
@@ -101,6 +158,12 @@ __device__ __forceinline__ void far_pair2(int k, const double* X, const double* 
 #pragma unroll
             for (int b = 0; b < 3; ++b) O[3 * a + b] += cq[3 + b] * na[a];
     }
+}
+
+template <int KO>
+__device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, double pe, double* SK,
+                                          double* ST, double* O) {
+    far_pair2<KO>(k, X, Y, KPow{pe}, SK, ST, O);
 }
 
 // Separated segments, k-point Gauss-Legendre on both (same outputs, slots
@@ -243,16 +306,23 @@ __device__ __forceinline__ void far_pair1_f32(int k, const double* X, const doub
     O[0] = o0; O[1] = o1; O[3] = o3; O[4] = o4;
 }
 
-template <int DIM, int MIX>
-__device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe,
+// runtime order k; kp evaluates the FP64 kernel power of 2D pairs
+template <int DIM, int MIX, class KP>
+__device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe, const KP& kp,
                                          double* SK, double* ST, double* O) {
     if (DIM == 2) {
         if (MIX) far_pair2_f32<0>(k, X, Y, pe, SK, ST, O);
-        else far_pair2<0>(k, X, Y, pe, SK, ST, O);
+        else far_pair2<0>(k, X, Y, kp, SK, ST, O);
     } else {
         if (MIX) far_pair1_f32(k, X, Y, pe, SK, ST, O);
         else far_pair1(k, X, Y, pe, SK, ST, O);
     }
+}
+
+template <int DIM, int MIX>
+__device__ __forceinline__ void far_pair(int k, const double* X, const double* Y, double pe, double* SK,
+                                         double* ST, double* O) {
+    far_pair<DIM, MIX>(k, X, Y, pe, KPow{pe}, SK, ST, O);
 }
 
 // Order class: #{m : d2 >= theta_m^2 * max(h2K, h2Kt)}.  Every product and
@@ -291,6 +361,8 @@ template <int DIM, int FARK, int MIX>
 __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
+    constexpr bool TAB = DIM == 2 && !MIX;  // FP64 kernel power by LDS tables
+    __shared__ double pw[TAB ? 768 : 1];
     __shared__ double L[MAXV * MAXV];
     __shared__ double SI[BE * 6];
     __shared__ double SJ[BE * 6];
@@ -323,6 +395,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     }
     for (int i = tid; i < BE * 6; i += 256) { SI[i] = 0.0; SJ[i] = 0.0; }
     if (tid <= FL_MAX_CLASSES) ccount[tid] = 0;
+    if constexpr (TAB) load_pow_tables(pw);
     for (int i = tid; i < 13 * BE; i += 256) {
         const int f = i / BE, r = i - f * BE, K = I0 + r;
         if (f < 10) {
@@ -397,8 +470,8 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
         if (FARK > 0) {
             if (valid) {
                 if (DIM == 2) {
-                    if (MIX) far_pair2_f32<FARK>(FARK, X, Y, P.pe, SK, ST, O);
-                    else far_pair2<FARK>(FARK, X, Y, P.pe, SK, ST, O);
+                    if constexpr (MIX) far_pair2_f32<FARK>(FARK, X, Y, P.pe, SK, ST, O);
+                    else far_pair2<FARK>(FARK, X, Y, make_kpow_tab(pw), SK, ST, O);
                 } else {
                     if (MIX) far_pair1_f32(FARK, X, Y, P.pe, SK, ST, O);
                     else far_pair1(FARK, X, Y, P.pe, SK, ST, O);
@@ -414,7 +487,10 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 if (!P.kfirst[c]) continue;
                 const int kc = P.kf[c];
                 if (__any(myk == kc)) {
-                    if (myk == kc) far_pair<DIM, MIX>(kc, X, Y, P.pe, SK, ST, O);
+                    if (myk == kc) {
+                        if constexpr (TAB) far_pair<DIM, MIX>(kc, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
+                        else far_pair<DIM, MIX>(kc, X, Y, P.pe, SK, ST, O);
+                    }
                 }
             }
         }
@@ -505,6 +581,8 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ unsigned short plist[BE * BE];
     __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
     __shared__ float souts[SUR ? 4 * 16 * 24 : 1];  // network outputs, 16 samples per wave
+    constexpr bool TAB = DIM == 2 && !MIX && !SUR;   // FP64 kernel power by LDS tables
+    __shared__ double pw[TAB ? 768 : 1];
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -529,6 +607,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     }
     for (int i = tid; i < BE * 6; i += 256) { SI[i] = 0.0; SJ[i] = 0.0; }
     if (tid <= FL_MAX_CLASSES) { ccnt[tid] = 0; cfill[tid] = 0; }
+    if constexpr (TAB) load_pow_tables(pw);
     for (int i = tid; i < 13 * BE; i += 256) {
         const int f = i / BE, r = i - f * BE;
         const int K = I0 + r, Kt = J0 + r;
@@ -771,7 +850,8 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 #pragma unroll
             for (int q = 0; q < NC; ++q) { X[q] = sI[q][r]; Y[q] = sJ[q][l]; }
             double SK[6], ST[6], O[9];
-            far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
+            if constexpr (TAB) far_pair<DIM, MIX>(k, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
+            else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
             const double f = P.C * sI[9][r] * sJ[9][l];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
