@@ -409,7 +409,18 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             for (int64_t K = 0; K < T; ++K)
                 key[K] = ((uint64_t)((cx[K] - lo0) / span * 4294967295.0) << 32) | (uint64_t)K;
         }
-        std::sort(key.begin(), key.end());
+        // stable LSD radix sort on the 32-bit position code (upper half of
+        // the key): equal codes keep increasing K, as a sort of the key would
+        std::vector<uint64_t> tmp(T);
+        for (int pass = 0; pass < 4; ++pass) {
+            const int sh = 32 + 8 * pass;
+            size_t cnt[257] = {0};
+            for (int64_t K = 0; K < T; ++K) cnt[((key[K] >> sh) & 0xff) + 1]++;
+            if (cnt[((key[0] >> sh) & 0xff) + 1] == (size_t)T) continue;  // one bucket: nothing to do
+            for (int b = 0; b < 256; ++b) cnt[b + 1] += cnt[b];
+            for (int64_t K = 0; K < T; ++K) tmp[cnt[(key[K] >> sh) & 0xff]++] = key[K];
+            key.swap(tmp);
+        }
         for (int64_t K = 0; K < T; ++K) perm[K] = (int32_t)(key[K] & 0xffffffffu);
     }
     // element SoA in internal order
@@ -464,8 +475,11 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     // touching pairs (Sec. 5): K < Kt sharing dim vertices (common edge, 2D)
     // or one vertex; shared-vertex counts through a marker array
     std::vector<int> edge_pairs, vert_pairs;
+    edge_pairs.reserve((size_t)T * 4);
+    vert_pairs.reserve((size_t)T * 12);
     {
         std::vector<int> mark(T, -1), cnt(T, 0), seen;
+        seen.reserve(64);
         for (int64_t Ki = 0; Ki < T; ++Ki) {
             seen.clear();
             for (int a = 0; a < nper; ++a) {
@@ -481,7 +495,7 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
                     cnt[Kt]++;
                 }
             }
-            std::sort(seen.begin(), seen.end());
+            // (first-seen order: deterministic; the touching kernels add into A)
             for (int Kt : seen) {
                 int sh = cnt[Kt];
                 if (dim == 2 && sh == 2) { edge_pairs.push_back((int)Ki); edge_pairs.push_back(Kt); }
@@ -526,22 +540,30 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
     std::vector<unsigned char> loc(T * 3, 255);
     {
-        std::vector<int> ds;
+        // distinct DOFs of each block (marker array), sorted, and each
+        // element vertex's index among them
+        std::vector<int> ds, mark(n, -1), pos(n, 0);
         for (int b = 0; b < nblk; ++b) {
             ds.clear();
             const int64_t k0 = (int64_t)b * BE, k1 = std::min<int64_t>(T, (int64_t)(b + 1) * BE);
             for (int64_t Ki = k0; Ki < k1; ++Ki)
-                for (int a = 0; a < nper; ++a)
-                    if (dof[a][Ki] >= 0) ds.push_back(dof[a][Ki]);
+                for (int a = 0; a < nper; ++a) {
+                    const int d = dof[a][Ki];
+                    if (d >= 0 && mark[d] != b) {
+                        mark[d] = b;
+                        ds.push_back(d);
+                    }
+                }
             std::sort(ds.begin(), ds.end());
-            ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
             blk_ndof[b] = (int)ds.size();
             if ((int)ds.size() > MAXV) continue;  // tile falls back to global atomics
-            for (size_t i = 0; i < ds.size(); ++i) blk_dofs[(size_t)b * MAXV + i] = ds[i];
+            for (size_t i = 0; i < ds.size(); ++i) {
+                blk_dofs[(size_t)b * MAXV + i] = ds[i];
+                pos[ds[i]] = (int)i;
+            }
             for (int64_t Ki = k0; Ki < k1; ++Ki)
                 for (int a = 0; a < nper; ++a)
-                    if (dof[a][Ki] >= 0)
-                        loc[Ki * 3 + a] = (unsigned char)(std::lower_bound(ds.begin(), ds.end(), dof[a][Ki]) - ds.begin());
+                    if (dof[a][Ki] >= 0) loc[Ki * 3 + a] = (unsigned char)pos[dof[a][Ki]];
         }
     }
     // boundary facets: coordinates, inward unit normal (Sec. 2)

@@ -1533,20 +1533,58 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ a, const do
     return wave_sum((acc0 + acc1) + (acc2 + acc3));
 }
 
+// Two rows per wave: every vector chunk loaded from cache serves both rows,
+// which halves the vector traffic (each row reads all of x).
+__device__ __forceinline__ void row_dot2(const double* __restrict__ a, const double* __restrict__ b,
+                                         const double* __restrict__ x, long long n, int lane, double& va,
+                                         double& vb) {
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    const long long n2 = n & ~1LL;
+    long long j = 2 * lane;
+    for (; j + 2 * 64 < n2; j += 4 * 64) {
+        const double2 x0 = *(const double2*)(x + j), x1 = *(const double2*)(x + j + 128);
+        const double2 p0 = *(const double2*)(a + j), p1 = *(const double2*)(a + j + 128);
+        const double2 q0 = *(const double2*)(b + j), q1 = *(const double2*)(b + j + 128);
+        a0 += p0.x * x0.x + p0.y * x0.y;
+        a1 += p1.x * x1.x + p1.y * x1.y;
+        b0 += q0.x * x0.x + q0.y * x0.y;
+        b1 += q1.x * x1.x + q1.y * x1.y;
+    }
+    for (; j < n2; j += 128) {
+        const double2 x0 = *(const double2*)(x + j), p0 = *(const double2*)(a + j), q0 = *(const double2*)(b + j);
+        a0 += p0.x * x0.x + p0.y * x0.y;
+        b0 += q0.x * x0.x + q0.y * x0.y;
+    }
+    if ((n & 1) && lane == 0) {
+        a1 += a[n - 1] * x[n - 1];
+        b1 += b[n - 1] * x[n - 1];
+    }
+    va = wave_sum(a0 + a1);
+    vb = wave_sum(b0 + b1);
+}
+
+constexpr int MV2_ROWS_PER_BLOCK = 2 * (MV_THREADS / 64);
+int mv2_blocks(long long n) { return (int)((n + MV2_ROWS_PER_BLOCK - 1) / MV2_ROWS_PER_BLOCK); }
+
 __global__ __launch_bounds__(MV_THREADS) void matvec_kernel(const double* __restrict__ A, long long lda,
                                                             long long n, const double* __restrict__ x,
                                                             double* __restrict__ y) {
-    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const long long row = 2 * ((long long)blockIdx.x * (MV_THREADS / 64) + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    double v = row_dot(A + row * lda, x, n, lane);
-    if (lane == 0) y[row] = v;
+    const bool two = row + 1 < n;
+    double v0, v1;
+    row_dot2(A + row * lda, A + (two ? row + 1 : row) * lda, x, n, lane, v0, v1);
+    if (lane == 0) {
+        y[row] = v0;
+        if (two) y[row + 1] = v1;
+    }
 }
 
 void launch_matvec(const double* A, long long lda, long long n, const double* x, double* y,
                    hipStream_t st) {
     if (n == 0) return;
-    hipLaunchKernelGGL(matvec_kernel, dim3(mv_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, y);
+    hipLaunchKernelGGL(matvec_kernel, dim3(mv2_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, y);
 }
 
 __global__ void diag_kernel(const double* A, long long lda, long long n, double* d) {
@@ -1649,6 +1687,42 @@ __device__ __forceinline__ double row_dot_comb(const double* __restrict__ a, con
     return wave_sum((acc0 + acc1) + (acc2 + acc3));
 }
 
+// two rows per wave of A (z + beta p_prev) with the direction combined on
+// the fly (shared by both rows)
+__device__ __forceinline__ void row_dot_comb2(const double* __restrict__ a, const double* __restrict__ b,
+                                              const double* __restrict__ z, const double* __restrict__ pp,
+                                              double beta, long long n, int lane, double& va, double& vb) {
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    const long long n2 = n & ~1LL;
+    long long j = 2 * lane;
+    for (; j + 2 * 64 < n2; j += 4 * 64) {
+        const double2 z0 = *(const double2*)(z + j), z1 = *(const double2*)(z + j + 128);
+        const double2 r0 = *(const double2*)(pp + j), r1 = *(const double2*)(pp + j + 128);
+        const double2 p0 = *(const double2*)(a + j), p1 = *(const double2*)(a + j + 128);
+        const double2 q0 = *(const double2*)(b + j), q1 = *(const double2*)(b + j + 128);
+        const double c0x = z0.x + beta * r0.x, c0y = z0.y + beta * r0.y;
+        const double c1x = z1.x + beta * r1.x, c1y = z1.y + beta * r1.y;
+        a0 += p0.x * c0x + p0.y * c0y;
+        a1 += p1.x * c1x + p1.y * c1y;
+        b0 += q0.x * c0x + q0.y * c0y;
+        b1 += q1.x * c1x + q1.y * c1y;
+    }
+    for (; j < n2; j += 128) {
+        const double2 z0 = *(const double2*)(z + j), r0 = *(const double2*)(pp + j);
+        const double2 p0 = *(const double2*)(a + j), q0 = *(const double2*)(b + j);
+        const double cx = z0.x + beta * r0.x, cy = z0.y + beta * r0.y;
+        a0 += p0.x * cx + p0.y * cy;
+        b0 += q0.x * cx + q0.y * cy;
+    }
+    if ((n & 1) && lane == 0) {
+        const double c = z[n - 1] + beta * pp[n - 1];
+        a1 += a[n - 1] * c;
+        b1 += b[n - 1] * c;
+    }
+    va = wave_sum(a0 + a1);
+    vb = wave_sum(b0 + b1);
+}
+
 __global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S, int it, int nmv) {
     __shared__ double sh[4];
     if (*(volatile int*)&S.flag[0]) return;
@@ -1669,16 +1743,25 @@ __global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S, int it
     if (it > 0) beta = rz / sum_partials(S.part + (1 - par) * S.nblk, S.nblk, sh);
     const double* pprev = S.p + (long long)(1 - par) * S.n;
     double* pcur = S.p + (long long)par * S.n;
-    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
+    const long long row = 2 * ((long long)blockIdx.x * (MV_THREADS / 64) + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     double pq = 0.0;
     if (row < S.n) {
-        double v = row_dot_comb(S.A + row * S.lda, S.z, pprev, beta, S.n, lane);
+        const bool two = row + 1 < S.n;
+        double v0, v1;
+        row_dot_comb2(S.A + row * S.lda, S.A + (two ? row + 1 : row) * S.lda, S.z, pprev, beta, S.n, lane, v0,
+                      v1);
         if (lane == 0) {
             const double pr = S.z[row] + beta * pprev[row];
             pcur[row] = pr;
-            S.q[row] = v;
-            pq = v * pr;
+            S.q[row] = v0;
+            pq = v0 * pr;
+            if (two) {
+                const double pr1 = S.z[row + 1] + beta * pprev[row + 1];
+                pcur[row + 1] = pr1;
+                S.q[row + 1] = v1;
+                pq += v1 * pr1;
+            }
         }
     }
     double t = block_sum(pq, sh);
@@ -1733,7 +1816,7 @@ void launch_cg_init(const CgState& s, hipStream_t st) {
 }
 
 void launch_cg_iter_at(const CgState& s, int it, hipStream_t st) {
-    int nmv = mv_blocks(s.n);
+    int nmv = mv2_blocks(s.n);
     hipLaunchKernelGGL(cg_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s, it, nmv);
     hipLaunchKernelGGL(cg_update_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
 }
