@@ -36,6 +36,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sums over the wave of six values at once (halving exchange): after the
+// xor-32 / 16 / 8 steps each lane holds a partial sum of one slot
+// m = 4 b5 + 2 b4 + b3 (b: lane bits), the xor-4 / 2 / 1 steps finish it;
+// lane 8 m returns the sum of v[m] (m < 6).  10 exchanges instead of 36.
+__device__ __forceinline__ double wave_sum6(const double* v, int lane) {
+    const int h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1;
+    double w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double mine = (4 * h5 + j) < 6 ? v[4 * h5 + j] : 0.0;
+        const double give = (4 * (1 - h5) + j) < 6 ? v[4 * (1 - h5) + j] : 0.0;
+        w[j] = mine + __shfl_xor(give, 32, 64);
+    }
+    double x[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) x[j] = w[2 * h4 + j] + __shfl_xor(w[2 * (1 - h4) + j], 16, 64);
+    double y = x[h3] + __shfl_xor(x[1 - h3], 8, 64);
+    y += __shfl_xor(y, 4, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
 // ----------------------------------------------------------- separated --
 
 // Separated triangles with the order-k collapsed rule on both.  X, Y:
@@ -54,8 +77,8 @@ struct KPow {
     __device__ __forceinline__ double operator()(double r2) const { return kpow(r2, pe); }
 };
 
-// ... or by tables held in LDS (pw: 2^(-i/256), 2^(pe i/256), 2^(pe n),
-// n = -128..127, 768 doubles) with the coefficients C(pe, k): the hardware
+// ... or by tables held in LDS (pw: pairs (2^(-i/256), 2^(pe i/256)), then
+// 2^(pe n), n = -128..127; 768 doubles) with the coefficients C(pe, k): the hardware
 // FP32 log2 picks the nearest 2^(n + i/256), the remaining factor 1 + t
 // (|t| < 1.4e-3) is raised to pe by its degree-5 Taylor polynomial.  10
 // FP64 operations instead of ~38; relative error ~5e-15 for r2 in
@@ -68,13 +91,14 @@ struct KPowTab {
         int q = (int)__builtin_rintf(l * 256.f);
         q = q < -32768 ? -32768 : (q > 32767 ? 32767 : q);
         const int n = q >> 8, i = q & 255;
-        const double t = ldexp(r2, -n) * pw[i] - 1.0;
+        const double2 f = ((const double2*)pw)[i];  // 2^(-i/256), 2^(pe i/256)
+        const double t = ldexp(r2, -n) * f.x - 1.0;
         double p = fma(c5, t, c4);
         p = fma(p, t, c3);
         p = fma(p, t, c2);
         p = fma(p, t, c1);
         p = fma(p, t, 1.0);
-        return (p * pw[256 + i]) * pw[512 + 128 + n];
+        return (p * f.y) * pw[512 + 128 + n];
     }
 };
 
@@ -85,7 +109,7 @@ __device__ __forceinline__ KPowTab make_kpow_tab(const double* pw_lds) {
 // copy the table part of c_R into LDS (768 doubles; caller synchronises)
 __device__ __forceinline__ void load_pow_tables(double* pw) {
     for (int i = threadIdx.x; i < 768; i += blockDim.x)
-        pw[i] = i < 256 ? c_R.pw_inv[i] : (i < 512 ? c_R.pw_fr[i - 256] : c_R.pw_ex[i - 512]);
+        pw[i] = i < 512 ? ((i & 1) ? c_R.pw_fr[i >> 1] : c_R.pw_inv[i >> 1]) : c_R.pw_ex[i - 512];
 }
 
 template <int KO, class KP>
@@ -362,7 +386,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
     constexpr bool TAB = DIM == 2 && !MIX;  // FP64 kernel power by LDS tables
-    __shared__ double pw[TAB ? 768 : 1];
+    __shared__ __align__(16) double pw[TAB ? 768 : 1];
     __shared__ double L[MAXV * MAXV];
     __shared__ double SI[BE * 6];
     __shared__ double SJ[BE * 6];
@@ -500,11 +524,11 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
             SK[m] *= f;
             STacc[m] += ST[m] * f;
         }
-        // diagonal block of K: reduce over the wave, this wave owns row r
-#pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            double v = wave_sum(SK[m]);
-            if (lane == 0) SI[r * 6 + m] += v;
+        // diagonal block of K: reduce over the wave (this wave owns row r);
+        // the six sums end in lanes 0, 8, ..., 40
+        {
+            const double v = wave_sum6(SK, lane);
+            if ((lane & 7) == 0 && (lane >> 3) < 6) SI[r * 6 + (lane >> 3)] += v;
         }
         if (valid) {
             if (!direct) {
@@ -582,7 +606,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
     __shared__ float souts[SUR ? 4 * 16 * 24 : 1];  // network outputs, 16 samples per wave
     constexpr bool TAB = DIM == 2 && !MIX && !SUR;   // FP64 kernel power by LDS tables
-    __shared__ double pw[TAB ? 768 : 1];
+    __shared__ __align__(16) double pw[TAB ? 768 : 1];
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
