@@ -434,6 +434,24 @@ def surrogate_leg(args):
     h.surrogate_predict(fv, pred)
     err = (pred - tv).abs()
     t3 = time.perf_counter()
+    # network throughput on the matrix cores: inference over 2^20 feature
+    # rows (held-out rows repeated), timed with events on the stream
+    big = fv.repeat((1 << 20) // fv.shape[0] + 1, 1)[:1 << 20].contiguous()
+    outp = torch.empty(big.shape[0], 21, dtype=torch.float64, device="cuda")
+    h.surrogate_predict(big, outp)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        h.surrogate_predict(big, outp)
+    ev1.record()
+    torch.cuda.synchronize()
+    inf_ms = ev0.elapsed_time(ev1) / 5
+    flops_pair = 2 * (32 * 64 + 64 * 64 + 64 * 32)  # padded layers, as executed
+    out["network_inference"] = {"pairs": int(big.shape[0]), "ms": round(inf_ms, 4),
+                                "pairs_per_s": round(big.shape[0] / (inf_ms * 1e-3), 1),
+                                "mfma_tflops": round(big.shape[0] * flops_pair / (inf_ms * 1e-3) / 1e12, 2),
+                                "peak_tflops": 2500.0, "flops_per_pair": flops_pair,
+                                "note": "includes reading 72 B of FP64 features and writing 168 B of FP64 targets per pair"}
     out["train"] = {"pairs": int(ft.shape[0]), "heldout_pairs": int(fv.shape[0]), "steps": topt.steps,
                     "batch": topt.batch, "dataset_ms": round((t1 - t0) * 1e3, 2),
                     "train_ms": round((t2 - t1) * 1e3, 2), "certify_ms": round((t3 - t2) * 1e3, 2),
