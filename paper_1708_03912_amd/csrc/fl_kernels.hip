@@ -112,9 +112,74 @@ __device__ __forceinline__ void load_pow_tables(double* pw) {
         pw[i] = i < 512 ? ((i & 1) ? c_R.pw_fr[i >> 1] : c_R.pw_inv[i >> 1]) : c_R.pw_ex[i - 512];
 }
 
+// Fixed order KO: factorised sums.  With k_pq = k(x_p, y_q) and the rule's
+// weights w and barycentric values l:
+//   G_p = sum_q w_q k_pq,  H_q = sum_p w_p k_pq,  M_pb = sum_q w_q l_b(y_q) k_pq,
+//   SK_ab = sum_p w_p l_a l_b(x_p) G_p,  ST_ab = sum_q w_q l_a l_b(y_q) H_q,
+//   O_ab = sum_p w_p l_a(x_p) M_pb.
+// Five accumulations per kernel evaluation, and the loop over Kt's points
+// needs only the current point's constants plus the KO^2 weights w_p.
+template <int KO, class KP>
+__device__ __forceinline__ void far_pair2_fixed(const double* X, const double* Y, const KP& kp, double* SK,
+                                                double* ST, double* O) {
+    constexpr int Q = KO * KO;
+    const int off = tri_off(KO);
+    const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
+    const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
+    double px[Q], py[Q], G[Q], M[Q][3];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const double* cp = c_R.tri[off + p];
+        px[p] = X[0] + cp[0] * ex0 + cp[1] * ex1;
+        py[p] = X[1] + cp[0] * ey0 + cp[1] * ey1;
+        G[p] = 0.0;
+        M[p][0] = M[p][1] = M[p][2] = 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) ST[m] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        const double* cq = c_R.tri[off + q];
+        const double yx = Y[0] + cq[0] * fx0 + cq[1] * fx1;
+        const double yy = Y[1] + cq[0] * fy0 + cq[1] * fy1;
+        const double wq = cq[2], v0 = cq[3], v1 = cq[4], v2 = cq[5];
+        double H = 0.0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const double dx = px[p] - yx, dy = py[p] - yy;
+            const double kv = kp(dx * dx + dy * dy);
+            G[p] += wq * kv;
+            H += c_R.tri[off + p][2] * kv;
+            M[p][0] += v0 * kv;
+            M[p][1] += v1 * kv;
+            M[p][2] += v2 * kv;
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ST[m] += cq[6 + m] * H;
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) SK[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) O[m] = 0.0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const double* cp = c_R.tri[off + p];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) SK[m] += cp[6 + m] * G[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) O[3 * a + b] += cp[3 + a] * M[p][b];
+    }
+}
+
 template <int KO, class KP>
 __device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, const KP& kp,
                                           double* SK, double* ST, double* O) {
+    if constexpr (KO > 0) {
+        far_pair2_fixed<KO>(X, Y, kp, SK, ST, O);
+        return;
+    }
     if (KO > 0) k = KO;
     const int Q = k * k;
     const int off = tri_off(k);
@@ -233,9 +298,71 @@ __device__ __forceinline__ float kpow32(float r2, float pe) {
     return __builtin_amdgcn_exp2f(pe * __builtin_amdgcn_logf(r2));
 }
 
+// FP32 counterpart of far_pair2_fixed (sums within the pair in FP32)
+template <int KO>
+__device__ __forceinline__ void far_pair2_f32_fixed(const double* X, const double* Y, double pe64, double* SK,
+                                                    double* ST, double* O) {
+    constexpr int Q = KO * KO;
+    const int off = tri_off(KO);
+    const float pe = (float)pe64;
+    const float ox = (float)(X[0] - Y[0]), oy = (float)(X[1] - Y[1]);
+    const float ex0 = (float)(X[2] - X[0]), ey0 = (float)(X[3] - X[1]);
+    const float ex1 = (float)(X[4] - X[0]), ey1 = (float)(X[5] - X[1]);
+    const float fx0 = (float)(Y[2] - Y[0]), fy0 = (float)(Y[3] - Y[1]);
+    const float fx1 = (float)(Y[4] - Y[0]), fy1 = (float)(Y[5] - Y[1]);
+    float px[Q], py[Q], G[Q], M[Q][3], st[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float* cp = c_R.trif[off + p];
+        px[p] = cp[0] * ex0 + cp[1] * ex1;
+        py[p] = cp[0] * ey0 + cp[1] * ey1;
+        G[p] = 0.f;
+        M[p][0] = M[p][1] = M[p][2] = 0.f;
+    }
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        const float* cq = c_R.trif[off + q];
+        const float yx = cq[0] * fx0 + cq[1] * fx1 - ox;
+        const float yy = cq[0] * fy0 + cq[1] * fy1 - oy;
+        const float wq = cq[2], v0 = cq[3], v1 = cq[4], v2 = cq[5];
+        float H = 0.f;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const float dx = px[p] - yx, dy = py[p] - yy;
+            const float kv = kpow32(dx * dx + dy * dy, pe);
+            G[p] += wq * kv;
+            H += c_R.trif[off + p][2] * kv;
+            M[p][0] += v0 * kv;
+            M[p][1] += v1 * kv;
+            M[p][2] += v2 * kv;
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) st[m] += cq[6 + m] * H;
+    }
+    float sk[6] = {0, 0, 0, 0, 0, 0}, oo[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float* cp = c_R.trif[off + p];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) sk[m] += cp[6 + m] * G[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) oo[3 * a + b] += cp[3 + a] * M[p][b];
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { SK[m] = sk[m]; ST[m] = st[m]; }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) O[m] = oo[m];
+}
+
 template <int KO>
 __device__ __forceinline__ void far_pair2_f32(int k, const double* X, const double* Y, double pe64,
                                               double* SK, double* ST, double* O) {
+    if constexpr (KO > 0) {
+        far_pair2_f32_fixed<KO>(X, Y, pe64, SK, ST, O);
+        return;
+    }
     if (KO > 0) k = KO;
     const int Q = k * k;
     const int off = tri_off(k);
