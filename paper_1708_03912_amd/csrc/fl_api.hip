@@ -302,6 +302,32 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
             meas = 0.5 * std::fabs((b[0] - a[0]) * (d[1] - a[1]) - (d[0] - a[0]) * (b[1] - a[1]));
         }
         if (!(meas > 0.0)) return fail(h, FL_EMESH, "degenerate cell " + std::to_string(K));
+        if (dim == 2) {
+            // The FP64 kernel power of the separated-pair kernels covers
+            // squared distances in [2^-125, 2^126).  A quadrature point of a
+            // triangle lies at least (smallest barycentric coordinate) x
+            // (smallest height) from its boundary: above 2^-11 x 2 x inradius
+            // for the rules of order <= 8, so separated pairs stay above
+            // 2^-114 for inradii >= 2^-48; no two points are further apart
+            // than the coordinate extent.
+            const double* a = verts + 2 * c[0];
+            const double* b = verts + 2 * c[1];
+            const double* d = verts + 2 * c[2];
+            const double per = std::hypot(b[0] - a[0], b[1] - a[1]) + std::hypot(d[0] - b[0], d[1] - b[1]) +
+                               std::hypot(a[0] - d[0], a[1] - d[1]);
+            if (!(2.0 * meas / per >= 0x1p-48))
+                return fail(h, FL_EMESH, "cell " + std::to_string(K) + " below the supported scale (inradius < 2^-48)");
+        }
+    }
+    if (dim == 2) {
+        double lo[2] = {verts[0], verts[1]}, hi[2] = {verts[0], verts[1]};
+        for (int64_t v = 0; v < nv; ++v)
+            for (int j = 0; j < 2; ++j) {
+                lo[j] = std::min(lo[j], verts[2 * v + j]);
+                hi[j] = std::max(hi[j], verts[2 * v + j]);
+            }
+        if (!(std::hypot(hi[0] - lo[0], hi[1] - lo[1]) < 0x1p60))
+            return fail(h, FL_EMESH, "mesh extent above the supported scale (2^60)");
     }
     // vertex -> cells (CSR) to find the cell owning each boundary facet
     std::vector<int32_t> ptr(nv + 1, 0), idx(nc * nper);

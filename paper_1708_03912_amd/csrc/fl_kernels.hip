@@ -1001,8 +1001,15 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 #pragma unroll
             for (int q = 0; q < NC; ++q) { X[q] = sI[q][r]; Y[q] = sJ[q][l]; }
             double SK[6], ST[6], O[9];
-            if constexpr (TAB) far_pair<DIM, MIX>(k, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
-            else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
+            if (DIM == 2 && k == 2) {
+                // the commonest order in near tiles: the unrolled fixed-order rule
+                if constexpr (MIX) far_pair2_f32<2>(2, X, Y, P.pe, SK, ST, O);
+                else if constexpr (TAB) far_pair2<2>(2, X, Y, make_kpow_tab(pw), SK, ST, O);
+                else far_pair2<2>(2, X, Y, P.pe, SK, ST, O);
+            } else {
+                if constexpr (TAB) far_pair<DIM, MIX>(k, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
+                else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
+            }
             const double f = P.C * sI[9][r] * sJ[9][l];
 #pragma unroll
             for (int m = 0; m < 6; ++m) {

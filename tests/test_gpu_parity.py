@@ -242,6 +242,16 @@ def test_error_paths():
     with pytest.raises(F.FraclapError) as e:
         h.set_mesh(nof)
     assert e.value.code == F.FL_EMESH
+    # scales outside the range of the FP64 kernel-power tables are refused
+    for f in (2.0 ** -56, 2.0 ** 62):
+        sc = dict(mesh)
+        sc["verts"] = mesh["verts"] * f
+        with pytest.raises(F.FraclapError) as e:
+            h.set_mesh(sc)
+        assert e.value.code == F.FL_EMESH
+    ok = dict(mesh)
+    ok["verts"] = mesh["verts"] * 2.0 ** -40
+    h.set_mesh(ok)
     h.close()
 
 
@@ -266,6 +276,25 @@ def test_repeatable():
     assert np.abs(A1 - A2).max() <= 1e-14 * np.abs(A1).max()
     h1.close()
     h2.close()
+
+
+@pytest.mark.parametrize("s", [0.3, 0.8])
+def test_scale_homogeneity(s):
+    """The bilinear form is homogeneous (Sec. 2, kernel |x-y|^(-d-2s)):
+    scaling every coordinate by a power of two f multiplies the matrix by
+    f^(d-2s) up to rounding.  Scales 2^-40 and 2^40 drive the separated-pair
+    kernel powers far from 1 (both ends of their exponent tables)."""
+    mesh = M.disk_for_cells(800, seed=3)
+    A = gpu_assemble(mesh, s, F.default_opts())
+    A1 = A.export_matrix()
+    A.close()
+    for e in (-40, 40):
+        sc = dict(mesh)
+        sc["verts"] = mesh["verts"] * 2.0 ** e
+        h = gpu_assemble(sc, s, F.default_opts())
+        Af = h.export_matrix() / 2.0 ** (e * (2 - 2 * s))
+        h.close()
+        assert np.abs(Af - A1).max() <= 1e-12 * np.abs(A1).max(), e
 
 
 @pytest.mark.parametrize("s", [0.25, 0.75])
