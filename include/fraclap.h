@@ -211,7 +211,9 @@ int fl_export_matrix(fl_handle *h, double *dst, int64_t ld, int on_device);
 int fl_load_vector_one(fl_handle *h, double *b);
 
 /* y = A x with the FP64 matrix.  x, y: device, length n, not aliased.
- * Sec. 5: the dense product costs n^2 and drives the iterative solve. */
+ * Sec. 5: the dense product costs n^2 and drives the iterative solve.  A is
+ * symmetric; this product, the solver and fl_energy_error2 read only its
+ * upper triangle (64 x 64 tiles on and above the diagonal). */
 int fl_matvec(fl_handle *h, const double *x, double *y);
 
 /* Jacobi-preconditioned CG on A u = b (Sec. 5).  b, u: device, length n;
@@ -238,7 +240,8 @@ int fl_stats(const fl_handle *h, fl_stats_t *out);
 
 /* Replace the assembled FP64 matrix by src (n x n, leading dimension
  * ld >= n, device pointer if on_device else host), e.g. to restore a saved
- * matrix; n and the DOF map are those of the last fl_assemble.  FL_ESTATE
+ * matrix; n and the DOF map are those of the last fl_assemble.  src must be
+ * symmetric: products and solves read its upper triangle only.  FL_ESTATE
  * before fl_assemble.  Synchronises the stream when src is on the host. */
 int fl_import_matrix(fl_handle *h, const double *src, int64_t ld, int on_device);
 

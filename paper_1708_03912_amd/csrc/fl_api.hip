@@ -82,7 +82,10 @@ void free_solver(fl_handle* h) {
     if (h->w_scal) (void)hipFree(h->w_scal);
     if (h->w_flag) (void)hipFree(h->w_flag);
     if (h->w32) (void)hipFree(h->w32);
+    if (h->w_sym) (void)hipFree(h->w_sym);
     h->w32 = nullptr;
+    h->w_sym = nullptr;
+    h->sym = SymPlan{};
     h->w = h->w_part = h->w_scal = nullptr;
     h->w_flag = nullptr;
     h->w_n = -1;
@@ -1028,6 +1031,8 @@ int fl_load_vector_one(fl_handle* h, double* b) {
     return FL_OK;
 }
 
+static int ensure_solver(fl_handle* h);
+
 int fl_matvec(fl_handle* h, const double* x, double* y) {
     if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
@@ -1035,22 +1040,30 @@ int fl_matvec(fl_handle* h, const double* x, double* y) {
     if (!x || !y) return fail(h, FL_EINVAL, "null vector");
     if (x == y) return fail(h, FL_EINVAL, "x and y must not alias");
     HIPCHK(hipSetDevice(h->device));
-    launch_matvec(h->dA, h->lda, h->n, x, y, h->stream);
+    int rc = ensure_solver(h);
+    if (rc) return rc;
+    launch_symv(h->sym, h->dA, h->lda, x, y, h->stream);
     HIPCHK(hipGetLastError());
     return FL_OK;
 }
 
+// Solver workspace for the current n: vectors, partial sums, status words
+// and the slots of the symmetric product.
 static int ensure_solver(fl_handle* h) {
     if (h->w_n == h->n && (h->opts.precision != FL_MIXED || h->w32)) return FL_OK;
     free_solver(h);
     const int64_t n = h->n;
-    const int nblk = (int)((n + 255) / 256);
-    const int nmv = mv_blocks(n);
+    SymPlan sp{};
+    sym_plan_geometry(n, &sp);
+    const int64_t ndot = (n + 255) / 256;
     HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(7 * n + 8)));
-    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * nblk + nmv + 8)));
+    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * std::max<int64_t>(sp.nred, ndot) + 8)));
     HIPCHK(hipMalloc((void**)&h->w_scal, sizeof(double) * 16));
     HIPCHK(hipMalloc((void**)&h->w_flag, sizeof(int) * 8));
     if (h->opts.precision == FL_MIXED) HIPCHK(hipMalloc((void**)&h->w32, sizeof(float) * (size_t)(9 * n + 16)));
+    HIPCHK(hipMalloc((void**)&h->w_sym, sizeof(double) * sym_plan_doubles(sp)));
+    sym_plan_bind(&sp, h->w_sym);
+    h->sym = sp;
     h->w_n = n;
     return FL_OK;
 }
@@ -1072,11 +1085,11 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     S.r = W + 3 * n;
     S.z = W + 4 * n;
     S.p = W + 5 * n;                  // 2 n
-    S.q = W + 7 * n;
     S.part = h->w_part;
     S.scal = h->w_scal;
     S.flag = h->w_flag;
-    S.nblk = nblk;
+    S.sp = h->sym;
+    S.nblk = h->sym.nred;
     const double rtol_in = 1e-4;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1087,7 +1100,7 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     double bb = -1.0, rr = 0.0;
     int total_inner = 0, outer = 0, status = FL_OK;
     for (;;) {
-        launch_residual(h->dA, h->lda, n, u, b, r, (float*)S.b, h->w_part, nblk, h->stream);
+        launch_residual(h->sym, h->dA, h->lda, u, b, r, (float*)S.b, h->stream);
         launch_dot2(r, r, r, n, h->w_part, nblk, h->w_scal + 8, h->stream);
         HIPCHK(hipGetLastError());
         double rs[2];
@@ -1160,7 +1173,6 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     S.r = h->w;
     S.z = h->w + n;
     S.p = h->w + 2 * n;  // two buffers
-    S.q = h->w + 4 * n;
     double* dd = h->w + 5 * n;
     S.d = dd;
     S.b = b;
@@ -1170,7 +1182,8 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     S.flag = h->w_flag;
     S.rtol = rtol;
     S.maxit = maxit;
-    S.nblk = (int)((n + 255) / 256);
+    S.sp = h->sym;
+    S.nblk = h->sym.nred;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1230,7 +1243,7 @@ int fl_energy_error2(fl_handle* h, double fu, const double* b, const double* uh,
     if (rc) return rc;
     const int64_t n = h->n;
     double* y = h->w + 6 * n;
-    launch_matvec(h->dA, h->lda, n, uh, y, h->stream);
+    launch_symv(h->sym, h->dA, h->lda, uh, y, h->stream);
     const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
     launch_dot2(uh, b, y, n, h->w_part, nblk, h->w_scal + 8, h->stream);
     HIPCHK(hipGetLastError());

@@ -99,6 +99,8 @@ struct fl_handle {
     double* w_scal = nullptr;
     int* w_flag = nullptr;
     int64_t w_n = -1;
+    fl::SymPlan sym{};     // symmetric product of the n x n matrix (slots in w_sym)
+    double* w_sym = nullptr;
 
     fl_stats_t st{};
     fl_batch B;

@@ -130,12 +130,41 @@ void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx
                      const double* meas, int dim, long long n, double* b, hipStream_t st);
 
 // solver kernels
-constexpr int MV_THREADS = 256;
-int mv_blocks(long long n);
-void launch_matvec(const double* A, long long lda, long long n, const double* x, double* y,
-                   hipStream_t st);
 void launch_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
-// CG building blocks; status layout in cg_status_layout
+
+// Symmetric dense product from the upper triangle (fl_kernels.hip): 64 x 64
+// tiles (bi <= bj); workgroup (c, bi) of a (nchx, nb) grid takes block row bi
+// and the m tiles from bj = bi + c m; partial sums in slot arrays (no
+// atomics), reduced with G lanes per element.
+constexpr int SYM_TB = 64;
+constexpr int SYM_M = 3;             // tiles per workgroup: 64 (m + 1) = 256 staged entries
+constexpr int SYM_PQ_BLOCKS = 256;   // pre-reduction of the v.Av partials
+struct SymPlan {
+    long long n;
+    int nb;          // block rows, ceil(n / 64)
+    int m;           // tiles per workgroup along a block row (SYM_M)
+    int nchx;        // chunks per block row, ceil(nb / m)
+    long long nwg;   // workgroups of a product, nchx x nb (some empty)
+    int G;           // lanes per element in the reductions (power of two <= 16)
+    int nred;        // blocks of the reductions, ceil(n G / 256)
+    double* prow;    // nchx x n row-sum slots
+    double* pcol;    // nb x n column-sum slots
+    double* wpart;   // nwg workgroup partials of v.Av
+    double* wpart2;  // SYM_PQ_BLOCKS pre-reduced partials
+    bool pre;        // pre-reduction in use
+    const double* pq;  // partials the CG update sums: wpart or wpart2
+    int npq;
+};
+void sym_plan_geometry(long long n, SymPlan* P);           // everything but the pointers
+size_t sym_plan_doubles(const SymPlan& P);                  // slot + partial storage
+void sym_plan_bind(SymPlan* P, double* buf);
+// y = A x; A symmetric, only its upper triangle is read
+void launch_symv(const SymPlan& P, const double* A, long long lda, const double* x, double* y, hipStream_t st);
+// r = b - A x (FP64), r32 = (float) r
+void launch_residual(const SymPlan& P, const double* A, long long lda, const double* x, const double* b,
+                     double* r, float* r32, hipStream_t st);
+
+// CG building blocks
 struct CgState {
     long long n;
     const double* A;
@@ -146,21 +175,21 @@ struct CgState {
     double* r;
     double* z;
     double* p;          // 2 x n (double-buffered by iteration parity)
-    double* q;
-    double* part;       // 4 x nblk (r.z, r.r by parity) + mv_blocks(n) partial sums
+    double* part;       // 4 x nblk: r.z, r.r by parity
     double* scal;       // [0] b.b, [1] last r.r
     int* flag;          // [0] stop, [1] iterations, [2] 1 breakdown / 2 non-finite
     double rtol;
     int maxit;
-    int nblk;
+    int nblk;           // = sp.nred
+    SymPlan sp;         // product slots; sp.wpart holds the p.Ap partials
 };
 void launch_cg_init(const CgState& s, hipStream_t st);
 void launch_cg_iter_at(const CgState& s, int it, hipStream_t st);
 void launch_cg_final(const CgState& s, int it, hipStream_t st);
 
 // FP32 Jacobi-PCG (inner solver of the mixed-precision refinement); same
-// algorithm and status layout as CgState, vectors and matrix in FP32, dot
-// products accumulated in FP64.
+// algorithm and status layout as CgState, vectors and matrix in FP32,
+// products and dot products accumulated in FP64.
 struct CgState32 {
     long long n;
     const float* A;
@@ -171,20 +200,18 @@ struct CgState32 {
     float* r;
     float* z;
     float* p;           // 2 x n
-    float* q;
     double* part;
     double* scal;
     int* flag;
     double rtol;
     int maxit;
     int nblk;
+    SymPlan sp;
 };
 void launch_cg32_init(const CgState32& s, hipStream_t st);
 void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st);
 void launch_cg32_final(const CgState32& s, int it, hipStream_t st);
-// y = b - A x (FP64 residual), x += e (FP32 correction)
-void launch_residual(const double* A, long long lda, long long n, const double* x, const double* b,
-                     double* r, float* r32, double* part, int nblk, hipStream_t st);
+// x += e (FP32 correction)
 void launch_diag32(const float* A, long long lda, long long n, float* d, hipStream_t st);
 void launch_add_correction(double* u, const float* e, long long n, hipStream_t st);
 void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,

@@ -12,6 +12,7 @@
 //   diagonal blocks  -> scatter_self (gather per DOF row, deterministic)
 // The CG kernels implement Jacobi-preconditioned CG (Sec. 5).
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "fl_internal.hpp"
 #include "fl_math.hpp"
@@ -1661,90 +1662,6 @@ void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx
 
 // ---------------------------------------------------------------- solve --
 
-// Dense FP64 matvec: one wave per row, 16-byte loads, four independent
-// accumulators in flight; rows are padded to lda (multiple of 32).
-constexpr int MV_ROWS_PER_BLOCK = MV_THREADS / 64;
-
-int mv_blocks(long long n) { return (int)((n + MV_ROWS_PER_BLOCK - 1) / MV_ROWS_PER_BLOCK); }
-
-__device__ __forceinline__ double row_dot(const double* __restrict__ a, const double* __restrict__ x,
-                                          long long n, int lane) {
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    const long long n2 = n & ~1LL;
-    long long j = 2 * lane;
-    // 4 x (64 lanes x 2 doubles) per trip
-    for (; j + 6 * 64 < n2; j += 8 * 64) {
-        double2 a0 = *(const double2*)(a + j), x0 = *(const double2*)(x + j);
-        double2 a1 = *(const double2*)(a + j + 128), x1 = *(const double2*)(x + j + 128);
-        double2 a2 = *(const double2*)(a + j + 256), x2 = *(const double2*)(x + j + 256);
-        double2 a3 = *(const double2*)(a + j + 384), x3 = *(const double2*)(x + j + 384);
-        acc0 += a0.x * x0.x + a0.y * x0.y;
-        acc1 += a1.x * x1.x + a1.y * x1.y;
-        acc2 += a2.x * x2.x + a2.y * x2.y;
-        acc3 += a3.x * x3.x + a3.y * x3.y;
-    }
-    for (; j < n2; j += 128) {
-        double2 a0 = *(const double2*)(a + j), x0 = *(const double2*)(x + j);
-        acc0 += a0.x * x0.x + a0.y * x0.y;
-    }
-    if ((n & 1) && lane == 0) acc1 += a[n - 1] * x[n - 1];
-    return wave_sum((acc0 + acc1) + (acc2 + acc3));
-}
-
-// Two rows per wave: every vector chunk loaded from cache serves both rows,
-// which halves the vector traffic (each row reads all of x).
-__device__ __forceinline__ void row_dot2(const double* __restrict__ a, const double* __restrict__ b,
-                                         const double* __restrict__ x, long long n, int lane, double& va,
-                                         double& vb) {
-    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-    const long long n2 = n & ~1LL;
-    long long j = 2 * lane;
-    for (; j + 2 * 64 < n2; j += 4 * 64) {
-        const double2 x0 = *(const double2*)(x + j), x1 = *(const double2*)(x + j + 128);
-        const double2 p0 = *(const double2*)(a + j), p1 = *(const double2*)(a + j + 128);
-        const double2 q0 = *(const double2*)(b + j), q1 = *(const double2*)(b + j + 128);
-        a0 += p0.x * x0.x + p0.y * x0.y;
-        a1 += p1.x * x1.x + p1.y * x1.y;
-        b0 += q0.x * x0.x + q0.y * x0.y;
-        b1 += q1.x * x1.x + q1.y * x1.y;
-    }
-    for (; j < n2; j += 128) {
-        const double2 x0 = *(const double2*)(x + j), p0 = *(const double2*)(a + j), q0 = *(const double2*)(b + j);
-        a0 += p0.x * x0.x + p0.y * x0.y;
-        b0 += q0.x * x0.x + q0.y * x0.y;
-    }
-    if ((n & 1) && lane == 0) {
-        a1 += a[n - 1] * x[n - 1];
-        b1 += b[n - 1] * x[n - 1];
-    }
-    va = wave_sum(a0 + a1);
-    vb = wave_sum(b0 + b1);
-}
-
-constexpr int MV2_ROWS_PER_BLOCK = 2 * (MV_THREADS / 64);
-int mv2_blocks(long long n) { return (int)((n + MV2_ROWS_PER_BLOCK - 1) / MV2_ROWS_PER_BLOCK); }
-
-__global__ __launch_bounds__(MV_THREADS) void matvec_kernel(const double* __restrict__ A, long long lda,
-                                                            long long n, const double* __restrict__ x,
-                                                            double* __restrict__ y) {
-    const long long row = 2 * ((long long)blockIdx.x * (MV_THREADS / 64) + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const bool two = row + 1 < n;
-    double v0, v1;
-    row_dot2(A + row * lda, A + (two ? row + 1 : row) * lda, x, n, lane, v0, v1);
-    if (lane == 0) {
-        y[row] = v0;
-        if (two) y[row + 1] = v1;
-    }
-}
-
-void launch_matvec(const double* A, long long lda, long long n, const double* x, double* y,
-                   hipStream_t st) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(matvec_kernel, dim3(mv2_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, y);
-}
-
 __global__ void diag_kernel(const double* A, long long lda, long long n, double* d) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = A[i * lda + i];
@@ -1773,42 +1690,347 @@ __device__ __forceinline__ double sum_partials(const double* part, int m, double
     return block_sum(v, sh);
 }
 
-// Jacobi-PCG (Sec. 5), two kernels per iteration.  Partial sums are kept
-// per block and reduced in a fixed order by every block that needs them
-// (deterministic); r.z and r.r partials are double-buffered by iteration
-// parity, the search direction p too.
-//   cg_matvec(it):  check ||r_it|| against rtol ||b||; beta = rz_it/rz_{it-1};
-//                   p_it = z + beta p_{it-1} (computed on the fly for the
-//                   product, stored for the block's own rows); q = A p_it;
-//                   partials of p_it.q
-//   cg_update(it):  alpha = rz_it / p.q; x += alpha p; r -= alpha q; z = r/d;
-//                   partials of r.z and r.r for iteration it+1
-// status: flag[0] stop, flag[1] iterations done, flag[2] 1 breakdown /
-// 2 non-finite; scal[0] = b.b, scal[1] = last r.r.
-__global__ __launch_bounds__(256) void cg_init_kernel(CgState S) {
-    __shared__ double sh[4];
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (i < S.n) {
-        double bi = S.b[i];
-        S.x[i] = 0.0;
-        S.r[i] = bi;
-        double zi = bi / S.d[i];
-        S.z[i] = zi;
-        S.p[S.n + i] = 0.0;  // p_{-1}
-        rz = bi * zi;
-        rr = bi * bi;
+// Symmetric dense product from the upper triangle.  The stiffness matrix is
+// symmetric (Sec. 5: every pair adds a block and its transpose), so a
+// product reads only its 64 x 64 tiles (bi <= bj): half of the n^2 entries.
+// Workgroup (c, bi) of a (ceil(nb / M), nb) grid takes block row bi and the
+// tiles bj = bi + c M .. bi + c M + M - 1 (< nb; workgroups with bi + c M >= nb
+// have nothing to do); M = 3 fills the 256 threads with the staged vector
+// entries (64 (M + 1)).  It loads all of them at once, forms the row sums
+// A_IJ v_J over its tiles and, for bi < bj, the column sums A_IJ^T v_I.
+// Partial sums go to slots that exactly one workgroup writes (no atomics):
+//   prow[c n + i]  row sums of chunk c of the block row of i,
+//   pcol[a n + j]  column sums of tile (a, b) for j in block b, a < b,
+// and (A v)_i is their sum over c < nch(b), then a < b (fixed order).
+// Thread t of 256 holds columns 2 (t & 31), 2 (t & 31) + 1 and rows
+// (t >> 5) + 8 k, k = 0..7, of each tile: one load of a wave covers two
+// contiguous row segments of 64 entries.  Every global load of a workgroup
+// (matrix entries, vector entries, partial sums) is issued before the
+// first wait.
+__device__ __forceinline__ void ld2(const double* p, double& a, double& b) {
+    const double2 v = *(const double2*)p;
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void ld2(const float* p, double& a, double& b) {
+    const float2 v = *(const float2*)p;
+    a = v.x;
+    b = v.y;
+}
+
+// this lane's share of the sum of the first m partials (lane stride 256,
+// four accumulators): the same order in every block
+__device__ __forceinline__ double load_partials(const double* part, int m) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 768 < m; i += 1024) {
+        s0 += part[i];
+        s1 += part[i + 256];
+        s2 += part[i + 512];
+        s3 += part[i + 768];
     }
-    double a = block_sum(rz, sh), b = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        S.part[blockIdx.x] = a;              // rz, parity 0
-        S.part[2 * S.nblk + blockIdx.x] = b; // rr, parity 0
+    for (; i < m; i += 256) s0 += part[i];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// three block sums with one pair of barriers (256 threads, sh: 12 doubles)
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[w] = a;
+        sh[4 + w] = b;
+        sh[8 + w] = c;
+    }
+    __syncthreads();
+    a = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    b = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+    c = (sh[8] + sh[9]) + (sh[10] + sh[11]);
+    __syncthreads();
+}
+
+// Sums of eight values over the 32 lanes of a half wave (halving exchange):
+// lane cp returns the sum of v[cp >> 2].  9 exchanges instead of 40.
+__device__ __forceinline__ double half_wave_sum8(const double* v, int cp) {
+    const int h4 = (cp >> 4) & 1, h3 = (cp >> 3) & 1, h2 = (cp >> 2) & 1;
+    double w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = (h4 ? v[4 + j] : v[j]) + __shfl_xor(h4 ? v[j] : v[4 + j], 16, 64);
+    double x[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) x[j] = (h3 ? w[2 + j] : w[j]) + __shfl_xor(h3 ? w[j] : w[2 + j], 8, 64);
+    double y = (h2 ? x[1] : x[0]) + __shfl_xor(h2 ? x[0] : x[1], 4, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
+// the thread's 8 x 2 entries of each of the workgroup's M tiles; zero
+// outside n x n and beyond the last block
+template <class T, int M>
+__device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda, const SymPlan& P, long long I0,
+                                         int bj0, double (&a0)[M][8], double (&a1)[M][8]) {
+    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
+    const long long n = P.n;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const long long j = (long long)(bj0 + q) * SYM_TB + 2 * cp;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long long i = I0 + rg + 8 * k;
+            a0[q][k] = 0.0;
+            a1[q][k] = 0.0;
+            if (i < n && j < n) ld2(A + i * lda + j, a0[q][k], a1[q][k]);
+        }
+        if (j + 1 >= n) {  // padding column: contents unspecified
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a1[q][k] = 0.0;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void cg_init_reduce_kernel(CgState S) {
-    __shared__ double sh[4];
-    double bb = sum_partials(S.part + 2 * S.nblk, S.nblk, sh);
+// Products of the loaded tiles with v (LDS sv: v_I, then v_J of each tile;
+// written and synchronised by the caller); writes the slots and returns
+// this thread's share of the workgroup's part of v^T A v (diagonal tile
+// once, off-diagonal tiles twice).  redc: M x 8 x 64 doubles.
+template <int M>
+__device__ __forceinline__ double sym_finish(const SymPlan& P, int bi, int c, const double (&a0)[M][8],
+                                             const double (&a1)[M][8], const double* sv, double* redc) {
+    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
+    const long long n = P.n, I0 = (long long)bi * SYM_TB;
+    const int bj0 = bi + c * M;
+    double racc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) racc[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const double* vJ = sv + 64 * (q + 1);
+        const double x0 = vJ[2 * cp], x1 = vJ[2 * cp + 1];
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            racc[k] += a0[q][k] * x0 + a1[q][k] * x1;
+            const double vi = sv[rg + 8 * k];
+            c0 += a0[q][k] * vi;
+            c1 += a1[q][k] * vi;
+        }
+        redc[q * 512 + rg * 64 + 2 * cp] = c0;
+        redc[q * 512 + rg * 64 + 2 * cp + 1] = c1;
+    }
+    __syncthreads();
+    double vd = 0.0;
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int bj = bj0 + q;
+            if (bj > bi && bj < P.nb) {
+                double s = 0.0;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) s += redc[q * 512 + g * 64 + t];
+                const long long j = (long long)bj * SYM_TB + t;
+                if (j < n) P.pcol[(long long)bi * n + j] = s;
+                vd += s * sv[64 * (q + 1) + t];
+            }
+        }
+    }
+    const double y = half_wave_sum8(racc, cp);
+    if ((cp & 3) == 0) {
+        const int r = rg + 8 * (cp >> 2);
+        if (I0 + r < n) {
+            P.prow[(long long)c * n + I0 + r] = y;
+            vd += y * sv[r];
+        }
+    }
+    return vd;
+}
+
+// this lane's share of (A v)_i from the slots (lane g of an aligned group
+// of P.G takes every G-th slot); group_sum completes it
+__device__ __forceinline__ double sym_gather_share(const SymPlan& P, long long i, int g) {
+    const int G = P.G;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < P.n) {
+        const int b = (int)(i / SYM_TB);
+        const int nch = (P.nb - b + P.m - 1) / P.m;
+        const int ns = nch + b;
+        auto slot = [&](int u) -> double {
+            return u < nch ? P.prow[(long long)u * P.n + i] : P.pcol[(long long)(u - nch) * P.n + i];
+        };
+        int u = g;
+        for (; u + 3 * G < ns; u += 4 * G) {
+            const double v0 = slot(u), v1 = slot(u + G), v2 = slot(u + 2 * G), v3 = slot(u + 3 * G);
+            s0 += v0;
+            s1 += v1;
+            s2 += v2;
+            s3 += v3;
+        }
+        for (; u < ns; u += G) s0 += slot(u);
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+// sum over an aligned group of G lanes (all lanes must call it)
+__device__ __forceinline__ double group_sum(double s, int G) {
+    for (int o = 1; o < G; o <<= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
+// index of the vector entry thread t stages for workgroup (bi, bj0): v_I
+// for t < 64, then the columns of the M tiles (consecutive blocks)
+__device__ __forceinline__ long long sym_vec_index(long long I0, int bj0, int t) {
+    return t < 64 ? I0 + t : (long long)bj0 * SYM_TB + (t - 64);
+}
+
+// slots of A x (plain product)
+template <class T, int M>
+__global__ __launch_bounds__(256) void symv_kernel(const T* __restrict__ A, long long lda, SymPlan P,
+                                                   const T* __restrict__ x) {
+    __shared__ double sv[64 * (M + 1)];
+    __shared__ double redc[M * 512];
+    const int bi = blockIdx.y, c = blockIdx.x, bj0 = bi + c * M, t = threadIdx.x;
+    if (bj0 >= P.nb) return;
+    const long long I0 = (long long)bi * SYM_TB;
+    double a0[M][8], a1[M][8];
+    sym_load<T, M>(A, lda, P, I0, bj0, a0, a1);
+    if (t < 64 * (M + 1)) {
+        const long long e = sym_vec_index(I0, bj0, t);
+        sv[t] = e < P.n ? (double)x[e] : 0.0;
+    }
+    __syncthreads();
+    (void)sym_finish<M>(P, bi, c, a0, a1, sv, redc);
+}
+
+// y = A x from the slots
+__global__ __launch_bounds__(256) void sym_reduce_kernel(SymPlan P, double* y) {
+    const long long i = (long long)blockIdx.x * (256 / P.G) + threadIdx.x / P.G;
+    const int g = threadIdx.x & (P.G - 1);
+    const double s = group_sum(sym_gather_share(P, i, g), P.G);
+    if (g == 0 && i < P.n) y[i] = s;
+}
+
+// r = b - A x in FP64 from the slots, also r32 = (float) r
+__global__ __launch_bounds__(256) void sym_residual_kernel(SymPlan P, const double* b, double* r, float* r32) {
+    const long long i = (long long)blockIdx.x * (256 / P.G) + threadIdx.x / P.G;
+    const int g = threadIdx.x & (P.G - 1);
+    const double s = group_sum(sym_gather_share(P, i, g), P.G);
+    if (g == 0 && i < P.n) {
+        const double ri = b[i] - s;
+        r[i] = ri;
+        r32[i] = (float)ri;
+    }
+}
+
+void sym_plan_geometry(long long n, SymPlan* P) {
+    P->n = n;
+    P->nb = (int)((n + SYM_TB - 1) / SYM_TB);
+    P->m = SYM_M;
+    P->nchx = (P->nb + P->m - 1) / P->m;
+    P->nwg = (long long)P->nchx * P->nb;
+    int G = 16;
+    while (G > 1 && (n * G + 255) / 256 > 1024) G >>= 1;
+    P->G = G;
+    P->nred = (int)std::max<long long>(1, (n * G + 255) / 256);
+}
+
+size_t sym_plan_doubles(const SymPlan& P) {
+    return (size_t)(P.nchx + P.nb) * (size_t)P.n + (size_t)P.nwg + SYM_PQ_BLOCKS + 8;
+}
+
+void sym_plan_bind(SymPlan* P, double* buf) {
+    P->prow = buf;
+    P->pcol = buf + (long long)P->nchx * P->n;
+    P->wpart = buf + (long long)(P->nchx + P->nb) * P->n;
+    P->wpart2 = P->wpart + P->nwg;
+    // many workgroups: one pre-reduction pass so that every block of the
+    // update sums SYM_PQ_BLOCKS partials instead of nwg
+    P->pre = P->nwg > 8192;
+    P->pq = P->pre ? P->wpart2 : P->wpart;
+    P->npq = P->pre ? SYM_PQ_BLOCKS : (int)P->nwg;
+}
+
+// wpart (nwg) -> wpart2 (SYM_PQ_BLOCKS), fixed assignment
+__global__ __launch_bounds__(256) void sym_pq_reduce_kernel(SymPlan P) {
+    __shared__ double sh[12];
+    double s = 0.0, u1 = 0.0, u2 = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < P.nwg; i += (long long)SYM_PQ_BLOCKS * 256)
+        s += P.wpart[i];
+    block_sum3(s, u1, u2, sh);
+    if (threadIdx.x == 0) P.wpart2[blockIdx.x] = s;
+}
+
+void launch_sym_pq_reduce(const SymPlan& P, hipStream_t st) {
+    if (P.pre) hipLaunchKernelGGL(sym_pq_reduce_kernel, dim3(SYM_PQ_BLOCKS), dim3(256), 0, st, P);
+}
+
+template <class T>
+void symv_launch(const SymPlan& P, const T* A, long long lda, const T* x, hipStream_t st) {
+    hipLaunchKernelGGL((symv_kernel<T, SYM_M>), dim3(P.nchx, P.nb), dim3(256), 0, st, A, lda, P, x);
+}
+
+void launch_symv(const SymPlan& P, const double* A, long long lda, const double* x, double* y, hipStream_t st) {
+    if (P.n == 0) return;
+    symv_launch(P, A, lda, x, st);
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3(P.nred), dim3(256), 0, st, P, y);
+}
+
+void launch_residual(const SymPlan& P, const double* A, long long lda, const double* x, const double* b,
+                     double* r, float* r32, hipStream_t st) {
+    if (P.n == 0) return;
+    symv_launch(P, A, lda, x, st);
+    hipLaunchKernelGGL(sym_residual_kernel, dim3(P.nred), dim3(256), 0, st, P, b, r, r32);
+}
+
+// Jacobi-PCG (Sec. 5), two kernels per iteration, for the FP64 state
+// (CgState) and the FP32 one (CgState32: FP32 matrix and vectors, products
+// and dot products accumulated in FP64).  Partial sums are kept per block
+// and reduced in a fixed order by every block that needs them
+// (deterministic); r.z and r.r partials are double-buffered by iteration
+// parity, the search direction p too.
+//   cg_symv(it):    check ||r_it|| against rtol ||b||; beta = rz_it/rz_{it-1};
+//                   p_it = z + beta p_{it-1} (computed on the fly for the
+//                   product, stored by the workgroup holding the diagonal
+//                   tile); slots of A p_it and workgroup partials of
+//                   p_it.A p_it
+//   cg_update(it):  alpha = rz_it / p.Ap; q = A p from the slots;
+//                   x += alpha p; r -= alpha q; z = r/d; partials of r.z
+//                   and r.r for iteration it+1
+// The update and the initialisation run G = sp.G lanes per element (nblk =
+// sp.nred blocks).  status: flag[0] stop, flag[1] iterations done, flag[2]
+// 1 breakdown / 2 non-finite; scal[0] = b.b, scal[1] = last r.r.
+template <class ST>
+using cg_elem_t = std::remove_const_t<std::remove_pointer_t<decltype(ST::b)>>;
+
+template <class ST>
+__global__ __launch_bounds__(256) void cg_init_kernel(ST S) {
+    using T = cg_elem_t<ST>;
+    __shared__ double sh[12];
+    const long long i = (long long)blockIdx.x * (256 / S.sp.G) + threadIdx.x / S.sp.G;
+    const bool lead = (threadIdx.x & (S.sp.G - 1)) == 0;
+    double rz = 0.0, rr = 0.0, unused = 0.0;
+    if (lead && i < S.n) {
+        const T bi = S.b[i];
+        S.x[i] = T(0);
+        S.r[i] = bi;
+        const T zi = bi / S.d[i];
+        S.z[i] = zi;
+        S.p[S.n + i] = T(0);  // p_{-1}
+        rz = (double)bi * zi;
+        rr = (double)bi * bi;
+    }
+    block_sum3(rz, rr, unused, sh);
+    if (threadIdx.x == 0) {
+        S.part[blockIdx.x] = rz;              // rz, parity 0
+        S.part[2 * S.nblk + blockIdx.x] = rr; // rr, parity 0
+    }
+}
+
+template <class ST>
+__global__ __launch_bounds__(256) void cg_init_reduce_kernel(ST S) {
+    __shared__ double sh[12];
+    double bb = load_partials(S.part + 2 * S.nblk, S.nblk), u1 = 0.0, u2 = 0.0;
+    block_sum3(bb, u1, u2, sh);
     if (threadIdx.x == 0) {
         S.scal[0] = bb;
         S.scal[1] = bb;
@@ -1819,77 +2041,41 @@ __global__ __launch_bounds__(256) void cg_init_reduce_kernel(CgState S) {
     }
 }
 
-__device__ __forceinline__ double row_dot_comb(const double* __restrict__ a, const double* __restrict__ z,
-                                               const double* __restrict__ pp, double beta, long long n,
-                                               int lane) {
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    const long long n2 = n & ~1LL;
-    long long j = 2 * lane;
-    for (; j + 6 * 64 < n2; j += 8 * 64) {
-        double2 a0 = *(const double2*)(a + j), a1 = *(const double2*)(a + j + 128);
-        double2 a2 = *(const double2*)(a + j + 256), a3 = *(const double2*)(a + j + 384);
-        double2 z0 = *(const double2*)(z + j), z1 = *(const double2*)(z + j + 128);
-        double2 z2 = *(const double2*)(z + j + 256), z3 = *(const double2*)(z + j + 384);
-        double2 p0 = *(const double2*)(pp + j), p1 = *(const double2*)(pp + j + 128);
-        double2 p2 = *(const double2*)(pp + j + 256), p3 = *(const double2*)(pp + j + 384);
-        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y);
-        acc1 += a1.x * (z1.x + beta * p1.x) + a1.y * (z1.y + beta * p1.y);
-        acc2 += a2.x * (z2.x + beta * p2.x) + a2.y * (z2.y + beta * p2.y);
-        acc3 += a3.x * (z3.x + beta * p3.x) + a3.y * (z3.y + beta * p3.y);
+template <class ST, int M>
+__global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
+    using T = cg_elem_t<ST>;
+    __shared__ double sh[12];
+    __shared__ double sv[64 * (M + 1)];
+    __shared__ double redc[M * 512];
+    const SymPlan& P = S.sp;
+    const int bi = blockIdx.y, c = blockIdx.x, bj0 = bi + c * M, t = threadIdx.x;
+    const long long wg = (long long)bi * gridDim.x + c;
+    if (bj0 >= P.nb) {  // beyond the triangle: an empty partial
+        if (t == 0) P.wpart[wg] = 0.0;
+        return;
     }
-    for (; j < n2; j += 128) {
-        double2 a0 = *(const double2*)(a + j), z0 = *(const double2*)(z + j), p0 = *(const double2*)(pp + j);
-        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y);
-    }
-    if ((n & 1) && lane == 0) acc1 += a[n - 1] * (z[n - 1] + beta * pp[n - 1]);
-    return wave_sum((acc0 + acc1) + (acc2 + acc3));
-}
-
-// two rows per wave of A (z + beta p_prev) with the direction combined on
-// the fly (shared by both rows)
-__device__ __forceinline__ void row_dot_comb2(const double* __restrict__ a, const double* __restrict__ b,
-                                              const double* __restrict__ z, const double* __restrict__ pp,
-                                              double beta, long long n, int lane, double& va, double& vb) {
-    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-    const long long n2 = n & ~1LL;
-    long long j = 2 * lane;
-    for (; j + 2 * 64 < n2; j += 4 * 64) {
-        const double2 z0 = *(const double2*)(z + j), z1 = *(const double2*)(z + j + 128);
-        const double2 r0 = *(const double2*)(pp + j), r1 = *(const double2*)(pp + j + 128);
-        const double2 p0 = *(const double2*)(a + j), p1 = *(const double2*)(a + j + 128);
-        const double2 q0 = *(const double2*)(b + j), q1 = *(const double2*)(b + j + 128);
-        const double c0x = z0.x + beta * r0.x, c0y = z0.y + beta * r0.y;
-        const double c1x = z1.x + beta * r1.x, c1y = z1.y + beta * r1.y;
-        a0 += p0.x * c0x + p0.y * c0y;
-        a1 += p1.x * c1x + p1.y * c1y;
-        b0 += q0.x * c0x + q0.y * c0y;
-        b1 += q1.x * c1x + q1.y * c1y;
-    }
-    for (; j < n2; j += 128) {
-        const double2 z0 = *(const double2*)(z + j), r0 = *(const double2*)(pp + j);
-        const double2 p0 = *(const double2*)(a + j), q0 = *(const double2*)(b + j);
-        const double cx = z0.x + beta * r0.x, cy = z0.y + beta * r0.y;
-        a0 += p0.x * cx + p0.y * cy;
-        b0 += q0.x * cx + q0.y * cy;
-    }
-    if ((n & 1) && lane == 0) {
-        const double c = z[n - 1] + beta * pp[n - 1];
-        a1 += a[n - 1] * c;
-        b1 += b[n - 1] * c;
-    }
-    va = wave_sum(a0 + a1);
-    vb = wave_sum(b0 + b1);
-}
-
-__global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S, int it, int nmv) {
-    __shared__ double sh[4];
-    if (*(volatile int*)&S.flag[0]) return;
+    const long long n = S.n, I0 = (long long)bi * SYM_TB;
     const int par = it & 1;
-    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
-    const double rr = sum_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk, sh);
+    const T* pprev = S.p + (long long)(1 - par) * n;
+    T* pcur = S.p + (long long)par * n;
+    // loads that do not depend on the scalars: the tiles, z and p_{it-1} at
+    // the staged vector entries, the partial sums
+    double a0[M][8], a1[M][8];
+    sym_load<T, M>(S.A, S.lda, P, I0, bj0, a0, a1);
+    const long long e = sym_vec_index(I0, bj0, t);
+    T zr = T(0), pr = T(0);
+    if (t < 64 * (M + 1) && e < n) {
+        zr = S.z[e];
+        pr = pprev[e];
+    }
+    double rz = load_partials(S.part + par * S.nblk, S.nblk);
+    double rr = load_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk);
+    double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
+    if (*(volatile int*)&S.flag[0]) return;
+    block_sum3(rz, rr, rzp, sh);
     const double bb = S.scal[0];
-    if (sqrt(rr) <= S.rtol * sqrt(bb) || !(rr == rr)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
             S.flag[0] = 1;
             S.flag[1] = it;
             S.scal[1] = rr;
@@ -1897,40 +2083,43 @@ __global__ __launch_bounds__(MV_THREADS) void cg_matvec_kernel(CgState S, int it
         }
         return;
     }
-    double beta = 0.0;
-    if (it > 0) beta = rz / sum_partials(S.part + (1 - par) * S.nblk, S.nblk, sh);
-    const double* pprev = S.p + (long long)(1 - par) * S.n;
-    double* pcur = S.p + (long long)par * S.n;
-    const long long row = 2 * ((long long)blockIdx.x * (MV_THREADS / 64) + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    double pq = 0.0;
-    if (row < S.n) {
-        const bool two = row + 1 < S.n;
-        double v0, v1;
-        row_dot_comb2(S.A + row * S.lda, S.A + (two ? row + 1 : row) * S.lda, S.z, pprev, beta, S.n, lane, v0,
-                      v1);
-        if (lane == 0) {
-            const double pr = S.z[row] + beta * pprev[row];
-            pcur[row] = pr;
-            S.q[row] = v0;
-            pq = v0 * pr;
-            if (two) {
-                const double pr1 = S.z[row + 1] + beta * pprev[row + 1];
-                pcur[row + 1] = pr1;
-                S.q[row + 1] = v1;
-                pq += v1 * pr1;
-            }
-        }
+    const T beta = (T)(it > 0 ? rz / rzp : 0.0);
+    if (t < 64 * (M + 1)) {
+        const T v = zr + beta * pr;
+        sv[t] = (double)v;
+        if (t < 64 && c == 0 && e < n) pcur[e] = v;  // the chunk holding the diagonal tile
     }
-    double t = block_sum(pq, sh);
-    if (threadIdx.x == 0) S.part[4 * S.nblk + blockIdx.x] = t;
+    __syncthreads();
+    double vd = sym_finish<M>(P, bi, c, a0, a1, sv, redc), u1 = 0.0, u2 = 0.0;
+    block_sum3(vd, u1, u2, sh);
+    if (t == 0) P.wpart[wg] = vd;
 }
 
-__global__ __launch_bounds__(256) void cg_update_kernel(CgState S, int it, int nmv) {
-    __shared__ double sh[4];
-    if (*(volatile int*)&S.flag[0]) return;
+template <class ST>
+__global__ __launch_bounds__(256) void cg_update_kernel(ST S, int it) {
+    using T = cg_elem_t<ST>;
+    __shared__ double sh[12];
+    const SymPlan& P = S.sp;
     const int par = it & 1;
-    const double pq = sum_partials(S.part + 4 * S.nblk, nmv, sh);
+    const long long n = S.n;
+    const long long i = (long long)blockIdx.x * (256 / P.G) + threadIdx.x / P.G;
+    const int g = threadIdx.x & (P.G - 1);
+    const bool own = g == 0 && i < n;
+    const T* pcur = S.p + (long long)par * n;
+    // every load first: partials, slots of A p, the element's vectors
+    double pq = load_partials(P.pq, P.npq);
+    double rz = load_partials(S.part + par * S.nblk, S.nblk);
+    double q = sym_gather_share(P, i, g);
+    T pi = T(0), xi = T(0), ri = T(0), di = T(1);
+    if (own) {
+        pi = pcur[i];
+        xi = S.x[i];
+        ri = S.r[i];
+        di = S.d[i];
+    }
+    if (*(volatile int*)&S.flag[0]) return;
+    double u = 0.0;
+    block_sum3(pq, rz, u, sh);
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             S.flag[0] = 1;
@@ -1939,49 +2128,60 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState S, int it, int n
         }
         return;
     }
-    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
-    const double alpha = rz / pq;
-    const double* pcur = S.p + (long long)par * S.n;
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    q = group_sum(q, P.G);
+    const T alpha = (T)(rz / pq);
     double a = 0.0, b = 0.0;
-    if (i < S.n) {
-        S.x[i] += alpha * pcur[i];
-        double ri = S.r[i] - alpha * S.q[i];
-        S.r[i] = ri;
-        double zi = ri / S.d[i];
+    if (own) {
+        S.x[i] = xi + alpha * pi;
+        const T rn = ri - alpha * (T)q;
+        S.r[i] = rn;
+        const T zi = rn / di;
         S.z[i] = zi;
-        a = ri * zi;
-        b = ri * ri;
+        a = (double)rn * zi;
+        b = (double)rn * rn;
     }
-    double ta = block_sum(a, sh), tb = block_sum(b, sh);
+    u = 0.0;
+    block_sum3(a, b, u, sh);
     if (threadIdx.x == 0) {
-        S.part[(1 - par) * S.nblk + blockIdx.x] = ta;
-        S.part[2 * S.nblk + (1 - par) * S.nblk + blockIdx.x] = tb;
+        S.part[(1 - par) * S.nblk + blockIdx.x] = a;
+        S.part[2 * S.nblk + (1 - par) * S.nblk + blockIdx.x] = b;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) S.flag[1] = it + 1;
 }
 
 // after the last launched iteration: residual of iteration `it`
-__global__ __launch_bounds__(256) void cg_final_kernel(CgState S, int it) {
-    __shared__ double sh[4];
-    const double rr = sum_partials(S.part + 2 * S.nblk + (it & 1) * S.nblk, S.nblk, sh);
+template <class ST>
+__global__ __launch_bounds__(256) void cg_final_kernel(ST S, int it) {
+    __shared__ double sh[12];
+    double rr = load_partials(S.part + 2 * S.nblk + (it & 1) * S.nblk, S.nblk), u1 = 0.0, u2 = 0.0;
+    block_sum3(rr, u1, u2, sh);
     if (threadIdx.x == 0 && !S.flag[0]) S.scal[1] = rr;
 }
 
-void launch_cg_init(const CgState& s, hipStream_t st) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3(s.nblk), dim3(256), 0, st, s);
-    hipLaunchKernelGGL(cg_init_reduce_kernel, dim3(1), dim3(256), 0, st, s);
+template <class ST>
+void cg_init_launch(const ST& s, hipStream_t st) {
+    hipLaunchKernelGGL(cg_init_kernel<ST>, dim3(s.nblk), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(cg_init_reduce_kernel<ST>, dim3(1), dim3(256), 0, st, s);
 }
 
-void launch_cg_iter_at(const CgState& s, int it, hipStream_t st) {
-    int nmv = mv2_blocks(s.n);
-    hipLaunchKernelGGL(cg_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s, it, nmv);
-    hipLaunchKernelGGL(cg_update_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
+template <class ST>
+void cg_iter_launch(const ST& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL((cg_symv_kernel<ST, SYM_M>), dim3(s.sp.nchx, s.sp.nb), dim3(256), 0, st, s, it);
+    launch_sym_pq_reduce(s.sp, st);
+    hipLaunchKernelGGL(cg_update_kernel<ST>, dim3(s.nblk), dim3(256), 0, st, s, it);
 }
 
-void launch_cg_final(const CgState& s, int it, hipStream_t st) {
-    hipLaunchKernelGGL(cg_final_kernel, dim3(1), dim3(256), 0, st, s, it);
+template <class ST>
+void cg_final_launch(const ST& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL(cg_final_kernel<ST>, dim3(1), dim3(256), 0, st, s, it);
 }
+
+void launch_cg_init(const CgState& s, hipStream_t st) { cg_init_launch(s, st); }
+void launch_cg_iter_at(const CgState& s, int it, hipStream_t st) { cg_iter_launch(s, it, st); }
+void launch_cg_final(const CgState& s, int it, hipStream_t st) { cg_final_launch(s, it, st); }
+void launch_cg32_init(const CgState32& s, hipStream_t st) { cg_init_launch(s, st); }
+void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) { cg_iter_launch(s, it, st); }
+void launch_cg32_final(const CgState32& s, int it, hipStream_t st) { cg_final_launch(s, it, st); }
 
 // out[0] = a.b, out[1] = a.c (deterministic two-pass)
 __global__ __launch_bounds__(256) void dot2_kernel(const double* a, const double* b, const double* c,
@@ -2038,36 +2238,6 @@ void launch_diag32(const float* A, long long lda, long long n, float* d, hipStre
     hipLaunchKernelGGL(diag32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, lda, n, d);
 }
 
-// r = b - A x in FP64 (one wave per row), also r32 = (float) r and
-// per-block partials of r.r
-__global__ __launch_bounds__(MV_THREADS) void residual_kernel(const double* __restrict__ A, long long lda,
-                                                              long long n, const double* __restrict__ x,
-                                                              const double* __restrict__ b, double* r,
-                                                              float* r32, double* part) {
-    __shared__ double sh[4];
-    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    double rr = 0.0;
-    if (row < n) {
-        double v = row_dot(A + row * lda, x, n, lane);
-        if (lane == 0) {
-            const double ri = b[row] - v;
-            r[row] = ri;
-            r32[row] = (float)ri;
-            rr = ri * ri;
-        }
-    }
-    double t = block_sum(rr, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-void launch_residual(const double* A, long long lda, long long n, const double* x, const double* b,
-                     double* r, float* r32, double* part, int nblk, hipStream_t st) {
-    (void)nblk;
-    if (n == 0) return;
-    hipLaunchKernelGGL(residual_kernel, dim3(mv_blocks(n)), dim3(MV_THREADS), 0, st, A, lda, n, x, b, r,
-                       r32, part);
-}
 
 __global__ void add_correction_kernel(double* u, const float* e, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2077,167 +2247,6 @@ __global__ void add_correction_kernel(double* u, const float* e, long long n) {
 void launch_add_correction(double* u, const float* e, long long n, hipStream_t st) {
     if (n == 0) return;
     hipLaunchKernelGGL(add_correction_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, e, n);
-}
-
-// FP32 row . (z + beta p) with 16-byte loads (4 floats), FP32 products
-// summed in FP32 per lane and in FP64 across the wave
-__device__ __forceinline__ double row_dot_comb32(const float* __restrict__ a, const float* __restrict__ z,
-                                                 const float* __restrict__ pp, float beta, long long n,
-                                                 int lane) {
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-    const long long n4 = n & ~3LL;
-    long long j = 4 * lane;
-    for (; j + 3 * 256 < n4; j += 4 * 256) {
-        float4 a0 = *(const float4*)(a + j), a1 = *(const float4*)(a + j + 256);
-        float4 a2 = *(const float4*)(a + j + 512), a3 = *(const float4*)(a + j + 768);
-        float4 z0 = *(const float4*)(z + j), z1 = *(const float4*)(z + j + 256);
-        float4 z2 = *(const float4*)(z + j + 512), z3 = *(const float4*)(z + j + 768);
-        float4 p0 = *(const float4*)(pp + j), p1 = *(const float4*)(pp + j + 256);
-        float4 p2 = *(const float4*)(pp + j + 512), p3 = *(const float4*)(pp + j + 768);
-        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y) + a0.z * (z0.z + beta * p0.z) +
-                a0.w * (z0.w + beta * p0.w);
-        acc1 += a1.x * (z1.x + beta * p1.x) + a1.y * (z1.y + beta * p1.y) + a1.z * (z1.z + beta * p1.z) +
-                a1.w * (z1.w + beta * p1.w);
-        acc2 += a2.x * (z2.x + beta * p2.x) + a2.y * (z2.y + beta * p2.y) + a2.z * (z2.z + beta * p2.z) +
-                a2.w * (z2.w + beta * p2.w);
-        acc3 += a3.x * (z3.x + beta * p3.x) + a3.y * (z3.y + beta * p3.y) + a3.z * (z3.z + beta * p3.z) +
-                a3.w * (z3.w + beta * p3.w);
-    }
-    for (; j < n4; j += 256) {
-        float4 a0 = *(const float4*)(a + j), z0 = *(const float4*)(z + j), p0 = *(const float4*)(pp + j);
-        acc0 += a0.x * (z0.x + beta * p0.x) + a0.y * (z0.y + beta * p0.y) + a0.z * (z0.z + beta * p0.z) +
-                a0.w * (z0.w + beta * p0.w);
-    }
-    if (lane == 0)
-        for (long long jj = n4; jj < n; ++jj) acc1 += a[jj] * (z[jj] + beta * pp[jj]);
-    return wave_sum((double)((acc0 + acc1) + (acc2 + acc3)));
-}
-
-__global__ __launch_bounds__(256) void cg32_init_kernel(CgState32 S) {
-    __shared__ double sh[4];
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (i < S.n) {
-        float bi = S.b[i];
-        S.x[i] = 0.f;
-        S.r[i] = bi;
-        float zi = bi / S.d[i];
-        S.z[i] = zi;
-        S.p[S.n + i] = 0.f;
-        rz = (double)bi * zi;
-        rr = (double)bi * bi;
-    }
-    double a = block_sum(rz, sh), b = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        S.part[blockIdx.x] = a;
-        S.part[2 * S.nblk + blockIdx.x] = b;
-    }
-}
-
-__global__ __launch_bounds__(256) void cg32_init_reduce_kernel(CgState32 S) {
-    __shared__ double sh[4];
-    double bb = sum_partials(S.part + 2 * S.nblk, S.nblk, sh);
-    if (threadIdx.x == 0) {
-        S.scal[0] = bb;
-        S.scal[1] = bb;
-        S.flag[0] = (bb == 0.0) ? 1 : 0;
-        S.flag[1] = 0;
-        S.flag[2] = 0;
-        if (!(bb == bb) || bb > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
-    }
-}
-
-__global__ __launch_bounds__(MV_THREADS) void cg32_matvec_kernel(CgState32 S, int it, int nmv) {
-    __shared__ double sh[4];
-    if (*(volatile int*)&S.flag[0]) return;
-    const int par = it & 1;
-    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
-    const double rr = sum_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk, sh);
-    const double bb = S.scal[0];
-    if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            S.flag[0] = 1;
-            S.flag[1] = it;
-            S.scal[1] = rr;
-            if (!(rr == rr)) S.flag[2] = 2;
-        }
-        return;
-    }
-    double beta = 0.0;
-    if (it > 0) beta = rz / sum_partials(S.part + (1 - par) * S.nblk, S.nblk, sh);
-    const float fb = (float)beta;
-    const float* pprev = S.p + (long long)(1 - par) * S.n;
-    float* pcur = S.p + (long long)par * S.n;
-    const long long row = (long long)blockIdx.x * MV_ROWS_PER_BLOCK + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    double pq = 0.0;
-    if (row < S.n) {
-        double v = row_dot_comb32(S.A + row * S.lda, S.z, pprev, fb, S.n, lane);
-        if (lane == 0) {
-            const float pr = S.z[row] + fb * pprev[row];
-            pcur[row] = pr;
-            S.q[row] = (float)v;
-            pq = v * pr;
-        }
-    }
-    double t = block_sum(pq, sh);
-    if (threadIdx.x == 0) S.part[4 * S.nblk + blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(256) void cg32_update_kernel(CgState32 S, int it, int nmv) {
-    __shared__ double sh[4];
-    if (*(volatile int*)&S.flag[0]) return;
-    const int par = it & 1;
-    const double pq = sum_partials(S.part + 4 * S.nblk, nmv, sh);
-    if (!(pq > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            S.flag[0] = 1;
-            S.flag[1] = it;
-            S.flag[2] = 1;
-        }
-        return;
-    }
-    const double rz = sum_partials(S.part + par * S.nblk, S.nblk, sh);
-    const float alpha = (float)(rz / pq);
-    const float* pcur = S.p + (long long)par * S.n;
-    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    double a = 0.0, b = 0.0;
-    if (i < S.n) {
-        S.x[i] += alpha * pcur[i];
-        float ri = S.r[i] - alpha * S.q[i];
-        S.r[i] = ri;
-        float zi = ri / S.d[i];
-        S.z[i] = zi;
-        a = (double)ri * zi;
-        b = (double)ri * ri;
-    }
-    double ta = block_sum(a, sh), tb = block_sum(b, sh);
-    if (threadIdx.x == 0) {
-        S.part[(1 - par) * S.nblk + blockIdx.x] = ta;
-        S.part[2 * S.nblk + (1 - par) * S.nblk + blockIdx.x] = tb;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) S.flag[1] = it + 1;
-}
-
-__global__ __launch_bounds__(256) void cg32_final_kernel(CgState32 S, int it) {
-    __shared__ double sh[4];
-    const double rr = sum_partials(S.part + 2 * S.nblk + (it & 1) * S.nblk, S.nblk, sh);
-    if (threadIdx.x == 0 && !S.flag[0]) S.scal[1] = rr;
-}
-
-void launch_cg32_init(const CgState32& s, hipStream_t st) {
-    hipLaunchKernelGGL(cg32_init_kernel, dim3(s.nblk), dim3(256), 0, st, s);
-    hipLaunchKernelGGL(cg32_init_reduce_kernel, dim3(1), dim3(256), 0, st, s);
-}
-
-void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) {
-    int nmv = mv_blocks(s.n);
-    hipLaunchKernelGGL(cg32_matvec_kernel, dim3(nmv), dim3(MV_THREADS), 0, st, s, it, nmv);
-    hipLaunchKernelGGL(cg32_update_kernel, dim3(s.nblk), dim3(256), 0, st, s, it, nmv);
-}
-
-void launch_cg32_final(const CgState32& s, int it, hipStream_t st) {
-    hipLaunchKernelGGL(cg32_final_kernel, dim3(1), dim3(256), 0, st, s, it);
 }
 
 // Pair integrals of m separated triangle pairs with the order-k rule.
