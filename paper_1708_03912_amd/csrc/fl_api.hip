@@ -79,15 +79,15 @@ void free_buffers(fl_handle* h) {
 void free_solver(fl_handle* h) {
     if (h->w) (void)hipFree(h->w);
     if (h->w_part) (void)hipFree(h->w_part);
-    if (h->w_scal) (void)hipFree(h->w_scal);
-    if (h->w_flag) (void)hipFree(h->w_flag);
+    if (h->w_stat) (void)hipFree(h->w_stat);
+    if (h->w_hstat) (void)hipHostFree(h->w_hstat);
     if (h->w32) (void)hipFree(h->w32);
     if (h->w_sym) (void)hipFree(h->w_sym);
     h->w32 = nullptr;
     h->w_sym = nullptr;
     h->sym = SymPlan{};
-    h->w = h->w_part = h->w_scal = nullptr;
-    h->w_flag = nullptr;
+    h->w = h->w_part = nullptr;
+    h->w_stat = h->w_hstat = nullptr;
     h->w_n = -1;
 }
 
@@ -130,9 +130,15 @@ uint64_t morton2(double x, double y, double x0, double y0, double span) {
         if (t > 1) t = 1;
         return (uint64_t)(t * 65535.0);
     };
-    uint64_t a = q(x, x0), b = q(y, y0), k = 0;
-    for (int i = 0; i < 16; ++i) k |= ((a >> i) & 1ull) << (2 * i) | ((b >> i) & 1ull) << (2 * i + 1);
-    return k;
+    // interleave the 16-bit codes (bits spread by shift-and-mask steps)
+    auto spread = [](uint64_t v) {
+        v = (v | (v << 8)) & 0x00ff00ffull;
+        v = (v | (v << 4)) & 0x0f0f0f0full;
+        v = (v | (v << 2)) & 0x33333333ull;
+        v = (v | (v << 1)) & 0x55555555ull;
+        return v;
+    };
+    return spread(q(x, x0)) | (spread(q(y, y0)) << 1);
 }
 
 int check_opts(fl_handle* h, const fl_opts& o) {
@@ -293,6 +299,16 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
         if (cells[i] < 0 || cells[i] >= nv) return fail(h, FL_EMESH, "cell vertex index out of range");
     for (int64_t i = 0; i < nb * dim; ++i)
         if (bfacets[i] < 0 || bfacets[i] >= nv) return fail(h, FL_EMESH, "facet vertex index out of range");
+    if (dim == 2) {  // (before the per-cell checks: their squares stay finite)
+        double lo[2] = {verts[0], verts[1]}, hi[2] = {verts[0], verts[1]};
+        for (int64_t v = 0; v < nv; ++v)
+            for (int j = 0; j < 2; ++j) {
+                lo[j] = std::min(lo[j], verts[2 * v + j]);
+                hi[j] = std::max(hi[j], verts[2 * v + j]);
+            }
+        if (!(std::hypot(hi[0] - lo[0], hi[1] - lo[1]) < 0x1p60))
+            return fail(h, FL_EMESH, "mesh extent above the supported scale (2^60)");
+    }
     for (int64_t K = 0; K < nc; ++K) {
         const int32_t* c = cells + nper * K;
         double meas;
@@ -316,21 +332,14 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
             const double* a = verts + 2 * c[0];
             const double* b = verts + 2 * c[1];
             const double* d = verts + 2 * c[2];
-            const double per = std::hypot(b[0] - a[0], b[1] - a[1]) + std::hypot(d[0] - b[0], d[1] - b[1]) +
-                               std::hypot(a[0] - d[0], a[1] - d[1]);
+            auto len = [](const double* p, const double* q) {
+                const double u = q[0] - p[0], w = q[1] - p[1];
+                return std::sqrt(u * u + w * w);
+            };
+            const double per = len(a, b) + len(b, d) + len(d, a);
             if (!(2.0 * meas / per >= 0x1p-48))
                 return fail(h, FL_EMESH, "cell " + std::to_string(K) + " below the supported scale (inradius < 2^-48)");
         }
-    }
-    if (dim == 2) {
-        double lo[2] = {verts[0], verts[1]}, hi[2] = {verts[0], verts[1]};
-        for (int64_t v = 0; v < nv; ++v)
-            for (int j = 0; j < 2; ++j) {
-                lo[j] = std::min(lo[j], verts[2 * v + j]);
-                hi[j] = std::max(hi[j], verts[2 * v + j]);
-            }
-        if (!(std::hypot(hi[0] - lo[0], hi[1] - lo[1]) < 0x1p60))
-            return fail(h, FL_EMESH, "mesh extent above the supported scale (2^60)");
     }
     // vertex -> cells (CSR) to find the cell owning each boundary facet
     std::vector<int32_t> ptr(nv + 1, 0), idx(nc * nper);
@@ -485,8 +494,10 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             meas[Ki] = 0.5 * std::fabs((bx - ax) * (dy - ay) - (dx - ax) * (by - ay));
         }
     }
-    // vertex -> internal elements (CSR) with the local index of the vertex
-    std::vector<int> v2c_ptr(nv + 1, 0), v2c_idx(T * nper);
+    // vertex -> internal elements (CSR, increasing element order) with the
+    // local index of the vertex; lpos: position of each (element, vertex)
+    // in its vertex's list
+    std::vector<int> v2c_ptr(nv + 1, 0), v2c_idx(T * nper), lpos(T * nper);
     std::vector<unsigned char> vloc(T * nper);
     for (int64_t Ki = 0; Ki < T; ++Ki)
         for (int a = 0; a < nper; ++a) v2c_ptr[vid[a][Ki] + 1]++;
@@ -496,13 +507,15 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         for (int64_t Ki = 0; Ki < T; ++Ki)
             for (int a = 0; a < nper; ++a) {
                 int v = vid[a][Ki];
+                lpos[Ki * nper + a] = fill[v];
                 v2c_idx[fill[v]] = (int)Ki;
                 vloc[fill[v]] = (unsigned char)a;
                 fill[v]++;
             }
     }
     // touching pairs (Sec. 5): K < Kt sharing dim vertices (common edge, 2D)
-    // or one vertex; shared-vertex counts through a marker array
+    // or one vertex.  The elements after Ki in a vertex's list are the Kt >
+    // Ki at that vertex; shared-vertex counts through a marker array.
     std::vector<int> edge_pairs, vert_pairs;
     edge_pairs.reserve((size_t)T * 4);
     vert_pairs.reserve((size_t)T * 12);
@@ -512,10 +525,9 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         for (int64_t Ki = 0; Ki < T; ++Ki) {
             seen.clear();
             for (int a = 0; a < nper; ++a) {
-                int v = vid[a][Ki];
-                for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
-                    int Kt = v2c_idx[e];
-                    if (Kt <= Ki) continue;
+                const int v = vid[a][Ki];
+                for (int e = lpos[Ki * nper + a] + 1; e < v2c_ptr[v + 1]; ++e) {
+                    const int Kt = v2c_idx[e];
                     if (mark[Kt] != (int)Ki) {
                         mark[Kt] = (int)Ki;
                         cnt[Kt] = 0;
@@ -569,8 +581,8 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
     std::vector<unsigned char> loc(T * 3, 255);
     {
-        // distinct DOFs of each block (marker array), sorted, and each
-        // element vertex's index among them
+        // distinct DOFs of each block (marker array, first-seen order) and
+        // each element vertex's index among them
         std::vector<int> ds, mark(n, -1), pos(n, 0);
         for (int b = 0; b < nblk; ++b) {
             ds.clear();
@@ -583,7 +595,6 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
                         ds.push_back(d);
                     }
                 }
-            std::sort(ds.begin(), ds.end());
             blk_ndof[b] = (int)ds.size();
             if ((int)ds.size() > MAXV) continue;  // tile falls back to global atomics
             for (size_t i = 0; i < ds.size(); ++i) {
@@ -1033,6 +1044,58 @@ int fl_load_vector_one(fl_handle* h, double* b) {
 
 static int ensure_solver(fl_handle* h);
 
+extern "C++" {
+static int* stat_flag(char* b) { return (int*)b; }
+static double* stat_scal(char* b) { return (double*)(b + FL_STAT_SCAL); }
+static double* stat_hist(char* b) { return (double*)(b + FL_STAT_HIST); }
+
+// Copy the whole status block to its pinned mirror and wait.
+static int pull_status(fl_handle* h) {
+    HIPCHK(hipMemcpyAsync(h->w_hstat, h->w_stat, FL_STAT_BYTES, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FL_OK;
+}
+
+// Runs CG iterations (launch(it) enqueues iteration it) in chunks until the
+// device status says stop or maxit iterations were launched.  After each
+// chunk the status block comes back in one copy; the next chunk covers the
+// iterations that the last chunk's convergence rate predicts (r.r history,
+// plus a margin), so that few host round trips are needed and few launched
+// iterations find the solver already stopped.  first: length of the first
+// chunk.  Leaves the status block in the pinned mirror; *launched: the
+// number of iterations launched.
+template <class F>
+static int cg_run_chunks(fl_handle* h, double rtol, int maxit, const F& launch, int* launched, int first = 16) {
+    const int* hf = stat_flag(h->w_hstat);
+    const double* hs = stat_scal(h->w_hstat);
+    const double* hh = stat_hist(h->w_hstat);
+    int it = 0, m = first;
+    *launched = 0;
+    while (!hf[0] && it < maxit) {
+        m = std::max(1, std::min(m, maxit - it));
+        for (int j = 0; j < m; ++j) launch(it + j);
+        HIPCHK(hipGetLastError());
+        it += m;
+        *launched = it;
+        int rc = pull_status(h);
+        if (rc) return rc;
+        if (hf[0]) break;
+        // geometric rate over the last (up to 8) iterations of this chunk
+        const int q = std::min(8, m - 1);
+        const double ra = hh[(it - 1 - q) & 63], rb = hh[(it - 1) & 63], target = rtol * rtol * hs[0];
+        int next = 16;
+        if (q >= 1 && ra > 0 && rb > 0 && rb < ra && target > 0) {
+            const double per = std::log(rb / ra) / q;              // log of the rate per iteration
+            const double need = std::log(target / rb) / per;       // iterations still needed
+            if (need > 0 && need < 1e6) next = (int)std::ceil(1.1 * need) + 1;
+            else if (need <= 0) next = 2;
+        }
+        m = std::max(2, std::min(64, next));
+    }
+    return FL_OK;
+}
+}  // extern "C++"
+
 int fl_matvec(fl_handle* h, const double* x, double* y) {
     if (!h) return FL_EINVAL;
     if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
@@ -1058,8 +1121,8 @@ static int ensure_solver(fl_handle* h) {
     const int64_t ndot = (n + 255) / 256;
     HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(7 * n + 8)));
     HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * std::max<int64_t>(sp.nred, ndot) + 8)));
-    HIPCHK(hipMalloc((void**)&h->w_scal, sizeof(double) * 16));
-    HIPCHK(hipMalloc((void**)&h->w_flag, sizeof(int) * 8));
+    HIPCHK(hipMalloc((void**)&h->w_stat, FL_STAT_BYTES));
+    HIPCHK(hipHostMalloc((void**)&h->w_hstat, FL_STAT_BYTES, 0));
     if (h->opts.precision == FL_MIXED) HIPCHK(hipMalloc((void**)&h->w32, sizeof(float) * (size_t)(9 * n + 16)));
     HIPCHK(hipMalloc((void**)&h->w_sym, sizeof(double) * sym_plan_doubles(sp)));
     sym_plan_bind(&sp, h->w_sym);
@@ -1071,6 +1134,7 @@ static int ensure_solver(fl_handle* h) {
 // FP64 iterative refinement around FP32 Jacobi-PCG (FL_MIXED).
 static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit,
                        int32_t* iters, double* relres) {
+    int rc = FL_OK;
     const int64_t n = h->n;
     const int nblk = (int)((n + 255) / 256);
     double* r = h->w;                 // FP64 residual
@@ -1086,8 +1150,9 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     S.z = W + 4 * n;
     S.p = W + 5 * n;                  // 2 n
     S.part = h->w_part;
-    S.scal = h->w_scal;
-    S.flag = h->w_flag;
+    S.scal = stat_scal(h->w_stat);
+    S.flag = stat_flag(h->w_stat);
+    S.hist = stat_hist(h->w_stat);
     S.sp = h->sym;
     S.nblk = h->sym.nred;
     const double rtol_in = 1e-4;
@@ -1098,15 +1163,13 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     launch_diag32(h->dA32, h->lda, n, (float*)S.d, h->stream);
     launch_zero(u, n, h->stream);
     double bb = -1.0, rr = 0.0;
-    int total_inner = 0, outer = 0, status = FL_OK;
+    int total_inner = 0, outer = 0, status = FL_OK, last_inner = 0;
     for (;;) {
         launch_residual(h->sym, h->dA, h->lda, u, b, r, (float*)S.b, h->stream);
-        launch_dot2(r, r, r, n, h->w_part, nblk, h->w_scal + 8, h->stream);
+        launch_dot2(r, r, r, n, h->w_part, nblk, stat_scal(h->w_stat) + 8, h->stream);
         HIPCHK(hipGetLastError());
-        double rs[2];
-        HIPCHK(hipMemcpyAsync(rs, h->w_scal + 8, sizeof(rs), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        rr = rs[0];
+        if ((rc = pull_status(h))) return rc;
+        rr = stat_scal(h->w_hstat)[8];
         if (bb < 0) bb = rr;
         if (!(rr == rr) || rr > 1.79e308) { status = FL_ENONFINITE; break; }
         if (std::sqrt(rr) <= rtol * std::sqrt(bb) || total_inner >= maxit || outer >= 60) break;
@@ -1114,20 +1177,17 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
         S.rtol = rtol_in;
         S.maxit = maxit - total_inner;
         launch_cg32_init(S, h->stream);
-        int flag[3] = {0, 0, 0};
-        int it = 0;
-        HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        while (!flag[0] && it < S.maxit) {
-            int m = std::min(16, S.maxit - it);
-            for (int j = 0; j < m; ++j) launch_cg32_iter_at(S, it + j, h->stream);
-            HIPCHK(hipGetLastError());
-            it += m;
-            HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-        }
+        if ((rc = pull_status(h))) return rc;
+        // the first chunk: the previous correction's iteration count (same
+        // matrix, same relative tolerance) plus two
+        int launched = 0;
+        if ((rc = cg_run_chunks(h, S.rtol, S.maxit, [&](int it) { launch_cg32_iter_at(S, it, h->stream); },
+                                &launched, last_inner > 0 ? last_inner + 2 : 16)))
+            return rc;
+        const int* flag = stat_flag(h->w_hstat);
         if (flag[2] == 1) { status = FL_EBREAKDOWN; break; }
         total_inner += flag[1];
+        last_inner = flag[1];
         launch_add_correction(u, S.x, n, h->stream);
         ++outer;
     }
@@ -1178,8 +1238,9 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     S.b = b;
     S.x = u;
     S.part = h->w_part;
-    S.scal = h->w_scal;
-    S.flag = h->w_flag;
+    S.scal = stat_scal(h->w_stat);
+    S.flag = stat_flag(h->w_stat);
+    S.hist = stat_hist(h->w_stat);
     S.rtol = rtol;
     S.maxit = maxit;
     S.sp = h->sym;
@@ -1191,20 +1252,10 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     launch_diag(h->dA, h->lda, n, dd, h->stream);
     launch_cg_init(S, h->stream);
     HIPCHK(hipGetLastError());
-    int flag[4] = {0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    if (flag[2] == 2) return fail(h, FL_ENONFINITE, "right-hand side is not finite");
+    if ((rc = pull_status(h))) return rc;
+    if (stat_flag(h->w_hstat)[2] == 2) return fail(h, FL_ENONFINITE, "right-hand side is not finite");
     int it = 0;
-    const int chunk = 16;
-    while (!flag[0] && it < maxit) {
-        int m = std::min(chunk, maxit - it);
-        for (int j = 0; j < m; ++j) launch_cg_iter_at(S, it + j, h->stream);
-        HIPCHK(hipGetLastError());
-        it += m;
-        HIPCHK(hipMemcpyAsync(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-    }
+    if ((rc = cg_run_chunks(h, rtol, maxit, [&](int k) { launch_cg_iter_at(S, k, h->stream); }, &it))) return rc;
     // residual of the final iterate (when the loop ended at maxit)
     launch_cg_final(S, it, h->stream);
     HIPCHK(hipEventRecord(e1, h->stream));
@@ -1213,9 +1264,9 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    HIPCHK(hipMemcpy(flag, S.flag, sizeof(int) * 3, hipMemcpyDeviceToHost));
-    double sc[2];
-    HIPCHK(hipMemcpy(sc, S.scal, sizeof(double) * 2, hipMemcpyDeviceToHost));
+    if ((rc = pull_status(h))) return rc;
+    const int* flag = stat_flag(h->w_hstat);
+    const double* sc = stat_scal(h->w_hstat);
     int iterations = flag[1];
     double rel = sc[0] > 0 ? std::sqrt(sc[1]) / std::sqrt(sc[0]) : 0.0;
     h->st.t_solve_ms = ms;
@@ -1245,11 +1296,10 @@ int fl_energy_error2(fl_handle* h, double fu, const double* b, const double* uh,
     double* y = h->w + 6 * n;
     launch_symv(h->sym, h->dA, h->lda, uh, y, h->stream);
     const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    launch_dot2(uh, b, y, n, h->w_part, nblk, h->w_scal + 8, h->stream);
+    launch_dot2(uh, b, y, n, h->w_part, nblk, stat_scal(h->w_stat) + 8, h->stream);
     HIPCHK(hipGetLastError());
-    double r[2];
-    HIPCHK(hipMemcpyAsync(r, h->w_scal + 8, sizeof(r), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    if ((rc = pull_status(h))) return rc;
+    const double* r = stat_scal(h->w_hstat) + 8;
     *e2_out = fu - 2.0 * r[0] + r[1];
     return FL_OK;
 }

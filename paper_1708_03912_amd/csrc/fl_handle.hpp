@@ -49,6 +49,9 @@ struct fl_sur {
     double* ws = nullptr;                   // statistics / certification scratch
 };
 
+// Layout of the solver status block.
+constexpr size_t FL_STAT_SCAL = 64, FL_STAT_HIST = 192, FL_STAT_BYTES = 1024;
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -96,8 +99,8 @@ struct fl_handle {
     double* w = nullptr;   // r, z, p (2n), q, d, tmp (7 n)
     float* w32 = nullptr;  // FP32 refinement workspace (8 n)
     double* w_part = nullptr;
-    double* w_scal = nullptr;
-    int* w_flag = nullptr;
+    char* w_stat = nullptr;   // solver status block (device): int flags[16], double scal[16], double hist[64]
+    char* w_hstat = nullptr;  // its pinned host mirror
     int64_t w_n = -1;
     fl::SymPlan sym{};     // symmetric product of the n x n matrix (slots in w_sym)
     double* w_sym = nullptr;

@@ -178,6 +178,7 @@ struct CgState {
     double* part;       // 4 x nblk: r.z, r.r by parity
     double* scal;       // [0] b.b, [1] last r.r
     int* flag;          // [0] stop, [1] iterations, [2] 1 breakdown / 2 non-finite
+    double* hist;       // r.r at the start of iteration it, at hist[it % 64]
     double rtol;
     int maxit;
     int nblk;           // = sp.nred
@@ -203,6 +204,7 @@ struct CgState32 {
     double* part;
     double* scal;
     int* flag;
+    double* hist;
     double rtol;
     int maxit;
     int nblk;

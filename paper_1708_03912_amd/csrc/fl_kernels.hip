@@ -2073,6 +2073,7 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
     if (*(volatile int*)&S.flag[0]) return;
     block_sum3(rz, rr, rzp, sh);
+    if (bi == 0 && c == 0 && t == 0) S.hist[it & 63] = rr;
     const double bb = S.scal[0];
     if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
         if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
