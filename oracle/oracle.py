@@ -14,6 +14,8 @@ References are to Ainsworth & Glusa, arXiv:1708.03912:
                otherwise), stiffness matrix A^s.
   * Sec. 5   -- element-pair decomposition, Gauss-type quadrature with
                regularised touching pairs, Jacobi-preconditioned CG.
+  * Sec. 6   -- implicit steps of the fractional heat equation,
+               (M + dt A^s) u = b with the P1 mass matrix M.
   * Sec. 7   -- closed-form solutions on the unit ball, energy-error
                identity ||u-u_h||^2 = (f,u) - (f,u_h).
   * App. B   -- per-pair quadrature orders decreasing with dist/h.
@@ -341,6 +343,28 @@ def load_vector_one(mesh, dofs):
     for j in range(dim + 1):
         np.add.at(full, cells[:, j], meas / (dim + 1))
     return full[dofs]
+
+
+def mass_matrix(mesh, dofs):
+    """P1 mass matrix M_ij = int phi_i phi_j on the DOF set (Sec. 6: the
+    fractional heat equation's implicit step solves (M + dt A^s) u = b).
+    On each cell the integral of lambda_a lambda_b is |K| (1 + delta_ab) /
+    ((d+1)(d+2))."""
+    dim = mesh["dim"]
+    verts = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1, dim)
+    cells = np.asarray(mesh["cells"]).reshape(-1, dim + 1)
+    if dim == 1:
+        meas = np.abs(verts[cells[:, 1], 0] - verts[cells[:, 0], 0])
+    else:
+        a, b, c = verts[cells[:, 0]], verts[cells[:, 1]], verts[cells[:, 2]]
+        meas = 0.5 * np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1]))
+    nv = verts.shape[0]
+    full = np.zeros((nv, nv))
+    den = (dim + 1) * (dim + 2)
+    for i in range(dim + 1):
+        for j in range(dim + 1):
+            np.add.at(full, (cells[:, i], cells[:, j]), meas * (2.0 if i == j else 1.0) / den)
+    return full[np.ix_(dofs, dofs)].copy()
 
 
 def load_vector_fn(mesh, dofs, f, k=4):
