@@ -126,6 +126,15 @@ typedef struct {
                                             of each pair integral) a
                                             distance bin must meet to use
                                             the network (default 1e-2)     */
+    double mass_shift;                   /* mu >= 0: the assembled matrix is
+                                            A^s + mu M, M the P1 mass matrix
+                                            (M_ij = integral of phi_i phi_j)
+                                            on the DOFs.  Sec. 6: a backward
+                                            Euler step of the fractional
+                                            heat equation solves
+                                            (M + dt A^s) u = b, i.e.
+                                            (A^s + M/dt) u = b/dt.  0
+                                            (default): A^s alone           */
 } fl_opts;
 
 typedef struct {
@@ -209,6 +218,13 @@ int fl_export_matrix(fl_handle *h, double *dst, int64_t ld, int on_device);
 /* Load vector (Sec. 2: <f, phi_i>) for f = 1 on Omega, exactly:
  * b_i = sum_{K containing i} |K| / (d+1).  b: device, length n. */
 int fl_load_vector_one(fl_handle *h, double *b);
+
+/* y = M x with the P1 mass matrix on the DOFs of the last assembly
+ * (M_ij = integral of phi_i phi_j, exactly: |K| (1 + delta_ab) /
+ * ((d+1)(d+2)) per element), e.g. the right-hand side M u^n of an implicit
+ * heat step (Sec. 6).  x, y: device, length n, not aliased.  FL_ESTATE
+ * before fl_assemble. */
+int fl_mass_matvec(fl_handle *h, const double *x, double *y);
 
 /* y = A x with the FP64 matrix.  x, y: device, length n, not aliased.
  * Sec. 5: the dense product costs n^2 and drives the iterative solve.  A is

@@ -159,6 +159,8 @@ int check_opts(fl_handle* h, const fl_opts& o) {
         return fail(h, FL_EINVAL, "surrogate must lie in 0..n_classes (the last class stays exact)");
     if (o.surrogate > 0 && h->dim != 2) return fail(h, FL_EINVAL, "the surrogate is for triangle meshes (dim 2)");
     if (!(o.sur_tol >= 0.0)) return fail(h, FL_EINVAL, "sur_tol must be >= 0");
+    if (!(o.mass_shift >= 0.0) || !std::isfinite(o.mass_shift))
+        return fail(h, FL_EINVAL, "mass_shift must be finite and >= 0");
     for (int m = 0; m < o.n_classes; ++m) {
         if (!(o.theta[m] > 0.0) || !std::isfinite(o.theta[m]))
             return fail(h, FL_EINVAL, "theta must be positive and finite");
@@ -517,34 +519,39 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     // or one vertex.  The elements after Ki in a vertex's list are the Kt >
     // Ki at that vertex; shared-vertex counts through a marker array.
     std::vector<int> edge_pairs, vert_pairs;
-    edge_pairs.reserve((size_t)T * 4);
-    vert_pairs.reserve((size_t)T * 12);
-    {
-        std::vector<int> mark(T, -1), cnt(T, 0), seen;
-        seen.reserve(64);
+    bool touch_ok = true;
+    auto find_touching = [&]() {
+        edge_pairs.reserve((size_t)T * 4);
+        vert_pairs.reserve((size_t)T * 12);
+        std::vector<int> mark(T, -1), cnt(T, 0);
+        int seen[256];
         for (int64_t Ki = 0; Ki < T; ++Ki) {
-            seen.clear();
+            int ns = 0;
             for (int a = 0; a < nper; ++a) {
                 const int v = vid[a][Ki];
-                for (int e = lpos[Ki * nper + a] + 1; e < v2c_ptr[v + 1]; ++e) {
+                const int e1 = v2c_ptr[v + 1];
+                for (int e = lpos[Ki * nper + a] + 1; e < e1; ++e) {
                     const int Kt = v2c_idx[e];
                     if (mark[Kt] != (int)Ki) {
                         mark[Kt] = (int)Ki;
                         cnt[Kt] = 0;
-                        seen.push_back(Kt);
+                        if (ns == 256) { touch_ok = false; return; }
+                        seen[ns++] = Kt;
                     }
                     cnt[Kt]++;
                 }
             }
             // (first-seen order: deterministic; the touching kernels add into A)
-            for (int Kt : seen) {
-                int sh = cnt[Kt];
+            for (int q = 0; q < ns; ++q) {
+                const int Kt = seen[q], sh = cnt[Kt];
                 if (dim == 2 && sh == 2) { edge_pairs.push_back((int)Ki); edge_pairs.push_back(Kt); }
                 else if (sh == 1) { vert_pairs.push_back((int)Ki); vert_pairs.push_back(Kt); }
-                else return fail(h, FL_EMESH, "duplicate cells");
+                else { touch_ok = false; return; }
             }
         }
-    }
+    };
+    find_touching();
+    if (!touch_ok) return fail(h, FL_EMESH, "duplicate cells or a vertex shared by more than 256 cells");
     // far-field tiles, see launch_far_tiles
     const int nblk = (int)((T + BE - 1) / BE);
     P.nblk = nblk;
@@ -800,7 +807,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
     launch_scatter_self(E, h->d_v2c_ptr, h->d_v2c_idx, h->d_node2dof, (const unsigned char*)dv(o_vloc),
-                        (int)nv, dim, dS, A, lda, h->stream);
+                        (int)nv, dim, dS, o.mass_shift, A, lda, h->stream);
     HIPCHK(hipGetLastError());
     if (A32) {
         launch_to_f32(A, lda, n, A32, h->stream);
@@ -1043,6 +1050,18 @@ int fl_load_vector_one(fl_handle* h, double* b) {
 }
 
 static int ensure_solver(fl_handle* h);
+
+int fl_mass_matvec(fl_handle* h, const double* x, double* y) {
+    if (!h) return FL_EINVAL;
+    if (!h->planned) return fail(h, FL_ESTATE, "no assembly");
+    if (h->n == 0) return FL_OK;
+    if (!x || !y) return fail(h, FL_EINVAL, "null vector");
+    if (x == y) return fail(h, FL_EINVAL, "x and y must not alias");
+    HIPCHK(hipSetDevice(h->device));
+    launch_mass_matvec(h->E, h->d_dof_node, h->d_v2c_ptr, h->d_v2c_idx, h->d_vloc, h->dim, h->n, x, y, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
 
 extern "C++" {
 static int* stat_flag(char* b) { return (int*)b; }

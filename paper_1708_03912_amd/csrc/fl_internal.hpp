@@ -121,9 +121,14 @@ void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st);
 void launch_touch_edge2(const ElemDev& E, const TouchParams& P, hipStream_t st);
 void launch_touch_vert(const ElemDev& E, const TouchParams& P, hipStream_t st);
+// diagonal-block accumulators S into A, plus mass * (P1 mass matrix)
 void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx,
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
-                         const double* S, double* A, long long lda, hipStream_t st);
+                         const double* S, double mass, double* A, long long lda, hipStream_t st);
+// y = M x, M the P1 mass matrix on the DOFs
+void launch_mass_matvec(const ElemDev& E, const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
+                        const unsigned char* vloc, int dim, long long n, const double* x, double* y,
+                        hipStream_t st);
 void launch_zero(double* p, long long n, hipStream_t st);
 void launch_to_f32(const double* A, long long lda, long long n, float* A32, hipStream_t st);
 void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,

@@ -1598,13 +1598,20 @@ void launch_touch_vert(const ElemDev& E, const TouchParams& P, hipStream_t st) {
 
 // --------------------------------------------------- diagonal blocks --
 
+// P1 mass matrix entry of element K: integral of lambda_a lambda_b over K =
+// |K| (1 + delta_ab) / ((d + 1)(d + 2))
+__device__ __forceinline__ double mass_entry(double meas, int a, int b, int dim) {
+    return meas * (a == b ? 2.0 : 1.0) / (double)((dim + 1) * (dim + 2));
+}
+
 // One thread per vertex: for every element K containing it, add the row
-// of K's diagonal-block accumulator into A (only this thread writes the
-// row, so the result is deterministic).
+// of K's diagonal-block accumulator (and mass times K's mass matrix row)
+// into A (only this thread writes the row, so the result is deterministic).
 __global__ __launch_bounds__(256) void scatter_self_kernel(ElemDev E, const int* v2c_ptr,
                                                            const int* v2c_idx, const int* node2dof,
                                                            const unsigned char* vloc, int nv, int dim,
-                                                           const double* S, double* A, long long lda) {
+                                                           const double* S, double mass, double* A,
+                                                           long long lda) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
     const int i = node2dof[v];
@@ -1613,20 +1620,51 @@ __global__ __launch_bounds__(256) void scatter_self_kernel(ElemDev E, const int*
     for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
         const int K = v2c_idx[e];
         const int a = vloc[e];
+        const double mk = mass * E.meas[K];
         for (int b = 0; b <= dim; ++b) {
             int j = E.dof[b][K];
             if (j < 0) continue;
-            row[j] += S[(long long)K * 6 + sym3(a, b)];
+            double add = S[(long long)K * 6 + sym3(a, b)];
+            if (mass != 0.0) add += mass_entry(mk, a, b, dim);
+            row[j] += add;
         }
     }
 }
 
 void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx,
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
-                         const double* S, double* A, long long lda, hipStream_t st) {
+                         const double* S, double mass, double* A, long long lda, hipStream_t st) {
     dim3 grid((nv + 255) / 256), block(256);
     hipLaunchKernelGGL(scatter_self_kernel, grid, block, 0, st, E, v2c_ptr, v2c_idx, node2dof, vloc,
-                       nv, dim, S, A, lda);
+                       nv, dim, S, mass, A, lda);
+}
+
+// y_i = sum over the elements K of DOF i's vertex of K's mass matrix row
+// times x (one thread per DOF, fixed order)
+__global__ __launch_bounds__(256) void mass_matvec_kernel(ElemDev E, const int* dof_node, const int* v2c_ptr,
+                                                          const int* v2c_idx, const unsigned char* vloc,
+                                                          int dim, long long n, const double* x, double* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int v = dof_node[i];
+    double acc = 0.0;
+    for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
+        const int K = v2c_idx[e];
+        const int a = vloc[e];
+        for (int b = 0; b <= dim; ++b) {
+            const int j = E.dof[b][K];
+            if (j >= 0) acc += mass_entry(E.meas[K], a, b, dim) * x[j];
+        }
+    }
+    y[i] = acc;
+}
+
+void launch_mass_matvec(const ElemDev& E, const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
+                        const unsigned char* vloc, int dim, long long n, const double* x, double* y,
+                        hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(mass_matvec_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, E, dof_node,
+                       v2c_ptr, v2c_idx, vloc, dim, n, x, y);
 }
 
 __global__ void zero_kernel(double* p, long long n) {

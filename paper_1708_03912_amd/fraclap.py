@@ -36,7 +36,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_matmul", "fl_solve_batch", "fl_autotune", "fl_default_train_opts", "fl_pair_integrals",
            "fl_surrogate_dataset", "fl_surrogate_init", "fl_surrogate_fit_scaling",
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
-           "fl_surrogate_predict", "fl_surrogate_certify"]
+           "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -46,7 +46,7 @@ class FlOpts(C.Structure):
                 ("theta", C.c_double * FL_MAX_CLASSES),
                 ("k_far", C.c_int * (FL_MAX_CLASSES + 1)),
                 ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1)), ("precision", C.c_int),
-                ("surrogate", C.c_int), ("sur_tol", C.c_double)]
+                ("surrogate", C.c_int), ("sur_tol", C.c_double), ("mass_shift", C.c_double)]
 
 
 class FlStats(C.Structure):
@@ -105,6 +105,7 @@ def lib():
         L.fl_export_matrix.argtypes = [vp, vp, i64, C.c_int]
         L.fl_load_vector_one.argtypes = [vp, vp]
         L.fl_matvec.argtypes = [vp, vp, vp]
+        L.fl_mass_matvec.argtypes = [vp, vp, vp]
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_energy_error2.argtypes = [vp, dp, vp, vp, C.POINTER(dp)]
         L.fl_stats.argtypes = [vp, C.POINTER(FlStats)]
@@ -146,8 +147,11 @@ def default_train_opts(**kw) -> FlTrainOpts:
 
 
 def make_opts(k_touch=None, k_touch_bnd=None, theta=None, k_far=None, k_far_bnd=None,
-              dof_mode=None, with_boundary=None, precision=None, surrogate=None, sur_tol=None) -> FlOpts:
+              dof_mode=None, with_boundary=None, precision=None, surrogate=None, sur_tol=None,
+              mass_shift=None) -> FlOpts:
     o = default_opts()
+    if mass_shift is not None:
+        o.mass_shift = float(mass_shift)
     if surrogate is not None:
         o.surrogate = int(surrogate)
     if sur_tol is not None:
@@ -257,6 +261,9 @@ class Handle:
 
     def matvec(self, x, y):
         self._check(lib().fl_matvec(self.h, _ptr(x), _ptr(y)))
+
+    def mass_matvec(self, x, y):
+        self._check(lib().fl_mass_matvec(self.h, _ptr(x), _ptr(y)))
 
     def solve(self, b, u, rtol=1e-12, maxit=100000):
         it = C.c_int32()
