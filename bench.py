@@ -554,7 +554,7 @@ def c5_leg(args):
     80 GB, its FP32 copy 40 GB.  For s in {0.25, 0.75}, f = 1, interior
     DOFs: (a) plain FP64 assembly + Jacobi-PCG to 1e-10; (b) FL_MIXED
     assembly with the learned surrogate in classes 0-1 (trained on this
-    mesh's band pairs) + FP32 inner CG inside FP64 refinement.  Energy-norm
+    mesh's band pairs) + FP32 inner CG inside FP64 refinement (fl_solve).  Energy-norm
     errors against the closed-form solution, and the gap of (b) to (a) in
     the FP64 matrix."""
     import numpy as np
@@ -596,23 +596,21 @@ def c5_leg(args):
         res["fp64"] = {"n": n, "assemble_ms": round(t_asm, 1), "assemble_device_ms": round(st.t_assemble_ms, 1),
                        "separated_ms": round(st.t_far_ms, 1), "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
                        "solve_ms": round(t_sol, 1), "cg_iters": it, "relres": rel, "u": u, "b": b}
-        # (b) FL_MIXED + surrogate assembly (batch call, one s) and the
-        # batched Jacobi-PCG with FP32 matrix storage and reliable updates
+        # (b) FL_MIXED + surrogate assembly and the FP32 Jacobi-PCG (symmetric
+        # FP32 product) inside FP64 iterative refinement
         om = F.make_opts(dof_mode="interior", precision="mixed", surrogate=2, sur_tol=args.sur_tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nm = hs.assemble_batch([s], om)
+        nm = hs.assemble(s, om)
         torch.cuda.synchronize()
         t_asm = (time.perf_counter() - t0) * 1e3
         st = hs.stats()
-        bm = torch.zeros(1, nm, dtype=torch.float64, device="cuda")
-        hs.load_vector("one", bm)
-        Um = torch.zeros(1, 1, nm, dtype=torch.float64, device="cuda")
-        hs.solve_batch(bm, Um, rtol=1e-10, maxit=20000, inner="f32")   # converts A to FP32 (first use)
-        Um.zero_()
+        bm = torch.empty(nm, dtype=torch.float64, device="cuda")
+        hs.load_vector_one(bm)
+        um = torch.zeros(nm, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        itm, relm, rcm = hs.solve_batch(bm, Um, rtol=1e-10, maxit=20000, inner="f32")
+        itm, relm, rcm = hs.solve(bm, um, rtol=1e-10, maxit=20000)
         torch.cuda.synchronize()
         t_sol = (time.perf_counter() - t0) * 1e3
         res["mixed_surrogate"] = {"n": nm, "assemble_ms": round(t_asm, 1),
@@ -620,9 +618,9 @@ def c5_leg(args):
                                   "separated_ms": round(st.t_far_ms, 1),
                                   "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
                                   "pairs_surrogate": int(st.pairs_surrogate), "pairs_fallback": int(st.pairs_fallback),
-                                  "solve_ms": round(t_sol, 1), "cg_iters": int(itm.max()),
-                                  "residual_replacements": hs.stats().last_outer, "relres": float(relm.max()),
-                                  "u": Um[0, 0].clone(), "b": bm[0]}
+                                  "solve_ms": round(t_sol, 1), "inner_iters": itm,
+                                  "refinements": hs.stats().last_outer, "relres": relm,
+                                  "u": um, "b": bm}
         e2 = h64.energy_error2(ball_fu(s), res["fp64"]["b"], res["fp64"]["u"])
         E = math.sqrt(max(e2, 0.0))
         du = res["mixed_surrogate"]["u"] - res["fp64"]["u"]

@@ -1805,11 +1805,43 @@ __device__ __forceinline__ double half_wave_sum8(const double* v, int cp) {
     return y;
 }
 
-// the thread's 8 x 2 entries of each of the workgroup's M tiles; zero
-// outside n x n and beyond the last block
+// Raw loads of the thread's 8 x 2 entries of each of the workgroup's M
+// tiles.  Branch-free: indices outside n x n are clamped into the matrix
+// (rows to n - 1, columns to lda - 2) so that all 8 M loads issue back to
+// back; sym_unpack zeroes those entries afterwards.
+template <class T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+    using type = double2;
+};
+template <>
+struct Pair2<float> {
+    using type = float2;
+};
+
 template <class T, int M>
 __device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda, const SymPlan& P, long long I0,
-                                         int bj0, double (&a0)[M][8], double (&a1)[M][8]) {
+                                         int bj0, typename Pair2<T>::type (&raw)[M][8]) {
+    using V2 = typename Pair2<T>::type;
+    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
+    const long long n = P.n;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const long long j = min((long long)(bj0 + q) * SYM_TB + 2 * cp, lda - 2);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long long i = min(I0 + rg + 8 * k, n - 1);
+            raw[q][k] = *(const V2*)(A + i * lda + j);
+        }
+    }
+}
+
+// the loaded entries as FP64, zero outside n x n (padding columns hold
+// unspecified values)
+template <class T, int M>
+__device__ __forceinline__ void sym_unpack(const typename Pair2<T>::type (&raw)[M][8], const SymPlan& P,
+                                           long long I0, int bj0, double (&a0)[M][8], double (&a1)[M][8]) {
     const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
     const long long n = P.n;
 #pragma unroll
@@ -1817,14 +1849,9 @@ __device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda,
         const long long j = (long long)(bj0 + q) * SYM_TB + 2 * cp;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const long long i = I0 + rg + 8 * k;
-            a0[q][k] = 0.0;
-            a1[q][k] = 0.0;
-            if (i < n && j < n) ld2(A + i * lda + j, a0[q][k], a1[q][k]);
-        }
-        if (j + 1 >= n) {  // padding column: contents unspecified
-#pragma unroll
-            for (int k = 0; k < 8; ++k) a1[q][k] = 0.0;
+            const bool in = I0 + rg + 8 * k < n && j < n;
+            a0[q][k] = in ? (double)raw[q][k].x : 0.0;
+            a1[q][k] = (in && j + 1 < n) ? (double)raw[q][k].y : 0.0;
         }
     }
 }
@@ -1930,12 +1957,13 @@ __global__ __launch_bounds__(256) void symv_kernel(const T* __restrict__ A, long
     const int bi = blockIdx.y, c = blockIdx.x, bj0 = bi + c * M, t = threadIdx.x;
     if (bj0 >= P.nb) return;
     const long long I0 = (long long)bi * SYM_TB;
+    typename Pair2<T>::type raw[M][8];
+    sym_load<T, M>(A, lda, P, I0, bj0, raw);
+    const long long e = sym_vec_index(I0, bj0, t);
+    const T xv = x[min(e, P.n - 1)];
+    if (t < 64 * (M + 1)) sv[t] = e < P.n ? (double)xv : 0.0;
     double a0[M][8], a1[M][8];
-    sym_load<T, M>(A, lda, P, I0, bj0, a0, a1);
-    if (t < 64 * (M + 1)) {
-        const long long e = sym_vec_index(I0, bj0, t);
-        sv[t] = e < P.n ? (double)x[e] : 0.0;
-    }
+    sym_unpack<T, M>(raw, P, I0, bj0, a0, a1);
     __syncthreads();
     (void)sym_finish<M>(P, bi, c, a0, a1, sv, redc);
 }
@@ -2098,14 +2126,12 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     T* pcur = S.p + (long long)par * n;
     // loads that do not depend on the scalars: the tiles, z and p_{it-1} at
     // the staged vector entries, the partial sums
-    double a0[M][8], a1[M][8];
-    sym_load<T, M>(S.A, S.lda, P, I0, bj0, a0, a1);
+    typename Pair2<T>::type raw[M][8];
+    sym_load<T, M>(S.A, S.lda, P, I0, bj0, raw);
     const long long e = sym_vec_index(I0, bj0, t);
-    T zr = T(0), pr = T(0);
-    if (t < 64 * (M + 1) && e < n) {
-        zr = S.z[e];
-        pr = pprev[e];
-    }
+    const bool ein = t < 64 * (M + 1) && e < n;
+    const T zl = S.z[min(e, n - 1)], pl = pprev[min(e, n - 1)];
+    const T zr = ein ? zl : T(0), pr = ein ? pl : T(0);
     double rz = load_partials(S.part + par * S.nblk, S.nblk);
     double rr = load_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk);
     double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
@@ -2123,6 +2149,8 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
         return;
     }
     const T beta = (T)(it > 0 ? rz / rzp : 0.0);
+    double a0[M][8], a1[M][8];
+    sym_unpack<T, M>(raw, P, I0, bj0, a0, a1);
     if (t < 64 * (M + 1)) {
         const T v = zr + beta * pr;
         sv[t] = (double)v;
