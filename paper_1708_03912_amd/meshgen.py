@@ -16,6 +16,9 @@ so seeded stand-ins are generated here):
                            geometrically toward the re-entrant corner and the
                            boundary, size ratio up to 1:64.
 * ``square3(N)``        -- structured three-direction mesh of (-1,1)^2.
+* ``refine_uniform``,
+  ``hierarchy``         -- nested uniform refinements (for multigrid), with
+                           each fine vertex's coarse parents.
 
 Every mesh is a dict with ``dim``, ``verts`` (nv x dim float64), ``cells``
 (nc x (dim+1) int32) and ``bfacets`` (nb x dim int32).  Vertices and cells
@@ -40,10 +43,11 @@ def _morton_key(xy: np.ndarray, bits: int = 16) -> np.ndarray:
     return key
 
 
-def _finish(dim, verts, cells, bfacets, sort=True):
+def _finish(dim, verts, cells, bfacets, sort=True, want_perm=False):
     verts = np.asarray(verts, dtype=np.float64).reshape(-1, dim)
     cells = np.asarray(cells, dtype=np.int64).reshape(-1, dim + 1)
     bfacets = np.asarray(bfacets, dtype=np.int64).reshape(-1, dim)
+    perm = np.arange(len(verts))
     if sort and dim == 2:
         perm = np.argsort(_morton_key(verts), kind="stable")
         inv = np.empty_like(perm)
@@ -59,9 +63,61 @@ def _finish(dim, verts, cells, bfacets, sort=True):
         neg = det < 0
         cells[neg] = cells[neg][:, [0, 2, 1]]
         bfacets = bfacets[np.lexsort((bfacets[:, 1], bfacets[:, 0]))]
-    return {"dim": dim, "verts": np.ascontiguousarray(verts),
+    mesh = {"dim": dim, "verts": np.ascontiguousarray(verts),
             "cells": np.ascontiguousarray(cells, dtype=np.int32),
             "bfacets": np.ascontiguousarray(bfacets, dtype=np.int32)}
+    return (mesh, perm) if want_perm else mesh
+
+
+def refine_uniform(mesh):
+    """One uniform refinement: every segment is halved, every triangle split
+    into four by its edge midpoints (nested meshes for multigrid).  Returns
+    (fine mesh, parents): parents[v] (nv_fine x 2, int32) are the two coarse
+    vertices whose midpoint fine vertex v is, or (p, p) for a vertex inherited
+    from coarse vertex p."""
+    dim = mesh["dim"]
+    V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1, dim)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    B = np.asarray(mesh["bfacets"], dtype=np.int64)
+    nv = len(V)
+    if dim == 1:
+        mid = nv + np.arange(len(C))
+        verts = np.concatenate([V, 0.5 * (V[C[:, 0]] + V[C[:, 1]])])
+        cells = np.concatenate([np.stack([C[:, 0], mid], 1), np.stack([mid, C[:, 1]], 1)])
+        parents = np.concatenate([np.stack([np.arange(nv)] * 2, 1), C])
+        # keep vertices ordered along the line
+        order = np.argsort(verts[:, 0], kind="stable")
+        inv = np.empty_like(order)
+        inv[order] = np.arange(len(order))
+        fine = _finish(1, verts[order], inv[cells], inv[B], sort=False)
+        return fine, np.ascontiguousarray(parents[order], dtype=np.int32)
+    edges = np.concatenate([C[:, [0, 1]], C[:, [1, 2]], C[:, [2, 0]]])
+    key = np.sort(edges, axis=1)
+    uniq, inv_e = np.unique(key, axis=0, return_inverse=True)
+    inv_e = inv_e.reshape(-1)
+    mid = nv + inv_e.reshape(3, -1).T  # midpoint of edges (01, 12, 20) of each cell
+    verts = np.concatenate([V, 0.5 * (V[uniq[:, 0]] + V[uniq[:, 1]])])
+    m01, m12, m20 = mid[:, 0], mid[:, 1], mid[:, 2]
+    cells = np.concatenate([np.stack([C[:, 0], m01, m20], 1), np.stack([m01, C[:, 1], m12], 1),
+                            np.stack([m20, m12, C[:, 2]], 1), np.stack([m01, m12, m20], 1)])
+    bkey = np.sort(B, axis=1)
+    pos = {tuple(e): i for i, e in enumerate(uniq.tolist())}
+    bm = np.array([nv + pos[tuple(e)] for e in bkey.tolist()], dtype=np.int64)
+    bf = np.concatenate([np.stack([B[:, 0], bm], 1), np.stack([bm, B[:, 1]], 1)])
+    parents = np.concatenate([np.stack([np.arange(nv)] * 2, 1), uniq])
+    fine, perm = _finish(2, verts, cells, bf, want_perm=True)
+    return fine, np.ascontiguousarray(parents[perm], dtype=np.int32)
+
+
+def hierarchy(mesh, levels: int):
+    """Nested meshes [mesh, refine(mesh), ...] (levels meshes) and the
+    parent arrays of levels 1 .. levels-1 (see refine_uniform)."""
+    meshes, parents = [mesh], []
+    for _ in range(levels - 1):
+        m, p = refine_uniform(meshes[-1])
+        meshes.append(m)
+        parents.append(p)
+    return meshes, parents
 
 
 def interval(N: int, a: float = -1.0, b: float = 1.0):
