@@ -219,6 +219,32 @@ int fl_export_matrix(fl_handle *h, double *dst, int64_t ld, int on_device);
  * b_i = sum_{K containing i} |K| / (d+1).  b: device, length n. */
 int fl_load_vector_one(fl_handle *h, double *b);
 
+/* Geometric multigrid on nested meshes (Sec. 5: a solver whose iteration
+ * count stays bounded under refinement).  The handle's mesh (fl_set_mesh)
+ * is the finest of nlevels nested meshes and fl_assemble has built its
+ * matrix.  nv[l]: vertex count of level l (l = 0 coarsest, nv[nlevels-1] =
+ * the mesh's).  parents: host, levels l = 1 .. nlevels-1 concatenated, each
+ * nv[l] x 2 int32: the two coarse (level l-1) vertices of which vertex v is
+ * the edge midpoint, or (p, p) for the copy of coarse vertex p (every
+ * coarse vertex exactly once).  Each level uses the assembly's DOF rule
+ * (boundary status inherited through the copies).  Builds the
+ * prolongations of P1 functions, the Galerkin operators P^T A P on the
+ * device and the inverse of the coarsest one (at most 2048 DOFs).  A new
+ * fl_assemble / fl_import_matrix discards the hierarchy.  FL_EMESH for an
+ * inconsistent hierarchy, FL_EBREAKDOWN if the coarsest operator is not
+ * positive definite.  Synchronises the stream. */
+int fl_mg_setup(fl_handle *h, int nlevels, const int64_t *nv, const int32_t *parents);
+
+/* CG on A u = b preconditioned by one multigrid V(2,2) cycle (damped
+ * Jacobi, omega = 2/3, through the symmetric product on every level;
+ * coarsest level solved exactly).  b, u: device, length n; u is
+ * overwritten (initial guess 0).  Stops when ||r||_2 <= rtol ||b||_2 or
+ * after maxit iterations (then FL_ENOCONV).  FL_ESTATE without a current
+ * hierarchy; FL_EBREAKDOWN, FL_ENONFINITE as fl_solve.  Host iters /
+ * relres may be NULL.  Synchronises the stream. */
+int fl_solve_mg(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                double *relres);
+
 /* y = M x with the P1 mass matrix on the DOFs of the last assembly
  * (M_ij = integral of phi_i phi_j, exactly: |K| (1 + delta_ab) /
  * ((d+1)(d+2)) per element), e.g. the right-hand side M u^n of an implicit

@@ -1,9 +1,10 @@
 """Build libfraclap.so (gfx950) in-tree with hipcc.
 
 Translation units: the assembly / single-system solver kernels, the
-batched product / solver kernels and the surrogate network kernels (default
-floating-point contraction), the host planner (no contraction, see
-fl_api.hip), the batched host calls and the surrogate host calls.
+batched product / solver kernels, the surrogate network kernels and the
+multigrid kernels (default floating-point contraction), the host planner
+(no contraction, see fl_api.hip), the batched host calls, the surrogate
+host calls and the multigrid host calls.
 Packed FP32 instructions are disabled for all device code.  Units are built
 in parallel.
 """
@@ -18,8 +19,9 @@ ARCH = os.environ.get("FRACLAP_ARCH", "gfx950")
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []),
-         ("fl_api.hip", ["-ffp-contract=off"]), ("fl_batch_api.hip", []), ("fl_sur_api.hip", [])]
+UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
+         ("fl_api.hip", ["-ffp-contract=off"]), ("fl_batch_api.hip", []), ("fl_sur_api.hip", []),
+         ("fl_mg_api.hip", [])]
 
 
 def build(verbose=False):

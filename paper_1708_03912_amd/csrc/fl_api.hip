@@ -43,6 +43,7 @@ int fail(fl_handle* h, int code, const std::string& msg) {
 
 void reset_assembly(fl_handle* h) {
     h->assembled = false;
+    h->mg.ready = false;  // the hierarchy belongs to the previous matrix
     h->planned = false;
     h->B.ns = 0;
     h->n = h->lda = 0;
@@ -275,6 +276,7 @@ void fl_destroy(fl_handle* h) {
     free_buffers(h);
     free_solver(h);
     fl_sur_free(h);
+    fl_mg_free(h);
     delete h;
 }
 
@@ -1031,6 +1033,7 @@ int fl_import_matrix(fl_handle* h, const double* src, int64_t ld, int on_device)
     if (!src) return fail(h, FL_EINVAL, "null source");
     if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
     HIPCHK(hipSetDevice(h->device));
+    h->mg.ready = false;  // the hierarchy's coarse operators came from the old matrix
     HIPCHK(hipMemcpy2DAsync(h->dA, h->lda * sizeof(double), src, ld * sizeof(double), h->n * sizeof(double),
                             h->n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
     if (h->opts.precision == FL_MIXED && h->dA32) launch_to_f32(h->dA, h->lda, h->n, h->dA32, h->stream);
@@ -1064,6 +1067,8 @@ int fl_mass_matvec(fl_handle* h, const double* x, double* y) {
 }
 
 extern "C++" {
+int fl_solver_workspace(fl_handle* h) { return ensure_solver(h); }
+
 static int* stat_flag(char* b) { return (int*)b; }
 static double* stat_scal(char* b) { return (double*)(b + FL_STAT_SCAL); }
 static double* stat_hist(char* b) { return (double*)(b + FL_STAT_HIST); }

@@ -52,6 +52,37 @@ struct fl_sur {
 // Layout of the solver status block.
 constexpr size_t FL_STAT_SCAL = 64, FL_STAT_HIST = 192, FL_STAT_BYTES = 1024;
 
+// Multigrid hierarchy (fl_mg_setup): levels coarsest first; the finest
+// level is the handle's assembled matrix.
+struct fl_mg_level {
+    int64_t n = 0, lda = 0;
+    double* A = nullptr;            // Galerkin operator (below the finest level)
+    double* d = nullptr;            // its diagonal
+    double* x = nullptr;            // cycle vectors: correction, right-hand side, residual
+    double* b = nullptr;
+    double* r = nullptr;
+    fl::SymPlan sp{};               // symmetric product (below the finest level)
+    double* slots = nullptr;
+    // prolongation from the next coarser level: parents of each DOF (-1:
+    // none) and weights; restriction: children of each coarser DOF (CSR)
+    int2* par = nullptr;
+    double2* pw = nullptr;
+    int* cptr = nullptr;
+    int* cidx = nullptr;
+    double* cw = nullptr;
+};
+
+struct fl_mg {
+    bool ready = false;
+    std::vector<fl_mg_level> lev;
+    double* Ainv = nullptr;         // inverse of the coarsest operator (ld lev[0].lda)
+    double* B = nullptr;            // Galerkin workspace
+    double* cg = nullptr;           // fine CG vectors r, z, p, q
+    double* sc = nullptr;           // device scalars
+    double* hsc = nullptr;          // pinned mirror
+    int* dflag = nullptr;
+};
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -108,6 +139,7 @@ struct fl_handle {
     fl_stats_t st{};
     fl_batch B;
     fl_sur sur;
+    fl_mg mg;
 };
 
 // Quadrature tables independent of s (defined with the assembly driver).
@@ -117,3 +149,8 @@ const fl::RuleTables& fl_base_rules();
 // surrogate calls.
 int fl_sur_params(fl_handle* h, double s, const fl_opts& o, fl::SurParams* sp);
 void fl_sur_free(fl_handle* h);
+// Release the multigrid hierarchy (defined with the multigrid calls).
+void fl_mg_free(fl_handle* h);
+// Solver workspace of the current matrix, incl. its symmetric-product plan
+// (defined with the single-system solver).
+int fl_solver_workspace(fl_handle* h);

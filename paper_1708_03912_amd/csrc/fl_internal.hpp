@@ -168,6 +168,32 @@ void launch_symv(const SymPlan& P, const double* A, long long lda, const double*
 // r = b - A x (FP64), r32 = (float) r
 void launch_residual(const SymPlan& P, const double* A, long long lda, const double* x, const double* b,
                      double* r, float* r32, hipStream_t st);
+// mode 0: x += omega (b - A x) / d;  mode 1: r = b - A x
+void launch_sym_smooth(const SymPlan& P, const double* A, long long lda, double* x, const double* b,
+                       const double* d, double omega, int mode, double* r, hipStream_t st);
+
+// ------------------------------------------------------------ multigrid --
+// (fl_mg.hip) transfer operators between nested levels, Galerkin products,
+// coarsest-level inverse and the vector kernels of MG-preconditioned CG.
+void launch_mg_scale(double* x, const double* b, const double* d, double omega, long long n, hipStream_t st);
+// b_c[c] = sum over the children (f, w) of c of w r_f[f]   (P^T r)
+void launch_mg_restrict(long long nc, const int* cptr, const int* cidx, const double* cw, const double* rf,
+                        double* bc, hipStream_t st);
+// x_f[i] += sum over the (<= 2) parents (c, w) of i of w x_c[c]   (x += P x_c)
+void launch_mg_prolong_add(long long nf, const int2* par, const double2* pw, const double* xc, double* xf,
+                           hipStream_t st);
+// B = A P (nf x nc, ld ldb), then Ac = P^T B (nc x nc, ld ldc)
+void launch_mg_galerkin(const double* A, long long lda, long long nf, long long nc, const int* cptr,
+                        const int* cidx, const double* cw, double* B, long long ldb, double* Ac, long long ldc,
+                        hipStream_t st);
+// in-place inverse of an SPD n x n matrix (ld), Gauss-Jordan without
+// pivoting in one workgroup; flag[0] = 1 if a pivot is not positive
+void launch_mg_invert(double* M, long long n, long long ld, int* flag, hipStream_t st);
+// x += (sc[ia] / sc[ib]) p;  r -= (sc[ia] / sc[ib]) q
+void launch_mg_axpy(double* x, double* r, const double* p, const double* q, long long n, const double* sc, int ia,
+                    int ib, hipStream_t st);
+// p = z + (sc[ia] / sc[ib]) p
+void launch_mg_pupdate(double* p, const double* z, long long n, const double* sc, int ia, int ib, hipStream_t st);
 
 // CG building blocks
 struct CgState {

@@ -1988,6 +1988,19 @@ __global__ __launch_bounds__(256) void sym_residual_kernel(SymPlan P, const doub
     }
 }
 
+// Jacobi step x += omega (b - A x) / d (mode 0) or residual r = b - A x
+// (mode 1) from the slots of A x
+__global__ __launch_bounds__(256) void sym_smooth_kernel(SymPlan P, double* x, const double* b, const double* d,
+                                                         double omega, int mode, double* r) {
+    const long long i = (long long)blockIdx.x * (256 / P.G) + threadIdx.x / P.G;
+    const int g = threadIdx.x & (P.G - 1);
+    const double s = group_sum(sym_gather_share(P, i, g), P.G);
+    if (g == 0 && i < P.n) {
+        if (mode == 0) x[i] += omega * (b[i] - s) / d[i];
+        else r[i] = b[i] - s;
+    }
+}
+
 void sym_plan_geometry(long long n, SymPlan* P) {
     P->n = n;
     P->nb = (int)((n + SYM_TB - 1) / SYM_TB);
@@ -2039,6 +2052,13 @@ void launch_symv(const SymPlan& P, const double* A, long long lda, const double*
     if (P.n == 0) return;
     symv_launch(P, A, lda, x, st);
     hipLaunchKernelGGL(sym_reduce_kernel, dim3(P.nred), dim3(256), 0, st, P, y);
+}
+
+void launch_sym_smooth(const SymPlan& P, const double* A, long long lda, double* x, const double* b,
+                       const double* d, double omega, int mode, double* r, hipStream_t st) {
+    if (P.n == 0) return;
+    symv_launch(P, A, lda, (const double*)x, st);
+    hipLaunchKernelGGL(sym_smooth_kernel, dim3(P.nred), dim3(256), 0, st, P, x, b, d, omega, mode, r);
 }
 
 void launch_residual(const SymPlan& P, const double* A, long long lda, const double* x, const double* b,

@@ -36,7 +36,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_matmul", "fl_solve_batch", "fl_autotune", "fl_default_train_opts", "fl_pair_integrals",
            "fl_surrogate_dataset", "fl_surrogate_init", "fl_surrogate_fit_scaling",
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
-           "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec"]
+           "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -106,6 +106,8 @@ def lib():
         L.fl_load_vector_one.argtypes = [vp, vp]
         L.fl_matvec.argtypes = [vp, vp, vp]
         L.fl_mass_matvec.argtypes = [vp, vp, vp]
+        L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
+        L.fl_solve_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_energy_error2.argtypes = [vp, dp, vp, vp, C.POINTER(dp)]
         L.fl_stats.argtypes = [vp, C.POINTER(FlStats)]
@@ -264,6 +266,23 @@ class Handle:
 
     def mass_matvec(self, x, y):
         self._check(lib().fl_mass_matvec(self.h, _ptr(x), _ptr(y)))
+
+    def mg_setup(self, nv, parents):
+        """nv: vertex counts of the nested levels (coarsest first, the last
+        = this mesh); parents: the (nv[l] x 2) parent arrays of levels 1.."""
+        import numpy as np
+        nv = np.ascontiguousarray(nv, dtype=np.int64)
+        par = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32).reshape(-1)
+                                                   for p in parents]), dtype=np.int32)
+        self._check(lib().fl_mg_setup(self.h, len(nv), nv.ctypes.data_as(C.c_void_p),
+                                      par.ctypes.data_as(C.c_void_p)))
+
+    def solve_mg(self, b, u, rtol=1e-12, maxit=1000):
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = self._check(lib().fl_solve_mg(self.h, _ptr(b), _ptr(u), rtol, maxit, C.byref(it), C.byref(rel)),
+                         allow=(FL_OK, FL_ENOCONV))
+        return it.value, rel.value, rc
 
     def solve(self, b, u, rtol=1e-12, maxit=100000):
         it = C.c_int32()
