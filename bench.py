@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--c5", action="store_true",
                     help="run only the large-disk leg (~2e5 triangles, ~1e5 DOFs, 80 GB FP64 matrix): plain "
                          "FP64 vs FL_MIXED + surrogate, s in {0.25, 0.75}, and print its object")
+    ap.add_argument("--no-mg", action="store_true",
+                    help="skip the multigrid leg (nested disk meshes up to ~32k triangles)")
+    ap.add_argument("--only-mg", action="store_true", help="run only the multigrid leg and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -94,8 +97,8 @@ def copy_calib(mib):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the dense path's multi-GPU "
-              "row sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the multi-GPU sharding of the dense path is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calib:
         copy_calib(args.copy_calib)
@@ -114,6 +117,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
+        return
+    if args.only_mg:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"multigrid": mg_leg(args)}), flush=True)
         return
     import numpy as np
     import torch
@@ -247,6 +255,8 @@ def main():
         out["batch"] = batch_leg(args)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args)
+    if not args.no_mg:
+        out["multigrid"] = mg_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -652,6 +662,58 @@ def c5_leg(args):
         out[str(s)] = res
         h64.close()
     hs.close()
+    return out
+
+
+def mg_leg(args):
+    """Nested uniform refinements of a disk mesh (~500 triangles, 3 and 4
+    levels: ~8k and ~32k triangles), s in {0.25, 0.75}, f = 1: Jacobi-PCG
+    against CG preconditioned by one multigrid V(2,2) cycle (Sec. 5), both
+    to 1e-10; iterations, solve times, the hierarchy's setup time and the
+    energy-norm distance of the two solutions."""
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    base = M.disk_for_cells(500, seed=2)
+    out = {"workload": "unit disk, ~500-triangle base mesh refined uniformly (nested), f=1, CG to 1e-10: "
+                       "Jacobi-PCG vs multigrid V(2,2)-preconditioned CG"}
+    for levels in (3, 4):
+        meshes, parents = M.hierarchy(base, levels)
+        nv = [len(m["verts"]) for m in meshes]
+        for s in (0.25, 0.75):
+            h = F.Handle(0)
+            h.set_mesh(meshes[-1])
+            n = h.assemble(s)
+            b = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.load_vector_one(b)
+            uj, um = torch.zeros_like(b), torch.zeros_like(b)
+            h.solve(b, uj, rtol=1e-10, maxit=20000)  # warm-up (workspace)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            itj, relj, _ = h.solve(b, uj, rtol=1e-10, maxit=20000)
+            torch.cuda.synchronize()
+            tj = (time.perf_counter() - t0) * 1e3
+            t0 = time.perf_counter()
+            h.mg_setup(nv, parents)
+            torch.cuda.synchronize()
+            tset = (time.perf_counter() - t0) * 1e3
+            h.solve_mg(b, um, rtol=1e-10)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            itm, relm, _ = h.solve_mg(b, um, rtol=1e-10)
+            torch.cuda.synchronize()
+            tm = (time.perf_counter() - t0) * 1e3
+            du = um - uj
+            y = torch.empty_like(du)
+            h.matvec(du, y)
+            gap = float(torch.dot(du, y)) ** 0.5
+            h.matvec(uj, y)
+            unorm = float(torch.dot(uj, y)) ** 0.5
+            out[f"levels{levels}_s{s}"] = {"cells": len(meshes[-1]["cells"]), "n": n, "jacobi_iters": itj,
+                                           "jacobi_ms": round(tj, 3), "mg_setup_ms": round(tset, 3),
+                                           "mg_iters": itm, "mg_ms": round(tm, 3),
+                                           "speedup": round(tj / tm, 3) if tm > 0 else None,
+                                           "relres": [relj, relm], "gap_rel": gap / unorm if unorm > 0 else None}
+            h.close()
     return out
 
 
