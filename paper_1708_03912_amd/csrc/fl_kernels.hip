@@ -610,11 +610,13 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 cls = order_class(d2, hm, P.ncls, P.th2);
             }
         }
+        if constexpr (FARK == 0) {
 #pragma unroll
-        for (int c = 0; c <= FL_MAX_CLASSES; ++c) {
-            if (c <= P.ncls) {
-                unsigned long long bal = __ballot(cls == c);
-                if (lane == 0 && bal) atomicAdd(&ccount[c], (unsigned long long)__popcll(bal));
+            for (int c = 0; c <= FL_MAX_CLASSES; ++c) {
+                if (c <= P.ncls) {
+                    unsigned long long bal = __ballot(cls == c);
+                    if (lane == 0 && bal) atomicAdd(&ccount[c], (unsigned long long)__popcll(bal));
+                }
             }
         }
         double SK[6] = {0, 0, 0, 0, 0, 0}, ST[6] = {0, 0, 0, 0, 0, 0};
@@ -710,7 +712,14 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
         if (K < T && SI[i] != 0.0) atomicAdd(&P.S[(long long)K * 6 + i % 6], SI[i]);
         if (Kt2 < T && SJ[i] != 0.0) atomicAdd(&P.S[(long long)Kt2 * 6 + i % 6], SJ[i]);
     }
-    if (tid <= P.ncls && ccount[tid]) atomicAdd(&P.cls_count[tid], ccount[tid]);
+    if constexpr (FARK > 0) {
+        // far tile (bi != bj): every pair of its rows and columns, last class
+        if (tid == 0)
+            atomicAdd(&P.cls_count[P.ncls],
+                      (unsigned long long)(min(BE, T - I0) * (long long)min(BE, T - J0)));
+    } else {
+        if (tid <= P.ncls && ccount[tid]) atomicAdd(&P.cls_count[tid], ccount[tid]);
+    }
 }
 
 // Near tiles: the pairs of the tile are classified first and bucketed by
