@@ -182,7 +182,9 @@ const RuleTables& base_rules() {
     static RuleTables R = [] {
         RuleTables T;
         std::memset(&T, 0, sizeof(T));
-        for (int i = 0; i < 256; ++i) T.pw_inv[i] = (double)exp2l(-(long double)i / 256.0L);
+        // kernel-power tables: 1 / m_i with m_i = 1 + (i + 1/2) / 256, the
+        // midpoint of the mantissas whose top 8 bits are i
+        for (int i = 0; i < 256; ++i) T.pw_inv[i] = (double)(1.0L / (1.0L + ((long double)i + 0.5L) / 256.0L));
         for (int k = 1; k <= 16; ++k) {
             gauss_jacobi01(k, 0.0, 0.0, T.gl_x + gl_off(k), T.gl_w + gl_off(k));
             gauss_jacobi01(k, 1.0, 0.0, T.gj_x + gl_off(k), T.gj_w + gl_off(k));
@@ -327,7 +329,7 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
         if (!(meas > 0.0)) return fail(h, FL_EMESH, "degenerate cell " + std::to_string(K));
         if (dim == 2) {
             // The FP64 kernel power of the separated-pair kernels covers
-            // squared distances in [2^-125, 2^126).  A quadrature point of a
+            // squared distances in [2^-128, 2^128).  A quadrature point of a
             // triangle lies at least (smallest barycentric coordinate) x
             // (smallest height) from its boundary: above 2^-11 x 2 x inradius
             // for the rules of order <= 8, so separated pairs stay above
@@ -894,7 +896,7 @@ namespace fl {
 // (1 + t)^pe, |t| < 1.4e-3 (degree 5: truncation below 5e-17).
 void set_pow_tables(RuleTables& R, double pe) {
     const long double P = pe;
-    for (int i = 0; i < 256; ++i) R.pw_fr[i] = (double)exp2l(P * (long double)i / 256.0L);
+    for (int i = 0; i < 256; ++i) R.pw_fr[i] = (double)powl(1.0L + ((long double)i + 0.5L) / 256.0L, P);
     for (int n = -128; n < 128; ++n) R.pw_ex[n + 128] = (double)exp2l(P * (long double)n);
     long double c = 1.0L;
     R.pw_c[0] = 1.0;
