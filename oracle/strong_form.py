@@ -2,8 +2,9 @@
 Babuska-Rheinboldt type error indicators, plain numpy (test
 infrastructure only, like the rest of ``oracle/``).
 
-Sec. 4 of arXiv:1708.03912 (lemma on the strong form, eq. 8, d = 2,
-s != 1 - d/2): for x in the element K0,
+Sec. 4 of arXiv:1708.03912 (lemma on the strong form, eq. 8 for
+s != 1 - d/2; eq. 9, the logarithmic form, for d = 1, s = 1/2): for x in
+the element K0,
 
   (-Delta)^s u(x) / C(d,s)
     =  1/(d+2s-2) int_{dK0} grad u|K0 . n |x-y|^{-(d+2s-2)} dy
@@ -11,7 +12,10 @@ s != 1 - d/2): for x in the element K0,
      + sum_{K != K0} [ 1/(2s(d+2s-2)) int_{dK} grad u|K . n |x-y|^{-(d+2s-2)} dy
                        - 1/(2s) int_{dK} u(y) n . (x-y) |x-y|^{-(d+2s)} dy ]
 
-with n the outward normal of each element; and the indicators (eq. for
+with n the outward normal of each element (eq. 9: |x-y|^{-(d+2s-2)}/(d+2s-2)
+becomes log(1/|x-y|), i.e. the coefficients 1/(d+2s-2) and 1/(2s(d+2s-2))
+become 1 and 1/(2s)).  In d = 1 the boundary of an element is its two end
+points and the boundary integrals are point values; and the indicators (eq. for
 eta-hat_i) eta_i^2 = sum_{K containing node i} h_K^{2s} ||f - (-Delta)^s u||^2_{L2(K)}.
 
 Rule (the paper says the edge integrals are regular and standard rules
@@ -38,9 +42,23 @@ def _elements(mesh):
     return V, C, P, det
 
 
+def _dim(mesh):
+    return np.asarray(mesh["cells"]).shape[1] - 1
+
+
 def eval_points(mesh, k_eval):
-    """Collapsed Gauss points of every element: (T, k^2, 2) coordinates,
-    (T, k^2, 3) barycentric coordinates and (T, k^2) weights times |K|."""
+    """Evaluation points of every element.  d = 2: collapsed Gauss points,
+    (T, k^2, 2) coordinates, (T, k^2, 3) barycentric coordinates and
+    (T, k^2) weights times |K|.  d = 1: k Gauss-Legendre points, (T, k, 1),
+    (T, k, 2) and (T, k)."""
+    if _dim(mesh) == 1:
+        V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1)
+        C = np.asarray(mesh["cells"], dtype=np.int64)
+        t, w = O.gauss_legendre01(k_eval)
+        lam = np.stack([1 - t, t], axis=1)                            # (k, 2)
+        X = (lam[None, :, :] * V[C][:, None, :]).sum(-1)[..., None]
+        W = np.abs(V[C[:, 1]] - V[C[:, 0]])[:, None] * w[None, :]
+        return X, np.broadcast_to(lam, (len(C), k_eval, 2)), W
     V, C, P, det = _elements(mesh)
     ux, uw = O.gauss_jacobi01(k_eval, 1.0, 0.0)
     vx, vw = O.gauss_legendre01(k_eval)
@@ -56,9 +74,42 @@ def eval_points(mesh, k_eval):
     return X, np.broadcast_to(lam, (len(C), len(lam), 3)), W
 
 
+def _strong_form_1d(mesh, dofs, u, s, k_eval):
+    """d = 1: each element [a, b] contributes at its two end points p with
+    the outward normal n_p = sign(p - other end point)."""
+    V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    nod = np.zeros(len(V))
+    nod[np.asarray(dofs)] = u
+    X, lam, _ = eval_points(mesh, k_eval)
+    X = X[..., 0]                                                     # (T, k)
+    ux = (lam * nod[C][:, None, :]).sum(-1)
+    log_case = abs(s - 0.5) < 1e-15                                   # s = 1 - d/2
+    d2 = 2.0 * s - 1.0
+    out = np.zeros_like(X)
+    for K in range(len(C)):
+        a, b = V[C[K]]
+        g = (nod[C[K, 1]] - nod[C[K, 0]]) / (b - a)                    # u' on K
+        for p, q, up in ((a, b, nod[C[K, 0]]), (b, a, nod[C[K, 1]])):
+            n = np.sign(p - q)
+            dx = X - p
+            r = np.abs(dx)
+            gk = np.log(1.0 / r) if log_case else r ** (-d2)
+            cg_own, cg = (1.0, 1.0 / (2 * s)) if log_case else (1.0 / d2, 1.0 / (2 * s * d2))
+            ku = n * dx * r ** (-(1.0 + 2 * s))
+            own = np.zeros(len(C), dtype=bool)
+            own[K] = True
+            out += np.where(own[:, None], cg_own * g * n * gk - ux / (2 * s) * ku,
+                            cg * g * n * gk - up / (2 * s) * ku)
+    return O.cdn(1, s) * out
+
+
 def strong_form(mesh, dofs, u, s, k_eval=2, q_far=2, q_near=12):
-    """(-Delta)^s u_h at the evaluation points, (T, k_eval^2).  u: values on
-    the DOFs (zero at the other vertices)."""
+    """(-Delta)^s u_h at the evaluation points, (T, k_eval^d).  u: values on
+    the DOFs (zero at the other vertices).  q_far / q_near: edge rules in
+    d = 2 (unused in d = 1)."""
+    if _dim(mesh) == 1:
+        return _strong_form_1d(mesh, dofs, u, s, k_eval)
     V, C, P, det = _elements(mesh)
     T = len(C)
     nod = np.zeros(len(V))
@@ -111,12 +162,17 @@ def indicators(mesh, dofs, u, s, Lu, k_eval=2, f=None):
     """eta_K^2 = h_K^{2s} ||f - Lu||^2_{L2(K)} (collapsed rule) and the nodal
     eta_i^2 = sum over the elements containing vertex i.  f: values at the
     evaluation points (default 1).  Returns (eta_K^2 (T,), eta_i^2 (nv,))."""
-    V, C, P, det = _elements(mesh)
     _, _, W = eval_points(mesh, k_eval)
     fv = np.ones_like(Lu) if f is None else f
-    h2 = ((P[:, [1, 2, 0]] - P) ** 2).sum(-1).max(1)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    if _dim(mesh) == 1:
+        V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1)
+        h2 = (V[C[:, 1]] - V[C[:, 0]]) ** 2
+    else:
+        V, C, P, det = _elements(mesh)
+        h2 = ((P[:, [1, 2, 0]] - P) ** 2).sum(-1).max(1)
     ek = h2 ** s * (W * (fv - Lu) ** 2).sum(1)
     en = np.zeros(len(V))
-    for a in range(3):
+    for a in range(C.shape[1]):
         np.add.at(en, C[:, a], ek)
     return ek, en

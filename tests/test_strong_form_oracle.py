@@ -94,3 +94,69 @@ def test_indicators_sum_and_zero_residual():
     assert abs(en.sum() - 3 * ek.sum()) <= 1e-12 * en.sum()
     ek0, _ = SF.indicators(mesh, dofs, u, s, Lu, f=Lu)
     assert np.all(ek0 == 0)
+
+
+@pytest.mark.parametrize("s", [0.15, 0.4])
+def test_1d_constant_function_closed_form(s):
+    """d = 1, u_h = 1 on all nodes: (-Delta)^s u(x) = C(1,s)/(2s)
+    ((1+x)^{-2s} + (1-x)^{-2s}) exactly (integral over the complement)."""
+    mesh = M.interval_graded(48, 1.7)
+    dofs = O.dof_nodes(49, mesh["bfacets"], s)
+    Lu = SF.strong_form(mesh, dofs, np.ones(len(dofs)), s, k_eval=3)
+    x = SF.eval_points(mesh, 3)[0][..., 0]
+    ref = O.cdn(1, s) / (2 * s) * ((1 + x) ** (-2 * s) + (1 - x) ** (-2 * s))
+    assert np.abs(Lu - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_1d_log_form_is_the_limit_of_eq8():
+    """d = 1, s = 1/2 uses the logarithmic form (eq. 9); eq. 8 at
+    s = 1/2 +- 1e-7 must approach it (first order in the offset)."""
+    mesh = M.interval(32)
+    V = np.asarray(mesh["verts"]).ravel()
+    dofs = O.dof_nodes(33, mesh["bfacets"], 0.5)
+    u = (1 - V[dofs] ** 2) * np.cos(V[dofs])
+    L0 = SF.strong_form(mesh, dofs, u, 0.5, k_eval=3)
+    for ds in (1e-7, -1e-7):
+        L1 = SF.strong_form(mesh, dofs, u, 0.5 + ds, k_eval=3)
+        assert np.abs(L1 - L0).max() <= 1e-5 * np.abs(L0).max()
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_1d_pairing_with_basis_functions_is_the_matrix(s):
+    """int (-Delta)^s u_h phi_j dx = (A u)_j in d = 1 (A: the oracle's
+    matrix, exact for uniform meshes): Gauss rules of growing order on each
+    element converge to it (the strong form has |x - z|^{1-2s} kinks at
+    the nodes)."""
+    mesh = M.interval(16)
+    V = np.asarray(mesh["verts"]).ravel()
+    dofs = O.dof_nodes(17, mesh["bfacets"], s)
+    u = np.sin(2.0 * V[dofs] + 0.3) * (1 - V[dofs] ** 2)
+    A, _, _ = O.assemble(mesh, s, O.Orders())
+    Au = A @ u
+    C = np.asarray(mesh["cells"])
+    col = np.full(len(V), -1)
+    col[dofs] = np.arange(len(dofs))
+    gaps = []
+    for k in (8, 32):
+        Lu = SF.strong_form(mesh, dofs, u, s, k_eval=k)
+        _, lam, W = SF.eval_points(mesh, k)
+        pair = np.zeros(len(dofs) + 1)
+        for a in range(2):
+            np.add.at(pair, col[C[:, a]], (W * lam[:, :, a] * Lu).sum(1))
+        gaps.append(np.abs(pair[:-1] - Au).max() / np.abs(Au).max())
+    # the rule converges at the rate the node singularity allows (k^-1 for
+    # s = 3/4), so the gap must shrink by 3x from k = 8 to k = 32
+    assert gaps[1] < gaps[0] / 3 and gaps[1] <= 2e-2, gaps
+
+
+def test_1d_scaling():
+    s = 0.75
+    mesh = M.interval_graded(20, 1.5)
+    V = np.asarray(mesh["verts"]).ravel()
+    dofs = O.dof_nodes(21, mesh["bfacets"], s)
+    u = 1 - V[dofs] ** 2
+    L0 = SF.strong_form(mesh, dofs, u, s)
+    m2 = dict(mesh)
+    m2["verts"] = -2.5 * np.asarray(mesh["verts"]) + 4.0
+    L1 = SF.strong_form(m2, dofs, u, s)
+    assert np.abs(L1 - 2.5 ** (-2 * s) * L0).max() <= 1e-12 * np.abs(L0).max()
