@@ -245,6 +245,41 @@ int fl_mg_setup(fl_handle *h, int nlevels, const int64_t *nv, const int32_t *par
 int fl_solve_mg(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
                 double *relres);
 
+/* Evaluation points of the a posteriori indicators (Sec. 4: local L2
+ * norms by quadrature): k_eval in 1..8 points per direction in every cell
+ * (d = 2: the collapsed Gauss rule, Gauss-Jacobi(1,0) in the first
+ * barycentric coordinate l1 times Gauss-Legendre in l2 / (1 - l1), point q
+ * = i k_eval + j; d = 1: Gauss-Legendre), cells in the order given to
+ * fl_set_mesh.  x: device, nc x Q x d doubles (Q = k_eval^d); w: device,
+ * nc x Q weights times |K|.  Synchronises the stream. */
+int fl_eval_points(fl_handle *h, int32_t k_eval, double *x, double *w);
+
+/* Strong form (-Delta)^s u_h at the evaluation points of every cell, by
+ * the lemma of Sec. 4 (eq. 8: regular integrals over the cell boundaries;
+ * eq. 9, the logarithmic form, for d = 1 and s = 1/2).  u: device, the n
+ * DOF values of the last assembly's DOF map (zero at the other vertices);
+ * Lu: device, nc x Q doubles (layout of fl_eval_points).  Edge integrals
+ * (d = 2): q_far Gauss-Legendre points on the edges of cells sharing no
+ * vertex with the evaluation cell, q_near (both 1..16) on the others and on
+ * the cell itself; in d = 1 they are point values (q_far, q_near are
+ * checked but unused).  The geometry is prepared on the first call for a
+ * (mesh, DOF map, k_eval, q_far, q_near) and kept.  FL_ESTATE before
+ * fl_assemble; FL_EMESH for an interval mesh with cells below 2^-56 or an
+ * extent of 2^60 or more.  Asynchronous on the handle's stream. */
+int fl_strong_form(fl_handle *h, double s, const double *u, int32_t k_eval, int32_t q_far,
+                   int32_t q_near, double *Lu);
+
+/* Babuska-Rheinboldt type indicators of Sec. 4 from the strong form Lu of
+ * the last fl_strong_form call with this k_eval:
+ *   eta_cell[K] = h_K^{2s} ||f - Lu||^2_{L2(K)}   (h_K: longest edge),
+ *   eta_node[i] = sum of eta_cell over the cells containing vertex i
+ *                 (the squared eta-hat_i; every vertex, nv values).
+ * f: device, nc x Q values at the evaluation points, or NULL for f = 1.
+ * eta_cell: device, nc doubles; eta_node: device, nv doubles, or NULL.
+ * FL_ESTATE without a strong-form plan for k_eval.  Asynchronous. */
+int fl_indicators(fl_handle *h, double s, const double *Lu, const double *f, int32_t k_eval,
+                  double *eta_cell, double *eta_node);
+
 /* y = M x with the P1 mass matrix on the DOFs of the last assembly
  * (M_ij = integral of phi_i phi_j, exactly: |K| (1 + delta_ab) /
  * ((d+1)(d+2)) per element), e.g. the right-hand side M u^n of an implicit

@@ -104,12 +104,14 @@ def _strong_form_1d(mesh, dofs, u, s, k_eval):
     return O.cdn(1, s) * out
 
 
-def strong_form(mesh, dofs, u, s, k_eval=2, q_far=2, q_near=12):
+def strong_form(mesh, dofs, u, s, k_eval=2, q_far=2, q_near=12, cells=None):
     """(-Delta)^s u_h at the evaluation points, (T, k_eval^d).  u: values on
     the DOFs (zero at the other vertices).  q_far / q_near: edge rules in
-    d = 2 (unused in d = 1)."""
+    d = 2 (unused in d = 1).  cells: evaluate only in these cells (rows in
+    that order)."""
     if _dim(mesh) == 1:
-        return _strong_form_1d(mesh, dofs, u, s, k_eval)
+        out = _strong_form_1d(mesh, dofs, u, s, k_eval)
+        return out if cells is None else out[np.asarray(cells)]
     V, C, P, det = _elements(mesh)
     T = len(C)
     nod = np.zeros(len(V))
@@ -122,13 +124,15 @@ def strong_form(mesh, dofs, u, s, k_eval=2, q_far=2, q_near=12):
     sgn = np.sign(det)                                                 # +1 counter-clockwise
     X, lam, _ = eval_points(mesh, k_eval)
     ux = np.einsum("tqa,ta->tq", lam, U)                               # u at the points
+    tc = np.arange(T) if cells is None else np.asarray(cells)
+    X, ux = X[tc], ux[tc]
     d2 = 2.0 * s                                                       # d + 2s - 2, d = 2
     tf, wf = O.gauss_legendre01(q_far)
     tn, wn = O.gauss_legendre01(q_near)
     out = np.zeros(X.shape[:2])
     vid = C
     for K in range(T):
-        near = np.isin(vid, vid[K]).any(axis=1)                        # elements sharing a vertex with K
+        near = np.isin(vid[tc], vid[K]).any(axis=1)                    # target cells sharing a vertex with K
         for e in range(3):
             A_, B_ = P[K, e], P[K, (e + 1) % 3]
             ua, ub = U[K, e], U[K, (e + 1) % 3]
@@ -140,7 +144,7 @@ def strong_form(mesh, dofs, u, s, k_eval=2, q_far=2, q_near=12):
                     continue
                 Xs = X[sel]                                            # (m, Q, 2)
                 own = np.zeros(sel.sum(), dtype=bool)
-                own[np.nonzero(sel)[0] == K] = True
+                own[tc[sel] == K] = True
                 Y = A_[None, :] + tq[:, None] * (B_ - A_)[None, :]     # (q, 2)
                 Dv = Xs[:, :, None, :] - Y[None, None, :, :]           # (m, Q, q, 2)
                 r2 = (Dv ** 2).sum(-1)

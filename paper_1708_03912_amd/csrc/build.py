@@ -2,9 +2,10 @@
 
 Translation units: the assembly / single-system solver kernels, the
 batched product / solver kernels, the surrogate network kernels and the
-multigrid kernels (default floating-point contraction), the host planner
-(no contraction, see fl_api.hip), the batched host calls, the surrogate
-host calls and the multigrid host calls.
+multigrid kernels and the strong-form kernels (default floating-point
+contraction), the host planner (no contraction, see fl_api.hip), the
+batched host calls, the surrogate host calls, the multigrid host calls and
+the strong-form host calls.
 Packed FP32 instructions are disabled for all device code.  Units are built
 in parallel.
 """
@@ -20,8 +21,8 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
-         ("fl_api.hip", ["-ffp-contract=off"]), ("fl_batch_api.hip", []), ("fl_sur_api.hip", []),
-         ("fl_mg_api.hip", [])]
+         ("fl_sf.hip", []), ("fl_api.hip", ["-ffp-contract=off"]), ("fl_batch_api.hip", []),
+         ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", [])]
 
 
 def build(verbose=False):

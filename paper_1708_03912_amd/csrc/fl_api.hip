@@ -44,6 +44,7 @@ int fail(fl_handle* h, int code, const std::string& msg) {
 void reset_assembly(fl_handle* h) {
     h->assembled = false;
     h->mg.ready = false;  // the hierarchy belongs to the previous matrix
+    h->sf.ready = false;  // so does the strong-form geometry (DOF map)
     h->planned = false;
     h->B.ns = 0;
     h->n = h->lda = 0;
@@ -279,6 +280,7 @@ void fl_destroy(fl_handle* h) {
     free_solver(h);
     fl_sur_free(h);
     fl_mg_free(h);
+    fl_sf_free(h);
     delete h;
 }
 
@@ -888,6 +890,7 @@ bool fits(fl_handle* h, double bytes) {
 }  // namespace
 
 const fl::RuleTables& fl_base_rules() { return base_rules(); }
+double fl_cdn(int d, double s) { return cdn(d, s); }
 
 namespace fl {
 // r2^pe = 2^(pe (n + i/256)) (1 + t)^pe with 2^(n + i/256) the nearest

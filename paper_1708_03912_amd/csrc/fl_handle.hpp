@@ -83,6 +83,26 @@ struct fl_mg {
     int* dflag = nullptr;
 };
 
+// Strong-form evaluation (fl_strong_form): geometry of one (mesh, DOF map,
+// k_eval, edge rules) combination, rebuilt when any of them changes.
+struct fl_sf {
+    bool ready = false;
+    int k = 0, qf = 0, qn = 0, nch = 0;
+    int64_t n = -1;                 // DOF count the plan was built for
+    fl::SfDev D{};
+    long long chunk = 0;
+    double* sx = nullptr;           // source coordinates
+    double* sy = nullptr;
+    double* W = nullptr;            // evaluation weights times |K|
+    double* h2 = nullptr;           // squared cell diameters
+    int* vptr = nullptr;            // vertex -> cells (CSR) for the nodal indicators
+    int* vidx = nullptr;
+    double* part = nullptr;         // far-field partial sums, nch x nt
+    double* tab = nullptr;          // kernel-power tables of tab_s
+    double tab_s = -1.0;
+    std::vector<void*> bufs;        // every allocation above
+};
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -140,10 +160,14 @@ struct fl_handle {
     fl_batch B;
     fl_sur sur;
     fl_mg mg;
+    fl_sf sf;
 };
 
 // Quadrature tables independent of s (defined with the assembly driver).
 const fl::RuleTables& fl_base_rules();
+// C(d,s), the constant of the operator (Sec. 2)
+double fl_cdn(int d, double s);
+void fl_sf_free(fl_handle* h);
 // Surrogate parameters of an assembly at s with options o (classes below
 // o.surrogate); FL_ESTATE without a network and scaling.  Defined with the
 // surrogate calls.

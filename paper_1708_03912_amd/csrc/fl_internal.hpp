@@ -195,6 +195,43 @@ void launch_mg_axpy(double* x, double* r, const double* p, const double* q, long
 // p = z + (sc[ia] / sc[ib]) p
 void launch_mg_pupdate(double* p, const double* z, long long n, const double* sc, int ia, int ib, hipStream_t st);
 
+// Strong form of the fractional Laplacian of a P1 function (Sec. 4, lemma
+// on the strong form) at the evaluation points of every cell, and the
+// error indicators built on it.  Cells in the caller's order.
+struct SfDev {
+    int dim, Q;             // space dimension, evaluation points per cell
+    long long T, nt;        // cells, targets T * Q
+    const double* cx;       // vertex coordinates of each cell, (dim + 1) * dim per cell
+    const int* cdof;        // DOF of each cell vertex, -1 if none
+    const double* lam;      // Q x (dim + 1) barycentric coordinates of the points
+    const double* tx;       // target coordinates (ty: zeros in d = 1)
+    const double* ty;
+    long long nf;           // facets: edges (d = 2), vertices (d = 1)
+    const int* fK;          // per facet: cell K1, cell K2 (-1 on the boundary)
+    const double* fN;       // outward normal of K1 times the facet measure (dim per facet)
+    int qf, qn;             // edge rules of the separated and the touching cells (d = 2)
+    const double* gx;       // Gauss-Legendre nodes / weights on [0,1], k = 1..16
+    const double* gw;
+    long long ns;           // sources: facets x qf (d = 2), facets (d = 1)
+    double* sc;             // source coefficients (per call)
+    const int* nptr;        // cells sharing a vertex with each cell, itself included (d = 1: itself)
+    const int* nidx;
+    long long nbf;          // boundary facets: owner cell, local facet index
+    const int2* bf;
+    int bnd_u;              // boundary vertices carry DOFs (u-terms of boundary facets)
+    double pe;              // exponent of r^2 in |x-y|^{-(d+2s-2)}: -(d + 2s - 2)/2
+    double cg, cg_own;      // 1/(2s(d+2s-2)) and 1/(d+2s-2); 1/(2s) and 1 in the log form
+    double inv2s, C;        // 1/(2s), C(d,s)
+};
+void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st);
+void launch_sf_far(const SfDev& D, const double* sx, const double* sy, long long chunk, int nch,
+                   const double* tab, double* part, bool logk, hipStream_t st);
+void launch_sf_near(const SfDev& D, const double* u, const double* part, int nch, const double* tab,
+                    double* Lu, bool logk, hipStream_t st);
+void launch_sf_indicators(const SfDev& D, const double* Lu, const double* f, const double* W,
+                          const double* h2, double s, long long nv, const int* vptr, const int* vidx,
+                          double* eta_cell, double* eta_node, hipStream_t st);
+
 // CG building blocks
 struct CgState {
     long long n;

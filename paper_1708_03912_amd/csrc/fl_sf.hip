@@ -1,0 +1,348 @@
+// Strong form of the fractional Laplacian of a P1 function and the
+// Babuska-Rheinboldt type error indicators (Sec. 4: the lemma on the strong
+// form, eq. 8, and eq. 9 for d = 1, s = 1/2; the indicators eta-hat_i).
+//
+// Eq. 8 sums, for x in K0, boundary integrals of every cell K: a gradient
+// term grad u|K . n |x-y|^{-(d+2s-2)} and a value term u(y) n.(x-y)
+// |x-y|^{-(d+2s)}, with other coefficients on K0 itself.  The evaluation is
+// split so that the all-pairs part is a plain potential sum:
+//   * far (sf_far_kernel): every cell with the separated-cell rule.  On a
+//     facet shared by two cells the value terms cancel (u is continuous,
+//     the normals are opposite), so each facet carries one coefficient,
+//     the jump of the normal derivative: a sum of c_j |x - y_j|^{-(d+2s-2)}
+//     over q_far Gauss points y_j per facet.  Boundary facets keep their
+//     gradient term here and their value term in the next kernel.
+//   * near (sf_near_kernel): for the cells sharing a vertex with K0 the
+//     separated-cell terms are replaced by the touching-cell rule (with
+//     K0's own coefficients on K0); the value terms of boundary facets
+//     (present only when boundary vertices carry DOFs, s < 1/2); the
+//     far-field partial sums are reduced in a fixed order.
+// Both kernels are FP64.  In d = 1 a facet is a vertex and its integral a
+// point value; only K0 itself needs a correction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fl_internal.hpp"
+#include "fl_math.hpp"
+
+namespace fl {
+
+namespace {
+
+constexpr int SF_TILE = 256;  // sources staged in LDS per step
+constexpr int SF_TPT = 2;     // targets per thread in the far kernel
+
+// u at vertex a of cell K (0 if the vertex carries no DOF)
+__device__ __forceinline__ double uval(const SfDev& D, const double* u, long long K, int a) {
+    const int d = D.cdof[K * (D.dim + 1) + a];
+    return d >= 0 ? u[d] : 0.0;
+}
+
+// Cell K: vertex coordinates, values, gradient of u and orientation sign.
+template <int DIM>
+struct SfCell {
+    double p[DIM + 1][DIM];
+    double u[DIM + 1];
+    double g[DIM];
+    double sgn;
+};
+
+template <int DIM>
+__device__ __forceinline__ void load_cell(const SfDev& D, const double* u, long long K, SfCell<DIM>& c) {
+    const double* x = D.cx + K * (DIM + 1) * DIM;
+    for (int a = 0; a <= DIM; ++a) {
+        for (int d = 0; d < DIM; ++d) c.p[a][d] = x[a * DIM + d];
+        c.u[a] = uval(D, u, K, a);
+    }
+    if constexpr (DIM == 1) {
+        const double h = c.p[1][0] - c.p[0][0];
+        c.g[0] = (c.u[1] - c.u[0]) / h;
+        c.sgn = h > 0.0 ? 1.0 : -1.0;
+    } else {
+        // solve [b - a; c - a] g = [u_b - u_a; u_c - u_a]
+        const double e1x = c.p[1][0] - c.p[0][0], e1y = c.p[1][1] - c.p[0][1];
+        const double e2x = c.p[2][0] - c.p[0][0], e2y = c.p[2][1] - c.p[0][1];
+        const double det = e1x * e2y - e2x * e1y;
+        const double d1 = c.u[1] - c.u[0], d2 = c.u[2] - c.u[0];
+        c.g[0] = (d1 * e2y - d2 * e1y) / det;
+        c.g[1] = (e1x * d2 - e2x * d1) / det;
+        c.sgn = det > 0.0 ? 1.0 : -1.0;
+    }
+}
+
+// Facet e of a cell: start point A, direction E (B - A), outward normal N
+// times the facet measure, end values.  d = 2: edge from vertex e to vertex
+// e + 1; d = 1: vertex e, E = 0, N = +-1.
+template <int DIM>
+struct SfFacet {
+    double A[2], E[2], N[2], ua, ub;
+};
+
+template <int DIM>
+__device__ __forceinline__ SfFacet<DIM> facet_of(const SfCell<DIM>& c, int e) {
+    SfFacet<DIM> f;
+    if constexpr (DIM == 1) {
+        f.A[0] = c.p[e][0];
+        f.A[1] = 0.0;
+        f.E[0] = f.E[1] = 0.0;
+        f.N[0] = (c.p[e][0] > c.p[1 - e][0]) ? 1.0 : -1.0;
+        f.N[1] = 0.0;
+        f.ua = f.ub = c.u[e];
+    } else {
+        const int b = e == 2 ? 0 : e + 1;
+        f.A[0] = c.p[e][0];
+        f.A[1] = c.p[e][1];
+        f.E[0] = c.p[b][0] - c.p[e][0];
+        f.E[1] = c.p[b][1] - c.p[e][1];
+        f.N[0] = c.sgn * f.E[1];
+        f.N[1] = -c.sgn * f.E[0];
+        f.ua = c.u[e];
+        f.ub = c.u[b];
+    }
+    return f;
+}
+
+// Rule sums over one facet: Ig = sum w g(r2), Iu = sum w kern n.(x-y) u(y),
+// Io = sum w kern n.(x-y), with g = |x-y|^{-(d+2s-2)} (log(1/|x-y|) in the
+// log form) and kern = |x-y|^{-(d+2s)} = g / r2 (1 / r2 in the log form).
+template <int DIM, bool LOGK, class POW>
+__device__ __forceinline__ void facet_sums(const SfFacet<DIM>& f, double x, double y, int q, const double* gx,
+                                           const double* gw, const POW& P, double& Ig, double& Iu, double& Io) {
+    Ig = Iu = Io = 0.0;
+    const int nq = DIM == 1 ? 1 : q;
+    const int off = gl_off(nq);
+    for (int j = 0; j < nq; ++j) {
+        const double t = DIM == 1 ? 0.0 : gx[off + j];
+        const double w = DIM == 1 ? 1.0 : gw[off + j];
+        const double dx = x - fma(t, f.E[0], f.A[0]);
+        const double dy = DIM == 1 ? 0.0 : y - fma(t, f.E[1], f.A[1]);
+        const double r2 = fma(dx, dx, dy * dy);
+        double g, kern;
+        if constexpr (LOGK) {
+            g = -0.5 * log(r2);
+            kern = 1.0 / r2;
+        } else {
+            g = P(r2);
+            kern = g / r2;
+        }
+        const double nd = fma(dx, f.N[0], dy * f.N[1]);
+        const double uy = fma(t, f.ub - f.ua, f.ua);
+        Ig = fma(w, g, Ig);
+        const double wk = w * kern * nd;
+        Iu = fma(wk, uy, Iu);
+        Io += wk;
+    }
+}
+
+__device__ __forceinline__ void load_tab(double* pw, const double* tab) {
+    for (int i = threadIdx.x; i < 768; i += blockDim.x) pw[i] = tab[i];
+}
+
+__device__ __forceinline__ KPowTab tab_pow(const double* pw, const double* tab) {
+    return KPowTab{pw, tab[769], tab[770], tab[771], tab[772], tab[773]};
+}
+
+// One thread per facet: coefficients of its q_far sources,
+//   c_j = w_j (grad u|K1 . N - grad u|K2 . N) cg   (N: outward of K1).
+template <int DIM>
+__global__ __launch_bounds__(256) void sf_sources_kernel(SfDev D, const double* __restrict__ u) {
+    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= D.nf) return;
+    const int K1 = D.fK[2 * f], K2 = D.fK[2 * f + 1];
+    SfCell<DIM> c;
+    load_cell<DIM>(D, u, K1, c);
+    const double N0 = D.fN[DIM * f], N1 = DIM == 2 ? D.fN[DIM * f + 1] : 0.0;
+    double gN = DIM == 2 ? fma(c.g[0], N0, c.g[DIM - 1] * N1) : c.g[0] * N0;
+    if (K2 >= 0) {
+        load_cell<DIM>(D, u, K2, c);
+        gN -= DIM == 2 ? fma(c.g[0], N0, c.g[DIM - 1] * N1) : c.g[0] * N0;
+    }
+    gN *= D.cg;
+    if constexpr (DIM == 1) {
+        D.sc[f] = gN;
+    } else {
+        const int off = gl_off(D.qf);
+        for (int j = 0; j < D.qf; ++j) D.sc[f * D.qf + j] = D.gw[off + j] * gN;
+    }
+}
+
+// Targets x SF_TPT per thread, a chunk of sources per workgroup row:
+//   part[chunk][t] = sum_j c_j g(|x_t - y_j|^2).
+// Sources pass through LDS (broadcast reads), the kernel power through the
+// LDS tables; no branch in the inner loop.
+template <bool LOGK>
+__global__ __launch_bounds__(256) void sf_far_kernel(long long nt, const double* __restrict__ tx,
+                                                     const double* __restrict__ ty, long long ns,
+                                                     const double* __restrict__ sx, const double* __restrict__ sy,
+                                                     const double* __restrict__ sc, long long chunk,
+                                                     const double* __restrict__ tab, double* __restrict__ part) {
+    __shared__ double pw[768];
+    __shared__ double4 src[SF_TILE];
+    const int tid = threadIdx.x;
+    if constexpr (!LOGK) load_tab(pw, tab);
+    const KPowTab P = tab_pow(pw, tab);
+    double x[SF_TPT], y[SF_TPT], acc[SF_TPT];
+#pragma unroll
+    for (int i = 0; i < SF_TPT; ++i) {
+        long long t = (long long)blockIdx.x * (256 * SF_TPT) + i * 256 + tid;
+        t = t < nt ? t : nt - 1;
+        x[i] = tx[t];
+        y[i] = ty[t];
+        acc[i] = 0.0;
+    }
+    const long long j0 = (long long)blockIdx.y * chunk;
+    const long long j1 = j0 + chunk < ns ? j0 + chunk : ns;
+    for (long long jt = j0; jt < j1; jt += SF_TILE) {
+        const int m = (int)(j1 - jt < SF_TILE ? j1 - jt : SF_TILE);
+        __syncthreads();
+        if (tid < m) src[tid] = make_double4(sx[jt + tid], sy[jt + tid], sc[jt + tid], 0.0);
+        __syncthreads();
+#pragma unroll 2
+        for (int j = 0; j < m; ++j) {
+            const double4 S = src[j];
+#pragma unroll
+            for (int i = 0; i < SF_TPT; ++i) {
+                const double dx = x[i] - S.x, dy = y[i] - S.y;
+                const double r2 = fma(dx, dx, dy * dy);
+                const double g = LOGK ? -0.5 * log(r2) : P(r2);
+                acc[i] = fma(S.z, g, acc[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < SF_TPT; ++i) {
+        const long long t = (long long)blockIdx.x * (256 * SF_TPT) + i * 256 + tid;
+        if (t < nt) part[(long long)blockIdx.y * nt + t] = acc[i];
+    }
+}
+
+// One thread per target (cell K0, point q): the far partial sums, the
+// touching cells with their own rule, the boundary value terms; times C.
+template <int DIM, bool LOGK>
+__global__ __launch_bounds__(256) void sf_near_kernel(SfDev D, const double* __restrict__ u,
+                                                      const double* __restrict__ part, int nch,
+                                                      const double* __restrict__ tab, double* __restrict__ Lu) {
+    __shared__ double pw[768];
+    if constexpr (!LOGK) load_tab(pw, tab);
+    __syncthreads();
+    const KPowTab P = tab_pow(pw, tab);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= D.nt) return;
+    const long long K0 = t / D.Q;
+    const int q = (int)(t - K0 * D.Q);
+    const double x = D.tx[t], y = D.ty[t];
+    double acc = 0.0;
+    for (int c = 0; c < nch; ++c) acc += part[(long long)c * D.nt + t];
+    double ux = 0.0;
+    for (int a = 0; a <= DIM; ++a) ux = fma(D.lam[q * (DIM + 1) + a], uval(D, u, K0, a), ux);
+    SfCell<DIM> c;
+    double corr = 0.0;
+    for (int e = D.nptr[K0]; e < D.nptr[K0 + 1]; ++e) {
+        const int K = D.nidx[e];
+        load_cell<DIM>(D, u, K, c);
+        const bool own = K == K0;
+        for (int fi = 0; fi <= DIM; ++fi) {
+            const SfFacet<DIM> f = facet_of<DIM>(c, fi);
+            const double gN = fma(c.g[0], f.N[0], DIM == 2 ? c.g[DIM - 1] * f.N[1] : 0.0);
+            double Igf, Iuf, Iof, Ign, Iun, Ion;
+            facet_sums<DIM, LOGK>(f, x, y, D.qf, D.gx, D.gw, P, Igf, Iuf, Iof);
+            facet_sums<DIM, LOGK>(f, x, y, D.qn, D.gx, D.gw, P, Ign, Iun, Ion);
+            const double farv = D.cg * gN * Igf - D.inv2s * Iuf;
+            const double nearv = own ? D.cg_own * gN * Ign - D.inv2s * ux * Ion : D.cg * gN * Ign - D.inv2s * Iun;
+            corr += nearv - farv;
+        }
+    }
+    if (D.bnd_u) {
+        for (long long b = 0; b < D.nbf; ++b) {
+            const int2 kb = D.bf[b];
+            load_cell<DIM>(D, u, kb.x, c);
+            const SfFacet<DIM> f = facet_of<DIM>(c, kb.y);
+            if (f.ua == 0.0 && f.ub == 0.0) continue;
+            double Ig, Iu, Io;
+            facet_sums<DIM, LOGK>(f, x, y, D.qf, D.gx, D.gw, P, Ig, Iu, Io);
+            corr -= D.inv2s * Iu;
+        }
+    }
+    Lu[t] = D.C * (acc + corr);
+}
+
+// eta_K^2 = h_K^{2s} sum_q W_q (f_q - Lu_q)^2 (f = 1 if null)
+__global__ __launch_bounds__(256) void sf_ind_cell_kernel(long long T, int Q, const double* __restrict__ Lu,
+                                                          const double* __restrict__ f,
+                                                          const double* __restrict__ W,
+                                                          const double* __restrict__ h2, double s,
+                                                          double* __restrict__ eta) {
+    const long long K = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= T) return;
+    double acc = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const long long i = K * Q + q;
+        const double r = (f ? f[i] : 1.0) - Lu[i];
+        acc = fma(W[i] * r, r, acc);
+    }
+    eta[K] = pow(h2[K], s) * acc;
+}
+
+// eta_i^2 = sum of eta_K^2 over the cells containing vertex i (fixed order)
+__global__ __launch_bounds__(256) void sf_ind_node_kernel(long long nv, const int* __restrict__ vptr,
+                                                          const int* __restrict__ vidx,
+                                                          const double* __restrict__ eta_c,
+                                                          double* __restrict__ eta_n) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    double acc = 0.0;
+    for (int e = vptr[v]; e < vptr[v + 1]; ++e) acc += eta_c[vidx[e]];
+    eta_n[v] = acc;
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st) {
+    if (D.nf == 0) return;
+    if (D.dim == 1)
+        hipLaunchKernelGGL(sf_sources_kernel<1>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
+    else
+        hipLaunchKernelGGL(sf_sources_kernel<2>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
+}
+
+void launch_sf_far(const SfDev& D, const double* sx, const double* sy, long long chunk, int nch,
+                   const double* tab, double* part, bool logk, hipStream_t st) {
+    if (D.nt == 0 || nch == 0) return;
+    const dim3 grid((unsigned)((D.nt + 256 * SF_TPT - 1) / (256 * SF_TPT)), (unsigned)nch);
+    if (logk)
+        hipLaunchKernelGGL(sf_far_kernel<true>, grid, dim3(256), 0, st, D.nt, D.tx, D.ty, D.ns, sx, sy, D.sc,
+                           chunk, tab, part);
+    else
+        hipLaunchKernelGGL(sf_far_kernel<false>, grid, dim3(256), 0, st, D.nt, D.tx, D.ty, D.ns, sx, sy, D.sc,
+                           chunk, tab, part);
+}
+
+void launch_sf_near(const SfDev& D, const double* u, const double* part, int nch, const double* tab,
+                    double* Lu, bool logk, hipStream_t st) {
+    if (D.nt == 0) return;
+    const dim3 grid(nblk(D.nt));
+    if (D.dim == 1) {
+        if (logk)
+            hipLaunchKernelGGL((sf_near_kernel<1, true>), grid, dim3(256), 0, st, D, u, part, nch, tab, Lu);
+        else
+            hipLaunchKernelGGL((sf_near_kernel<1, false>), grid, dim3(256), 0, st, D, u, part, nch, tab, Lu);
+    } else {
+        hipLaunchKernelGGL((sf_near_kernel<2, false>), grid, dim3(256), 0, st, D, u, part, nch, tab, Lu);
+    }
+}
+
+void launch_sf_indicators(const SfDev& D, const double* Lu, const double* f, const double* W,
+                          const double* h2, double s, long long nv, const int* vptr, const int* vidx,
+                          double* eta_cell, double* eta_node, hipStream_t st) {
+    if (D.T == 0) return;
+    hipLaunchKernelGGL(sf_ind_cell_kernel, dim3(nblk(D.T)), dim3(256), 0, st, D.T, D.Q, Lu, f, W, h2, s,
+                       eta_cell);
+    if (eta_node && nv > 0)
+        hipLaunchKernelGGL(sf_ind_node_kernel, dim3(nblk(nv)), dim3(256), 0, st, nv, vptr, vidx, eta_cell,
+                           eta_node);
+}
+
+}  // namespace fl

@@ -1,0 +1,412 @@
+// Host side of the strong-form evaluation and the error indicators
+// (include/fraclap.h: fl_eval_points, fl_strong_form, fl_indicators).
+// Sec. 4: the indicators eta-hat_i need the L2 norms of the residual
+// f - (-Delta)^s u_h on every cell, and the lemma on the strong form turns
+// the pointwise values into regular boundary integrals (eq. 8; eq. 9 for
+// d = 1, s = 1/2).  The plan holds the geometry (evaluation points,
+// facets, Gauss points on the facets, touching-cell lists); the kernels
+// (fl_sf.hip) take the coefficients of u.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "fl_handle.hpp"
+#include "fl_internal.hpp"
+
+using namespace fl;
+
+namespace {
+
+constexpr int SF_WG_TARGETS = 512;   // targets per far-kernel workgroup
+constexpr int SF_MAX_CHUNKS = 64;
+
+int sfail(fl_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return sfail(h, FL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int sf_upload(fl_handle* h, T** p, const std::vector<T>& v) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(v.size(), 1)) != hipSuccess)
+        return sfail(h, FL_ENOMEM, "strong form: device allocation failed");
+    h->sf.bufs.push_back(q);
+    *p = (T*)q;
+    if (!v.empty()) HIPCHK(hipMemcpy(q, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return FL_OK;
+}
+
+template <class T>
+int sf_alloc(fl_handle* h, T** p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return sfail(h, FL_ENOMEM, "strong form: device allocation failed");
+    h->sf.bufs.push_back(q);
+    *p = (T*)q;
+    return FL_OK;
+}
+
+void sf_release(fl_handle* h) {
+    for (void* p : h->sf.bufs) (void)hipFree(p);
+    h->sf = fl_sf{};
+}
+
+// Evaluation rule of a cell with k points per direction: barycentric
+// coordinates (Q x (d+1)) and weights on the reference cell summing to 1.
+// d = 2: the collapsed Gauss rule (Gauss-Jacobi(1,0) x Gauss-Legendre);
+// d = 1: Gauss-Legendre.
+void eval_rule(int dim, int k, std::vector<double>& lam, std::vector<double>& w) {
+    const RuleTables& R = fl_base_rules();
+    lam.clear();
+    w.clear();
+    if (dim == 1) {
+        for (int i = 0; i < k; ++i) {
+            const double t = R.gl_x[gl_off(k) + i];
+            lam.push_back(1.0 - t);
+            lam.push_back(t);
+            w.push_back(R.gl_w[gl_off(k) + i]);
+        }
+    } else {
+        for (int m = tri_off(k); m < tri_off(k) + k * k; ++m) {
+            const double l1 = R.tl1[m], l2 = R.tl2[m];
+            lam.push_back(1.0 - l1 - l2);
+            lam.push_back(l1);
+            lam.push_back(l2);
+            w.push_back(R.tw[m]);
+        }
+    }
+}
+
+// Points (nc x Q x dim) and weights times |K| (nc x Q), cells in the
+// caller's order.
+void eval_points_host(const fl_handle* h, int k, std::vector<double>& X, std::vector<double>& W) {
+    const int dim = h->dim, nper = dim + 1;
+    std::vector<double> lam, w;
+    eval_rule(dim, k, lam, w);
+    const int Q = (int)w.size();
+    X.assign((size_t)h->nc * Q * dim, 0.0);
+    W.assign((size_t)h->nc * Q, 0.0);
+    for (int64_t K = 0; K < h->nc; ++K) {
+        const int32_t* c = &h->cells[nper * K];
+        double meas;
+        if (dim == 1) {
+            meas = std::fabs(h->verts[c[1]] - h->verts[c[0]]);
+        } else {
+            const double* a = &h->verts[2 * c[0]];
+            const double* b = &h->verts[2 * c[1]];
+            const double* d = &h->verts[2 * c[2]];
+            meas = 0.5 * std::fabs((b[0] - a[0]) * (d[1] - a[1]) - (d[0] - a[0]) * (b[1] - a[1]));
+        }
+        for (int q = 0; q < Q; ++q) {
+            for (int j = 0; j < dim; ++j) {
+                double x = 0.0;
+                for (int a = 0; a < nper; ++a) x += lam[q * nper + a] * h->verts[dim * c[a] + j];
+                X[((size_t)K * Q + q) * dim + j] = x;
+            }
+            W[(size_t)K * Q + q] = meas * w[q];
+        }
+    }
+}
+
+int check_rules(fl_handle* h, int k, int qf, int qn) {
+    if (k < 1 || k > 8) return sfail(h, FL_EINVAL, "k_eval must lie in 1..8");
+    if (qf < 1 || qf > 16 || qn < 1 || qn > 16) return sfail(h, FL_EINVAL, "q_far and q_near must lie in 1..16");
+    return FL_OK;
+}
+
+// Geometry of the evaluation for (mesh, DOF map, k, qf, qn).
+int sf_plan(fl_handle* h, int k, int qf, int qn) {
+    fl_sf& S = h->sf;
+    if (S.ready && S.k == k && S.qf == qf && S.qn == qn && S.n == h->n) return FL_OK;
+    HIPCHK(hipStreamSynchronize(h->stream));  // earlier launches may still read the old plan
+    sf_release(h);
+    const int dim = h->dim, nper = dim + 1;
+    const int64_t T = h->nc, nv = h->nv;
+    if (dim == 1) {
+        // the kernel-power tables cover r^2 in [2^-128, 2^128): points lie
+        // at least 0.0198 h_K from the vertices for k <= 8
+        double lo = h->verts[0], hi = h->verts[0], hmin = INFINITY;
+        for (int64_t v = 0; v < nv; ++v) lo = std::min(lo, h->verts[v]), hi = std::max(hi, h->verts[v]);
+        for (int64_t K = 0; K < T; ++K)
+            hmin = std::min(hmin, std::fabs(h->verts[h->cells[2 * K + 1]] - h->verts[h->cells[2 * K]]));
+        if (!(hi - lo < 0x1p60) || !(hmin >= 0x1p-56))
+            return sfail(h, FL_EMESH, "interval mesh outside the supported scale (cells >= 2^-56, extent < 2^60)");
+    }
+    std::vector<double> lam, wq, X, W;
+    eval_rule(dim, k, lam, wq);
+    const int Q = (int)wq.size();
+    eval_points_host(h, k, X, W);
+    const long long nt = (long long)T * Q;
+    std::vector<double> tx(nt), ty(nt, 0.0), h2(T), cx((size_t)T * nper * dim);
+    std::vector<int> cdof((size_t)T * nper);
+    for (long long t = 0; t < nt; ++t) {
+        tx[t] = X[(size_t)t * dim];
+        if (dim == 2) ty[t] = X[(size_t)t * dim + 1];
+    }
+    for (int64_t K = 0; K < T; ++K) {
+        const int32_t* c = &h->cells[nper * K];
+        for (int a = 0; a < nper; ++a) {
+            cdof[K * nper + a] = h->node2dof[c[a]];
+            for (int j = 0; j < dim; ++j) cx[(K * nper + a) * dim + j] = h->verts[dim * c[a] + j];
+        }
+        double m = 0.0;
+        for (int a = 0; a < nper; ++a)
+            for (int b = a + 1; b < nper; ++b) {
+                double l = 0.0;
+                for (int j = 0; j < dim; ++j) {
+                    const double e = h->verts[dim * c[b] + j] - h->verts[dim * c[a] + j];
+                    l += e * e;
+                }
+                m = std::max(m, l);
+            }
+        h2[K] = m;
+    }
+    // vertex -> cells (increasing)
+    std::vector<int> vptr(nv + 1, 0), vidx((size_t)T * nper);
+    for (int64_t i = 0; i < T * nper; ++i) vptr[h->cells[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    {
+        std::vector<int> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t K = 0; K < T; ++K)
+            for (int a = 0; a < nper; ++a) vidx[fill[h->cells[nper * K + a]]++] = (int)K;
+    }
+    // facets: (K1, local index e1) and (K2, e2) or K2 = -1
+    std::vector<int> fK;
+    std::vector<int> fE;
+    if (dim == 1) {
+        for (int64_t v = 0; v < nv; ++v) {
+            const int n = vptr[v + 1] - vptr[v];
+            if (n == 0) continue;
+            const int K1 = vidx[vptr[v]];
+            fK.push_back(K1);
+            fK.push_back(n > 1 ? vidx[vptr[v] + 1] : -1);
+            fE.push_back(h->cells[2 * K1] == v ? 0 : 1);
+        }
+    } else {
+        std::vector<unsigned long long> key((size_t)T * 3);
+        for (int64_t K = 0; K < T; ++K)
+            for (int e = 0; e < 3; ++e) {
+                const unsigned a = (unsigned)h->cells[3 * K + e], b = (unsigned)h->cells[3 * K + (e + 1) % 3];
+                const unsigned long long lo = std::min(a, b), hi = std::max(a, b);
+                key[K * 3 + e] = (lo << 32) | hi;
+            }
+        std::vector<int64_t> ord((size_t)T * 3);
+        for (int64_t i = 0; i < T * 3; ++i) ord[i] = i;
+        std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return key[x] < key[y] || (key[x] == key[y] && x < y); });
+        for (size_t i = 0; i < ord.size();) {
+            size_t j = i + 1;
+            while (j < ord.size() && key[ord[j]] == key[ord[i]]) ++j;
+            if (j - i > 2) return sfail(h, FL_EMESH, "an edge lies on more than two cells");
+            fK.push_back((int)(ord[i] / 3));
+            fK.push_back(j - i == 2 ? (int)(ord[i + 1] / 3) : -1);
+            fE.push_back((int)(ord[i] % 3));
+            i = j;
+        }
+    }
+    const long long nf = (long long)fE.size();
+    const RuleTables& R = fl_base_rules();
+    const int qsrc = dim == 1 ? 1 : qf;
+    const long long ns = nf * qsrc;
+    std::vector<double> fN(nf * dim), sx(ns), sy(ns, 0.0);
+    std::vector<int2> bf;
+    for (long long f = 0; f < nf; ++f) {
+        const int K1 = fK[2 * f], e = fE[f];
+        const int32_t* c = &h->cells[nper * K1];
+        if (dim == 1) {
+            const double p = h->verts[c[e]], o = h->verts[c[1 - e]];
+            fN[f] = p > o ? 1.0 : -1.0;
+            sx[f] = p;
+        } else {
+            const double* A = &h->verts[2 * c[e]];
+            const double* B = &h->verts[2 * c[(e + 1) % 3]];
+            const double* Cc = &h->verts[2 * c[(e + 2) % 3]];
+            const double E0 = B[0] - A[0], E1 = B[1] - A[1];
+            const double det = E0 * (Cc[1] - A[1]) - (Cc[0] - A[0]) * E1;
+            const double sg = det > 0.0 ? 1.0 : -1.0;
+            fN[2 * f] = sg * E1;
+            fN[2 * f + 1] = -sg * E0;
+            for (int j = 0; j < qf; ++j) {
+                const double t = R.gl_x[gl_off(qf) + j];
+                sx[f * qf + j] = std::fma(t, E0, A[0]);
+                sy[f * qf + j] = std::fma(t, E1, A[1]);
+            }
+        }
+        if (fK[2 * f + 1] < 0) bf.push_back(make_int2(K1, e));
+    }
+    // touching cells: sharing a vertex (d = 2), the cell itself (d = 1)
+    std::vector<int> nptr(T + 1, 0), nidx;
+    {
+        std::vector<int> tmp;
+        for (int64_t K = 0; K < T; ++K) {
+            if (dim == 1) {
+                nidx.push_back((int)K);
+            } else {
+                tmp.clear();
+                for (int a = 0; a < 3; ++a) {
+                    const int v = h->cells[3 * K + a];
+                    tmp.insert(tmp.end(), vidx.begin() + vptr[v], vidx.begin() + vptr[v + 1]);
+                }
+                std::sort(tmp.begin(), tmp.end());
+                tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+                nidx.insert(nidx.end(), tmp.begin(), tmp.end());
+            }
+            nptr[K + 1] = (int)nidx.size();
+        }
+    }
+    // far-kernel grid: enough workgroups for the chip, sources split in chunks
+    const long long ntb = (nt + SF_WG_TARGETS - 1) / SF_WG_TARGETS;
+    int nch = (int)std::min<long long>(SF_MAX_CHUNKS, std::max<long long>(1, (2048 + ntb - 1) / std::max<long long>(ntb, 1)));
+    long long chunk = (ns + nch - 1) / nch;
+    chunk = std::max<long long>(256, (chunk + 255) / 256 * 256);
+    nch = (int)std::max<long long>(1, (ns + chunk - 1) / chunk);
+
+    std::vector<double> gx(R.gl_x, R.gl_x + GL_TAB), gw(R.gl_w, R.gl_w + GL_TAB);
+    SfDev D{};
+    D.dim = dim;
+    D.Q = Q;
+    D.T = T;
+    D.nt = nt;
+    D.nf = nf;
+    D.qf = dim == 1 ? 1 : qf;
+    D.qn = dim == 1 ? 1 : qn;
+    D.ns = ns;
+    D.nbf = (long long)bf.size();
+    D.bnd_u = 0;
+    for (int64_t v = 0; v < nv; ++v)
+        if (h->on_boundary[v] && h->node2dof[v] >= 0) D.bnd_u = 1;
+    int rc;
+    double *p_cx, *p_lam, *p_tx, *p_ty, *p_fN, *p_gx, *p_gw, *p_sc;
+    int *p_cdof, *p_fK, *p_nptr, *p_nidx;
+    int2* p_bf;
+    if ((rc = sf_upload(h, &p_cx, cx)) || (rc = sf_upload(h, &p_cdof, cdof)) || (rc = sf_upload(h, &p_lam, lam)) ||
+        (rc = sf_upload(h, &p_tx, tx)) || (rc = sf_upload(h, &p_ty, ty)) || (rc = sf_upload(h, &p_fK, fK)) ||
+        (rc = sf_upload(h, &p_fN, fN)) || (rc = sf_upload(h, &p_gx, gx)) || (rc = sf_upload(h, &p_gw, gw)) ||
+        (rc = sf_upload(h, &p_nptr, nptr)) || (rc = sf_upload(h, &p_nidx, nidx)) || (rc = sf_upload(h, &p_bf, bf)) ||
+        (rc = sf_upload(h, &S.sx, sx)) || (rc = sf_upload(h, &S.sy, sy)) || (rc = sf_upload(h, &S.W, W)) ||
+        (rc = sf_upload(h, &S.h2, h2)) || (rc = sf_upload(h, &S.vptr, vptr)) || (rc = sf_upload(h, &S.vidx, vidx)) ||
+        (rc = sf_alloc(h, &p_sc, (size_t)ns)) || (rc = sf_alloc(h, &S.part, (size_t)nch * nt)) ||
+        (rc = sf_alloc(h, &S.tab, 776))) {
+        sf_release(h);
+        return rc;
+    }
+    D.cx = p_cx;
+    D.cdof = p_cdof;
+    D.lam = p_lam;
+    D.tx = p_tx;
+    D.ty = p_ty;
+    D.fK = p_fK;
+    D.fN = p_fN;
+    D.gx = p_gx;
+    D.gw = p_gw;
+    D.sc = p_sc;
+    D.nptr = p_nptr;
+    D.nidx = p_nidx;
+    D.bf = p_bf;
+    S.D = D;
+    S.k = k;
+    S.qf = qf;
+    S.qn = qn;
+    S.n = h->n;
+    S.nch = nch;
+    S.chunk = chunk;
+    S.tab_s = -1.0;
+    S.ready = true;
+    return FL_OK;
+}
+
+bool log_form(int dim, double s) { return dim == 1 && std::fabs(s - 0.5) < 1e-15; }
+
+// kernel-power tables of r2^pe, pe = -(d + 2s - 2)/2: pairs (1/m_i,
+// m_i^pe), 2^(pe n), the Taylor coefficients (776 doubles)
+int sf_tables(fl_handle* h, double s) {
+    fl_sf& S = h->sf;
+    if (S.tab_s == s) return FL_OK;
+    std::unique_ptr<RuleTables> R(new RuleTables(fl_base_rules()));
+    set_pow_tables(*R, -0.5 * (h->dim + 2.0 * s - 2.0));
+    std::vector<double> t(776, 0.0);
+    for (int i = 0; i < 256; ++i) {
+        t[2 * i] = R->pw_inv[i];
+        t[2 * i + 1] = R->pw_fr[i];
+        t[512 + i] = R->pw_ex[i];
+    }
+    for (int i = 0; i < 8; ++i) t[768 + i] = R->pw_c[i];
+    HIPCHK(hipStreamSynchronize(h->stream));  // earlier launches may still read the old tables
+    HIPCHK(hipMemcpy(S.tab, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    S.tab_s = s;
+    return FL_OK;
+}
+
+}  // namespace
+
+void fl_sf_free(fl_handle* h) { sf_release(h); }
+
+extern "C" {
+
+int fl_eval_points(fl_handle* h, int32_t k_eval, double* x, double* w) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return sfail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    if (k_eval < 1 || k_eval > 8) return sfail(h, FL_EINVAL, "k_eval must lie in 1..8");
+    if (!x || !w) return sfail(h, FL_EINVAL, "null output");
+    HIPCHK(hipSetDevice(h->device));
+    std::vector<double> X, W;
+    eval_points_host(h, k_eval, X, W);
+    HIPCHK(hipMemcpyAsync(x, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(w, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FL_OK;
+}
+
+int fl_strong_form(fl_handle* h, double s, const double* u, int32_t k_eval, int32_t q_far, int32_t q_near,
+                   double* Lu) {
+    if (!h) return FL_EINVAL;
+    if (!h->planned) return sfail(h, FL_ESTATE, "no DOF map: call fl_assemble first");
+    if (!(s > 0.0 && s < 1.0)) return sfail(h, FL_EINVAL, "s must lie in (0,1)");
+    if (!u || !Lu) return sfail(h, FL_EINVAL, "null vector");
+    int rc = check_rules(h, k_eval, q_far, q_near);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(h->device));
+    if ((rc = sf_plan(h, k_eval, q_far, q_near))) return rc;
+    const bool logk = log_form(h->dim, s);
+    if (!logk && (rc = sf_tables(h, s))) return rc;
+    fl_sf& S = h->sf;
+    SfDev D = S.D;
+    const double d2 = h->dim + 2.0 * s - 2.0;
+    D.pe = -0.5 * d2;
+    D.inv2s = 1.0 / (2.0 * s);
+    D.cg = logk ? 1.0 / (2.0 * s) : 1.0 / (2.0 * s * d2);
+    D.cg_own = logk ? 1.0 : 1.0 / d2;
+    D.C = fl_cdn(h->dim, s);
+    launch_sf_sources(D, u, h->stream);
+    launch_sf_far(D, S.sx, S.sy, S.chunk, S.nch, S.tab, S.part, logk, h->stream);
+    launch_sf_near(D, u, S.part, S.nch, S.tab, Lu, logk, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_indicators(fl_handle* h, double s, const double* Lu, const double* f, int32_t k_eval, double* eta_cell,
+                  double* eta_node) {
+    if (!h) return FL_EINVAL;
+    if (!(s > 0.0 && s < 1.0)) return sfail(h, FL_EINVAL, "s must lie in (0,1)");
+    if (!Lu || !eta_cell) return sfail(h, FL_EINVAL, "null vector");
+    if (!h->sf.ready || h->sf.k != k_eval)
+        return sfail(h, FL_ESTATE, "no strong-form evaluation with this k_eval: call fl_strong_form first");
+    HIPCHK(hipSetDevice(h->device));
+    const fl_sf& S = h->sf;
+    launch_sf_indicators(S.D, Lu, f, S.W, S.h2, s, h->nv, S.vptr, S.vidx, eta_cell, eta_node, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+}  // extern "C"

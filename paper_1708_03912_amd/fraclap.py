@@ -36,7 +36,8 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_matmul", "fl_solve_batch", "fl_autotune", "fl_default_train_opts", "fl_pair_integrals",
            "fl_surrogate_dataset", "fl_surrogate_init", "fl_surrogate_fit_scaling",
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
-           "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg"]
+           "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
+           "fl_eval_points", "fl_strong_form", "fl_indicators"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -107,6 +108,9 @@ def lib():
         L.fl_matvec.argtypes = [vp, vp, vp]
         L.fl_mass_matvec.argtypes = [vp, vp, vp]
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
+        L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
+        L.fl_strong_form.argtypes = [vp, dp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.fl_indicators.argtypes = [vp, dp, vp, vp, C.c_int32, vp, vp]
         L.fl_solve_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_energy_error2.argtypes = [vp, dp, vp, vp, C.POINTER(dp)]
@@ -283,6 +287,19 @@ class Handle:
         rc = self._check(lib().fl_solve_mg(self.h, _ptr(b), _ptr(u), rtol, maxit, C.byref(it), C.byref(rel)),
                          allow=(FL_OK, FL_ENOCONV))
         return it.value, rel.value, rc
+
+    def eval_points(self, k_eval, x, w):
+        """Evaluation points (nc x Q x d) and weights (nc x Q) into device x, w."""
+        self._check(lib().fl_eval_points(self.h, k_eval, _ptr(x), _ptr(w)))
+
+    def strong_form(self, s, u, Lu, k_eval=2, q_far=2, q_near=12):
+        """(-Delta)^s u_h at the evaluation points into device Lu (nc x Q)."""
+        self._check(lib().fl_strong_form(self.h, s, _ptr(u), k_eval, q_far, q_near, _ptr(Lu)))
+
+    def indicators(self, s, Lu, eta_cell, eta_node=None, f=None, k_eval=2):
+        """eta_K^2 into eta_cell (nc), their vertex sums into eta_node (nv)."""
+        self._check(lib().fl_indicators(self.h, s, _ptr(Lu), None if f is None else _ptr(f), k_eval,
+                                        _ptr(eta_cell), None if eta_node is None else _ptr(eta_node)))
 
     def solve(self, b, u, rtol=1e-12, maxit=100000):
         it = C.c_int32()

@@ -1,0 +1,165 @@
+"""Strong form of the fractional Laplacian of a P1 function and the error
+indicators on the GPU (Sec. 4: lemma on the strong form, eq. 8 / eq. 9;
+the indicators eta-hat_i) against the oracle, element by element."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from oracle import strong_form as SF  # noqa: E402
+from paper_1708_03912_amd import fraclap as F, meshgen as M  # noqa: E402
+
+TOL = 1e-10  # FP64, relative to the largest value compared
+
+
+def _u(mesh, dofs, seed):
+    """Seeded P1 input: a smooth profile plus noise on the DOFs."""
+    V = np.asarray(mesh["verts"], dtype=np.float64).reshape(len(mesh["verts"]), -1)
+    r2 = (V[dofs] ** 2).sum(1)
+    rng = np.random.default_rng(seed)
+    return np.clip(1.0 - r2, 0.0, None) ** 0.5 + 0.1 * rng.standard_normal(len(dofs))
+
+
+def _gpu(mesh, s, u, k=2, qf=2, qn=12, f=None, mode="paper"):
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    n = h.assemble(s, F.make_opts(dof_mode=mode))
+    assert n == len(u)
+    Q = k ** (np.asarray(mesh["cells"]).shape[1] - 1)
+    T = len(mesh["cells"])
+    ud = torch.tensor(u, dtype=torch.float64, device="cuda")
+    Lu = torch.empty(T * Q, dtype=torch.float64, device="cuda")
+    h.strong_form(s, ud, Lu, k_eval=k, q_far=qf, q_near=qn)
+    ec = torch.empty(T, dtype=torch.float64, device="cuda")
+    en = torch.empty(len(mesh["verts"]), dtype=torch.float64, device="cuda")
+    fd = None if f is None else torch.tensor(f.reshape(-1), dtype=torch.float64, device="cuda")
+    h.indicators(s, Lu, ec, en, f=fd, k_eval=k)
+    torch.cuda.synchronize()
+    out = Lu.cpu().numpy().reshape(T, Q), ec.cpu().numpy(), en.cpu().numpy()
+    h.close()
+    return out
+
+
+def _close(a, b, tol=TOL):
+    scale = np.abs(b).max()
+    err = np.abs(a - b).max()
+    assert err <= tol * scale, (err, scale, err / scale)
+
+
+@pytest.mark.parametrize("s", [0.3, 0.75])
+def test_strong_form_parity_2d(s):
+    mesh = M.disk_for_cells(300, seed=7)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = _u(mesh, dofs, 1)
+    Lu, ec, en = _gpu(mesh, s, u)
+    ref = SF.strong_form(mesh, dofs, u, s)
+    _close(Lu, ref)
+    eo, no = SF.indicators(mesh, dofs, u, s, ref)
+    _close(ec, eo)
+    _close(en, no)
+
+
+def test_strong_form_rules_and_rhs_2d():
+    """Other rules (k_eval 3, q_far 3, q_near 7) and a seeded right-hand side
+    at the points, on the L-shape (graded mesh)."""
+    s = 0.5
+    mesh = M.lshape(h_max=0.3, ratio=8.0)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = _u(mesh, dofs, 2)
+    T = len(mesh["cells"])
+    f = np.random.default_rng(3).uniform(0.5, 1.5, (T, 9))
+    Lu, ec, en = _gpu(mesh, s, u, k=3, qf=3, qn=7, f=f)
+    ref = SF.strong_form(mesh, dofs, u, s, k_eval=3, q_far=3, q_near=7)
+    _close(Lu, ref)
+    eo, no = SF.indicators(mesh, dofs, u, s, ref, k_eval=3, f=f)
+    _close(ec, eo)
+    _close(en, no)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_strong_form_parity_1d(s):
+    """d = 1 with s = 1/2 in the logarithmic form (eq. 9)."""
+    mesh = M.interval_graded(96, 1.8)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = _u(mesh, dofs, 4)
+    Lu, ec, en = _gpu(mesh, s, u, k=3)
+    ref = SF.strong_form(mesh, dofs, u, s, k_eval=3)
+    _close(Lu, ref)
+    eo, no = SF.indicators(mesh, dofs, u, s, ref, k_eval=3)
+    _close(ec, eo)
+    _close(en, no)
+
+
+def test_eval_points_match():
+    for mesh, k in ((M.disk_for_cells(120, seed=1), 3), (M.interval(10), 4)):
+        X, _, W = SF.eval_points(mesh, k)
+        h = F.Handle(0)
+        h.set_mesh(mesh)
+        x = torch.empty(X.size, dtype=torch.float64, device="cuda")
+        w = torch.empty(W.size, dtype=torch.float64, device="cuda")
+        h.eval_points(k, x, w)
+        _close(x.cpu().numpy(), X.reshape(-1), 1e-15)
+        _close(w.cpu().numpy(), W.reshape(-1), 1e-15)
+        h.close()
+
+
+def test_degenerate_meshes():
+    """One triangle (all three vertices carry DOFs at s < 1/2), two cells
+    in d = 1, the interior-DOF rule with no boundary values."""
+    tri = M.tiny("one")
+    for mesh, s, mode in ((tri, 0.3, "paper"), (M.interval(2), 0.3, "paper"),
+                          (M.disk_for_cells(60, seed=3), 0.3, "interior")):
+        dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s, mode)
+        u = _u(mesh, dofs, 5)
+        Lu, ec, en = _gpu(mesh, s, u, mode=mode)
+        ref = SF.strong_form(mesh, dofs, u, s)
+        _close(Lu, ref)
+
+
+def test_constant_function_1d_large():
+    """Property at any size (d = 1, all nodes, u = 1): the strong form is
+    C(1,s)/(2s) ((1+x)^{-2s} + (1-x)^{-2s}) at every point; 20000 cells."""
+    s = 0.3
+    mesh = M.interval_graded(20000, 2.0)
+    nv = len(mesh["verts"])
+    Lu, _, _ = _gpu(mesh, s, np.ones(nv), k=2)
+    x = SF.eval_points(mesh, 2)[0][..., 0]
+    ref = O.cdn(1, s) / (2 * s) * ((1 + x) ** (-2 * s) + (1 - x) ** (-2 * s))
+    assert np.abs(Lu - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_strong_form_full_size_sampled(s):
+    """The disk of ~8k triangles (the assembly benchmark's mesh), launch
+    configuration of the benchmark: 48 sampled cells against the oracle."""
+    mesh = M.disk_for_cells(8000, seed=2)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = _u(mesh, dofs, 6)
+    Lu, _, _ = _gpu(mesh, s, u)
+    cells = np.random.default_rng(7).choice(len(mesh["cells"]), 48, replace=False)
+    ref = SF.strong_form(mesh, dofs, u, s, cells=cells)
+    _close(Lu[cells], ref)
+
+
+def test_errors():
+    mesh = M.disk_for_cells(60, seed=3)
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    u = torch.zeros(len(mesh["verts"]), dtype=torch.float64, device="cuda")
+    Lu = torch.empty(4 * len(mesh["cells"]), dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FraclapError) as e:
+        h.strong_form(0.3, u, Lu)
+    assert e.value.code == F.FL_ESTATE
+    h.assemble(0.3, F.default_opts())
+    for kw in ({"k_eval": 0}, {"k_eval": 9}, {"q_far": 0}, {"q_near": 17}):
+        with pytest.raises(F.FraclapError) as e:
+            h.strong_form(0.3, u, Lu, **kw)
+        assert e.value.code == F.FL_EINVAL
+    ec = torch.empty(len(mesh["cells"]), dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FraclapError) as e:
+        h.indicators(0.3, Lu, ec, k_eval=3)
+    assert e.value.code == F.FL_ESTATE
+    h.close()
