@@ -203,12 +203,14 @@ def square3(N: int, a: float = -1.0, b: float = 1.0):
 
 # ----------------------------------------------------------- L-shape NVB --
 
-def _nvb_refine(verts, tris, marked_fn, max_pass=200):
+def _nvb_refine(verts, tris, marked_fn, max_pass=200, marked_ids=None):
     """Conforming newest-vertex bisection.  Each triangle (a,b,c) has its
     refinement edge (b,c) opposite the newest vertex a.  A triangle is
     bisected only together with the neighbour that shares its refinement
     edge as that neighbour's refinement edge (recursively refining the
-    neighbour first), so no hanging nodes arise."""
+    neighbour first), so no hanging nodes arise.  Passes refine the
+    triangles that marked_fn selects until none is; with marked_ids, one
+    pass bisects those triangles (indices into tris) once each."""
     verts = [tuple(v) for v in verts]
     tris = {i: tuple(t) for i, t in enumerate(tris)}
     nxt = len(tris)
@@ -267,6 +269,10 @@ def _nvb_refine(verts, tris, marked_fn, max_pass=200):
         else:
             bisect(tid)
 
+    if marked_ids is not None:
+        for t in marked_ids:
+            refine(int(t))
+        return np.array(verts), np.array(list(tris.values()))
     for _ in range(max_pass):
         marked = [t for t, abc in tris.items() if marked_fn([verts[v] for v in abc])]
         if not marked:
@@ -274,6 +280,64 @@ def _nvb_refine(verts, tris, marked_fn, max_pass=200):
         for t in marked:
             refine(t)
     return np.array(verts), np.array(list(tris.values()))
+
+
+def nvb_label(mesh):
+    """Newest-vertex labels for a triangle mesh that has none: every cell is
+    rotated (orientation kept) so that its longest edge joins columns 1 and
+    2, the refinement edge of refine_marked."""
+    V = np.asarray(mesh["verts"], dtype=np.float64)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    L = np.stack([((V[C[:, (i + 1) % 3]] - V[C[:, (i + 2) % 3]]) ** 2).sum(1) for i in range(3)], 1)
+    r = np.argmax(L, axis=1)  # vertex opposite the longest edge
+    idx = (r[:, None] + np.arange(3)[None, :]) % 3
+    out = dict(mesh)
+    out["cells"] = np.ascontiguousarray(np.take_along_axis(C, idx, 1), dtype=np.int32)
+    return out
+
+
+def project_disk(xy):
+    """Radial projection onto the unit circle (new boundary vertices of a
+    disk mesh)."""
+    xy = np.asarray(xy, dtype=np.float64)
+    return xy / np.linalg.norm(xy, axis=-1, keepdims=True)
+
+
+def refine_marked(mesh, marked, project=None):
+    """Refine the marked cells (indices) of a mesh.  d = 1: each marked
+    cell is halved.  d = 2: newest-vertex bisection with column 0 the newest
+    vertex (see nvb_label), each marked cell bisected once, neighbours
+    bisected as far as conformity requires; the children keep the labels.
+    project (d = 2): maps the new boundary vertices (edge midpoints) onto
+    the curved boundary, e.g. project_disk.  Returns the new (sorted)
+    mesh."""
+    dim = mesh["dim"]
+    V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1, dim)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    marked = np.unique(np.asarray(marked, dtype=np.int64))
+    if dim == 1:
+        keep = np.ones(len(C), dtype=bool)
+        keep[marked] = False
+        mid = len(V) + np.arange(len(marked))
+        verts = np.concatenate([V[:, 0], 0.5 * (V[C[marked, 0], 0] + V[C[marked, 1], 0])])
+        cells = np.concatenate([C[keep], np.stack([C[marked, 0], mid], 1), np.stack([mid, C[marked, 1]], 1)])
+        order = np.argsort(verts, kind="stable")
+        inv = np.empty_like(order)
+        inv[order] = np.arange(len(order))
+        cells = inv[cells]
+        cells = cells[np.argsort(verts[order][cells].mean(1), kind="stable")]
+        B = inv[np.asarray(mesh["bfacets"], dtype=np.int64)]
+        return _finish(1, verts[order][:, None], cells, B, sort=False)
+    verts, tris = _nvb_refine([tuple(v) for v in V], [tuple(t) for t in C.tolist()], None,
+                              marked_ids=marked.tolist())
+    bf = _boundary_edges(tris)
+    if project is not None:
+        nb = np.unique(np.asarray(bf, dtype=np.int64))
+        nb = nb[nb >= len(V)]
+        if len(nb):
+            verts = np.array(verts, dtype=np.float64)
+            verts[nb] = project(verts[nb])
+    return _finish(2, verts, tris, bf)
 
 
 def lshape(h_max: float = 0.1, gamma: float = 1.0, ratio: float = 64.0, R: float = 1.0):
