@@ -60,6 +60,10 @@ def parse():
     ap.add_argument("--no-mg", action="store_true",
                     help="skip the multigrid leg (nested disk meshes up to ~32k triangles)")
     ap.add_argument("--only-mg", action="store_true", help="run only the multigrid leg and print its object")
+    ap.add_argument("--no-indicators", action="store_true",
+                    help="skip the a posteriori leg (strong form + indicators on the disk, adaptive loops)")
+    ap.add_argument("--only-indicators", action="store_true",
+                    help="run only the a posteriori leg and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -117,6 +121,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
+        return
+    if args.only_indicators:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"indicators": indicators_leg(args)}), flush=True)
         return
     if args.only_mg:
         import torch
@@ -257,6 +266,8 @@ def main():
         out["surrogate"] = surrogate_leg(args)
     if not args.no_mg:
         out["multigrid"] = mg_leg(args)
+    if not args.no_indicators:
+        out["indicators"] = indicators_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -714,6 +725,89 @@ def mg_leg(args):
                                            "speedup": round(tj / tm, 3) if tm > 0 else None,
                                            "relres": [relj, relm], "gap_rel": gap / unorm if unorm > 0 else None}
             h.close()
+    return out
+
+
+def indicators_leg(args):
+    """A posteriori path (Sec. 4): the strong form of the discrete solution
+    at the 4 collapsed Gauss points of every cell (edge rules 2 / 12
+    points) and the BR indicators, on the disk mesh of the headline
+    (~8k triangles), s in {0.25, 0.75}, timed against the assembly of the
+    same matrix; then the adaptive loops of Sec. 7 (d = 1: 32 steps from
+    8 cells; d = 2: 8 steps from a 200-triangle disk) with the time of each
+    phase and the fitted energy-error rate."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import adaptive as AD, fraclap as F, meshgen as M
+    from math import gamma, pi
+    mesh = M.disk_for_cells(args.cells, seed=2)
+    T = len(mesh["cells"])
+    out = {"workload": f"unit disk, {T} triangles, f=1, u_h = the FP64 solution; strong form at 4 points "
+                       f"per cell (edge rules 2 far / 12 touching) + indicators"}
+    for s in (0.25, 0.75):
+        h = F.Handle(0)
+        h.set_mesh(mesh)
+        n = h.assemble(s)                  # first call: buffers and plan
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = h.assemble(s)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.load_vector_one(b)
+        u = torch.zeros_like(b)
+        h.solve(b, u, rtol=1e-10)
+        Lu = torch.empty(T * 4, dtype=torch.float64, device="cuda")
+        ec = torch.empty(T, dtype=torch.float64, device="cuda")
+        en = torch.empty(len(mesh["verts"]), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.strong_form(s, u, Lu)            # first call: geometry plan
+        torch.cuda.synchronize()
+        t_first = (time.perf_counter() - t0) * 1e3
+        reps = max(3, args.steps)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            h.strong_form(s, u, Lu)
+            h.indicators(s, Lu, ec, en)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        nt = T * 4
+        edges = (3 * T + len(mesh["bfacets"])) // 2
+        inter = nt * edges * 2
+        out[f"s{s}"] = {"n": n, "targets": nt, "edge_sources": edges * 2, "ms": round(ms, 4),
+                        "first_call_ms": round(t_first, 3), "assembly_ms": round(t_asm, 3),
+                        "far_interactions_per_s": inter / (ms * 1e-3),
+                        "estimator": float(ec.sum().item())}
+        h.close()
+    # adaptive loops (Sec. 7, f = 1 on the unit ball)
+    def ball_fu(d, s):
+        c = 2.0 ** (-2 * s) * gamma(d / 2) / (gamma(d / 2 + s) * gamma(1 + s))
+        if d == 1:
+            return c * gamma(0.5) * gamma(s + 1) / gamma(s + 1.5)
+        return c * pi / (s + 1.0)
+    o = F.make_opts(k_touch=8, k_touch_bnd=8, k_far=[6, 5, 4, 3], k_far_bnd=[6, 5, 4, 3])
+    loops = {}
+    for name, m0, s, nst, proj in (("1d_s0.25", M.interval(8), 0.25, 32, None),
+                                   ("1d_s0.75", M.interval(8), 0.75, 32, None),
+                                   ("2d_s0.75", M.disk_for_cells(200, seed=2), 0.75, 8, M.project_disk)):
+        t0 = time.perf_counter()
+        steps, _ = AD.adaptive_loop(m0, s, nst, opts=o if m0["dim"] == 1 else None, fu=ball_fu(m0["dim"], s),
+                                    rtol=1e-12, project=proj)
+        wall = time.perf_counter() - t0
+        nn = np.array([st.n for st in steps], dtype=float)
+        ee = np.sqrt(np.maximum([st.e2 for st in steps], 1e-300))
+        k = min(8, len(steps))
+        loops[name] = {"steps": len(steps), "n_first": int(nn[0]), "n_last": int(nn[-1]),
+                       "energy_err_last": float(ee[-1]),
+                       "rate_last8": float(np.polyfit(np.log(nn[-k:]), np.log(ee[-k:]), 1)[0]),
+                       "t_assemble_s": round(sum(st.t_assemble for st in steps), 4),
+                       "t_solve_s": round(sum(st.t_solve for st in steps), 4),
+                       "t_indicators_s": round(sum(st.t_indicators for st in steps), 4),
+                       "wall_s": round(wall, 3)}
+    out["adaptive"] = loops
     return out
 
 

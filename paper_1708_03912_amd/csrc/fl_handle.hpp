@@ -87,17 +87,19 @@ struct fl_mg {
 // k_eval, edge rules) combination, rebuilt when any of them changes.
 struct fl_sf {
     bool ready = false;
-    int k = 0, qf = 0, qn = 0, nch = 0;
+    int k = 0, qf = 0, qn = 0, nch = 0, nchb = 0;   // far chunks: facet sources, boundary sources
     int64_t n = -1;                 // DOF count the plan was built for
     fl::SfDev D{};
     long long chunk = 0;
     double* sx = nullptr;           // source coordinates
     double* sy = nullptr;
+    double* bsx = nullptr;          // boundary-source coordinates
+    double* bsy = nullptr;
     double* W = nullptr;            // evaluation weights times |K|
     double* h2 = nullptr;           // squared cell diameters
     int* vptr = nullptr;            // vertex -> cells (CSR) for the nodal indicators
     int* vidx = nullptr;
-    double* part = nullptr;         // far-field partial sums, nch x nt
+    double* part = nullptr;         // far-field partial sums, (nch + nchb) x nt
     double* tab = nullptr;          // kernel-power tables of tab_s
     double tab_s = -1.0;
     std::vector<void*> bufs;        // every allocation above

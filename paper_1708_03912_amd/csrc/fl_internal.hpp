@@ -218,14 +218,17 @@ struct SfDev {
     const int* nidx;
     long long nbf;          // boundary facets: owner cell, local facet index
     const int2* bf;
-    int bnd_u;              // boundary vertices carry DOFs (u-terms of boundary facets)
+    int bnd_u;              // boundary vertices carry DOFs (value terms of boundary facets)
+    long long nbs;          // boundary sources: boundary facets x qf (d = 2), boundary facets (d = 1)
+    double* bc;             // their value-term coefficients, 2 per source (per call)
     double pe;              // exponent of r^2 in |x-y|^{-(d+2s-2)}: -(d + 2s - 2)/2
     double cg, cg_own;      // 1/(2s(d+2s-2)) and 1/(d+2s-2); 1/(2s) and 1 in the log form
     double inv2s, C;        // 1/(2s), C(d,s)
 };
 void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st);
-void launch_sf_far(const SfDev& D, const double* sx, const double* sy, long long chunk, int nch,
-                   const double* tab, double* part, bool logk, hipStream_t st);
+void launch_sf_far(const SfDev& D, const double* sx, const double* sy, const double* bsx, const double* bsy,
+                   long long chunk, int nch, int nchb, const double* tab, double* part, bool logk,
+                   hipStream_t st);
 void launch_sf_near(const SfDev& D, const double* u, const double* part, int nch, const double* tab,
                     double* Lu, bool logk, hipStream_t st);
 void launch_sf_indicators(const SfDev& D, const double* Lu, const double* f, const double* W,

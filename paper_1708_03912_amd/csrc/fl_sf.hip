@@ -16,7 +16,8 @@
 //     separated-cell terms are replaced by the touching-cell rule (with
 //     K0's own coefficients on K0); the value terms of boundary facets
 //     (present only when boundary vertices carry DOFs, s < 1/2); the
-//     far-field partial sums are reduced in a fixed order.
+//     far-field partial sums are reduced in a fixed order.  16 lanes per
+//     evaluation point share its touching cells and boundary facets.
 // Both kernels are FP64.  In d = 1 a facet is a vertex and its integral a
 // point value; only K0 itself needs a correction.
 #include <hip/hip_runtime.h>
@@ -168,14 +169,20 @@ __global__ __launch_bounds__(256) void sf_sources_kernel(SfDev D, const double* 
 }
 
 // Targets x SF_TPT per thread, a chunk of sources per workgroup row:
-//   part[chunk][t] = sum_j c_j g(|x_t - y_j|^2).
-// Sources pass through LDS (broadcast reads), the kernel power through the
-// LDS tables; no branch in the inner loop.
+//   part[chunk][t] = sum_j c_j g(|x_t - y_j|^2)
+// for the rows below nch (jumps of the normal derivative), and for the
+// rows from nch on the value terms of the boundary facets,
+//   part[nch + chunk][t] = sum_j g(r2) / r2 (b_j . (x_t - y_j)),
+// b_j = -w_j u(y_j) N / (2s).  Sources pass through LDS (broadcast reads),
+// the kernel power through the LDS tables; no branch in the inner loops.
 template <bool LOGK>
 __global__ __launch_bounds__(256) void sf_far_kernel(long long nt, const double* __restrict__ tx,
                                                      const double* __restrict__ ty, long long ns,
                                                      const double* __restrict__ sx, const double* __restrict__ sy,
-                                                     const double* __restrict__ sc, long long chunk,
+                                                     const double* __restrict__ sc, long long chunk, int nch,
+                                                     long long nbs, const double* __restrict__ bsx,
+                                                     const double* __restrict__ bsy,
+                                                     const double* __restrict__ bc,
                                                      const double* __restrict__ tab, double* __restrict__ part) {
     __shared__ double pw[768];
     __shared__ double4 src[SF_TILE];
@@ -191,22 +198,41 @@ __global__ __launch_bounds__(256) void sf_far_kernel(long long nt, const double*
         y[i] = ty[t];
         acc[i] = 0.0;
     }
-    const long long j0 = (long long)blockIdx.y * chunk;
-    const long long j1 = j0 + chunk < ns ? j0 + chunk : ns;
+    const bool bnd = (int)blockIdx.y >= nch;
+    const long long n_src = bnd ? nbs : ns;
+    const long long j0 = (long long)(bnd ? blockIdx.y - nch : blockIdx.y) * chunk;
+    const long long j1 = j0 + chunk < n_src ? j0 + chunk : n_src;
     for (long long jt = j0; jt < j1; jt += SF_TILE) {
         const int m = (int)(j1 - jt < SF_TILE ? j1 - jt : SF_TILE);
         __syncthreads();
-        if (tid < m) src[tid] = make_double4(sx[jt + tid], sy[jt + tid], sc[jt + tid], 0.0);
+        if (tid < m) {
+            const long long j = jt + tid;
+            src[tid] = bnd ? make_double4(bsx[j], bsy[j], bc[2 * j], bc[2 * j + 1])
+                           : make_double4(sx[j], sy[j], sc[j], 0.0);
+        }
         __syncthreads();
+        if (!bnd) {
 #pragma unroll 2
-        for (int j = 0; j < m; ++j) {
-            const double4 S = src[j];
+            for (int j = 0; j < m; ++j) {
+                const double4 S = src[j];
 #pragma unroll
-            for (int i = 0; i < SF_TPT; ++i) {
-                const double dx = x[i] - S.x, dy = y[i] - S.y;
-                const double r2 = fma(dx, dx, dy * dy);
-                const double g = LOGK ? -0.5 * log(r2) : P(r2);
-                acc[i] = fma(S.z, g, acc[i]);
+                for (int i = 0; i < SF_TPT; ++i) {
+                    const double dx = x[i] - S.x, dy = y[i] - S.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const double g = LOGK ? -0.5 * log(r2) : P(r2);
+                    acc[i] = fma(S.z, g, acc[i]);
+                }
+            }
+        } else {
+            for (int j = 0; j < m; ++j) {
+                const double4 S = src[j];
+#pragma unroll
+                for (int i = 0; i < SF_TPT; ++i) {
+                    const double dx = x[i] - S.x, dy = y[i] - S.y;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const double kern = LOGK ? 1.0 / r2 : P(r2) / r2;
+                    acc[i] = fma(kern, fma(S.z, dx, S.w * dy), acc[i]);
+                }
             }
         }
     }
@@ -217,8 +243,32 @@ __global__ __launch_bounds__(256) void sf_far_kernel(long long nt, const double*
     }
 }
 
-// One thread per target (cell K0, point q): the far partial sums, the
-// touching cells with their own rule, the boundary value terms; times C.
+// One thread per boundary facet (only when boundary vertices carry DOFs):
+// the value-term coefficients b_j = -w_j u(y_j) N / (2s) of its q_far points.
+template <int DIM>
+__global__ __launch_bounds__(256) void sf_bsources_kernel(SfDev D, const double* __restrict__ u) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= D.nbf) return;
+    const int2 kb = D.bf[b];
+    SfCell<DIM> c;
+    load_cell<DIM>(D, u, kb.x, c);
+    const SfFacet<DIM> f = facet_of<DIM>(c, kb.y);
+    const int nq = DIM == 1 ? 1 : D.qf;
+    const int off = gl_off(nq);
+    for (int j = 0; j < nq; ++j) {
+        const double t = DIM == 1 ? 0.0 : D.gx[off + j];
+        const double w = DIM == 1 ? 1.0 : D.gw[off + j];
+        const double c0 = -D.inv2s * w * fma(t, f.ub - f.ua, f.ua);
+        D.bc[2 * (b * nq + j)] = c0 * f.N[0];
+        D.bc[2 * (b * nq + j) + 1] = c0 * f.N[1];
+    }
+}
+
+// SF_G lanes per target (cell K0, point q), 64 / SF_G targets per wave: the
+// lanes of a group split the touching cells, a fixed-order reduction over
+// the group, then the far partial sums (all rows); times C.
+constexpr int SF_G = 16;
+
 template <int DIM, bool LOGK>
 __global__ __launch_bounds__(256) void sf_near_kernel(SfDev D, const double* __restrict__ u,
                                                       const double* __restrict__ part, int nch,
@@ -227,18 +277,18 @@ __global__ __launch_bounds__(256) void sf_near_kernel(SfDev D, const double* __r
     if constexpr (!LOGK) load_tab(pw, tab);
     __syncthreads();
     const KPowTab P = tab_pow(pw, tab);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= D.nt) return;
+    const int g = threadIdx.x & (SF_G - 1);
+    const long long t0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / SF_G;
+    const bool live = t0 < D.nt;
+    const long long t = live ? t0 : D.nt - 1;
     const long long K0 = t / D.Q;
     const int q = (int)(t - K0 * D.Q);
     const double x = D.tx[t], y = D.ty[t];
-    double acc = 0.0;
-    for (int c = 0; c < nch; ++c) acc += part[(long long)c * D.nt + t];
     double ux = 0.0;
     for (int a = 0; a <= DIM; ++a) ux = fma(D.lam[q * (DIM + 1) + a], uval(D, u, K0, a), ux);
     SfCell<DIM> c;
     double corr = 0.0;
-    for (int e = D.nptr[K0]; e < D.nptr[K0 + 1]; ++e) {
+    for (int e = D.nptr[K0] + g; e < D.nptr[K0 + 1]; e += SF_G) {
         const int K = D.nidx[e];
         load_cell<DIM>(D, u, K, c);
         const bool own = K == K0;
@@ -253,18 +303,14 @@ __global__ __launch_bounds__(256) void sf_near_kernel(SfDev D, const double* __r
             corr += nearv - farv;
         }
     }
-    if (D.bnd_u) {
-        for (long long b = 0; b < D.nbf; ++b) {
-            const int2 kb = D.bf[b];
-            load_cell<DIM>(D, u, kb.x, c);
-            const SfFacet<DIM> f = facet_of<DIM>(c, kb.y);
-            if (f.ua == 0.0 && f.ub == 0.0) continue;
-            double Ig, Iu, Io;
-            facet_sums<DIM, LOGK>(f, x, y, D.qf, D.gx, D.gw, P, Ig, Iu, Io);
-            corr -= D.inv2s * Iu;
-        }
+    // lanes g, g^8, g^4 ... of the group: a fixed butterfly order
+#pragma unroll
+    for (int m = SF_G / 2; m >= 1; m >>= 1) corr += __shfl_xor(corr, m, 64);
+    if (g == 0 && live) {
+        double acc = 0.0;
+        for (int ch = 0; ch < nch; ++ch) acc += part[(long long)ch * D.nt + t];
+        Lu[t] = D.C * (acc + corr);
     }
-    Lu[t] = D.C * (acc + corr);
 }
 
 // eta_K^2 = h_K^{2s} sum_q W_q (f_q - Lu_q)^2 (f = 1 if null)
@@ -301,29 +347,38 @@ inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st) {
-    if (D.nf == 0) return;
-    if (D.dim == 1)
-        hipLaunchKernelGGL(sf_sources_kernel<1>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
-    else
-        hipLaunchKernelGGL(sf_sources_kernel<2>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
+    if (D.nf > 0) {
+        if (D.dim == 1)
+            hipLaunchKernelGGL(sf_sources_kernel<1>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
+        else
+            hipLaunchKernelGGL(sf_sources_kernel<2>, dim3(nblk(D.nf)), dim3(256), 0, st, D, u);
+    }
+    if (D.bnd_u && D.nbf > 0) {
+        if (D.dim == 1)
+            hipLaunchKernelGGL(sf_bsources_kernel<1>, dim3(nblk(D.nbf)), dim3(256), 0, st, D, u);
+        else
+            hipLaunchKernelGGL(sf_bsources_kernel<2>, dim3(nblk(D.nbf)), dim3(256), 0, st, D, u);
+    }
 }
 
-void launch_sf_far(const SfDev& D, const double* sx, const double* sy, long long chunk, int nch,
-                   const double* tab, double* part, bool logk, hipStream_t st) {
-    if (D.nt == 0 || nch == 0) return;
-    const dim3 grid((unsigned)((D.nt + 256 * SF_TPT - 1) / (256 * SF_TPT)), (unsigned)nch);
+void launch_sf_far(const SfDev& D, const double* sx, const double* sy, const double* bsx, const double* bsy,
+                   long long chunk, int nch, int nchb, const double* tab, double* part, bool logk,
+                   hipStream_t st) {
+    if (D.nt == 0 || nch + nchb == 0) return;
+    const dim3 grid((unsigned)((D.nt + 256 * SF_TPT - 1) / (256 * SF_TPT)), (unsigned)(nch + nchb));
+    const long long nbs = nchb > 0 ? D.nbs : 0;
     if (logk)
         hipLaunchKernelGGL(sf_far_kernel<true>, grid, dim3(256), 0, st, D.nt, D.tx, D.ty, D.ns, sx, sy, D.sc,
-                           chunk, tab, part);
+                           chunk, nch, nbs, bsx, bsy, D.bc, tab, part);
     else
         hipLaunchKernelGGL(sf_far_kernel<false>, grid, dim3(256), 0, st, D.nt, D.tx, D.ty, D.ns, sx, sy, D.sc,
-                           chunk, tab, part);
+                           chunk, nch, nbs, bsx, bsy, D.bc, tab, part);
 }
 
 void launch_sf_near(const SfDev& D, const double* u, const double* part, int nch, const double* tab,
                     double* Lu, bool logk, hipStream_t st) {
     if (D.nt == 0) return;
-    const dim3 grid(nblk(D.nt));
+    const dim3 grid(nblk(D.nt * SF_G));
     if (D.dim == 1) {
         if (logk)
             hipLaunchKernelGGL((sf_near_kernel<1, true>), grid, dim3(256), 0, st, D, u, part, nch, tab, Lu);

@@ -245,6 +245,29 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
         }
         if (fK[2 * f + 1] < 0) bf.push_back(make_int2(K1, e));
     }
+    // boundary sources (value terms, only if boundary vertices carry DOFs):
+    // the q_far points of each boundary facet in its cell's orientation
+    int bnd_u = 0;
+    for (int64_t v = 0; v < nv; ++v)
+        if (h->on_boundary[v] && h->node2dof[v] >= 0) bnd_u = 1;
+    std::vector<double> bsx, bsy;
+    if (bnd_u)
+        for (const int2& kb : bf) {
+            const int32_t* c = &h->cells[nper * kb.x];
+            if (dim == 1) {
+                bsx.push_back(h->verts[c[kb.y]]);
+                bsy.push_back(0.0);
+            } else {
+                const double* A = &h->verts[2 * c[kb.y]];
+                const double* B = &h->verts[2 * c[(kb.y + 1) % 3]];
+                for (int j = 0; j < qf; ++j) {
+                    const double t = R.gl_x[gl_off(qf) + j];
+                    bsx.push_back(std::fma(t, B[0] - A[0], A[0]));
+                    bsy.push_back(std::fma(t, B[1] - A[1], A[1]));
+                }
+            }
+        }
+    const long long nbs = (long long)bsx.size();
     // touching cells: sharing a vertex (d = 2), the cell itself (d = 1)
     std::vector<int> nptr(T + 1, 0), nidx;
     {
@@ -271,6 +294,7 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
     long long chunk = (ns + nch - 1) / nch;
     chunk = std::max<long long>(256, (chunk + 255) / 256 * 256);
     nch = (int)std::max<long long>(1, (ns + chunk - 1) / chunk);
+    const int nchb = (int)((nbs + chunk - 1) / chunk);
 
     std::vector<double> gx(R.gl_x, R.gl_x + GL_TAB), gw(R.gl_w, R.gl_w + GL_TAB);
     SfDev D{};
@@ -283,11 +307,10 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
     D.qn = dim == 1 ? 1 : qn;
     D.ns = ns;
     D.nbf = (long long)bf.size();
-    D.bnd_u = 0;
-    for (int64_t v = 0; v < nv; ++v)
-        if (h->on_boundary[v] && h->node2dof[v] >= 0) D.bnd_u = 1;
+    D.bnd_u = bnd_u;
+    D.nbs = nbs;
     int rc;
-    double *p_cx, *p_lam, *p_tx, *p_ty, *p_fN, *p_gx, *p_gw, *p_sc;
+    double *p_cx, *p_lam, *p_tx, *p_ty, *p_fN, *p_gx, *p_gw, *p_sc, *p_bc;
     int *p_cdof, *p_fK, *p_nptr, *p_nidx;
     int2* p_bf;
     if ((rc = sf_upload(h, &p_cx, cx)) || (rc = sf_upload(h, &p_cdof, cdof)) || (rc = sf_upload(h, &p_lam, lam)) ||
@@ -296,7 +319,9 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
         (rc = sf_upload(h, &p_nptr, nptr)) || (rc = sf_upload(h, &p_nidx, nidx)) || (rc = sf_upload(h, &p_bf, bf)) ||
         (rc = sf_upload(h, &S.sx, sx)) || (rc = sf_upload(h, &S.sy, sy)) || (rc = sf_upload(h, &S.W, W)) ||
         (rc = sf_upload(h, &S.h2, h2)) || (rc = sf_upload(h, &S.vptr, vptr)) || (rc = sf_upload(h, &S.vidx, vidx)) ||
-        (rc = sf_alloc(h, &p_sc, (size_t)ns)) || (rc = sf_alloc(h, &S.part, (size_t)nch * nt)) ||
+        (rc = sf_upload(h, &S.bsx, bsx)) || (rc = sf_upload(h, &S.bsy, bsy)) ||
+        (rc = sf_alloc(h, &p_bc, (size_t)2 * nbs)) ||
+        (rc = sf_alloc(h, &p_sc, (size_t)ns)) || (rc = sf_alloc(h, &S.part, (size_t)(nch + nchb) * nt)) ||
         (rc = sf_alloc(h, &S.tab, 776))) {
         sf_release(h);
         return rc;
@@ -311,6 +336,7 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
     D.gx = p_gx;
     D.gw = p_gw;
     D.sc = p_sc;
+    D.bc = p_bc;
     D.nptr = p_nptr;
     D.nidx = p_nidx;
     D.bf = p_bf;
@@ -320,6 +346,7 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
     S.qn = qn;
     S.n = h->n;
     S.nch = nch;
+    S.nchb = nchb;
     S.chunk = chunk;
     S.tab_s = -1.0;
     S.ready = true;
@@ -389,8 +416,8 @@ int fl_strong_form(fl_handle* h, double s, const double* u, int32_t k_eval, int3
     D.cg_own = logk ? 1.0 : 1.0 / d2;
     D.C = fl_cdn(h->dim, s);
     launch_sf_sources(D, u, h->stream);
-    launch_sf_far(D, S.sx, S.sy, S.chunk, S.nch, S.tab, S.part, logk, h->stream);
-    launch_sf_near(D, u, S.part, S.nch, S.tab, Lu, logk, h->stream);
+    launch_sf_far(D, S.sx, S.sy, S.bsx, S.bsy, S.chunk, S.nch, S.nchb, S.tab, S.part, logk, h->stream);
+    launch_sf_near(D, u, S.part, S.nch + S.nchb, S.tab, Lu, logk, h->stream);
     HIPCHK(hipGetLastError());
     return FL_OK;
 }
