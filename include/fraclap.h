@@ -245,6 +245,32 @@ int fl_mg_setup(fl_handle *h, int nlevels, const int64_t *nv, const int32_t *par
 int fl_solve_mg(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
                 double *relres);
 
+/* Cluster (H-matrix) approximation of the assembled matrix (Sec. 6): a
+ * cluster tree over the DOFs (median bisection; leaves of at most `leaf`
+ * DOFs), cluster boxes = cubes containing the supports, admissible pairs
+ * eta dist >= max(diam) approximated by -C V_s K_st V_t^T with the tensor
+ * Chebyshev interpolation of order m (1..15 points per direction) of the
+ * kernel and nested bases (shift coefficients); the other leaf pairs are
+ * copied from the assembled matrix.  Requires fl_assemble; a new
+ * fl_assemble / fl_import_matrix discards it.  Synchronises the stream. */
+int fl_cluster_build(fl_handle *h, int32_t m, double eta, int32_t leaf);
+
+/* y = A_H x with the cluster approximation: upward pass, kernel blocks,
+ * downward pass, near blocks.  x, y: device, length n, not aliased.
+ * FL_ESTATE without fl_cluster_build.  Asynchronous. */
+int fl_cluster_matvec(fl_handle *h, const double *x, double *y);
+
+/* Jacobi-preconditioned CG (Sec. 5) on A_H u = b (the preconditioner is the
+ * diagonal of the assembled matrix).  Arguments and results as fl_solve.
+ * Synchronises the stream. */
+int fl_solve_cluster(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,
+                     int32_t *iters, double *relres);
+
+/* Sizes of the cluster approximation, host out[7]: clusters, leaves,
+ * admissible pairs, near pairs, near entries, device bytes, depth.
+ * FL_ESTATE without one. */
+int fl_cluster_info(const fl_handle *h, int64_t *out);
+
 /* Evaluation points of the a posteriori indicators (Sec. 4: local L2
  * norms by quadrature): k_eval in 1..8 points per direction in every cell
  * (d = 2: the collapsed Gauss rule, Gauss-Jacobi(1,0) in the first

@@ -2,10 +2,11 @@
 
 Translation units: the assembly / single-system solver kernels, the
 batched product / solver kernels, the surrogate network kernels and the
-multigrid kernels and the strong-form kernels (default floating-point
-contraction), the host planner (no contraction, see fl_api.hip), the
-batched host calls, the surrogate host calls, the multigrid host calls and
-the strong-form host calls.
+multigrid kernels, the strong-form kernels and the cluster kernels (default
+floating-point contraction), the host planner (no contraction, see
+fl_api.hip), the batched host calls, the surrogate host calls, the
+multigrid host calls, the strong-form host calls and the cluster host calls
+(no contraction: the cluster boxes decide admissibility).
 Packed FP32 instructions are disabled for all device code.  Units are built
 in parallel.
 """
@@ -21,8 +22,9 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
-         ("fl_sf.hip", []), ("fl_api.hip", ["-ffp-contract=off"]), ("fl_batch_api.hip", []),
-         ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", [])]
+         ("fl_sf.hip", []), ("fl_cluster.hip", []), ("fl_api.hip", ["-ffp-contract=off"]),
+         ("fl_batch_api.hip", []), ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", []),
+         ("fl_cluster_api.hip", ["-ffp-contract=off"])]
 
 
 def build(verbose=False):

@@ -45,6 +45,7 @@ void reset_assembly(fl_handle* h) {
     h->assembled = false;
     h->mg.ready = false;  // the hierarchy belongs to the previous matrix
     h->sf.ready = false;  // so does the strong-form geometry (DOF map)
+    h->hm.ready = false;  // and the cluster approximation
     h->planned = false;
     h->B.ns = 0;
     h->n = h->lda = 0;
@@ -281,6 +282,7 @@ void fl_destroy(fl_handle* h) {
     fl_sur_free(h);
     fl_mg_free(h);
     fl_sf_free(h);
+    fl_hm_free(h);
     delete h;
 }
 
@@ -1039,6 +1041,7 @@ int fl_import_matrix(fl_handle* h, const double* src, int64_t ld, int on_device)
     if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
     HIPCHK(hipSetDevice(h->device));
     h->mg.ready = false;  // the hierarchy's coarse operators came from the old matrix
+    h->hm.ready = false;  // so did the cluster approximation
     HIPCHK(hipMemcpy2DAsync(h->dA, h->lda * sizeof(double), src, ld * sizeof(double), h->n * sizeof(double),
                             h->n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
     if (h->opts.precision == FL_MIXED && h->dA32) launch_to_f32(h->dA, h->lda, h->n, h->dA32, h->stream);

@@ -1,0 +1,258 @@
+// Cluster (H-matrix) approximation of the stiffness matrix (Sec. 6):
+// tensor Chebyshev interpolation of the kernel on admissible pairs of
+// cluster boxes, nested bases through the shift coefficients, the near
+// field as dense leaf blocks.  Set-up kernels (basis coefficients, shift
+// coefficients, kernel blocks, near blocks) and the product (upward pass,
+// far field, downward pass, leaves); the tree and the block lists come from
+// fl_cluster_api.hip.  All FP64, fixed summation orders.
+#include <hip/hip_runtime.h>
+
+#include "fl_internal.hpp"
+#include "fl_math.hpp"
+
+namespace fl {
+
+namespace {
+
+// Lagrange polynomial a of the m reference nodes t at xi (product over b != a
+// in increasing b)
+__device__ __forceinline__ double lag(const double* t, int m, int a, double xi) {
+    double p = 1.0;
+    for (int b = 0; b < m; ++b)
+        if (b != a) p *= (xi - t[b]) / (t[a] - t[b]);
+    return p;
+}
+
+// tensor Lagrange basis function a (first coordinate slowest) of cluster c
+// at the point (x, y)
+__device__ __forceinline__ double lag_box(const HDev& H, int c, int a, double x, double y) {
+    const double* bx = H.box + 3 * c;
+    if (H.dim == 1) return lag(H.tnode, H.m, a, (x - bx[0]) / bx[2]);
+    const int a0 = a / H.m, a1 = a - a0 * H.m;
+    return lag(H.tnode, H.m, a0, (x - bx[0]) / bx[2]) * lag(H.tnode, H.m, a1, (y - bx[1]) / bx[2]);
+}
+
+// Chebyshev point b of cluster c
+__device__ __forceinline__ void cheb_pt(const HDev& H, int c, int b, double& x, double& y) {
+    const double* bx = H.box + 3 * c;
+    if (H.dim == 1) {
+        x = bx[0] + bx[2] * H.tnode[b];
+        y = 0.0;
+        return;
+    }
+    const int b0 = b / H.m, b1 = b - b0 * H.m;
+    x = bx[0] + bx[2] * H.tnode[b0];
+    y = bx[1] + bx[2] * H.tnode[b1];
+}
+
+// V[r][a] = int phi_i L_a^leaf(r) over the cells around DOF i = perm[r], by
+// the (m+1)-point rule of every cell.  One thread per (r, a).
+__global__ __launch_bounds__(256) void h_basis_kernel(HDev H) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= H.n * H.M) return;
+    const long long r = id / H.M;
+    const int a = (int)(id - r * H.M);
+    const int v = H.node[r];
+    const int c = H.rleaf[r];
+    const int nper = H.dim + 1;
+    double acc = 0.0;
+    for (int e = H.vptr[v]; e < H.vptr[v + 1]; ++e) {
+        const int K = H.vidx[e];
+        const int* cv = H.cells + (long long)K * nper;
+        double P[3][2];
+        int loc = 0;
+        for (int b = 0; b < nper; ++b) {
+            P[b][0] = H.verts[(long long)cv[b] * H.dim];
+            P[b][1] = H.dim == 2 ? H.verts[(long long)cv[b] * H.dim + 1] : 0.0;
+            if (cv[b] == v) loc = b;
+        }
+        double meas;
+        if (H.dim == 1) {
+            meas = fabs(P[1][0] - P[0][0]);
+        } else {
+            meas = 0.5 * fabs((P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[2][0] - P[0][0]) * (P[1][1] - P[0][1]));
+        }
+        for (int q = 0; q < H.nq; ++q) {
+            const double* l = H.qlam + q * nper;
+            double x = 0.0, y = 0.0;
+            for (int b = 0; b < nper; ++b) {
+                x += l[b] * P[b][0];
+                y += l[b] * P[b][1];
+            }
+            acc += (meas * H.qw[q] * l[loc]) * lag_box(H, c, a, x, y);
+        }
+    }
+    H.V[id] = acc;
+}
+
+// T_c[b][a] = L_a^parent(xi_b^c), clusters c >= 1.  One thread per entry.
+__global__ __launch_bounds__(256) void h_transfer_kernel(HDev H) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long MM = (long long)H.M * H.M;
+    if (id >= (long long)H.nc * MM) return;
+    const int c = (int)(id / MM);
+    if (c == 0) return;
+    const int rem = (int)(id - (long long)c * MM);
+    const int b = rem / H.M, a = rem - b * H.M;
+    double x, y;
+    cheb_pt(H, c, b, x, y);
+    H.T[id] = lag_box(H, H.cpar[c], a, x, y);
+}
+
+// Kernel blocks of the admissible pairs, stored column by column:
+// Kb[p][b][a] = k(xi_a^sigma, xi_b^tau).  One thread per entry.
+__global__ __launch_bounds__(256) void h_kblock_kernel(HDev H, double pe) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long MM = (long long)H.M * H.M;
+    if (id >= H.nfar * MM) return;
+    const long long p = id / MM;
+    const int rem = (int)(id - p * MM);
+    const int b = rem / H.M, a = rem - b * H.M;
+    double xs, ys, xt, yt;
+    cheb_pt(H, H.fsrc[p], a, xs, ys);
+    cheb_pt(H, H.fdst[p], b, xt, yt);
+    const double dx = xs - xt, dy = ys - yt;
+    H.Kb[id] = kpow(dx * dx + dy * dy, pe);
+}
+
+// Near blocks copied from the dense matrix (row-major per block, tree order).
+__global__ __launch_bounds__(256) void h_near_kernel(HDev H, const double* __restrict__ A, long long lda) {
+    for (long long p = blockIdx.y; p < H.nnear; p += gridDim.y) {
+        const int s = H.nsrc[p], t = H.ndst[p];
+        const int rs = H.clo[s], ns = H.chi[s] - rs, rt = H.clo[t], nt = H.chi[t] - rt;
+        for (int id = threadIdx.x + blockIdx.x * blockDim.x; id < ns * nt; id += blockDim.x * gridDim.x) {
+            const int i = id / nt, j = id - i * nt;
+            H.An[H.noff[p] + id] = A[(long long)H.perm[rs + i] * lda + H.perm[rt + j]];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- product
+
+// xp[r] = x[perm[r]]
+__global__ __launch_bounds__(256) void h_gather_kernel(HDev H, const double* __restrict__ x) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < H.n) H.xp[r] = x[H.perm[r]];
+}
+
+// leaves: xh[c][a] = sum_r V[r][a] xp[r]; one workgroup per leaf
+__global__ __launch_bounds__(64) void h_up_leaf_kernel(HDev H) {
+    const int c = H.leaf[blockIdx.x];
+    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+        double acc = 0.0;
+        for (int r = H.clo[c]; r < H.chi[c]; ++r) acc = fma(H.V[(long long)r * H.M + a], H.xp[r], acc);
+        H.xh[(long long)c * H.M + a] = acc;
+    }
+}
+
+// internal clusters of one level: xh[c][a] = sum_sons sum_b T_son[b][a] xh[son][b]
+__global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int* __restrict__ list) {
+    const int c = list[blockIdx.x];
+    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+        double acc = 0.0;
+        for (int e = H.sptr[c]; e < H.sptr[c + 1]; ++e) {
+            const int sn = H.sidx[e];
+            const double* Ts = H.T + (long long)sn * H.M * H.M;
+            const double* xs = H.xh + (long long)sn * H.M;
+            for (int b = 0; b < H.M; ++b) acc = fma(Ts[b * H.M + a], xs[b], acc);
+        }
+        H.xh[(long long)c * H.M + a] = acc;
+    }
+}
+
+// far field: yh[s][a] = sum over admissible (s, t) of sum_b K[a][b] xh[t][b];
+// one workgroup per cluster, pairs in list order
+__global__ __launch_bounds__(64) void h_far_kernel(HDev H) {
+    const int c = blockIdx.x;
+    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+        double acc = 0.0;
+        for (long long p = H.fptr[c]; p < H.fptr[c + 1]; ++p) {
+            const double* Kp = H.Kb + p * H.M * H.M;
+            const double* xt = H.xh + (long long)H.fdst[p] * H.M;
+            for (int b = 0; b < H.M; ++b) acc = fma(Kp[b * H.M + a], xt[b], acc);
+        }
+        H.yh[(long long)c * H.M + a] = acc;
+    }
+}
+
+// clusters of one level (>= 1): yh[c][b] += sum_a T_c[b][a] yh[parent][a]
+__global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int* __restrict__ list) {
+    const int c = list[blockIdx.x];
+    const double* Tc = H.T + (long long)c * H.M * H.M;
+    const double* yp = H.yh + (long long)H.cpar[c] * H.M;
+    for (int b = threadIdx.x; b < H.M; b += blockDim.x) {
+        double acc = 0.0;
+        for (int a = 0; a < H.M; ++a) acc = fma(Tc[b * H.M + a], yp[a], acc);
+        H.yh[(long long)c * H.M + b] += acc;
+    }
+}
+
+// leaves: y[perm[r]] = -C sum_a V[r][a] yh[c][a] + sum over near (c, t) of
+// the block row times xp[t]; one workgroup per leaf, one thread per row
+__global__ __launch_bounds__(64) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
+    const int li = blockIdx.x;
+    const int c = H.leaf[li];
+    const int lo = H.clo[c], nr = H.chi[c] - lo;
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        const long long r = lo + i;
+        double f = 0.0;
+        for (int a = 0; a < H.M; ++a) f = fma(H.V[r * H.M + a], H.yh[(long long)c * H.M + a], f);
+        double acc = -C * f;
+        for (int e = H.lnptr[li]; e < H.lnptr[li + 1]; ++e) {
+            const int t = H.ndst[e];
+            const int rt = H.clo[t], nt = H.chi[t] - rt;
+            const double* blk = H.An + H.noff[e] + (long long)i * nt;
+            double s = 0.0;
+            for (int j = 0; j < nt; ++j) s = fma(blk[j], H.xp[rt + j], s);
+            acc += s;
+        }
+        y[H.perm[r]] = acc;
+    }
+}
+
+inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hipStream_t st) {
+    if (H.n > 0) hipLaunchKernelGGL(h_basis_kernel, dim3(nb256(H.n * H.M)), dim3(256), 0, st, H);
+    if (H.nc > 1)
+        hipLaunchKernelGGL(h_transfer_kernel, dim3(nb256((long long)H.nc * H.M * H.M)), dim3(256), 0, st, H);
+    if (H.nfar > 0)
+        hipLaunchKernelGGL(h_kblock_kernel, dim3(nb256(H.nfar * H.M * H.M)), dim3(256), 0, st, H, pe);
+    if (H.nnear > 0)
+        hipLaunchKernelGGL(h_near_kernel, dim3(4, (unsigned)(H.nnear < 32768 ? H.nnear : 32768)), dim3(256), 0, st,
+                           H, A, lda);
+}
+
+void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_counts, int n_up,
+                     const int* const* down_lists, const int* down_counts, int n_down, double C, const double* x,
+                     double* y, hipStream_t st) {
+    if (H.n == 0) return;
+    hipLaunchKernelGGL(h_gather_kernel, dim3(nb256(H.n)), dim3(256), 0, st, H, x);
+    hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
+    for (int l = 0; l < n_up; ++l)
+        if (up_counts[l] > 0)
+            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 0, st, H, up_lists[l]);
+    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(64), 0, st, H);
+    for (int l = 0; l < n_down; ++l)
+        if (down_counts[l] > 0)
+            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), 0, st, H, down_lists[l]);
+    hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H, C, y);
+}
+
+}  // namespace fl
+
+namespace fl {
+namespace {
+__global__ __launch_bounds__(256) void h_diag_kernel(const double* __restrict__ A, long long lda, long long n,
+                                                     double* __restrict__ d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = A[i * lda + i];
+}
+}  // namespace
+
+void launch_h_diag(const double* A, long long lda, long long n, double* d, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(h_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, lda, n, d);
+}
+}  // namespace fl

@@ -1,0 +1,522 @@
+// Host side of the cluster (H-matrix) approximation (include/fraclap.h:
+// fl_cluster_build, fl_cluster_matvec, fl_solve_cluster, fl_cluster_info).
+// Sec. 6: a cluster tree over the DOFs, cluster boxes (cubes containing the
+// supports), admissible pairs eta dist >= max diam approximated by the
+// tensor Chebyshev interpolation of the kernel with nested bases, the rest
+// (leaf pairs) kept exactly.  Readings: leaves of at most `leaf` DOFs (the
+// paper's leaves are single DOFs); a cluster is split at the median of its
+// DOF coordinates along the longest extent (stable order); its box is the
+// cube of the largest extent of the supports' bounding box, centred on it;
+// the near blocks are copied from the assembled dense matrix.  Built
+// without floating-point contraction so that the boxes, and with them the
+// admissibility decisions, are those of an independent implementation of
+// the same formulas.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "fl_handle.hpp"
+#include "fl_internal.hpp"
+
+using namespace fl;
+
+namespace {
+
+int cfail(fl_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return cfail(h, FL_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int hm_upload(fl_handle* h, T** p, const std::vector<T>& v) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(v.size(), 1)) != hipSuccess)
+        return cfail(h, FL_ENOMEM, "cluster approximation: device allocation failed");
+    h->hm.bufs.push_back(q);
+    h->hm.bytes += sizeof(T) * v.size();
+    *p = (T*)q;
+    if (!v.empty()) HIPCHK(hipMemcpy(q, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return FL_OK;
+}
+
+template <class T>
+int hm_alloc(fl_handle* h, T** p, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return cfail(h, FL_ENOMEM, "cluster approximation: device allocation failed");
+    h->hm.bufs.push_back(q);
+    h->hm.bytes += sizeof(T) * count;
+    *p = (T*)q;
+    return FL_OK;
+}
+
+void hm_release(fl_handle* h) {
+    for (void* p : h->hm.bufs) (void)hipFree(p);
+    if (h->hm.hsc) (void)hipHostFree(h->hm.hsc);
+    h->hm = fl_hm{};
+}
+
+struct HCl {
+    int lo, hi, level, parent;
+    double blo[2], side;
+    std::vector<int> sons;
+};
+
+bool admissible(const HCl& a, const HCl& b, double eta, int dim) {
+    double g2 = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        const double g = std::max(0.0, std::max(b.blo[j] - (a.blo[j] + a.side), a.blo[j] - (b.blo[j] + b.side)));
+        g2 += g * g;
+    }
+    const double dist = std::sqrt(g2);
+    const double sq = std::sqrt((double)dim);
+    return eta * dist >= std::max(a.side * sq, b.side * sq);
+}
+
+}  // namespace
+
+void fl_hm_free(fl_handle* h) { hm_release(h); }
+
+extern "C" {
+
+int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
+    if (!h) return FL_EINVAL;
+    if (!h->assembled) return cfail(h, FL_ESTATE, "no assembled matrix (fl_assemble)");
+    if (m < 1 || m > 15) return cfail(h, FL_EINVAL, "m must lie in 1..15");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return cfail(h, FL_EINVAL, "eta must be positive and finite");
+    if (leaf < 1 || leaf > 1024) return cfail(h, FL_EINVAL, "leaf must lie in 1..1024");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hm_release(h);
+    const int dim = h->dim, nper = dim + 1;
+    const int64_t n = h->n, nv = h->nv, T = h->nc;
+    int M = 1;
+    for (int j = 0; j < dim; ++j) M *= m;
+    // supports: bounding box of the cells around every vertex
+    std::vector<double> vlo(nv * 2, INFINITY), vhi(nv * 2, -INFINITY);
+    for (int64_t K = 0; K < T; ++K) {
+        double clo[2] = {INFINITY, INFINITY}, chi[2] = {-INFINITY, -INFINITY};
+        for (int a = 0; a < nper; ++a)
+            for (int j = 0; j < dim; ++j) {
+                const double x = h->verts[dim * h->cells[nper * K + a] + j];
+                clo[j] = std::min(clo[j], x);
+                chi[j] = std::max(chi[j], x);
+            }
+        for (int a = 0; a < nper; ++a) {
+            const int v = h->cells[nper * K + a];
+            for (int j = 0; j < dim; ++j) {
+                vlo[2 * v + j] = std::min(vlo[2 * v + j], clo[j]);
+                vhi[2 * v + j] = std::max(vhi[2 * v + j], chi[j]);
+            }
+        }
+    }
+    // tree (pre-order ids), perm: tree position -> DOF
+    std::vector<HCl> cl;
+    std::vector<int> perm(n);
+    auto coord = [&](int i, int j) { return h->verts[dim * h->dof_node[i] + j]; };
+    std::function<int(std::vector<int>&, int, int, int)> make = [&](std::vector<int>& idx, int lo, int level,
+                                                                    int parent) -> int {
+        HCl c;
+        c.lo = lo;
+        c.hi = lo + (int)idx.size();
+        c.level = level;
+        c.parent = parent;
+        double blo[2] = {INFINITY, INFINITY}, bhi[2] = {-INFINITY, -INFINITY};
+        for (int i : idx) {
+            const int v = h->dof_node[i];
+            for (int j = 0; j < dim; ++j) {
+                blo[j] = std::min(blo[j], vlo[2 * v + j]);
+                bhi[j] = std::max(bhi[j], vhi[2 * v + j]);
+            }
+        }
+        double side = 0.0;
+        for (int j = 0; j < dim; ++j) side = std::max(side, bhi[j] - blo[j]);
+        c.side = side;
+        c.blo[1] = 0.0;
+        for (int j = 0; j < dim; ++j) {
+            const double cen = 0.5 * (blo[j] + bhi[j]);
+            c.blo[j] = cen - 0.5 * side;
+        }
+        const int cid = (int)cl.size();
+        cl.push_back(c);
+        for (size_t k = 0; k < idx.size(); ++k) perm[lo + k] = idx[k];
+        if ((int)idx.size() > leaf) {
+            int ax = 0;
+            double best = -1.0;
+            for (int j = 0; j < dim; ++j) {
+                double lo_ = INFINITY, hi_ = -INFINITY;
+                for (int i : idx) {
+                    lo_ = std::min(lo_, coord(i, j));
+                    hi_ = std::max(hi_, coord(i, j));
+                }
+                if (hi_ - lo_ > best) {
+                    best = hi_ - lo_;
+                    ax = j;
+                }
+            }
+            std::vector<int> order(idx);
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return coord(a, ax) < coord(b, ax); });
+            const size_t half = order.size() / 2;
+            std::vector<int> p1(order.begin(), order.begin() + half), p2(order.begin() + half, order.end());
+            const int s1 = make(p1, lo, level + 1, cid);
+            cl[cid].sons.push_back(s1);
+            const int s2 = make(p2, lo + (int)half, level + 1, cid);
+            cl[cid].sons.push_back(s2);
+        }
+        return cid;
+    };
+    {
+        std::vector<int> all(n);
+        for (int64_t i = 0; i < n; ++i) all[i] = (int)i;
+        if (n > 0) make(all, 0, 0, -1);
+    }
+    const int nc = (int)cl.size();
+    // admissible pairs and near leaf pairs (recursion from (root, root))
+    std::vector<std::pair<int, int>> far, near;
+    std::function<void(int, int)> rec = [&](int s, int t) {
+        if (admissible(cl[s], cl[t], eta, dim)) {
+            far.push_back({s, t});
+            return;
+        }
+        const bool ls = cl[s].sons.empty(), lt = cl[t].sons.empty();
+        if (ls && lt) {
+            near.push_back({s, t});
+        } else if (ls) {
+            for (int tt : cl[t].sons) rec(s, tt);
+        } else if (lt) {
+            for (int ss : cl[s].sons) rec(ss, t);
+        } else {
+            for (int ss : cl[s].sons)
+                for (int tt : cl[t].sons) rec(ss, tt);
+        }
+    };
+    if (nc > 0) rec(0, 0);
+    std::stable_sort(far.begin(), far.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return a.first < b.first;
+    });
+    std::vector<int> leaf_ids, leaf_of(nc, -1);
+    for (int c = 0; c < nc; ++c)
+        if (cl[c].sons.empty()) {
+            leaf_of[c] = (int)leaf_ids.size();
+            leaf_ids.push_back(c);
+        }
+    std::stable_sort(near.begin(), near.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return leaf_of[a.first] < leaf_of[b.first];
+    });
+    // flattened host arrays
+    std::vector<int> clo(nc), chi(nc), cpar(nc), sptr(nc + 1, 0), sidx, node(n), rleaf(n);
+    std::vector<double> box(3 * (size_t)nc);
+    int depth = 0;
+    for (int c = 0; c < nc; ++c) {
+        clo[c] = cl[c].lo;
+        chi[c] = cl[c].hi;
+        cpar[c] = cl[c].parent;
+        box[3 * c] = cl[c].blo[0];
+        box[3 * c + 1] = cl[c].blo[1];
+        box[3 * c + 2] = cl[c].side;
+        for (int sn : cl[c].sons) sidx.push_back(sn);
+        sptr[c + 1] = (int)sidx.size();
+        depth = std::max(depth, cl[c].level);
+        if (cl[c].sons.empty())
+            for (int r = cl[c].lo; r < cl[c].hi; ++r) rleaf[r] = c;
+    }
+    for (int64_t r = 0; r < n; ++r) node[r] = h->dof_node[perm[r]];
+    std::vector<long long> fptr(nc + 1, 0);
+    std::vector<int> fsrc, fdst;
+    for (auto& p : far) {
+        fsrc.push_back(p.first);
+        fdst.push_back(p.second);
+        fptr[p.first + 1]++;
+    }
+    for (int c = 0; c < nc; ++c) fptr[c + 1] += fptr[c];
+    const int nleaf = (int)leaf_ids.size();
+    std::vector<int> lnptr(nleaf + 1, 0), nsrc, ndst;
+    std::vector<long long> noff;
+    long long near_entries = 0;
+    for (auto& p : near) {
+        nsrc.push_back(p.first);
+        ndst.push_back(p.second);
+        noff.push_back(near_entries);
+        near_entries += (long long)(chi[p.first] - clo[p.first]) * (chi[p.second] - clo[p.second]);
+        lnptr[leaf_of[p.first] + 1]++;
+    }
+    for (int l = 0; l < nleaf; ++l) lnptr[l + 1] += lnptr[l];
+    // Chebyshev points of the first kind on [0, 1] (increasing) and the
+    // (m+1)-point cell rule
+    std::vector<double> tnode(m);
+    for (int k = 0; k < m; ++k) tnode[k] = 0.5 - 0.5 * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * m));
+    const RuleTables& R = fl_base_rules();
+    const int kq = m + 1;
+    std::vector<double> qlam, qw;
+    if (dim == 1) {
+        for (int i = 0; i < kq; ++i) {
+            const double t = R.gl_x[gl_off(kq) + i];
+            qlam.push_back(1.0 - t);
+            qlam.push_back(t);
+            qw.push_back(R.gl_w[gl_off(kq) + i]);
+        }
+    } else {
+        for (int i = 0; i < kq; ++i)
+            for (int j = 0; j < kq; ++j) {
+                const double l1 = R.gj_x[gl_off(kq) + i], l2 = (1.0 - l1) * R.gl_x[gl_off(kq) + j];
+                qlam.push_back(1.0 - l1 - l2);
+                qlam.push_back(l1);
+                qlam.push_back(l2);
+                qw.push_back(2.0 * R.gj_w[gl_off(kq) + i] * R.gl_w[gl_off(kq) + j]);
+            }
+    }
+    // vertex -> cells (increasing)
+    std::vector<int> vptr(nv + 1, 0), vidx((size_t)T * nper);
+    for (int64_t i = 0; i < T * nper; ++i) vptr[h->cells[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    {
+        std::vector<int> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t K = 0; K < T; ++K)
+            for (int a = 0; a < nper; ++a) vidx[fill[h->cells[nper * K + a]]++] = (int)K;
+    }
+    // per-level cluster lists: upward (internal clusters, deepest first),
+    // downward (every cluster below the root, shallowest first)
+    std::vector<std::vector<int>> up(depth + 1), down(depth + 1);
+    for (int c = 0; c < nc; ++c) {
+        if (!cl[c].sons.empty()) up[cl[c].level].push_back(c);
+        if (c > 0) down[cl[c].level].push_back(c);
+    }
+    // device
+    fl_hm& Hm = h->hm;
+    HDev H{};
+    H.dim = dim;
+    H.m = m;
+    H.M = M;
+    H.n = n;
+    H.nc = nc;
+    H.nleaf = nleaf;
+    H.nfar = (long long)far.size();
+    H.nnear = (long long)near.size();
+    H.nq = (int)qw.size();
+    int rc;
+    const int *p_clo, *p_chi, *p_cpar, *p_sptr, *p_sidx, *p_perm, *p_node, *p_rleaf, *p_leaf, *p_cells, *p_vptr,
+        *p_vidx, *p_fsrc, *p_fdst, *p_lnptr, *p_nsrc, *p_ndst;
+    const double *p_box, *p_tnode, *p_verts, *p_qlam, *p_qw;
+    const long long *p_fptr, *p_noff;
+    std::vector<int> cells(h->cells.begin(), h->cells.end());
+    std::vector<double> verts(h->verts.begin(), h->verts.end());
+#define UP(ptr, vec)                                                         \
+    do {                                                                     \
+        using E_ = std::remove_const_t<std::remove_pointer_t<decltype(ptr)>>; \
+        E_* q_ = nullptr;                                                    \
+        if ((rc = hm_upload(h, &q_, vec))) {                                 \
+            hm_release(h);                                                   \
+            return rc;                                                       \
+        }                                                                    \
+        ptr = q_;                                                            \
+    } while (0)
+    UP(p_clo, clo);
+    UP(p_chi, chi);
+    UP(p_cpar, cpar);
+    UP(p_sptr, sptr);
+    UP(p_sidx, sidx);
+    UP(p_perm, perm);
+    UP(p_node, node);
+    UP(p_rleaf, rleaf);
+    UP(p_leaf, leaf_ids);
+    UP(p_cells, cells);
+    UP(p_vptr, vptr);
+    UP(p_vidx, vidx);
+    UP(p_fsrc, fsrc);
+    UP(p_fdst, fdst);
+    UP(p_lnptr, lnptr);
+    UP(p_nsrc, nsrc);
+    UP(p_ndst, ndst);
+    UP(p_box, box);
+    UP(p_tnode, tnode);
+    UP(p_verts, verts);
+    UP(p_qlam, qlam);
+    UP(p_qw, qw);
+    UP(p_fptr, fptr);
+    UP(p_noff, noff);
+#undef UP
+    H.clo = p_clo;
+    H.chi = p_chi;
+    H.cpar = p_cpar;
+    H.sptr = p_sptr;
+    H.sidx = p_sidx;
+    H.box = p_box;
+    H.tnode = p_tnode;
+    H.perm = p_perm;
+    H.node = p_node;
+    H.rleaf = p_rleaf;
+    H.leaf = p_leaf;
+    H.verts = p_verts;
+    H.cells = p_cells;
+    H.vptr = p_vptr;
+    H.vidx = p_vidx;
+    H.qlam = p_qlam;
+    H.qw = p_qw;
+    H.fptr = p_fptr;
+    H.fsrc = p_fsrc;
+    H.fdst = p_fdst;
+    H.lnptr = p_lnptr;
+    H.nsrc = p_nsrc;
+    H.ndst = p_ndst;
+    H.noff = p_noff;
+    if ((rc = hm_alloc(h, &H.V, (size_t)n * M)) || (rc = hm_alloc(h, &H.T, (size_t)nc * M * M)) ||
+        (rc = hm_alloc(h, &H.Kb, (size_t)H.nfar * M * M)) || (rc = hm_alloc(h, &H.An, (size_t)near_entries)) ||
+        (rc = hm_alloc(h, &H.xp, (size_t)n)) || (rc = hm_alloc(h, &H.xh, (size_t)nc * M)) ||
+        (rc = hm_alloc(h, &H.yh, (size_t)nc * M)) || (rc = hm_alloc(h, &Hm.d, (size_t)n)) ||
+        (rc = hm_alloc(h, &Hm.cg, (size_t)4 * n)) || (rc = hm_alloc(h, &Hm.sc, 16))) {
+        hm_release(h);
+        return rc;
+    }
+    if (hipHostMalloc((void**)&Hm.hsc, 16 * sizeof(double)) != hipSuccess) {
+        hm_release(h);
+        return cfail(h, FL_ENOMEM, "cluster approximation: pinned allocation failed");
+    }
+    for (int l = depth; l >= 0; --l) {
+        int* q = nullptr;
+        if ((rc = hm_upload(h, &q, up[l]))) {
+            hm_release(h);
+            return rc;
+        }
+        Hm.up_lists.push_back(q);
+        Hm.up_counts.push_back((int)up[l].size());
+    }
+    for (int l = 1; l <= depth; ++l) {
+        int* q = nullptr;
+        if ((rc = hm_upload(h, &q, down[l]))) {
+            hm_release(h);
+            return rc;
+        }
+        Hm.down_lists.push_back(q);
+        Hm.down_counts.push_back((int)down[l].size());
+    }
+    launch_h_setup(H, h->dA, h->lda, -0.5 * (dim + 2.0 * h->s), h->stream);
+    launch_h_diag(h->dA, h->lda, n, Hm.d, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    Hm.H = H;
+    Hm.m = m;
+    Hm.leaf = leaf;
+    Hm.eta = eta;
+    Hm.depth = depth;
+    Hm.C = fl_cdn(dim, h->s);
+    Hm.near_entries = near_entries;
+    Hm.ready = true;
+    return FL_OK;
+}
+
+int fl_cluster_matvec(fl_handle* h, const double* x, double* y) {
+    if (!h) return FL_EINVAL;
+    if (!h->hm.ready) return cfail(h, FL_ESTATE, "no cluster approximation of the current matrix (fl_cluster_build)");
+    if (!x || !y) return cfail(h, FL_EINVAL, "null vector");
+    HIPCHK(hipSetDevice(h->device));
+    const fl_hm& Hm = h->hm;
+    launch_h_matvec(Hm.H, Hm.up_lists.data(), Hm.up_counts.data(), (int)Hm.up_lists.size(), Hm.down_lists.data(),
+                    Hm.down_counts.data(), (int)Hm.down_lists.size(), Hm.C, x, y, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_cluster_info(const fl_handle* h, int64_t* out) {
+    if (!h || !out) return FL_EINVAL;
+    if (!h->hm.ready) return FL_ESTATE;
+    const fl_hm& Hm = h->hm;
+    out[0] = Hm.H.nc;
+    out[1] = Hm.H.nleaf;
+    out[2] = Hm.H.nfar;
+    out[3] = Hm.H.nnear;
+    out[4] = Hm.near_entries;
+    out[5] = (int64_t)Hm.bytes;
+    out[6] = Hm.depth;
+    return FL_OK;
+}
+
+int fl_solve_cluster(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
+                     double* relres) {
+    if (!h) return FL_EINVAL;
+    if (!h->hm.ready) return cfail(h, FL_ESTATE, "no cluster approximation of the current matrix (fl_cluster_build)");
+    if (!(rtol >= 0.0) || maxit < 0) return cfail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
+    if (!b || !u) return cfail(h, FL_EINVAL, "null vector");
+    HIPCHK(hipSetDevice(h->device));
+    int rc = fl_solver_workspace(h);
+    if (rc) return rc;
+    fl_hm& Hm = h->hm;
+    const int64_t n = h->n;
+    double *r = Hm.cg, *z = Hm.cg + n, *p = Hm.cg + 2 * n, *q = Hm.cg + 3 * n;
+    const int nblk = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    auto Hmul = [&](const double* x, double* y) {
+        launch_h_matvec(Hm.H, Hm.up_lists.data(), Hm.up_counts.data(), (int)Hm.up_lists.size(),
+                        Hm.down_lists.data(), Hm.down_counts.data(), (int)Hm.down_lists.size(), Hm.C, x, y,
+                        h->stream);
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    launch_zero(u, n, h->stream);
+    HIPCHK(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    launch_mg_scale(z, r, Hm.d, 1.0, n, h->stream);
+    launch_dot2(r, z, r, n, h->w_part, nblk, Hm.sc, h->stream);
+    HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(Hm.hsc, Hm.sc, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const double bb = Hm.hsc[1];
+    int status = FL_OK, it = 0;
+    double rr = bb;
+    if (!std::isfinite(bb)) status = FL_ENONFINITE;
+    // iteration k: rz_k, rr_k at sc[2 (k & 1)], sc[2 (k & 1) + 1]; p.Ap at sc[4]
+    while (status == FL_OK && bb > 0.0 && !(std::sqrt(rr) <= rtol * std::sqrt(bb)) && it < maxit) {
+        const int cur = 2 * (it & 1), nxt = 2 * ((it + 1) & 1);
+        Hmul(p, q);
+        launch_dot2(p, q, q, n, h->w_part, nblk, Hm.sc + 4, h->stream);
+        launch_mg_axpy(u, r, p, q, n, Hm.sc, cur, 4, h->stream);
+        launch_mg_scale(z, r, Hm.d, 1.0, n, h->stream);
+        launch_dot2(r, z, r, n, h->w_part, nblk, Hm.sc + nxt, h->stream);
+        launch_mg_pupdate(p, z, n, Hm.sc, nxt, cur, h->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(Hm.hsc, Hm.sc, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        ++it;
+        rr = Hm.hsc[nxt + 1];
+        const double pq = Hm.hsc[4], rz = Hm.hsc[nxt];
+        if (!std::isfinite(rr) || !std::isfinite(pq) || !std::isfinite(rz)) {
+            status = FL_ENONFINITE;
+            break;
+        }
+        if (!(pq > 0.0) || (!(rz > 0.0) && rr > 0.0)) {
+            status = FL_EBREAKDOWN;
+            break;
+        }
+    }
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double rel = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
+    h->st.t_solve_ms = ms;
+    h->st.last_iters = it;
+    h->st.last_relres = rel;
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (status == FL_EBREAKDOWN) return cfail(h, FL_EBREAKDOWN, "CG breakdown: p.Ap <= 0 or r.z <= 0");
+    if (status == FL_ENONFINITE) return cfail(h, FL_ENONFINITE, "non-finite residual");
+    if (!(rel <= rtol)) return FL_ENOCONV;
+    return FL_OK;
+}
+
+}  // extern "C"

@@ -105,6 +105,23 @@ struct fl_sf {
     std::vector<void*> bufs;        // every allocation above
 };
 
+// Cluster approximation of the assembled matrix (fl_cluster_build).
+struct fl_hm {
+    bool ready = false;
+    int m = 0, leaf = 0, depth = 0;
+    double eta = 0.0, C = 0.0;
+    fl::HDev H{};
+    std::vector<const int*> up_lists, down_lists;
+    std::vector<int> up_counts, down_counts;
+    double* d = nullptr;            // diagonal of A (Jacobi)
+    double* cg = nullptr;           // r, z, p, q
+    double* sc = nullptr;           // device scalars and their pinned mirror
+    double* hsc = nullptr;
+    long long near_entries = 0;
+    size_t bytes = 0;               // device bytes of the representation
+    std::vector<void*> bufs;        // every device allocation above
+};
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -163,6 +180,7 @@ struct fl_handle {
     fl_sur sur;
     fl_mg mg;
     fl_sf sf;
+    fl_hm hm;
 };
 
 // Quadrature tables independent of s (defined with the assembly driver).
@@ -170,6 +188,7 @@ const fl::RuleTables& fl_base_rules();
 // C(d,s), the constant of the operator (Sec. 2)
 double fl_cdn(int d, double s);
 void fl_sf_free(fl_handle* h);
+void fl_hm_free(fl_handle* h);
 // Surrogate parameters of an assembly at s with options o (classes below
 // o.surrogate); FL_ESTATE without a network and scaling.  Defined with the
 // surrogate calls.

@@ -225,6 +225,54 @@ struct SfDev {
     double cg, cg_own;      // 1/(2s(d+2s-2)) and 1/(d+2s-2); 1/(2s) and 1 in the log form
     double inv2s, C;        // 1/(2s), C(d,s)
 };
+// Cluster (H-matrix) approximation of A (Sec. 6): tree in DOF ranges
+// (tree order), Chebyshev boxes, nested bases, admissible and near pairs.
+struct HDev {
+    int dim, m, M;          // space dimension, points per direction, M = m^dim
+    long long n;            // DOFs
+    int nc, nleaf;          // clusters (pre-order, root 0), leaves
+    const int* clo;         // DOF range [clo, chi) of each cluster in tree order
+    const int* chi;
+    const int* cpar;        // parent (-1 at the root)
+    const int* sptr;        // sons (CSR)
+    const int* sidx;
+    const double* box;      // per cluster: corner x, corner y, side
+    const double* tnode;    // m Chebyshev points on [0, 1]
+    const int* perm;        // tree position -> DOF
+    const int* node;        // tree position -> vertex
+    const int* rleaf;       // tree position -> leaf cluster
+    const int* leaf;        // leaf cluster ids
+    // mesh (caller's order) for the basis coefficients
+    const double* verts;
+    const int* cells;
+    const int* vptr;        // vertex -> cells (CSR, increasing)
+    const int* vidx;
+    int nq;                 // (m+1)-point cell rule: barycentric coordinates, weights
+    const double* qlam;
+    const double* qw;
+    double* V;              // n x M basis coefficients (tree order)
+    double* T;              // nc x M x M shift coefficients T_c[b][a]
+    long long nfar;         // admissible pairs, grouped by the first cluster
+    const long long* fptr;  // nc + 1
+    const int* fsrc;
+    const int* fdst;
+    double* Kb;             // nfar x M x M kernel blocks, column by column
+    long long nnear;        // near leaf pairs, grouped by the first leaf
+    const int* lnptr;       // nleaf + 1 (by leaf index)
+    const int* nsrc;
+    const int* ndst;
+    const long long* noff;  // offset of each block in An
+    double* An;             // near blocks, row-major
+    double* xp;             // product workspace: x and y in tree order, cluster vectors
+    double* xh;
+    double* yh;
+};
+void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hipStream_t st);
+void launch_h_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
+void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_counts, int n_up,
+                     const int* const* down_lists, const int* down_counts, int n_down, double C, const double* x,
+                     double* y, hipStream_t st);
+
 void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st);
 void launch_sf_far(const SfDev& D, const double* sx, const double* sy, const double* bsx, const double* bsy,
                    long long chunk, int nch, int nchb, const double* tab, double* part, bool logk,

@@ -37,7 +37,8 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_dataset", "fl_surrogate_init", "fl_surrogate_fit_scaling",
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
-           "fl_eval_points", "fl_strong_form", "fl_indicators"]
+           "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
+           "fl_solve_cluster", "fl_cluster_info"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -109,6 +110,10 @@ def lib():
         L.fl_mass_matvec.argtypes = [vp, vp, vp]
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
         L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
+        L.fl_cluster_build.argtypes = [vp, C.c_int32, dp, C.c_int32]
+        L.fl_cluster_matvec.argtypes = [vp, vp, vp]
+        L.fl_solve_cluster.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
+        L.fl_cluster_info.argtypes = [vp, vp]
         L.fl_strong_form.argtypes = [vp, dp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
         L.fl_indicators.argtypes = [vp, dp, vp, vp, C.c_int32, vp, vp]
         L.fl_solve_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
@@ -300,6 +305,27 @@ class Handle:
         """eta_K^2 into eta_cell (nc), their vertex sums into eta_node (nv)."""
         self._check(lib().fl_indicators(self.h, s, _ptr(Lu), None if f is None else _ptr(f), k_eval,
                                         _ptr(eta_cell), None if eta_node is None else _ptr(eta_node)))
+
+    def cluster_build(self, m=6, eta=2.0, leaf=32):
+        """Cluster approximation of the assembled matrix (order m, admissibility eta)."""
+        self._check(lib().fl_cluster_build(self.h, m, eta, leaf))
+
+    def cluster_matvec(self, x, y):
+        self._check(lib().fl_cluster_matvec(self.h, _ptr(x), _ptr(y)))
+
+    def solve_cluster(self, b, u, rtol=1e-12, maxit=100000):
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = self._check(lib().fl_solve_cluster(self.h, _ptr(b), _ptr(u), rtol, maxit, C.byref(it), C.byref(rel)),
+                         allow=(FL_OK, FL_ENOCONV))
+        return it.value, rel.value, rc
+
+    def cluster_info(self) -> dict:
+        import numpy as np
+        out = np.zeros(7, dtype=np.int64)
+        self._check(lib().fl_cluster_info(self.h, out.ctypes.data_as(C.c_void_p)))
+        keys = ("clusters", "leaves", "far_pairs", "near_pairs", "near_entries", "bytes", "depth")
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def solve(self, b, u, rtol=1e-12, maxit=100000):
         it = C.c_int32()
