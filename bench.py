@@ -64,6 +64,9 @@ def parse():
                     help="skip the a posteriori leg (strong form + indicators on the disk, adaptive loops)")
     ap.add_argument("--only-indicators", action="store_true",
                     help="run only the a posteriori leg and print its object")
+    ap.add_argument("--no-cluster", action="store_true",
+                    help="skip the cluster leg (H-matrix approximation of disks of ~8k / 32k / 128k triangles)")
+    ap.add_argument("--only-cluster", action="store_true", help="run only the cluster leg and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -126,6 +129,11 @@ def main():
         import torch
         torch.cuda.init()
         print(json.dumps({"indicators": indicators_leg(args)}), flush=True)
+        return
+    if args.only_cluster:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"cluster": cluster_leg(args)}), flush=True)
         return
     if args.only_mg:
         import torch
@@ -268,6 +276,8 @@ def main():
         out["multigrid"] = mg_leg(args)
     if not args.no_indicators:
         out["indicators"] = indicators_leg(args)
+    if not args.no_cluster:
+        out["cluster"] = cluster_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -808,6 +818,64 @@ def indicators_leg(args):
                        "t_indicators_s": round(sum(st.t_indicators for st in steps), 4),
                        "wall_s": round(wall, 3)}
     out["adaptive"] = loops
+    return out
+
+
+def cluster_leg(args):
+    """Cluster approximation (Sec. 6) of the assembled FP64 matrix on unit
+    disks of ~8k, 32k and 128k triangles (s = 0.75, interior DOFs), m = 6,
+    eta = 2, leaves of 32 DOFs: set-up time, device bytes against the dense
+    upper triangle, product time against the dense symmetric product, the
+    relative product error, and Jacobi-PCG to 1e-10 on both operators."""
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    out = {"workload": "unit disk, s=0.75, f=1; cluster approximation m=6, eta=2, leaf 32 vs the dense FP64 matrix"}
+    for cells in (8000, 32000, 128000):
+        mesh = M.disk_for_cells(cells, seed=2)
+        h = F.Handle(0)
+        h.set_mesh(mesh)
+        n = h.assemble(0.75)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.cluster_build(m=6, eta=2.0, leaf=32)
+        torch.cuda.synchronize()
+        t_build = (time.perf_counter() - t0) * 1e3
+        info = h.cluster_info()
+        x = torch.tensor(__import__("numpy").random.default_rng(1).standard_normal(n), device="cuda")
+        yd, yh = torch.empty_like(x), torch.empty_like(x)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        h.matvec(x, yd)
+        h.cluster_matvec(x, yh)
+        reps = 20
+        ev[0].record()
+        for _ in range(reps):
+            h.matvec(x, yd)
+        ev[1].record()
+        for _ in range(reps):
+            h.cluster_matvec(x, yh)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_dense = ev[0].elapsed_time(ev[1]) / reps
+        t_h = ev[1].elapsed_time(ev[2]) / reps
+        err = float(torch.linalg.norm(yh - yd) / torch.linalg.norm(yd))
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.load_vector_one(b)
+        ud, uh = torch.zeros_like(b), torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        itd, _, _ = h.solve(b, ud, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ith, _, _ = h.solve_cluster(b, uh, rtol=1e-10)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[f"cells{len(mesh['cells'])}"] = {
+            "n": n, "build_ms": round(t_build, 2), "clusters": info["clusters"], "far_pairs": info["far_pairs"],
+            "near_entries": info["near_entries"], "bytes": info["bytes"],
+            "dense_upper_bytes": n * (n + 1) // 2 * 8, "matvec_dense_ms": round(t_dense, 4),
+            "matvec_cluster_ms": round(t_h, 4), "rel_err": err, "cg_dense": [itd, round((t1 - t0) * 1e3, 2)],
+            "cg_cluster": [ith, round((t2 - t1) * 1e3, 2)]}
+        h.close()
     return out
 
 

@@ -115,13 +115,14 @@ __global__ __launch_bounds__(256) void h_kblock_kernel(HDev H, double pe) {
     H.Kb[id] = kpow(dx * dx + dy * dy, pe);
 }
 
-// Near blocks copied from the dense matrix (row-major per block, tree order).
+// Near blocks copied from the dense matrix (column by column per block,
+// tree order).
 __global__ __launch_bounds__(256) void h_near_kernel(HDev H, const double* __restrict__ A, long long lda) {
     for (long long p = blockIdx.y; p < H.nnear; p += gridDim.y) {
         const int s = H.nsrc[p], t = H.ndst[p];
         const int rs = H.clo[s], ns = H.chi[s] - rs, rt = H.clo[t], nt = H.chi[t] - rt;
         for (int id = threadIdx.x + blockIdx.x * blockDim.x; id < ns * nt; id += blockDim.x * gridDim.x) {
-            const int i = id / nt, j = id - i * nt;
+            const int j = id / ns, i = id - j * ns;
             H.An[H.noff[p] + id] = A[(long long)H.perm[rs + i] * lda + H.perm[rt + j]];
         }
     }
@@ -161,17 +162,25 @@ __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int* __restrict_
 }
 
 // far field: yh[s][a] = sum over admissible (s, t) of sum_b K[a][b] xh[t][b];
-// one workgroup per cluster, pairs in list order
-__global__ __launch_bounds__(64) void h_far_kernel(HDev H) {
+// one workgroup per cluster, four groups of 64 lanes take every fourth pair,
+// their partial sums are added in group order
+__global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
+    __shared__ double red[4][64];
     const int c = blockIdx.x;
-    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int a0 = 0; a0 < H.M; a0 += 64) {
+        const int a = a0 + lane;
         double acc = 0.0;
-        for (long long p = H.fptr[c]; p < H.fptr[c + 1]; ++p) {
-            const double* Kp = H.Kb + p * H.M * H.M;
-            const double* xt = H.xh + (long long)H.fdst[p] * H.M;
-            for (int b = 0; b < H.M; ++b) acc = fma(Kp[b * H.M + a], xt[b], acc);
-        }
-        H.yh[(long long)c * H.M + a] = acc;
+        if (a < H.M)
+            for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
+                const double* Kp = H.Kb + p * H.M * H.M;
+                const double* xt = H.xh + (long long)H.fdst[p] * H.M;
+                for (int b = 0; b < H.M; ++b) acc = fma(Kp[b * H.M + a], xt[b], acc);
+            }
+        red[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && a < H.M) H.yh[(long long)c * H.M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
     }
 }
 
@@ -188,25 +197,43 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int* __restric
 }
 
 // leaves: y[perm[r]] = -C sum_a V[r][a] yh[c][a] + sum over near (c, t) of
-// the block row times xp[t]; one workgroup per leaf, one thread per row
-__global__ __launch_bounds__(64) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
+// the block row times xp[t]; one workgroup per leaf, rows in chunks of 32
+// lanes, eight groups take every eighth near block (column-major blocks:
+// the lanes of a group read consecutive entries), group partials added in
+// group order
+__global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
+    __shared__ double red[8][32];
     const int li = blockIdx.x;
     const int c = H.leaf[li];
     const int lo = H.clo[c], nr = H.chi[c] - lo;
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        const long long r = lo + i;
-        double f = 0.0;
-        for (int a = 0; a < H.M; ++a) f = fma(H.V[r * H.M + a], H.yh[(long long)c * H.M + a], f);
-        double acc = -C * f;
-        for (int e = H.lnptr[li]; e < H.lnptr[li + 1]; ++e) {
-            const int t = H.ndst[e];
-            const int rt = H.clo[t], nt = H.chi[t] - rt;
-            const double* blk = H.An + H.noff[e] + (long long)i * nt;
-            double s = 0.0;
-            for (int j = 0; j < nt; ++j) s = fma(blk[j], H.xp[rt + j], s);
-            acc += s;
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int r0 = 0; r0 < nr; r0 += 32) {
+        const int i = r0 + lane;
+        double acc = 0.0;
+        if (i < nr) {
+            if (g == 0) {
+                const long long r = lo + i;
+                double f = 0.0;
+                for (int a = 0; a < H.M; ++a) f = fma(H.V[r * H.M + a], H.yh[(long long)c * H.M + a], f);
+                acc = -C * f;
+            }
+            for (int e = H.lnptr[li] + g; e < H.lnptr[li + 1]; e += 8) {
+                const int t = H.ndst[e];
+                const int rt = H.clo[t], nt = H.chi[t] - rt;
+                const double* blk = H.An + H.noff[e] + i;
+                double s = 0.0;
+                for (int j = 0; j < nt; ++j) s = fma(blk[(long long)j * nr], H.xp[rt + j], s);
+                acc += s;
+            }
         }
-        y[H.perm[r]] = acc;
+        red[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && i < nr) {
+            double tot = red[0][lane];
+            for (int k = 1; k < 8; ++k) tot += red[k][lane];
+            y[H.perm[lo + i]] = tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -234,11 +261,11 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
     for (int l = 0; l < n_up; ++l)
         if (up_counts[l] > 0)
             hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 0, st, H, up_lists[l]);
-    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(64), 0, st, H);
+    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0)
             hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), 0, st, H, down_lists[l]);
-    hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H, C, y);
+    hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(256), 0, st, H, C, y);
 }
 
 }  // namespace fl

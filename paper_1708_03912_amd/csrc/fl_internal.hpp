@@ -262,7 +262,7 @@ struct HDev {
     const int* nsrc;
     const int* ndst;
     const long long* noff;  // offset of each block in An
-    double* An;             // near blocks, row-major
+    double* An;             // near blocks, column by column
     double* xp;             // product workspace: x and y in tree order, cluster vectors
     double* xh;
     double* yh;
