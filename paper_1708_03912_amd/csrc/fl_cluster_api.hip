@@ -420,6 +420,7 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
 int fl_cluster_matvec(fl_handle* h, const double* x, double* y) {
     if (!h) return FL_EINVAL;
     if (!h->hm.ready) return cfail(h, FL_ESTATE, "no cluster approximation of the current matrix (fl_cluster_build)");
+    if (h->n == 0) return FL_OK;
     if (!x || !y) return cfail(h, FL_EINVAL, "null vector");
     HIPCHK(hipSetDevice(h->device));
     const fl_hm& Hm = h->hm;
@@ -448,6 +449,11 @@ int fl_solve_cluster(fl_handle* h, const double* b, double* u, double rtol, int3
     if (!h) return FL_EINVAL;
     if (!h->hm.ready) return cfail(h, FL_ESTATE, "no cluster approximation of the current matrix (fl_cluster_build)");
     if (!(rtol >= 0.0) || maxit < 0) return cfail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
+    if (h->n == 0) {
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return FL_OK;
+    }
     if (!b || !u) return cfail(h, FL_EINVAL, "null vector");
     HIPCHK(hipSetDevice(h->device));
     int rc = fl_solver_workspace(h);

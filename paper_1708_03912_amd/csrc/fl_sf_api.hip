@@ -400,7 +400,7 @@ int fl_strong_form(fl_handle* h, double s, const double* u, int32_t k_eval, int3
     if (!h) return FL_EINVAL;
     if (!h->planned) return sfail(h, FL_ESTATE, "no DOF map: call fl_assemble first");
     if (!(s > 0.0 && s < 1.0)) return sfail(h, FL_EINVAL, "s must lie in (0,1)");
-    if (!u || !Lu) return sfail(h, FL_EINVAL, "null vector");
+    if (!Lu || (!u && h->n > 0)) return sfail(h, FL_EINVAL, "null vector");
     int rc = check_rules(h, k_eval, q_far, q_near);
     if (rc) return rc;
     HIPCHK(hipSetDevice(h->device));

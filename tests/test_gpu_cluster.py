@@ -109,3 +109,27 @@ def test_cluster_errors():
         h.cluster_matvec(x, y)
     assert e.value.code == F.FL_ESTATE
     h.close()
+
+
+def test_cluster_degenerate():
+    """One leaf (no admissible pair): the product is the dense one; no DOFs
+    at all (one triangle, s >= 1/2): build, product and solve are no-ops."""
+    mesh = M.disk_for_cells(60, seed=3)
+    h, n = _handle(mesh, 0.3)
+    h.cluster_build(m=4, eta=2.0, leaf=1024)
+    info = h.cluster_info()
+    assert info["clusters"] == 1 and info["far_pairs"] == 0 and info["near_entries"] == n * n
+    x = torch.tensor(np.random.default_rng(2).standard_normal(n), device="cuda")
+    y, yd = torch.empty_like(x), torch.empty_like(x)
+    h.cluster_matvec(x, y)
+    h.matvec(x, yd)
+    assert float((y - yd).abs().max()) <= 1e-13 * float(yd.abs().max())
+    h.close()
+    h, n = _handle(M.tiny("one"), 0.75)
+    assert n == 0
+    h.cluster_build()
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    h.cluster_matvec(e, e.clone())
+    it, rel, rc = h.solve_cluster(e, e.clone())
+    assert it == 0 and rc == F.FL_OK
+    h.close()

@@ -163,3 +163,17 @@ def test_errors():
         h.indicators(0.3, Lu, ec, k_eval=3)
     assert e.value.code == F.FL_ESTATE
     h.close()
+
+
+def test_no_dofs():
+    """One triangle with s >= 1/2: u_h = 0, so the strong form vanishes and
+    the indicators are h^{2s} |K| (f = 1)."""
+    mesh = M.tiny("one")
+    s = 0.75
+    dofs = O.dof_nodes(3, mesh["bfacets"], s)
+    assert len(dofs) == 0
+    Lu, ec, en = _gpu(mesh, s, np.zeros(0))
+    assert np.all(Lu == 0.0)
+    eo, no = SF.indicators(mesh, dofs, np.zeros(0), s, np.zeros((1, 4)))
+    _close(ec, eo, 1e-14)
+    _close(en, no, 1e-14)
