@@ -579,6 +579,10 @@ typedef struct {
     int which;             /* bitmask: 1 far, 2 touching, 4 boundary */
     int far_skip_below;    /* separated pairs of class < this are left out
                               (counted only); 0: none */
+    const double *cell_w;  /* NULL, or a weight per cell: pair (K, Kt) counts
+                              with (w_K + w_Kt) / 2 (identical pairs and the
+                              boundary term with w_K), pairs of weight 0 are
+                              skipped (symmetry reduction, Sec. 7) */
 } orc_opts;
 
 static double cdn(int dim, double s) {
@@ -629,6 +633,8 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
         const int32_t *cK = cells + nper * K;
         for (int64_t Kt = K; Kt < nc; ++Kt) {
             if (!hit[K] && !hit[Kt]) continue;
+            const double wp = o->cell_w ? 0.5 * (o->cell_w[K] + o->cell_w[Kt]) : 1.0;
+            if (wp == 0.0) continue;
             const int32_t *cT = cells + nper * Kt;
             int gK[3], gT[3];
             for (int a = 0; a < nper; ++a) { gK[a] = cK[a]; gT[a] = cT[a]; }
@@ -643,7 +649,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     for (int a = 0; a < 3; ++a) { X[2 * a] = verts[2 * gK[a]]; X[2 * a + 1] = verts[2 * gK[a] + 1]; }
                     orc_ident2(R, s, o->k_touch, X, I);
                 }
-                add_block(A, nv, rowmask, gK, nper, gK, nper, I, nper, 0.5 * C);
+                add_block(A, nv, rowmask, gK, nper, gK, nper, I, nper, 0.5 * C * wp);
                 continue;
             }
             /* shared vertices */
@@ -675,13 +681,13 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     }
                     orc_far2(R, s, k, X, Y, SK, ST, O);
                 }
-                add_block(A, nv, rowmask, gK, nper, gK, nper, SK, nper, C);
-                add_block(A, nv, rowmask, gT, nper, gT, nper, ST, nper, C);
-                add_block(A, nv, rowmask, gK, nper, gT, nper, O, nper, C);
+                add_block(A, nv, rowmask, gK, nper, gK, nper, SK, nper, C * wp);
+                add_block(A, nv, rowmask, gT, nper, gT, nper, ST, nper, C * wp);
+                add_block(A, nv, rowmask, gK, nper, gT, nper, O, nper, C * wp);
                 double OT[9];
                 for (int a = 0; a < nper; ++a)
                     for (int b = 0; b < nper; ++b) OT[nper * a + b] = O[nper * b + a];
-                add_block(A, nv, rowmask, gT, nper, gK, nper, OT, nper, C);
+                add_block(A, nv, rowmask, gT, nper, gK, nper, OT, nper, C * wp);
                 continue;
             }
             if (!(o->which & 2)) continue;
@@ -691,7 +697,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                 double I[9];
                 orc_vert1(R, s, o->k_touch, verts[l], verts[q], verts[r], I);
                 int g[3] = {l, q, r};
-                add_block(A, nv, rowmask, g, 3, g, 3, I, 3, C);
+                add_block(A, nv, rowmask, g, 3, g, 3, I, 3, C * wp);
             } else if (nsh == 2) {
                 int a0 = gK[shK[0]], a1 = gK[shK[1]];
                 int q0 = a0 < a1 ? a0 : a1, q1 = a0 < a1 ? a1 : a0;
@@ -700,7 +706,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                 orc_edge2(R, s, o->k_touch, verts + 2 * q0, verts + 2 * q1, verts + 2 * pa,
                           verts + 2 * pb, I);
                 int g[4] = {q0, q1, pa, pb};
-                add_block(A, nv, rowmask, g, 4, g, 4, I, 4, C);
+                add_block(A, nv, rowmask, g, 4, g, 4, I, 4, C * wp);
             } else {
                 int q = gK[shK[0]];
                 int b1 = gK[(shK[0] + 1) % 3], b2 = gK[(shK[0] + 2) % 3];
@@ -711,7 +717,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                 orc_vert2(R, s, o->k_touch, verts + 2 * q, verts + 2 * b1, verts + 2 * b2,
                           verts + 2 * c1, verts + 2 * c2, I);
                 int g[5] = {q, b1, b2, c1, c2};
-                add_block(A, nv, rowmask, g, 5, g, 5, I, 5, C);
+                add_block(A, nv, rowmask, g, 5, g, 5, I, 5, C * wp);
             }
         }
     }
@@ -721,6 +727,8 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
 #pragma omp parallel for schedule(dynamic, 4)
         for (int64_t K = 0; K < nc; ++K) {
             if (!hit[K]) continue;
+            const double fbK = fb * (o->cell_w ? o->cell_w[K] : 1.0);
+            if (fbK == 0.0) continue;
             const int32_t *cK = cells + nper * K;
             int gK[3];
             for (int a = 0; a < nper; ++a) gK[a] = cK[a];
@@ -740,7 +748,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                         k = o->k_far_bnd[cls];
                     }
                     orc_bnd1(R, s, k, X, verts[fe[0]], touching, I);
-                    add_block(A, nv, rowmask, gK, 2, gK, 2, I, 2, fb);
+                    add_block(A, nv, rowmask, gK, 2, gK, 2, I, 2, fbK);
                     continue;
                 }
                 int sh0 = -1, sh1 = -1;
@@ -753,7 +761,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     int pa = gK[3 - sh0 - sh1];
                     orc_bndedge2(R, s, o->k_touch_bnd, p0, p1, verts + 2 * pa, n, I);
                     int g[3] = {fe[0], fe[1], pa};
-                    add_block(A, nv, rowmask, g, 3, g, 3, I, 3, fb);
+                    add_block(A, nv, rowmask, g, 3, g, 3, I, 3, fbK);
                 } else if (sh0 >= 0 || sh1 >= 0) {
                     int a = sh0 >= 0 ? sh0 : sh1;
                     int q = gK[a];
@@ -763,7 +771,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     orc_bndvert2(R, s, o->k_touch_bnd, verts + 2 * q, verts + 2 * b1,
                                  verts + 2 * b2, verts + 2 * pother, n, I);
                     int g[3] = {q, b1, b2};
-                    add_block(A, nv, rowmask, g, 3, g, 3, I, 3, fb);
+                    add_block(A, nv, rowmask, g, 3, g, 3, I, 3, fbK);
                 } else {
                     double c[2], hh;
                     centroid_h2(2, verts, cK, c, &hh);
@@ -776,7 +784,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     double X[6];
                     for (int b = 0; b < 3; ++b) { X[2 * b] = verts[2 * gK[b]]; X[2 * b + 1] = verts[2 * gK[b] + 1]; }
                     orc_bndfar2(R, s, o->k_far_bnd[cls], X, p0, p1, n, I);
-                    add_block(A, nv, rowmask, gK, 3, gK, 3, I, 3, fb);
+                    add_block(A, nv, rowmask, gK, 3, gK, 3, I, 3, fbK);
                 }
             }
         }

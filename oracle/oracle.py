@@ -240,7 +240,8 @@ class _Opts(C.Structure):
     _fields_ = [("s", C.c_double), ("k_touch", C.c_int), ("k_touch_bnd", C.c_int),
                 ("ncls", C.c_int), ("theta", C.POINTER(C.c_double)),
                 ("k_far", C.POINTER(C.c_int)), ("k_far_bnd", C.POINTER(C.c_int)),
-                ("with_boundary", C.c_int), ("which", C.c_int), ("far_skip_below", C.c_int)]
+                ("with_boundary", C.c_int), ("which", C.c_int), ("far_skip_below", C.c_int),
+                ("cell_w", C.POINTER(C.c_double))]
 
 
 def boundary_normals(dim, verts, cells, bfacets):
@@ -282,13 +283,15 @@ def dof_nodes(nv, bfacets, s, mode="paper"):
 
 
 def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None,
-                  far_skip_below=0, compact=False):
+                  far_skip_below=0, compact=False, cell_w=None):
     """Full-node matrix (nv x nv) of a(phi_i, phi_j) by the element-pair
     decomposition of Sec. 5.  ``rows``: optional vertex indices; only those
     rows are accumulated (others stay zero); with ``compact`` the result is
     just those rows (len(rows) x nv, in the order given).
     ``far_skip_below``: separated pairs of a lower order class are left out
-    (still counted).  Returns (A, class_counts)."""
+    (still counted).  ``cell_w``: optional weight per cell, a pair counting
+    with the mean of its two cells' weights (the symmetry reduction of
+    Sec. 7: 1 on the sector, 0 on its images).  Returns (A, class_counts)."""
     orders.check()
     dim = mesh["dim"]
     verts = np.ascontiguousarray(mesh["verts"], dtype=np.float64).reshape(-1)
@@ -307,9 +310,11 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     th = np.ascontiguousarray(orders.theta, dtype=np.float64)
     kf = np.ascontiguousarray(orders.k_far, dtype=np.int32)
     kb = np.ascontiguousarray(orders.k_far_bnd, dtype=np.int32)
+    cw = None if cell_w is None else np.ascontiguousarray(cell_w, dtype=np.float64)
     o = _Opts(s, orders.k_touch, orders.k_touch_bnd, len(orders.theta), _dp(th),
               kf.ctypes.data_as(C.POINTER(C.c_int)), kb.ctypes.data_as(C.POINTER(C.c_int)),
-              1 if with_boundary else 0, which, int(far_skip_below))
+              1 if with_boundary else 0, which, int(far_skip_below),
+              None if cw is None else _dp(cw))
     cnt = np.zeros(16, dtype=np.int64)
     if threads is not None:
         os.environ["OMP_NUM_THREADS"] = str(threads)

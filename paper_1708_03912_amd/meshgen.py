@@ -179,6 +179,85 @@ def disk(h: float, seed: int = 2, jitter: float = 0.15):
     return _finish(2, P, cells, bf)
 
 
+def disk_symmetric(h: float, K: int, seed: int = 2, jitter: float = 0.15):
+    """Unit-disk mesh invariant under the rotation B by 2 pi / K (K >= 2),
+    built from a sector omega = {r <= 1, 0 <= phi <= 2 pi / K} and its
+    images.  The sector holds the origin, points at radii j h on its two
+    radial edges (the second edge the image of the first), points on the
+    arc, and a jittered hexagonal lattice (numpy default_rng(seed)) kept
+    0.5 h away from the edges; Delaunay on the sector, then rotated copies
+    glued along the radial edges.  Returns (mesh, vfold, T_omega): the cells
+    of omega come first (T_omega of them, not Morton-sorted); vfold maps
+    every vertex to its representative (the omega vertex it is an image of,
+    the first radial edge standing for the second)."""
+    from scipy.spatial import Delaunay
+    assert K >= 2
+    al = 2 * math.pi / K
+    rng = np.random.default_rng(seed)
+    N = max(2, int(round(1.0 / h)))
+    r = np.arange(1, N + 1) / N                       # radii on the edges (1 = the arc's end)
+    e1 = np.stack([r, np.zeros_like(r)], 1)
+    e2 = np.stack([r * math.cos(al), r * math.sin(al)], 1)
+    nb = max(2, int(round(al / h)))
+    th = al * np.arange(1, nb) / nb
+    arc = np.stack([np.cos(th), np.sin(th)], 1)
+    ny = int(math.ceil(1.0 / (h * math.sqrt(3) / 2))) + 1
+    pts = []
+    for j in range(-ny, ny + 1):
+        y = j * h * math.sqrt(3) / 2
+        off = 0.5 * h if (j % 2) else 0.0
+        nx = int(math.ceil(1.0 / h)) + 1
+        xs = np.arange(-nx, nx + 1) * h + off
+        pts.append(np.stack([xs, np.full_like(xs, y)], 1))
+    ip = np.concatenate(pts)
+    ip = ip + rng.uniform(-jitter * h, jitter * h, size=ip.shape)
+    rr = np.hypot(ip[:, 0], ip[:, 1])
+    ph = np.mod(np.arctan2(ip[:, 1], ip[:, 0]), 2 * math.pi)
+    d1 = rr * np.sin(np.minimum(ph, math.pi / 2))      # distance to the first edge (phi < pi/2)
+    d2 = rr * np.sin(np.clip(al - ph, 0.0, math.pi / 2))
+    keep = (rr < 1.0 - 0.7 * h) & (ph < al) & (d1 > 0.5 * h) & (d2 > 0.5 * h)
+    ip = ip[keep]
+    P = np.concatenate([[[0.0, 0.0]], e1, e2, arc, ip])
+    n1 = len(e1)
+    tri = Delaunay(P)
+    cells = tri.simplices
+    a = P[cells]
+    area = 0.5 * np.abs((a[:, 1, 0] - a[:, 0, 0]) * (a[:, 2, 1] - a[:, 0, 1])
+                        - (a[:, 2, 0] - a[:, 0, 0]) * (a[:, 1, 1] - a[:, 0, 1]))
+    cells = cells[area > 1e-12 * h * h]
+    used = np.unique(cells)
+    assert len(used) == len(P), "every sector point must be a vertex"
+    # sector representatives: the second edge (indices 1 + n1 .. 2 n1) stands for the first
+    rep_s = np.arange(len(P))
+    rep_s[1 + n1:1 + 2 * n1] = np.arange(1, 1 + n1)
+    # glue K rotated copies; a vertex is keyed by its rounded coordinates.
+    # Copy i of sector point p stands for the sector vertex rep_s[p] (a
+    # vertex shared by two copies gets the same answer from both).
+    verts, vrep, key = [], {}, {}
+    cell_all = []
+    ids0 = None
+    for i in range(K):
+        c, s_ = math.cos(i * al), math.sin(i * al)
+        Q = P @ np.array([[c, s_], [-s_, c]])
+        ids = np.empty(len(P), dtype=np.int64)
+        for p in range(len(P)):
+            kk = (round(Q[p, 0] * 1e9), round(Q[p, 1] * 1e9))
+            if kk not in key:
+                key[kk] = len(verts)
+                verts.append(Q[p])
+            ids[p] = key[kk]
+        if i == 0:
+            ids0 = ids.copy()
+        for p in range(len(P)):
+            vrep[int(ids[p])] = int(ids0[rep_s[p]])
+        cell_all.append(ids[cells])
+    vrep = np.array([vrep[v] for v in range(len(verts))])
+    C = np.concatenate(cell_all)
+    V = np.array(verts)
+    bf = _boundary_edges(C)
+    return _finish(2, V, C, bf, sort=False), vrep.astype(np.int32), len(cells)
+
+
 def disk_for_cells(T: int, seed: int = 2):
     """Disk mesh with about T triangles (T ~ 7.25 / h^2)."""
     return disk(math.sqrt(7.25 / T), seed=seed)
