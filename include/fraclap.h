@@ -271,6 +271,29 @@ int fl_solve_cluster(fl_handle *h, const double *b, double *u, double rtol, int3
  * FL_ESTATE without one. */
 int fl_cluster_info(const fl_handle *h, int64_t *out);
 
+/* Symmetry reduction (Sec. 7: a rotation B with B^K = Id mapping the domain
+ * and the data to themselves).  The mesh given to fl_set_mesh is the whole
+ * symmetric mesh with the cells of the sector omega first
+ * (ncells_sector of them); vfold (host, nv int32) maps every vertex to its
+ * representative, the vertex of the sector it is an image of (vfold[r] = r
+ * for representatives; the sector's second radial edge folds onto the
+ * first).  The following assemblies then form the reduced system of the
+ * symmetric functions: DOFs are the representatives (increasing vertex
+ * order, the DOF rule of Sec. 3), every cell pair counts with the mean of
+ * its cells' weights (1 on the sector, 0 on the images: each sector cell
+ * meets every image of the other cells once, which is the effective
+ * kernel k_eff = sum_i |x - B^i y|^{-d-2s}), identical pairs and the
+ * boundary term (against the whole boundary) come from the sector's cells,
+ * and load vectors and the mass matrix integrate over the sector.  This is
+ * P^T A P / K of the full system (P: orbit sums), so a symmetric solution
+ * has the full solution's values, and the energy identity of
+ * fl_energy_error2 takes (f,u)/K.  Image-image pairs are never computed.
+ * order = 1 with ncells_sector = 0 switches the reduction off.  The cluster
+ * approximation and multigrid refuse a reduced system (FL_EINVAL).
+ * FL_EMESH for an inconsistent vfold (out of range, not idempotent, a
+ * representative outside the sector, boundary status not shared). */
+int fl_set_symmetry(fl_handle *h, int32_t order, int64_t ncells_sector, const int32_t *vfold);
+
 /* Evaluation points of the a posteriori indicators (Sec. 4: local L2
  * norms by quadrature): k_eval in 1..8 points per direction in every cell
  * (d = 2: the collapsed Gauss rule, Gauss-Jacobi(1,0) in the first

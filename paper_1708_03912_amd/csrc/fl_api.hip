@@ -302,6 +302,9 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     reset_assembly(h);
     h->dim = 0;
+    h->sym_T = 0;
+    h->sym_order = 1;
+    h->vfold.clear();
     const int nper = dim + 1;
     for (int64_t i = 0; i < nv * dim; ++i)
         if (!std::isfinite(verts[i])) return fail(h, FL_EMESH, "non-finite vertex coordinate");
@@ -389,6 +392,37 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     return FL_OK;
 }
 
+int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const int32_t* vfold) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    reset_assembly(h);
+    if (order == 1 && ncells_sector == 0) {
+        h->sym_T = 0;
+        h->sym_order = 1;
+        h->vfold.clear();
+        return FL_OK;
+    }
+    if (order < 2) return fail(h, FL_EINVAL, "order must be >= 2 (or 1 with 0 sector cells to switch off)");
+    if (ncells_sector < 1 || ncells_sector > h->nc) return fail(h, FL_EINVAL, "sector cell count out of range");
+    if (!vfold) return fail(h, FL_EINVAL, "null vfold");
+    std::vector<char> in_sector(h->nv, 0);
+    const int nper = h->dim + 1;
+    for (int64_t i = 0; i < ncells_sector * nper; ++i) in_sector[h->cells[i]] = 1;
+    for (int64_t v = 0; v < h->nv; ++v) {
+        const int32_t r = vfold[v];
+        if (r < 0 || r >= h->nv) return fail(h, FL_EMESH, "vfold entry out of range");
+        if (vfold[r] != r) return fail(h, FL_EMESH, "vfold must map onto representatives (vfold[vfold[v]] = vfold[v])");
+        if (!in_sector[r]) return fail(h, FL_EMESH, "a representative is not a vertex of the sector's cells");
+        if (h->on_boundary[v] != h->on_boundary[r])
+            return fail(h, FL_EMESH, "a vertex and its representative differ in boundary status");
+    }
+    h->vfold.assign(vfold, vfold + h->nv);
+    h->sym_T = ncells_sector;
+    h->sym_order = order;
+    return FL_OK;
+}
+
 int64_t fl_matrix_ld(const fl_handle* h) { return (h && h->assembled) ? h->lda : 0; }
 
 const double* fl_matrix_ptr(const fl_handle* h) { return (h && h->assembled) ? h->dA : nullptr; }
@@ -415,13 +449,17 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     int rc = FL_OK;
     const int dim = h->dim, nper = dim + 1;
     const int64_t T = h->nc, nv = h->nv;
+    const bool symm = h->sym_T > 0;
+    const int64_t Tw = symm ? h->sym_T : T;
     h->node2dof.assign(nv, -1);
     h->dof_node.clear();
     for (int64_t v = 0; v < nv; ++v)
-        if (all_nodes || !h->on_boundary[v]) {
+        if ((!symm || h->vfold[v] == v) && (all_nodes || !h->on_boundary[v])) {
             h->node2dof[v] = (int32_t)h->dof_node.size();
             h->dof_node.push_back((int32_t)v);
         }
+    if (symm)  // images take the DOF of their representative
+        for (int64_t v = 0; v < nv; ++v) h->node2dof[v] = h->node2dof[h->vfold[v]];
     const int64_t n = (int64_t)h->dof_node.size();
     P.T = T;
     P.nv = nv;
@@ -457,6 +495,11 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             for (int64_t K = 0; K < T; ++K)
                 key[K] = ((uint64_t)((cx[K] - lo0) / span * 4294967295.0) << 32) | (uint64_t)K;
         }
+        // with a symmetry reduction the sector's cells come first: the top
+        // bit of the position code marks an image cell (the code keeps 31 bits)
+        if (symm)
+            for (int64_t K = 0; K < T; ++K)
+                key[K] = ((((key[K] >> 33) | (K >= Tw ? 0x80000000ull : 0ull))) << 32) | (key[K] & 0xffffffffull);
         // stable LSD radix sort on the 32-bit position code (upper half of
         // the key): equal codes keep increasing K, as a sort of the key would
         std::vector<uint64_t> tmp(T);
@@ -552,9 +595,10 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             // (first-seen order: deterministic; the touching kernels add into A)
             for (int q = 0; q < ns; ++q) {
                 const int Kt = seen[q], sh = cnt[Kt];
+                if (!(dim == 2 && sh == 2) && sh != 1) { touch_ok = false; return; }
+                if (symm && Ki >= Tw && Kt >= Tw) continue;  // two images: weight 0
                 if (dim == 2 && sh == 2) { edge_pairs.push_back((int)Ki); edge_pairs.push_back(Kt); }
-                else if (sh == 1) { vert_pairs.push_back((int)Ki); vert_pairs.push_back(Kt); }
-                else { touch_ok = false; return; }
+                else { vert_pairs.push_back((int)Ki); vert_pairs.push_back(Kt); }
             }
         }
     };
@@ -583,6 +627,7 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         const bool use_far = o.k_far[o.n_classes] <= 4;
         for (int bi = 0; bi < nblk; ++bi)
             for (int bj = bi; bj < nblk; ++bj) {
+                if (symm && (int64_t)bi * BE >= Tw) continue;  // image blocks only: weight 0
                 bool far = false;
                 if (use_far && bi != bj) {
                     double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
@@ -646,6 +691,46 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             fvid[2 * e + 1] = f[1];
         }
     }
+    // symmetry reduction: cell weights (the sector's cells are the first Tw
+    // internal ones), and per-DOF (cell, local vertex) lists: over all cells
+    // for the diagonal-block scatter, over the sector for load and mass
+    std::vector<double> wcell;
+    std::vector<int> sc_ptr, sc_idx, sw_ptr, sw_idx, ident;
+    std::vector<unsigned char> sc_vloc, sw_vloc;
+    if (symm) {
+        wcell.assign(T, 0.0);
+        for (int64_t Ki = 0; Ki < Tw; ++Ki) wcell[Ki] = 1.0;
+        sc_ptr.assign(n + 1, 0);
+        sw_ptr.assign(n + 1, 0);
+        for (int64_t Ki = 0; Ki < T; ++Ki)
+            for (int a = 0; a < nper; ++a)
+                if (dof[a][Ki] >= 0) {
+                    sc_ptr[dof[a][Ki] + 1]++;
+                    if (Ki < Tw) sw_ptr[dof[a][Ki] + 1]++;
+                }
+        for (int64_t i = 0; i < n; ++i) {
+            sc_ptr[i + 1] += sc_ptr[i];
+            sw_ptr[i + 1] += sw_ptr[i];
+        }
+        sc_idx.resize(sc_ptr[n]);
+        sc_vloc.resize(sc_ptr[n]);
+        sw_idx.resize(sw_ptr[n]);
+        sw_vloc.resize(sw_ptr[n]);
+        std::vector<int> fc(sc_ptr.begin(), sc_ptr.end() - 1), fw(sw_ptr.begin(), sw_ptr.end() - 1);
+        for (int64_t Ki = 0; Ki < T; ++Ki)
+            for (int a = 0; a < nper; ++a) {
+                const int d = dof[a][Ki];
+                if (d < 0) continue;
+                sc_idx[fc[d]] = (int)Ki;
+                sc_vloc[fc[d]++] = (unsigned char)a;
+                if (Ki < Tw) {
+                    sw_idx[fw[d]] = (int)Ki;
+                    sw_vloc[fw[d]++] = (unsigned char)a;
+                }
+            }
+        ident.resize(n);
+        for (int64_t i = 0; i < n; ++i) ident[i] = (int)i;
+    }
     // pack everything into the pinned staging buffer, one copy to the device
     Packer pk;
     std::vector<size_t> offX(NC);
@@ -658,6 +743,8 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
                  o_v2ci = pk.add(v2c_idx), o_vloc = pk.add(vloc), o_n2d = pk.add(h->node2dof),
                  o_dn = pk.add(h->dof_node), o_ep = pk.add(edge_pairs), o_vp = pk.add(vert_pairs),
                  o_fac = pk.add(fac), o_fvid = pk.add(fvid);
+    const size_t o_w = pk.add(wcell), o_scp = pk.add(sc_ptr), o_sci = pk.add(sc_idx), o_scv = pk.add(sc_vloc),
+                 o_swp = pk.add(sw_ptr), o_swi = pk.add(sw_idx), o_swv = pk.add(sw_vloc), o_id = pk.add(ident);
     if (pk.total > h->pin_cap) {
         if (h->pin) (void)hipHostFree(h->pin);
         h->pin = nullptr;
@@ -683,6 +770,7 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         E.vid[a] = (const int*)dv(o_vid[a]);
         E.dof[a] = (const int*)dv(o_dof[a]);
     }
+    E.w = symm ? (const double*)dv(o_w) : nullptr;
     h->E = E;
     h->d_meas = (double*)dv(o_me);
     h->d_v2c_ptr = (int*)dv(o_v2cp);
@@ -690,6 +778,24 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
     h->d_node2dof = (int*)dv(o_n2d);
     h->d_dof_node = (int*)dv(o_dn);
     h->d_vloc = (const unsigned char*)dv(o_vloc);
+    h->d_sc_ptr = h->d_v2c_ptr;
+    h->d_sc_idx = h->d_v2c_idx;
+    h->d_sc_map = h->d_node2dof;
+    h->d_sc_vloc = h->d_vloc;
+    h->sc_rows = (int)nv;
+    if (symm) {
+        // DOF-indexed lists: the scatter owns DOF rows, load and mass sum over
+        // the sector's cells of every vertex folded onto the DOF
+        h->d_sc_ptr = (int*)dv(o_scp);
+        h->d_sc_idx = (int*)dv(o_sci);
+        h->d_sc_vloc = (const unsigned char*)dv(o_scv);
+        h->d_sc_map = (int*)dv(o_id);
+        h->sc_rows = (int)n;
+        h->d_v2c_ptr = (int*)dv(o_swp);
+        h->d_v2c_idx = (int*)dv(o_swi);
+        h->d_vloc = (const unsigned char*)dv(o_swv);
+        h->d_dof_node = (int*)dv(o_id);
+    }
     P.o_ft = o_ft; P.o_nt = o_nt; P.o_bnd = o_bnd; P.o_bdofs = o_bdofs; P.o_loc = o_loc;
     P.o_vloc = o_vloc; P.o_ep = o_ep; P.o_vp = o_vp; P.o_fac = o_fac; P.o_fvid = o_fvid;
     P.n_tiles = (long long)tiles.size();
@@ -778,7 +884,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     BP.s = s;
     BP.pe = pe;
     BP.C = C;
-    BP.T = (int)T;
+    BP.T = (int)(h->sym_T > 0 ? h->sym_T : T);  // identical pairs and boundary terms: the sector's cells
     BP.nb = (int)h->nb;
     BP.fac = (const double*)dv(o_fac);
     BP.fvid = (const int*)dv(o_fvid);
@@ -814,8 +920,8 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
-    launch_scatter_self(E, h->d_v2c_ptr, h->d_v2c_idx, h->d_node2dof, (const unsigned char*)dv(o_vloc),
-                        (int)nv, dim, dS, o.mass_shift, A, lda, h->stream);
+    launch_scatter_self(E, h->d_sc_ptr, h->d_sc_idx, h->d_sc_map, h->d_sc_vloc, h->sc_rows, dim, dS, o.mass_shift,
+                        A, lda, h->stream);
     HIPCHK(hipGetLastError());
     if (A32) {
         launch_to_f32(A, lda, n, A32, h->stream);
@@ -926,7 +1032,8 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
     // DOF map (Sec. 3): all nodes if s < 1/2 (paper rule), else interior
     const bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s < 0.5);
     int64_t n = 0;
-    for (int64_t v = 0; v < h->nv; ++v) n += (all_nodes || !h->on_boundary[v]) ? 1 : 0;
+    for (int64_t v = 0; v < h->nv; ++v)
+        n += ((h->sym_T == 0 || h->vfold[v] == v) && (all_nodes || !h->on_boundary[v])) ? 1 : 0;
     const int64_t lda = ((n + 31) / 32) * 32;
     const size_t A_bytes = sizeof(double) * (size_t)n * (size_t)lda + 8;
     if (A_bytes > h->A_cap) {
@@ -976,7 +1083,8 @@ int fl_assemble_batch(fl_handle* h, const double* s, int ns, const fl_opts* opts
     B.ns = 0;
     B.have32 = B.havehi = B.havelo = false;
     int64_t n = 0;
-    for (int64_t v = 0; v < h->nv; ++v) n += (all_nodes || !h->on_boundary[v]) ? 1 : 0;
+    for (int64_t v = 0; v < h->nv; ++v)
+        n += ((h->sym_T == 0 || h->vfold[v] == v) && (all_nodes || !h->on_boundary[v])) ? 1 : 0;
     const int64_t n_pad = std::max<int64_t>(256, ((n + 255) / 256) * 256);
     const size_t bytes = sizeof(double) * (size_t)ns * (size_t)n_pad * (size_t)n_pad;
     if (bytes > B.A64_cap) {

@@ -815,7 +815,7 @@ __global__ void load_fourier_kernel(LoadArgs a) {
 __global__ void load_nodal_kernel(LoadArgs a) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const int v = a.dof_node[i];
+    const int v = a.dof_node[i];  // owner of the (cell, local vertex) list
     const int nper = a.dim + 1;
     const double den = a.dim == 2 ? 12.0 : 6.0;
     for (int c = 0; c < a.nrhs; ++c) {
@@ -825,7 +825,9 @@ __global__ void load_nodal_kernel(LoadArgs a) {
             const int K = a.v2c_idx[e];
             double sum = 0.0;
             for (int b = 0; b < nper; ++b) sum += f[a.E.vid[b][K]];
-            s += a.meas[K] / den * (sum + f[v]);
+            // the hat function's own vertex (v itself, or its image under a
+            // symmetry reduction)
+            s += a.meas[K] / den * (sum + f[a.E.vid[a.vloc[e]][K]]);
         }
         a.b[(long long)c * a.n + i] = s;
     }

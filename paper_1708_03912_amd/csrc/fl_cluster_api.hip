@@ -95,6 +95,7 @@ extern "C" {
 int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
     if (!h) return FL_EINVAL;
     if (!h->assembled) return cfail(h, FL_ESTATE, "no assembled matrix (fl_assemble)");
+    if (h->sym_T > 0) return cfail(h, FL_EINVAL, "the cluster approximation does not take a symmetry reduction");
     if (m < 1 || m > 15) return cfail(h, FL_EINVAL, "m must lie in 1..15");
     if (!(eta > 0.0) || !std::isfinite(eta)) return cfail(h, FL_EINVAL, "eta must be positive and finite");
     if (leaf < 1 || leaf > 1024) return cfail(h, FL_EINVAL, "leaf must lie in 1..1024");

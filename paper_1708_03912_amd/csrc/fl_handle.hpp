@@ -134,6 +134,11 @@ struct fl_handle {
     std::vector<int32_t> cells, bfacets;
     std::vector<int32_t> facet_opp;     // vertex of the owning cell opposite the facet
     std::vector<char> on_boundary;
+    // symmetry reduction (fl_set_symmetry): cells [0, sym_T) form the sector,
+    // vfold maps every vertex to its representative; sym_T = 0: none
+    int64_t sym_T = 0;
+    int sym_order = 1;
+    std::vector<int32_t> vfold;
 
     // assembly
     bool assembled = false;   // single matrix (fl_assemble) present
@@ -163,6 +168,13 @@ struct fl_handle {
     int* d_node2dof = nullptr;
     int* d_dof_node = nullptr;
     const unsigned char* d_vloc = nullptr;  // local index of the vertex in each v2c entry
+    // rows of the diagonal-block scatter: per row owner (vertex, or DOF with a
+    // symmetry reduction) its (cell, local vertex) entries and its DOF
+    const int* d_sc_ptr = nullptr;
+    const int* d_sc_idx = nullptr;
+    const int* d_sc_map = nullptr;
+    const unsigned char* d_sc_vloc = nullptr;
+    int sc_rows = 0;
     double* d_meas = nullptr;
 
     // solver workspace

@@ -47,6 +47,8 @@ struct ElemDev {
     const double* meas;     // |K|
     const int* vid[3];      // vertex ids
     const int* dof[3];      // DOF ids, -1 if the vertex is not a DOF
+    const double* w;        // weight per cell (symmetry reduction: 1 on the sector, 0 on its
+                            // images; a pair counts with the mean of its two cells), or null
 };
 
 // Learned surrogate for the separated pairs of the closest classes: the

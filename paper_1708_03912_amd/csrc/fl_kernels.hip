@@ -31,6 +31,11 @@ __device__ __forceinline__ int sym3(int a, int b) {
     return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
 }
 
+// weight of the cell pair (K, Kt) in a symmetry-reduced assembly (1 without)
+__device__ __forceinline__ double pair_w(const ElemDev& E, int K, int Kt) {
+    return E.w ? 0.5 * (E.w[K] + E.w[Kt]) : 1.0;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 }
             }
         }
-        const double f = valid ? P.C * mk * mt : 0.0;
+        const double f = valid ? P.C * mk * mt * pair_w(E, K, Kt) : 0.0;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             SK[m] *= f;
@@ -936,7 +941,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
             const double* BT = swap ? SK : ST;
             const int* pK = swap ? o2 : o1;
             const int* pT = swap ? o1 : o2;
-            const double fct = P.C * sI[9][r] * sJ[9][l];
+            const double fct = P.C * sI[9][r] * sJ[9][l] * pair_w(E, I0 + r, J0 + l);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -996,7 +1001,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                 if constexpr (TAB) far_pair<DIM, MIX>(k, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
                 else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
             }
-            const double f = P.C * sI[9][r] * sJ[9][l];
+            const double f = P.C * sI[9][r] * sJ[9][l] * pair_w(E, I0 + r, J0 + l);
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 if (SK[m] != 0.0) atomicAdd(&SI[r * 6 + m], f * SK[m]);
@@ -1368,8 +1373,9 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
         if (ntouch) atomicAdd(&P.counters[0], ntouch);
         if (nfar) atomicAdd(&P.counters[1], nfar);
     }
+    const double wk = E.w ? E.w[K] : 1.0;
     for (int m = 0; m < 6; ++m)
-        if (acc[m] != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], acc[m]);
+        if (acc[m] != 0.0 && wk != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], wk * acc[m]);
 }
 
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st) {
@@ -1453,7 +1459,7 @@ __global__ __launch_bounds__(256) void touch_edge2_kernel(ElemDev E, TouchParams
     }
     const double Cm[4][3] = {{-1, 1, -1}, {0, 0, 1}, {1, 0, 0}, {0, -1, 0}};
     double aK = E.meas[K], aT = E.meas[Kt];
-    double f = P.C * 4.0 * aK * aT / ((3.0 - 2.0 * P.s) * (4.0 - 2.0 * P.s));
+    double f = P.C * 4.0 * aK * aT / ((3.0 - 2.0 * P.s) * (4.0 - 2.0 * P.s)) * pair_w(E, K, Kt);
     int g[4] = {E.dof[sk[0]][K], E.dof[sk[1]][K], E.dof[ia][K], E.dof[ib][Kt]};
     for (int i = 0; i < 4; ++i) {
         if (g[i] < 0) continue;
@@ -1498,7 +1504,7 @@ __global__ __launch_bounds__(256) void touch_vert_kernel(ElemDev E, TouchParams 
                 for (int p = 0; p < 3; ++p)
                     for (int q = p; q < 3; ++q) M[sym3(p, q)] += kv * N[p] * N[q];
             }
-        double f = P.C * h1 * h2 / (3.0 - 2.0 * P.s);
+        double f = P.C * h1 * h2 / (3.0 - 2.0 * P.s) * pair_w(E, K, Kt);
         int g[3] = {E.dof[1 - a][K], E.dof[a][K], E.dof[1 - b][Kt]};
         for (int i = 0; i < 3; ++i) {
             if (g[i] < 0) continue;
@@ -1552,7 +1558,7 @@ __global__ __launch_bounds__(256) void touch_vert_kernel(ElemDev E, TouchParams 
             for (int q = p; q < 4; ++q) { F[p][q] = M[m]; F[q][p] = M[m]; ++m; }
     }
     const double Cm[5][4] = {{-1, -1, 1, 1}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, -1, 0}, {0, 0, 0, -1}};
-    double f = P.C * 4.0 * E.meas[K] * E.meas[Kt] / (4.0 - 2.0 * P.s);
+    double f = P.C * 4.0 * E.meas[K] * E.meas[Kt] / (4.0 - 2.0 * P.s) * pair_w(E, K, Kt);
     int g[5] = {E.dof[a][K], E.dof[i1][K], E.dof[i2][K], E.dof[j1][Kt], E.dof[j2][Kt]};
     for (int i = 0; i < 5; ++i) {
         if (g[i] < 0) continue;
@@ -1605,7 +1611,7 @@ __global__ __launch_bounds__(256) void scatter_self_kernel(ElemDev E, const int*
     for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
         const int K = v2c_idx[e];
         const int a = vloc[e];
-        const double mk = mass * E.meas[K];
+        const double mk = mass * E.meas[K] * (E.w ? E.w[K] : 1.0);
         for (int b = 0; b <= dim; ++b) {
             int j = E.dof[b][K];
             if (j < 0) continue;

@@ -95,6 +95,7 @@ void fl_mg_free(fl_handle* h) {
 extern "C" {
 
 int fl_mg_setup(fl_handle* h, int nlevels, const int64_t* nv, const int32_t* parents) {
+    if (h && h->sym_T > 0) return mfail(h, FL_EINVAL, "multigrid does not take a symmetry reduction");
     if (!h) return FL_EINVAL;
     if (!h->assembled || h->B.ns > 0) return mfail(h, FL_ESTATE, "fl_mg_setup needs a matrix from fl_assemble");
     if (nlevels < 2 || nlevels > 16 || !nv || !parents) return mfail(h, FL_EINVAL, "2..16 levels and arrays required");

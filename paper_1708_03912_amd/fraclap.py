@@ -38,7 +38,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
            "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
-           "fl_solve_cluster", "fl_cluster_info"]
+           "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -111,6 +111,7 @@ def lib():
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
         L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
         L.fl_cluster_build.argtypes = [vp, C.c_int32, dp, C.c_int32]
+        L.fl_set_symmetry.argtypes = [vp, C.c_int32, i64, vp]
         L.fl_cluster_matvec.argtypes = [vp, vp, vp]
         L.fl_solve_cluster.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_cluster_info.argtypes = [vp, vp]
@@ -305,6 +306,13 @@ class Handle:
         """eta_K^2 into eta_cell (nc), their vertex sums into eta_node (nv)."""
         self._check(lib().fl_indicators(self.h, s, _ptr(Lu), None if f is None else _ptr(f), k_eval,
                                         _ptr(eta_cell), None if eta_node is None else _ptr(eta_node)))
+
+    def set_symmetry(self, order, ncells_sector, vfold):
+        """Symmetry reduction: sector cells first in the mesh, vfold the
+        representative of every vertex; order 1 with 0 cells switches it off."""
+        import numpy as np
+        vf = np.ascontiguousarray(vfold, dtype=np.int32)
+        self._check(lib().fl_set_symmetry(self.h, order, ncells_sector, vf.ctypes.data_as(C.c_void_p)))
 
     def cluster_build(self, m=6, eta=2.0, leaf=32):
         """Cluster approximation of the assembled matrix (order m, admissibility eta)."""
