@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--no-cluster", action="store_true",
                     help="skip the cluster leg (H-matrix approximation of disks of ~8k / 32k / 128k triangles)")
     ap.add_argument("--only-cluster", action="store_true", help="run only the cluster leg and print its object")
+    ap.add_argument("--no-symmetry", action="store_true",
+                    help="skip the symmetry leg (8-fold symmetric disk, reduced vs full system)")
+    ap.add_argument("--only-symmetry", action="store_true", help="run only the symmetry leg and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -129,6 +132,11 @@ def main():
         import torch
         torch.cuda.init()
         print(json.dumps({"indicators": indicators_leg(args)}), flush=True)
+        return
+    if args.only_symmetry:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({"symmetry": symmetry_leg(args)}), flush=True)
         return
     if args.only_cluster:
         import torch
@@ -278,6 +286,8 @@ def main():
         out["indicators"] = indicators_leg(args)
     if not args.no_cluster:
         out["cluster"] = cluster_leg(args)
+    if not args.no_symmetry:
+        out["symmetry"] = symmetry_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
     print(json.dumps(out), flush=True)
@@ -876,6 +886,52 @@ def cluster_leg(args):
             "matvec_cluster_ms": round(t_h, 4), "rel_err": err, "cg_dense": [itd, round((t1 - t0) * 1e3, 2)],
             "cg_cluster": [ith, round((t2 - t1) * 1e3, 2)]}
         h.close()
+    return out
+
+
+def symmetry_leg(args):
+    """Symmetry reduction (Sec. 7): a unit disk invariant under rotations by
+    2 pi / 8 (~32k triangles), s = 0.75, f = 1: the full system against the
+    reduced one (sector against all images): DOFs, separated pairs,
+    assembly and CG times, and the largest gap between the two solutions
+    at the representatives."""
+    import numpy as np
+    import torch
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    K = 8
+    mesh, vfold, Tw = M.disk_symmetric(0.0152, K, seed=2)
+    out = {"workload": f"unit disk, {len(mesh['cells'])} triangles invariant under rotation by 2pi/{K} "
+                       f"(sector of {Tw}), s=0.75, f=1, CG to 1e-10"}
+    res = {}
+    for name, sym in (("full", False), ("reduced", True)):
+        h = F.Handle(0)
+        h.set_mesh(mesh)
+        if sym:
+            h.set_symmetry(K, Tw, vfold)
+        n = h.assemble(0.75)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = h.assemble(0.75)
+        torch.cuda.synchronize()
+        t_asm = (time.perf_counter() - t0) * 1e3
+        st = h.stats()
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        h.load_vector_one(b)
+        u = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, _, _ = h.solve(b, u, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_cg = (time.perf_counter() - t0) * 1e3
+        res[name] = (h.dofs(), u.cpu().numpy())
+        out[name] = {"n": n, "separated_pairs": int(sum(st.pairs_far)), "assembly_ms": round(t_asm, 2),
+                     "cg_iters": it, "cg_ms": round(t_cg, 2)}
+        h.close()
+    dof_f, uf = res["full"]
+    dof_r, ur = res["reduced"]
+    pos = np.searchsorted(dof_f, dof_r)
+    out["max_gap_rel"] = float(np.abs(ur - uf[pos]).max() / np.abs(uf).max())
+    out["assembly_speedup"] = round(out["full"]["assembly_ms"] / out["reduced"]["assembly_ms"], 2)
     return out
 
 
