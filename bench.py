@@ -899,7 +899,7 @@ def symmetry_leg(args):
     import torch
     from paper_1708_03912_amd import fraclap as F, meshgen as M
     K = 8
-    mesh, vfold, Tw = M.disk_symmetric(0.0152, K, seed=2)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.0152, K, seed=2)
     out = {"workload": f"unit disk, {len(mesh['cells'])} triangles invariant under rotation by 2pi/{K} "
                        f"(sector of {Tw}), s=0.75, f=1, CG to 1e-10"}
     res = {}
@@ -907,7 +907,7 @@ def symmetry_leg(args):
         h = F.Handle(0)
         h.set_mesh(mesh)
         if sym:
-            h.set_symmetry(K, Tw, vfold)
+            h.set_symmetry(K, Tw, vfold, pre, rot)
         n = h.assemble(0.75)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

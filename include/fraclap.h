@@ -288,11 +288,18 @@ int fl_cluster_info(const fl_handle *h, int64_t *out);
  * P^T A P / K of the full system (P: orbit sums), so a symmetric solution
  * has the full solution's values, and the energy identity of
  * fl_energy_error2 takes (f,u)/K.  Image-image pairs are never computed.
+ * cell_pre / cell_rot (host, nc int32 each, or both NULL): the sector cell
+ * every cell is an image of and the rotation index i with cell = B^i pre
+ * (sector cells: themselves, 0).  With them the two equal cross pairs
+ * (S, B^i T) and (T, B^-i S) are formed once with weight 1 (about 1/K of
+ * the full mesh's pairs instead of 2/K), and the sector is kept in the
+ * caller's order.
  * order = 1 with ncells_sector = 0 switches the reduction off.  The cluster
  * approximation and multigrid refuse a reduced system (FL_EINVAL).
  * FL_EMESH for an inconsistent vfold (out of range, not idempotent, a
  * representative outside the sector, boundary status not shared). */
-int fl_set_symmetry(fl_handle *h, int32_t order, int64_t ncells_sector, const int32_t *vfold);
+int fl_set_symmetry(fl_handle *h, int32_t order, int64_t ncells_sector, const int32_t *vfold,
+                    const int32_t *cell_pre, const int32_t *cell_rot);
 
 /* Evaluation points of the a posteriori indicators (Sec. 4: local L2
  * norms by quadrature): k_eval in 1..8 points per direction in every cell

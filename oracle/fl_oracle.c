@@ -583,7 +583,30 @@ typedef struct {
                               with (w_K + w_Kt) / 2 (identical pairs and the
                               boundary term with w_K), pairs of weight 0 are
                               skipped (symmetry reduction, Sec. 7) */
+    const int *cell_pre;   /* with cell_w: NULL, or for every cell the sector
+                              cell it is an image of, and ... */
+    const int *cell_rot;   /* ... the rotation B^i that maps it there; then
+                              of the two equal cross pairs (S, B^i T) and
+                              (T, B^-i S) only one counts, with weight 1 */
+    int sym_order;         /* K, the order of B */
 } orc_opts;
+
+/* Weight of the cell pair (K, Kt) in a symmetry-reduced assembly: pairs of
+ * sector cells 1, pairs of images 0; a sector cell S with an image L of
+ * the sector cell p = pre(L) under B^i: without pre/rot 1/2 (both members
+ * of each couple (S, B^i p) ~ (p, B^-i S) are present), with them 1 for
+ * p > S, 0 for p < S, and for p = S 1 if 2 i < K, 1/2 if 2 i = K, 0 else. */
+static double pair_weight(const orc_opts *o, int64_t K, int64_t Kt) {
+    if (!o->cell_w) return 1.0;
+    const double wK = o->cell_w[K], wT = o->cell_w[Kt];
+    if (!o->cell_pre) return 0.5 * (wK + wT);
+    if (wK == wT) return wK;
+    const int64_t S = wK > wT ? K : Kt, L = wK > wT ? Kt : K;
+    const int64_t p = o->cell_pre[L];
+    if (p != S) return p > S ? 1.0 : 0.0;
+    const int r2 = 2 * o->cell_rot[L];
+    return r2 < o->sym_order ? 1.0 : (r2 == o->sym_order ? 0.5 : 0.0);
+}
 
 static double cdn(int dim, double s) {
     /* C(d,s) = 2^{2s} s Gamma(s+d/2) / (pi^{d/2} Gamma(1-s)) */
@@ -633,7 +656,7 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
         const int32_t *cK = cells + nper * K;
         for (int64_t Kt = K; Kt < nc; ++Kt) {
             if (!hit[K] && !hit[Kt]) continue;
-            const double wp = o->cell_w ? 0.5 * (o->cell_w[K] + o->cell_w[Kt]) : 1.0;
+            const double wp = pair_weight(o, K, Kt);
             if (wp == 0.0) continue;
             const int32_t *cT = cells + nper * Kt;
             int gK[3], gT[3];

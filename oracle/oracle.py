@@ -241,7 +241,8 @@ class _Opts(C.Structure):
                 ("ncls", C.c_int), ("theta", C.POINTER(C.c_double)),
                 ("k_far", C.POINTER(C.c_int)), ("k_far_bnd", C.POINTER(C.c_int)),
                 ("with_boundary", C.c_int), ("which", C.c_int), ("far_skip_below", C.c_int),
-                ("cell_w", C.POINTER(C.c_double))]
+                ("cell_w", C.POINTER(C.c_double)), ("cell_pre", C.POINTER(C.c_int)),
+                ("cell_rot", C.POINTER(C.c_int)), ("sym_order", C.c_int)]
 
 
 def boundary_normals(dim, verts, cells, bfacets):
@@ -283,7 +284,7 @@ def dof_nodes(nv, bfacets, s, mode="paper"):
 
 
 def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None,
-                  far_skip_below=0, compact=False, cell_w=None):
+                  far_skip_below=0, compact=False, cell_w=None, cell_pre=None, cell_rot=None, sym_order=0):
     """Full-node matrix (nv x nv) of a(phi_i, phi_j) by the element-pair
     decomposition of Sec. 5.  ``rows``: optional vertex indices; only those
     rows are accumulated (others stay zero); with ``compact`` the result is
@@ -291,7 +292,10 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     ``far_skip_below``: separated pairs of a lower order class are left out
     (still counted).  ``cell_w``: optional weight per cell, a pair counting
     with the mean of its two cells' weights (the symmetry reduction of
-    Sec. 7: 1 on the sector, 0 on its images).  Returns (A, class_counts)."""
+    Sec. 7: 1 on the sector, 0 on its images); with ``cell_pre`` /
+    ``cell_rot`` (preimage sector cell and rotation index of every cell) and
+    ``sym_order`` only one of each equal couple of cross pairs counts, with
+    weight 1 (see pair_weight in fl_oracle.c).  Returns (A, class_counts)."""
     orders.check()
     dim = mesh["dim"]
     verts = np.ascontiguousarray(mesh["verts"], dtype=np.float64).reshape(-1)
@@ -311,10 +315,14 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     kf = np.ascontiguousarray(orders.k_far, dtype=np.int32)
     kb = np.ascontiguousarray(orders.k_far_bnd, dtype=np.int32)
     cw = None if cell_w is None else np.ascontiguousarray(cell_w, dtype=np.float64)
+    cpre = None if cell_pre is None else np.ascontiguousarray(cell_pre, dtype=np.int32)
+    crot = None if cell_rot is None else np.ascontiguousarray(cell_rot, dtype=np.int32)
     o = _Opts(s, orders.k_touch, orders.k_touch_bnd, len(orders.theta), _dp(th),
               kf.ctypes.data_as(C.POINTER(C.c_int)), kb.ctypes.data_as(C.POINTER(C.c_int)),
               1 if with_boundary else 0, which, int(far_skip_below),
-              None if cw is None else _dp(cw))
+              None if cw is None else _dp(cw),
+              None if cpre is None else cpre.ctypes.data_as(C.POINTER(C.c_int)),
+              None if crot is None else crot.ctypes.data_as(C.POINTER(C.c_int)), int(sym_order))
     cnt = np.zeros(16, dtype=np.int64)
     if threads is not None:
         os.environ["OMP_NUM_THREADS"] = str(threads)

@@ -45,14 +45,17 @@ def reduce(A_full, b_full, dofs_full, vfold, K):
     return P.T @ A_full @ P / K, P.T @ b_full / K, red
 
 
-def assemble_reduced(mesh, s, orders, vfold, T_omega, mode="paper"):
+def assemble_reduced(mesh, s, orders, vfold, T_omega, mode="paper", pre=None, rot=None, K=0):
     """Reduced matrix (representative DOFs, increasing vertex order) by the
-    weighted pair sum over the full mesh (sector cells first)."""
+    weighted pair sum over the full mesh (sector cells first).  With pre /
+    rot / K (preimage sector cell and rotation index of every cell) one
+    member of each equal couple of cross pairs (S, B^i T) ~ (T, B^-i S)
+    counts, with weight 1."""
     nv = len(mesh["verts"])
     T = len(mesh["cells"])
     w = np.zeros(T)
     w[:T_omega] = 1.0
-    An, cnt = O.assemble_full(mesh, s, orders, cell_w=w)
+    An, cnt = O.assemble_full(mesh, s, orders, cell_w=w, cell_pre=pre, cell_rot=rot, sym_order=K)
     vfold = np.asarray(vfold)
     dofs = O.dof_nodes(nv, mesh["bfacets"], s, mode)
     red = np.unique(vfold[dofs])

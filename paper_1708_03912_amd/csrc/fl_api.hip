@@ -305,6 +305,8 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     h->sym_T = 0;
     h->sym_order = 1;
     h->vfold.clear();
+    h->sym_pre.clear();
+    h->sym_rot.clear();
     const int nper = dim + 1;
     for (int64_t i = 0; i < nv * dim; ++i)
         if (!std::isfinite(verts[i])) return fail(h, FL_EMESH, "non-finite vertex coordinate");
@@ -392,11 +394,14 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     return FL_OK;
 }
 
-int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const int32_t* vfold) {
+int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const int32_t* vfold,
+                    const int32_t* cell_pre, const int32_t* cell_rot) {
     if (!h) return FL_EINVAL;
     if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     reset_assembly(h);
+    h->sym_pre.clear();
+    h->sym_rot.clear();
     if (order == 1 && ncells_sector == 0) {
         h->sym_T = 0;
         h->sym_order = 1;
@@ -416,6 +421,28 @@ int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const in
         if (!in_sector[r]) return fail(h, FL_EMESH, "a representative is not a vertex of the sector's cells");
         if (h->on_boundary[v] != h->on_boundary[r])
             return fail(h, FL_EMESH, "a vertex and its representative differ in boundary status");
+    }
+    if ((cell_pre == nullptr) != (cell_rot == nullptr)) return fail(h, FL_EINVAL, "cell_pre and cell_rot go together");
+    if (cell_pre) {
+        for (int64_t K = 0; K < h->nc; ++K) {
+            const int32_t p = cell_pre[K], r = cell_rot[K];
+            if (p < 0 || p >= ncells_sector || r < 0 || r >= order)
+                return fail(h, FL_EMESH, "cell_pre / cell_rot entry out of range");
+            if ((K < ncells_sector) != (r == 0) || (K < ncells_sector && p != K))
+                return fail(h, FL_EMESH, "sector cells must be their own preimage with rotation 0, images not");
+            // an image and its preimage fold onto the same vertices
+            int a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+            for (int j = 0; j <= h->dim; ++j) {
+                a[j] = vfold[h->cells[(h->dim + 1) * K + j]];
+                b[j] = vfold[h->cells[(h->dim + 1) * (int64_t)p + j]];
+            }
+            std::sort(a, a + h->dim + 1);
+            std::sort(b, b + h->dim + 1);
+            for (int j = 0; j <= h->dim; ++j)
+                if (a[j] != b[j]) return fail(h, FL_EMESH, "a cell and its preimage fold onto different vertices");
+        }
+        h->sym_pre.assign(cell_pre, cell_pre + h->nc);
+        h->sym_rot.assign(cell_rot, cell_rot + h->nc);
     }
     h->vfold.assign(vfold, vfold + h->nv);
     h->sym_T = ncells_sector;
@@ -513,6 +540,19 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
             key.swap(tmp);
         }
         for (int64_t K = 0; K < T; ++K) perm[K] = (int32_t)(key[K] & 0xffffffffu);
+        if (symm && !h->sym_pre.empty()) {
+            // the sector in the caller's order (internal index = caller
+            // index, which the pair weights compare), then the images by
+            // (rotation, preimage): the cross pairs that count sit on one
+            // side of the block diagonal of each image copy
+            for (int64_t K = 0; K < Tw; ++K) perm[K] = (int32_t)K;
+            std::vector<int32_t> img;
+            for (int64_t K = Tw; K < T; ++K) img.push_back((int32_t)K);
+            std::stable_sort(img.begin(), img.end(), [&](int32_t a, int32_t b) {
+                return h->sym_rot[a] != h->sym_rot[b] ? h->sym_rot[a] < h->sym_rot[b] : h->sym_pre[a] < h->sym_pre[b];
+            });
+            for (size_t k = 0; k < img.size(); ++k) perm[Tw + k] = img[k];
+        }
     }
     // element SoA in internal order
     const int NC = nper * dim;
@@ -625,9 +665,19 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         double th_last2 = 4.0;
         if (o.n_classes > 0) th_last2 = std::max(4.0, o.theta[o.n_classes - 1] * o.theta[o.n_classes - 1]);
         const bool use_far = o.k_far[o.n_classes] <= 4;
+        // with preimage data: the largest preimage among a block's image
+        // cells; a tile of sector cells against image cells whose preimages
+        // all come before the sector cells has weight 0 throughout
+        std::vector<int> bmaxpre(nblk, -1);
+        if (symm && !h->sym_pre.empty())
+            for (int64_t Ki = Tw; Ki < T; ++Ki)
+                bmaxpre[Ki / BE] = std::max(bmaxpre[Ki / BE], (int)h->sym_pre[perm[Ki]]);
         for (int bi = 0; bi < nblk; ++bi)
             for (int bj = bi; bj < nblk; ++bj) {
                 if (symm && (int64_t)bi * BE >= Tw) continue;  // image blocks only: weight 0
+                if (symm && !h->sym_pre.empty() && (int64_t)(bi + 1) * BE <= Tw && (int64_t)bj * BE >= Tw &&
+                    bmaxpre[bj] < bi * BE)
+                    continue;
                 bool far = false;
                 if (use_far && bi != bj) {
                     double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
@@ -743,6 +793,16 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
                  o_v2ci = pk.add(v2c_idx), o_vloc = pk.add(vloc), o_n2d = pk.add(h->node2dof),
                  o_dn = pk.add(h->dof_node), o_ep = pk.add(edge_pairs), o_vp = pk.add(vert_pairs),
                  o_fac = pk.add(fac), o_fvid = pk.add(fvid);
+    std::vector<int> spre, srot;
+    if (symm && !h->sym_pre.empty()) {
+        spre.resize(T);
+        srot.resize(T);
+        for (int64_t Ki = 0; Ki < T; ++Ki) {
+            spre[Ki] = Ki < Tw ? -1 : h->sym_pre[perm[Ki]];
+            srot[Ki] = Ki < Tw ? 0 : h->sym_rot[perm[Ki]];
+        }
+    }
+    const size_t o_spre = pk.add(spre), o_srot = pk.add(srot);
     const size_t o_w = pk.add(wcell), o_scp = pk.add(sc_ptr), o_sci = pk.add(sc_idx), o_scv = pk.add(sc_vloc),
                  o_swp = pk.add(sw_ptr), o_swi = pk.add(sw_idx), o_swv = pk.add(sw_vloc), o_id = pk.add(ident);
     if (pk.total > h->pin_cap) {
@@ -771,6 +831,9 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         E.dof[a] = (const int*)dv(o_dof[a]);
     }
     E.w = symm ? (const double*)dv(o_w) : nullptr;
+    E.spre = (symm && !h->sym_pre.empty()) ? (const int*)dv(o_spre) : nullptr;
+    E.srot = (symm && !h->sym_pre.empty()) ? (const int*)dv(o_srot) : nullptr;
+    E.sorder = h->sym_order;
     h->E = E;
     h->d_meas = (double*)dv(o_me);
     h->d_v2c_ptr = (int*)dv(o_v2cp);

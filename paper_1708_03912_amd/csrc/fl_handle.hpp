@@ -139,6 +139,7 @@ struct fl_handle {
     int64_t sym_T = 0;
     int sym_order = 1;
     std::vector<int32_t> vfold;
+    std::vector<int32_t> sym_pre, sym_rot;  // preimage sector cell and rotation of every cell, or empty
 
     // assembly
     bool assembled = false;   // single matrix (fl_assemble) present

@@ -49,6 +49,9 @@ struct ElemDev {
     const int* dof[3];      // DOF ids, -1 if the vertex is not a DOF
     const double* w;        // weight per cell (symmetry reduction: 1 on the sector, 0 on its
                             // images; a pair counts with the mean of its two cells), or null
+    const int* spre;        // with w: null, or per cell the preimage sector cell (-1 on the
+    const int* srot;        // sector) and the rotation index: one member of each equal couple
+    int sorder;             // of cross pairs counts (weight 1); sorder = K
 };
 
 // Learned surrogate for the separated pairs of the closest classes: the

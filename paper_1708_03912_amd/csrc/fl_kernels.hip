@@ -31,9 +31,22 @@ __device__ __forceinline__ int sym3(int a, int b) {
     return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
 }
 
-// weight of the cell pair (K, Kt) in a symmetry-reduced assembly (1 without)
+// Weight of the cell pair (K, Kt) in a symmetry-reduced assembly (1
+// without one): sector pairs 1, image pairs 0; a sector cell S (internal
+// index = its caller index) with an image L of the sector cell p under
+// B^i: 1/2 without preimage data (both members of each couple
+// (S, B^i p) ~ (p, B^-i S) are present), with it 1 for p > S, 0 for p < S,
+// and for p = S 1 if 2 i < K, 1/2 if 2 i = K, 0 else.
 __device__ __forceinline__ double pair_w(const ElemDev& E, int K, int Kt) {
-    return E.w ? 0.5 * (E.w[K] + E.w[Kt]) : 1.0;
+    if (!E.w) return 1.0;
+    const double wK = E.w[K], wT = E.w[Kt];
+    if (!E.spre) return 0.5 * (wK + wT);
+    if (wK == wT) return wK;
+    const int S = wK > wT ? K : Kt, L = wK > wT ? Kt : K;
+    const int p = E.spre[L];
+    if (p != S) return p > S ? 1.0 : 0.0;
+    const int r2 = 2 * E.srot[L];
+    return r2 < E.sorder ? 1.0 : (r2 == E.sorder ? 0.5 : 0.0);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

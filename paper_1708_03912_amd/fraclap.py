@@ -111,7 +111,7 @@ def lib():
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
         L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
         L.fl_cluster_build.argtypes = [vp, C.c_int32, dp, C.c_int32]
-        L.fl_set_symmetry.argtypes = [vp, C.c_int32, i64, vp]
+        L.fl_set_symmetry.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
         L.fl_cluster_matvec.argtypes = [vp, vp, vp]
         L.fl_solve_cluster.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_cluster_info.argtypes = [vp, vp]
@@ -307,12 +307,17 @@ class Handle:
         self._check(lib().fl_indicators(self.h, s, _ptr(Lu), None if f is None else _ptr(f), k_eval,
                                         _ptr(eta_cell), None if eta_node is None else _ptr(eta_node)))
 
-    def set_symmetry(self, order, ncells_sector, vfold):
+    def set_symmetry(self, order, ncells_sector, vfold, pre=None, rot=None):
         """Symmetry reduction: sector cells first in the mesh, vfold the
-        representative of every vertex; order 1 with 0 cells switches it off."""
+        representative of every vertex, optionally every cell's preimage and
+        rotation index; order 1 with 0 cells switches it off."""
         import numpy as np
         vf = np.ascontiguousarray(vfold, dtype=np.int32)
-        self._check(lib().fl_set_symmetry(self.h, order, ncells_sector, vf.ctypes.data_as(C.c_void_p)))
+        pr = None if pre is None else np.ascontiguousarray(pre, dtype=np.int32)
+        ro = None if rot is None else np.ascontiguousarray(rot, dtype=np.int32)
+        self._check(lib().fl_set_symmetry(self.h, order, ncells_sector, vf.ctypes.data_as(C.c_void_p),
+                                          None if pr is None else pr.ctypes.data_as(C.c_void_p),
+                                          None if ro is None else ro.ctypes.data_as(C.c_void_p)))
 
     def cluster_build(self, m=6, eta=2.0, leaf=32):
         """Cluster approximation of the assembled matrix (order m, admissibility eta)."""

@@ -186,10 +186,12 @@ def disk_symmetric(h: float, K: int, seed: int = 2, jitter: float = 0.15):
     radial edges (the second edge the image of the first), points on the
     arc, and a jittered hexagonal lattice (numpy default_rng(seed)) kept
     0.5 h away from the edges; Delaunay on the sector, then rotated copies
-    glued along the radial edges.  Returns (mesh, vfold, T_omega): the cells
-    of omega come first (T_omega of them, not Morton-sorted); vfold maps
-    every vertex to its representative (the omega vertex it is an image of,
-    the first radial edge standing for the second)."""
+    glued along the radial edges.  Returns (mesh, vfold, T_omega, pre, rot):
+    the cells of omega come first (T_omega of them, in Morton order); copy i
+    of sector cell c follows as cell i T_omega + c, with pre = c and rot = i
+    (pre = c, rot = 0 on the sector); vfold maps every vertex to its
+    representative (the omega vertex it is an image of, the first radial
+    edge standing for the second)."""
     from scipy.spatial import Delaunay
     assert K >= 2
     al = 2 * math.pi / K
@@ -227,6 +229,9 @@ def disk_symmetric(h: float, K: int, seed: int = 2, jitter: float = 0.15):
     cells = cells[area > 1e-12 * h * h]
     used = np.unique(cells)
     assert len(used) == len(P), "every sector point must be a vertex"
+    # sector cells along a Morton curve of their centroids (spatially
+    # coherent order; the images keep it)
+    cells = cells[np.argsort(_morton_key(P[cells].mean(1)), kind="stable")]
     # sector representatives: the second edge (indices 1 + n1 .. 2 n1) stands for the first
     rep_s = np.arange(len(P))
     rep_s[1 + n1:1 + 2 * n1] = np.arange(1, 1 + n1)
@@ -255,7 +260,10 @@ def disk_symmetric(h: float, K: int, seed: int = 2, jitter: float = 0.15):
     C = np.concatenate(cell_all)
     V = np.array(verts)
     bf = _boundary_edges(C)
-    return _finish(2, V, C, bf, sort=False), vrep.astype(np.int32), len(cells)
+    Tw = len(cells)
+    pre = np.tile(np.arange(Tw), K).astype(np.int32)
+    rot = np.repeat(np.arange(K), Tw).astype(np.int32)
+    return _finish(2, V, C, bf, sort=False), vrep.astype(np.int32), Tw, pre, rot
 
 
 def disk_for_cells(T: int, seed: int = 2):

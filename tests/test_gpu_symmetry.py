@@ -15,15 +15,22 @@ from paper_1708_03912_amd import fraclap as F, meshgen as M  # noqa: E402
 from test_gpu_parity import oracle_orders  # noqa: E402
 
 
-@pytest.mark.parametrize("K,s", [(2, 0.3), (4, 0.75), (8, 0.5)])
-def test_reduced_matrix_parity(K, s):
-    mesh, vfold, Tw = M.disk_symmetric(0.2, K, seed=6)
+@pytest.mark.parametrize("K,s,couples", [(2, 0.3, False), (4, 0.75, False), (8, 0.5, False),
+                                          (2, 0.75, True), (4, 0.3, True), (8, 0.5, True)])
+def test_reduced_matrix_parity(K, s, couples):
+    """couples: one member of each equal couple of cross pairs (preimage and
+    rotation of every cell given) instead of both with weight 1/2."""
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.2, K, seed=6)
     h = F.Handle(0)
     h.set_mesh(mesh)
-    h.set_symmetry(K, Tw, vfold)
+    if couples:
+        h.set_symmetry(K, Tw, vfold, pre, rot)
+    else:
+        h.set_symmetry(K, Tw, vfold)
     n = h.assemble(s, F.default_opts())
     A = h.export_matrix()
-    Ao, red, _ = SY.assemble_reduced(mesh, s, oracle_orders(F.default_opts()), vfold, Tw)
+    kw = dict(pre=pre, rot=rot, K=K) if couples else {}
+    Ao, red, _ = SY.assemble_reduced(mesh, s, oracle_orders(F.default_opts()), vfold, Tw, **kw)
     assert n == len(red)
     assert np.abs(A - Ao).max() <= 1e-10 * np.abs(Ao).max()
     b = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -36,10 +43,10 @@ def test_reduced_matrix_parity(K, s):
 def test_reduced_solution_is_the_full_one():
     """d = 2, K = 4, s = 0.75: CG on the reduced system gives the full
     mesh's solution at the representatives (up to the quadrature's lack of
-    exact rotation invariance); the sector cells meet all cells, about 2/K
-    of the full mesh's separated pairs."""
+    exact rotation invariance); one member of each couple of equal cross
+    pairs: about 1/K of the full mesh's separated pairs."""
     K, s = 4, 0.75
-    mesh, vfold, Tw = M.disk_symmetric(0.08, K, seed=7)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.08, K, seed=7)
     hf = F.Handle(0)
     hf.set_mesh(mesh)
     nf = hf.assemble(s)
@@ -51,7 +58,7 @@ def test_reduced_solution_is_the_full_one():
     dofs_full = hf.dofs()
     hr = F.Handle(0)
     hr.set_mesh(mesh)
-    hr.set_symmetry(K, Tw, vfold)
+    hr.set_symmetry(K, Tw, vfold, pre, rot)
     nr = hr.assemble(s)
     str_ = hr.stats()
     br = torch.empty(nr, dtype=torch.float64, device="cuda")
@@ -71,13 +78,15 @@ def test_reduced_solution_is_the_full_one():
     er, ef = float(torch.dot(ur, y)), float(torch.dot(uf, yf))
     assert abs(K * er - ef) <= 1e-7 * ef
     far_f, far_r = sum(stf.pairs_far), sum(str_.pairs_far)
-    assert far_r < (2.0 / K + 0.05) * far_f, (far_r, far_f)
+    # computed pairs: the weight-0 half of the cross pairs is skipped tile by
+    # tile, so small meshes (few blocks per image copy) keep more of it
+    assert far_r < 0.5 * far_f, (far_r, far_f)
     hf.close()
     hr.close()
 
 
 def test_symmetry_errors():
-    mesh, vfold, Tw = M.disk_symmetric(0.3, 2, seed=1)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.3, 2, seed=1)
     h = F.Handle(0)
     h.set_mesh(mesh)
     bad = np.array(vfold)
@@ -88,7 +97,12 @@ def test_symmetry_errors():
     with pytest.raises(F.FraclapError) as e:
         h.set_symmetry(2, len(mesh["cells"]) + 1, vfold)
     assert e.value.code == F.FL_EINVAL
-    h.set_symmetry(2, Tw, vfold)
+    bad_pre = np.array(pre)
+    bad_pre[-1] = (bad_pre[-1] + 1) % Tw
+    with pytest.raises(F.FraclapError) as e:
+        h.set_symmetry(2, Tw, vfold, bad_pre, rot)
+    assert e.value.code == F.FL_EMESH
+    h.set_symmetry(2, Tw, vfold, pre, rot)
     h.assemble(0.4)
     with pytest.raises(F.FraclapError) as e:
         h.cluster_build()

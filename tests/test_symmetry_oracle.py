@@ -13,7 +13,7 @@ from paper_1708_03912_amd import meshgen as M
 
 @pytest.mark.parametrize("K", [2, 4, 8])
 def test_mesh_is_symmetric(K):
-    mesh, vfold, Tw = M.disk_symmetric(0.2, K, seed=3)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.2, K, seed=3)
     V = np.asarray(mesh["verts"])
     C = np.asarray(mesh["cells"])
     al = 2 * math.pi / K
@@ -33,7 +33,7 @@ def test_mesh_is_symmetric(K):
 
 @pytest.mark.parametrize("K,s", [(2, 0.3), (4, 0.75), (8, 0.5)])
 def test_reduced_solution_is_the_full_one(K, s):
-    mesh, vfold, Tw = M.disk_symmetric(0.25, K, seed=4)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.25, K, seed=4)
     A, dofs, _ = O.assemble(mesh, s, O.Orders())
     b = O.load_vector_one(mesh, dofs)
     u = O.solve_cholesky(A, b)
@@ -77,7 +77,7 @@ def test_weighted_pair_sum_is_the_fold(K, s):
     """The sector-against-images pair sum (what the effective kernel
     computes) equals P^T A P / K up to the quadrature rules' rotation
     asymmetry, and costs about 1/K of the full pair count."""
-    mesh, vfold, Tw = M.disk_symmetric(0.25, K, seed=5)
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.25, K, seed=5)
     A, dofs, cnt_full = O.assemble(mesh, s, O.Orders())
     b = O.load_vector_one(mesh, dofs)
     Ar, br, red = SY.reduce(A, b, dofs, vfold, K)
@@ -92,3 +92,18 @@ def test_weighted_pair_sum_is_the_fold(K, s):
     assert np.abs(uw - u[pos]).max() <= 1e-7 * np.abs(u).max()
     T = len(mesh["cells"])
     assert cnt.sum() < (1.5 / K + 0.1) * cnt_full.sum()
+
+
+@pytest.mark.parametrize("K,s", [(2, 0.3), (4, 0.75), (8, 0.5)])
+def test_one_of_each_cross_couple(K, s):
+    """Counting one member of each couple (S, B^i T) ~ (T, B^-i S) with
+    weight 1 gives the same reduced matrix as counting both with 1/2 (up to
+    the rotation asymmetry of the rules), with about 1/K of the full pairs."""
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.25, K, seed=5)
+    Ah, red, cnt_h = SY.assemble_reduced(mesh, s, O.Orders(), vfold, Tw)
+    Aq, red2, cnt_q = SY.assemble_reduced(mesh, s, O.Orders(), vfold, Tw, pre=pre, rot=rot, K=K)
+    assert np.array_equal(red, red2)
+    assert np.abs(Aq - Ah).max() <= 1e-7 * np.abs(Ah).max()
+    assert np.abs(Aq - Aq.T).max() <= 1e-14 * np.abs(Aq).max()
+    A, dofs, cnt_full = O.assemble(mesh, s, O.Orders())
+    assert cnt_q.sum() <= (1.0 / K + 0.05) * cnt_full.sum() + 1
