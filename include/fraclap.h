@@ -325,6 +325,19 @@ int fl_eval_points(fl_handle *h, int32_t k_eval, double *x, double *w);
 int fl_strong_form(fl_handle *h, double s, const double *u, int32_t k_eval, int32_t q_far,
                    int32_t q_near, double *Lu);
 
+/* fl_strong_form with the all-pairs part evaluated by the cluster method
+ * (Sec. 6: the strong form at the indicator points reuses the cluster
+ * machinery): a tree over the cells (median bisection of the centroids,
+ * leaves of at most `leaf` cells, cube boxes), admissible pairs eta dist >=
+ * max diam through Chebyshev moments of the edge sources (m points per
+ * direction, nested by shift coefficients) and local expansions, the other
+ * leaf pairs summed directly; the touching-cell terms and the boundary
+ * value terms as in fl_strong_form.  d = 2 only (FL_EINVAL otherwise).
+ * The tree is kept for the next call with the same (m, eta, leaf).
+ * Arguments and results otherwise as fl_strong_form.  Asynchronous. */
+int fl_strong_form_cluster(fl_handle *h, double s, const double *u, int32_t k_eval, int32_t q_far,
+                           int32_t q_near, int32_t m, double eta, int32_t leaf, double *Lu);
+
 /* Babuska-Rheinboldt type indicators of Sec. 4 from the strong form Lu of
  * the last fl_strong_form call with this k_eval:
  *   eta_cell[K] = h_K^{2s} ||f - Lu||^2_{L2(K)}   (h_K: longest edge),

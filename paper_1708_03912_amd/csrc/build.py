@@ -23,7 +23,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
          ("fl_sf.hip", []), ("fl_cluster.hip", []), ("fl_api.hip", ["-ffp-contract=off"]),
-         ("fl_batch_api.hip", []), ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", []),
+         ("fl_batch_api.hip", []), ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", ["-ffp-contract=off"]),
          ("fl_cluster_api.hip", ["-ffp-contract=off"])]
 
 

@@ -103,6 +103,14 @@ struct fl_sf {
     double* tab = nullptr;          // kernel-power tables of tab_s
     double tab_s = -1.0;
     std::vector<void*> bufs;        // every allocation above
+    // cluster evaluation of the all-pairs part (fl_strong_form_cluster)
+    bool cl_ready = false;
+    int cl_m = 0, cl_leaf = 0;
+    double cl_eta = 0.0;
+    fl::SfClDev C{};
+    std::vector<const int*> cl_up, cl_down;
+    std::vector<int> cl_upc, cl_downc;
+    std::vector<void*> clbufs;
 };
 
 // Cluster approximation of the assembled matrix (fl_cluster_build).

@@ -278,6 +278,34 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
                      const int* const* down_lists, const int* down_counts, int n_down, double C, const double* x,
                      double* y, hipStream_t st);
 
+// Cluster evaluation of the strong form's all-pairs part (Sec. 6): a tree
+// over the cells (tree positions), Chebyshev moments of the edge sources
+// owned by a cluster's cells, local expansions, near leaf pairs directly.
+struct SfClDev {
+    int m, M, nc, nleaf;
+    const int* clo;         // tree-position range [clo, chi) of each cluster
+    const int* chi;
+    const int* cpar;
+    const int* sptr;        // sons (CSR)
+    const int* sidx;
+    const double* box;      // corner x, corner y, side
+    const double* tnode;    // m Chebyshev points on [0, 1]
+    const int* perm;        // tree position -> cell
+    const int* leaf;        // leaf cluster ids
+    const int* optr;        // tree position -> edges it owns (CSR)
+    const int* oidx;
+    const long long* fptr;  // admissible pairs by first cluster
+    const int* fdst;
+    const int* lnptr;       // near leaf pairs by leaf index
+    const int* ndst;
+    double* T;              // nc x M x M shift coefficients
+    double* mom;            // nc x M moments
+    double* loc;            // nc x M local expansions
+};
+void launch_sfc_transfer(const SfClDev& Cl, hipStream_t st);
+void launch_sfc_eval(const SfClDev& Cl, const SfDev& D, const double* sx, const double* sy,
+                     const int* const* up_lists, const int* up_counts, int n_up, const int* const* down_lists,
+                     const int* down_counts, int n_down, double* part0, hipStream_t st);
 void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st);
 void launch_sf_far(const SfDev& D, const double* sx, const double* sy, const double* bsx, const double* bsy,
                    long long chunk, int nch, int nchb, const double* tab, double* part, bool logk,

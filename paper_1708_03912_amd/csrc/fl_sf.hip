@@ -342,6 +342,149 @@ __global__ __launch_bounds__(256) void sf_ind_node_kernel(long long nv, const in
     eta_n[v] = acc;
 }
 
+
+// ------------------------------------------------- cluster evaluation --
+
+__device__ __forceinline__ double sfc_lag(const double* t, int m, int a, double xi) {
+    double p = 1.0;
+    for (int b = 0; b < m; ++b)
+        if (b != a) p *= (xi - t[b]) / (t[a] - t[b]);
+    return p;
+}
+
+// tensor Lagrange basis function a (first coordinate slowest) of cluster c
+__device__ __forceinline__ double sfc_lag_box(const SfClDev& C, int c, int a, double x, double y) {
+    const double* bx = C.box + 3 * c;
+    const int a0 = a / C.m, a1 = a - a0 * C.m;
+    return sfc_lag(C.tnode, C.m, a0, (x - bx[0]) / bx[2]) * sfc_lag(C.tnode, C.m, a1, (y - bx[1]) / bx[2]);
+}
+
+__device__ __forceinline__ void sfc_pt(const SfClDev& C, int c, int b, double& x, double& y) {
+    const double* bx = C.box + 3 * c;
+    const int b0 = b / C.m, b1 = b - b0 * C.m;
+    x = bx[0] + bx[2] * C.tnode[b0];
+    y = bx[1] + bx[2] * C.tnode[b1];
+}
+
+// T_c[b][a] = L_a^parent(xi_b^c), clusters c >= 1
+__global__ __launch_bounds__(256) void sfc_transfer_kernel(SfClDev C) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long MM = (long long)C.M * C.M;
+    if (id >= (long long)C.nc * MM) return;
+    const int c = (int)(id / MM);
+    if (c == 0) return;
+    const int rem = (int)(id - (long long)c * MM);
+    const int b = rem / C.M, a = rem - b * C.M;
+    double x, y;
+    sfc_pt(C, c, b, x, y);
+    C.T[id] = sfc_lag_box(C, C.cpar[c], a, x, y);
+}
+
+// leaves: mom[c][b] = sum over the sources of the cells of c of w L_b(y)
+__global__ __launch_bounds__(64) void sfc_mom_leaf_kernel(SfClDev C, SfDev D, const double* __restrict__ sx,
+                                                          const double* __restrict__ sy) {
+    const int c = C.leaf[blockIdx.x];
+    for (int b = threadIdx.x; b < C.M; b += blockDim.x) {
+        double acc = 0.0;
+        for (int p = C.clo[c]; p < C.chi[c]; ++p)
+            for (int e = C.optr[p]; e < C.optr[p + 1]; ++e) {
+                const long long f = C.oidx[e];
+                for (int j = 0; j < D.qf; ++j) {
+                    const long long k = f * D.qf + j;
+                    acc = fma(D.sc[k], sfc_lag_box(C, c, b, sx[k], sy[k]), acc);
+                }
+            }
+        C.mom[(long long)c * C.M + b] = acc;
+    }
+}
+
+// internal clusters of one level: mom[c][a] = sum_sons sum_b T_son[b][a] mom[son][b]
+__global__ __launch_bounds__(64) void sfc_up_kernel(SfClDev C, const int* __restrict__ list) {
+    const int c = list[blockIdx.x];
+    for (int a = threadIdx.x; a < C.M; a += blockDim.x) {
+        double acc = 0.0;
+        for (int e = C.sptr[c]; e < C.sptr[c + 1]; ++e) {
+            const int sn = C.sidx[e];
+            const double* Ts = C.T + (long long)sn * C.M * C.M;
+            const double* ms = C.mom + (long long)sn * C.M;
+            for (int b = 0; b < C.M; ++b) acc = fma(Ts[b * C.M + a], ms[b], acc);
+        }
+        C.mom[(long long)c * C.M + a] = acc;
+    }
+}
+
+// far field: loc[s][a] = sum over admissible (s, t) of sum_b g(xi_a^s, xi_b^t)
+// mom[t][b]; four lane groups over the pairs, added in group order
+__global__ __launch_bounds__(256) void sfc_far_kernel(SfClDev C, double pe) {
+    __shared__ double red[4][64];
+    const int c = blockIdx.x;
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int a0 = 0; a0 < C.M; a0 += 64) {
+        const int a = a0 + lane;
+        double acc = 0.0;
+        if (a < C.M) {
+            double xa, ya;
+            sfc_pt(C, c, a, xa, ya);
+            for (long long p = C.fptr[c] + g; p < C.fptr[c + 1]; p += 4) {
+                const int t = C.fdst[p];
+                const double* mt = C.mom + (long long)t * C.M;
+                for (int b = 0; b < C.M; ++b) {
+                    double xb, yb;
+                    sfc_pt(C, t, b, xb, yb);
+                    const double dx = xa - xb, dy = ya - yb;
+                    acc = fma(kpow(fma(dx, dx, dy * dy), pe), mt[b], acc);
+                }
+            }
+        }
+        red[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && a < C.M) C.loc[(long long)c * C.M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        __syncthreads();
+    }
+}
+
+// clusters of one level (>= 1): loc[c][b] += sum_a T_c[b][a] loc[parent][a]
+__global__ __launch_bounds__(64) void sfc_down_kernel(SfClDev C, const int* __restrict__ list) {
+    const int c = list[blockIdx.x];
+    const double* Tc = C.T + (long long)c * C.M * C.M;
+    const double* lp = C.loc + (long long)C.cpar[c] * C.M;
+    for (int b = threadIdx.x; b < C.M; b += blockDim.x) {
+        double acc = 0.0;
+        for (int a = 0; a < C.M; ++a) acc = fma(Tc[b * C.M + a], lp[a], acc);
+        C.loc[(long long)c * C.M + b] += acc;
+    }
+}
+
+// leaves: every evaluation point of the leaf's cells adds its local
+// expansion and the direct sums over the near leaves' sources to part0
+__global__ __launch_bounds__(64) void sfc_leaf_eval_kernel(SfClDev C, SfDev D, const double* __restrict__ sx,
+                                                           const double* __restrict__ sy, double pe,
+                                                           double* __restrict__ part0) {
+    const int li = blockIdx.x;
+    const int c = C.leaf[li];
+    const int np = (C.chi[c] - C.clo[c]) * D.Q;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int cell = C.perm[C.clo[c] + i / D.Q];
+        const long long t = (long long)cell * D.Q + (i % D.Q);
+        const double x = D.tx[t], y = D.ty[t];
+        double acc = 0.0;
+        for (int a = 0; a < C.M; ++a) acc = fma(sfc_lag_box(C, c, a, x, y), C.loc[(long long)c * C.M + a], acc);
+        for (int e = C.lnptr[li]; e < C.lnptr[li + 1]; ++e) {
+            const int tc = C.ndst[e];
+            for (int p = C.clo[tc]; p < C.chi[tc]; ++p)
+                for (int o = C.optr[p]; o < C.optr[p + 1]; ++o) {
+                    const long long f = C.oidx[o];
+                    for (int j = 0; j < D.qf; ++j) {
+                        const long long k = f * D.qf + j;
+                        const double dx = x - sx[k], dy = y - sy[k];
+                        acc = fma(D.sc[k], kpow(fma(dx, dx, dy * dy), pe), acc);
+                    }
+                }
+        }
+        part0[t] += acc;
+    }
+}
+
 inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -398,6 +541,26 @@ void launch_sf_indicators(const SfDev& D, const double* Lu, const double* f, con
     if (eta_node && nv > 0)
         hipLaunchKernelGGL(sf_ind_node_kernel, dim3(nblk(nv)), dim3(256), 0, st, nv, vptr, vidx, eta_cell,
                            eta_node);
+}
+
+void launch_sfc_transfer(const SfClDev& C, hipStream_t st) {
+    if (C.nc > 1)
+        hipLaunchKernelGGL(sfc_transfer_kernel, dim3(nblk((long long)C.nc * C.M * C.M)), dim3(256), 0, st, C);
+}
+
+void launch_sfc_eval(const SfClDev& C, const SfDev& D, const double* sx, const double* sy,
+                     const int* const* up_lists, const int* up_counts, int n_up, const int* const* down_lists,
+                     const int* down_counts, int n_down, double* part0, hipStream_t st) {
+    if (C.nc == 0) return;
+    hipLaunchKernelGGL(sfc_mom_leaf_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy);
+    for (int l = 0; l < n_up; ++l)
+        if (up_counts[l] > 0)
+            hipLaunchKernelGGL(sfc_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 0, st, C, up_lists[l]);
+    hipLaunchKernelGGL(sfc_far_kernel, dim3((unsigned)C.nc), dim3(256), 0, st, C, D.pe);
+    for (int l = 0; l < n_down; ++l)
+        if (down_counts[l] > 0)
+            hipLaunchKernelGGL(sfc_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), 0, st, C, down_lists[l]);
+    hipLaunchKernelGGL(sfc_leaf_eval_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy, D.pe, part0);
 }
 
 }  // namespace fl

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -58,9 +59,47 @@ int sf_alloc(fl_handle* h, T** p, size_t count) {
     return FL_OK;
 }
 
+void sf_cl_release(fl_handle* h) {
+    for (void* p : h->sf.clbufs) (void)hipFree(p);
+    h->sf.clbufs.clear();
+    h->sf.cl_ready = false;
+    h->sf.cl_up.clear();
+    h->sf.cl_down.clear();
+    h->sf.cl_upc.clear();
+    h->sf.cl_downc.clear();
+    h->sf.C = SfClDev{};
+}
+
 void sf_release(fl_handle* h) {
+    sf_cl_release(h);
     for (void* p : h->sf.bufs) (void)hipFree(p);
     h->sf = fl_sf{};
+}
+
+template <class T>
+int cl_upload(fl_handle* h, T** p, const std::vector<T>& v) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<size_t>(v.size(), 1)) != hipSuccess)
+        return sfail(h, FL_ENOMEM, "strong form: device allocation failed");
+    h->sf.clbufs.push_back(q);
+    *p = (T*)q;
+    if (!v.empty()) HIPCHK(hipMemcpy(q, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return FL_OK;
+}
+
+struct SfCl {
+    int lo, hi, level, parent;
+    double blo[2], side;
+    std::vector<int> sons;
+};
+
+bool sf_admissible(const SfCl& a, const SfCl& b, double eta) {
+    double g2 = 0.0;
+    for (int j = 0; j < 2; ++j) {
+        const double g = std::max(0.0, std::max(b.blo[j] - (a.blo[j] + a.side), a.blo[j] - (b.blo[j] + b.side)));
+        g2 += g * g;
+    }
+    return eta * std::sqrt(g2) >= std::max(a.side * std::sqrt(2.0), b.side * std::sqrt(2.0));
 }
 
 // Evaluation rule of a cell with k points per direction: barycentric
@@ -353,6 +392,217 @@ int sf_plan(fl_handle* h, int k, int qf, int qn) {
     return FL_OK;
 }
 
+// Cell tree, block lists and source ownership of the cluster evaluation
+// (d = 2): the same construction as the oracle's (median split of the
+// centroids along their longest extent, cube boxes of the cells' vertex
+// bounding boxes, admissibility eta dist >= max diam).
+int sf_cl_plan(fl_handle* h, int m, double eta, int leaf) {
+    fl_sf& S = h->sf;
+    if (S.cl_ready && S.cl_m == m && S.cl_eta == eta && S.cl_leaf == leaf) return FL_OK;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    sf_cl_release(h);
+    const int64_t T = h->nc;
+    std::vector<double> cx(T), cy(T), lo0(T), lo1(T), hi0(T), hi1(T);
+    for (int64_t K = 0; K < T; ++K) {
+        const int32_t* c = &h->cells[3 * K];
+        const double* a = &h->verts[2 * c[0]];
+        const double* b = &h->verts[2 * c[1]];
+        const double* d = &h->verts[2 * c[2]];
+        cx[K] = ((a[0] + b[0]) + d[0]) / 3.0;
+        cy[K] = ((a[1] + b[1]) + d[1]) / 3.0;
+        lo0[K] = std::min(std::min(a[0], b[0]), d[0]);
+        lo1[K] = std::min(std::min(a[1], b[1]), d[1]);
+        hi0[K] = std::max(std::max(a[0], b[0]), d[0]);
+        hi1[K] = std::max(std::max(a[1], b[1]), d[1]);
+    }
+    std::vector<SfCl> cl;
+    std::vector<int> perm(T);
+    std::function<int(std::vector<int>&, int, int, int)> make = [&](std::vector<int>& idx, int lo, int level,
+                                                                    int parent) -> int {
+        SfCl c;
+        c.lo = lo;
+        c.hi = lo + (int)idx.size();
+        c.level = level;
+        c.parent = parent;
+        double bl[2] = {INFINITY, INFINITY}, bh[2] = {-INFINITY, -INFINITY};
+        for (int K : idx) {
+            bl[0] = std::min(bl[0], lo0[K]);
+            bl[1] = std::min(bl[1], lo1[K]);
+            bh[0] = std::max(bh[0], hi0[K]);
+            bh[1] = std::max(bh[1], hi1[K]);
+        }
+        const double side = std::max(bh[0] - bl[0], bh[1] - bl[1]);
+        c.side = side;
+        for (int j = 0; j < 2; ++j) c.blo[j] = 0.5 * (bl[j] + bh[j]) - 0.5 * side;
+        const int cid = (int)cl.size();
+        cl.push_back(c);
+        for (size_t k = 0; k < idx.size(); ++k) perm[lo + k] = idx[k];
+        if ((int)idx.size() > leaf) {
+            double e0l = INFINITY, e0h = -INFINITY, e1l = INFINITY, e1h = -INFINITY;
+            for (int K : idx) {
+                e0l = std::min(e0l, cx[K]);
+                e0h = std::max(e0h, cx[K]);
+                e1l = std::min(e1l, cy[K]);
+                e1h = std::max(e1h, cy[K]);
+            }
+            const int ax = (e1h - e1l > e0h - e0l) ? 1 : 0;
+            const std::vector<double>& key = ax == 0 ? cx : cy;
+            std::vector<int> order(idx);
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+            const size_t half = order.size() / 2;
+            std::vector<int> p1(order.begin(), order.begin() + half), p2(order.begin() + half, order.end());
+            const int s1 = make(p1, lo, level + 1, cid);
+            cl[cid].sons.push_back(s1);
+            const int s2 = make(p2, lo + (int)half, level + 1, cid);
+            cl[cid].sons.push_back(s2);
+        }
+        return cid;
+    };
+    {
+        std::vector<int> all(T);
+        for (int64_t K = 0; K < T; ++K) all[K] = (int)K;
+        make(all, 0, 0, -1);
+    }
+    const int nc = (int)cl.size();
+    std::vector<std::pair<int, int>> far, near;
+    std::function<void(int, int)> rec = [&](int a, int b) {
+        if (sf_admissible(cl[a], cl[b], eta)) {
+            far.push_back({a, b});
+            return;
+        }
+        const bool la = cl[a].sons.empty(), lb = cl[b].sons.empty();
+        if (la && lb) near.push_back({a, b});
+        else if (la) for (int t : cl[b].sons) rec(a, t);
+        else if (lb) for (int t : cl[a].sons) rec(t, b);
+        else for (int u : cl[a].sons) for (int t : cl[b].sons) rec(u, t);
+    };
+    rec(0, 0);
+    std::stable_sort(far.begin(), far.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return a.first < b.first;
+    });
+    std::vector<int> leaf_ids, leaf_of(nc, -1);
+    for (int c = 0; c < nc; ++c)
+        if (cl[c].sons.empty()) {
+            leaf_of[c] = (int)leaf_ids.size();
+            leaf_ids.push_back(c);
+        }
+    std::stable_sort(near.begin(), near.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return leaf_of[a.first] < leaf_of[b.first];
+    });
+    std::vector<int> clo(nc), chi(nc), cpar(nc), sptr(nc + 1, 0), sidx;
+    std::vector<double> box(3 * (size_t)nc);
+    int depth = 0;
+    for (int c = 0; c < nc; ++c) {
+        clo[c] = cl[c].lo;
+        chi[c] = cl[c].hi;
+        cpar[c] = cl[c].parent;
+        box[3 * c] = cl[c].blo[0];
+        box[3 * c + 1] = cl[c].blo[1];
+        box[3 * c + 2] = cl[c].side;
+        for (int sn : cl[c].sons) sidx.push_back(sn);
+        sptr[c + 1] = (int)sidx.size();
+        depth = std::max(depth, cl[c].level);
+    }
+    std::vector<long long> fptr(nc + 1, 0);
+    std::vector<int> fdst;
+    for (auto& p : far) {
+        fdst.push_back(p.second);
+        fptr[p.first + 1]++;
+    }
+    for (int c = 0; c < nc; ++c) fptr[c + 1] += fptr[c];
+    const int nleaf = (int)leaf_ids.size();
+    std::vector<int> lnptr(nleaf + 1, 0), ndst;
+    for (auto& p : near) {
+        ndst.push_back(p.second);
+        lnptr[leaf_of[p.first] + 1]++;
+    }
+    for (int l = 0; l < nleaf; ++l) lnptr[l + 1] += lnptr[l];
+    // edges owned by each tree position (the edge's first cell)
+    std::vector<int> pos(T);
+    for (int64_t k = 0; k < T; ++k) pos[perm[k]] = (int)k;
+    std::vector<int> fK(2 * S.D.nf);
+    HIPCHK(hipMemcpy(fK.data(), S.D.fK, sizeof(int) * fK.size(), hipMemcpyDeviceToHost));
+    std::vector<int> optr(T + 1, 0), oidx(S.D.nf);
+    for (long long f = 0; f < S.D.nf; ++f) optr[pos[fK[2 * f]] + 1]++;
+    for (int64_t k = 0; k < T; ++k) optr[k + 1] += optr[k];
+    {
+        std::vector<int> fill(optr.begin(), optr.end() - 1);
+        for (long long f = 0; f < S.D.nf; ++f) oidx[fill[pos[fK[2 * f]]]++] = (int)f;
+    }
+    std::vector<double> tnode(m);
+    for (int k = 0; k < m; ++k) tnode[k] = 0.5 - 0.5 * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * m));
+    std::vector<std::vector<int>> up(depth + 1), down(depth + 1);
+    for (int c = 0; c < nc; ++c) {
+        if (!cl[c].sons.empty()) up[cl[c].level].push_back(c);
+        if (c > 0) down[cl[c].level].push_back(c);
+    }
+    SfClDev C{};
+    C.m = m;
+    C.M = m * m;
+    C.nc = nc;
+    C.nleaf = nleaf;
+    int rc;
+    int *p_clo, *p_chi, *p_cpar, *p_sptr, *p_sidx, *p_perm, *p_leaf, *p_optr, *p_oidx, *p_fdst, *p_lnptr, *p_ndst;
+    double *p_box, *p_tnode;
+    long long* p_fptr;
+    if ((rc = cl_upload(h, &p_clo, clo)) || (rc = cl_upload(h, &p_chi, chi)) || (rc = cl_upload(h, &p_cpar, cpar)) ||
+        (rc = cl_upload(h, &p_sptr, sptr)) || (rc = cl_upload(h, &p_sidx, sidx)) || (rc = cl_upload(h, &p_perm, perm)) ||
+        (rc = cl_upload(h, &p_leaf, leaf_ids)) || (rc = cl_upload(h, &p_optr, optr)) ||
+        (rc = cl_upload(h, &p_oidx, oidx)) || (rc = cl_upload(h, &p_fdst, fdst)) ||
+        (rc = cl_upload(h, &p_lnptr, lnptr)) || (rc = cl_upload(h, &p_ndst, ndst)) || (rc = cl_upload(h, &p_box, box)) ||
+        (rc = cl_upload(h, &p_tnode, tnode)) || (rc = cl_upload(h, &p_fptr, fptr))) {
+        sf_cl_release(h);
+        return rc;
+    }
+    C.clo = p_clo;
+    C.chi = p_chi;
+    C.cpar = p_cpar;
+    C.sptr = p_sptr;
+    C.sidx = p_sidx;
+    C.perm = p_perm;
+    C.leaf = p_leaf;
+    C.optr = p_optr;
+    C.oidx = p_oidx;
+    C.fdst = p_fdst;
+    C.lnptr = p_lnptr;
+    C.ndst = p_ndst;
+    C.box = p_box;
+    C.tnode = p_tnode;
+    C.fptr = p_fptr;
+    std::vector<double> zT((size_t)nc * C.M * C.M, 0.0), zc((size_t)nc * C.M, 0.0);
+    if ((rc = cl_upload(h, &C.T, zT)) || (rc = cl_upload(h, &C.mom, zc)) || (rc = cl_upload(h, &C.loc, zc))) {
+        sf_cl_release(h);
+        return rc;
+    }
+    for (int l = depth; l >= 0; --l) {
+        int* q = nullptr;
+        if ((rc = cl_upload(h, &q, up[l]))) {
+            sf_cl_release(h);
+            return rc;
+        }
+        S.cl_up.push_back(q);
+        S.cl_upc.push_back((int)up[l].size());
+    }
+    for (int l = 1; l <= depth; ++l) {
+        int* q = nullptr;
+        if ((rc = cl_upload(h, &q, down[l]))) {
+            sf_cl_release(h);
+            return rc;
+        }
+        S.cl_down.push_back(q);
+        S.cl_downc.push_back((int)down[l].size());
+    }
+    launch_sfc_transfer(C, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    S.C = C;
+    S.cl_m = m;
+    S.cl_eta = eta;
+    S.cl_leaf = leaf;
+    S.cl_ready = true;
+    return FL_OK;
+}
+
 bool log_form(int dim, double s) { return dim == 1 && std::fabs(s - 0.5) < 1e-15; }
 
 // kernel-power tables of r2^pe, pe = -(d + 2s - 2)/2: pairs (1/m_i,
@@ -418,6 +668,42 @@ int fl_strong_form(fl_handle* h, double s, const double* u, int32_t k_eval, int3
     launch_sf_sources(D, u, h->stream);
     launch_sf_far(D, S.sx, S.sy, S.bsx, S.bsy, S.chunk, S.nch, S.nchb, S.tab, S.part, logk, h->stream);
     launch_sf_near(D, u, S.part, S.nch + S.nchb, S.tab, Lu, logk, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_strong_form_cluster(fl_handle* h, double s, const double* u, int32_t k_eval, int32_t q_far, int32_t q_near,
+                           int32_t m, double eta, int32_t leaf, double* Lu) {
+    if (!h) return FL_EINVAL;
+    if (!h->planned) return sfail(h, FL_ESTATE, "no DOF map: call fl_assemble first");
+    if (h->dim != 2) return sfail(h, FL_EINVAL, "the cluster evaluation is for triangle meshes (dim 2)");
+    if (!(s > 0.0 && s < 1.0)) return sfail(h, FL_EINVAL, "s must lie in (0,1)");
+    if (!Lu || (!u && h->n > 0)) return sfail(h, FL_EINVAL, "null vector");
+    if (m < 1 || m > 15) return sfail(h, FL_EINVAL, "m must lie in 1..15");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return sfail(h, FL_EINVAL, "eta must be positive and finite");
+    if (leaf < 1 || leaf > 1024) return sfail(h, FL_EINVAL, "leaf must lie in 1..1024");
+    int rc = check_rules(h, k_eval, q_far, q_near);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(h->device));
+    if ((rc = sf_plan(h, k_eval, q_far, q_near))) return rc;
+    if ((rc = sf_tables(h, s))) return rc;
+    if ((rc = sf_cl_plan(h, m, eta, leaf))) return rc;
+    fl_sf& S = h->sf;
+    SfDev D = S.D;
+    const double d2 = 2.0 * s;
+    D.pe = -0.5 * d2;
+    D.inv2s = 1.0 / (2.0 * s);
+    D.cg = 1.0 / (2.0 * s * d2);
+    D.cg_own = 1.0 / d2;
+    D.C = fl_cdn(2, s);
+    launch_sf_sources(D, u, h->stream);
+    // row 0: no direct sources (zeros), rows 1..nchb: the boundary value terms
+    SfDev Dz = D;
+    Dz.ns = 0;
+    launch_sf_far(Dz, S.sx, S.sy, S.bsx, S.bsy, S.chunk, 1, S.nchb, S.tab, S.part, false, h->stream);
+    launch_sfc_eval(S.C, D, S.sx, S.sy, S.cl_up.data(), S.cl_upc.data(), (int)S.cl_up.size(), S.cl_down.data(),
+                    S.cl_downc.data(), (int)S.cl_down.size(), S.part, h->stream);
+    launch_sf_near(D, u, S.part, 1 + S.nchb, S.tab, Lu, false, h->stream);
     HIPCHK(hipGetLastError());
     return FL_OK;
 }

@@ -38,7 +38,8 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_set_params", "fl_surrogate_get_params", "fl_surrogate_grad", "fl_surrogate_train",
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
            "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
-           "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry"]
+           "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry",
+           "fl_strong_form_cluster"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -116,6 +117,8 @@ def lib():
         L.fl_solve_cluster.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_cluster_info.argtypes = [vp, vp]
         L.fl_strong_form.argtypes = [vp, dp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.fl_strong_form_cluster.argtypes = [vp, dp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp,
+                                             C.c_int32, vp]
         L.fl_indicators.argtypes = [vp, dp, vp, vp, C.c_int32, vp, vp]
         L.fl_solve_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
@@ -301,6 +304,10 @@ class Handle:
     def strong_form(self, s, u, Lu, k_eval=2, q_far=2, q_near=12):
         """(-Delta)^s u_h at the evaluation points into device Lu (nc x Q)."""
         self._check(lib().fl_strong_form(self.h, s, _ptr(u), k_eval, q_far, q_near, _ptr(Lu)))
+
+    def strong_form_cluster(self, s, u, Lu, k_eval=2, q_far=2, q_near=12, m=6, eta=2.0, leaf=16):
+        """fl_strong_form with the all-pairs part by the cluster method."""
+        self._check(lib().fl_strong_form_cluster(self.h, s, _ptr(u), k_eval, q_far, q_near, m, eta, leaf, _ptr(Lu)))
 
     def indicators(self, s, Lu, eta_cell, eta_node=None, f=None, k_eval=2):
         """eta_K^2 into eta_cell (nc), their vertex sums into eta_node (nv)."""

@@ -177,3 +177,46 @@ def test_no_dofs():
     eo, no = SF.indicators(mesh, dofs, np.zeros(0), s, np.zeros((1, 4)))
     _close(ec, eo, 1e-14)
     _close(en, no, 1e-14)
+
+
+@pytest.mark.parametrize("s,m", [(0.3, 4), (0.75, 6)])
+def test_strong_form_cluster_parity(s, m):
+    """The cluster evaluation against the oracle's (same tree, same
+    admissible pairs, same Chebyshev order) to 1e-10."""
+    from oracle import sf_cluster as SC
+    mesh = M.disk_for_cells(900, seed=2)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = _u(mesh, dofs, 8)
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    h.assemble(s)
+    T = len(mesh["cells"])
+    Lu = torch.empty(T * 4, dtype=torch.float64, device="cuda")
+    h.strong_form_cluster(s, torch.tensor(u, device="cuda"), Lu, m=m, eta=2.0, leaf=16)
+    torch.cuda.synchronize()
+    ref, (far, near, cl) = SC.strong_form_cluster(mesh, dofs, u, s, m=m, eta=2.0, leaf=16)
+    assert len(far) > 0
+    _close(Lu.cpu().numpy().reshape(T, 4), ref)
+    h.close()
+
+
+def test_strong_form_cluster_converges_full_size():
+    """c2-sized disk: the cluster evaluation approaches the direct one
+    geometrically in m."""
+    s = 0.75
+    mesh = M.disk_for_cells(8000, seed=2)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = torch.tensor(_u(mesh, dofs, 9), device="cuda")
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    h.assemble(s)
+    T = len(mesh["cells"])
+    Ld = torch.empty(T * 4, dtype=torch.float64, device="cuda")
+    h.strong_form(s, u, Ld)
+    gaps = []
+    for m in (2, 4, 6):
+        Lc = torch.empty_like(Ld)
+        h.strong_form_cluster(s, u, Lc, m=m, eta=2.0, leaf=16)
+        gaps.append(float((Lc - Ld).abs().max() / Ld.abs().max()))
+    assert gaps[0] > 5 * gaps[1] > 25 * gaps[2] and gaps[2] < 1e-5, gaps
+    h.close()
