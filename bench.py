@@ -828,6 +828,32 @@ def indicators_leg(args):
                        "t_indicators_s": round(sum(st.t_indicators for st in steps), 4),
                        "wall_s": round(wall, 3)}
     out["adaptive"] = loops
+    # the all-pairs part by the cluster method (m = 6, eta = 2, leaves of 16
+    # cells) against the direct sum, growing meshes, s = 0.75
+    cl = {}
+    for cells in (8000, 32000, 128000):
+        mesh = M.disk_for_cells(cells, seed=2)
+        T = len(mesh["cells"])
+        h = F.Handle(0)
+        h.set_mesh(mesh)
+        n = h.assemble(0.75)
+        u = torch.tensor(np.random.default_rng(3).standard_normal(n), device="cuda")
+        Ld, Lc = torch.empty(T * 4, dtype=torch.float64, device="cuda"), torch.empty(T * 4, dtype=torch.float64,
+                                                                                     device="cuda")
+        h.strong_form(0.75, u, Ld)
+        h.strong_form_cluster(0.75, u, Lc, m=6, eta=2.0, leaf=16)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        h.strong_form(0.75, u, Ld)
+        ev[1].record()
+        h.strong_form_cluster(0.75, u, Lc, m=6, eta=2.0, leaf=16)
+        ev[2].record()
+        torch.cuda.synchronize()
+        cl[f"cells{T}"] = {"direct_ms": round(ev[0].elapsed_time(ev[1]), 3),
+                           "cluster_ms": round(ev[1].elapsed_time(ev[2]), 3),
+                           "rel_gap": float((Lc - Ld).abs().max() / Ld.abs().max())}
+        h.close()
+    out["cluster_strong_form"] = cl
     return out
 
 
