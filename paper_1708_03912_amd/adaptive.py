@@ -42,11 +42,13 @@ class Step:
 
 
 def adaptive_loop(mesh, s, steps, theta=0.8, opts=None, k_eval=2, q_far=2, q_near=12, rtol=1e-10,
-                  fu=None, max_cells=None, project=None, device=0):
+                  fu=None, max_cells=None, project=None, cluster_sf=None, device=0):
     """Run `steps` solve-estimate-mark-refine cycles from `mesh`; returns the
     list of Step records and the last mesh.  fu = (f, u) of the exact
     solution, if known, gives the energy error by the identity of Sec. 7.
     project: map of new boundary vertices onto a curved boundary (d = 2).
+    cluster_sf: None, or (m, eta, leaf) to evaluate the strong form's
+    all-pairs part by the cluster method (d = 2), as Sec. 7 does.
     Stops early once the mesh would exceed max_cells."""
     if mesh["dim"] == 2:
         mesh = M.nvb_label(mesh)
@@ -72,7 +74,11 @@ def adaptive_loop(mesh, s, steps, theta=0.8, opts=None, k_eval=2, q_far=2, q_nea
             Lu = torch.empty(T * Q, dtype=torch.float64, device="cuda")
             eta_c = torch.empty(T, dtype=torch.float64, device="cuda")
             eta_n = torch.empty(len(mesh["verts"]), dtype=torch.float64, device="cuda")
-            h.strong_form(s, u, Lu, k_eval=k_eval, q_far=q_far, q_near=q_near)
+            if cluster_sf is not None and mesh["dim"] == 2:
+                m, eta, leaf = cluster_sf
+                h.strong_form_cluster(s, u, Lu, k_eval=k_eval, q_far=q_far, q_near=q_near, m=m, eta=eta, leaf=leaf)
+            else:
+                h.strong_form(s, u, Lu, k_eval=k_eval, q_far=q_far, q_near=q_near)
             h.indicators(s, Lu, eta_c, eta_n, k_eval=k_eval)
             torch.cuda.synchronize()
             t3 = time.perf_counter()

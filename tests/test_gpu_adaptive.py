@@ -68,3 +68,18 @@ def test_adaptive_2d_disk():
     e = np.array([st.e2 for st in steps])
     assert np.all(np.diff(e) < 0)
     assert _slope(steps, 8) < -0.38
+
+
+def test_adaptive_2d_with_cluster_strong_form():
+    """The loop with the strong form's all-pairs part by the cluster method
+    (as in Sec. 7) refines like the direct one: the same DOF counts and
+    errors to the approximation's accuracy."""
+    s = 0.75
+    base = M.disk_for_cells(200, seed=2)
+    a, _ = AD.adaptive_loop(base, s, 5, fu=O.ball_fu(2, s), rtol=1e-12, project=M.project_disk)
+    b, _ = AD.adaptive_loop(base, s, 5, fu=O.ball_fu(2, s), rtol=1e-12, project=M.project_disk,
+                            cluster_sf=(6, 2.0, 16))
+    assert [st.n for st in a] == [st.n for st in b]
+    for x, y in zip(a, b):
+        assert abs(x.e2 - y.e2) <= 1e-9 * x.e2
+        assert abs(x.estimator - y.estimator) <= 1e-3 * x.estimator

@@ -220,3 +220,36 @@ def test_strong_form_cluster_converges_full_size():
         gaps.append(float((Lc - Ld).abs().max() / Ld.abs().max()))
     assert gaps[0] > 5 * gaps[1] > 25 * gaps[2] and gaps[2] < 1e-5, gaps
     h.close()
+
+
+def test_strong_form_cluster_one_leaf_and_errors():
+    """One leaf holding every cell: no admissible pair, so the cluster
+    evaluation is the direct one to rounding; 1D and bad arguments refused."""
+    s = 0.4
+    mesh = M.disk_for_cells(300, seed=3)
+    dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
+    u = torch.tensor(_u(mesh, dofs, 10), device="cuda")
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    h.assemble(s)
+    T = len(mesh["cells"])
+    Ld, Lc = torch.empty(T * 4, dtype=torch.float64, device="cuda"), torch.empty(T * 4, dtype=torch.float64,
+                                                                                 device="cuda")
+    h.strong_form(s, u, Ld)
+    h.strong_form_cluster(s, u, Lc, m=4, eta=2.0, leaf=1024)
+    assert float((Lc - Ld).abs().max()) <= 1e-12 * float(Ld.abs().max())
+    for kw in ({"m": 0}, {"eta": 0.0}, {"leaf": 0}):
+        with pytest.raises(F.FraclapError) as e:
+            h.strong_form_cluster(s, u, Lc, **kw)
+        assert e.value.code == F.FL_EINVAL
+    h.close()
+    m1 = M.interval(16)
+    h = F.Handle(0)
+    h.set_mesh(m1)
+    n = h.assemble(0.3)
+    u1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    L1 = torch.empty(16 * 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FraclapError) as e:
+        h.strong_form_cluster(0.3, u1, L1)
+    assert e.value.code == F.FL_EINVAL
+    h.close()
