@@ -149,6 +149,27 @@ __global__ __launch_bounds__(64) void h_up_leaf_kernel(HDev H) {
 // internal clusters of one level: xh[c][a] = sum_sons sum_b T_son[b][a] xh[son][b]
 __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int* __restrict__ list) {
     const int c = list[blockIdx.x];
+    if (H.M <= 64) {
+        // stage each son's shift coefficients in LDS (all loads in flight
+        // at once), its coefficients travel by shuffles
+        __shared__ double ts[64 * 64];
+        const int a = threadIdx.x;
+        double acc = 0.0;
+        for (int e = H.sptr[c]; e < H.sptr[c + 1]; ++e) {
+            const int sn = H.sidx[e];
+            const double* Ts = H.T + (long long)sn * H.M * H.M;
+            for (int i = a; i < H.M * H.M; i += 64) ts[i] = Ts[i];
+            const double xv = a < H.M ? H.xh[(long long)sn * H.M + a] : 0.0;
+            __syncthreads();
+            for (int b = 0; b < H.M; ++b) {
+                const double xb = __shfl(xv, b, 64);
+                if (a < H.M) acc = fma(ts[b * H.M + a], xb, acc);
+            }
+            __syncthreads();
+        }
+        if (a < H.M) H.xh[(long long)c * H.M + a] = acc;
+        return;
+    }
     for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
         double acc = 0.0;
         for (int e = H.sptr[c]; e < H.sptr[c + 1]; ++e) {
@@ -171,12 +192,25 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
     for (int a0 = 0; a0 < H.M; a0 += 64) {
         const int a = a0 + lane;
         double acc = 0.0;
-        if (a < H.M)
+        if (H.M == 36) {
+            // m = 6 in 2D: the block column of this lane in 36 registers,
+            // every load issued before the first product
+            for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
+                const double* Kp = H.Kb + p * 36 * 36;
+                const double xv = lane < 36 ? H.xh[(long long)H.fdst[p] * 36 + lane] : 0.0;
+                double kr[36];
+#pragma unroll
+                for (int b = 0; b < 36; ++b) kr[b] = lane < 36 ? Kp[b * 36 + lane] : 0.0;
+#pragma unroll
+                for (int b = 0; b < 36; ++b) acc = fma(kr[b], __shfl(xv, b, 64), acc);
+            }
+        } else if (a < H.M) {
             for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
                 const double* Kp = H.Kb + p * H.M * H.M;
                 const double* xt = H.xh + (long long)H.fdst[p] * H.M;
                 for (int b = 0; b < H.M; ++b) acc = fma(Kp[b * H.M + a], xt[b], acc);
             }
+        }
         red[g][lane] = acc;
         __syncthreads();
         if (g == 0 && a < H.M) H.yh[(long long)c * H.M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
@@ -189,6 +223,20 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int* __restric
     const int c = list[blockIdx.x];
     const double* Tc = H.T + (long long)c * H.M * H.M;
     const double* yp = H.yh + (long long)H.cpar[c] * H.M;
+    if (H.M <= 64) {
+        __shared__ double ts[64 * 64];
+        const int b = threadIdx.x;
+        for (int i = b; i < H.M * H.M; i += 64) ts[i] = Tc[i];
+        const double yv = b < H.M ? yp[b] : 0.0;
+        __syncthreads();
+        double acc = 0.0;
+        for (int a = 0; a < H.M; ++a) {
+            const double ya = __shfl(yv, a, 64);
+            if (b < H.M) acc = fma(ts[b * H.M + a], ya, acc);
+        }
+        if (b < H.M) H.yh[(long long)c * H.M + b] += acc;
+        return;
+    }
     for (int b = threadIdx.x; b < H.M; b += blockDim.x) {
         double acc = 0.0;
         for (int a = 0; a < H.M; ++a) acc = fma(Tc[b * H.M + a], yp[a], acc);

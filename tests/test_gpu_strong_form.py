@@ -66,7 +66,7 @@ def test_strong_form_rules_and_rhs_2d():
     """Other rules (k_eval 3, q_far 3, q_near 7) and a seeded right-hand side
     at the points, on the L-shape (graded mesh)."""
     s = 0.5
-    mesh = M.lshape(h_max=0.3, ratio=8.0)
+    mesh = M.lshape(h_max=0.8, ratio=8.0)
     dofs = O.dof_nodes(len(mesh["verts"]), mesh["bfacets"], s)
     u = _u(mesh, dofs, 2)
     T = len(mesh["cells"])
