@@ -698,19 +698,22 @@ def c5_leg(args):
 
 def mg_leg(args):
     """Nested uniform refinements of a disk mesh (~500 triangles, 3 and 4
-    levels: ~8k and ~32k triangles), s in {0.25, 0.75}, f = 1: Jacobi-PCG
-    against CG preconditioned by one multigrid V(2,2) cycle (Sec. 5), both
-    to 1e-10; iterations, solve times, the hierarchy's setup time and the
-    energy-norm distance of the two solutions."""
+    levels: ~8k and ~32k triangles, s in {0.25, 0.75}; 5 levels: ~128k
+    triangles, s = 0.75), f = 1: Jacobi-PCG against CG preconditioned by one
+    multigrid V(2,2) cycle (Sec. 5), both to 1e-10; iterations, solve times,
+    the hierarchy's setup time and the energy-norm distance of the two
+    solutions.  Then the same multigrid CG with the cluster approximation
+    (Sec. 6: m = 6, eta = 2, leaves of 32) as the operator of CG and of the
+    finest level of the cycle."""
     import torch
     from paper_1708_03912_amd import fraclap as F, meshgen as M
     base = M.disk_for_cells(500, seed=2)
     out = {"workload": "unit disk, ~500-triangle base mesh refined uniformly (nested), f=1, CG to 1e-10: "
                        "Jacobi-PCG vs multigrid V(2,2)-preconditioned CG"}
-    for levels in (3, 4):
+    for levels, svals in ((3, (0.25, 0.75)), (4, (0.25, 0.75)), (5, (0.75,))):
         meshes, parents = M.hierarchy(base, levels)
         nv = [len(m["verts"]) for m in meshes]
-        for s in (0.25, 0.75):
+        for s in svals:
             h = F.Handle(0)
             h.set_mesh(meshes[-1])
             n = h.assemble(s)
@@ -739,11 +742,29 @@ def mg_leg(args):
             gap = float(torch.dot(du, y)) ** 0.5
             h.matvec(uj, y)
             unorm = float(torch.dot(uj, y)) ** 0.5
+            # the cluster approximation as the fine operator
+            t0 = time.perf_counter()
+            h.cluster_build(m=6, eta=2.0, leaf=32)
+            torch.cuda.synchronize()
+            tcb = (time.perf_counter() - t0) * 1e3
+            uh = torch.zeros_like(b)
+            h.solve_cluster_mg(b, uh, rtol=1e-10)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ith, relh, _ = h.solve_cluster_mg(b, uh, rtol=1e-10)
+            torch.cuda.synchronize()
+            th = (time.perf_counter() - t0) * 1e3
+            du = uh - um
+            h.matvec(du, y)
+            gaph = float(torch.dot(du, y)) ** 0.5
             out[f"levels{levels}_s{s}"] = {"cells": len(meshes[-1]["cells"]), "n": n, "jacobi_iters": itj,
                                            "jacobi_ms": round(tj, 3), "mg_setup_ms": round(tset, 3),
                                            "mg_iters": itm, "mg_ms": round(tm, 3),
                                            "speedup": round(tj / tm, 3) if tm > 0 else None,
-                                           "relres": [relj, relm], "gap_rel": gap / unorm if unorm > 0 else None}
+                                           "relres": [relj, relm], "gap_rel": gap / unorm if unorm > 0 else None,
+                                           "cluster_build_ms": round(tcb, 3), "cluster_mg_iters": ith,
+                                           "cluster_mg_ms": round(th, 3), "cluster_mg_relres": relh,
+                                           "cluster_gap_rel": gaph / unorm if unorm > 0 else None}
             h.close()
     return out
 

@@ -266,6 +266,17 @@ int fl_cluster_matvec(fl_handle *h, const double *x, double *y);
 int fl_solve_cluster(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,
                      int32_t *iters, double *relres);
 
+/* Multigrid-preconditioned CG (Sec. 5 multigrid, Sec. 6 operator) on
+ * A_H u = b: the operator of CG and of the finest level of the V(2,2) cycle
+ * is the cluster approximation (its diagonal blocks are exact, so the
+ * smoother divides by the diagonal of the assembled matrix); the coarser
+ * levels are the Galerkin operators of fl_mg_setup.  Requires both
+ * fl_mg_setup and fl_cluster_build on the current matrix (FL_ESTATE
+ * otherwise).  Arguments and results as fl_solve_mg.  Synchronises the
+ * stream. */
+int fl_solve_cluster_mg(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,
+                        int32_t *iters, double *relres);
+
 /* Sizes of the cluster approximation, host out[7]: clusters, leaves,
  * admissible pairs, near pairs, near entries, device bytes, depth.
  * FL_ESTATE without one. */

@@ -181,6 +181,8 @@ void launch_sym_smooth(const SymPlan& P, const double* A, long long lda, double*
 // (fl_mg.hip) transfer operators between nested levels, Galerkin products,
 // coarsest-level inverse and the vector kernels of MG-preconditioned CG.
 void launch_mg_scale(double* x, const double* b, const double* d, double omega, long long n, hipStream_t st);
+void launch_mg_jacobi(double* x, const double* b, const double* y, const double* d, double omega, int mode,
+                      double* r, long long n, hipStream_t st);
 // b_c[c] = sum over the children (f, w) of c of w r_f[f]   (P^T r)
 void launch_mg_restrict(long long nc, const int* cptr, const int* cidx, const double* cw, const double* rf,
                         double* bc, hipStream_t st);

@@ -18,6 +18,16 @@ __global__ void mg_scale_kernel(double* x, const double* b, const double* d, dou
     if (i < n) x[i] = omega * b[i] / d[i];
 }
 
+// Jacobi step from a product y = A x computed elsewhere (the cluster
+// product): x += omega (b - y) / d (mode 0) or the residual r = b - y (mode 1)
+__global__ void mg_jacobi_kernel(double* x, const double* b, const double* y, const double* d, double omega,
+                                 int mode, double* r, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (mode == 0) x[i] += omega * (b[i] - y[i]) / d[i];
+    else r[i] = b[i] - y[i];
+}
+
 // one thread per coarse DOF, children in a fixed order
 __global__ void mg_restrict_kernel(long long nc, const int* cptr, const int* cidx, const double* cw,
                                    const double* rf, double* bc) {
@@ -118,6 +128,12 @@ inline dim3 grid1(long long n) { return dim3((unsigned)((n + 255) / 256)); }
 void launch_mg_scale(double* x, const double* b, const double* d, double omega, long long n, hipStream_t st) {
     if (n == 0) return;
     hipLaunchKernelGGL(mg_scale_kernel, grid1(n), dim3(256), 0, st, x, b, d, omega, n);
+}
+
+void launch_mg_jacobi(double* x, const double* b, const double* y, const double* d, double omega, int mode,
+                      double* r, long long n, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(mg_jacobi_kernel, grid1(n), dim3(256), 0, st, x, b, y, d, omega, mode, r, n);
 }
 
 void launch_mg_restrict(long long nc, const int* cptr, const int* cidx, const double* cw, const double* rf,

@@ -51,9 +51,18 @@ int upload(fl_handle* h, T** p, const std::vector<T>& v) {
 
 int64_t ld_of(int64_t n) { return ((n + 31) / 32) * 32; }
 
+void hm_product(fl_handle* h, const double* x, double* y) {
+    const fl_hm& Hm = h->hm;
+    launch_h_matvec(Hm.H, Hm.up_lists.data(), Hm.up_counts.data(), (int)Hm.up_lists.size(), Hm.down_lists.data(),
+                    Hm.down_counts.data(), (int)Hm.down_lists.size(), Hm.C, x, y, h->stream);
+}
+
 // One V(2,2) cycle on level l from x = 0 for the right-hand side b; the
-// finest level is the handle's matrix.
-void vcycle(fl_handle* h, int l, const double* b, double* x) {
+// finest level is the handle's matrix, or its cluster approximation when
+// `hfine` (then the smoother's products go through the cluster product into
+// the finest level's spare vector; its diagonal blocks are exact, so the
+// diagonal is A's).
+void vcycle(fl_handle* h, int l, const double* b, double* x, bool hfine) {
     fl_mg& G = h->mg;
     const int L = (int)G.lev.size();
     fl_mg_level& V = G.lev[l];
@@ -62,6 +71,23 @@ void vcycle(fl_handle* h, int l, const double* b, double* x) {
         return;
     }
     const bool fine = l == L - 1;
+    if (fine && hfine) {
+        fl_mg_level& C = G.lev[l - 1];
+        double* y = V.x;
+        launch_mg_scale(x, b, V.d, OMEGA, V.n, h->stream);
+        hm_product(h, x, y);
+        launch_mg_jacobi(x, b, y, V.d, OMEGA, 0, nullptr, V.n, h->stream);
+        hm_product(h, x, y);
+        launch_mg_jacobi(x, b, y, V.d, OMEGA, 1, V.r, V.n, h->stream);
+        launch_mg_restrict(C.n, V.cptr, V.cidx, V.cw, V.r, C.b, h->stream);
+        vcycle(h, l - 1, C.b, C.x, hfine);
+        launch_mg_prolong_add(V.n, V.par, V.pw, C.x, x, h->stream);
+        for (int k = 0; k < 2; ++k) {
+            hm_product(h, x, y);
+            launch_mg_jacobi(x, b, y, V.d, OMEGA, 0, nullptr, V.n, h->stream);
+        }
+        return;
+    }
     const double* A = fine ? h->dA : V.A;
     const int64_t lda = fine ? h->lda : V.lda;
     const SymPlan& sp = fine ? h->sym : V.sp;
@@ -70,7 +96,7 @@ void vcycle(fl_handle* h, int l, const double* b, double* x) {
     launch_sym_smooth(sp, A, lda, x, b, V.d, OMEGA, 0, nullptr, h->stream);
     launch_sym_smooth(sp, A, lda, x, b, V.d, OMEGA, 1, V.r, h->stream);
     launch_mg_restrict(C.n, V.cptr, V.cidx, V.cw, V.r, C.b, h->stream);
-    vcycle(h, l - 1, C.b, C.x);
+    vcycle(h, l - 1, C.b, C.x, hfine);
     launch_mg_prolong_add(V.n, V.par, V.pw, C.x, x, h->stream);
     launch_sym_smooth(sp, A, lda, x, b, V.d, OMEGA, 0, nullptr, h->stream);
     launch_sym_smooth(sp, A, lda, x, b, V.d, OMEGA, 0, nullptr, h->stream);
@@ -239,12 +265,15 @@ int fl_mg_setup(fl_handle* h, int nlevels, const int64_t* nv, const int32_t* par
     return FL_OK;
 }
 
-int fl_solve_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
-                double* relres) {
-    if (!h) return FL_EINVAL;
-    if (!h->mg.ready) return mfail(h, FL_ESTATE, "no multigrid hierarchy for the current matrix (fl_mg_setup)");
-    if (!(rtol >= 0.0) || maxit < 0) return mfail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
-    if (!b || !u) return mfail(h, FL_EINVAL, "null vector");
+}  // extern "C"
+
+namespace {
+
+// CG preconditioned by one V-cycle; the operator (of CG and of the finest
+// level of the cycle) is the handle's matrix or, with `hfine`, its cluster
+// approximation.
+int mg_pcg(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters, double* relres,
+           bool hfine) {
     HIPCHK(hipSetDevice(h->device));
     int rc = fl_solver_workspace(h);
     if (rc) return rc;
@@ -259,7 +288,7 @@ int fl_solve_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t m
     HIPCHK(hipEventRecord(e0, h->stream));
     launch_zero(u, n, h->stream);
     HIPCHK(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    vcycle(h, L - 1, r, z);
+    vcycle(h, L - 1, r, z, hfine);
     launch_dot2(r, z, r, n, h->w_part, nblk, G.sc, h->stream);  // rz_0, rr_0
     HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipGetLastError());
@@ -272,10 +301,11 @@ int fl_solve_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t m
     // iteration k: rz_k, rr_k at sc[2 (k & 1)], sc[2 (k & 1) + 1]; p.Ap at sc[4]
     while (status == FL_OK && bb > 0.0 && !(std::sqrt(rr) <= rtol * std::sqrt(bb)) && it < maxit) {
         const int cur = 2 * (it & 1), nxt = 2 * ((it + 1) & 1);
-        launch_symv(h->sym, h->dA, h->lda, p, q, h->stream);
+        if (hfine) hm_product(h, p, q);
+        else launch_symv(h->sym, h->dA, h->lda, p, q, h->stream);
         launch_dot2(p, q, q, n, h->w_part, nblk, G.sc + 4, h->stream);
         launch_mg_axpy(u, r, p, q, n, G.sc, cur, 4, h->stream);
-        vcycle(h, L - 1, r, z);
+        vcycle(h, L - 1, r, z, hfine);
         launch_dot2(r, z, r, n, h->w_part, nblk, G.sc + nxt, h->stream);
         launch_mg_pupdate(p, z, n, G.sc, nxt, cur, h->stream);
         HIPCHK(hipGetLastError());
@@ -310,6 +340,30 @@ int fl_solve_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t m
     if (status == FL_ENONFINITE) return mfail(h, FL_ENONFINITE, "non-finite residual");
     if (!(rel <= rtol)) return FL_ENOCONV;
     return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fl_solve_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
+                double* relres) {
+    if (!h) return FL_EINVAL;
+    if (!h->mg.ready) return mfail(h, FL_ESTATE, "no multigrid hierarchy for the current matrix (fl_mg_setup)");
+    if (!(rtol >= 0.0) || maxit < 0) return mfail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
+    if (!b || !u) return mfail(h, FL_EINVAL, "null vector");
+    return mg_pcg(h, b, u, rtol, maxit, iters, relres, false);
+}
+
+int fl_solve_cluster_mg(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
+                        double* relres) {
+    if (!h) return FL_EINVAL;
+    if (!h->mg.ready) return mfail(h, FL_ESTATE, "no multigrid hierarchy for the current matrix (fl_mg_setup)");
+    if (!h->hm.ready)
+        return mfail(h, FL_ESTATE, "no cluster approximation of the current matrix (fl_cluster_build)");
+    if (!(rtol >= 0.0) || maxit < 0) return mfail(h, FL_EINVAL, "rtol >= 0 and maxit >= 0 required");
+    if (!b || !u) return mfail(h, FL_EINVAL, "null vector");
+    return mg_pcg(h, b, u, rtol, maxit, iters, relres, true);
 }
 
 }  // extern "C"

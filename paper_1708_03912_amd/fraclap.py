@@ -39,7 +39,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
            "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
            "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry",
-           "fl_strong_form_cluster"]
+           "fl_strong_form_cluster", "fl_solve_cluster_mg"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -121,6 +121,7 @@ def lib():
                                              C.c_int32, vp]
         L.fl_indicators.argtypes = [vp, dp, vp, vp, C.c_int32, vp, vp]
         L.fl_solve_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
+        L.fl_solve_cluster_mg.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_solve.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
         L.fl_energy_error2.argtypes = [vp, dp, vp, vp, C.POINTER(dp)]
         L.fl_stats.argtypes = [vp, C.POINTER(FlStats)]
@@ -338,6 +339,15 @@ class Handle:
         rel = C.c_double()
         rc = self._check(lib().fl_solve_cluster(self.h, _ptr(b), _ptr(u), rtol, maxit, C.byref(it), C.byref(rel)),
                          allow=(FL_OK, FL_ENOCONV))
+        return it.value, rel.value, rc
+
+    def solve_cluster_mg(self, b, u, rtol=1e-12, maxit=1000):
+        """CG on the cluster approximation, preconditioned by one V-cycle whose
+        finest level smooths with the cluster product."""
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = self._check(lib().fl_solve_cluster_mg(self.h, _ptr(b), _ptr(u), rtol, maxit, C.byref(it),
+                                                   C.byref(rel)), allow=(FL_OK, FL_ENOCONV))
         return it.value, rel.value, rc
 
     def cluster_info(self) -> dict:

@@ -133,3 +133,99 @@ def test_cluster_degenerate():
     it, rel, rc = h.solve_cluster(e, e.clone())
     assert it == 0 and rc == F.FL_OK
     h.close()
+
+
+def _mg_cluster_handle(meshes, parents, s, m=4, leaf=16):
+    h = F.Handle(0)
+    h.set_mesh(meshes[-1])
+    n = h.assemble(s, F.default_opts())
+    h.mg_setup([len(x["verts"]) for x in meshes], parents)
+    h.cluster_build(m=m, eta=2.0, leaf=leaf)
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    h.load_vector_one(b)
+    return h, n, b
+
+
+def test_cluster_mg_parity():
+    """Multigrid-preconditioned CG on the cluster approximation against the
+    oracle's mg_pcg on the same hierarchy with the finest operator replaced
+    by the oracle's cluster matrix: the oracle's iteration count (+-1) and
+    the solution of A_H u = b."""
+    from oracle import multigrid as G
+    s = 0.75
+    meshes, parents = M.hierarchy(M.disk_for_cells(150, seed=4), 3)
+    mesh = meshes[-1]
+    h, n, b = _mg_cluster_handle(meshes, parents, s)
+    assert h.cluster_info()["far_pairs"] > 0
+    u = torch.zeros_like(b)
+    it, rel, rc = h.solve_cluster_mg(b, u, rtol=1e-12, maxit=200)
+    assert rc == F.FL_OK and rel <= 1e-12
+    dofs = [O.dof_nodes(len(x["verts"]), x["bfacets"], s) for x in meshes]
+    A, _, _ = O.assemble(mesh, s, oracle_orders(F.default_opts()))
+    Hd = H.dense(H.build(mesh, dofs[-1], A, s, m=4, eta=2.0, leaf=16), n)
+    # the diagonal blocks are copied from A, so the smoother's diagonal is A's
+    assert np.array_equal(np.diag(Hd), np.diag(A))
+    As, Ps = G.hierarchy_operators(A, parents, dofs, [len(x["verts"]) for x in meshes])
+    As[-1] = Hd
+    bo = O.load_vector_one(mesh, dofs[-1])
+    assert np.abs(b.cpu().numpy() - bo).max() <= 1e-13 * np.abs(bo).max()
+    _, ito = G.mg_pcg(As, Ps, bo, rtol=1e-12)
+    uo = np.linalg.solve(Hd, bo)
+    e = u.cpu().numpy() - uo
+    assert np.sqrt(e @ Hd @ e) <= 1e-10 * np.sqrt(uo @ Hd @ uo)
+    assert abs(it - ito) <= 1, (it, ito)
+    h.close()
+
+
+def test_cluster_mg_flat_under_refinement():
+    """The iteration count of the cluster operator's MG-PCG stays flat over
+    2..4 levels and within 2 of the dense operator's."""
+    s = 0.75
+    base = M.disk_for_cells(150, seed=4)
+    its = []
+    for L in (2, 3, 4):
+        meshes, parents = M.hierarchy(base, L)
+        h, n, b = _mg_cluster_handle(meshes, parents, s, m=5, leaf=24)
+        u = torch.zeros_like(b)
+        it, rel, rc = h.solve_cluster_mg(b, u, rtol=1e-10)
+        assert rc == F.FL_OK and rel <= 1e-10
+        ud = torch.zeros_like(b)
+        itd, _, rcd = h.solve_mg(b, ud, rtol=1e-10)
+        assert rcd == F.FL_OK and abs(it - itd) <= 2, (it, itd)
+        # the dense residual of the cluster solution: b - A u_H =
+        # (b - A_H u_H) + (A_H - A) u_H, the first at most 1e-10 |b|
+        yd, yh = torch.empty_like(b), torch.empty_like(b)
+        h.matvec(u, yd)
+        h.cluster_matvec(u, yh)
+        lhs = float(torch.linalg.norm(b - yd))
+        rhs = float(torch.linalg.norm(yh - yd)) + 1e-10 * float(torch.linalg.norm(b))
+        assert lhs <= 1.001 * rhs, (lhs, rhs)
+        its.append(it)
+        h.close()
+    assert its[-1] <= its[0] + 3, its
+
+
+def test_cluster_mg_errors():
+    s = 0.75
+    meshes, parents = M.hierarchy(M.disk_for_cells(150, seed=4), 2)
+    h = F.Handle(0)
+    h.set_mesh(meshes[-1])
+    n = h.assemble(s, F.default_opts())
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(b)
+    h.cluster_build(m=4, eta=2.0, leaf=16)
+    with pytest.raises(F.FraclapError) as e:
+        h.solve_cluster_mg(b, u)                      # no hierarchy
+    assert e.value.code == F.FL_ESTATE
+    h.assemble(s, F.default_opts())                   # discards both
+    h.mg_setup([len(x["verts"]) for x in meshes], parents)
+    with pytest.raises(F.FraclapError) as e:
+        h.solve_cluster_mg(b, u)                      # no cluster approximation
+    assert e.value.code == F.FL_ESTATE
+    h.cluster_build(m=4, eta=2.0, leaf=16)
+    with pytest.raises(F.FraclapError) as e:
+        h.solve_cluster_mg(b, u, rtol=-1.0)
+    assert e.value.code == F.FL_EINVAL
+    it, rel, rc = h.solve_cluster_mg(b, u, rtol=1e-10)
+    assert rc == F.FL_OK and it > 0
+    h.close()
