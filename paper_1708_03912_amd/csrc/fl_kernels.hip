@@ -118,7 +118,11 @@ template <int KO, class KP>
 __device__ __forceinline__ void far_pair2_fixed(const double* X, const double* Y, const KP& kp, double* SK,
                                                 double* ST, double* O) {
     constexpr int Q = KO * KO;
-    const int off = tri_off(KO);
+    // the rule's offset is opaque to the optimiser, so its constants are
+    // fetched by scalar loads on each call instead of being kept live (and
+    // spilled) across the caller's loop over pairs
+    int off = tri_off(KO);
+    asm volatile("" : "+s"(off));
     const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
     const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
     double px[Q], py[Q], G[Q], M[Q][3];
@@ -168,10 +172,13 @@ __device__ __forceinline__ void far_pair2_fixed(const double* X, const double* Y
     }
 }
 
+// KO = 0: order k at run time; KO = 2: the factorised form above; KO = 3, 4
+// (the orders of the closest separated pairs): the loop below with the
+// inner loop over K's points unrolled, its kernel evaluations independent.
 template <int KO, class KP>
 __device__ __forceinline__ void far_pair2(int k, const double* X, const double* Y, const KP& kp,
                                           double* SK, double* ST, double* O) {
-    if constexpr (KO > 0) {
+    if constexpr (KO > 0 && KO <= 2) {
         far_pair2_fixed<KO>(X, Y, kp, SK, ST, O);
         return;
     }
@@ -202,8 +209,10 @@ __device__ __forceinline__ void far_pair2(int k, const double* X, const double* 
         const double yy = Y[1] + cq[0] * fy0 + cq[1] * fy1;
         double gy = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
-        auto body = [&](int p) {
-            const double* cp = c_R.tri[off + p];
+        // opaque per iteration: the unrolled loop's factors are fetched by
+        // scalar loads on each pass rather than kept live (and spilled)
+        auto body = [&](int p, int offp) {
+            const double* cp = c_R.tri[offp + p];
             double dx, dy;
             if constexpr (KO > 0) {
                 dx = px[p] - yx;
@@ -225,11 +234,21 @@ __device__ __forceinline__ void far_pair2(int k, const double* X, const double* 
             t5 += cp[11] * kv;
         };
         if constexpr (KO > 0) {
+            // chunks of at most 9 points, each behind an opaque offset: the
+            // factors are fetched by scalar loads per chunk and pass rather
+            // than kept live (and spilled) across the loops
+            constexpr int CH = KO * KO <= 9 ? KO * KO : 4;
 #pragma unroll
-            for (int p = 0; p < KO * KO; ++p) body(p);
+            for (int p0 = 0; p0 < KO * KO; p0 += CH) {
+                int offp = off;
+                asm volatile("" : "+s"(offp));
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+                    if (p0 + j < KO * KO) body(p0 + j, offp);
+            }
         } else {
 #pragma unroll 1
-            for (int p = 0; p < Q; ++p) body(p);
+            for (int p = 0; p < Q; ++p) body(p, off);
         }
         const double wq = cq[2];
         SK[0] += wq * t0; SK[1] += wq * t1; SK[2] += wq * t2;
@@ -1010,6 +1029,10 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                 if constexpr (MIX) far_pair2_f32<2>(2, X, Y, P.pe, SK, ST, O);
                 else if constexpr (TAB) far_pair2<2>(2, X, Y, make_kpow_tab(pw), SK, ST, O);
                 else far_pair2<2>(2, X, Y, P.pe, SK, ST, O);
+            } else if (TAB && k == 3) {
+                if constexpr (TAB) far_pair2<3>(3, X, Y, make_kpow_tab(pw), SK, ST, O);
+            } else if (TAB && k == 4) {
+                if constexpr (TAB) far_pair2<4>(4, X, Y, make_kpow_tab(pw), SK, ST, O);
             } else {
                 if constexpr (TAB) far_pair<DIM, MIX>(k, X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
                 else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
