@@ -147,38 +147,44 @@ __global__ __launch_bounds__(64) void h_up_leaf_kernel(HDev H) {
 }
 
 // internal clusters of one level: xh[c][a] = sum_sons sum_b T_son[b][a] xh[son][b]
-__global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int* __restrict__ list) {
-    const int c = list[blockIdx.x];
-    if (H.M <= 64) {
-        // stage each son's shift coefficients in LDS (all loads in flight
-        // at once), its coefficients travel by shuffles
-        __shared__ double ts[64 * 64];
+__global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int4* __restrict__ list) {
+    const int4 e = list[blockIdx.x];  // {c, son 0, son 1, -}
+    const int c = e.x, M = H.M;
+    if (M <= 64) {
+        // both sons' shift coefficients staged in LDS (2 M^2 doubles of
+        // dynamic LDS), every load issued before the first product; the
+        // sons' coefficients travel by shuffles; son 0 is summed first
+        extern __shared__ double hdyn[];
         const int a = threadIdx.x;
-        double acc = 0.0;
-        for (int e = H.sptr[c]; e < H.sptr[c + 1]; ++e) {
-            const int sn = H.sidx[e];
-            const double* Ts = H.T + (long long)sn * H.M * H.M;
-            for (int i = a; i < H.M * H.M; i += 64) ts[i] = Ts[i];
-            const double xv = a < H.M ? H.xh[(long long)sn * H.M + a] : 0.0;
-            __syncthreads();
-            for (int b = 0; b < H.M; ++b) {
-                const double xb = __shfl(xv, b, 64);
-                if (a < H.M) acc = fma(ts[b * H.M + a], xb, acc);
-            }
-            __syncthreads();
+        const double* T0 = H.T + (long long)e.y * M * M;
+        const double* T1 = H.T + (long long)e.z * M * M;
+        for (int i = a; i < M * M; i += 64) {
+            hdyn[i] = T0[i];
+            hdyn[M * M + i] = T1[i];
         }
-        if (a < H.M) H.xh[(long long)c * H.M + a] = acc;
+        const double x0 = a < M ? H.xh[(long long)e.y * M + a] : 0.0;
+        const double x1 = a < M ? H.xh[(long long)e.z * M + a] : 0.0;
+        __syncthreads();
+        double acc = 0.0;
+        for (int b = 0; b < M; ++b) {
+            const double xb = __shfl(x0, b, 64);
+            if (a < M) acc = fma(hdyn[b * M + a], xb, acc);
+        }
+        for (int b = 0; b < M; ++b) {
+            const double xb = __shfl(x1, b, 64);
+            if (a < M) acc = fma(hdyn[M * M + b * M + a], xb, acc);
+        }
+        if (a < M) H.xh[(long long)c * M + a] = acc;
         return;
     }
-    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+    for (int a = threadIdx.x; a < M; a += blockDim.x) {
         double acc = 0.0;
-        for (int e = H.sptr[c]; e < H.sptr[c + 1]; ++e) {
-            const int sn = H.sidx[e];
-            const double* Ts = H.T + (long long)sn * H.M * H.M;
-            const double* xs = H.xh + (long long)sn * H.M;
-            for (int b = 0; b < H.M; ++b) acc = fma(Ts[b * H.M + a], xs[b], acc);
+        for (int sn : {e.y, e.z}) {
+            const double* Ts = H.T + (long long)sn * M * M;
+            const double* xs = H.xh + (long long)sn * M;
+            for (int b = 0; b < M; ++b) acc = fma(Ts[b * M + a], xs[b], acc);
         }
-        H.xh[(long long)c * H.M + a] = acc;
+        H.xh[(long long)c * M + a] = acc;
     }
 }
 
@@ -219,28 +225,29 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
 }
 
 // clusters of one level (>= 1): yh[c][b] += sum_a T_c[b][a] yh[parent][a]
-__global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int* __restrict__ list) {
-    const int c = list[blockIdx.x];
-    const double* Tc = H.T + (long long)c * H.M * H.M;
-    const double* yp = H.yh + (long long)H.cpar[c] * H.M;
-    if (H.M <= 64) {
-        __shared__ double ts[64 * 64];
+__global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restrict__ list) {
+    const int4 e = list[blockIdx.x];  // {c, parent, -, -}
+    const int c = e.x, M = H.M;
+    const double* Tc = H.T + (long long)c * M * M;
+    const double* yp = H.yh + (long long)e.y * M;
+    if (M <= 64) {
+        extern __shared__ double hdyn[];  // M^2 doubles of dynamic LDS
         const int b = threadIdx.x;
-        for (int i = b; i < H.M * H.M; i += 64) ts[i] = Tc[i];
-        const double yv = b < H.M ? yp[b] : 0.0;
+        for (int i = b; i < M * M; i += 64) hdyn[i] = Tc[i];
+        const double yv = b < M ? yp[b] : 0.0;
         __syncthreads();
         double acc = 0.0;
-        for (int a = 0; a < H.M; ++a) {
+        for (int a = 0; a < M; ++a) {
             const double ya = __shfl(yv, a, 64);
-            if (b < H.M) acc = fma(ts[b * H.M + a], ya, acc);
+            if (b < M) acc = fma(hdyn[b * M + a], ya, acc);
         }
-        if (b < H.M) H.yh[(long long)c * H.M + b] += acc;
+        if (b < M) H.yh[(long long)c * M + b] += acc;
         return;
     }
-    for (int b = threadIdx.x; b < H.M; b += blockDim.x) {
+    for (int b = threadIdx.x; b < M; b += blockDim.x) {
         double acc = 0.0;
-        for (int a = 0; a < H.M; ++a) acc = fma(Tc[b * H.M + a], yp[a], acc);
-        H.yh[(long long)c * H.M + b] += acc;
+        for (int a = 0; a < M; ++a) acc = fma(Tc[b * M + a], yp[a], acc);
+        H.yh[(long long)c * M + b] += acc;
     }
 }
 
@@ -306,13 +313,17 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
     if (H.n == 0) return;
     hipLaunchKernelGGL(h_gather_kernel, dim3(nb256(H.n)), dim3(256), 0, st, H, x);
     hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
+    // the lists hold four ints per cluster (device allocations: 256-byte aligned)
+    const size_t lds = H.M <= 64 ? sizeof(double) * H.M * H.M : 0;
     for (int l = 0; l < n_up; ++l)
         if (up_counts[l] > 0)
-            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 0, st, H, up_lists[l]);
+            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, H,
+                               (const int4*)up_lists[l]);
     hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0)
-            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), 0, st, H, down_lists[l]);
+            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, H,
+                               (const int4*)down_lists[l]);
     hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(256), 0, st, H, C, y);
 }
 

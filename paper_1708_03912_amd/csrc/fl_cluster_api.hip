@@ -288,12 +288,19 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
         for (int64_t K = 0; K < T; ++K)
             for (int a = 0; a < nper; ++a) vidx[fill[h->cells[nper * K + a]]++] = (int)K;
     }
-    // per-level cluster lists: upward (internal clusters, deepest first),
-    // downward (every cluster below the root, shallowest first)
+    // per-level cluster lists, four ints per entry so that a workgroup has
+    // every index it needs after one load: upward (internal clusters,
+    // deepest level first) {c, son 0, son 1, 0}, downward (every cluster
+    // below the root, shallowest first) {c, parent, 0, 0}.  The bisection
+    // gives every internal cluster exactly two sons.
     std::vector<std::vector<int>> up(depth + 1), down(depth + 1);
     for (int c = 0; c < nc; ++c) {
-        if (!cl[c].sons.empty()) up[cl[c].level].push_back(c);
-        if (c > 0) down[cl[c].level].push_back(c);
+        if (!cl[c].sons.empty()) {
+            if (cl[c].sons.size() != 2) return cfail(h, FL_EINVAL, "cluster tree: internal cluster without two sons");
+            for (int v : {c, cl[c].sons[0], cl[c].sons[1], 0}) up[cl[c].level].push_back(v);
+        }
+        if (c > 0)
+            for (int v : {c, cpar[c], 0, 0}) down[cl[c].level].push_back(v);
     }
     // device
     fl_hm& Hm = h->hm;
@@ -392,7 +399,7 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
             return rc;
         }
         Hm.up_lists.push_back(q);
-        Hm.up_counts.push_back((int)up[l].size());
+        Hm.up_counts.push_back((int)up[l].size() / 4);
     }
     for (int l = 1; l <= depth; ++l) {
         int* q = nullptr;
@@ -401,7 +408,7 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
             return rc;
         }
         Hm.down_lists.push_back(q);
-        Hm.down_counts.push_back((int)down[l].size());
+        Hm.down_counts.push_back((int)down[l].size() / 4);
     }
     launch_h_setup(H, h->dA, h->lda, -0.5 * (dim + 2.0 * h->s), h->stream);
     launch_h_diag(h->dA, h->lda, n, Hm.d, h->stream);
