@@ -399,17 +399,43 @@ __global__ __launch_bounds__(64) void sfc_mom_leaf_kernel(SfClDev C, SfDev D, co
 }
 
 // internal clusters of one level: mom[c][a] = sum_sons sum_b T_son[b][a] mom[son][b]
-__global__ __launch_bounds__(64) void sfc_up_kernel(SfClDev C, const int* __restrict__ list) {
-    const int c = list[blockIdx.x];
-    for (int a = threadIdx.x; a < C.M; a += blockDim.x) {
-        double acc = 0.0;
-        for (int e = C.sptr[c]; e < C.sptr[c + 1]; ++e) {
-            const int sn = C.sidx[e];
-            const double* Ts = C.T + (long long)sn * C.M * C.M;
-            const double* ms = C.mom + (long long)sn * C.M;
-            for (int b = 0; b < C.M; ++b) acc = fma(Ts[b * C.M + a], ms[b], acc);
+__global__ __launch_bounds__(64) void sfc_up_kernel(SfClDev C, const int4* __restrict__ list) {
+    const int4 e = list[blockIdx.x];  // {c, son 0, son 1, -}
+    const int c = e.x, M = C.M;
+    if (M <= 64) {
+        // both sons' shift coefficients in dynamic LDS (2 M^2 doubles), all
+        // loads issued before the first product; son 0 is summed first
+        extern __shared__ double sdyn[];
+        const int a = threadIdx.x;
+        const double* T0 = C.T + (long long)e.y * M * M;
+        const double* T1 = C.T + (long long)e.z * M * M;
+        for (int i = a; i < M * M; i += 64) {
+            sdyn[i] = T0[i];
+            sdyn[M * M + i] = T1[i];
         }
-        C.mom[(long long)c * C.M + a] = acc;
+        const double m0 = a < M ? C.mom[(long long)e.y * M + a] : 0.0;
+        const double m1 = a < M ? C.mom[(long long)e.z * M + a] : 0.0;
+        __syncthreads();
+        double acc = 0.0;
+        for (int b = 0; b < M; ++b) {
+            const double mb = __shfl(m0, b, 64);
+            if (a < M) acc = fma(sdyn[b * M + a], mb, acc);
+        }
+        for (int b = 0; b < M; ++b) {
+            const double mb = __shfl(m1, b, 64);
+            if (a < M) acc = fma(sdyn[M * M + b * M + a], mb, acc);
+        }
+        if (a < M) C.mom[(long long)c * M + a] = acc;
+        return;
+    }
+    for (int a = threadIdx.x; a < M; a += blockDim.x) {
+        double acc = 0.0;
+        for (int sn : {e.y, e.z}) {
+            const double* Ts = C.T + (long long)sn * M * M;
+            const double* ms = C.mom + (long long)sn * M;
+            for (int b = 0; b < M; ++b) acc = fma(Ts[b * M + a], ms[b], acc);
+        }
+        C.mom[(long long)c * M + a] = acc;
     }
 }
 
@@ -444,14 +470,29 @@ __global__ __launch_bounds__(256) void sfc_far_kernel(SfClDev C, double pe) {
 }
 
 // clusters of one level (>= 1): loc[c][b] += sum_a T_c[b][a] loc[parent][a]
-__global__ __launch_bounds__(64) void sfc_down_kernel(SfClDev C, const int* __restrict__ list) {
-    const int c = list[blockIdx.x];
-    const double* Tc = C.T + (long long)c * C.M * C.M;
-    const double* lp = C.loc + (long long)C.cpar[c] * C.M;
-    for (int b = threadIdx.x; b < C.M; b += blockDim.x) {
+__global__ __launch_bounds__(64) void sfc_down_kernel(SfClDev C, const int4* __restrict__ list) {
+    const int4 e = list[blockIdx.x];  // {c, parent, -, -}
+    const int c = e.x, M = C.M;
+    const double* Tc = C.T + (long long)c * M * M;
+    const double* lp = C.loc + (long long)e.y * M;
+    if (M <= 64) {
+        extern __shared__ double sdyn[];  // M^2 doubles of dynamic LDS
+        const int b = threadIdx.x;
+        for (int i = b; i < M * M; i += 64) sdyn[i] = Tc[i];
+        const double lv = b < M ? lp[b] : 0.0;
+        __syncthreads();
         double acc = 0.0;
-        for (int a = 0; a < C.M; ++a) acc = fma(Tc[b * C.M + a], lp[a], acc);
-        C.loc[(long long)c * C.M + b] += acc;
+        for (int a = 0; a < M; ++a) {
+            const double la = __shfl(lv, a, 64);
+            if (b < M) acc = fma(sdyn[b * M + a], la, acc);
+        }
+        if (b < M) C.loc[(long long)c * M + b] += acc;
+        return;
+    }
+    for (int b = threadIdx.x; b < M; b += blockDim.x) {
+        double acc = 0.0;
+        for (int a = 0; a < M; ++a) acc = fma(Tc[b * M + a], lp[a], acc);
+        C.loc[(long long)c * M + b] += acc;
     }
 }
 
@@ -553,13 +594,17 @@ void launch_sfc_eval(const SfClDev& C, const SfDev& D, const double* sx, const d
                      const int* down_counts, int n_down, double* part0, hipStream_t st) {
     if (C.nc == 0) return;
     hipLaunchKernelGGL(sfc_mom_leaf_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy);
+    // four ints per list entry (device allocations: 256-byte aligned)
+    const size_t lds = C.M <= 64 ? sizeof(double) * C.M * C.M : 0;
     for (int l = 0; l < n_up; ++l)
         if (up_counts[l] > 0)
-            hipLaunchKernelGGL(sfc_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 0, st, C, up_lists[l]);
+            hipLaunchKernelGGL(sfc_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, C,
+                               (const int4*)up_lists[l]);
     hipLaunchKernelGGL(sfc_far_kernel, dim3((unsigned)C.nc), dim3(256), 0, st, C, D.pe);
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0)
-            hipLaunchKernelGGL(sfc_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), 0, st, C, down_lists[l]);
+            hipLaunchKernelGGL(sfc_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, C,
+                               (const int4*)down_lists[l]);
     hipLaunchKernelGGL(sfc_leaf_eval_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy, D.pe, part0);
 }
 

@@ -531,10 +531,16 @@ int sf_cl_plan(fl_handle* h, int m, double eta, int leaf) {
     }
     std::vector<double> tnode(m);
     for (int k = 0; k < m; ++k) tnode[k] = 0.5 - 0.5 * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * m));
+    // per-level lists, four ints per entry: upward {c, son 0, son 1, 0},
+    // downward {c, parent, 0, 0} (the bisection gives two sons)
     std::vector<std::vector<int>> up(depth + 1), down(depth + 1);
     for (int c = 0; c < nc; ++c) {
-        if (!cl[c].sons.empty()) up[cl[c].level].push_back(c);
-        if (c > 0) down[cl[c].level].push_back(c);
+        if (!cl[c].sons.empty()) {
+            if (cl[c].sons.size() != 2) return sfail(h, FL_EINVAL, "cell tree: internal cluster without two sons");
+            for (int v : {c, cl[c].sons[0], cl[c].sons[1], 0}) up[cl[c].level].push_back(v);
+        }
+        if (c > 0)
+            for (int v : {c, cpar[c], 0, 0}) down[cl[c].level].push_back(v);
     }
     SfClDev C{};
     C.m = m;
@@ -581,7 +587,7 @@ int sf_cl_plan(fl_handle* h, int m, double eta, int leaf) {
             return rc;
         }
         S.cl_up.push_back(q);
-        S.cl_upc.push_back((int)up[l].size());
+        S.cl_upc.push_back((int)up[l].size() / 4);
     }
     for (int l = 1; l <= depth; ++l) {
         int* q = nullptr;
@@ -590,7 +596,7 @@ int sf_cl_plan(fl_handle* h, int m, double eta, int leaf) {
             return rc;
         }
         S.cl_down.push_back(q);
-        S.cl_downc.push_back((int)down[l].size());
+        S.cl_downc.push_back((int)down[l].size() / 4);
     }
     launch_sfc_transfer(C, h->stream);
     HIPCHK(hipGetLastError());
