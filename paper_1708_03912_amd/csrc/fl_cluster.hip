@@ -276,9 +276,20 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
                 const int t = H.ndst[e];
                 const int rt = H.clo[t], nt = H.chi[t] - rt;
                 const double* blk = H.An + H.noff[e] + i;
-                double s = 0.0;
-                for (int j = 0; j < nt; ++j) s = fma(blk[(long long)j * nr], H.xp[rt + j], s);
-                acc += s;
+                const double* xt = H.xp + rt;
+                // four partial sums over columns j mod 4: four loads in flight
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int j = 0;
+                for (; j + 4 <= nt; j += 4) {
+                    const double b0 = blk[(long long)j * nr], b1 = blk[(long long)(j + 1) * nr];
+                    const double b2 = blk[(long long)(j + 2) * nr], b3 = blk[(long long)(j + 3) * nr];
+                    s0 = fma(b0, xt[j], s0);
+                    s1 = fma(b1, xt[j + 1], s1);
+                    s2 = fma(b2, xt[j + 2], s2);
+                    s3 = fma(b3, xt[j + 3], s3);
+                }
+                for (; j < nt; ++j) s0 = fma(blk[(long long)j * nr], xt[j], s0);
+                acc += (s0 + s1) + (s2 + s3);
             }
         }
         red[g][lane] = acc;
