@@ -307,7 +307,7 @@ struct SfClDev {
 void launch_sfc_transfer(const SfClDev& Cl, hipStream_t st);
 void launch_sfc_eval(const SfClDev& Cl, const SfDev& D, const double* sx, const double* sy,
                      const int* const* up_lists, const int* up_counts, int n_up, const int* const* down_lists,
-                     const int* down_counts, int n_down, double* part0, hipStream_t st);
+                     const int* down_counts, int n_down, const double* tab, double* part0, hipStream_t st);
 void launch_sf_sources(const SfDev& D, const double* u, hipStream_t st);
 void launch_sf_far(const SfDev& D, const double* sx, const double* sy, const double* bsx, const double* bsy,
                    long long chunk, int nch, int nchb, const double* tab, double* part, bool logk,

@@ -441,7 +441,12 @@ __global__ __launch_bounds__(64) void sfc_up_kernel(SfClDev C, const int4* __res
 
 // far field: loc[s][a] = sum over admissible (s, t) of sum_b g(xi_a^s, xi_b^t)
 // mom[t][b]; four lane groups over the pairs, added in group order
-__global__ __launch_bounds__(256) void sfc_far_kernel(SfClDev C, double pe) {
+__global__ __launch_bounds__(256) void sfc_far_kernel(SfClDev C, const double* __restrict__ tab) {
+    // the kernel power by the LDS tables of the direct far sum (same exponent)
+    __shared__ __align__(16) double pw[768];
+    load_tab(pw, tab);
+    __syncthreads();
+    const KPowTab P = tab_pow(pw, tab);
     __shared__ double red[4][64];
     const int c = blockIdx.x;
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -458,7 +463,7 @@ __global__ __launch_bounds__(256) void sfc_far_kernel(SfClDev C, double pe) {
                     double xb, yb;
                     sfc_pt(C, t, b, xb, yb);
                     const double dx = xa - xb, dy = ya - yb;
-                    acc = fma(kpow(fma(dx, dx, dy * dy), pe), mt[b], acc);
+                    acc = fma(P(fma(dx, dx, dy * dy)), mt[b], acc);
                 }
             }
         }
@@ -499,8 +504,14 @@ __global__ __launch_bounds__(64) void sfc_down_kernel(SfClDev C, const int4* __r
 // leaves: every evaluation point of the leaf's cells adds its local
 // expansion and the direct sums over the near leaves' sources to part0
 __global__ __launch_bounds__(64) void sfc_leaf_eval_kernel(SfClDev C, SfDev D, const double* __restrict__ sx,
-                                                           const double* __restrict__ sy, double pe,
+                                                           const double* __restrict__ sy,
+                                                           const double* __restrict__ tab,
                                                            double* __restrict__ part0) {
+    // the kernel power by the LDS tables of the direct far sum (same exponent)
+    __shared__ __align__(16) double pw[768];
+    load_tab(pw, tab);
+    __syncthreads();
+    const KPowTab P = tab_pow(pw, tab);
     const int li = blockIdx.x;
     const int c = C.leaf[li];
     const int np = (C.chi[c] - C.clo[c]) * D.Q;
@@ -518,7 +529,7 @@ __global__ __launch_bounds__(64) void sfc_leaf_eval_kernel(SfClDev C, SfDev D, c
                     for (int j = 0; j < D.qf; ++j) {
                         const long long k = f * D.qf + j;
                         const double dx = x - sx[k], dy = y - sy[k];
-                        acc = fma(D.sc[k], kpow(fma(dx, dx, dy * dy), pe), acc);
+                        acc = fma(D.sc[k], P(fma(dx, dx, dy * dy)), acc);
                     }
                 }
         }
@@ -591,7 +602,7 @@ void launch_sfc_transfer(const SfClDev& C, hipStream_t st) {
 
 void launch_sfc_eval(const SfClDev& C, const SfDev& D, const double* sx, const double* sy,
                      const int* const* up_lists, const int* up_counts, int n_up, const int* const* down_lists,
-                     const int* down_counts, int n_down, double* part0, hipStream_t st) {
+                     const int* down_counts, int n_down, const double* tab, double* part0, hipStream_t st) {
     if (C.nc == 0) return;
     hipLaunchKernelGGL(sfc_mom_leaf_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy);
     // four ints per list entry (device allocations: 256-byte aligned)
@@ -600,12 +611,12 @@ void launch_sfc_eval(const SfClDev& C, const SfDev& D, const double* sx, const d
         if (up_counts[l] > 0)
             hipLaunchKernelGGL(sfc_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, C,
                                (const int4*)up_lists[l]);
-    hipLaunchKernelGGL(sfc_far_kernel, dim3((unsigned)C.nc), dim3(256), 0, st, C, D.pe);
+    hipLaunchKernelGGL(sfc_far_kernel, dim3((unsigned)C.nc), dim3(256), 0, st, C, tab);
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0)
             hipLaunchKernelGGL(sfc_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, C,
                                (const int4*)down_lists[l]);
-    hipLaunchKernelGGL(sfc_leaf_eval_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy, D.pe, part0);
+    hipLaunchKernelGGL(sfc_leaf_eval_kernel, dim3((unsigned)C.nleaf), dim3(64), 0, st, C, D, sx, sy, tab, part0);
 }
 
 }  // namespace fl

@@ -708,7 +708,7 @@ int fl_strong_form_cluster(fl_handle* h, double s, const double* u, int32_t k_ev
     Dz.ns = 0;
     launch_sf_far(Dz, S.sx, S.sy, S.bsx, S.bsy, S.chunk, 1, S.nchb, S.tab, S.part, false, h->stream);
     launch_sfc_eval(S.C, D, S.sx, S.sy, S.cl_up.data(), S.cl_upc.data(), (int)S.cl_up.size(), S.cl_down.data(),
-                    S.cl_downc.data(), (int)S.cl_down.size(), S.part, h->stream);
+                    S.cl_downc.data(), (int)S.cl_down.size(), S.tab, S.part, h->stream);
     launch_sf_near(D, u, S.part, 1 + S.nchb, S.tab, Lu, false, h->stream);
     HIPCHK(hipGetLastError());
     return FL_OK;
