@@ -1164,7 +1164,8 @@ __device__ void ident2(const double* X, double s, double pe, int k, double* M6) 
 
 // Boundary facet e = [p0,p1] (inward normal n) separated from triangle K:
 // order-k triangle rule on K times k-point Gauss-Legendre on e.
-__device__ void bnd_far2(const double* X, const double* fe, double pe, int k, double* M6) {
+template <class KP>
+__device__ void bnd_far2(const double* X, const double* fe, const KP& kp, int k, double* M6) {
     const int to = tri_off(k), go = gl_off(k);
     const int Q = k * k;
     double area = 0.5 * fabs((X[2] - X[0]) * (X[5] - X[1]) - (X[4] - X[0]) * (X[3] - X[1]));
@@ -1179,7 +1180,7 @@ __device__ void bnd_far2(const double* X, const double* fe, double pe, int k, do
         for (int q = 0; q < k; ++q) {
             double t = c_R.gl_x[go + q];
             double d0 = xx - (fe[0] + t * e0), d1 = xy - (fe[1] + t * e1);
-            g += c_R.gl_w[go + q] * (fe[4] * d0 + fe[5] * d1) * kpow(d0 * d0 + d1 * d1, pe);
+            g += c_R.gl_w[go + q] * (fe[4] * d0 + fe[5] * d1) * kp(d0 * d0 + d1 * d1);
         }
         g *= area * Le * c_R.tw[to + p];
         double lam[3] = {l0, l1, l2};
@@ -1297,6 +1298,14 @@ constexpr int FACET_CHUNK = 4;
 // is added to the element's diagonal-block accumulator S atomically.
 template <int DIM>
 __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
+    // 2D: the kernel power of the separated element-edge pairs by the LDS
+    // tables (same exponent as the separated element pairs), loaded before
+    // any thread leaves
+    __shared__ __align__(16) double pw[DIM == 2 ? 768 : 1];
+    if constexpr (DIM == 2) {
+        load_pow_tables(pw);
+        __syncthreads();
+    }
     const int K = blockIdx.x * blockDim.x + threadIdx.x;
     if (K >= P.T) return;
     const int e_lo = blockIdx.y * FACET_CHUNK;
@@ -1402,7 +1411,7 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
                 double hm = h2k > le2 ? h2k : le2;
                 int cls = order_class(dist2_nc(cx, cy, m0, m1, 2), hm, P.ncls, P.th2);
                 double M6[6] = {0, 0, 0, 0, 0, 0};
-                bnd_far2(X, fe, P.pe, P.kfb[cls], M6);
+                bnd_far2(X, fe, make_kpow_tab(pw), P.kfb[cls], M6);
                 for (int m = 0; m < 6; ++m) acc[m] += fb * M6[m];
             }
         }
