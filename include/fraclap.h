@@ -129,7 +129,7 @@ typedef struct {
     double mass_shift;                   /* mu >= 0: the assembled matrix is
                                             A^s + mu M, M the P1 mass matrix
                                             (M_ij = integral of phi_i phi_j)
-                                            on the DOFs.  Sec. 6: a backward
+                                            on the DOFs.  Sec. 5: a backward
                                             Euler step of the fractional
                                             heat equation solves
                                             (M + dt A^s) u = b, i.e.
@@ -363,7 +363,7 @@ int fl_indicators(fl_handle *h, double s, const double *Lu, const double *f, int
 /* y = M x with the P1 mass matrix on the DOFs of the last assembly
  * (M_ij = integral of phi_i phi_j, exactly: |K| (1 + delta_ab) /
  * ((d+1)(d+2)) per element), e.g. the right-hand side M u^n of an implicit
- * heat step (Sec. 6).  x, y: device, length n, not aliased.  FL_ESTATE
+ * heat step (Sec. 5).  x, y: device, length n, not aliased.  FL_ESTATE
  * before fl_assemble. */
 int fl_mass_matvec(fl_handle *h, const double *x, double *y);
 

@@ -14,7 +14,7 @@ References are to Ainsworth & Glusa, arXiv:1708.03912:
                otherwise), stiffness matrix A^s.
   * Sec. 5   -- element-pair decomposition, Gauss-type quadrature with
                regularised touching pairs, Jacobi-preconditioned CG.
-  * Sec. 6   -- implicit steps of the fractional heat equation,
+  * Sec. 5   -- implicit steps of the fractional heat equation,
                (M + dt A^s) u = b with the P1 mass matrix M.
   * Sec. 7   -- closed-form solutions on the unit ball, energy-error
                identity ||u-u_h||^2 = (f,u) - (f,u_h).
@@ -43,15 +43,24 @@ _LIB = os.path.join(_HERE, "libfl_oracle.so")
 MAXK = 32
 
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (FP64, no fast-math, no contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-             "-D_DEFAULT_SOURCE", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_SAN = os.path.join(_HERE, "libfl_oracle_san.so")
+_CFLAGS = ["-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_DEFAULT_SOURCE",
+           "-shared", "-fPIC"]
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the C oracle with gcc (FP64, no fast-math, no contraction).
+    ``sanitize``: a separate AddressSanitizer + UndefinedBehaviorSanitizer
+    build (libfl_oracle_san.so, loaded when FL_ORACLE_SANITIZED=1; the
+    process must preload libasan)."""
+    out = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"] if sanitize else ["-O3"])
+        subprocess.check_call(["gcc"] + opt + _CFLAGS + [_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -60,8 +69,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        san = os.environ.get("FL_ORACLE_SANITIZED") == "1"
+        path = build(sanitize=san)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_cdn.restype = C.c_double
         L.orc_cdn.argtypes = [C.c_int, C.c_double]
@@ -359,7 +369,7 @@ def load_vector_one(mesh, dofs):
 
 
 def mass_matrix(mesh, dofs):
-    """P1 mass matrix M_ij = int phi_i phi_j on the DOF set (Sec. 6: the
+    """P1 mass matrix M_ij = int phi_i phi_j on the DOF set (Sec. 5: the
     fractional heat equation's implicit step solves (M + dt A^s) u = b).
     On each cell the integral of lambda_a lambda_b is |K| (1 + delta_ab) /
     ((d+1)(d+2))."""

@@ -1,6 +1,6 @@
-"""Implicit steps of the fractional heat equation (Sec. 6) on the GPU:
+"""Implicit steps of the fractional heat equation (Sec. 5) on the GPU:
 mass-shifted assembly A^s + mu M, the mass product, and backward Euler
-steps against the CPU oracle's dense solves; the Sec. 6 lemma's bounded
+steps against the CPU oracle's dense solves; the Sec. 5 lemma's bounded
 iteration counts for dt = h^(2s)."""
 import math
 
@@ -110,7 +110,7 @@ def test_backward_euler_steps(s):
 
 
 def test_heat_iterations_bounded_under_refinement():
-    """Sec. 6 lemma: with dt = h^(2s) the Jacobi-preconditioned system
+    """Sec. 5 lemma: with dt = h^(2s) the Jacobi-preconditioned system
     M + dt A^s has a condition number bounded under refinement, so the CG
     iteration count stays nearly flat from ~1000 to ~4000 cells, while the
     Poisson system's grows (s = 0.75)."""

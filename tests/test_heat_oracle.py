@@ -1,5 +1,5 @@
 """Pins of the oracle's P1 mass matrix and of the implicit heat step
-(Sec. 6: (M + dt A^s) u = b) against facts other than its own formula."""
+(Sec. 5: (M + dt A^s) u = b) against facts other than its own formula."""
 import math
 import os
 import sys
@@ -69,7 +69,7 @@ def test_mass_matrix_1d_uniform():
 def test_heat_step_fixed_point_and_conditioning():
     """The Poisson solution is the fixed point of the implicit step, and with
     dt = h^(2s) the Jacobi-scaled (M + dt A^s) stays well conditioned under
-    refinement while A^s does not (Sec. 6 lemma on the condition number)."""
+    refinement while A^s does not (Sec. 5 lemma on the condition number)."""
     s = 0.75
     kappa = {}
     for T in (300, 1200):

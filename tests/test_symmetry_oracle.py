@@ -107,3 +107,45 @@ def test_one_of_each_cross_couple(K, s):
     assert np.abs(Aq - Aq.T).max() <= 1e-14 * np.abs(Aq).max()
     A, dofs, cnt_full = O.assemble(mesh, s, O.Orders())
     assert cnt_q.sum() <= (1.0 / K + 0.05) * cnt_full.sum() + 1
+
+
+# one order for every separated pair: no distance-class threshold, so a
+# rotated copy of a pair takes the same rule as the pair itself
+_ONE_CLASS = O.Orders(k_touch=5, k_touch_bnd=5, theta=[], k_far=[3], k_far_bnd=[3])
+
+
+@pytest.mark.parametrize("K,s", [(2, 0.3), (4, 0.75)])
+def test_weighted_pair_sum_is_the_fold_exactly(K, s):
+    """With a single separated-pair order the weighted pair sum is the
+    definition P^T A P / K up to rounding, both when each couple of equal
+    cross pairs counts twice with weight 1/2 and when one member counts with
+    weight 1.  (For K = 2, 4 the images keep the vertex-id order of every
+    touching pair, so the touching rules are the same on every copy.)"""
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.25, K, seed=5)
+    A, dofs, _ = O.assemble(mesh, s, _ONE_CLASS)
+    b = O.load_vector_one(mesh, dofs)
+    Ar, br, red = SY.reduce(A, b, dofs, vfold, K)
+    Ah, red_h, _ = SY.assemble_reduced(mesh, s, _ONE_CLASS, vfold, Tw)
+    Aq, red_q, _ = SY.assemble_reduced(mesh, s, _ONE_CLASS, vfold, Tw, pre=pre, rot=rot, K=K)
+    assert np.array_equal(red, red_h) and np.array_equal(red, red_q)
+    scale = np.abs(Ar).max()
+    assert np.abs(Ah - Ar).max() <= 1e-12 * scale
+    assert np.abs(Aq - Ar).max() <= 1e-12 * scale
+    assert np.linalg.norm(Aq - Ar) <= 1e-12 * np.linalg.norm(Ar)
+
+
+def test_weighted_pair_sum_gap_is_the_touching_rules():
+    """K = 8: rotated copies of a touching pair are labelled in another
+    vertex-id order, so their regularised rules differ by the rules' own
+    error; the gap to P^T A P / K falls with the touching order."""
+    K, s = 8, 0.5
+    mesh, vfold, Tw, pre, rot = M.disk_symmetric(0.25, K, seed=5)
+    gaps = []
+    for kt in (5, 10):
+        ords = O.Orders(k_touch=kt, k_touch_bnd=kt, theta=[], k_far=[3], k_far_bnd=[3])
+        A, dofs, _ = O.assemble(mesh, s, ords)
+        b = O.load_vector_one(mesh, dofs)
+        Ar, _, _ = SY.reduce(A, b, dofs, vfold, K)
+        Aq, _, _ = SY.assemble_reduced(mesh, s, ords, vfold, Tw, pre=pre, rot=rot, K=K)
+        gaps.append(np.abs(Aq - Ar).max() / np.abs(Ar).max())
+    assert gaps[1] <= 1e-9 and gaps[1] <= 1e-2 * gaps[0]
