@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the dense fractional-Laplacian hot path on one MI355X.
 
-Workload (unit disk, the paper's 2D test domain, Sec. 7): seeded jittered
-Delaunay mesh with ~7.9k triangles (~4k DOFs), s in {0.25, 0.75}, f = 1.
-One step = for each s: mesh ingest (fl_set_mesh), FP64 assembly of A^s
-(all element pairs and element/boundary-facet pairs), load vector,
-Jacobi-PCG to ||r|| <= 1e-12 ||b||, energy-norm error against the closed-form
-solution.  Everything runs in libfraclap.so; inputs are resident before the
-timed region.
+Default workload (the paper's 2D test domain, Sec. 7, at the largest size
+that one GPU holds): unit disk, seeded jittered-Delaunay quasi-uniform mesh
+of 199,452 triangles, 99,205 interior DOFs (the FP64 matrix takes 80 GB),
+s in {0.25, 0.75}, f = 1.  One step = for each s: mesh ingest
+(fl_set_mesh), FP64 assembly of A^s (all element pairs and
+element/boundary-facet pairs), load vector, Jacobi-PCG to
+||r|| <= 1e-10 ||b||, energy-norm error against the closed-form solution.
+Everything runs in libfraclap.so; inputs are resident before the timed
+region.  ``--workload disk8k`` runs the ~7.9k-triangle disk instead.
 
 Prints ONE JSON line (rank 0, N = 1).  Metric: element-pair quadratures per
 second over the whole step (pairs = T(T+1)/2 element pairs + T*B
 element/facet pairs per assembly), plus the dense matvec bandwidth, the
-roofline of the dominant kernel and the CPU oracle baseline.
+roofline of the dominant kernel (and of the other one), the mixed-precision
++ surrogate form against FP64 at equal energy-norm error on the same
+workload, the extra legs (7.9k-triangle disk; batched solves of the
+~16k-DOF disk with 8 values of s and 64 right-hand sides; the surrogate on
+the graded L-shape) and the CPU oracle baseline.
 """
 import argparse
 import json
@@ -27,21 +33,28 @@ sys.path.insert(0, ROOT)
 METRIC = "element-pair quadratures/s & matvec GB/s; mixed+surrogate vs FP64 at equal err"
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic FP64 work per kernel evaluation |x-y|^{-2-2s} on the separated
-# path: r^2 from the two mapped points (14 flops incl. 4 FMAs of the maps),
-# 10 FMAs of accumulation (20 flops), and a pow = log2 + multiply + exp2,
-# counted at 21 flops each for log2 / exp2 (degree-~9 polynomial + reduction)
-# and 1 for the multiply.
-FLOPS_PER_EVAL = 14 + 20 + 21 + 1 + 21
+# algorithmic work per kernel evaluation |x - y|^{-2-2s} on the separated
+# path: r^2 from the two mapped points (2 differences, 2 squares, 1 add),
+# the power's multiply (pe * log r^2), and four FMAs of accumulation
+# (8 flops) -- 14 flops -- plus two transcendentals (log, exp), which are
+# counted apart.
+FLOPS_PER_EVAL = 14
+TRANS_PER_EVAL = 2
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cells", type=int, default=8000, help="target triangle count of the disk mesh")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("disk200k", "disk8k"), default="disk200k",
+                    help="disk200k: ~2e5 triangles, ~1e5 interior DOFs (default); disk8k: ~7.9k triangles")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FL_MIXED + surrogate leg on the benchmark workload")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 7.9k-triangle disk leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=64, help="DOF rows of the all-core oracle sample")
+    ap.add_argument("--cpu-rows-1core", type=int, default=2, help="DOF rows of the one-core oracle sample")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (disk ~16k DOFs, 8 values of s, 64 right-hand sides)")
     ap.add_argument("--batch-cells", type=int, default=32000)
@@ -54,21 +67,12 @@ def parse():
     ap.add_argument("--sur-train", type=int, default=65536, help="training pairs of the surrogate")
     ap.add_argument("--sur-steps", type=int, default=20000, help="Adam steps of the surrogate")
     ap.add_argument("--sur-tol", type=float, default=0.02, help="certified bound for the surrogate")
-    ap.add_argument("--c5", action="store_true",
-                    help="run only the large-disk leg (~2e5 triangles, ~1e5 DOFs, 80 GB FP64 matrix): plain "
-                         "FP64 vs FL_MIXED + surrogate, s in {0.25, 0.75}, and print its object")
-    ap.add_argument("--no-mg", action="store_true",
-                    help="skip the multigrid leg (nested disk meshes up to ~32k triangles)")
+    ap.add_argument("--all-legs", action="store_true",
+                    help="also run the multigrid, a posteriori, cluster and symmetry legs")
     ap.add_argument("--only-mg", action="store_true", help="run only the multigrid leg and print its object")
-    ap.add_argument("--no-indicators", action="store_true",
-                    help="skip the a posteriori leg (strong form + indicators on the disk, adaptive loops)")
     ap.add_argument("--only-indicators", action="store_true",
                     help="run only the a posteriori leg and print its object")
-    ap.add_argument("--no-cluster", action="store_true",
-                    help="skip the cluster leg (H-matrix approximation of disks of ~8k / 32k / 128k triangles)")
     ap.add_argument("--only-cluster", action="store_true", help="run only the cluster leg and print its object")
-    ap.add_argument("--no-symmetry", action="store_true",
-                    help="skip the symmetry leg (8-fold symmetric disk, reduced vs full system)")
     ap.add_argument("--only-symmetry", action="store_true", help="run only the symmetry leg and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
@@ -104,6 +108,134 @@ def copy_calib(mib):
     print(json.dumps({"copy_calib_KiB_per_launch": mib * 1024, "launches": 3}), flush=True)
 
 
+def ball_fu(s):
+    """(f, u) for f = 1 on the unit disk (Sec. 7 closed form
+    u = c (1 - |x|^2)^s, c = 2^{-2s} Gamma(1) / Gamma(1 + s)^2 in 2D):
+    c pi / (s + 1)."""
+    c = 2.0 ** (-2 * s) / (math.gamma(1 + s) * math.gamma(1 + s))
+    return c * math.pi / (s + 1.0)
+
+
+def dense_leg(args, mesh, svals, dof_mode, rtol, steps, warmup):
+    """The dense FP64 path, timed over whole steps.  One step = for each s:
+    mesh ingest (fl_set_mesh), FP64 assembly, load vector (f = 1),
+    Jacobi-PCG to ||r|| <= rtol ||b||, energy-norm error against the
+    closed form.  Returns the timing, per-s results, the roofline inputs
+    and the handle (holding A for the last s) with the solutions."""
+    import torch
+    from paper_1708_03912_amd import fraclap as F
+    T, B = len(mesh["cells"]), len(mesh["bfacets"])
+    opts = F.make_opts(dof_mode=dof_mode)
+    h = F.Handle(0)
+    bufs, result = {}, {}
+
+    def step():
+        for s in svals:
+            h.set_mesh(mesh)
+            n = h.assemble(s, opts)
+            if s not in bufs or bufs[s][0].numel() != n:
+                bufs[s] = (torch.empty(n, dtype=torch.float64, device="cuda"),
+                           torch.empty(n, dtype=torch.float64, device="cuda"))
+            b, u = bufs[s]
+            h.load_vector_one(b)
+            it, rel, rc = h.solve(b, u, rtol=rtol, maxit=20000)
+            e2 = h.energy_error2(ball_fu(s), b, u)
+            st = h.stats()
+            result[s] = dict(n=n, iters=it, relres=rel, e2=e2, t_asm=st.t_assemble_ms, t_far=st.t_far_ms,
+                             t_self=st.t_self_ms, t_touch=st.t_touch_ms, t_scatter=st.t_scatter_ms,
+                             t_solve=st.t_solve_ms, t_cgk=st.t_cg_kernels_ms, cg_launched=st.cg_launched,
+                             t_plan=st.t_plan_ms,
+                             pairs_far=list(st.pairs_far)[:opts.n_classes + 1],
+                             far_evals=sum(st.pairs_far[m] * (opts.k_far[m] ** 2) ** 2
+                                           for m in range(opts.n_classes + 1)))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    acc = {k: [] for k in ("t_far", "t_asm", "t_solve", "t_cgk", "cg_launched")}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        for k in acc:
+            acc[k].append(sum(result[s][k] for s in svals))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    pairs_per_step = len(svals) * (T * (T + 1) // 2 + T * B)
+    mean = {k: sum(v) / len(v) for k, v in acc.items()}
+    return dict(h=h, bufs=bufs, result=result, ms_per_step=ms_per_step, pairs_per_step=pairs_per_step,
+                mean=mean, T=T, B=B, opts=opts)
+
+
+def matvec_rate(h, reps=10):
+    """fl_matvec (symmetric FP64 product from the upper triangle) timed with
+    events on the library's stream (torch's current stream)."""
+    import torch
+    n = h.n
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        h.matvec(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.matvec(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tri = n * (n + 1) // 2 * 8 + 2 * n * 8
+    return {"ms": round(ms, 4), "GBps": round(tri / (ms * 1e-3) / 1e9, 1),
+            "bytes": tri, "full_matrix_equiv_GBps": round((n * n * 8 + 2 * n * 8) / (ms * 1e-3) / 1e9, 1)}
+
+
+def rooflines(D, svals, cache_resident):
+    """Roofline objects of the two kernels that share the step: the
+    separated-pair assembly kernels (FP64 VALU) and the CG iteration
+    (symmetric product, HBM).  Algorithmic work: 14 FP64 flops per kernel
+    evaluation (r^2 from the mapped points 5, the power's multiply 1, four
+    FMAs of accumulation 8) plus 2 transcendentals (log, exp) counted apart;
+    the product reads the upper triangle of A, n (n + 1) / 2 * 8 bytes, plus
+    the CG vectors."""
+    res, mean = D["result"], D["mean"]
+    nsv = len(svals)
+    far_evals = sum(res[s]["far_evals"] for s in svals)
+    far_ms = mean["t_far"]
+    evals_per_s = far_evals / (far_ms * 1e-3)
+    far_tflops = evals_per_s * FLOPS_PER_EVAL / 1e12
+    traffic = measured_traffic()
+    rf_far = {"kernel": "far_kernel<2,2,0> + near_kernel<2,0,0> (separated element pairs, FP64)",
+              "bound": "alu", "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+              "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4),
+              "traffic": traffic and traffic.get("separated_pairs_bytes_per_assembly"),
+              "per_launch_ms": round(far_ms / nsv, 4), "evals_per_launch": far_evals // nsv,
+              "evals_per_s": round(evals_per_s, 1), "flops_per_eval": FLOPS_PER_EVAL,
+              "transcendentals_per_eval": TRANS_PER_EVAL,
+              "note": "per launch = one assembly's separated pairs (near + far tiles); achieved = algorithmic "
+                      "flops (14 per kernel evaluation) / measured time, transcendentals not counted"}
+    # CG iteration: cg_symv + cg_update, device time of the launched
+    # iterations (events around each chunk)
+    n = res[svals[-1]]["n"]
+    launched = mean["cg_launched"]
+    cg_ms_it = mean["t_cgk"] / launched if launched else float("nan")
+    vec_bytes = 12 * n * 8  # p, z, r, x, b, d and the slots' reads and writes, about
+    cg_bytes = n * (n + 1) // 2 * 8 + vec_bytes
+    cg_gbps = cg_bytes / (cg_ms_it * 1e-3) / 1e9
+    rf_cg = {"kernel": "cg_symv_kernel + cg_update_kernel (one Jacobi-PCG iteration, FP64 symmetric product "
+                       "from the upper triangle)",
+             "bound": "hbm", "achieved": round(cg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+             "frac": round(cg_gbps / HBM_PEAK_GBPS, 4),
+             "traffic": traffic and traffic.get("cg_iteration_bytes"),
+             "per_launch_ms": round(cg_ms_it, 4), "bytes_per_launch": cg_bytes,
+             "iterations_launched_per_step": launched}
+    if cache_resident:
+        rf_cg["note"] = ("A is %.0f MB (upper triangle %.0f MB), below the 256 MB Infinity Cache: "
+                         "cache-resident rate" % (n * n * 8 / 1e6, n * (n + 1) / 2 * 8 / 1e6))
+    cg_total = mean["t_cgk"]
+    if far_ms >= cg_total:
+        return rf_far, rf_cg
+    return rf_cg, rf_far
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -113,236 +245,223 @@ def main():
     if args.copy_calib:
         copy_calib(args.copy_calib)
         return
-    if args.only_batch:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps({"batch": batch_leg(args)}), flush=True)
-        return
-    if args.c5:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps({"c5": c5_leg(args)}), flush=True)
-        return
-    if args.only_surrogate:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps({"surrogate": surrogate_leg(args)}), flush=True)
-        return
-    if args.only_indicators:
-        import torch
-        torch.cuda.init()
-        print(json.dumps({"indicators": indicators_leg(args)}), flush=True)
-        return
-    if args.only_symmetry:
-        import torch
-        torch.cuda.init()
-        print(json.dumps({"symmetry": symmetry_leg(args)}), flush=True)
-        return
-    if args.only_cluster:
-        import torch
-        torch.cuda.init()
-        print(json.dumps({"cluster": cluster_leg(args)}), flush=True)
-        return
-    if args.only_mg:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps({"multigrid": mg_leg(args)}), flush=True)
-        return
-    import numpy as np
+    only = {"batch": (args.only_batch, batch_leg), "surrogate": (args.only_surrogate, surrogate_leg),
+            "indicators": (args.only_indicators, indicators_leg), "symmetry": (args.only_symmetry, symmetry_leg),
+            "cluster": (args.only_cluster, cluster_leg), "multigrid": (args.only_mg, mg_leg)}
+    for key, (flag, fn) in only.items():
+        if flag:
+            import torch
+            torch.cuda.set_device(0)
+            print(json.dumps({key: fn(args)}), flush=True)
+            return
     import torch
-    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    from paper_1708_03912_amd import meshgen as M
 
-    dev = 0
-    torch.cuda.set_device(dev)
-    mesh = M.disk_for_cells(args.cells, seed=2)
-    T, B = len(mesh["cells"]), len(mesh["bfacets"])
+    torch.cuda.set_device(0)
+    big = args.workload == "disk200k"
+    mesh = M.disk_for_cells(200000 if big else 8000, seed=2)
     svals = (0.25, 0.75)
-    opts = F.default_opts()
-    handles = {s: F.Handle(dev) for s in svals}
-    stream = torch.cuda.current_stream(dev)
-    bufs = {}
-    fu = {s: None for s in svals}
-
-    def ball_fu(s):
-        # (f,u) for f = 1 on the unit disk: c pi/(s+1), c = 2^{-2s}/(Gamma(1+s)^2)
-        c = 2.0 ** (-2 * s) * math.gamma(1.0) / (math.gamma(1 + s) * math.gamma(1 + s))
-        return c * math.pi / (s + 1.0)
-
-    result = {}
-
-    def step():
-        for s in svals:
-            h = handles[s]
-            h.set_mesh(mesh)
-            n = h.assemble(s, opts)
-            if s not in bufs or bufs[s][0].numel() != n:
-                bufs[s] = (torch.empty(n, dtype=torch.float64, device="cuda"),
-                           torch.empty(n, dtype=torch.float64, device="cuda"))
-            b, u = bufs[s]
-            h.load_vector_one(b)
-            it, rel, rc = h.solve(b, u, rtol=1e-12, maxit=20000)
-            e2 = h.energy_error2(ball_fu(s), b, u)
-            st = h.stats()
-            result[s] = dict(n=n, iters=it, relres=rel, e2=e2, t_asm=st.t_assemble_ms, t_far=st.t_far_ms,
-                             t_self=st.t_self_ms, t_touch=st.t_touch_ms, t_scatter=st.t_scatter_ms,
-                             t_solve=st.t_solve_ms, evals=st.kernel_evals,
-                             far_pairs=list(st.pairs_far)[:opts.n_classes + 1],
-                             far_evals=sum(st.pairs_far[m] * (opts.k_far[m] ** 2) ** 2
-                                           for m in range(opts.n_classes + 1)))
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    far_ms, solve_ms, asm_ms = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        far_ms.append(sum(result[s]["t_far"] for s in svals))
-        asm_ms.append(sum(result[s]["t_asm"] for s in svals))
-        solve_ms.append(sum(result[s]["t_solve"] for s in svals))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    pairs_per_step = len(svals) * (T * (T + 1) // 2 + T * B)
-    value = pairs_per_step / (ms_per_step * 1e-3)
-
-    # dense FP64 matvec bandwidth (A resident, timed with events on the
-    # library's stream = torch's current stream)
-    s_mv = 0.75
-    h = handles[s_mv]
-    n = h.n
-    x = torch.rand(n, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(5):
-        h.matvec(x, y)
-    reps = 50
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        h.matvec(x, y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    mv_ms = e0.elapsed_time(e1) / reps
-    # the product reads the upper triangle of the symmetric A (its unique
-    # half) plus x and y
-    mv_bytes = n * (n + 1) // 2 * 8 + 2 * n * 8
-    mv_gbps = mv_bytes / (mv_ms * 1e-3) / 1e9
-    mv_equiv = (n * n * 8 + 2 * n * 8) / (mv_ms * 1e-3) / 1e9
-
-    # far-field kernel roofline (plain FP64 ALU work)
-    far_evals = sum(result[s]["far_evals"] for s in svals)
-    far_time = sum(far_ms) / len(far_ms) * 1e-3  # both s per step
-    far_tflops = far_evals * FLOPS_PER_EVAL / far_time / 1e12
-    solve_time = sum(solve_ms) / len(solve_ms)
-    asm_time = sum(asm_ms) / len(asm_ms)
-    iters = sum(result[s]["iters"] for s in svals)
-    traffic = measured_traffic()
-    rf_far = {"kernel": "near_kernel<2> + far_kernel<2> (separated element pairs)", "bound": "alu",
-              "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-              "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4),
-              "traffic": traffic and traffic["separated_pairs_bytes_per_assembly"],
-              "per_launch_ms": round(far_time * 1e3 / len(svals), 4),
-              "evals_per_launch": far_evals // len(svals), "flops_per_eval": FLOPS_PER_EVAL}
-    rf_mv = {"kernel": "symv + sym_reduce / cg_symv (symmetric FP64 product from the upper triangle)",
-             "bound": "hbm",
-             "achieved": round(mv_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-             "frac": round(mv_gbps / HBM_PEAK_GBPS, 4),
-             "traffic": traffic and traffic["matvec_bytes_per_launch"],
-             "per_launch_ms": round(mv_ms, 5), "bytes_per_launch": mv_bytes,
-             "full_matrix_equiv_GBps": round(mv_equiv, 1),
-             "note": "A is %.0f MB (upper triangle %.0f MB), below the 256 MB Infinity Cache: cache-resident "
-                     "rate" % (n * n * 8 / 1e6, n * (n + 1) / 2 * 8 / 1e6)}
-    # dominant: the far kernel's total time vs the CG matvec time (iterations x matvec)
-    mv_total = iters * mv_ms
-    far_total = far_time * 1e3
-    roof = rf_far if far_total >= mv_total else rf_mv
-    other = rf_mv if roof is rf_far else rf_far
-
+    dof_mode = "interior" if big else "paper"
+    rtol = 1e-10 if big else 1e-12
+    D = dense_leg(args, mesh, svals, dof_mode, rtol, args.steps, args.warmup)
+    T, B, res = D["T"], D["B"], D["result"]
+    value = D["pairs_per_step"] / (D["ms_per_step"] * 1e-3)
+    n = res[svals[-1]]["n"]
+    roof, other = rooflines(D, svals, cache_resident=n * n * 8 < 256e6)
+    mv = matvec_rate(D["h"])
+    wl = ("d=2 unit disk, seeded jittered-Delaunay quasi-uniform mesh T=%d B=%d, %s DOFs (n=%d), s in "
+          "{0.25,0.75}, f=1: mesh ingest + FP64 assembly (all element pairs, boundary term) + load vector + "
+          "Jacobi-PCG to %g + energy error, per s" % (T, B, dof_mode, n, rtol))
     out = {"metric": METRIC, "value": round(value, 1), "unit": "element-pair quadratures/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(D["ms_per_step"], 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": f"d=2 unit disk, seeded jittered-Delaunay quasi-uniform mesh T={T} "
-                                  f"B={B}, s in {{0.25,0.75}}, f=1: FP64 assembly + Jacobi-PCG to 1e-12 + "
-                                  f"energy error",
-                      "cells": T, "bfacets": B, "n_dofs": {str(s): result[s]["n"] for s in svals},
-                      "s": list(svals), "orders": "k_touch=6 theta=(1.5,3,6) k_far=(4,3,2,2)"},
-           "matvec_GBps": round(mv_gbps, 1),
-           "assemble_ms": round(asm_time, 3), "solve_ms": round(solve_time, 3),
-           "cg_iters": {str(s): result[s]["iters"] for s in svals},
-           "energy_error": {str(s): math.sqrt(max(result[s]["e2"], 0.0)) for s in svals},
-           "phase_ms": {str(s): {k: round(result[s][k], 4) for k in ("t_far", "t_self", "t_touch", "t_scatter")}
+           "config": {"workload": wl, "cells": T, "bfacets": B,
+                      "n_dofs": {str(s): res[s]["n"] for s in svals}, "s": list(svals),
+                      "orders": "k_touch=6 theta=(1.5,3,6) k_far=(4,3,2,2)",
+                      "pairs_per_step": D["pairs_per_step"]},
+           "matvec_GBps": mv["GBps"], "matvec": mv,
+           "assemble_ms": round(D["mean"]["t_asm"], 3), "solve_ms": round(D["mean"]["t_solve"], 3),
+           "cg_kernels_ms": round(D["mean"]["t_cgk"], 3),
+           "cg_iters": {str(s): res[s]["iters"] for s in svals},
+           "energy_error": {str(s): math.sqrt(max(res[s]["e2"], 0.0)) for s in svals},
+           "phase_ms": {str(s): {k: round(res[s][k], 4) for k in ("t_plan", "t_far", "t_self", "t_touch",
+                                                                  "t_scatter", "t_solve", "t_cgk")}
                         for s in svals},
            "roofline": roof, "roofline_other": other}
-
-    out["mixed"] = mixed_leg(args, mesh, svals, handles, bufs, ball_fu, pairs_per_step)
-    if not args.no_batch:
-        out["batch"] = batch_leg(args)
-    if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(args)
-    if not args.no_mg:
-        out["multigrid"] = mg_leg(args)
-    if not args.no_indicators:
-        out["indicators"] = indicators_leg(args)
-    if not args.no_cluster:
-        out["cluster"] = cluster_leg(args)
-    if not args.no_symmetry:
-        out["symmetry"] = symmetry_leg(args)
+    print(json.dumps({"progress": "dense step timed", "ms_per_step": out["ms_per_step"]}), file=sys.stderr,
+          flush=True)
+    if not args.no_mixed:
+        out["mixed_surrogate"] = mixed_surrogate_leg(args, mesh, svals, dof_mode, rtol, D)
+        print(json.dumps({"progress": "mixed leg done"}), file=sys.stderr, flush=True)
+    D["h"].close()
+    del D
+    torch.cuda.empty_cache()
+    if big and not args.no_c2:
+        m2 = M.disk_for_cells(8000, seed=2)
+        D2 = dense_leg(args, m2, svals, "paper", 1e-12, max(1, min(args.steps, 5)), 1)
+        out["disk8k"] = {"ms_per_step": round(D2["ms_per_step"], 3),
+                         "value": round(D2["pairs_per_step"] / (D2["ms_per_step"] * 1e-3), 1),
+                         "cells": D2["T"], "assemble_ms": round(D2["mean"]["t_asm"], 3),
+                         "separated_ms": round(D2["mean"]["t_far"], 3),
+                         "solve_ms": round(D2["mean"]["t_solve"], 3),
+                         "cg_iters": {str(s): D2["result"][s]["iters"] for s in svals},
+                         "matvec": matvec_rate(D2["h"], reps=50),
+                         "roofline": rooflines(D2, svals, cache_resident=True)[0]}
+        D2["h"].close()
+        del D2
+    legs = [("batch", not args.no_batch, batch_leg), ("surrogate", not args.no_surrogate, surrogate_leg),
+            ("multigrid", args.all_legs, mg_leg), ("indicators", args.all_legs, indicators_leg),
+            ("cluster", args.all_legs, cluster_leg), ("symmetry", args.all_legs, symmetry_leg)]
+    for key, on, fn in legs:
+        if on:
+            out[key] = fn(args)
+            print(json.dumps({"progress": key + " leg done"}), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, svals, pairs_per_step)
+        out["cpu_baseline"] = cpu_baseline_rows(args, mesh, svals, dof_mode, D_pairs=out["config"]["pairs_per_step"],
+                                                big=big)
     print(json.dumps(out), flush=True)
-    for hh in handles.values():
-        hh.close()
 
 
-def mixed_leg(args, mesh, svals, handles64, bufs64, ball_fu, pairs_per_step):
-    """Same workload with FL_MIXED (FP32 separated pairs + FP32 inner CG in
-    FP64 refinement); the energy-norm gap to the FP64 solution is measured in
-    the FP64 matrix (equal error: gap <= 0.1 E)."""
-    import numpy as np
+def mixed_surrogate_leg(args, mesh, svals, dof_mode, rtol, D):
+    """The same workload with FL_MIXED (FP32 separated pairs, FP32 inner CG
+    inside FP64 iterative refinement) and the learned surrogate in distance
+    classes 0-1 (trained on this mesh's band pairs, exact fallback where not
+    certified), one step per s after one untimed one.  Equal error: the gap
+    ||u_X - u_64||_A in the FP64 matrix against the FP64 energy error E."""
     import torch
     from paper_1708_03912_amd import fraclap as F
-    opts = F.make_opts(precision="mixed")
-    hm = {s: F.Handle(0) for s in svals}
-    res = {}
-
-    def step():
-        for s in svals:
-            h = hm[s]
-            h.set_mesh(mesh)
-            n = h.assemble(s, opts)
-            b, _ = bufs64[s]
-            u = res.setdefault(("u", s), torch.empty(n, dtype=torch.float64, device="cuda"))
-            h.load_vector_one(b)
-            it, rel, rc = h.solve(b, u, rtol=1e-12, maxit=20000)
-            st = h.stats()
-            res[s] = dict(iters=it, outer=st.last_outer, t_far=st.t_far_ms, t_solve=st.t_solve_ms,
-                          t_asm=st.t_assemble_ms)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    out = {"ms_per_step": round(ms, 3), "value": round(pairs_per_step / (ms * 1e-3), 1),
-           "unit": "element-pair quadratures/s"}
+    h64 = D["h"]
+    hs = F.Handle(0)
+    hs.set_mesh(mesh)
+    out = {"surrogate_training": train_surrogate_for(mesh, args, hs)}
+    om = F.make_opts(dof_mode=dof_mode, precision="mixed", surrogate=2, sur_tol=args.sur_tol)
+    o64 = D["opts"]
+    tot_m = tot_64 = 0.0
     for s in svals:
-        h64 = handles64[s]
-        b, u64 = bufs64[s]
-        u = res[("u", s)]
-        y = torch.empty_like(u)
-        du = u - u64
+        r = {}
+        # the FP64 reference solution of this s (the dense leg keeps only the
+        # last s's matrix)
+        h64.set_mesh(mesh)
+        n = h64.assemble(s, o64)
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        u64 = torch.zeros_like(b)
+        h64.load_vector_one(b)
+        h64.solve(b, u64, rtol=rtol, maxit=20000)
+        st64 = h64.stats()
+        r["fp64"] = {"assemble_ms": round(st64.t_assemble_ms, 2), "separated_ms": round(st64.t_far_ms, 2),
+                     "solve_ms": round(st64.t_solve_ms, 2), "cg_iters": st64.last_iters}
+        um = torch.zeros_like(b)
+        for rep in range(2):                      # first pass untimed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hs.set_mesh(mesh)
+            nm = hs.assemble(s, om)
+            bm = torch.empty(nm, dtype=torch.float64, device="cuda")
+            hs.load_vector_one(bm)
+            itm, relm, rcm = hs.solve(bm, um, rtol=rtol, maxit=20000)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+        st = hs.stats()
+        r["mixed_surrogate"] = {"wall_ms": round(wall, 2), "assemble_ms": round(st.t_assemble_ms, 2),
+                                "separated_ms": round(st.t_far_ms, 2), "solve_ms": round(st.t_solve_ms, 2),
+                                "inner_iters": itm, "refinements": st.last_outer, "relres": relm,
+                                "pairs_surrogate": int(st.pairs_surrogate),
+                                "pairs_fallback": int(st.pairs_fallback)}
+        E = math.sqrt(max(h64.energy_error2(ball_fu(s), b, u64), 0.0))
+        du = um - u64
+        y = torch.empty_like(du)
         h64.matvec(du, y)
         gap = math.sqrt(max(float(torch.dot(du, y)), 0.0))
-        E = math.sqrt(max(h64.energy_error2(ball_fu(s), b, u64), 0.0))
-        out[str(s)] = {"assemble_ms": round(res[s]["t_asm"], 3), "far_ms": round(res[s]["t_far"], 3),
-                       "solve_ms": round(res[s]["t_solve"], 3), "inner_iters": res[s]["iters"],
-                       "refinements": res[s]["outer"], "energy_gap_over_E": gap / E if E > 0 else None}
-    for h in hm.values():
-        h.close()
+        r["energy_error_fp64"] = E
+        r["energy_error_mixed_surrogate"] = math.sqrt(max(h64.energy_error2(ball_fu(s), b, um), 0.0))
+        r["gap_over_E"] = gap / E if E > 0 else None
+        r["equal_error"] = bool(E > 0 and gap <= 0.1 * E)
+        t64 = st64.t_assemble_ms + st64.t_solve_ms
+        tm = st.t_assemble_ms + st.t_solve_ms
+        r["speedup_assembly"] = round(st64.t_assemble_ms / st.t_assemble_ms, 3)
+        r["speedup_solve"] = round(st64.t_solve_ms / st.t_solve_ms, 3)
+        r["speedup_assembly_plus_solve"] = round(t64 / tm, 3)
+        tot_64 += t64
+        tot_m += tm
+        out[str(s)] = r
+    out["speedup_assembly_plus_solve_both_s"] = round(tot_64 / tot_m, 3)
+    hs.close()
+    return out
+
+
+def cpu_baseline_rows(args, mesh, svals, dof_mode, D_pairs, big):
+    """The oracle as it stands (plain C, FP64, OpenMP) on the host cores.
+    Large workload: a row sample -- the rows of randomly chosen DOFs of A^0.75
+    (every element pair touching them, separated, touching and boundary),
+    once on all cores and once on one core; rate = element pairs integrated
+    per second; the full step would take pairs_per_step / rate (an
+    extrapolation, assembly only).  Small workload: one full step (assembly,
+    PCG, energy error).  Also the host's dense FP64 matrix-vector rate
+    (numpy / OpenBLAS dgemv on a 1 GiB matrix)."""
+    import numpy as np
+    from oracle import oracle as O
+    ncores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    O.lib()
+    ords = O.Orders(k_touch=6, k_touch_bnd=6, theta=[1.5, 3.0, 6.0], k_far=[4, 3, 2, 2], k_far_bnd=[4, 3, 2, 2])
+    out = {"unit": "element-pair quadratures/s", "kind": "oracle", "nproc": ncores, "cpu_model": model}
+    if not big:
+        os.environ["OMP_NUM_THREADS"] = str(ncores)
+        t0 = time.perf_counter()
+        for s in svals:
+            A, dofs, _ = O.assemble(mesh, s, ords)
+            b = O.load_vector_one(mesh, dofs)
+            u, it, rel = O.pcg(A, b, rtol=1e-12)
+            O.energy_error(O.ball_fu(2, s), b, u, A)
+        dt = time.perf_counter() - t0
+        out.update({"value": round(D_pairs / dt, 1), "cores": ncores, "seconds": round(dt, 2),
+                    "sample": "one full step of the same workload (both s: assembly + Jacobi-PCG + energy error)"})
+        return out
+    nv = len(mesh["verts"])
+    cells = np.asarray(mesh["cells"])
+    T, B = len(cells), len(mesh["bfacets"])
+    s = svals[-1]
+    dofs = O.dof_nodes(nv, mesh["bfacets"], s, dof_mode)
+    rng = np.random.default_rng(77)
+
+    def run(nrows, threads):
+        rows = np.sort(rng.choice(dofs, nrows, replace=False))
+        hit = np.isin(cells, rows).any(axis=1)
+        nh = int(hit.sum())
+        pairs = nh * T - nh * (nh - 1) // 2 + nh * B   # pairs (K, Kt) with K or Kt hit, plus facets
+        t0 = time.perf_counter()
+        O.assemble_full(mesh, s, ords, rows=rows, compact=True, threads=threads)
+        dt = time.perf_counter() - t0
+        return {"rows": nrows, "cells_hit": nh, "pairs": pairs, "seconds": round(dt, 2),
+                "value": round(pairs / dt, 1), "threads": threads}
+
+    allc = run(args.cpu_rows, ncores)
+    one = run(args.cpu_rows_1core, 1)
+    os.environ["OMP_NUM_THREADS"] = str(ncores)
+    # host dense matvec rate (the CPU library reference for a8)
+    M_ = np.random.default_rng(3).standard_normal((8192, 16384))
+    x = np.ones(16384)
+    M_ @ x
+    t0 = time.perf_counter()
+    for _ in range(5):
+        M_ @ x
+    mv_s = (time.perf_counter() - t0) / 5
+    out.update({"value": allc["value"], "cores": ncores, "seconds": allc["seconds"] + one["seconds"],
+                "sample": "rows of %d (all cores) / %d (one core) random DOFs of A^%g on the same mesh: every "
+                          "element pair touching them (separated, touching, boundary); value = pairs integrated "
+                          "per second on all cores" % (args.cpu_rows, args.cpu_rows_1core, s),
+                "all_cores": allc, "one_core": one,
+                "extrapolated_step_assembly_s": round(D_pairs / allc["value"], 1),
+                "host_dgemv_GBps": round(M_.nbytes / mv_s / 1e9, 2)})
     return out
 
 
@@ -588,112 +707,6 @@ def train_surrogate_for(mesh, args, h):
     torch.cuda.synchronize()
     return {"train_total_ms": round((time.perf_counter() - t0) * 1e3, 1), "loss_last": float(np.mean(hist[-200:])),
             "bound_at_s": {"0.25": [float(b) for b in bound[:, 1]], "0.75": [float(b) for b in bound[:, 3]]}}
-
-
-def c5_leg(args):
-    """Unit disk, ~2e5 triangles, ~1e5 interior DOFs: the FP64 matrix takes
-    80 GB, its FP32 copy 40 GB.  For s in {0.25, 0.75}, f = 1, interior
-    DOFs: (a) plain FP64 assembly + Jacobi-PCG to 1e-10; (b) FL_MIXED
-    assembly with the learned surrogate in classes 0-1 (trained on this
-    mesh's band pairs) + FP32 inner CG inside FP64 refinement (fl_solve).  Energy-norm
-    errors against the closed-form solution, and the gap of (b) to (a) in
-    the FP64 matrix."""
-    import numpy as np
-    import torch
-    from paper_1708_03912_amd import fraclap as F, meshgen as M
-    mesh = M.disk_for_cells(200000, seed=2)
-    T, Bf = len(mesh["cells"]), len(mesh["bfacets"])
-    pairs = T * (T + 1) // 2 + T * Bf
-    out = {"workload": f"d=2 unit disk T={T} B={Bf}, interior DOFs, s in {{0.25,0.75}}, f=1: plain FP64 vs "
-                       f"FL_MIXED + learned surrogate, Jacobi-PCG to 1e-10", "cells": T}
-    hs = F.Handle(0)
-    hs.set_mesh(mesh)
-    out["surrogate_training"] = train_surrogate_for(mesh, args, hs)
-
-    def ball_fu(s):
-        c = 2.0 ** (-2 * s) / (math.gamma(1 + s) * math.gamma(1 + s))
-        return c * math.pi / (s + 1.0)
-
-    for s in (0.25, 0.75):
-        res = {}
-        h64 = F.Handle(0)
-        h64.set_mesh(mesh)
-        # (a) plain FP64: fl_assemble + fl_solve
-        o64 = F.make_opts(dof_mode="interior")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n = h64.assemble(s, o64)
-        torch.cuda.synchronize()
-        t_asm = (time.perf_counter() - t0) * 1e3
-        st = h64.stats()
-        b = torch.empty(n, dtype=torch.float64, device="cuda")
-        u = torch.zeros(n, dtype=torch.float64, device="cuda")
-        h64.load_vector_one(b)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        it, rel, rc = h64.solve(b, u, rtol=1e-10, maxit=20000)
-        torch.cuda.synchronize()
-        t_sol = (time.perf_counter() - t0) * 1e3
-        res["fp64"] = {"n": n, "assemble_ms": round(t_asm, 1), "assemble_device_ms": round(st.t_assemble_ms, 1),
-                       "separated_ms": round(st.t_far_ms, 1), "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
-                       "solve_ms": round(t_sol, 1), "cg_iters": it, "relres": rel, "u": u, "b": b}
-        # (b) FL_MIXED + surrogate assembly and the FP32 Jacobi-PCG (symmetric
-        # FP32 product) inside FP64 iterative refinement
-        om = F.make_opts(dof_mode="interior", precision="mixed", surrogate=2, sur_tol=args.sur_tol)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        nm = hs.assemble(s, om)
-        torch.cuda.synchronize()
-        t_asm = (time.perf_counter() - t0) * 1e3
-        st = hs.stats()
-        bm = torch.empty(nm, dtype=torch.float64, device="cuda")
-        hs.load_vector_one(bm)
-        um = torch.zeros(nm, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        itm, relm, rcm = hs.solve(bm, um, rtol=1e-10, maxit=20000)
-        torch.cuda.synchronize()
-        t_sol = (time.perf_counter() - t0) * 1e3
-        res["mixed_surrogate"] = {"n": nm, "assemble_ms": round(t_asm, 1),
-                                  "assemble_device_ms": round(st.t_assemble_ms, 1),
-                                  "separated_ms": round(st.t_far_ms, 1),
-                                  "pairs_per_s": round(pairs / (t_asm * 1e-3), 1),
-                                  "pairs_surrogate": int(st.pairs_surrogate), "pairs_fallback": int(st.pairs_fallback),
-                                  "solve_ms": round(t_sol, 1), "inner_iters": itm,
-                                  "refinements": hs.stats().last_outer, "relres": relm,
-                                  "u": um, "b": bm}
-        e2 = h64.energy_error2(ball_fu(s), res["fp64"]["b"], res["fp64"]["u"])
-        E = math.sqrt(max(e2, 0.0))
-        du = res["mixed_surrogate"]["u"] - res["fp64"]["u"]
-        y = torch.empty_like(du)
-        h64.matvec(du, y)
-        gap = math.sqrt(max(float(torch.dot(du, y)), 0.0))
-        e2m = h64.energy_error2(ball_fu(s), res["fp64"]["b"], res["mixed_surrogate"]["u"])
-        # dense FP64 matvec rate on the 80 GB matrix (HBM-bound, not cache-resident)
-        x = torch.rand(res["fp64"]["n"], dtype=torch.float64, device="cuda")
-        for _ in range(2):
-            h64.matvec(x, y)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            h64.matvec(x, y)
-        ev1.record()
-        torch.cuda.synchronize()
-        mv_ms = ev0.elapsed_time(ev1) / 5
-        n = res["fp64"]["n"]
-        for r in res.values():
-            r.pop("u")
-            r.pop("b")
-        res["energy_error_fp64"] = E
-        res["energy_error_mixed_surrogate"] = math.sqrt(max(e2m, 0.0))
-        res["gap_over_E"] = gap / E if E > 0 else None
-        res["matvec_ms"] = round(mv_ms, 3)
-        res["matvec_GBps"] = round(n * (n + 1) // 2 * 8 / (mv_ms * 1e-3) / 1e9, 1)
-        res["matvec_full_matrix_equiv_GBps"] = round(n * n * 8 / (mv_ms * 1e-3) / 1e9, 1)
-        out[str(s)] = res
-        h64.close()
-    hs.close()
-    return out
 
 
 def mg_leg(args):
@@ -980,27 +993,6 @@ def symmetry_leg(args):
     out["max_gap_rel"] = float(np.abs(ur - uf[pos]).max() / np.abs(uf).max())
     out["assembly_speedup"] = round(out["full"]["assembly_ms"] / out["reduced"]["assembly_ms"], 2)
     return out
-
-
-def cpu_baseline(mesh, svals, pairs_per_step):
-    """The oracle as it stands (plain C + numpy, FP64) on the host cores,
-    timed on one full step of the same workload."""
-    import numpy as np
-    from oracle import oracle as O
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(cores)
-    O.lib()
-    t0 = time.perf_counter()
-    for s in svals:
-        A, dofs, _ = O.assemble(mesh, s, O.Orders(k_touch=6, k_touch_bnd=6, theta=[1.5, 3.0, 6.0],
-                                                  k_far=[4, 3, 2, 2], k_far_bnd=[4, 3, 2, 2]))
-        b = O.load_vector_one(mesh, dofs)
-        u, it, rel = O.pcg(A, b, rtol=1e-12)
-        O.energy_error(O.ball_fu(2, s), b, u, A)
-    dt = time.perf_counter() - t0
-    return {"value": round(pairs_per_step / dt, 1), "unit": "element-pair quadratures/s", "cores": cores,
-            "kind": "oracle", "seconds": round(dt, 2),
-            "sample": "one full step of the same workload (both s: assembly + Jacobi-PCG + energy error)"}
 
 
 if __name__ == "__main__":

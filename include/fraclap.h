@@ -151,13 +151,20 @@ typedef struct {
     double t_touch_ms;        /* ... common-edge / common-vertex pairs      */
     double t_scatter_ms;      /* ... diagonal blocks into A                 */
     double t_solve_ms;        /* device time of the last solve              */
-    int32_t last_iters;       /* iterations of the last solve (mixed: inner
-                                 FP32 iterations summed over refinements)  */
+    int32_t last_iters;       /* iterations of the last solve (mixed: the
+                                 FP32 iterations)                          */
     double last_relres;
-    int32_t last_outer;       /* FP64 refinement steps of the last solve
-                                 (fl_solve_batch: residual replacements)   */
+    int32_t last_outer;       /* FP64 residual replacements of the last
+                                 solve (mixed fl_solve, fl_solve_batch)    */
     int64_t pairs_surrogate;  /* band pairs done by the network             */
     int64_t pairs_fallback;   /* band pairs that kept the exact rule        */
+    double t_cg_kernels_ms;   /* device time of the CG iteration kernels of
+                                 the last fl_solve (events around each
+                                 chunk of launched iterations; host round
+                                 trips excluded)                           */
+    int64_t cg_launched;      /* CG iterations launched by the last fl_solve
+                                 (>= iterations done: launched iterations
+                                 after the stop test exit at once)         */
 } fl_stats_t;
 
 /* Default orders (the calibrated table: k_touch = k_touch_bnd = 6,
@@ -376,10 +383,13 @@ int fl_matvec(fl_handle *h, const double *x, double *y);
 /* Jacobi-preconditioned CG on A u = b (Sec. 5).  b, u: device, length n;
  * u is overwritten (initial guess 0).  Stops when ||r||_2 <= rtol ||b||_2
  * or after maxit iterations (then FL_ENOCONV with the last iterate).
- * After an FL_MIXED assembly: FP64 iterative refinement u += e with the
- * residual r = b - A u in FP64, each correction from FP32 Jacobi-PCG on the
- * FP32 copy of A to a relative residual 1e-4 (maxit bounds the total inner
- * iterations).
+ * After an FL_MIXED assembly: Jacobi-PCG whose products read the FP32 copy
+ * of A (FP32 vectors), with FP64 residual replacement: whenever the
+ * recursive residual has dropped by a factor 100 since the last
+ * replacement (or by what rtol still needs), the FP32 correction is added
+ * to u in FP64 and the recursive residual is replaced by b - A u formed
+ * with the FP64 matrix; the search direction is kept (no restart).  The
+ * stop test is on the FP64 residual; maxit bounds the FP32 iterations.
  * FL_EBREAKDOWN if p.Ap <= 0; FL_ENONFINITE if b is not finite.  Host
  * outputs iters / relres (may be NULL).  Synchronises the stream. */
 int fl_solve(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,

@@ -1268,20 +1268,39 @@ static int pull_status(fl_handle* h) {
 // chunk.  Leaves the status block in the pinned mirror; *launched: the
 // number of iterations launched.
 template <class F>
-static int cg_run_chunks(fl_handle* h, double rtol, int maxit, const F& launch, int* launched, int first = 16) {
+static int cg_run_chunks(fl_handle* h, double rtol, int maxit, const F& launch, int* launched, int first = 16,
+                         int start = 0) {
     const int* hf = stat_flag(h->w_hstat);
     const double* hs = stat_scal(h->w_hstat);
     const double* hh = stat_hist(h->w_hstat);
-    int it = 0, m = first;
-    *launched = 0;
+    int it = start, m = first;
+    *launched = start;
+    // device time of the launched iterations alone (events around each
+    // chunk), summed into the handle's statistics
+    hipEvent_t c0, c1;
+    HIPCHK(hipEventCreate(&c0));
+    HIPCHK(hipEventCreate(&c1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{c0, c1};
     while (!hf[0] && it < maxit) {
         m = std::max(1, std::min(m, maxit - it));
+        HIPCHK(hipEventRecord(c0, h->stream));
         for (int j = 0; j < m; ++j) launch(it + j);
         HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(c1, h->stream));
         it += m;
         *launched = it;
         int rc = pull_status(h);
         if (rc) return rc;
+        float cms = 0.f;
+        HIPCHK(hipEventElapsedTime(&cms, c0, c1));
+        h->st.t_cg_kernels_ms += cms;
+        h->st.cg_launched += m;
         if (hf[0]) break;
         // geometric rate over the last (up to 8) iterations of this chunk
         const int q = std::min(8, m - 1);
@@ -1323,7 +1342,9 @@ static int ensure_solver(fl_handle* h) {
     sym_plan_geometry(n, &sp);
     const int64_t ndot = (n + 255) / 256;
     HIPCHK(hipMalloc((void**)&h->w, sizeof(double) * (size_t)(7 * n + 8)));
-    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(4 * std::max<int64_t>(sp.nred, ndot) + 8)));
+    // CG partials (4 per reduction block), then the dot products of the
+    // mixed-precision refinement (which must not touch the CG partials)
+    HIPCHK(hipMalloc((void**)&h->w_part, sizeof(double) * (size_t)(6 * std::max<int64_t>(sp.nred, ndot) + 8)));
     HIPCHK(hipMalloc((void**)&h->w_stat, FL_STAT_BYTES));
     HIPCHK(hipHostMalloc((void**)&h->w_hstat, FL_STAT_BYTES, 0));
     if (h->opts.precision == FL_MIXED) HIPCHK(hipMalloc((void**)&h->w32, sizeof(float) * (size_t)(9 * n + 16)));
@@ -1334,21 +1355,29 @@ static int ensure_solver(fl_handle* h) {
     return FL_OK;
 }
 
-// FP64 iterative refinement around FP32 Jacobi-PCG (FL_MIXED).
-static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit,
-                       int32_t* iters, double* relres) {
+// FL_MIXED: Jacobi-PCG whose products read the FP32 matrix (half the bytes
+// of the FP64 one) with FP32 vectors, and FP64 residual replacement: when
+// the recursive residual has dropped by DELTA (or reached what the
+// tolerance needs), the FP32 correction is added to u in FP64, the true
+// residual b - A u is formed with the FP64 matrix and replaces the
+// recursive one, and the iteration continues with the same search
+// direction (no restart), so the iteration count stays close to that of
+// the FP64 solver.  Stops on the FP64 residual.
+static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, int32_t maxit, int32_t* iters,
+                       double* relres) {
     int rc = FL_OK;
     const int64_t n = h->n;
     const int nblk = (int)((n + 255) / 256);
     double* r = h->w;                 // FP64 residual
     float* W = h->w32;
+    double* dpart = h->w_part + 4 * std::max<int64_t>(h->sym.nred, nblk);
     CgState32 S{};
     S.n = n;
     S.A = h->dA32;
     S.lda = h->lda;
     S.d = W;
-    S.b = W + n;                      // FP32 copy of the residual
-    S.x = W + 2 * n;                  // FP32 correction
+    S.b = W + n;                      // FP32 copy of the true residual
+    S.x = W + 2 * n;                  // FP32 correction since the last replacement
     S.r = W + 3 * n;
     S.z = W + 4 * n;
     S.p = W + 5 * n;                  // 2 n
@@ -1358,40 +1387,48 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     S.hist = stat_hist(h->w_stat);
     S.sp = h->sym;
     S.nblk = h->sym.nred;
-    const double rtol_in = 1e-4;
+    S.maxit = maxit;
+    const double DELTA = 1e-2;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, h->stream));
     launch_diag32(h->dA32, h->lda, n, (float*)S.d, h->stream);
     launch_zero(u, n, h->stream);
-    double bb = -1.0, rr = 0.0;
-    int total_inner = 0, outer = 0, status = FL_OK, last_inner = 0;
-    for (;;) {
-        launch_residual(h->sym, h->dA, h->lda, u, b, r, (float*)S.b, h->stream);
-        launch_dot2(r, r, r, n, h->w_part, nblk, stat_scal(h->w_stat) + 8, h->stream);
-        HIPCHK(hipGetLastError());
+    // u = 0: the residual is b
+    launch_cast_f32(b, (float*)S.b, n, h->stream);
+    launch_dot2(b, b, b, n, dpart, nblk, stat_scal(h->w_stat) + 8, h->stream);
+    HIPCHK(hipGetLastError());
+    if ((rc = pull_status(h))) return rc;
+    const double bb = stat_scal(h->w_hstat)[8];
+    double rr = bb;
+    int it = 0, outer = 0, status = FL_OK, seg_len = 16;
+    if (!(bb == bb) || bb > 1.79e308) status = FL_ENONFINITE;
+    bool first = true;
+    while (status == FL_OK && bb > 0.0 && !(std::sqrt(rr) <= rtol * std::sqrt(bb)) && it < maxit && outer < 400) {
+        // segment: FP32 iterations until the recursive residual has dropped
+        // by DELTA, or by what the tolerance still needs (with a margin)
+        S.rtol = std::max(DELTA, 0.5 * rtol * std::sqrt(bb / rr));
+        if (first) launch_cg32_init(S, h->stream);
+        else launch_cg32_replace(S, it, h->stream);
+        first = false;
         if ((rc = pull_status(h))) return rc;
-        rr = stat_scal(h->w_hstat)[8];
-        if (bb < 0) bb = rr;
-        if (!(rr == rr) || rr > 1.79e308) { status = FL_ENONFINITE; break; }
-        if (std::sqrt(rr) <= rtol * std::sqrt(bb) || total_inner >= maxit || outer >= 60) break;
-        // inner FP32 solve A32 e = r32
-        S.rtol = rtol_in;
-        S.maxit = maxit - total_inner;
-        launch_cg32_init(S, h->stream);
-        if ((rc = pull_status(h))) return rc;
-        // the first chunk: the previous correction's iteration count (same
-        // matrix, same relative tolerance) plus two
         int launched = 0;
-        if ((rc = cg_run_chunks(h, S.rtol, S.maxit, [&](int it) { launch_cg32_iter_at(S, it, h->stream); },
-                                &launched, last_inner > 0 ? last_inner + 2 : 16)))
+        if ((rc = cg_run_chunks(h, S.rtol, maxit, [&](int k) { launch_cg32_iter_at(S, k, h->stream); }, &launched,
+                                seg_len + 2, it)))
             return rc;
         const int* flag = stat_flag(h->w_hstat);
         if (flag[2] == 1) { status = FL_EBREAKDOWN; break; }
-        total_inner += flag[1];
-        last_inner = flag[1];
+        seg_len = std::max(2, flag[1] - it);
+        it = flag[1];
+        // u += correction; true residual in FP64 (and its FP32 copy)
         launch_add_correction(u, S.x, n, h->stream);
+        launch_residual(h->sym, h->dA, h->lda, u, b, r, (float*)S.b, h->stream);
+        launch_dot2(r, r, r, n, dpart, nblk, stat_scal(h->w_stat) + 8, h->stream);
+        HIPCHK(hipGetLastError());
+        if ((rc = pull_status(h))) return rc;
+        rr = stat_scal(h->w_hstat)[8];
+        if (!(rr == rr) || rr > 1.79e308) { status = FL_ENONFINITE; break; }
         ++outer;
     }
     HIPCHK(hipEventRecord(e1, h->stream));
@@ -1402,10 +1439,10 @@ static int solve_mixed(fl_handle* h, const double* b, double* u, double rtol, in
     (void)hipEventDestroy(e1);
     double rel = bb > 0 ? std::sqrt(rr) / std::sqrt(bb) : 0.0;
     h->st.t_solve_ms = ms;
-    h->st.last_iters = total_inner;
+    h->st.last_iters = it;
     h->st.last_relres = rel;
     h->st.last_outer = outer;
-    if (iters) *iters = total_inner;
+    if (iters) *iters = it;
     if (relres) *relres = rel;
     if (status == FL_EBREAKDOWN) return fail(h, FL_EBREAKDOWN, "CG breakdown: p.Ap <= 0");
     if (status == FL_ENONFINITE) return fail(h, FL_ENONFINITE, "non-finite residual");
@@ -1427,6 +1464,8 @@ int fl_solve(fl_handle* h, const double* b, double* u, double rtol, int32_t maxi
     HIPCHK(hipSetDevice(h->device));
     int rc = ensure_solver(h);
     if (rc) return rc;
+    h->st.t_cg_kernels_ms = 0.0;
+    h->st.cg_launched = 0;
     if (h->opts.precision == FL_MIXED) return solve_mixed(h, b, u, rtol, maxit, iters, relres);
     const int64_t n = h->n;
     CgState S{};

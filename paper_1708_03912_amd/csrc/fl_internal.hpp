@@ -147,12 +147,14 @@ void launch_diag(const double* A, long long lda, long long n, double* d, hipStre
 // and the m tiles from bj = bi + c m; partial sums in slot arrays (no
 // atomics), reduced with G lanes per element.
 constexpr int SYM_TB = 64;
-constexpr int SYM_M = 3;             // tiles per workgroup: 64 (m + 1) = 256 staged entries
+constexpr int SYM_M = 16;            // longest strip of tiles per workgroup
+constexpr long long SYM_SK_N = 16384;  // larger systems: CG scalars by their own kernel
 constexpr int SYM_PQ_BLOCKS = 256;   // pre-reduction of the v.Av partials
 struct SymPlan {
     long long n;
     int nb;          // block rows, ceil(n / 64)
-    int m;           // tiles per workgroup along a block row (SYM_M)
+    int m;           // tiles per workgroup along a block row (<= SYM_M)
+    int sk;          // 1: CG scalars by cg_scalar_kernel (large n)
     int nchx;        // chunks per block row, ceil(nb / m)
     long long nwg;   // workgroups of a product, nchx x nb (some empty)
     int G;           // lanes per element in the reductions (power of two <= 16)
@@ -367,9 +369,13 @@ struct CgState32 {
 void launch_cg32_init(const CgState32& s, hipStream_t st);
 void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st);
 void launch_cg32_final(const CgState32& s, int it, hipStream_t st);
+// replace the residual of iteration it by s.b, keep p (mixed-precision
+// refinement without restarts)
+void launch_cg32_replace(const CgState32& s, int it, hipStream_t st);
 // x += e (FP32 correction)
 void launch_diag32(const float* A, long long lda, long long n, float* d, hipStream_t st);
 void launch_add_correction(double* u, const float* e, long long n, hipStream_t st);
+void launch_cast_f32(const double* a, float* b, long long n, hipStream_t st);  // b = (float) a
 void launch_dot2(const double* a, const double* b, const double* c, long long n, double* part,
                  int nblk, double* out, hipStream_t st);
 

@@ -55,6 +55,27 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Sums over the wave of four values at once (halving exchange): after the
+// xor-32 and xor-16 steps lane l holds a partial sum of value
+// m = 2 b5 + b4 (b: lane bits), the xor-8 .. 1 steps finish it; lane 16 m
+// returns the sum of v[m].  7 exchanges instead of 24.
+__device__ __forceinline__ double wave_sum4(const double* v, int lane) {
+    const int h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1;
+    double w[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double mine = h5 ? v[2 + j] : v[j];
+        const double give = h5 ? v[j] : v[2 + j];
+        w[j] = mine + __shfl_xor(give, 32, 64);
+    }
+    double x = (h4 ? w[1] : w[0]) + __shfl_xor(h4 ? w[0] : w[1], 16, 64);
+    x += __shfl_xor(x, 8, 64);
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 1, 64);
+    return x;
+}
+
 // Sums over the wave of six values at once (halving exchange): after the
 // xor-32 / 16 / 8 steps each lane holds a partial sum of one slot
 // m = 4 b5 + 2 b4 + b3 (b: lane bits), the xor-4 / 2 / 1 steps finish it;
@@ -1093,6 +1114,259 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     if (tid <= P.ncls && ccnt[tid]) atomicAdd(&P.cls_count[tid], (unsigned long long)ccnt[tid]);
 }
 
+// ------------------------------------------- far tiles, 2D, FP64, KO <= 2 --
+//
+// Every pair of a far tile (bi < bj) is separated and in the last distance
+// class (proved on the host from the blocks' centroid boxes), so all its
+// pairs take the same order-KO rule.  With the rule's points x_p of K and
+// y_q of Kt, weights w, barycentric values l and k_pq = |x_p - y_q|^{-2-2s}:
+//   M_pb = sum_q w_q l_b(y_q) k_pq,   H_q = sum_p w_p k_pq,
+//   off-diagonal block   O_ab = sum_p w_p l_a(x_p) M_pb,
+//   diagonal block of K:  sum_p w_p l_a l_b(x_p) G_p,  G_p = sum_b M_pb
+//                         (= sum_q w_q k_pq: the l_b sum to 1),
+//   diagonal block of Kt: sum_q w_q l_a l_b(y_q) H_q,
+// four accumulations per kernel evaluation.  The diagonal blocks are linear
+// in G and H, so the tile sums the scaled potentials
+//   Phi_p(K)  = sum_Kt C |K| |Kt| G_p   (over the lanes, once per row),
+//   Psi_q(Kt) = sum_K  C |K| |Kt| H_q   (in the lane's registers),
+// and applies the l_a l_b weights once per element and tile.  Wave w takes
+// rows K = I0 + w, w + 4, ...; lane l takes Kt = J0 + l, whose mapped points
+// stay in registers; the rows' mapped points are staged in LDS.  The
+// off-diagonal blocks are summed in LDS over the two blocks' local DOF
+// numbering; a spare row and column take the vertices without a DOF, so the
+// adds are branch-free.  The Psi partials of the four waves are added in
+// wave order.
+template <int KO, int W>
+__global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
+    constexpr int Q = KO * KO;
+    constexpr int LS = MAXV + 1;  // row stride of L; row / column MAXV: vertices without a DOF
+    __shared__ __align__(16) double pw[768];
+    __shared__ __align__(16) double L[LS * LS];
+    __shared__ __align__(16) double sX[BE][2 * Q];  // rows' mapped points, (x, y) per point
+    __shared__ double sMK[BE];                      // |K| of the rows (0 past T)
+    __shared__ int sRO[BE][3];                      // byte offsets of the rows' L rows
+    __shared__ double sPhi[BE][Q];
+    __shared__ int vI[MAXV], vJ[MAXV];
+
+    const int2 tb = P.tiles[blockIdx.x];
+    const int bi = tb.x, bj = tb.y;
+    const int I0 = bi * BE, J0 = bj * BE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nVI = P.blk_ndof[bi], nVJ = P.blk_ndof[bj];
+    const bool direct = (nVI > MAXV) || (nVJ > MAXV);
+    const int T = P.T;
+    constexpr int off = (KO - 1) * KO * (2 * KO - 1) / 6;  // tri_off(KO)
+
+    load_pow_tables(pw);
+    for (int i = tid; i < LS * LS; i += 256) L[i] = 0.0;
+    if (!direct)
+        for (int i = tid; i < MAXV; i += 256) {
+            vI[i] = P.blk_dofs[(long long)bi * MAXV + i];
+            vJ[i] = P.blk_dofs[(long long)bj * MAXV + i];
+        }
+    if (tid < BE) {
+        const int r = tid, K = I0 + r;
+        const bool ok = K < T;
+        const int Kc = ok ? K : T - 1;
+        double X[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) X[c] = E.x[c][Kc];
+        const double ex0 = X[2] - X[0], ey0 = X[3] - X[1], ex1 = X[4] - X[0], ey1 = X[5] - X[1];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const double* cp = c_R.tri[off + p];
+            sX[r][2 * p] = X[0] + cp[0] * ex0 + cp[1] * ex1;
+            sX[r][2 * p + 1] = X[1] + cp[0] * ey0 + cp[1] * ey1;
+        }
+        sMK[r] = ok ? E.meas[Kc] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int la = ok ? P.loc[(long long)Kc * 3 + a] : 255;
+            sRO[r][a] = (la == 255 ? MAXV : la) * LS * 8;
+        }
+    }
+
+    // the lane's column element
+    const int Kt = J0 + lane;
+    const bool okt = Kt < T;
+    const int Ktc = okt ? Kt : T - 1;
+    double yq[2 * Q];
+    {
+        double Y[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Y[c] = E.x[c][Ktc];
+        const double fx0 = Y[2] - Y[0], fy0 = Y[3] - Y[1], fx1 = Y[4] - Y[0], fy1 = Y[5] - Y[1];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double* cq = c_R.tri[off + q];
+            yq[2 * q] = Y[0] + cq[0] * fx0 + cq[1] * fx1;
+            yq[2 * q + 1] = Y[1] + cq[0] * fy0 + cq[1] * fy1;
+        }
+    }
+    const double ct = okt ? P.C * E.meas[Ktc] : 0.0;
+    int cbo[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int lb = okt ? P.loc[(long long)Ktc * 3 + b] : 255;
+        cbo[b] = (lb == 255 ? MAXV : lb) * 8;
+    }
+    // rule constants: w_q l_b(y_q) and w_p
+    double cw[Q][3], wq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        wq[q] = c_R.tri[off + q][2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) cw[q][b] = c_R.tri[off + q][3 + b];
+    }
+    const KPowTab kp = make_kpow_tab(pw);
+    double Psi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) Psi[q] = 0.0;
+    __syncthreads();
+
+    for (int r = wave; r < BE; r += 4) {
+        if (I0 + r >= T) break;
+        double xp[2 * Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const double2 v = *(const double2*)&sX[r][2 * p];
+            xp[2 * p] = v.x;
+            xp[2 * p + 1] = v.y;
+        }
+        double f = sMK[r] * ct;
+        if constexpr (W) f *= okt ? pair_w(E, I0 + r, Kt) : 0.0;
+        double M[Q][3], H[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) M[p][0] = M[p][1] = M[p][2] = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            // the Q evaluations of this point of Kt in three phases, so that
+            // their table reads are in flight together: squared distances
+            // and table offsets, the reads, then the polynomials
+            int hi[Q];
+            double m[Q];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const double dx = xp[2 * p] - yq[2 * q], dy = xp[2 * p + 1] - yq[2 * q + 1];
+                const double r2 = dx * dx + dy * dy;
+                hi[p] = __double2hiint(r2);
+                m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2));
+            }
+            double2 fr[Q];
+            double ex[Q];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                fr[p] = ((const double2*)pw)[(hi[p] >> 12) & 255];
+                ex[p] = pw[512 + (hi[p] >> 20) - 895];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            double h = 0.0;
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const double t = fma(m[p], fr[p].x, -1.0);
+                double pp = fma(kp.c5, t, kp.c4);
+                pp = fma(pp, t, kp.c3);
+                pp = fma(pp, t, kp.c2);
+                pp = fma(pp, t, kp.c1);
+                pp = fma(pp, t, 1.0);
+                const double kv = (pp * fr[p].y) * ex[p];
+                M[p][0] += cw[q][0] * kv;
+                M[p][1] += cw[q][1] * kv;
+                M[p][2] += cw[q][2] * kv;
+                h += wq[p] * kv;
+            }
+            H[q] = h;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Psi[q] += f * H[q];
+        // Phi_p of row r: the sum over the lanes of f G_p
+        {
+            double g[Q];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) g[p] = f * ((M[p][0] + M[p][1]) + M[p][2]);
+            if constexpr (Q == 4) {
+                const double v = wave_sum4(g, lane);
+                if ((lane & 15) == 0) sPhi[r][lane >> 4] = v;
+            } else {
+                const double v = wave_sum(g[0]);
+                if (lane == 0) sPhi[r][0] = v;
+            }
+        }
+        // off-diagonal block, scaled by -f
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double o[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int p = 0; p < Q; ++p)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) o[b] += cw[p][a] * M[p][b];
+            if (!direct) {
+                const int ro = sRO[r][a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    atomicAdd((double*)((char*)L + ro + cbo[b]), -f * o[b]);
+            } else if (okt) {
+                const int ga = E.dof[a][I0 + r];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int gb = E.dof[b][Kt];
+                    if (ga < 0 || gb < 0) continue;
+                    const double v = -f * o[b];
+                    atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                    atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // diagonal blocks of the rows
+    for (int i = tid; i < BE * 6; i += 256) {
+        const int r = i / 6, m = i - r * 6, K = I0 + r;
+        if (K >= T) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) v += c_R.tri[off + p][6 + m] * sPhi[r][p];
+        if (v != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], v);
+    }
+    // off-diagonal block and its mirror into A
+    if (!direct) {
+        for (int i = tid; i < nVI * nVJ; i += 256) {
+            const int rr = i / nVJ, cc = i - rr * nVJ;
+            const double v = L[rr * LS + cc];
+            if (v == 0.0) continue;
+            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+            atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+        }
+    }
+    __syncthreads();
+    // diagonal blocks of the columns: each wave's part, added in wave order
+    {
+        double st[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v += c_R.tri[off + q][6 + m] * Psi[q];
+            st[m] = v;
+        }
+        double* stage = L;  // 4 x 64 x 6 doubles
+#pragma unroll
+        for (int m = 0; m < 6; ++m) stage[(wave * 64 + lane) * 6 + m] = st[m];
+    }
+    __syncthreads();
+    for (int i = tid; i < BE * 6; i += 256) {
+        const int l = i / 6, m = i - l * 6, Ktt = J0 + l;
+        if (Ktt >= T) continue;
+        const double* stage = L;
+        const double v = ((stage[(0 * 64 + l) * 6 + m] + stage[(1 * 64 + l) * 6 + m]) +
+                          stage[(2 * 64 + l) * 6 + m]) + stage[(3 * 64 + l) * 6 + m];
+        if (v != 0.0) atomicAdd(&P.S[(long long)Ktt * 6 + m], v);
+    }
+    if (tid == 0)
+        atomicAdd(&P.cls_count[P.ncls], (unsigned long long)(min(BE, T - I0) * (long long)min(BE, T - J0)));
+}
+
 void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
@@ -1118,7 +1392,16 @@ void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_
         if (P.mixed) hipLaunchKernelGGL((far_kernel<D, K, 1>), grid, block, 0, st, E, P); \
         else hipLaunchKernelGGL((far_kernel<D, K, 0>), grid, block, 0, st, E, P);         \
     } while (0)
-    if (P.dim == 2) {
+    if (P.dim == 2 && !P.mixed && fark <= 2) {
+        const bool w = E.w != nullptr;
+        if (fark == 1) {
+            if (w) hipLaunchKernelGGL((far2_kernel<1, 1>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((far2_kernel<1, 0>), grid, block, 0, st, E, P);
+        } else {
+            if (w) hipLaunchKernelGGL((far2_kernel<2, 1>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((far2_kernel<2, 0>), grid, block, 0, st, E, P);
+        }
+    } else if (P.dim == 2) {
         switch (fark) {
             case 1: FL_FAR_CASE(2, 1); break;
             case 2: FL_FAR_CASE(2, 2); break;
@@ -1764,34 +2047,6 @@ __device__ __forceinline__ double sum_partials(const double* part, int m, double
     return block_sum(v, sh);
 }
 
-// Symmetric dense product from the upper triangle.  The stiffness matrix is
-// symmetric (Sec. 5: every pair adds a block and its transpose), so a
-// product reads only its 64 x 64 tiles (bi <= bj): half of the n^2 entries.
-// Workgroup (c, bi) of a (ceil(nb / M), nb) grid takes block row bi and the
-// tiles bj = bi + c M .. bi + c M + M - 1 (< nb; workgroups with bi + c M >= nb
-// have nothing to do); M = 3 fills the 256 threads with the staged vector
-// entries (64 (M + 1)).  It loads all of them at once, forms the row sums
-// A_IJ v_J over its tiles and, for bi < bj, the column sums A_IJ^T v_I.
-// Partial sums go to slots that exactly one workgroup writes (no atomics):
-//   prow[c n + i]  row sums of chunk c of the block row of i,
-//   pcol[a n + j]  column sums of tile (a, b) for j in block b, a < b,
-// and (A v)_i is their sum over c < nch(b), then a < b (fixed order).
-// Thread t of 256 holds columns 2 (t & 31), 2 (t & 31) + 1 and rows
-// (t >> 5) + 8 k, k = 0..7, of each tile: one load of a wave covers two
-// contiguous row segments of 64 entries.  Every global load of a workgroup
-// (matrix entries, vector entries, partial sums) is issued before the
-// first wait.
-__device__ __forceinline__ void ld2(const double* p, double& a, double& b) {
-    const double2 v = *(const double2*)p;
-    a = v.x;
-    b = v.y;
-}
-__device__ __forceinline__ void ld2(const float* p, double& a, double& b) {
-    const float2 v = *(const float2*)p;
-    a = v.x;
-    b = v.y;
-}
-
 // this lane's share of the sum of the first m partials (lane stride 256,
 // four accumulators): the same order in every block
 __device__ __forceinline__ double load_partials(const double* part, int m) {
@@ -1825,123 +2080,192 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
     __syncthreads();
 }
 
-// Sums of eight values over the 32 lanes of a half wave (halving exchange):
-// lane cp returns the sum of v[cp >> 2].  9 exchanges instead of 40.
-__device__ __forceinline__ double half_wave_sum8(const double* v, int cp) {
-    const int h4 = (cp >> 4) & 1, h3 = (cp >> 3) & 1, h2 = (cp >> 2) & 1;
-    double w[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = (h4 ? v[4 + j] : v[j]) + __shfl_xor(h4 ? v[j] : v[4 + j], 16, 64);
-    double x[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) x[j] = (h3 ? w[2 + j] : w[j]) + __shfl_xor(h3 ? w[j] : w[2 + j], 8, 64);
-    double y = (h2 ? x[1] : x[0]) + __shfl_xor(h2 ? x[0] : x[1], 4, 64);
-    y += __shfl_xor(y, 2, 64);
-    y += __shfl_xor(y, 1, 64);
-    return y;
-}
-
-// Raw loads of the thread's 8 x 2 entries of each of the workgroup's M
-// tiles.  Branch-free: indices outside n x n are clamped into the matrix
-// (rows to n - 1, columns to lda - 2) so that all 8 M loads issue back to
-// back; sym_unpack zeroes those entries afterwards.
+// Symmetric dense product from the upper triangle.  The stiffness matrix is
+// symmetric (Sec. 5: every pair adds a block and its transpose), so a
+// product reads only its 64 x 64 tiles (bi <= bj): half of the n^2 entries.
+// Workgroup (c, bi) of a (nchx, nb) grid streams the strip of tiles
+// bj = bi + c m .. bi + c m + m - 1 (< nb) of block row bi (workgroups past
+// the end of the row have nothing to do), with the next tile's loads in
+// flight while the current one is used.  It forms the row sums A_IJ v_J,
+// summed over the strip in registers, and for bi < bj the column sums
+// A_IJ^T v_I of every tile.  Partial sums go to slots that exactly one
+// workgroup writes (no atomics):
+//   prow[c n + i]  row sums of strip c of the block row of i,
+//   pcol[a n + j]  column sums of tile (a, b) for j in block b, a < b,
+// and (A v)_i is their sum over c < nch(b), then a < b (fixed order).
+// Thread (wave w, lane l) holds columns 16 w + 2 (l & 7) + {0, 1} and rows
+// (l >> 3) + 8 k, k = 0..7, of each tile: one load of a wave covers eight
+// contiguous row segments of 16 entries.  A column sum is complete after
+// three exchanges inside the wave; the row sums are reduced once per strip
+// (three exchanges, then the four waves in order through LDS).
+typedef double sym_d2 __attribute__((ext_vector_type(2)));
+typedef float sym_f2 __attribute__((ext_vector_type(2)));
 template <class T>
 struct Pair2;
 template <>
 struct Pair2<double> {
-    using type = double2;
+    using type = sym_d2;
 };
 template <>
 struct Pair2<float> {
-    using type = float2;
+    using type = sym_f2;
 };
 
-template <class T, int M>
-__device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda, const SymPlan& P, long long I0,
-                                         int bj0, typename Pair2<T>::type (&raw)[M][8]) {
+// the thread's 8 x 2 entries of tile (bi, bj).  Branch-free: indices
+// outside n x n are clamped into the matrix (rows to n - 1, columns to
+// lda - 2); sym_unpack zeroes those entries.
+template <class T>
+__device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda, long long n, long long I0,
+                                         long long j, typename Pair2<T>::type (&raw)[8]) {
     using V2 = typename Pair2<T>::type;
-    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
-    const long long n = P.n;
+    const int rg = (threadIdx.x & 63) >> 3;
+    const long long jc = min(j, lda - 2);
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        const long long j = min((long long)(bj0 + q) * SYM_TB + 2 * cp, lda - 2);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const long long i = min(I0 + rg + 8 * k, n - 1);
-            raw[q][k] = *(const V2*)(A + i * lda + j);
-        }
+    for (int k = 0; k < 8; ++k) {
+        const long long i = min(I0 + rg + 8 * k, n - 1);
+        raw[k] = __builtin_nontemporal_load((const V2*)(A + i * lda + jc));
     }
 }
 
-// the loaded entries as FP64, zero outside n x n (padding columns hold
-// unspecified values)
-template <class T, int M>
-__device__ __forceinline__ void sym_unpack(const typename Pair2<T>::type (&raw)[M][8], const SymPlan& P,
-                                           long long I0, int bj0, double (&a0)[M][8], double (&a1)[M][8]) {
-    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
-    const long long n = P.n;
+template <class T>
+__device__ __forceinline__ void sym_unpack(const typename Pair2<T>::type (&raw)[8], long long n, long long I0,
+                                           long long j, double (&a0)[8], double (&a1)[8]) {
+    const int rg = (threadIdx.x & 63) >> 3;
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        const long long j = (long long)(bj0 + q) * SYM_TB + 2 * cp;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const bool in = I0 + rg + 8 * k < n && j < n;
-            a0[q][k] = in ? (double)raw[q][k].x : 0.0;
-            a1[q][k] = (in && j + 1 < n) ? (double)raw[q][k].y : 0.0;
-        }
+    for (int k = 0; k < 8; ++k) {
+        const bool in = I0 + rg + 8 * k < n && j < n;
+        a0[k] = in ? (double)raw[k].x : 0.0;
+        a1[k] = (in && j + 1 < n) ? (double)raw[k].y : 0.0;
     }
 }
 
-// Products of the loaded tiles with v (LDS sv: v_I, then v_J of each tile;
-// written and synchronised by the caller); writes the slots and returns
-// this thread's share of the workgroup's part of v^T A v (diagonal tile
-// once, off-diagonal tiles twice).  redc: M x 8 x 64 doubles.
-template <int M>
-__device__ __forceinline__ double sym_finish(const SymPlan& P, int bi, int c, const double (&a0)[M][8],
-                                             const double (&a1)[M][8], const double* sv, double* redc) {
-    const int t = threadIdx.x, cp = t & 31, rg = t >> 5;
+// Vectors of the product, read as raw loads (issued early, with the tiles)
+// and turned into FP64 values afterwards: the vector x itself, or the CG
+// direction p_it = z + beta p_{it-1} formed on the fly.
+template <class T>
+struct SymVecX {
+    const T* x;
+    struct L {
+        T a;
+    };
+    __device__ __forceinline__ L load(long long i) const { return {x[i]}; }
+    __device__ __forceinline__ double val(const L& l) const { return (double)l.a; }
+};
+template <class T>
+struct SymVecP {
+    const T* z;
+    const T* pp;
+    T beta;
+    struct L {
+        T a, b;
+    };
+    __device__ __forceinline__ L load(long long i) const { return {z[i], pp[i]}; }
+    __device__ __forceinline__ double val(const L& l) const { return (double)(T)(l.a + beta * l.b); }
+};
+
+// One strip of the product with the vector V.  Writes the slots; returns
+// this thread's share of the strip's part of v^T A v (diagonal tile once,
+// off-diagonal tiles twice).  red: 256 doubles of LDS.  Loads of the next
+// tile and of its vector entries (indices clamped into the arrays, so the
+// loads are unconditional and the waits count only older ones) are issued
+// before the current tile is used.
+template <class T, class VF>
+__device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long lda, const SymPlan& P, int bi,
+                                            int c, const VF& V, double* red) {
+    using V2 = typename Pair2<T>::type;
+    using VL = typename VF::L;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, cp = lane & 7, rg = lane >> 3;
     const long long n = P.n, I0 = (long long)bi * SYM_TB;
-    const int bj0 = bi + c * M;
-    double racc[8];
+    const int b0 = bi + c * P.m, b1 = min(P.nb, b0 + P.m);
+    const int coff = 16 * w + 2 * cp;
+    double vi[8], racc[8];
+    {
+        VL li[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) racc[k] = 0.0;
+        for (int k = 0; k < 8; ++k) li[k] = V.load(min(I0 + rg + 8 * k, n - 1));
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-        const double* vJ = sv + 64 * (q + 1);
-        const double x0 = vJ[2 * cp], x1 = vJ[2 * cp + 1];
+        for (int k = 0; k < 8; ++k) {
+            vi[k] = I0 + rg + 8 * k < n ? V.val(li[k]) : 0.0;
+            racc[k] = 0.0;
+        }
+    }
+    double vd = 0.0;
+    // tile bj (its entries raw, its vector entries l0, l1) into the row and
+    // column sums
+    auto tile = [&](int bj, long long j, const V2 (&raw)[8], const VL& l0, const VL& l1) {
+        const double x0 = j < n ? V.val(l0) : 0.0, x1 = j + 1 < n ? V.val(l1) : 0.0;
+        double a0[8], a1[8];
+        sym_unpack<T>(raw, n, I0, j, a0, a1);
         double c0 = 0.0, c1 = 0.0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            racc[k] += a0[q][k] * x0 + a1[q][k] * x1;
-            const double vi = sv[rg + 8 * k];
-            c0 += a0[q][k] * vi;
-            c1 += a1[q][k] * vi;
+            racc[k] += a0[k] * x0 + a1[k] * x1;
+            c0 += a0[k] * vi[k];
+            c1 += a1[k] * vi[k];
         }
-        redc[q * 512 + rg * 64 + 2 * cp] = c0;
-        redc[q * 512 + rg * 64 + 2 * cp + 1] = c1;
-    }
-    __syncthreads();
-    double vd = 0.0;
-    if (t < 64) {
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const int bj = bj0 + q;
-            if (bj > bi && bj < P.nb) {
-                double s = 0.0;
-#pragma unroll
-                for (int g = 0; g < 8; ++g) s += redc[q * 512 + g * 64 + t];
-                const long long j = (long long)bj * SYM_TB + t;
-                if (j < n) P.pcol[(long long)bi * n + j] = s;
-                vd += s * sv[64 * (q + 1) + t];
+        if (bj > bi) {
+            // column sums over the 8 row groups (lane bits 3..5); lanes 0..7
+            // end with column j, lanes 32..39 with column j + 1
+            const int h5 = (lane >> 5) & 1;
+            double y = (h5 ? c1 : c0) + __shfl_xor(h5 ? c0 : c1, 32, 64);
+            y += __shfl_xor(y, 16, 64);
+            y += __shfl_xor(y, 8, 64);
+            if ((lane & 0x18) == 0) {
+                const long long jj = j + h5;
+                if (jj < n) {
+                    P.pcol[(long long)bi * n + jj] = y;
+                    vd += y * (h5 ? x1 : x0);
+                }
             }
         }
+    };
+    // two buffers in turn: the next tile's loads (and its vector entries)
+    // are issued before the current tile is used, with no copy between the
+    // buffers and no branch around the loads (the tile index is clamped to
+    // the strip: the last tile is loaded twice), so the waits count only
+    // the older loads
+    V2 ra[8], rb[8];
+    VL a0, a1, c0, c1;
+    const long long jl = (long long)(b1 - 1) * SYM_TB + coff;  // last tile of the strip
+    long long j = (long long)b0 * SYM_TB + coff;
+    sym_load<T>(A, lda, n, I0, j, ra);
+    a0 = V.load(min(j, n - 1));
+    a1 = V.load(min(j + 1, n - 1));
+    for (int bj = b0;; bj += 2, j += 2 * SYM_TB) {
+        const long long jb = min(j + SYM_TB, jl);
+        sym_load<T>(A, lda, n, I0, jb, rb);
+        c0 = V.load(min(jb, n - 1));
+        c1 = V.load(min(jb + 1, n - 1));
+        tile(bj, j, ra, a0, a1);
+        if (bj + 1 >= b1) break;
+        const long long ja = min(j + 2 * SYM_TB, jl);
+        sym_load<T>(A, lda, n, I0, ja, ra);
+        a0 = V.load(min(ja, n - 1));
+        a1 = V.load(min(ja + 1, n - 1));
+        tile(bj + 1, j + SYM_TB, rb, c0, c1);
+        if (bj + 2 >= b1) break;
     }
-    const double y = half_wave_sum8(racc, cp);
-    if ((cp & 3) == 0) {
-        const int r = rg + 8 * (cp >> 2);
-        if (I0 + r < n) {
-            P.prow[(long long)c * n + I0 + r] = y;
-            vd += y * sv[r];
+    // row sums: over the column pairs (lane bits 0..2, halving exchange:
+    // lane cp ends with row rg + 8 cp), then over the waves in order
+    {
+        const int q2 = (cp >> 2) & 1, q1 = (cp >> 1) & 1, q0 = cp & 1;
+        double w4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            w4[u] = (q2 ? racc[4 + u] : racc[u]) + __shfl_xor(q2 ? racc[u] : racc[4 + u], 4, 64);
+        double w2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) w2[u] = (q1 ? w4[2 + u] : w4[u]) + __shfl_xor(q1 ? w4[u] : w4[2 + u], 2, 64);
+        const double y = (q0 ? w2[1] : w2[0]) + __shfl_xor(q0 ? w2[0] : w2[1], 1, 64);
+        red[w * 64 + rg + 8 * cp] = y;
+    }
+    __syncthreads();
+    if (t < 64) {
+        const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
+        const long long i = I0 + t;
+        if (i < n) {
+            P.prow[(long long)c * n + i] = s;
+            vd += s * V.val(V.load(i));
         }
     }
     return vd;
@@ -1978,30 +2302,14 @@ __device__ __forceinline__ double group_sum(double s, int G) {
     return s;
 }
 
-// index of the vector entry thread t stages for workgroup (bi, bj0): v_I
-// for t < 64, then the columns of the M tiles (consecutive blocks)
-__device__ __forceinline__ long long sym_vec_index(long long I0, int bj0, int t) {
-    return t < 64 ? I0 + t : (long long)bj0 * SYM_TB + (t - 64);
-}
-
 // slots of A x (plain product)
-template <class T, int M>
+template <class T>
 __global__ __launch_bounds__(256) void symv_kernel(const T* __restrict__ A, long long lda, SymPlan P,
                                                    const T* __restrict__ x) {
-    __shared__ double sv[64 * (M + 1)];
-    __shared__ double redc[M * 512];
-    const int bi = blockIdx.y, c = blockIdx.x, bj0 = bi + c * M, t = threadIdx.x;
-    if (bj0 >= P.nb) return;
-    const long long I0 = (long long)bi * SYM_TB;
-    typename Pair2<T>::type raw[M][8];
-    sym_load<T, M>(A, lda, P, I0, bj0, raw);
-    const long long e = sym_vec_index(I0, bj0, t);
-    const T xv = x[min(e, P.n - 1)];
-    if (t < 64 * (M + 1)) sv[t] = e < P.n ? (double)xv : 0.0;
-    double a0[M][8], a1[M][8];
-    sym_unpack<T, M>(raw, P, I0, bj0, a0, a1);
-    __syncthreads();
-    (void)sym_finish<M>(P, bi, c, a0, a1, sv, redc);
+    __shared__ double red[256];
+    const int bi = blockIdx.y, c = blockIdx.x;
+    if (bi + c * P.m >= P.nb) return;
+    (void)sym_strip<T>(A, lda, P, bi, c, SymVecX<T>{x}, red);
 }
 
 // y = A x from the slots
@@ -2040,11 +2348,20 @@ __global__ __launch_bounds__(256) void sym_smooth_kernel(SymPlan P, double* x, c
 void sym_plan_geometry(long long n, SymPlan* P) {
     P->n = n;
     P->nb = (int)((n + SYM_TB - 1) / SYM_TB);
-    P->m = SYM_M;
+    // strip length: as long as SYM_M tiles while the triangle still holds
+    // about 4096 strips, so that the chip stays filled
+    const long long tiles = (long long)P->nb * (P->nb + 1) / 2;
+    P->m = (int)std::max<long long>(1, std::min<long long>(SYM_M, tiles / 4096));
     P->nchx = (P->nb + P->m - 1) / P->m;
     P->nwg = (long long)P->nchx * P->nb;
+    // large systems: CG scalars by a one-workgroup kernel, so the
+    // reductions may use 16 lanes per element; otherwise every workgroup
+    // of the product reduces the partials itself and their count stays
+    // below 1024
+    P->sk = n > SYM_SK_N ? 1 : 0;
     int G = 16;
-    while (G > 1 && (n * G + 255) / 256 > 1024) G >>= 1;
+    if (!P->sk)
+        while (G > 1 && (n * G + 255) / 256 > 1024) G >>= 1;
     P->G = G;
     P->nred = (int)std::max<long long>(1, (n * G + 255) / 256);
 }
@@ -2081,7 +2398,7 @@ void launch_sym_pq_reduce(const SymPlan& P, hipStream_t st) {
 
 template <class T>
 void symv_launch(const SymPlan& P, const T* A, long long lda, const T* x, hipStream_t st) {
-    hipLaunchKernelGGL((symv_kernel<T, SYM_M>), dim3(P.nchx, P.nb), dim3(256), 0, st, A, lda, P, x);
+    hipLaunchKernelGGL(symv_kernel<T>, dim3(P.nchx, P.nb), dim3(256), 0, st, A, lda, P, x);
 }
 
 void launch_symv(const SymPlan& P, const double* A, long long lda, const double* x, double* y, hipStream_t st) {
@@ -2151,8 +2468,8 @@ __global__ __launch_bounds__(256) void cg_init_kernel(ST S) {
 template <class ST>
 __global__ __launch_bounds__(256) void cg_init_reduce_kernel(ST S) {
     __shared__ double sh[12];
-    double bb = load_partials(S.part + 2 * S.nblk, S.nblk), u1 = 0.0, u2 = 0.0;
-    block_sum3(bb, u1, u2, sh);
+    double bb = load_partials(S.part + 2 * S.nblk, S.nblk), rz = load_partials(S.part, S.nblk), u2 = 0.0;
+    block_sum3(bb, rz, u2, sh);
     if (threadIdx.x == 0) {
         S.scal[0] = bb;
         S.scal[1] = bb;
@@ -2160,19 +2477,53 @@ __global__ __launch_bounds__(256) void cg_init_reduce_kernel(ST S) {
         S.flag[1] = 0;
         S.flag[2] = 0;
         if (!(bb == bb) || bb > 1.79e308) { S.flag[0] = 1; S.flag[2] = 2; }
+        if (S.sp.sk) {
+            // the scalar kernel's state for iteration 0 and its stop test
+            S.scal[2] = 0.0;
+            S.scal[3] = rz;
+            S.hist[0] = bb;
+            if (!S.flag[0] && (sqrt(bb) <= S.rtol * sqrt(bb) || S.maxit <= 0)) S.flag[0] = 1;
+        }
     }
 }
 
-template <class ST, int M>
+// Large systems: after cg_update(it), one workgroup reduces the r.z and r.r
+// partials of iteration it + 1 (fixed order), records r.r, applies the stop
+// test and leaves beta_{it+1} = rz_{it+1} / rz_it and rz_{it+1} for the
+// next cg_symv and cg_update, which then read two scalars instead of
+// reducing the partials in every workgroup.
+template <class ST>
+__global__ __launch_bounds__(256) void cg_scalar_kernel(ST S, int it) {
+    __shared__ double sh[12];
+    if (*(volatile int*)&S.flag[0]) return;
+    const int par1 = (it + 1) & 1;
+    double rz = load_partials(S.part + par1 * S.nblk, S.nblk);
+    double rr = load_partials(S.part + 2 * S.nblk + par1 * S.nblk, S.nblk), u = 0.0;
+    block_sum3(rz, rr, u, sh);
+    if (threadIdx.x == 0) {
+        S.hist[(it + 1) & 63] = rr;
+        const double bb = S.scal[0];
+        if (sqrt(rr) <= S.rtol * sqrt(bb) || it + 1 >= S.maxit || !(rr == rr)) {
+            S.flag[0] = 1;
+            S.flag[1] = it + 1;
+            S.scal[1] = rr;
+            if (!(rr == rr)) S.flag[2] = 2;
+        } else {
+            S.scal[2] = rz / S.scal[3];
+            S.scal[3] = rz;
+        }
+    }
+}
+
+template <class ST>
 __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     using T = cg_elem_t<ST>;
     __shared__ double sh[12];
-    __shared__ double sv[64 * (M + 1)];
-    __shared__ double redc[M * 512];
+    __shared__ double red[256];
     const SymPlan& P = S.sp;
-    const int bi = blockIdx.y, c = blockIdx.x, bj0 = bi + c * M, t = threadIdx.x;
+    const int bi = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
     const long long wg = (long long)bi * gridDim.x + c;
-    if (bj0 >= P.nb) {  // beyond the triangle: an empty partial
+    if (bi + c * P.m >= P.nb) {  // beyond the triangle: an empty partial
         if (t == 0) P.wpart[wg] = 0.0;
         return;
     }
@@ -2180,40 +2531,35 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     const int par = it & 1;
     const T* pprev = S.p + (long long)(1 - par) * n;
     T* pcur = S.p + (long long)par * n;
-    // loads that do not depend on the scalars: the tiles, z and p_{it-1} at
-    // the staged vector entries, the partial sums
-    typename Pair2<T>::type raw[M][8];
-    sym_load<T, M>(S.A, S.lda, P, I0, bj0, raw);
-    const long long e = sym_vec_index(I0, bj0, t);
-    const bool ein = t < 64 * (M + 1) && e < n;
-    const T zl = S.z[min(e, n - 1)], pl = pprev[min(e, n - 1)];
-    const T zr = ein ? zl : T(0), pr = ein ? pl : T(0);
-    double rz = load_partials(S.part + par * S.nblk, S.nblk);
-    double rr = load_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk);
-    double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
-    if (*(volatile int*)&S.flag[0]) return;
-    block_sum3(rz, rr, rzp, sh);
-    if (bi == 0 && c == 0 && t == 0) S.hist[it & 63] = rr;
-    const double bb = S.scal[0];
-    if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
-            S.flag[0] = 1;
-            S.flag[1] = it;
-            S.scal[1] = rr;
-            if (!(rr == rr)) S.flag[2] = 2;
+    double beta64;
+    if (P.sk) {
+        // stop test and beta from the scalar kernel of the last iteration
+        if (*(volatile int*)&S.flag[0]) return;
+        beta64 = it > 0 ? S.scal[2] : 0.0;
+    } else {
+        double rz = load_partials(S.part + par * S.nblk, S.nblk);
+        double rr = load_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk);
+        double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
+        if (*(volatile int*)&S.flag[0]) return;
+        block_sum3(rz, rr, rzp, sh);
+        if (bi == 0 && c == 0 && t == 0) S.hist[it & 63] = rr;
+        const double bb = S.scal[0];
+        if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
+            if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
+                S.flag[0] = 1;
+                S.flag[1] = it;
+                S.scal[1] = rr;
+                if (!(rr == rr)) S.flag[2] = 2;
+            }
+            return;
         }
-        return;
+        beta64 = it > 0 ? rz / rzp : 0.0;
     }
-    const T beta = (T)(it > 0 ? rz / rzp : 0.0);
-    double a0[M][8], a1[M][8];
-    sym_unpack<T, M>(raw, P, I0, bj0, a0, a1);
-    if (t < 64 * (M + 1)) {
-        const T v = zr + beta * pr;
-        sv[t] = (double)v;
-        if (t < 64 && c == 0 && e < n) pcur[e] = v;  // the chunk holding the diagonal tile
-    }
-    __syncthreads();
-    double vd = sym_finish<M>(P, bi, c, a0, a1, sv, redc), u1 = 0.0, u2 = 0.0;
+    const T beta = (T)beta64;
+    // p_it = z + beta p_{it-1}, formed where the product needs it; the
+    // strip holding the diagonal tile stores it
+    double vd = sym_strip<T>(S.A, S.lda, P, bi, c, SymVecP<T>{S.z, pprev, beta}, red), u1 = 0.0, u2 = 0.0;
+    if (c == 0 && t < 64 && I0 + t < n) pcur[I0 + t] = S.z[I0 + t] + beta * pprev[I0 + t];
     block_sum3(vd, u1, u2, sh);
     if (t == 0) P.wpart[wg] = vd;
 }
@@ -2231,7 +2577,7 @@ __global__ __launch_bounds__(256) void cg_update_kernel(ST S, int it) {
     const T* pcur = S.p + (long long)par * n;
     // every load first: partials, slots of A p, the element's vectors
     double pq = load_partials(P.pq, P.npq);
-    double rz = load_partials(S.part + par * S.nblk, S.nblk);
+    double rz = P.sk ? 0.0 : load_partials(S.part + par * S.nblk, S.nblk);
     double q = sym_gather_share(P, i, g);
     T pi = T(0), xi = T(0), ri = T(0), di = T(1);
     if (own) {
@@ -2243,6 +2589,7 @@ __global__ __launch_bounds__(256) void cg_update_kernel(ST S, int it) {
     if (*(volatile int*)&S.flag[0]) return;
     double u = 0.0;
     block_sum3(pq, rz, u, sh);
+    if (P.sk) rz = S.scal[3];
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             S.flag[0] = 1;
@@ -2281,6 +2628,60 @@ __global__ __launch_bounds__(256) void cg_final_kernel(ST S, int it) {
     if (threadIdx.x == 0 && !S.flag[0]) S.scal[1] = rr;
 }
 
+// Residual replacement for iteration it of a running CG (the FP32 inner
+// solve of the mixed-precision path): the correction x restarts from zero,
+// the recursive residual is replaced by S.b (the true residual, computed in
+// FP64 by the caller and rounded), z = r / d, and the r.z, r.r partials of
+// iteration it are rewritten; p_{it-1} is kept, so the next iteration
+// continues the same sequence of search directions (beta from the new r.z
+// and the last one) instead of restarting.
+template <class ST>
+__global__ __launch_bounds__(256) void cg_replace_kernel(ST S, int it) {
+    using T = cg_elem_t<ST>;
+    __shared__ double sh[12];
+    const long long i = (long long)blockIdx.x * (256 / S.sp.G) + threadIdx.x / S.sp.G;
+    const bool lead = (threadIdx.x & (S.sp.G - 1)) == 0;
+    double rz = 0.0, rr = 0.0, unused = 0.0;
+    if (lead && i < S.n) {
+        const T ri = S.b[i];
+        S.x[i] = T(0);
+        S.r[i] = ri;
+        const T zi = ri / S.d[i];
+        S.z[i] = zi;
+        rz = (double)ri * zi;
+        rr = (double)ri * ri;
+    }
+    block_sum3(rz, rr, unused, sh);
+    const int par = it & 1;
+    if (threadIdx.x == 0) {
+        S.part[par * S.nblk + blockIdx.x] = rz;
+        S.part[2 * S.nblk + par * S.nblk + blockIdx.x] = rr;
+    }
+}
+
+// after cg_replace: the new reference norm (the stop test of the segment
+// compares with it) and, for the scalar-kernel mode, beta_it and rz_it;
+// clears the stop flag (flag[1] keeps the iteration count)
+template <class ST>
+__global__ __launch_bounds__(256) void cg_replace_reduce_kernel(ST S, int it) {
+    __shared__ double sh[12];
+    const int par = it & 1;
+    double rr = load_partials(S.part + 2 * S.nblk + par * S.nblk, S.nblk);
+    double rz = load_partials(S.part + par * S.nblk, S.nblk), u = 0.0;
+    block_sum3(rr, rz, u, sh);
+    if (threadIdx.x == 0) {
+        S.scal[0] = rr;
+        S.scal[1] = rr;
+        S.flag[0] = 0;
+        S.flag[2] = 0;
+        if (S.sp.sk) {
+            S.hist[it & 63] = rr;
+            S.scal[2] = it > 0 ? rz / S.scal[3] : 0.0;
+            S.scal[3] = rz;
+        }
+    }
+}
+
 template <class ST>
 void cg_init_launch(const ST& s, hipStream_t st) {
     hipLaunchKernelGGL(cg_init_kernel<ST>, dim3(s.nblk), dim3(256), 0, st, s);
@@ -2289,9 +2690,10 @@ void cg_init_launch(const ST& s, hipStream_t st) {
 
 template <class ST>
 void cg_iter_launch(const ST& s, int it, hipStream_t st) {
-    hipLaunchKernelGGL((cg_symv_kernel<ST, SYM_M>), dim3(s.sp.nchx, s.sp.nb), dim3(256), 0, st, s, it);
+    hipLaunchKernelGGL(cg_symv_kernel<ST>, dim3(s.sp.nchx, s.sp.nb), dim3(256), 0, st, s, it);
     launch_sym_pq_reduce(s.sp, st);
     hipLaunchKernelGGL(cg_update_kernel<ST>, dim3(s.nblk), dim3(256), 0, st, s, it);
+    if (s.sp.sk) hipLaunchKernelGGL(cg_scalar_kernel<ST>, dim3(1), dim3(256), 0, st, s, it);
 }
 
 template <class ST>
@@ -2305,6 +2707,10 @@ void launch_cg_final(const CgState& s, int it, hipStream_t st) { cg_final_launch
 void launch_cg32_init(const CgState32& s, hipStream_t st) { cg_init_launch(s, st); }
 void launch_cg32_iter_at(const CgState32& s, int it, hipStream_t st) { cg_iter_launch(s, it, st); }
 void launch_cg32_final(const CgState32& s, int it, hipStream_t st) { cg_final_launch(s, it, st); }
+void launch_cg32_replace(const CgState32& s, int it, hipStream_t st) {
+    hipLaunchKernelGGL(cg_replace_kernel<CgState32>, dim3(s.nblk), dim3(256), 0, st, s, it);
+    hipLaunchKernelGGL(cg_replace_reduce_kernel<CgState32>, dim3(1), dim3(256), 0, st, s, it);
+}
 
 // out[0] = a.b, out[1] = a.c (deterministic two-pass)
 __global__ __launch_bounds__(256) void dot2_kernel(const double* a, const double* b, const double* c,
@@ -2365,6 +2771,16 @@ void launch_diag32(const float* A, long long lda, long long n, float* d, hipStre
 __global__ void add_correction_kernel(double* u, const float* e, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) u[i] += (double)e[i];
+}
+
+__global__ void cast_f32_kernel(const double* a, float* b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+void launch_cast_f32(const double* a, float* b, long long n, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(cast_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
 }
 
 void launch_add_correction(double* u, const float* e, long long n, hipStream_t st) {

@@ -62,7 +62,8 @@ class FlStats(C.Structure):
                 ("t_assemble_ms", C.c_double), ("t_far_ms", C.c_double), ("t_self_ms", C.c_double),
                 ("t_touch_ms", C.c_double), ("t_scatter_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("last_iters", C.c_int32), ("last_relres", C.c_double), ("last_outer", C.c_int32),
-                ("pairs_surrogate", C.c_int64), ("pairs_fallback", C.c_int64)]
+                ("pairs_surrogate", C.c_int64), ("pairs_fallback", C.c_int64),
+                ("t_cg_kernels_ms", C.c_double), ("cg_launched", C.c_int64)]
 
 
 class FlTrainOpts(C.Structure):

@@ -44,11 +44,11 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "fraclap.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
          offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres),
          sizeof(fl_tune_entry), offsetof(fl_tune_entry, gbps), offsetof(fl_opts, sur_tol),
          offsetof(fl_stats_t, pairs_fallback), sizeof(fl_train_opts), offsetof(fl_train_opts, seed),
-         (size_t)FL_SUR_BLOB);
+         (size_t)FL_SUR_BLOB, offsetof(fl_stats_t, cg_launched));
   return 0; }
 """)
     exe = tmp_path / "lay"
@@ -57,7 +57,8 @@ int main(void) {
     assert vals == [C.sizeof(F.FlOpts), F.FlOpts.theta.offset, F.FlOpts.k_far_bnd.offset,
                     C.sizeof(F.FlStats), F.FlStats.last_relres.offset,
                     C.sizeof(F.FlTuneEntry), F.FlTuneEntry.gbps.offset, F.FlOpts.sur_tol.offset,
-                    C.sizeof(F.FlStats) - 8, C.sizeof(F.FlTrainOpts), F.FlTrainOpts.seed.offset, F.SUR_BLOB]
+                    F.FlStats.pairs_fallback.offset, C.sizeof(F.FlTrainOpts), F.FlTrainOpts.seed.offset, F.SUR_BLOB,
+                    F.FlStats.cg_launched.offset]
 
 
 def test_surrogate_constants_match_generator():
