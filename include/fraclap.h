@@ -380,6 +380,19 @@ int fl_mass_matvec(fl_handle *h, const double *x, double *y);
  * upper triangle (64 x 64 tiles on and above the diagonal). */
 int fl_matvec(fl_handle *h, const double *x, double *y);
 
+/* fl_matvec without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same result,
+ * bit for bit, with the product's slots and partials in a scratch array of
+ * 48 MiB that the library holds on each device (resolved by fl_create).
+ * x, y: device, length n, not aliased.  FL_EINVAL (nothing launched) when
+ * the system needs more scratch than that (n above 19,456: use
+ * fl_matvec); FL_ESTATE before fl_assemble.  Every call on one device
+ * shares that device's scratch: calls that overlap on one GPU (two streams,
+ * two handles at once) race and must be serialised by the caller.
+ * Asynchronous on the handle's stream. */
+int fl_matvec_noalloc(fl_handle *h, const double *x, double *y);
+
 /* Jacobi-preconditioned CG on A u = b (Sec. 5).  b, u: device, length n;
  * u is overwritten (initial guess 0).  Stops when ||r||_2 <= rtol ||b||_2
  * or after maxit iterations (then FL_ENOCONV with the last iterate).

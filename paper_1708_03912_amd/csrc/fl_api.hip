@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,8 @@
 #include "fl_quad.hpp"
 
 using namespace fl;
+
+static double* noalloc_scratch(fl_handle* h);
 
 namespace {
 
@@ -265,6 +268,10 @@ int fl_create(fl_handle** out, int device, void* hip_stream) {
     h->device = device;
     h->stream = (hipStream_t)hip_stream;
     if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return FL_EDEVICE;
+    }
+    if (!noalloc_scratch(h)) {
         delete h;
         return FL_EDEVICE;
     }
@@ -1248,6 +1255,34 @@ int fl_mass_matvec(fl_handle* h, const double* x, double* y) {
 extern "C++" {
 int fl_solver_workspace(fl_handle* h) { return ensure_solver(h); }
 
+// Scratch of fl_matvec_noalloc, for callers that cannot allocate (code
+// under graph capture, serving loops): the slots and partials of the
+// symmetric product in a file-scope device array (each device the library
+// runs on holds its own copy until the process ends).  Host code uses only
+// the per-device address that hipGetSymbolAddress returns (the array's name
+// is not a device address on the host); it is resolved once per device by
+// fl_create, with that device current.
+static constexpr size_t FL_NOALLOC_DOUBLES = (size_t)6 << 20;  // 48 MiB
+static __device__ __align__(256) double scratch[FL_NOALLOC_DOUBLES];
+static constexpr int FL_NOALLOC_MAXDEV = 64;
+static double* g_scratch_dev[FL_NOALLOC_MAXDEV];
+static std::mutex g_scratch_mu;
+
+// the scratch address on h->device (the device must be current)
+static double* noalloc_scratch(fl_handle* h) {
+    if (h->device < 0 || h->device >= FL_NOALLOC_MAXDEV) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[h->device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_dev[h->device] = (double*)ptr;
+    }
+    return g_scratch_dev[h->device];
+}
+
 static int* stat_flag(char* b) { return (int*)b; }
 static double* stat_scal(char* b) { return (double*)(b + FL_STAT_SCAL); }
 static double* stat_hist(char* b) { return (double*)(b + FL_STAT_HIST); }
@@ -1328,6 +1363,32 @@ int fl_matvec(fl_handle* h, const double* x, double* y) {
     int rc = ensure_solver(h);
     if (rc) return rc;
     launch_symv(h->sym, h->dA, h->lda, x, y, h->stream);
+    HIPCHK(hipGetLastError());
+    return FL_OK;
+}
+
+int fl_matvec_noalloc(fl_handle* h, const double* x, double* y) {
+    if (!h) return FL_EINVAL;
+    if (!h->assembled) return fail(h, FL_ESTATE, "no assembled matrix");
+    if (h->n == 0) return FL_OK;
+    if (!x || !y) return fail(h, FL_EINVAL, "null vector");
+    if (x == y) return fail(h, FL_EINVAL, "x and y must not alias");
+    HIPCHK(hipSetDevice(h->device));
+    SymPlan sp{};
+    sym_plan_geometry(h->n, &sp);
+    const size_t need = sym_plan_doubles(sp);
+    if (need > FL_NOALLOC_DOUBLES) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "fl_matvec_noalloc: n = %lld needs %zu MiB of scratch, more than its %zu MiB; use fl_matvec",
+                      (long long)h->n, (need * sizeof(double) + (1 << 20) - 1) >> 20,
+                      (FL_NOALLOC_DOUBLES * sizeof(double)) >> 20);
+        return fail(h, FL_EINVAL, msg);
+    }
+    double* buf = noalloc_scratch(h);
+    if (!buf) return fail(h, FL_EDEVICE, "fl_matvec_noalloc: no scratch address on this device");
+    sym_plan_bind(&sp, buf);
+    launch_symv(sp, h->dA, h->lda, x, y, h->stream);
     HIPCHK(hipGetLastError());
     return FL_OK;
 }

@@ -39,7 +39,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
            "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
            "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry",
-           "fl_strong_form_cluster", "fl_solve_cluster_mg"]
+           "fl_strong_form_cluster", "fl_solve_cluster_mg", "fl_matvec_noalloc"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -109,6 +109,7 @@ def lib():
         L.fl_export_matrix.argtypes = [vp, vp, i64, C.c_int]
         L.fl_load_vector_one.argtypes = [vp, vp]
         L.fl_matvec.argtypes = [vp, vp, vp]
+        L.fl_matvec_noalloc.argtypes = [vp, vp, vp]
         L.fl_mass_matvec.argtypes = [vp, vp, vp]
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
         L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
@@ -278,6 +279,9 @@ class Handle:
 
     def matvec(self, x, y):
         self._check(lib().fl_matvec(self.h, _ptr(x), _ptr(y)))
+
+    def matvec_noalloc(self, x, y):
+        self._check(lib().fl_matvec_noalloc(self.h, _ptr(x), _ptr(y)))
 
     def mass_matvec(self, x, y):
         self._check(lib().fl_mass_matvec(self.h, _ptr(x), _ptr(y)))
