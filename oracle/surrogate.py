@@ -352,16 +352,33 @@ def band_pairs(mesh, theta, nsur):
 
 
 def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True, full=False,
-                       with_boundary=True):
+                       with_boundary=True, rows=None):
     """A^s on the DOF set with the band pairs (order class < nsur) done by
     the surrogate where certified (features inside net['lo'] .. net['hi']
     and net['bound'][distance bin, s bin] <= tol), by the exact rule of
     their class otherwise.  Returns (A, dofs, n_surrogate, n_fallback);
-    full=True: A over all nodes instead."""
-    Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur, with_boundary=with_boundary)
+    full=True: A over all nodes instead.  rows (vertex indices): only
+    those rows of the all-node matrix, (len(rows) x nv), from the pairs
+    that touch them; the counts are then those of these pairs."""
     V = np.asarray(mesh["verts"], dtype=np.float64)
     Cc = np.asarray(mesh["cells"], dtype=np.int64)
     P = band_pairs(mesh, orders.theta, nsur)
+    rowpos = None
+    if rows is not None:
+        rows = np.asarray(rows, dtype=np.int64)
+        Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur, with_boundary=with_boundary,
+                                   rows=rows, compact=True)
+        rowpos = {int(v): r for r, v in enumerate(rows)}
+        hit = np.isin(Cc, rows).any(axis=1)
+        P = P[hit[P[:, 0]] | hit[P[:, 1]]]
+    else:
+        Afull, _ = O.assemble_full(mesh, s, orders, far_skip_below=nsur, with_boundary=with_boundary)
+
+    def add(i, j, x):
+        if rowpos is None:
+            Afull[i, j] += x
+        elif int(i) in rowpos:
+            Afull[rowpos[int(i)], j] += x
     Cd = O.cdn(2, s)
     X = V[Cc[P[:, 0]]].reshape(-1, 6)
     Y = V[Cc[P[:, 1]]].reshape(-1, 6)
@@ -392,13 +409,16 @@ def assemble_surrogate(mesh, s, orders, net, nsur, tol, mode="paper", fp16=True,
         v = vals[i]
         for q, (a, b) in enumerate(SYM):
             for (u, w) in {(a, b), (b, a)}:
-                Afull[g1[u], g1[w]] += Cd * v[q]
-                Afull[g2[u], g2[w]] += Cd * v[6 + q]
+                add(g1[u], g1[w], Cd * v[q])
+                add(g2[u], g2[w], Cd * v[6 + q])
         for a in range(3):
             for b in range(3):
                 x = Cd * v[12 + 3 * a + b]
-                Afull[g1[a], g2[b]] -= x
-                Afull[g2[b], g1[a]] -= x
+                add(g1[a], g2[b], -x)
+                add(g2[b], g1[a], -x)
     dofs = O.dof_nodes(len(V), np.asarray(mesh["bfacets"]), s, mode)
-    A = Afull if full else Afull[np.ix_(dofs, dofs)]
+    if rowpos is not None:
+        A = Afull if full else Afull[:, dofs]
+    else:
+        A = Afull if full else Afull[np.ix_(dofs, dofs)]
     return A, dofs, int(use.sum()), int((~use).sum())

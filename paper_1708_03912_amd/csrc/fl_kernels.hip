@@ -128,6 +128,40 @@ __device__ __forceinline__ void load_pow_tables(double* pw) {
         pw[i] = i < 512 ? ((i & 1) ? c_R.pw_fr[i >> 1] : c_R.pw_inv[i >> 1]) : c_R.pw_ex[i - 512];
 }
 
+// N kernel powers from the LDS tables in three phases -- squared-distance
+// bits and table offsets, the table reads, the polynomials -- with
+// scheduling barriers between them, so that the N pairs of reads are in
+// flight together instead of one pair at a time.
+template <int N>
+__device__ __forceinline__ void kpow_tab_batch(const KPowTab& kp, const double (&r2)[N], double (&kv)[N]) {
+    int hi[N];
+    double m[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        hi[p] = __double2hiint(r2[p]);
+        m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2[p]));
+    }
+    double2 fr[N];
+    double ex[N];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        fr[p] = ((const double2*)kp.pw)[(hi[p] >> 12) & 255];
+        ex[p] = kp.pw[512 + (hi[p] >> 20) - 895];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        const double t = fma(m[p], fr[p].x, -1.0);
+        double pp = fma(kp.c5, t, kp.c4);
+        pp = fma(pp, t, kp.c3);
+        pp = fma(pp, t, kp.c2);
+        pp = fma(pp, t, kp.c1);
+        pp = fma(pp, t, 1.0);
+        kv[p] = (pp * fr[p].y) * ex[p];
+    }
+}
+
 // Fixed order KO: factorised sums.  With k_pq = k(x_p, y_q) and the rule's
 // weights w and barycentric values l:
 //   G_p = sum_q w_q k_pq,  H_q = sum_p w_p k_pq,  M_pb = sum_q w_q l_b(y_q) k_pq,
@@ -164,10 +198,25 @@ __device__ __forceinline__ void far_pair2_fixed(const double* X, const double* Y
         const double yy = Y[1] + cq[0] * fy0 + cq[1] * fy1;
         const double wq = cq[2], v0 = cq[3], v1 = cq[4], v2 = cq[5];
         double H = 0.0;
+        double kvs[Q];
+        if constexpr (std::is_same<KP, KPowTab>::value) {
+            double r2[Q];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const double dx = px[p] - yx, dy = py[p] - yy;
+                r2[p] = dx * dx + dy * dy;
+            }
+            kpow_tab_batch<Q>(kp, r2, kvs);
+        } else {
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const double dx = px[p] - yx, dy = py[p] - yy;
+                kvs[p] = kp(dx * dx + dy * dy);
+            }
+        }
 #pragma unroll
         for (int p = 0; p < Q; ++p) {
-            const double dx = px[p] - yx, dy = py[p] - yy;
-            const double kv = kp(dx * dx + dy * dy);
+            const double kv = kvs[p];
             G[p] += wq * kv;
             H += c_R.tri[off + p][2] * kv;
             M[p][0] += v0 * kv;
@@ -776,7 +825,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ unsigned short plist[BE * BE];
     __shared__ int ccnt[FL_MAX_CLASSES + 1], coff[FL_MAX_CLASSES + 2], cfill[FL_MAX_CLASSES + 1];
     __shared__ float souts[SUR ? 4 * 16 * 24 : 1];  // network outputs, 16 samples per wave
-    constexpr bool TAB = DIM == 2 && !MIX && !SUR;   // FP64 kernel power by LDS tables
+    constexpr bool TAB = DIM == 2 && !MIX;   // FP64 kernel power by LDS tables
     __shared__ __align__(16) double pw[TAB ? 768 : 1];
 
     const long long t = blockIdx.x;
@@ -967,7 +1016,8 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                         C2[2 * a] = Sp[2 * o2[a]];
                         C2[2 * a + 1] = Sp[2 * o2[a] + 1];
                     }
-                    if (MIX) far_pair2_f32<2>(2, C1, C2, P.pe, SK, ST, O);
+                    if constexpr (MIX) far_pair2_f32<2>(2, C1, C2, P.pe, SK, ST, O);
+                    else if constexpr (TAB) far_pair2<2>(2, C1, C2, make_kpow_tab(pw), SK, ST, O);
                     else far_pair2<2>(2, C1, C2, P.pe, SK, ST, O);
 #pragma unroll
                     for (int j = 0; j < 6; ++j) {
@@ -979,7 +1029,8 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                         O[j] *= 1.0 + ((double)tv[12 + j] * (double)SP.N.st[12 + j] + (double)SP.N.mt[12 + j]);
                     sur_sum_rules(SK, ST, O);
                 } else {
-                    far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, SK, ST, O);
+                    if constexpr (TAB) far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, make_kpow_tab(pw), SK, ST, O);
+                    else far_pair<2, MIX>(P.kf[cls], X, Y, P.pe, SK, ST, O);
                 }
             }
             for (int c = 0; c < c0; ++c) {
@@ -1136,13 +1187,18 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 // numbering; a spare row and column take the vertices without a DOF, so the
 // adds are branch-free.  The Psi partials of the four waves are added in
 // wave order.
-template <int KO, int W>
+// MIX = 1 (FL_MIXED): the evaluations in FP32 (hardware log2 / exp2), the
+// points relative to an origin in the row block (the first row's first
+// vertex), so that their rounding error stays relative to the pair's
+// distance; the sums of a pair are formed in FP32 and added in FP64.
+template <int KO, int MIX, int W>
 __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
     constexpr int Q = KO * KO;
     constexpr int LS = MAXV + 1;  // row stride of L; row / column MAXV: vertices without a DOF
-    __shared__ __align__(16) double pw[768];
+    __shared__ __align__(16) double pw[MIX ? 2 : 768];
     __shared__ __align__(16) double L[LS * LS];
-    __shared__ __align__(16) double sX[BE][2 * Q];  // rows' mapped points, (x, y) per point
+    using XT = std::conditional_t<MIX, float, double>;
+    __shared__ __align__(16) XT sX[BE][2 * Q];       // rows' mapped points, (x, y) per point
     __shared__ double sMK[BE];                      // |K| of the rows (0 past T)
     __shared__ int sRO[BE][3];                      // byte offsets of the rows' L rows
     __shared__ double sPhi[BE][Q];
@@ -1156,8 +1212,10 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
     const bool direct = (nVI > MAXV) || (nVJ > MAXV);
     const int T = P.T;
     constexpr int off = (KO - 1) * KO * (2 * KO - 1) / 6;  // tri_off(KO)
+    // origin of the FP32 coordinates (unused in FP64)
+    const double o0 = MIX ? E.x[0][I0] : 0.0, o1 = MIX ? E.x[1][I0] : 0.0;
 
-    load_pow_tables(pw);
+    if constexpr (!MIX) load_pow_tables(pw);
     for (int i = tid; i < LS * LS; i += 256) L[i] = 0.0;
     if (!direct)
         for (int i = tid; i < MAXV; i += 256) {
@@ -1175,8 +1233,8 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
 #pragma unroll
         for (int p = 0; p < Q; ++p) {
             const double* cp = c_R.tri[off + p];
-            sX[r][2 * p] = X[0] + cp[0] * ex0 + cp[1] * ex1;
-            sX[r][2 * p + 1] = X[1] + cp[0] * ey0 + cp[1] * ey1;
+            sX[r][2 * p] = (XT)((X[0] - o0) + cp[0] * ex0 + cp[1] * ex1);
+            sX[r][2 * p + 1] = (XT)((X[1] - o1) + cp[0] * ey0 + cp[1] * ey1);
         }
         sMK[r] = ok ? E.meas[Kc] : 0.0;
 #pragma unroll
@@ -1199,8 +1257,8 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double* cq = c_R.tri[off + q];
-            yq[2 * q] = Y[0] + cq[0] * fx0 + cq[1] * fx1;
-            yq[2 * q + 1] = Y[1] + cq[0] * fy0 + cq[1] * fy1;
+            yq[2 * q] = (Y[0] - o0) + cq[0] * fx0 + cq[1] * fx1;
+            yq[2 * q + 1] = (Y[1] - o1) + cq[0] * fy0 + cq[1] * fy1;
         }
     }
     const double ct = okt ? P.C * E.meas[Ktc] : 0.0;
@@ -1219,6 +1277,10 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
         for (int b = 0; b < 3; ++b) cw[q][b] = c_R.tri[off + q][3 + b];
     }
     const KPowTab kp = make_kpow_tab(pw);
+    float yqf[2 * Q];
+#pragma unroll
+    for (int c = 0; c < 2 * Q; ++c) yqf[c] = (float)yq[c];
+    const float pef = (float)P.pe;
     double Psi[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) Psi[q] = 0.0;
@@ -1228,55 +1290,59 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
         if (I0 + r >= T) break;
         double xp[2 * Q];
 #pragma unroll
-        for (int p = 0; p < Q; ++p) {
-            const double2 v = *(const double2*)&sX[r][2 * p];
-            xp[2 * p] = v.x;
-            xp[2 * p + 1] = v.y;
-        }
+        for (int c = 0; c < 2 * Q; ++c) xp[c] = sX[r][c];
         double f = sMK[r] * ct;
         if constexpr (W) f *= okt ? pair_w(E, I0 + r, Kt) : 0.0;
         double M[Q][3], H[Q];
+        if constexpr (MIX) {
+            float xf[2 * Q], Mf[Q][3];
+#pragma unroll
+            for (int c = 0; c < 2 * Q; ++c) xf[c] = sX[r][c];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) Mf[p][0] = Mf[p][1] = Mf[p][2] = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                float h = 0.f;
+#pragma unroll
+                for (int p = 0; p < Q; ++p) {
+                    const float dx = xf[2 * p] - yqf[2 * q], dy = xf[2 * p + 1] - yqf[2 * q + 1];
+                    const float kv = kpow32(dx * dx + dy * dy, pef);
+                    Mf[p][0] += (float)cw[q][0] * kv;
+                    Mf[p][1] += (float)cw[q][1] * kv;
+                    Mf[p][2] += (float)cw[q][2] * kv;
+                    h += (float)wq[p] * kv;
+                }
+                H[q] = h;
+            }
+#pragma unroll
+            for (int p = 0; p < Q; ++p)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) M[p][b] = Mf[p][b];
+        } else {
 #pragma unroll
         for (int p = 0; p < Q; ++p) M[p][0] = M[p][1] = M[p][2] = 0.0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            // the Q evaluations of this point of Kt in three phases, so that
-            // their table reads are in flight together: squared distances
-            // and table offsets, the reads, then the polynomials
-            int hi[Q];
-            double m[Q];
+            // the Q evaluations of this point of Kt, their table reads in
+            // flight together
+            double r2[Q], kvs[Q];
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
                 const double dx = xp[2 * p] - yq[2 * q], dy = xp[2 * p + 1] - yq[2 * q + 1];
-                const double r2 = dx * dx + dy * dy;
-                hi[p] = __double2hiint(r2);
-                m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2));
+                r2[p] = dx * dx + dy * dy;
             }
-            double2 fr[Q];
-            double ex[Q];
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int p = 0; p < Q; ++p) {
-                fr[p] = ((const double2*)pw)[(hi[p] >> 12) & 255];
-                ex[p] = pw[512 + (hi[p] >> 20) - 895];
-            }
-            __builtin_amdgcn_sched_barrier(0);
+            kpow_tab_batch<Q>(kp, r2, kvs);
             double h = 0.0;
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
-                const double t = fma(m[p], fr[p].x, -1.0);
-                double pp = fma(kp.c5, t, kp.c4);
-                pp = fma(pp, t, kp.c3);
-                pp = fma(pp, t, kp.c2);
-                pp = fma(pp, t, kp.c1);
-                pp = fma(pp, t, 1.0);
-                const double kv = (pp * fr[p].y) * ex[p];
+                const double kv = kvs[p];
                 M[p][0] += cw[q][0] * kv;
                 M[p][1] += cw[q][1] * kv;
                 M[p][2] += cw[q][2] * kv;
                 h += wq[p] * kv;
             }
             H[q] = h;
+        }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) Psi[q] += f * H[q];
@@ -1392,15 +1458,17 @@ void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_
         if (P.mixed) hipLaunchKernelGGL((far_kernel<D, K, 1>), grid, block, 0, st, E, P); \
         else hipLaunchKernelGGL((far_kernel<D, K, 0>), grid, block, 0, st, E, P);         \
     } while (0)
-    if (P.dim == 2 && !P.mixed && fark <= 2) {
+    if (P.dim == 2 && fark <= 2) {
         const bool w = E.w != nullptr;
+#define FL_FAR2(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W>), grid, block, 0, st, E, P)
         if (fark == 1) {
-            if (w) hipLaunchKernelGGL((far2_kernel<1, 1>), grid, block, 0, st, E, P);
-            else hipLaunchKernelGGL((far2_kernel<1, 0>), grid, block, 0, st, E, P);
+            if (P.mixed) { if (w) FL_FAR2(1, 1, 1); else FL_FAR2(1, 1, 0); }
+            else { if (w) FL_FAR2(1, 0, 1); else FL_FAR2(1, 0, 0); }
         } else {
-            if (w) hipLaunchKernelGGL((far2_kernel<2, 1>), grid, block, 0, st, E, P);
-            else hipLaunchKernelGGL((far2_kernel<2, 0>), grid, block, 0, st, E, P);
+            if (P.mixed) { if (w) FL_FAR2(2, 1, 1); else FL_FAR2(2, 1, 0); }
+            else { if (w) FL_FAR2(2, 0, 1); else FL_FAR2(2, 0, 0); }
         }
+#undef FL_FAR2
     } else if (P.dim == 2) {
         switch (fark) {
             case 1: FL_FAR_CASE(2, 1); break;
@@ -2114,15 +2182,18 @@ struct Pair2<float> {
 // the thread's 8 x 2 entries of tile (bi, bj).  Branch-free: indices
 // outside n x n are clamped into the matrix (rows to n - 1, columns to
 // lda - 2); sym_unpack zeroes those entries.
+// live = false: the loads still issue (so that the waits of the caller
+// count the same loads on every path) but all read row I0 of the tile just
+// loaded, which is in the cache; the values are not used.
 template <class T>
 __device__ __forceinline__ void sym_load(const T* __restrict__ A, long long lda, long long n, long long I0,
-                                         long long j, typename Pair2<T>::type (&raw)[8]) {
+                                         long long j, typename Pair2<T>::type (&raw)[8], bool live = true) {
     using V2 = typename Pair2<T>::type;
     const int rg = (threadIdx.x & 63) >> 3;
     const long long jc = min(j, lda - 2);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const long long i = min(I0 + rg + 8 * k, n - 1);
+        const long long i = live ? min(I0 + rg + 8 * k, n - 1) : min(I0, n - 1);
         raw[k] = __builtin_nontemporal_load((const V2*)(A + i * lda + jc));
     }
 }
@@ -2221,29 +2292,32 @@ __device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long l
     };
     // two buffers in turn: the next tile's loads (and its vector entries)
     // are issued before the current tile is used, with no copy between the
-    // buffers and no branch around the loads (the tile index is clamped to
-    // the strip: the last tile is loaded twice), so the waits count only
-    // the older loads
+    // buffers and no branch around the loads (past the end of the strip they
+    // read the current tile's first row again), so the waits count only the
+    // older loads
     V2 ra[8], rb[8];
     VL a0, a1, c0, c1;
-    const long long jl = (long long)(b1 - 1) * SYM_TB + coff;  // last tile of the strip
     long long j = (long long)b0 * SYM_TB + coff;
     sym_load<T>(A, lda, n, I0, j, ra);
     a0 = V.load(min(j, n - 1));
     a1 = V.load(min(j + 1, n - 1));
     for (int bj = b0;; bj += 2, j += 2 * SYM_TB) {
-        const long long jb = min(j + SYM_TB, jl);
-        sym_load<T>(A, lda, n, I0, jb, rb);
+        const bool lb = bj + 1 < b1;
+        const long long jb = lb ? j + SYM_TB : j;
+        sym_load<T>(A, lda, n, I0, jb, rb, lb);
         c0 = V.load(min(jb, n - 1));
         c1 = V.load(min(jb + 1, n - 1));
+        __builtin_amdgcn_sched_barrier(0);  // no use of rb, c0, c1 moves above here
         tile(bj, j, ra, a0, a1);
-        if (bj + 1 >= b1) break;
-        const long long ja = min(j + 2 * SYM_TB, jl);
-        sym_load<T>(A, lda, n, I0, ja, ra);
+        if (!lb) break;
+        const bool la = bj + 2 < b1;
+        const long long ja = la ? j + 2 * SYM_TB : j + SYM_TB;
+        sym_load<T>(A, lda, n, I0, ja, ra, la);
         a0 = V.load(min(ja, n - 1));
         a1 = V.load(min(ja + 1, n - 1));
+        __builtin_amdgcn_sched_barrier(0);
         tile(bj + 1, j + SYM_TB, rb, c0, c1);
-        if (bj + 2 >= b1) break;
+        if (!la) break;
     }
     // row sums: over the column pairs (lane bits 0..2, halving exchange:
     // lane cp ends with row rg + 8 cp), then over the waves in order
@@ -2269,6 +2343,149 @@ __device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long l
         }
     }
     return vd;
+}
+
+// FP32 matrix: the same strip with 16-byte loads.  Thread (wave w, lane l)
+// holds columns 32 (w & 1) + 4 (l & 7) .. + 3 of tile b + (w >> 1) and rows
+// (l >> 3) + 8 k, so one step of the workgroup covers two tiles (waves 0, 1
+// the first, waves 2, 3 the second) with eight loads per thread.  Column
+// sums: a four-value halving exchange over the row groups (lanes with
+// (l >> 3) = 0, 2, 4, 6 end with columns +0..+3); row sums as above.
+typedef float sym_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void sym_load4(const float* __restrict__ A, long long lda, long long n, long long I0,
+                                          long long j, sym_f4 (&raw)[8], bool live) {
+    const int rg = (threadIdx.x & 63) >> 3;
+    const long long jc = min(j, lda - 4);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const long long i = live ? min(I0 + rg + 8 * k, n - 1) : min(I0, n - 1);
+        raw[k] = __builtin_nontemporal_load((const sym_f4*)(A + i * lda + jc));
+    }
+}
+
+template <class VF>
+__device__ __forceinline__ double sym_strip4(const float* __restrict__ A, long long lda, const SymPlan& P, int bi,
+                                             int c, const VF& V, double* red) {
+    using VL = typename VF::L;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, cq = lane & 7, rg = lane >> 3;
+    const long long n = P.n, I0 = (long long)bi * SYM_TB;
+    const int b0 = bi + c * P.m, b1 = min(P.nb, b0 + P.m);
+    const int half = w >> 1, coff = 32 * (w & 1) + 4 * cq;
+    double vi[8], racc[8];
+    {
+        VL li[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) li[k] = V.load(min(I0 + rg + 8 * k, n - 1));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            vi[k] = I0 + rg + 8 * k < n ? V.val(li[k]) : 0.0;
+            racc[k] = 0.0;
+        }
+    }
+    double vd = 0.0;
+    // this wave's tile of step s (tile b0 + 2 s + half), its first column,
+    // and whether it lies in the strip
+    auto col = [&](int s) { return (long long)(b0 + 2 * s + half) * SYM_TB + coff; };
+    auto live = [&](int s) { return b0 + 2 * s + half < b1; };
+    auto step = [&](int s, const sym_f4 (&raw)[8], const VL (&lx)[4]) {
+        const int bj = b0 + 2 * s + half;
+        const bool lv = bj < b1;
+        const long long j = (long long)bj * SYM_TB + coff;
+        double x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = (lv && j + m < n) ? V.val(lx[m]) : 0.0;
+        double cs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool in = lv && I0 + rg + 8 * k < n;
+            const double a[4] = {(in && j < n) ? (double)raw[k].x : 0.0, (in && j + 1 < n) ? (double)raw[k].y : 0.0,
+                                 (in && j + 2 < n) ? (double)raw[k].z : 0.0,
+                                 (in && j + 3 < n) ? (double)raw[k].w : 0.0};
+            racc[k] += (a[0] * x[0] + a[1] * x[1]) + (a[2] * x[2] + a[3] * x[3]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) cs[m] += a[m] * vi[k];
+        }
+        if (lv && bj > bi) {
+            const int h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1;
+            double u[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                u[q] = (h5 ? cs[2 + q] : cs[q]) + __shfl_xor(h5 ? cs[q] : cs[2 + q], 32, 64);
+            double y = (h4 ? u[1] : u[0]) + __shfl_xor(h4 ? u[0] : u[1], 16, 64);
+            y += __shfl_xor(y, 8, 64);
+            if ((lane & 8) == 0) {
+                const int m = 2 * h5 + h4;
+                if (j + m < n) {
+                    P.pcol[(long long)bi * n + j + m] = y;
+                    vd += y * x[m];
+                }
+            }
+        }
+    };
+    const int ns = (b1 - b0 + 1) / 2;  // steps of two tiles
+    sym_f4 ra[8], rb[8];
+    VL la[4], lb[4];
+    {
+        const bool l0 = live(0);
+        const long long j = l0 ? col(0) : (long long)b0 * SYM_TB + coff;
+        sym_load4(A, lda, n, I0, j, ra, l0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) la[m] = V.load(min(j + m, n - 1));
+    }
+    for (int s = 0;; s += 2) {
+        {
+            const bool ln = s + 1 < ns && live(s + 1);
+            const long long j = ln ? col(s + 1) : (long long)b0 * SYM_TB + coff;
+            sym_load4(A, lda, n, I0, j, rb, ln);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) lb[m] = V.load(min(j + m, n - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        step(s, ra, la);
+        if (s + 1 >= ns) break;
+        {
+            const bool ln = s + 2 < ns && live(s + 2);
+            const long long j = ln ? col(s + 2) : (long long)b0 * SYM_TB + coff;
+            sym_load4(A, lda, n, I0, j, ra, ln);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) la[m] = V.load(min(j + m, n - 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        step(s + 1, rb, lb);
+        if (s + 2 >= ns) break;
+    }
+    // row sums: over the column quads (lane bits 0..2), then the waves
+    {
+        const int q2 = (cq >> 2) & 1, q1 = (cq >> 1) & 1, q0 = cq & 1;
+        double w4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            w4[u] = (q2 ? racc[4 + u] : racc[u]) + __shfl_xor(q2 ? racc[u] : racc[4 + u], 4, 64);
+        double w2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) w2[u] = (q1 ? w4[2 + u] : w4[u]) + __shfl_xor(q1 ? w4[u] : w4[2 + u], 2, 64);
+        const double y = (q0 ? w2[1] : w2[0]) + __shfl_xor(q0 ? w2[0] : w2[1], 1, 64);
+        red[w * 64 + rg + 8 * cq] = y;
+    }
+    __syncthreads();
+    if (t < 64) {
+        const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
+        const long long i = I0 + t;
+        if (i < n) {
+            P.prow[(long long)c * n + i] = s;
+            vd += s * V.val(V.load(i));
+        }
+    }
+    return vd;
+}
+
+// the strip for either matrix type
+template <class T, class VF>
+__device__ __forceinline__ double sym_strip_any(const T* __restrict__ A, long long lda, const SymPlan& P, int bi,
+                                                int c, const VF& V, double* red) {
+    if constexpr (std::is_same<T, float>::value) return sym_strip4(A, lda, P, bi, c, V, red);
+    else return sym_strip<T>(A, lda, P, bi, c, V, red);
 }
 
 // this lane's share of (A v)_i from the slots (lane g of an aligned group
@@ -2309,7 +2526,7 @@ __global__ __launch_bounds__(256) void symv_kernel(const T* __restrict__ A, long
     __shared__ double red[256];
     const int bi = blockIdx.y, c = blockIdx.x;
     if (bi + c * P.m >= P.nb) return;
-    (void)sym_strip<T>(A, lda, P, bi, c, SymVecX<T>{x}, red);
+    (void)sym_strip_any<T>(A, lda, P, bi, c, SymVecX<T>{x}, red);
 }
 
 // y = A x from the slots
@@ -2348,10 +2565,11 @@ __global__ __launch_bounds__(256) void sym_smooth_kernel(SymPlan P, double* x, c
 void sym_plan_geometry(long long n, SymPlan* P) {
     P->n = n;
     P->nb = (int)((n + SYM_TB - 1) / SYM_TB);
-    // strip length: as long as SYM_M tiles while the triangle still holds
-    // about 4096 strips, so that the chip stays filled
+    // strip length: up to SYM_M tiles while the triangle still holds about
+    // 2048 strips (the chip stays filled), at least 3 (the fixed cost of a
+    // workgroup is spread over several tiles)
     const long long tiles = (long long)P->nb * (P->nb + 1) / 2;
-    P->m = (int)std::max<long long>(1, std::min<long long>(SYM_M, tiles / 4096));
+    P->m = (int)std::max<long long>(3, std::min<long long>(SYM_M, tiles / 2048));
     P->nchx = (P->nb + P->m - 1) / P->m;
     P->nwg = (long long)P->nchx * P->nb;
     // large systems: CG scalars by a one-workgroup kernel, so the
@@ -2558,7 +2776,7 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     const T beta = (T)beta64;
     // p_it = z + beta p_{it-1}, formed where the product needs it; the
     // strip holding the diagonal tile stores it
-    double vd = sym_strip<T>(S.A, S.lda, P, bi, c, SymVecP<T>{S.z, pprev, beta}, red), u1 = 0.0, u2 = 0.0;
+    double vd = sym_strip_any<T>(S.A, S.lda, P, bi, c, SymVecP<T>{S.z, pprev, beta}, red), u1 = 0.0, u2 = 0.0;
     if (c == 0 && t < 64 && I0 + t < n) pcur[I0 + t] = S.z[I0 + t] + beta * pprev[I0 + t];
     block_sum3(vd, u1, u2, sh);
     if (t == 0) P.wpart[wg] = vd;

@@ -267,3 +267,25 @@ def test_band_pairs_match_class_counts():
     assert (P[:, 2] == 0).sum() == cnt[0] and (P[:, 2] == 1).sum() == cnt[1]
     # class 0/1 = centroid distance below 3 max(h): distance bins 0..4
     assert P[:, 3].max() <= 4
+
+
+@pytest.mark.parametrize("s", [0.3, 0.75])
+def test_surrogate_assembly_rows_mode_equals_full(s):
+    """The rows-only mode (used for the parity of large meshes) gives the
+    same rows as the full surrogate assembly, with a random network so
+    that both certified and fallback pairs occur."""
+    mesh = M.disk_for_cells(300, seed=4)
+    o = O.Orders(6, 6, [1.5, 3.0, 6.0], [4, 3, 2, 2], [4, 3, 2, 2])
+    net = _zero_net()
+    p = S.unpack(net["theta"])
+    p.update({k: v for k, v in S.unpack(G.glorot_params(5)).items() if k.startswith("W")})
+    net["theta"] = S.pack(p)
+    net["st"] = np.full(21, 0.05)
+    net["bound"][1:3, :] = np.inf       # some distance bins stay exact
+    A, dofs, nsur, nfb = S.assemble_surrogate(mesh, s, o, net, 2, 1e-3)
+    assert nsur > 0 and nfb > 0
+    rows = dofs[np.random.default_rng(3).choice(len(dofs), 7, replace=False)]
+    Ar, dr, _, _ = S.assemble_surrogate(mesh, s, o, net, 2, 1e-3, rows=rows)
+    assert np.array_equal(dr, dofs)
+    pos = np.searchsorted(dofs, rows)
+    assert np.abs(Ar - A[pos]).max() <= 1e-14 * np.abs(A).max()
