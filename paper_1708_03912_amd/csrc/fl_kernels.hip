@@ -76,6 +76,40 @@ __device__ __forceinline__ double wave_sum4(const double* v, int lane) {
     return x;
 }
 
+// The same four sums by cross-lane VALU operations instead of LDS
+// permutes: v_permlane32_swap(x, y) exchanges the upper 32 lanes of x with
+// the lower 32 lanes of y, so the sum of its two results holds, in the
+// lower half, x summed over the lane pairs (l, l + 32) and, in the upper
+// half, y summed over them; v_permlane16_swap does the same for the 16-lane
+// rows (rows 0, 2 take x, rows 1, 3 take y); four DPP row rotations (by 8,
+// 4, 2, 1) complete the sums within each row.  Every lane of row m returns
+// the sum of v[m].
+__device__ __forceinline__ double dsum_pl32(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double dsum_pl16(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum4_lanes(const double* v) {
+    const double w0 = dsum_pl32(v[0], v[2]), w1 = dsum_pl32(v[1], v[3]);
+    double x = dsum_pl16(w0, w1);
+    x += dpp_d<0x128>(x);  // row_ror:8
+    x += dpp_d<0x124>(x);  // row_ror:4
+    x += dpp_d<0x122>(x);  // row_ror:2
+    x += dpp_d<0x121>(x);  // row_ror:1
+    return x;
+}
+
 // Sums over the wave of six values at once (halving exchange): after the
 // xor-32 / 16 / 8 steps each lane holds a partial sum of one slot
 // m = 4 b5 + 2 b4 + b3 (b: lane bits), the xor-4 / 2 / 1 steps finish it;
@@ -159,6 +193,45 @@ __device__ __forceinline__ void kpow_tab_batch(const KPowTab& kp, const double (
         pp = fma(pp, t, kp.c1);
         pp = fma(pp, t, 1.0);
         kv[p] = (pp * fr[p].y) * ex[p];
+    }
+}
+
+// The same in two stages, for software pipelining: the first computes the
+// table offsets and issues the reads of a batch, the second (after other
+// work) finishes the powers.
+template <int N>
+struct KPowStage {
+    double m[N];
+    double2 fr[N];
+    double ex[N];
+};
+
+template <int N>
+__device__ __forceinline__ void kpow_tab_issue(const KPowTab& kp, const double (&r2)[N], KPowStage<N>& st) {
+    int hi[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        hi[p] = __double2hiint(r2[p]);
+        st.m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2[p]));
+    }
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        st.fr[p] = ((const double2*)kp.pw)[(hi[p] >> 12) & 255];
+        st.ex[p] = kp.pw[512 + (hi[p] >> 20) - 895];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void kpow_tab_finish(const KPowTab& kp, const KPowStage<N>& st, double (&kv)[N]) {
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        const double t = fma(st.m[p], st.fr[p].x, -1.0);
+        double pp = fma(kp.c5, t, kp.c4);
+        pp = fma(pp, t, kp.c3);
+        pp = fma(pp, t, kp.c2);
+        pp = fma(pp, t, kp.c1);
+        pp = fma(pp, t, 1.0);
+        kv[p] = (pp * st.fr[p].y) * st.ex[p];
     }
 }
 
@@ -1192,7 +1265,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 // vertex), so that their rounding error stays relative to the pair's
 // distance; the sums of a pair are formed in FP32 and added in FP64.
 template <int KO, int MIX, int W>
-__global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void far2_kernel(ElemDev E, FarParams P) {
     constexpr int Q = KO * KO;
     constexpr int LS = MAXV + 1;  // row stride of L; row / column MAXV: vertices without a DOF
     __shared__ __align__(16) double pw[MIX ? 2 : 768];
@@ -1293,7 +1366,7 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
         for (int c = 0; c < 2 * Q; ++c) xp[c] = sX[r][c];
         double f = sMK[r] * ct;
         if constexpr (W) f *= okt ? pair_w(E, I0 + r, Kt) : 0.0;
-        double M[Q][3], H[Q];
+        double M[Q][3];
         if constexpr (MIX) {
             float xf[2 * Q], Mf[Q][3];
 #pragma unroll
@@ -1312,7 +1385,7 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
                     Mf[p][2] += (float)cw[q][2] * kv;
                     h += (float)wq[p] * kv;
                 }
-                H[q] = h;
+                Psi[q] += f * (double)h;
             }
 #pragma unroll
             for (int p = 0; p < Q; ++p)
@@ -1321,17 +1394,27 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
         } else {
 #pragma unroll
         for (int p = 0; p < Q; ++p) M[p][0] = M[p][1] = M[p][2] = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            // the Q evaluations of this point of Kt, their table reads in
-            // flight together
-            double r2[Q], kvs[Q];
+        // the Q evaluations of each point y_q of Kt form a batch; the table
+        // reads of batch q + 1 are issued before the powers of batch q are
+        // finished (two stages in turn), so their latency is covered by
+        // this wave's own arithmetic
+        KPowStage<Q> stg[2];
+        auto issue = [&](int q, KPowStage<Q>& st) {
+            double r2[Q];
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
                 const double dx = xp[2 * p] - yq[2 * q], dy = xp[2 * p + 1] - yq[2 * q + 1];
                 r2[p] = dx * dx + dy * dy;
             }
-            kpow_tab_batch<Q>(kp, r2, kvs);
+            kpow_tab_issue<Q>(kp, r2, st);
+        };
+        issue(0, stg[0]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q + 1 < Q) issue(q + 1, stg[(q + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            double kvs[Q];
+            kpow_tab_finish<Q>(kp, stg[q & 1], kvs);
             double h = 0.0;
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
@@ -1341,18 +1424,17 @@ __global__ __launch_bounds__(256) void far2_kernel(ElemDev E, FarParams P) {
                 M[p][2] += cw[q][2] * kv;
                 h += wq[p] * kv;
             }
-            H[q] = h;
+            Psi[q] += f * h;
+            __builtin_amdgcn_sched_barrier(0);
         }
         }
-#pragma unroll
-        for (int q = 0; q < Q; ++q) Psi[q] += f * H[q];
         // Phi_p of row r: the sum over the lanes of f G_p
         {
             double g[Q];
 #pragma unroll
             for (int p = 0; p < Q; ++p) g[p] = f * ((M[p][0] + M[p][1]) + M[p][2]);
             if constexpr (Q == 4) {
-                const double v = wave_sum4(g, lane);
+                const double v = wave_sum4_lanes(g);
                 if ((lane & 15) == 0) sPhi[r][lane >> 4] = v;
             } else {
                 const double v = wave_sum(g[0]);
