@@ -13,8 +13,9 @@ Chebyshev interpolation of k of order m on the two boxes:
 with nested bases V_parent = sum over sons of V_son T_son,
 T_son[b, a] = L_a^parent(xi_b^son) (the shift coefficients).  The other
 leaf pairs form the near field, kept exactly (here: taken from a dense
-matrix).  The product runs upward (x_hat = V^T x), through the kernel
-blocks, and downward.
+matrix by ``build``, or assembled from the mesh by ``build_direct``).
+The product runs upward (x_hat = V^T x), through the kernel blocks, and
+downward.
 
 Readings (the paper defers the details to the boundary-element
 literature): leaves hold at most `leaf` DOFs (the paper's leaves are single
@@ -90,19 +91,63 @@ def _supports(mesh, dofs):
     return V[dofs], lo[dofs], hi[dofs]
 
 
+def cell_anchors(mesh, dofs, perm):
+    """Anchor DOF (index into ``dofs``) of every cell: among the cell's
+    vertices that carry a DOF, the one first in tree order (``perm``: tree
+    position -> DOF index).  A cell with no DOF vertex takes the anchor of
+    its neighbour across a facet (2D: a common edge, 1D: a common vertex)
+    of smallest cell index that has one; such passes repeat until no cell
+    changes.  -1 where none is found (no DOF in the cell's component)."""
+    d = mesh["dim"]
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    nv = np.asarray(mesh["verts"]).size // d
+    T = len(C)
+    node2dof = np.full(nv, -1, dtype=np.int64)
+    node2dof[np.asarray(dofs)] = np.arange(len(dofs))
+    pos = np.empty(len(dofs), dtype=np.int64)
+    pos[np.asarray(perm)] = np.arange(len(dofs))
+    anchor = np.full(T, -1, dtype=np.int64)
+    for K in range(T):
+        ds = [node2dof[v] for v in C[K] if node2dof[v] >= 0]
+        if ds:
+            anchor[K] = min(ds, key=lambda i: pos[i])
+    if (anchor >= 0).all():
+        return anchor
+    nbr = [[] for _ in range(T)]
+    owners = {}
+    for K in range(T):
+        for a in range(d + 1):
+            face = tuple(sorted(int(C[K, b]) for b in range(d + 1) if b != a))
+            owners.setdefault(face, []).append(K)
+    for ks in owners.values():
+        for K in ks:
+            nbr[K].extend(k for k in ks if k != K)
+    changed = True
+    while changed:
+        changed = False
+        for K in range(T):
+            if anchor[K] >= 0:
+                continue
+            cand = sorted(k for k in nbr[K] if anchor[k] >= 0)
+            if cand:
+                anchor[K] = anchor[cand[0]]
+                changed = True
+    return anchor
+
+
 def build_tree(mesh, dofs, leaf=32):
-    """Cluster tree by recursive median bisection of the DOF coordinates."""
+    """Cluster tree by recursive median bisection of the DOF coordinates;
+    then every cluster's box: the cube with the side of the largest extent
+    of the supports' bounding box, centred on it.  A cell without a DOF
+    vertex widens the support box of its anchor DOF (cell_anchors), so that
+    every cell lies in the box of its anchor's clusters."""
     d = mesh["dim"]
     X, slo, shi = _supports(mesh, dofs)
     perm = np.arange(len(dofs))
     clusters = []
 
     def make(idx, lo, level, parent):
-        blo = slo[idx].min(0)
-        bhi = shi[idx].max(0)
-        side = float((bhi - blo).max())
-        cen = 0.5 * (blo + bhi)
-        c = Cluster(lo, lo + len(idx), cen - 0.5 * side, side, level, parent)
+        c = Cluster(lo, lo + len(idx), np.zeros(d), 0.0, level, parent)
         cid = len(clusters)
         clusters.append(c)
         perm[lo:lo + len(idx)] = idx
@@ -116,7 +161,25 @@ def build_tree(mesh, dofs, leaf=32):
                 c.sons.append(sid)
         return cid
 
-    make(np.arange(len(dofs)), 0, 0, -1)
+    if len(dofs):
+        make(np.arange(len(dofs)), 0, 0, -1)
+    anchor = cell_anchors(mesh, dofs, perm)
+    V = np.asarray(mesh["verts"], dtype=np.float64).reshape(-1, d)
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    nv = len(V)
+    on_dof = np.zeros(nv, dtype=bool)
+    on_dof[np.asarray(dofs, dtype=np.int64)] = True
+    for K in np.nonzero(~on_dof[C].any(1) & (anchor >= 0))[0]:
+        P = V[C[K]]
+        i = anchor[K]
+        slo[i] = np.minimum(slo[i], P.min(0))
+        shi[i] = np.maximum(shi[i], P.max(0))
+    for c in clusters:
+        idx = perm[c.lo:c.hi]
+        blo = slo[idx].min(0)
+        bhi = shi[idx].max(0)
+        c.side = float((bhi - blo).max())
+        c.box_lo = 0.5 * (blo + bhi) - 0.5 * c.side
     return Tree(perm.copy(), clusters, d)
 
 
@@ -268,6 +331,108 @@ def build(mesh, dofs, A, s, m=6, eta=2.0, leaf=32):
     cl = tree.clusters
     An = {(a, b): A[np.ix_(P[cl[a].lo:cl[a].hi], P[cl[b].lo:cl[b].hi])] for a, b in near}
     return HMatrix(tree, far, near, m, s, O.cdn(mesh["dim"], s), Vleaf, T, K, An)
+
+
+def leaf_labels(tree: Tree, near):
+    """Leaf index of every leaf cluster (increasing cluster id), the leaf
+    cluster of every tree position, and the near table (nleaf x nleaf, 0/1)
+    of the leaf pairs that are not admissible."""
+    leaves = tree.leaves()
+    li = {c: i for i, c in enumerate(leaves)}
+    rleaf = np.empty(len(tree.perm), dtype=np.int64)
+    for c in leaves:
+        rleaf[tree.clusters[c].lo:tree.clusters[c].hi] = c
+    tab = np.zeros((len(leaves), len(leaves)), dtype=np.uint8)
+    for a, b in near:
+        tab[li[a], li[b]] = 1
+    return leaves, li, rleaf, tab
+
+
+def self_far(mesh, tree: Tree, far, T_shift, m, sval, cell_leafc):
+    """Far part of the cells' diagonal blocks.  For x in a cell K, the sum
+    over the separated cells Kt whose anchor leaf is not near K's of
+    int_Kt k(x, y) dy is the far field of the density 1 on those cells:
+    with the interpolation of k on every admissible pair of boxes it is
+    sum_a L_a(x) P_a, where the leaf coefficients of the density,
+    int_Kt L_b^leaf over the cells anchored in the leaf ((m+1)-point rule),
+    run upward through the shift coefficients, through the kernel blocks and
+    downward (the matrix-vector product's passes).  Returns (T, d+1, d+1):
+    int_K l_a l_b(x) sum_a L_a(x) P_a dx by the same rule (exact for these
+    polynomials)."""
+    d = tree.dim
+    cl = tree.clusters
+    M = m ** d
+    X, lam, W = _cell_rule(mesh, m + 1)
+    nc = len(cl)
+    xh = [np.zeros(M) for _ in range(nc)]
+    for K in range(len(cell_leafc)):
+        c = cell_leafc[K]
+        if c >= 0:
+            xh[c] = xh[c] + W[K] @ lagrange_box(cl[c], m, d, X[K])
+    for c in sorted(range(nc), key=lambda c: -cl[c].level):
+        if cl[c].sons:
+            xh[c] = sum(T_shift[sn].T @ xh[sn] for sn in cl[c].sons)
+    yh = [np.zeros(M) for _ in range(nc)]
+    for a, b in far:
+        yh[a] = yh[a] + kernel_block(tree, a, b, m, sval) @ xh[b]
+    for c in sorted(range(nc), key=lambda c: cl[c].level):
+        for sn in cl[c].sons:
+            yh[sn] = yh[sn] + T_shift[sn] @ yh[c]
+    S = np.zeros((len(cell_leafc), d + 1, d + 1))
+    for K in range(len(cell_leafc)):
+        c = cell_leafc[K]
+        if c < 0:
+            continue
+        g = lagrange_box(cl[c], m, d, X[K]) @ yh[c]          # (q,)
+        S[K] = np.einsum("q,qa,qb->ab", W[K] * g, lam, lam)
+    return S
+
+
+def build_direct(mesh, dofs, s, orders, m=6, eta=2.0, leaf=32, with_boundary=True):
+    """The cluster approximation assembled from the mesh, without the dense
+    matrix (Sec. 6: the near field from the pair contributions of Sec. 5).
+    Near blocks: every off-diagonal pair block and touching-pair
+    contribution in full; the diagonal-block (self) parts of a separated
+    pair only when the anchor leaves of its two cells are a near pair
+    (masked assembly, oracle.assemble_full with cell labels), the rest of
+    every cell's self part from the far field (self_far).  Far blocks as in
+    build.  Returns the HMatrix."""
+    tree = build_tree(mesh, dofs, leaf)
+    far, near = block_tree(tree, eta)
+    d = mesh["dim"]
+    C = np.asarray(mesh["cells"], dtype=np.int64)
+    nv = np.asarray(mesh["verts"]).size // d
+    n = len(dofs)
+    leaves, li, rleaf, tab = leaf_labels(tree, near)
+    Vleaf = {c: basis_coeffs(mesh, dofs, tree, c, m) for c in leaves}
+    Tsh = {c: transfer(tree, c, m) for c in range(1, len(tree.clusters))}
+    Kb = {(a, b): kernel_block(tree, a, b, m, s) for a, b in far}
+    if n == 0:
+        return HMatrix(tree, far, near, m, s, O.cdn(d, s), Vleaf, Tsh, Kb, {})
+    anchor = cell_anchors(mesh, dofs, tree.perm)
+    pos = np.empty(n, dtype=np.int64)
+    pos[tree.perm] = np.arange(n)
+    cell_leafc = np.where(anchor >= 0, rleaf[pos[np.maximum(anchor, 0)]], -1)
+    lab = np.array([li[c] if c >= 0 else 0 for c in cell_leafc], dtype=np.int32)
+    Afull, _ = O.assemble_full(mesh, s, orders, with_boundary=with_boundary, cell_leaf=lab, leaf_near=tab)
+    node2dof = np.full(nv, -1, dtype=np.int64)
+    node2dof[np.asarray(dofs)] = np.arange(n)
+    A = Afull[np.ix_(dofs, dofs)].copy()
+    Cds = O.cdn(d, s)
+    S = self_far(mesh, tree, far, Tsh, m, s, cell_leafc)
+    for K in range(len(C)):
+        for a in range(d + 1):
+            i = node2dof[C[K, a]]
+            if i < 0:
+                continue
+            for b in range(d + 1):
+                j = node2dof[C[K, b]]
+                if j >= 0:
+                    A[i, j] += Cds * S[K, a, b]
+    P = tree.perm
+    cl = tree.clusters
+    An = {(a, b): A[np.ix_(P[cl[a].lo:cl[a].hi], P[cl[b].lo:cl[b].hi])] for a, b in near}
+    return HMatrix(tree, far, near, m, s, Cds, Vleaf, Tsh, Kb, An)
 
 
 def matvec(H: HMatrix, x):

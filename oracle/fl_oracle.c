@@ -589,6 +589,15 @@ typedef struct {
                               of the two equal cross pairs (S, B^i T) and
                               (T, B^-i S) only one counts, with weight 1 */
     int sym_order;         /* K, the order of B */
+    const int *cell_leaf;  /* NULL, or a label per cell (a leaf of a cluster
+                              tree, 0..nleaf-1) ... */
+    int nleaf;
+    const unsigned char *leaf_near;  /* ... and an nleaf x nleaf table: the
+                              separated pair (K, Kt) adds its diagonal-block
+                              parts (the terms phi_i phi_j(x) and
+                              phi_i phi_j(y) of Sec. 5's pair integrand) only
+                              if leaf_near[label K][label Kt] is nonzero; its
+                              off-diagonal block is always added */
 } orc_opts;
 
 /* Weight of the cell pair (K, Kt) in a symmetry-reduced assembly: pairs of
@@ -704,8 +713,10 @@ void orc_assemble(const orc_rules *R, const orc_opts *o, int dim, int64_t nv, co
                     }
                     orc_far2(R, s, k, X, Y, SK, ST, O);
                 }
-                add_block(A, nv, rowmask, gK, nper, gK, nper, SK, nper, C * wp);
-                add_block(A, nv, rowmask, gT, nper, gT, nper, ST, nper, C * wp);
+                if (!o->cell_leaf || o->leaf_near[(int64_t)o->cell_leaf[K] * o->nleaf + o->cell_leaf[Kt]]) {
+                    add_block(A, nv, rowmask, gK, nper, gK, nper, SK, nper, C * wp);
+                    add_block(A, nv, rowmask, gT, nper, gT, nper, ST, nper, C * wp);
+                }
                 add_block(A, nv, rowmask, gK, nper, gT, nper, O, nper, C * wp);
                 double OT[9];
                 for (int a = 0; a < nper; ++a)

@@ -252,7 +252,8 @@ class _Opts(C.Structure):
                 ("k_far", C.POINTER(C.c_int)), ("k_far_bnd", C.POINTER(C.c_int)),
                 ("with_boundary", C.c_int), ("which", C.c_int), ("far_skip_below", C.c_int),
                 ("cell_w", C.POINTER(C.c_double)), ("cell_pre", C.POINTER(C.c_int)),
-                ("cell_rot", C.POINTER(C.c_int)), ("sym_order", C.c_int)]
+                ("cell_rot", C.POINTER(C.c_int)), ("sym_order", C.c_int),
+                ("cell_leaf", C.POINTER(C.c_int)), ("nleaf", C.c_int), ("leaf_near", C.POINTER(C.c_ubyte))]
 
 
 def boundary_normals(dim, verts, cells, bfacets):
@@ -294,7 +295,8 @@ def dof_nodes(nv, bfacets, s, mode="paper"):
 
 
 def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=True, threads=None,
-                  far_skip_below=0, compact=False, cell_w=None, cell_pre=None, cell_rot=None, sym_order=0):
+                  far_skip_below=0, compact=False, cell_w=None, cell_pre=None, cell_rot=None, sym_order=0,
+                  cell_leaf=None, leaf_near=None):
     """Full-node matrix (nv x nv) of a(phi_i, phi_j) by the element-pair
     decomposition of Sec. 5.  ``rows``: optional vertex indices; only those
     rows are accumulated (others stay zero); with ``compact`` the result is
@@ -305,7 +307,11 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     Sec. 7: 1 on the sector, 0 on its images); with ``cell_pre`` /
     ``cell_rot`` (preimage sector cell and rotation index of every cell) and
     ``sym_order`` only one of each equal couple of cross pairs counts, with
-    weight 1 (see pair_weight in fl_oracle.c).  Returns (A, class_counts)."""
+    weight 1 (see pair_weight in fl_oracle.c).  ``cell_leaf`` (a label per
+    cell, 0..L-1) with ``leaf_near`` (L x L, 0/1): a separated pair adds its
+    diagonal-block parts only where leaf_near[label K, label Kt] is 1 (the
+    near-field self terms of the cluster method); its off-diagonal block
+    always.  Returns (A, class_counts)."""
     orders.check()
     dim = mesh["dim"]
     verts = np.ascontiguousarray(mesh["verts"], dtype=np.float64).reshape(-1)
@@ -327,12 +333,19 @@ def assemble_full(mesh, s, orders: Orders, rows=None, which=7, with_boundary=Tru
     cw = None if cell_w is None else np.ascontiguousarray(cell_w, dtype=np.float64)
     cpre = None if cell_pre is None else np.ascontiguousarray(cell_pre, dtype=np.int32)
     crot = None if cell_rot is None else np.ascontiguousarray(cell_rot, dtype=np.int32)
+    cl = None if cell_leaf is None else np.ascontiguousarray(cell_leaf, dtype=np.int32)
+    ln = None if leaf_near is None else np.ascontiguousarray(leaf_near, dtype=np.uint8)
+    if cl is not None:
+        assert ln is not None and ln.ndim == 2 and ln.shape[0] == ln.shape[1] and len(cl) == nc
+        assert cl.min() >= 0 and cl.max() < ln.shape[0]
     o = _Opts(s, orders.k_touch, orders.k_touch_bnd, len(orders.theta), _dp(th),
               kf.ctypes.data_as(C.POINTER(C.c_int)), kb.ctypes.data_as(C.POINTER(C.c_int)),
               1 if with_boundary else 0, which, int(far_skip_below),
               None if cw is None else _dp(cw),
               None if cpre is None else cpre.ctypes.data_as(C.POINTER(C.c_int)),
-              None if crot is None else crot.ctypes.data_as(C.POINTER(C.c_int)), int(sym_order))
+              None if crot is None else crot.ctypes.data_as(C.POINTER(C.c_int)), int(sym_order),
+              None if cl is None else cl.ctypes.data_as(C.POINTER(C.c_int)), 0 if ln is None else ln.shape[0],
+              None if ln is None else ln.ctypes.data_as(C.POINTER(C.c_ubyte)))
     cnt = np.zeros(16, dtype=np.int64)
     if threads is not None:
         os.environ["OMP_NUM_THREADS"] = str(threads)
