@@ -262,13 +262,40 @@ int fl_solve_mg(fl_handle *h, const double *b, double *u, double rtol, int32_t m
  * fl_assemble / fl_import_matrix discards it.  Synchronises the stream. */
 int fl_cluster_build(fl_handle *h, int32_t m, double eta, int32_t leaf);
 
+/* The cluster approximation of A^s assembled from the mesh alone, without
+ * the dense matrix (Sec. 6: the near field from the pair contributions of
+ * Sec. 5, assembly and memory growing like the near field, not like n^2).
+ * Tree, boxes, admissibility and far blocks as fl_cluster_build.  Near
+ * blocks: every touching pair, boundary term and off-diagonal pair block
+ * of the element pairs whose DOFs meet in a near leaf pair, in full; the
+ * diagonal-block parts of a separated pair (K, Kt) -- the terms
+ * phi_i phi_j(x) int_Kt k and phi_i phi_j(y) int_K k of the pair integrand
+ * -- only when the anchor leaves of K and Kt are a near pair; for the other
+ * cells the same integral is the far field of the density 1 on them,
+ * evaluated through the cluster tree (upward pass of its leaf
+ * coefficients, kernel blocks, downward pass) and integrated over K with
+ * the (m+1)-point rule.  A cell's anchor is its DOF vertex first in tree
+ * order; a cell without one takes the anchor of its facet neighbour of
+ * smallest index that has one and widens that DOF's support box.
+ * opts: as fl_assemble, but precision FL_FP64 and surrogate 0 only
+ * (FL_EINVAL otherwise); no symmetry reduction (FL_EINVAL).  FL_EMESH for a
+ * mesh component without any DOF.  Replaces (and frees) a dense matrix of
+ * an earlier fl_assemble; afterwards fl_cluster_matvec, fl_solve_cluster,
+ * fl_load_vector_one and fl_dofs work, the dense-matrix calls return
+ * FL_ESTATE.  Host *n_out (may be NULL): the number of DOFs.  The phase
+ * times and pair counts of fl_stats cover the near-field tiles.
+ * Synchronises the stream. */
+int fl_cluster_assemble(fl_handle *h, double s, const fl_opts *opts, int32_t m, double eta, int32_t leaf,
+                        int64_t *n_out);
+
 /* y = A_H x with the cluster approximation: upward pass, kernel blocks,
  * downward pass, near blocks.  x, y: device, length n, not aliased.
  * FL_ESTATE without fl_cluster_build.  Asynchronous. */
 int fl_cluster_matvec(fl_handle *h, const double *x, double *y);
 
 /* Jacobi-preconditioned CG (Sec. 5) on A_H u = b (the preconditioner is the
- * diagonal of the assembled matrix).  Arguments and results as fl_solve.
+ * diagonal of the assembled matrix, or of the near blocks after
+ * fl_cluster_assemble: the same entries).  Arguments and results as fl_solve.
  * Synchronises the stream. */
 int fl_solve_cluster(fl_handle *h, const double *b, double *u, double rtol, int32_t maxit,
                      int32_t *iters, double *relres);

@@ -463,37 +463,34 @@ const double* fl_matrix_ptr(const fl_handle* h) { return (h && h->assembled) ? h
 
 }  // extern "C"
 
-namespace {
+namespace fl {
 
-// Result of the s-independent planning of an assembly: device views live in
-// the handle (plan buffer), the offsets of the per-launch lists here.
-struct Plan {
-    int64_t T = 0, nv = 0, n = 0;
-    int dim = 0, nper = 0, nblk = 0;
-    size_t o_ft = 0, o_nt = 0, o_bnd = 0, o_bdofs = 0, o_loc = 0, o_vloc = 0, o_ep = 0, o_vp = 0,
-           o_fac = 0, o_fvid = 0;
-    long long n_tiles = 0, n_far_tiles = 0, n_edge = 0, n_vert = 0;
-    double t_plan_ms = 0.0;
-};
+// DOF map (Sec. 3): all nodes, or the interior ones; with a symmetry
+// reduction the representatives only, images taking their DOF.
+void set_dof_map(fl_handle* h, bool all_nodes) {
+    const bool symm = h->sym_T > 0;
+    h->node2dof.assign(h->nv, -1);
+    h->dof_node.clear();
+    for (int64_t v = 0; v < h->nv; ++v)
+        if ((!symm || h->vfold[v] == v) && (all_nodes || !h->on_boundary[v])) {
+            h->node2dof[v] = (int32_t)h->dof_node.size();
+            h->dof_node.push_back((int32_t)v);
+        }
+    if (symm)  // images take the DOF of their representative
+        for (int64_t v = 0; v < h->nv; ++v) h->node2dof[v] = h->node2dof[h->vfold[v]];
+}
 
-// DOF map (Sec. 3), element order, touching-pair lists, tiles, facet data;
-// everything packed and sent to the device plan buffer.
-int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
+// Element order, touching-pair lists, tiles, facet data after the DOF map;
+// everything packed and sent to the device plan buffer.  sel: the element
+// block pairs to tile (all pairs bi <= bj when null).
+int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const TileSelect* sel) {
     auto t0 = std::chrono::steady_clock::now();
     int rc = FL_OK;
     const int dim = h->dim, nper = dim + 1;
     const int64_t T = h->nc, nv = h->nv;
     const bool symm = h->sym_T > 0;
     const int64_t Tw = symm ? h->sym_T : T;
-    h->node2dof.assign(nv, -1);
-    h->dof_node.clear();
-    for (int64_t v = 0; v < nv; ++v)
-        if ((!symm || h->vfold[v] == v) && (all_nodes || !h->on_boundary[v])) {
-            h->node2dof[v] = (int32_t)h->dof_node.size();
-            h->dof_node.push_back((int32_t)v);
-        }
-    if (symm)  // images take the DOF of their representative
-        for (int64_t v = 0; v < nv; ++v) h->node2dof[v] = h->node2dof[h->vfold[v]];
+    set_dof_map(h, all_nodes);
     const int64_t n = (int64_t)h->dof_node.size();
     P.T = T;
     P.nv = nv;
@@ -679,21 +676,28 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
         if (symm && !h->sym_pre.empty())
             for (int64_t Ki = Tw; Ki < T; ++Ki)
                 bmaxpre[Ki / BE] = std::max(bmaxpre[Ki / BE], (int)h->sym_pre[perm[Ki]]);
-        for (int bi = 0; bi < nblk; ++bi)
-            for (int bj = bi; bj < nblk; ++bj) {
-                if (symm && (int64_t)bi * BE >= Tw) continue;  // image blocks only: weight 0
-                if (symm && !h->sym_pre.empty() && (int64_t)(bi + 1) * BE <= Tw && (int64_t)bj * BE >= Tw &&
-                    bmaxpre[bj] < bi * BE)
-                    continue;
-                bool far = false;
-                if (use_far && bi != bj) {
-                    double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
-                    double dy = std::max(0.0, std::max(by0[bj] - by1[bi], by0[bi] - by1[bj]));
-                    double d2 = dx * dx + dy * dy;
-                    far = d2 > th_last2 * std::max(bh[bi], bh[bj]) * (1.0 + 1e-9);
-                }
-                (far ? far_tiles : tiles).push_back(make_int2(bi, bj));
+        auto classify = [&](int bi, int bj) {
+            if (symm && (int64_t)bi * BE >= Tw) return;  // image blocks only: weight 0
+            if (symm && !h->sym_pre.empty() && (int64_t)(bi + 1) * BE <= Tw && (int64_t)bj * BE >= Tw &&
+                bmaxpre[bj] < bi * BE)
+                return;
+            bool far = false;
+            if (use_far && bi != bj) {
+                double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
+                double dy = std::max(0.0, std::max(by0[bj] - by1[bi], by0[bi] - by1[bj]));
+                double d2 = dx * dx + dy * dy;
+                far = d2 > th_last2 * std::max(bh[bi], bh[bj]) * (1.0 + 1e-9);
             }
+            (far ? far_tiles : tiles).push_back(make_int2(bi, bj));
+        };
+        if (!sel) {
+            for (int bi = 0; bi < nblk; ++bi)
+                for (int bj = bi; bj < nblk; ++bj) classify(bi, bj);
+        } else {
+            std::vector<int2> pairs;
+            (*sel)(perm, dof, nblk, pairs);
+            for (const int2& t : pairs) classify(t.x, t.y);
+        }
     }
     std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
     std::vector<unsigned char> loc(T * 3, 255);
@@ -880,7 +884,8 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
 // a_elems elements zeroed first), optional FP32 copy A32 (same lda).
 // Adds the phase times to *st and fills its pair counts.
 int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double* A, int64_t lda,
-                 long long a_elems, float* A32, fl_stats_t* st) {
+                 long long a_elems, float* A32, fl_stats_t* st, const NearMap* nm,
+                 const std::function<int()>* before_scatter) {
     int rc = FL_OK;
     const int dim = P.dim;
     const int64_t T = P.T, nv = P.nv, n = P.n;
@@ -934,6 +939,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     FP.S = dS;
     FP.cls_count = dcnt;
     FP.mixed = o.precision == FL_MIXED ? 1 : 0;
+    if (nm) FP.nm = *nm;
     if (o.surrogate > 0) {
         if ((rc = fl_sur_params(h, s, o, &FP.sur))) return rc;
         FP.sur.counters = dcnt + 12;
@@ -978,6 +984,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     TP.k = o.k_touch;
     TP.A = A;
     TP.lda = lda;
+    if (nm) TP.nm = *nm;
     if (dim == 2) {
         TP.npairs = P.n_edge;
         TP.pairs = (const int*)dv(o_ep);
@@ -990,8 +997,16 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
-    launch_scatter_self(E, h->d_sc_ptr, h->d_sc_idx, h->d_sc_map, h->d_sc_vloc, h->sc_rows, dim, dS, o.mass_shift,
-                        A, lda, h->stream);
+    if (before_scatter) {
+        if ((rc = (*before_scatter)())) return rc;
+        HIPCHK(hipGetLastError());
+    }
+    if (nm)
+        launch_scatter_self_near(E, h->d_sc_ptr, h->d_sc_idx, h->d_sc_map, h->d_sc_vloc, h->sc_rows, dim, dS,
+                                 o.mass_shift, *nm, h->stream);
+    else
+        launch_scatter_self(E, h->d_sc_ptr, h->d_sc_idx, h->d_sc_map, h->d_sc_vloc, h->sc_rows, dim, dS,
+                            o.mass_shift, A, lda, h->stream);
     HIPCHK(hipGetLastError());
     if (A32) {
         launch_to_f32(A, lda, n, A32, h->stream);
@@ -1051,6 +1066,9 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     return FL_OK;
 }
 
+}  // namespace fl
+
+namespace {
 
 int check_s_opts(fl_handle* h, double s, const fl_opts* opts_in, fl_opts* o) {
     if (!(s > 0.0 && s < 1.0)) return fail(h, FL_EINVAL, "s must lie in (0,1)");
@@ -1068,6 +1086,16 @@ bool fits(fl_handle* h, double bytes) {
 }  // namespace
 
 const fl::RuleTables& fl_base_rules() { return base_rules(); }
+
+void fl_release_dense(fl_handle* h) {
+    reset_assembly(h);
+    if (h->dA) (void)hipFree(h->dA);
+    if (h->dA32) (void)hipFree(h->dA32);
+    h->dA = nullptr;
+    h->dA32 = nullptr;
+    h->A_cap = h->A32_cap = 0;
+    free_solver(h);
+}
 double fl_cdn(int d, double s) { return cdn(d, s); }
 
 namespace fl {
@@ -1114,7 +1142,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
     }
     Plan P;
-    if ((rc = plan_assembly(h, all_nodes, o, P))) return rc;
+    if ((rc = plan_assembly(h, all_nodes, o, P, nullptr))) return rc;
     if ((rc = ensure_dev(h, &h->dA, &h->A_cap, A_bytes))) return rc;
     float* A32 = nullptr;
     if (o.precision == FL_MIXED) {
@@ -1165,7 +1193,7 @@ int fl_assemble_batch(fl_handle* h, const double* s, int ns, const fl_opts* opts
             return fail(h, FL_ENOMEM, "batch of " + std::to_string(ns) + " matrices does not fit in device memory");
     }
     Plan P;
-    if ((rc = plan_assembly(h, all_nodes, o, P))) return rc;
+    if ((rc = plan_assembly(h, all_nodes, o, P, nullptr))) return rc;
     if ((rc = ensure_dev(h, &B.A64, &B.A64_cap, bytes))) return rc;
     fl_stats_t S{};
     for (int j = 0; j < ns; ++j) {

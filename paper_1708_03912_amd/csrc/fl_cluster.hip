@@ -303,9 +303,112 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
     }
 }
 
+// ------------------------------------------- far part of the self terms
+
+// Leaf coefficients of the density 1 on the elements anchored in each leaf:
+// xh[c][a] = sum over those elements K of int_K L_a^c, by the (m+1)-point
+// rule.  One workgroup per leaf.
+__global__ __launch_bounds__(64) void h_density_kernel(HDev H, ElemDev E, const int* __restrict__ lc_ptr,
+                                                       const int* __restrict__ lc_idx) {
+    const int li = blockIdx.x;
+    const int c = H.leaf[li];
+    const int nper = H.dim + 1;
+    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+        double acc = 0.0;
+        for (int e = lc_ptr[li]; e < lc_ptr[li + 1]; ++e) {
+            const int K = lc_idx[e];
+            double P[3][2];
+            for (int b = 0; b < nper; ++b) {
+                P[b][0] = E.x[H.dim * b][K];
+                P[b][1] = H.dim == 2 ? E.x[H.dim * b + 1][K] : 0.0;
+            }
+            const double meas = E.meas[K];
+            for (int q = 0; q < H.nq; ++q) {
+                const double* l = H.qlam + q * nper;
+                double x = 0.0, y = 0.0;
+                for (int b = 0; b < nper; ++b) {
+                    x += l[b] * P[b][0];
+                    y += l[b] * P[b][1];
+                }
+                acc += (meas * H.qw[q]) * lag_box(H, c, a, x, y);
+            }
+        }
+        H.xh[(long long)c * H.M + a] = acc;
+    }
+}
+
+// S[K][ab] += C int_K l_a l_b g, g(x) = sum_a L_a^c(x) yh[c][a] (c: the leaf
+// of K's anchor), by the (m+1)-point rule; one thread per element.  The
+// tensor basis is evaluated as sum_a0 L_a0(x) sum_a1 L_a1(y) yh[a0 m + a1].
+__global__ __launch_bounds__(256) void h_self_far_kernel(HDev H, ElemDev E, int T, const int* __restrict__ aleafc,
+                                                        double C, double* __restrict__ S) {
+    const int K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= T) return;
+    const int c = aleafc[K];
+    if (c < 0) return;
+    const int nper = H.dim + 1, m = H.m;
+    double P[3][2];
+    for (int b = 0; b < nper; ++b) {
+        P[b][0] = E.x[H.dim * b][K];
+        P[b][1] = H.dim == 2 ? E.x[H.dim * b + 1][K] : 0.0;
+    }
+    const double meas = E.meas[K];
+    const double* yh = H.yh + (long long)c * H.M;
+    const double* bx = H.box + 3 * c;
+    double acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < H.nq; ++q) {
+        const double* l = H.qlam + q * nper;
+        double x = 0.0, y = 0.0;
+        for (int b = 0; b < nper; ++b) {
+            x += l[b] * P[b][0];
+            y += l[b] * P[b][1];
+        }
+        const double xi = (x - bx[0]) / bx[2];
+        double g = 0.0;
+        if (H.dim == 1) {
+            for (int a = 0; a < m; ++a) g += lag(H.tnode, m, a, xi) * yh[a];
+        } else {
+            const double eta = (y - bx[1]) / bx[2];
+            double l1[15];
+            for (int b = 0; b < m; ++b) l1[b] = lag(H.tnode, m, b, eta);
+            for (int a = 0; a < m; ++a) {
+                double t = 0.0;
+                for (int b = 0; b < m; ++b) t += l1[b] * yh[a * m + b];
+                g += lag(H.tnode, m, a, xi) * t;
+            }
+        }
+        const double w = meas * H.qw[q] * g;
+        for (int a = 0; a < nper; ++a)
+            for (int b = a; b < nper; ++b) acc[a][b] += w * l[a] * l[b];
+    }
+    // packed symmetric 3 x 3: (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+    const int pk[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (int a = 0; a < nper; ++a)
+        for (int b = a; b < nper; ++b) S[(long long)K * 6 + pk[a][b]] += C * acc[a][b];
+}
+
 inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr, const int* lc_idx,
+                       const int* aleafc, const int* const* up_lists, const int* up_counts, int n_up,
+                       const int* const* down_lists, const int* down_counts, int n_down, double C, double* S,
+                       hipStream_t st) {
+    if (H.n == 0 || T == 0) return;
+    hipLaunchKernelGGL(h_density_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H, E, lc_ptr, lc_idx);
+    const size_t lds = H.M <= 64 ? sizeof(double) * H.M * H.M : 0;
+    for (int l = 0; l < n_up; ++l)
+        if (up_counts[l] > 0)
+            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, H,
+                               (const int4*)up_lists[l]);
+    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
+    for (int l = 0; l < n_down; ++l)
+        if (down_counts[l] > 0)
+            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, H,
+                               (const int4*)down_lists[l]);
+    hipLaunchKernelGGL(h_self_far_kernel, dim3(nb256(T)), dim3(256), 0, st, H, E, T, aleafc, C, S);
+}
 
 void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hipStream_t st) {
     if (H.n > 0) hipLaunchKernelGGL(h_basis_kernel, dim3(nb256(H.n * H.M)), dim3(256), 0, st, H);
@@ -313,7 +416,7 @@ void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hi
         hipLaunchKernelGGL(h_transfer_kernel, dim3(nb256((long long)H.nc * H.M * H.M)), dim3(256), 0, st, H);
     if (H.nfar > 0)
         hipLaunchKernelGGL(h_kblock_kernel, dim3(nb256(H.nfar * H.M * H.M)), dim3(256), 0, st, H, pe);
-    if (H.nnear > 0)
+    if (H.nnear > 0 && A)
         hipLaunchKernelGGL(h_near_kernel, dim3(4, (unsigned)(H.nnear < 32768 ? H.nnear : 32768)), dim3(256), 0, st,
                            H, A, lda);
 }

@@ -1,14 +1,20 @@
 // Host side of the cluster (H-matrix) approximation (include/fraclap.h:
-// fl_cluster_build, fl_cluster_matvec, fl_solve_cluster, fl_cluster_info).
-// Sec. 6: a cluster tree over the DOFs, cluster boxes (cubes containing the
-// supports), admissible pairs eta dist >= max diam approximated by the
-// tensor Chebyshev interpolation of the kernel with nested bases, the rest
-// (leaf pairs) kept exactly.  Readings: leaves of at most `leaf` DOFs (the
-// paper's leaves are single DOFs); a cluster is split at the median of its
-// DOF coordinates along the longest extent (stable order); its box is the
-// cube of the largest extent of the supports' bounding box, centred on it;
-// the near blocks are copied from the assembled dense matrix.  Built
-// without floating-point contraction so that the boxes, and with them the
+// fl_cluster_build, fl_cluster_assemble, fl_cluster_matvec,
+// fl_solve_cluster, fl_cluster_info).  Sec. 6: a cluster tree over the DOFs,
+// cluster boxes (cubes containing the supports), admissible pairs
+// eta dist >= max diam approximated by the tensor Chebyshev interpolation of
+// the kernel with nested bases, the rest (leaf pairs) kept exactly.
+// Readings: leaves of at most `leaf` DOFs (the paper's leaves are single
+// DOFs); a cluster is split at the median of its DOF coordinates along the
+// longest extent (stable order); its box is the cube of the largest extent
+// of the supports' bounding box, centred on it.  The near blocks are copied
+// from the assembled dense matrix (fl_cluster_build) or assembled from the
+// element pairs of the element tiles that hold near pairs
+// (fl_cluster_assemble): off-diagonal parts of every pair, diagonal-block
+// parts of the pairs whose cells' anchor leaves are near, the rest of every
+// cell's diagonal block through the far field (the kernel integrated over
+// the far cells as the far field of the density 1).  Built without
+// floating-point contraction so that the boxes, and with them the
 // admissibility decisions, are those of an independent implementation of
 // the same formulas.
 #include <hip/hip_runtime.h>
@@ -86,36 +92,42 @@ bool admissible(const HCl& a, const HCl& b, double eta, int dim) {
     return eta * dist >= std::max(a.side * sq, b.side * sq);
 }
 
-}  // namespace
+// Tree, boxes and block partition of the current DOF map (host side).
+struct HostTree {
+    int dim = 0, depth = 0;
+    std::vector<HCl> cl;
+    std::vector<int> perm;                        // tree position -> DOF
+    std::vector<std::pair<int, int>> far, near;   // near: by (leaf index, leaf index)
+    std::vector<int> leaf_ids, leaf_of;           // leaf index -> cluster, cluster -> leaf index
+    std::vector<int> anchor;                      // caller cell -> anchor DOF (-1: none)
+};
 
-void fl_hm_free(fl_handle* h) { hm_release(h); }
-
-extern "C" {
-
-int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
-    if (!h) return FL_EINVAL;
-    if (!h->assembled) return cfail(h, FL_ESTATE, "no assembled matrix (fl_assemble)");
-    if (h->sym_T > 0) return cfail(h, FL_EINVAL, "the cluster approximation does not take a symmetry reduction");
-    if (m < 1 || m > 15) return cfail(h, FL_EINVAL, "m must lie in 1..15");
-    if (!(eta > 0.0) || !std::isfinite(eta)) return cfail(h, FL_EINVAL, "eta must be positive and finite");
-    if (leaf < 1 || leaf > 1024) return cfail(h, FL_EINVAL, "leaf must lie in 1..1024");
-    HIPCHK(hipSetDevice(h->device));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    hm_release(h);
+// Cluster tree by median bisection of the DOF coordinates, the anchor DOF
+// of every cell (its DOF vertex first in tree order; a cell without one
+// takes the anchor of its facet neighbour of smallest index that has one,
+// repeated until nothing changes), the boxes (cube of the largest extent of
+// the supports' bounding box, centred on it; a cell without DOF widens its
+// anchor's support box), and the block partition from (root, root).
+void build_host_tree(const fl_handle* h, double eta, int leaf, HostTree& t) {
     const int dim = h->dim, nper = dim + 1;
-    const int64_t n = h->n, nv = h->nv, T = h->nc;
-    int M = 1;
-    for (int j = 0; j < dim; ++j) M *= m;
+    const int64_t n = (int64_t)h->dof_node.size(), nv = h->nv, T = h->nc;
+    t = HostTree{};
+    t.dim = dim;
     // supports: bounding box of the cells around every vertex
     std::vector<double> vlo(nv * 2, INFINITY), vhi(nv * 2, -INFINITY);
-    for (int64_t K = 0; K < T; ++K) {
-        double clo[2] = {INFINITY, INFINITY}, chi[2] = {-INFINITY, -INFINITY};
+    auto cell_box = [&](int64_t K, double* clo, double* chi) {
+        clo[0] = clo[1] = INFINITY;
+        chi[0] = chi[1] = -INFINITY;
         for (int a = 0; a < nper; ++a)
             for (int j = 0; j < dim; ++j) {
                 const double x = h->verts[dim * h->cells[nper * K + a] + j];
                 clo[j] = std::min(clo[j], x);
                 chi[j] = std::max(chi[j], x);
             }
+    };
+    for (int64_t K = 0; K < T; ++K) {
+        double clo[2], chi[2];
+        cell_box(K, clo, chi);
         for (int a = 0; a < nper; ++a) {
             const int v = h->cells[nper * K + a];
             for (int j = 0; j < dim; ++j) {
@@ -124,9 +136,8 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
             }
         }
     }
-    // tree (pre-order ids), perm: tree position -> DOF
-    std::vector<HCl> cl;
-    std::vector<int> perm(n);
+    // tree structure (pre-order ids), perm: tree position -> DOF
+    t.perm.assign(n, 0);
     auto coord = [&](int i, int j) { return h->verts[dim * h->dof_node[i] + j]; };
     std::function<int(std::vector<int>&, int, int, int)> make = [&](std::vector<int>& idx, int lo, int level,
                                                                     int parent) -> int {
@@ -135,25 +146,11 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
         c.hi = lo + (int)idx.size();
         c.level = level;
         c.parent = parent;
-        double blo[2] = {INFINITY, INFINITY}, bhi[2] = {-INFINITY, -INFINITY};
-        for (int i : idx) {
-            const int v = h->dof_node[i];
-            for (int j = 0; j < dim; ++j) {
-                blo[j] = std::min(blo[j], vlo[2 * v + j]);
-                bhi[j] = std::max(bhi[j], vhi[2 * v + j]);
-            }
-        }
-        double side = 0.0;
-        for (int j = 0; j < dim; ++j) side = std::max(side, bhi[j] - blo[j]);
-        c.side = side;
-        c.blo[1] = 0.0;
-        for (int j = 0; j < dim; ++j) {
-            const double cen = 0.5 * (blo[j] + bhi[j]);
-            c.blo[j] = cen - 0.5 * side;
-        }
-        const int cid = (int)cl.size();
-        cl.push_back(c);
-        for (size_t k = 0; k < idx.size(); ++k) perm[lo + k] = idx[k];
+        c.blo[0] = c.blo[1] = 0.0;
+        c.side = 0.0;
+        const int cid = (int)t.cl.size();
+        t.cl.push_back(c);
+        for (size_t k = 0; k < idx.size(); ++k) t.perm[lo + k] = idx[k];
         if ((int)idx.size() > leaf) {
             int ax = 0;
             double best = -1.0;
@@ -173,86 +170,179 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
             const size_t half = order.size() / 2;
             std::vector<int> p1(order.begin(), order.begin() + half), p2(order.begin() + half, order.end());
             const int s1 = make(p1, lo, level + 1, cid);
-            cl[cid].sons.push_back(s1);
+            t.cl[cid].sons.push_back(s1);
             const int s2 = make(p2, lo + (int)half, level + 1, cid);
-            cl[cid].sons.push_back(s2);
+            t.cl[cid].sons.push_back(s2);
         }
         return cid;
     };
-    {
+    if (n > 0) {
         std::vector<int> all(n);
         for (int64_t i = 0; i < n; ++i) all[i] = (int)i;
-        if (n > 0) make(all, 0, 0, -1);
+        make(all, 0, 0, -1);
     }
-    const int nc = (int)cl.size();
+    // anchors
+    std::vector<int> pos(n);
+    for (int64_t r = 0; r < n; ++r) pos[t.perm[r]] = (int)r;
+    t.anchor.assign(T, -1);
+    bool dofless = false;
+    for (int64_t K = 0; K < T; ++K) {
+        int best = -1;
+        for (int a = 0; a < nper; ++a) {
+            const int i = h->node2dof[h->cells[nper * K + a]];
+            if (i >= 0 && (best < 0 || pos[i] < pos[best])) best = i;
+        }
+        t.anchor[K] = best;
+        dofless = dofless || best < 0;
+    }
+    if (dofless && n > 0) {
+        // facet neighbours: cells sharing dim vertices (sorted facet keys)
+        std::vector<std::pair<std::pair<int, int>, int>> fk;
+        fk.reserve(T * nper);
+        for (int64_t K = 0; K < T; ++K)
+            for (int a = 0; a < nper; ++a) {
+                int v0 = -1, v1 = -1;
+                for (int b = 0; b < nper; ++b) {
+                    if (b == a) continue;
+                    const int v = h->cells[nper * K + b];
+                    if (v0 < 0) v0 = v;
+                    else v1 = v;
+                }
+                if (dim == 2 && v0 > v1) std::swap(v0, v1);
+                fk.push_back({{v0, v1}, (int)K});
+            }
+        std::sort(fk.begin(), fk.end());
+        std::vector<std::vector<int>> nbr(T);
+        for (size_t i = 0; i < fk.size();) {
+            size_t j = i;
+            while (j < fk.size() && fk[j].first == fk[i].first) ++j;
+            for (size_t a = i; a < j; ++a)
+                for (size_t b = i; b < j; ++b)
+                    if (a != b) nbr[fk[a].second].push_back(fk[b].second);
+            i = j;
+        }
+        for (auto& v : nbr) std::sort(v.begin(), v.end());
+        bool changed = true;
+        while (changed) {
+            changed = false;
+            for (int64_t K = 0; K < T; ++K) {
+                if (t.anchor[K] >= 0) continue;
+                for (int k : nbr[K])
+                    if (t.anchor[k] >= 0) {
+                        t.anchor[K] = t.anchor[k];
+                        changed = true;
+                        break;
+                    }
+            }
+        }
+        for (int64_t K = 0; K < T; ++K) {
+            bool has = false;
+            for (int a = 0; a < nper; ++a) has = has || h->node2dof[h->cells[nper * K + a]] >= 0;
+            if (has || t.anchor[K] < 0) continue;
+            double clo[2], chi[2];
+            cell_box(K, clo, chi);
+            const int v = h->dof_node[t.anchor[K]];
+            for (int j = 0; j < dim; ++j) {
+                vlo[2 * v + j] = std::min(vlo[2 * v + j], clo[j]);
+                vhi[2 * v + j] = std::max(vhi[2 * v + j], chi[j]);
+            }
+        }
+    }
+    // boxes
+    for (HCl& c : t.cl) {
+        double blo[2] = {INFINITY, INFINITY}, bhi[2] = {-INFINITY, -INFINITY};
+        for (int r = c.lo; r < c.hi; ++r) {
+            const int v = h->dof_node[t.perm[r]];
+            for (int j = 0; j < dim; ++j) {
+                blo[j] = std::min(blo[j], vlo[2 * v + j]);
+                bhi[j] = std::max(bhi[j], vhi[2 * v + j]);
+            }
+        }
+        double side = 0.0;
+        for (int j = 0; j < dim; ++j) side = std::max(side, bhi[j] - blo[j]);
+        c.side = side;
+        c.blo[1] = 0.0;
+        for (int j = 0; j < dim; ++j) {
+            const double cen = 0.5 * (blo[j] + bhi[j]);
+            c.blo[j] = cen - 0.5 * side;
+        }
+        t.depth = std::max(t.depth, c.level);
+    }
     // admissible pairs and near leaf pairs (recursion from (root, root))
-    std::vector<std::pair<int, int>> far, near;
-    std::function<void(int, int)> rec = [&](int s, int t) {
-        if (admissible(cl[s], cl[t], eta, dim)) {
-            far.push_back({s, t});
+    std::function<void(int, int)> rec = [&](int s, int u) {
+        if (admissible(t.cl[s], t.cl[u], eta, dim)) {
+            t.far.push_back({s, u});
             return;
         }
-        const bool ls = cl[s].sons.empty(), lt = cl[t].sons.empty();
+        const bool ls = t.cl[s].sons.empty(), lt = t.cl[u].sons.empty();
         if (ls && lt) {
-            near.push_back({s, t});
+            t.near.push_back({s, u});
         } else if (ls) {
-            for (int tt : cl[t].sons) rec(s, tt);
+            for (int tt : t.cl[u].sons) rec(s, tt);
         } else if (lt) {
-            for (int ss : cl[s].sons) rec(ss, t);
+            for (int ss : t.cl[s].sons) rec(ss, u);
         } else {
-            for (int ss : cl[s].sons)
-                for (int tt : cl[t].sons) rec(ss, tt);
+            for (int ss : t.cl[s].sons)
+                for (int tt : t.cl[u].sons) rec(ss, tt);
         }
     };
+    const int nc = (int)t.cl.size();
     if (nc > 0) rec(0, 0);
-    std::stable_sort(far.begin(), far.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
-        return a.first < b.first;
-    });
-    std::vector<int> leaf_ids, leaf_of(nc, -1);
+    std::stable_sort(t.far.begin(), t.far.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+    t.leaf_of.assign(nc, -1);
     for (int c = 0; c < nc; ++c)
-        if (cl[c].sons.empty()) {
-            leaf_of[c] = (int)leaf_ids.size();
-            leaf_ids.push_back(c);
+        if (t.cl[c].sons.empty()) {
+            t.leaf_of[c] = (int)t.leaf_ids.size();
+            t.leaf_ids.push_back(c);
         }
-    std::stable_sort(near.begin(), near.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
-        return leaf_of[a.first] < leaf_of[b.first];
+    std::stable_sort(t.near.begin(), t.near.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        const int la = t.leaf_of[a.first], lb = t.leaf_of[b.first];
+        return la != lb ? la < lb : t.leaf_of[a.second] < t.leaf_of[b.second];
     });
-    // flattened host arrays
+}
+
+// Device copy of the tree and block lists, the workspaces and the near
+// blocks (An, allocated, not filled).  Fills H and the handle's lists.
+int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
+    const int dim = t.dim, nper = dim + 1;
+    const int64_t n = h->n, nv = h->nv, T = h->nc;
+    int M = 1;
+    for (int j = 0; j < dim; ++j) M *= m;
+    const int nc = (int)t.cl.size();
     std::vector<int> clo(nc), chi(nc), cpar(nc), sptr(nc + 1, 0), sidx, node(n), rleaf(n);
     std::vector<double> box(3 * (size_t)nc);
-    int depth = 0;
     for (int c = 0; c < nc; ++c) {
-        clo[c] = cl[c].lo;
-        chi[c] = cl[c].hi;
-        cpar[c] = cl[c].parent;
-        box[3 * c] = cl[c].blo[0];
-        box[3 * c + 1] = cl[c].blo[1];
-        box[3 * c + 2] = cl[c].side;
-        for (int sn : cl[c].sons) sidx.push_back(sn);
+        clo[c] = t.cl[c].lo;
+        chi[c] = t.cl[c].hi;
+        cpar[c] = t.cl[c].parent;
+        box[3 * c] = t.cl[c].blo[0];
+        box[3 * c + 1] = t.cl[c].blo[1];
+        box[3 * c + 2] = t.cl[c].side;
+        for (int sn : t.cl[c].sons) sidx.push_back(sn);
         sptr[c + 1] = (int)sidx.size();
-        depth = std::max(depth, cl[c].level);
-        if (cl[c].sons.empty())
-            for (int r = cl[c].lo; r < cl[c].hi; ++r) rleaf[r] = c;
+        if (t.cl[c].sons.empty())
+            for (int r = t.cl[c].lo; r < t.cl[c].hi; ++r) rleaf[r] = c;
     }
-    for (int64_t r = 0; r < n; ++r) node[r] = h->dof_node[perm[r]];
+    for (int64_t r = 0; r < n; ++r) node[r] = h->dof_node[t.perm[r]];
     std::vector<long long> fptr(nc + 1, 0);
     std::vector<int> fsrc, fdst;
-    for (auto& p : far) {
+    for (auto& p : t.far) {
         fsrc.push_back(p.first);
         fdst.push_back(p.second);
         fptr[p.first + 1]++;
     }
     for (int c = 0; c < nc; ++c) fptr[c + 1] += fptr[c];
-    const int nleaf = (int)leaf_ids.size();
+    const int nleaf = (int)t.leaf_ids.size();
     std::vector<int> lnptr(nleaf + 1, 0), nsrc, ndst;
     std::vector<long long> noff;
     long long near_entries = 0;
-    for (auto& p : near) {
+    for (auto& p : t.near) {
         nsrc.push_back(p.first);
         ndst.push_back(p.second);
         noff.push_back(near_entries);
         near_entries += (long long)(chi[p.first] - clo[p.first]) * (chi[p.second] - clo[p.second]);
-        lnptr[leaf_of[p.first] + 1]++;
+        lnptr[t.leaf_of[p.first] + 1]++;
     }
     for (int l = 0; l < nleaf; ++l) lnptr[l + 1] += lnptr[l];
     // Chebyshev points of the first kind on [0, 1] (increasing) and the
@@ -264,9 +354,9 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
     std::vector<double> qlam, qw;
     if (dim == 1) {
         for (int i = 0; i < kq; ++i) {
-            const double t = R.gl_x[gl_off(kq) + i];
-            qlam.push_back(1.0 - t);
-            qlam.push_back(t);
+            const double x = R.gl_x[gl_off(kq) + i];
+            qlam.push_back(1.0 - x);
+            qlam.push_back(x);
             qw.push_back(R.gl_w[gl_off(kq) + i]);
         }
     } else {
@@ -293,26 +383,26 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
     // deepest level first) {c, son 0, son 1, 0}, downward (every cluster
     // below the root, shallowest first) {c, parent, 0, 0}.  The bisection
     // gives every internal cluster exactly two sons.
+    const int depth = t.depth;
     std::vector<std::vector<int>> up(depth + 1), down(depth + 1);
     for (int c = 0; c < nc; ++c) {
-        if (!cl[c].sons.empty()) {
-            if (cl[c].sons.size() != 2) return cfail(h, FL_EINVAL, "cluster tree: internal cluster without two sons");
-            for (int v : {c, cl[c].sons[0], cl[c].sons[1], 0}) up[cl[c].level].push_back(v);
+        if (!t.cl[c].sons.empty()) {
+            if (t.cl[c].sons.size() != 2) return cfail(h, FL_EINVAL, "cluster tree: internal cluster without two sons");
+            for (int v : {c, t.cl[c].sons[0], t.cl[c].sons[1], 0}) up[t.cl[c].level].push_back(v);
         }
         if (c > 0)
-            for (int v : {c, cpar[c], 0, 0}) down[cl[c].level].push_back(v);
+            for (int v : {c, cpar[c], 0, 0}) down[t.cl[c].level].push_back(v);
     }
-    // device
     fl_hm& Hm = h->hm;
-    HDev H{};
+    H = HDev{};
     H.dim = dim;
     H.m = m;
     H.M = M;
     H.n = n;
     H.nc = nc;
     H.nleaf = nleaf;
-    H.nfar = (long long)far.size();
-    H.nnear = (long long)near.size();
+    H.nfar = (long long)t.far.size();
+    H.nnear = (long long)t.near.size();
     H.nq = (int)qw.size();
     int rc;
     const int *p_clo, *p_chi, *p_cpar, *p_sptr, *p_sidx, *p_perm, *p_node, *p_rleaf, *p_leaf, *p_cells, *p_vptr,
@@ -336,10 +426,10 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
     UP(p_cpar, cpar);
     UP(p_sptr, sptr);
     UP(p_sidx, sidx);
-    UP(p_perm, perm);
+    UP(p_perm, t.perm);
     UP(p_node, node);
     UP(p_rleaf, rleaf);
-    UP(p_leaf, leaf_ids);
+    UP(p_leaf, t.leaf_ids);
     UP(p_cells, cells);
     UP(p_vptr, vptr);
     UP(p_vidx, vidx);
@@ -410,18 +500,201 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
         Hm.down_lists.push_back(q);
         Hm.down_counts.push_back((int)down[l].size() / 4);
     }
-    launch_h_setup(H, h->dA, h->lda, -0.5 * (dim + 2.0 * h->s), h->stream);
-    launch_h_diag(h->dA, h->lda, n, Hm.d, h->stream);
+    Hm.m = m;
+    Hm.depth = depth;
+    Hm.near_entries = near_entries;
+    return FL_OK;
+}
+
+int check_cluster_args(fl_handle* h, int32_t m, double eta, int32_t leaf) {
+    if (h->sym_T > 0) return cfail(h, FL_EINVAL, "the cluster approximation does not take a symmetry reduction");
+    if (m < 1 || m > 15) return cfail(h, FL_EINVAL, "m must lie in 1..15");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return cfail(h, FL_EINVAL, "eta must be positive and finite");
+    if (leaf < 1 || leaf > 1024) return cfail(h, FL_EINVAL, "leaf must lie in 1..1024");
+    return FL_OK;
+}
+
+}  // namespace
+
+void fl_hm_free(fl_handle* h) { hm_release(h); }
+
+extern "C" {
+
+int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
+    if (!h) return FL_EINVAL;
+    if (!h->assembled) return cfail(h, FL_ESTATE, "no assembled matrix (fl_assemble)");
+    int rc = check_cluster_args(h, m, eta, leaf);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hm_release(h);
+    HostTree t;
+    build_host_tree(h, eta, leaf, t);
+    HDev H{};
+    if ((rc = upload_tree(h, t, m, H))) return rc;
+    fl_hm& Hm = h->hm;
+    launch_h_setup(H, h->dA, h->lda, -0.5 * (h->dim + 2.0 * h->s), h->stream);
+    launch_h_diag(h->dA, h->lda, h->n, Hm.d, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
     Hm.H = H;
-    Hm.m = m;
     Hm.leaf = leaf;
     Hm.eta = eta;
-    Hm.depth = depth;
-    Hm.C = fl_cdn(dim, h->s);
-    Hm.near_entries = near_entries;
+    Hm.C = fl_cdn(h->dim, h->s);
+    Hm.direct = false;
     Hm.ready = true;
+    return FL_OK;
+}
+
+int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t m, double eta, int32_t leaf,
+                        int64_t* n_out) {
+    if (!h) return FL_EINVAL;
+    if (h->dim == 0) return cfail(h, FL_ESTATE, "fl_set_mesh must be called first");
+    if (!(s > 0.0 && s < 1.0)) return cfail(h, FL_EINVAL, "s must lie in (0,1)");
+    fl_opts o;
+    if (opts_in) o = *opts_in;
+    else fl_default_opts(&o);
+    int rc = check_cluster_args(h, m, eta, leaf);
+    if (rc) return rc;
+    if (o.precision != FL_FP64) return cfail(h, FL_EINVAL, "the cluster near field is assembled in FP64");
+    if (o.surrogate != 0) return cfail(h, FL_EINVAL, "the cluster near field takes the exact rules (surrogate = 0)");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
+    hm_release(h);
+    // the dense matrix of an earlier assembly is released: this path exists
+    // for problems whose dense matrix does not fit
+    fl_release_dense(h);
+    const bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s < 0.5);
+    set_dof_map(h, all_nodes);
+    const int64_t n = (int64_t)h->dof_node.size(), T = h->nc;
+    const int nper = h->dim + 1;
+    HostTree t;
+    build_host_tree(h, eta, leaf, t);
+    for (int64_t K = 0; K < T && n > 0; ++K)
+        if (t.anchor[K] < 0)
+            return cfail(h, FL_EMESH, "a mesh component without DOF (cell " + std::to_string(K) + ")");
+    const int nleaf = (int)t.leaf_ids.size();
+    // DOF -> leaf index and position in the leaf
+    std::vector<int> dleaf(n), drow(n), lsize(nleaf), lpart;
+    for (int l = 0; l < nleaf; ++l) {
+        const HCl& c = t.cl[t.leaf_ids[l]];
+        lsize[l] = c.hi - c.lo;
+        for (int r = c.lo; r < c.hi; ++r) {
+            dleaf[t.perm[r]] = l;
+            drow[t.perm[r]] = r - c.lo;
+        }
+    }
+    std::vector<int> aleaf_cell(T, 0);
+    for (int64_t K = 0; K < T; ++K) aleaf_cell[K] = n > 0 ? dleaf[t.anchor[K]] : 0;
+    std::vector<std::vector<int>> partners(nleaf);
+    for (auto& p : t.near) {
+        partners[t.leaf_of[p.first]].push_back(t.leaf_of[p.second]);
+        lpart.push_back(t.leaf_of[p.second]);
+    }
+    // element tiles: the block pairs holding a DOF pair or an anchor pair
+    // of near leaves; also the internal order's anchor leaves and the
+    // leaf -> anchored elements lists
+    std::vector<int> aleaf_int(T), lc_ptr(nleaf + 1, 0), lc_idx(T), aleafc(T);
+    TileSelect sel = [&](const std::vector<int32_t>& perm, const std::vector<std::vector<int>>& dof, int nblk,
+                         std::vector<int2>& pairs) {
+        std::vector<std::vector<int>> bl(nleaf);   // leaf -> blocks (increasing)
+        std::vector<int> seen(nleaf, -1);
+        for (int b = 0; b < nblk; ++b) {
+            const int64_t k0 = (int64_t)b * BE, k1 = std::min<int64_t>(T, (int64_t)(b + 1) * BE);
+            auto note = [&](int l) {
+                if (seen[l] != b) {
+                    seen[l] = b;
+                    bl[l].push_back(b);
+                }
+            };
+            for (int64_t Ki = k0; Ki < k1; ++Ki) {
+                note(aleaf_cell[perm[Ki]]);
+                for (int a = 0; a < nper; ++a)
+                    if (dof[a][Ki] >= 0) note(dleaf[dof[a][Ki]]);
+            }
+        }
+        std::vector<uint64_t> keys;
+        for (int l = 0; l < nleaf; ++l)
+            for (int u : partners[l]) {
+                if (u < l) continue;
+                for (int b1 : bl[l])
+                    for (int b2 : bl[u]) {
+                        const uint64_t lo = (uint64_t)std::min(b1, b2), hi = (uint64_t)std::max(b1, b2);
+                        keys.push_back((lo << 32) | hi);
+                    }
+            }
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        pairs.resize(keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) pairs[i] = make_int2((int)(keys[i] >> 32), (int)(keys[i] & 0xffffffffu));
+        for (int64_t Ki = 0; Ki < T; ++Ki) aleaf_int[Ki] = aleaf_cell[perm[Ki]];
+        for (int64_t Ki = 0; Ki < T; ++Ki) lc_ptr[aleaf_int[Ki] + 1]++;
+        for (int l = 0; l < nleaf; ++l) lc_ptr[l + 1] += lc_ptr[l];
+        std::vector<int> fill(lc_ptr.begin(), lc_ptr.end() - 1);
+        for (int64_t Ki = 0; Ki < T; ++Ki) lc_idx[fill[aleaf_int[Ki]]++] = (int)Ki;
+        for (int64_t Ki = 0; Ki < T; ++Ki) aleafc[Ki] = t.leaf_ids.empty() ? -1 : t.leaf_ids[aleaf_int[Ki]];
+    };
+    Plan P;
+    h->n = n;
+    if (n > 0 && (rc = plan_assembly(h, all_nodes, o, P, &sel))) return rc;
+    HDev H{};
+    if ((rc = upload_tree(h, t, m, H))) return rc;
+    fl_hm& Hm = h->hm;
+    const double C = fl_cdn(h->dim, s);
+    fl_stats_t st{};
+    if (n > 0) {
+        NearMap nm{};
+        int *p_dleaf = nullptr, *p_drow = nullptr, *p_lsize = nullptr, *p_lpart = nullptr, *p_aleaf = nullptr,
+            *p_lcp = nullptr, *p_lci = nullptr, *p_aleafc = nullptr;
+        if ((rc = hm_upload(h, &p_dleaf, dleaf)) || (rc = hm_upload(h, &p_drow, drow)) ||
+            (rc = hm_upload(h, &p_lsize, lsize)) || (rc = hm_upload(h, &p_lpart, lpart)) ||
+            (rc = hm_upload(h, &p_aleaf, aleaf_int)) || (rc = hm_upload(h, &p_lcp, lc_ptr)) ||
+            (rc = hm_upload(h, &p_lci, lc_idx)) || (rc = hm_upload(h, &p_aleafc, aleafc))) {
+            hm_release(h);
+            return rc;
+        }
+        nm.An = H.An;
+        nm.dleaf = p_dleaf;
+        nm.drow = p_drow;
+        nm.lsize = p_lsize;
+        nm.lptr = H.lnptr;
+        nm.lpart = p_lpart;
+        nm.lpoff = H.noff;
+        nm.aleaf = p_aleaf;
+        launch_zero(H.An, Hm.near_entries, h->stream);
+        // far field first: the self terms' far part runs through it
+        const double pe = -0.5 * (h->dim + 2.0 * s);
+        launch_h_setup(H, nullptr, 0, pe, h->stream);
+        HIPCHK(hipGetLastError());
+        std::function<int()> far_self = [&]() -> int {
+            launch_h_self_far(H, h->E, (int)T, p_lcp, p_lci, p_aleafc, Hm.up_lists.data(), Hm.up_counts.data(),
+                              (int)Hm.up_lists.size(), Hm.down_lists.data(), Hm.down_counts.data(),
+                              (int)Hm.down_lists.size(), C, h->dS, h->stream);
+            return FL_OK;
+        };
+        if ((rc = run_assembly(h, P, s, o, nullptr, 0, 0, nullptr, &st, &nm, &far_self))) {
+            hm_release(h);
+            return rc;
+        }
+        launch_near_diag(nm, n, Hm.d, h->stream);
+        HIPCHK(hipGetLastError());
+        Hm.nm = nm;
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->st = st;
+    h->s = s;
+    h->opts = o;
+    h->n = n;
+    h->lda = 0;
+    h->assembled = false;
+    h->planned = n > 0;
+    Hm.H = H;
+    Hm.leaf = leaf;
+    Hm.eta = eta;
+    Hm.C = C;
+    Hm.direct = true;
+    Hm.ready = true;
+    if (n_out) *n_out = n;
     return FL_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -113,9 +114,12 @@ struct fl_sf {
     std::vector<void*> clbufs;
 };
 
-// Cluster approximation of the assembled matrix (fl_cluster_build).
+// Cluster approximation: of the assembled matrix (fl_cluster_build), or
+// assembled directly from the mesh (fl_cluster_assemble, direct = true).
 struct fl_hm {
     bool ready = false;
+    bool direct = false;
+    fl::NearMap nm{};               // direct: the near blocks' map
     int m = 0, leaf = 0, depth = 0;
     double eta = 0.0, C = 0.0;
     fl::HDev H{};
@@ -203,6 +207,38 @@ struct fl_handle {
     fl_sf sf;
     fl_hm hm;
 };
+
+namespace fl {
+// Result of the s-independent planning of an assembly: device views live in
+// the handle (plan buffer), the offsets of the per-launch lists here.
+struct Plan {
+    int64_t T = 0, nv = 0, n = 0;
+    int dim = 0, nper = 0, nblk = 0;
+    size_t o_ft = 0, o_nt = 0, o_bnd = 0, o_bdofs = 0, o_loc = 0, o_vloc = 0, o_ep = 0, o_vp = 0,
+           o_fac = 0, o_fvid = 0;
+    long long n_tiles = 0, n_far_tiles = 0, n_edge = 0, n_vert = 0;
+    double t_plan_ms = 0.0;
+};
+// Chooses the element-block pairs (bi <= bj) to tile, from the internal
+// element order (perm: internal -> caller index) and the DOF of every
+// internal element's vertices (dof[a][Ki], -1: none).
+using TileSelect = std::function<void(const std::vector<int32_t>& perm, const std::vector<std::vector<int>>& dof,
+                                      int nblk, std::vector<int2>& pairs)>;
+// Planning and one assembly run (defined with the assembly driver).  With nm
+// the pair kernels write the cluster near field instead of A (A may be
+// null), and before_scatter runs just before the diagonal blocks are
+// scattered (on the handle's stream).
+int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const TileSelect* sel);
+int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double* A, int64_t lda,
+                 long long a_elems, float* A32, fl_stats_t* st, const NearMap* nm = nullptr,
+                 const std::function<int()>* before_scatter = nullptr);
+// DOF map for the current mesh (Sec. 3: all nodes, or the interior ones)
+void set_dof_map(fl_handle* h, bool all_nodes);
+}  // namespace fl
+
+// Drop the dense matrix of the last assembly (and everything built on it)
+// and free its device memory.
+void fl_release_dense(fl_handle* h);
 
 // Quadrature tables independent of s (defined with the assembly driver).
 const fl::RuleTables& fl_base_rules();

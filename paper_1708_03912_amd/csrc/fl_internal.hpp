@@ -67,6 +67,41 @@ struct SurParams {
     unsigned long long* counters;  // [0] surrogate pairs, [1] fallback pairs, [4 + c] fallback of class c
 };
 
+// Where the pair kernels put their output when the cluster method's near
+// field is assembled instead of the dense matrix: the near blocks (leaf
+// pairs that are not admissible), each stored column by column, found from
+// the two DOFs' leaves by a binary search of the first leaf's partners
+// (increasing leaf index).  An == nullptr: dense mode.
+struct NearMap {
+    double* An = nullptr;
+    const int* dleaf = nullptr;     // DOF -> leaf index
+    const int* drow = nullptr;      // DOF -> position in its leaf
+    const int* lsize = nullptr;     // leaf -> DOFs
+    const int* lptr = nullptr;      // leaf -> first partner (nleaf + 1)
+    const int* lpart = nullptr;     // partner leaf indices
+    const long long* lpoff = nullptr;  // offset of each (leaf, partner) block in An
+    const int* aleaf = nullptr;     // internal element -> leaf index of its anchor DOF
+};
+
+// index of the block (leaf a, leaf b) among a's partners, -1 if not near
+__device__ __forceinline__ int nm_block(const NearMap& M, int a, int b) {
+    int lo = M.lptr[a], hi = M.lptr[a + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (M.lpart[mid] < b) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < M.lptr[a + 1] && M.lpart[lo] == b) ? lo : -1;
+}
+
+// entry (i, j) of the near field, nullptr when (i, j) lies in the far field
+__device__ __forceinline__ double* nm_slot(const NearMap& M, int i, int j) {
+    const int a = M.dleaf[i];
+    const int p = nm_block(M, a, M.dleaf[j]);
+    if (p < 0) return nullptr;
+    return M.An + M.lpoff[p] + M.drow[i] + (long long)M.drow[j] * M.lsize[a];
+}
+
 struct FarParams {
     int dim;
     int T;
@@ -88,6 +123,7 @@ struct FarParams {
     unsigned long long* cls_count;  // ncls+1 counters
     int mixed;              // 1: separated pairs evaluated in FP32
     SurParams sur;          // learned surrogate for the closest classes
+    NearMap nm;             // cluster near field (nm.An set): output map, self-part mask
 };
 
 struct TouchParams {
@@ -98,6 +134,7 @@ struct TouchParams {
     const int* pairs;       // npairs x 2 element ids (K < Kt)
     double* A;
     long long lda;
+    NearMap nm;             // cluster near field (nm.An set): output map
 };
 
 struct BndParams {
@@ -131,6 +168,12 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
                          const double* S, double mass, double* A, long long lda, hipStream_t st);
 // y = M x, M the P1 mass matrix on the DOFs
+// the same into the cluster near field; mass as above
+void launch_scatter_self_near(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx, const int* node2dof,
+                              const unsigned char* vloc, int nv, int dim, const double* S, double mass,
+                              const NearMap& nm, hipStream_t st);
+// d[i] = near-field entry (i, i)
+void launch_near_diag(const NearMap& nm, long long n, double* d, hipStream_t st);
 void launch_mass_matvec(const ElemDev& E, const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
                         const unsigned char* vloc, int dim, long long n, const double* x, double* y,
                         hipStream_t st);
@@ -277,6 +320,15 @@ struct HDev {
     double* yh;
 };
 void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hipStream_t st);
+// Far part of the elements' diagonal blocks (cluster method): the density 1
+// on the elements anchored in each leaf, its leaf coefficients, the upward,
+// far and downward passes, and S[K] += C int_K l_a l_b sum_a L_a P_a.
+// lc_ptr / lc_idx: leaf index -> internal elements anchored there;
+// aleafc: internal element -> leaf cluster id.
+void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr, const int* lc_idx,
+                       const int* aleafc, const int* const* up_lists, const int* up_counts, int n_up,
+                       const int* const* down_lists, const int* down_counts, int n_down, double C, double* S,
+                       hipStream_t st);
 void launch_h_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
 void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_counts, int n_up,
                      const int* const* down_lists, const int* down_counts, int n_down, double C, const double* x,

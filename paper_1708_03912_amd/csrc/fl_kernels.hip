@@ -660,12 +660,42 @@ __device__ __forceinline__ double dist2_nc(double x0, double y0, double x1, doub
     return d2;
 }
 
+// Cluster near field: bit l % 16 of nb[r][l / 16] is set when the anchor
+// leaves of the row element I0 + r and the column element J0 + l are a near
+// pair (the pair's diagonal-block parts are then assembled here, otherwise
+// they come from the far field).  256 threads: row tid / 4, 16 columns each.
+__device__ void nm_tile_bits(const NearMap& M, int I0, int J0, int T, unsigned short (*nb)[4], int tid) {
+    const int r = tid >> 2, q = tid & 3;
+    unsigned bits = 0;
+    const int K = I0 + r;
+    if (K < T) {
+        const int a = M.aleaf[K];
+        for (int u = 0; u < 16; ++u) {
+            const int Kt = J0 + q * 16 + u;
+            if (Kt < T && nm_block(M, a, M.aleaf[Kt]) >= 0) bits |= 1u << u;
+        }
+    }
+    nb[r][q] = (unsigned short)bits;
+}
+
+__device__ __forceinline__ bool nm_bit(const unsigned short (*nb)[4], int r, int l) {
+    return (nb[r][l >> 4] >> (l & 15)) & 1;
+}
+
+// add v to near-field entry (i, j) if (i, j) lies in the near field
+__device__ __forceinline__ void nm_add(const NearMap& M, int i, int j, double v) {
+    double* q = nm_slot(M, i, j);
+    if (q) atomicAdd(q, v);
+}
+
 // One workgroup per tile (bi <= bj) of BE x BE element pairs.  Wave w takes
 // rows K = I0 + w, w+4, ...; lane l takes Kt = J0 + l.  Off-diagonal blocks
 // are accumulated in LDS over the block's local DOF numbering and flushed
 // to A (and its mirror) with one global atomic per touched entry; the
-// diagonal-block increments go to per-element accumulators S.
-template <int DIM, int FARK, int MIX>
+// diagonal-block increments go to per-element accumulators S.  CL = 1: the
+// cluster near field (P.nm): diagonal-block parts only for pairs of near
+// anchor leaves, off-diagonal entries only in near blocks.
+template <int DIM, int FARK, int MIX, int CL>
 __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
@@ -679,6 +709,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     __shared__ unsigned long long ccount[FL_MAX_CLASSES + 1];
     __shared__ double sI[10][BE];  // row elements: coordinates, centroid, h^2, |K|
     __shared__ int sV[3][BE];      // row elements: vertex ids
+    __shared__ unsigned short nbits[CL ? BE : 1][4];
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -721,6 +752,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
             sV[a][r] = (K < T && a < NV) ? E.vid[a][K] : -2;
         }
     }
+    if constexpr (CL) nm_tile_bits(P.nm, I0, J0, T, nbits, tid);
     __syncthreads();
 
     const int Kt = J0 + lane;
@@ -805,10 +837,11 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
             }
         }
         const double f = valid ? P.C * mk * mt * pair_w(E, K, Kt) : 0.0;
+        const double fs = (CL && !nm_bit(nbits, r, lane)) ? 0.0 : f;
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            SK[m] *= f;
-            STacc[m] += ST[m] * f;
+            SK[m] *= fs;
+            STacc[m] += ST[m] * fs;
         }
         // diagonal block of K: reduce over the wave (this wave owns row r);
         // the six sums end in lanes 0, 8, ..., 40
@@ -841,8 +874,13 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                         int gb = E.dof[b][Kt];
                         if (gb < 0) continue;
                         double v = -f * O[3 * a + b];
-                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        if constexpr (CL) {
+                            nm_add(P.nm, ga, gb, v);
+                            nm_add(P.nm, gb, ga, v);
+                        } else {
+                            atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                            atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        }
                     }
                 }
             }
@@ -859,8 +897,13 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
             double v = L[i];
             if (v == 0.0) continue;
             int rr = i / nVJ, cc = i - rr * nVJ;
-            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-            if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            if constexpr (CL) {
+                nm_add(P.nm, vI[rr], vJ[cc], v);
+                if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
+            } else {
+                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+                if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            }
         }
     }
     for (int i = tid; i < BE * 6; i += 256) {
@@ -883,8 +926,9 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
 // bucket at a time, so all lanes of a wave run the same order.  Diagonal
 // blocks, self terms and off-diagonal blocks are accumulated in LDS as in
 // far_kernel and flushed once per tile.
-template <int DIM, int MIX, int SUR>
+template <int DIM, int MIX, int SUR, int CL>
 __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
+    static_assert(!(CL && SUR), "the cluster near field takes the exact rules");
     constexpr int NV = DIM + 1;
     constexpr int NC = NV * DIM;
     __shared__ double L[MAXV * MAXV];
@@ -900,6 +944,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     __shared__ float souts[SUR ? 4 * 16 * 24 : 1];  // network outputs, 16 samples per wave
     constexpr bool TAB = DIM == 2 && !MIX;   // FP64 kernel power by LDS tables
     __shared__ __align__(16) double pw[TAB ? 768 : 1];
+    __shared__ unsigned short nbits[CL ? BE : 1][4];
 
     const long long t = blockIdx.x;
     const int2 tb = P.tiles[t];
@@ -954,6 +999,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
             sVJ[a][r] = (Kt < T && a < NV) ? E.vid[a][Kt] : -3;
         }
     }
+    if constexpr (CL) nm_tile_bits(P.nm, I0, J0, T, nbits, tid);
     __syncthreads();
     // classify
     for (int pidx = tid; pidx < BE * BE; pidx += 256) {
@@ -1183,10 +1229,11 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                 else far_pair<DIM, MIX>(k, X, Y, P.pe, SK, ST, O);
             }
             const double f = P.C * sI[9][r] * sJ[9][l] * pair_w(E, I0 + r, J0 + l);
+            const double fs = (CL && !nm_bit(nbits, r, l)) ? 0.0 : f;
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                if (SK[m] != 0.0) atomicAdd(&SI[r * 6 + m], f * SK[m]);
-                if (ST[m] != 0.0) atomicAdd(&SJ[l * 6 + m], f * ST[m]);
+                if (SK[m] != 0.0 && fs != 0.0) atomicAdd(&SI[r * 6 + m], fs * SK[m]);
+                if (ST[m] != 0.0 && fs != 0.0) atomicAdd(&SJ[l * 6 + m], fs * ST[m]);
             }
             if (!direct) {
 #pragma unroll
@@ -1213,8 +1260,13 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                         int gb = E.dof[b][Kt];
                         if (gb < 0) continue;
                         double v = -f * O[3 * a + b];
-                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        if constexpr (CL) {
+                            nm_add(P.nm, ga, gb, v);
+                            nm_add(P.nm, gb, ga, v);
+                        } else {
+                            atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                            atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        }
                     }
                 }
             }
@@ -1226,8 +1278,13 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
             double v = L[i];
             if (v == 0.0) continue;
             int rr = i / nVJ, cc = i - rr * nVJ;
-            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-            if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            if constexpr (CL) {
+                nm_add(P.nm, vI[rr], vJ[cc], v);
+                if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
+            } else {
+                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+                if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            }
         }
     }
     for (int i = tid; i < BE * 6; i += 256) {
@@ -1264,7 +1321,9 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 // points relative to an origin in the row block (the first row's first
 // vertex), so that their rounding error stays relative to the pair's
 // distance; the sums of a pair are formed in FP32 and added in FP64.
-template <int KO, int MIX, int W>
+// CL = 1: the cluster near field, as in far_kernel (the potentials take only
+// the pairs of near anchor leaves).
+template <int KO, int MIX, int W, int CL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void far2_kernel(ElemDev E, FarParams P) {
     constexpr int Q = KO * KO;
     constexpr int LS = MAXV + 1;  // row stride of L; row / column MAXV: vertices without a DOF
@@ -1276,6 +1335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
     __shared__ int sRO[BE][3];                      // byte offsets of the rows' L rows
     __shared__ double sPhi[BE][Q];
     __shared__ int vI[MAXV], vJ[MAXV];
+    __shared__ unsigned short nbits[CL ? BE : 1][4];
 
     const int2 tb = P.tiles[blockIdx.x];
     const int bi = tb.x, bj = tb.y;
@@ -1357,6 +1417,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
     double Psi[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) Psi[q] = 0.0;
+    if constexpr (CL) nm_tile_bits(P.nm, I0, J0, T, nbits, tid);
     __syncthreads();
 
     for (int r = wave; r < BE; r += 4) {
@@ -1366,6 +1427,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         for (int c = 0; c < 2 * Q; ++c) xp[c] = sX[r][c];
         double f = sMK[r] * ct;
         if constexpr (W) f *= okt ? pair_w(E, I0 + r, Kt) : 0.0;
+        const double fs = (CL && !nm_bit(nbits, r, lane)) ? 0.0 : f;
         double M[Q][3];
         if constexpr (MIX) {
             float xf[2 * Q], Mf[Q][3];
@@ -1385,7 +1447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                     Mf[p][2] += (float)cw[q][2] * kv;
                     h += (float)wq[p] * kv;
                 }
-                Psi[q] += f * (double)h;
+                Psi[q] += fs * (double)h;
             }
 #pragma unroll
             for (int p = 0; p < Q; ++p)
@@ -1424,7 +1486,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                 M[p][2] += cw[q][2] * kv;
                 h += wq[p] * kv;
             }
-            Psi[q] += f * h;
+            Psi[q] += fs * h;
             __builtin_amdgcn_sched_barrier(0);
         }
         }
@@ -1432,7 +1494,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         {
             double g[Q];
 #pragma unroll
-            for (int p = 0; p < Q; ++p) g[p] = f * ((M[p][0] + M[p][1]) + M[p][2]);
+            for (int p = 0; p < Q; ++p) g[p] = fs * ((M[p][0] + M[p][1]) + M[p][2]);
             if constexpr (Q == 4) {
                 const double v = wave_sum4_lanes(g);
                 if ((lane & 15) == 0) sPhi[r][lane >> 4] = v;
@@ -1461,8 +1523,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                     const int gb = E.dof[b][Kt];
                     if (ga < 0 || gb < 0) continue;
                     const double v = -f * o[b];
-                    atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                    atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                    if constexpr (CL) {
+                        nm_add(P.nm, ga, gb, v);
+                        nm_add(P.nm, gb, ga, v);
+                    } else {
+                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
+                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                    }
                 }
             }
         }
@@ -1483,8 +1550,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
             const int rr = i / nVJ, cc = i - rr * nVJ;
             const double v = L[rr * LS + cc];
             if (v == 0.0) continue;
-            atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-            atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            if constexpr (CL) {
+                nm_add(P.nm, vI[rr], vJ[cc], v);
+                nm_add(P.nm, vJ[cc], vI[rr], v);
+            } else {
+                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+                atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+            }
         }
     }
     __syncthreads();
@@ -1518,32 +1590,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
 void launch_far(const ElemDev& E, const FarParams& P, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
+    if (P.nm.An) {
+        // cluster near field: FP64, exact rules (the host refuses the rest)
+        if (P.dim == 2) hipLaunchKernelGGL((near_kernel<2, 0, 0, 1>), grid, block, 0, st, E, P);
+        else hipLaunchKernelGGL((near_kernel<1, 0, 0, 1>), grid, block, 0, st, E, P);
+        return;
+    }
     if (P.dim == 2) {
         if (P.sur.nsur > 0) {
-            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 1>), grid, block, 0, st, E, P);
-            else hipLaunchKernelGGL((near_kernel<2, 0, 1>), grid, block, 0, st, E, P);
+            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 1, 0>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((near_kernel<2, 0, 1, 0>), grid, block, 0, st, E, P);
         } else {
-            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 0>), grid, block, 0, st, E, P);
-            else hipLaunchKernelGGL((near_kernel<2, 0, 0>), grid, block, 0, st, E, P);
+            if (P.mixed) hipLaunchKernelGGL((near_kernel<2, 1, 0, 0>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((near_kernel<2, 0, 0, 0>), grid, block, 0, st, E, P);
         }
     } else {
-        if (P.mixed) hipLaunchKernelGGL((near_kernel<1, 1, 0>), grid, block, 0, st, E, P);
-        else hipLaunchKernelGGL((near_kernel<1, 0, 0>), grid, block, 0, st, E, P);
+        if (P.mixed) hipLaunchKernelGGL((near_kernel<1, 1, 0, 0>), grid, block, 0, st, E, P);
+        else hipLaunchKernelGGL((near_kernel<1, 0, 0, 0>), grid, block, 0, st, E, P);
     }
 }
 
 void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_t st) {
     if (P.ntiles == 0) return;
     dim3 grid((unsigned)P.ntiles), block(256);
-#define FL_FAR_CASE(D, K)                                                          \
-    do {                                                                           \
-        if (P.mixed) hipLaunchKernelGGL((far_kernel<D, K, 1>), grid, block, 0, st, E, P); \
-        else hipLaunchKernelGGL((far_kernel<D, K, 0>), grid, block, 0, st, E, P);         \
+#define FL_FAR_CASE(D, K)                                                                    \
+    do {                                                                                     \
+        if (P.nm.An) hipLaunchKernelGGL((far_kernel<D, K, 0, 1>), grid, block, 0, st, E, P);      \
+        else if (P.mixed) hipLaunchKernelGGL((far_kernel<D, K, 1, 0>), grid, block, 0, st, E, P); \
+        else hipLaunchKernelGGL((far_kernel<D, K, 0, 0>), grid, block, 0, st, E, P);              \
     } while (0)
     if (P.dim == 2 && fark <= 2) {
         const bool w = E.w != nullptr;
-#define FL_FAR2(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W>), grid, block, 0, st, E, P)
-        if (fark == 1) {
+#define FL_FAR2(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W, 0>), grid, block, 0, st, E, P)
+        if (P.nm.An) {
+            if (fark == 1) hipLaunchKernelGGL((far2_kernel<1, 0, 0, 1>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((far2_kernel<2, 0, 0, 1>), grid, block, 0, st, E, P);
+        } else if (fark == 1) {
             if (P.mixed) { if (w) FL_FAR2(1, 1, 1); else FL_FAR2(1, 1, 0); }
             else { if (w) FL_FAR2(1, 0, 1); else FL_FAR2(1, 0, 0); }
         } else {
@@ -1878,6 +1960,13 @@ __device__ __forceinline__ void edge_acc(const double* E, const double* ap, cons
         for (int b = a; b < 3; ++b) M6[sym3(a, b)] += kv * P[a] * P[b];
 }
 
+// output of the touching-pair kernels: the dense matrix, or the cluster
+// near field (every touching pair lies in a near block)
+__device__ __forceinline__ void touch_add(const TouchParams& P, int i, int j, double v) {
+    if (P.nm.An) nm_add(P.nm, i, j, v);
+    else atomicAdd(&P.A[(long long)i * P.lda + j], v);
+}
+
 // Triangles sharing an edge: K = (q0,q1,a), Kt = (q0,q1,b), q0 < q1 by
 // vertex id.  Coordinates (u,v,w) relative to the edge, analytic radial
 // factor 1/((3-2s)(4-2s)), faces of the unit gauge surface: triangles F1,
@@ -1946,7 +2035,7 @@ __global__ __launch_bounds__(256) void touch_edge2_kernel(ElemDev E, TouchParams
             double acc = 0.0;
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) acc += Cm[i][a] * M6[sym3(a, b)] * Cm[j][b];
-            atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * acc);
+            touch_add(P, g[i], g[j], f * acc);
         }
     }
 }
@@ -1988,7 +2077,7 @@ __global__ __launch_bounds__(256) void touch_vert_kernel(ElemDev E, TouchParams 
             if (g[i] < 0) continue;
             for (int j = 0; j < 3; ++j) {
                 if (g[j] < 0) continue;
-                atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * M[sym3(i, j)]);
+                touch_add(P, g[i], g[j], f * M[sym3(i, j)]);
             }
         }
         return;
@@ -2045,7 +2134,7 @@ __global__ __launch_bounds__(256) void touch_vert_kernel(ElemDev E, TouchParams 
             double acc = 0.0;
             for (int p = 0; p < 4; ++p)
                 for (int q = 0; q < 4; ++q) acc += Cm[i][p] * F[p][q] * Cm[j][q];
-            atomicAdd(&P.A[(long long)g[i] * P.lda + g[j]], f * acc);
+            touch_add(P, g[i], g[j], f * acc);
         }
     }
 }
@@ -2106,6 +2195,50 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
     dim3 grid((nv + 255) / 256), block(256);
     hipLaunchKernelGGL(scatter_self_kernel, grid, block, 0, st, E, v2c_ptr, v2c_idx, node2dof, vloc,
                        nv, dim, S, mass, A, lda);
+}
+
+// The same into the cluster near field (entries (i, j) of elements around
+// DOF i: near blocks; one thread per vertex owns row i, so no atomics).
+__global__ __launch_bounds__(256) void scatter_self_near_kernel(ElemDev E, const int* v2c_ptr,
+                                                                const int* v2c_idx, const int* node2dof,
+                                                                const unsigned char* vloc, int nv, int dim,
+                                                                const double* S, double mass, NearMap nm) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int i = node2dof[v];
+    if (i < 0) return;
+    for (int e = v2c_ptr[v]; e < v2c_ptr[v + 1]; ++e) {
+        const int K = v2c_idx[e];
+        const int a = vloc[e];
+        const double mk = mass * E.meas[K];
+        for (int b = 0; b <= dim; ++b) {
+            int j = E.dof[b][K];
+            if (j < 0) continue;
+            double add = S[(long long)K * 6 + sym3(a, b)];
+            if (mass != 0.0) add += mass_entry(mk, a, b, dim);
+            double* q = nm_slot(nm, i, j);
+            if (q) *q += add;
+        }
+    }
+}
+
+void launch_scatter_self_near(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx, const int* node2dof,
+                              const unsigned char* vloc, int nv, int dim, const double* S, double mass,
+                              const NearMap& nm, hipStream_t st) {
+    if (nv == 0) return;
+    hipLaunchKernelGGL(scatter_self_near_kernel, dim3((nv + 255) / 256), dim3(256), 0, st, E, v2c_ptr, v2c_idx,
+                       node2dof, vloc, nv, dim, S, mass, nm);
+}
+
+__global__ __launch_bounds__(256) void near_diag_kernel(NearMap nm, long long n, double* d) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* q = nm_slot(nm, (int)i, (int)i);
+    d[i] = q ? *q : 0.0;
+}
+
+void launch_near_diag(const NearMap& nm, long long n, double* d, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(near_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nm, n, d);
 }
 
 // y_i = sum over the elements K of DOF i's vertex of K's mass matrix row

@@ -39,7 +39,7 @@ EXPORTS = ["fl_default_opts", "fl_create", "fl_destroy", "fl_last_error", "fl_se
            "fl_surrogate_predict", "fl_surrogate_certify", "fl_mass_matvec", "fl_mg_setup", "fl_solve_mg",
            "fl_eval_points", "fl_strong_form", "fl_indicators", "fl_cluster_build", "fl_cluster_matvec",
            "fl_solve_cluster", "fl_cluster_info", "fl_set_symmetry",
-           "fl_strong_form_cluster", "fl_solve_cluster_mg", "fl_matvec_noalloc"]
+           "fl_strong_form_cluster", "fl_solve_cluster_mg", "fl_matvec_noalloc", "fl_cluster_assemble"]
 SUR_NIN, SUR_NOUT, SUR_NPARAM, SUR_NRB, SUR_NSB, SUR_BLOB = 9, 21, 8352, 6, 4, 8454
 
 
@@ -114,6 +114,7 @@ def lib():
         L.fl_mg_setup.argtypes = [vp, C.c_int, vp, vp]
         L.fl_eval_points.argtypes = [vp, C.c_int32, vp, vp]
         L.fl_cluster_build.argtypes = [vp, C.c_int32, dp, C.c_int32]
+        L.fl_cluster_assemble.argtypes = [vp, dp, C.POINTER(FlOpts), C.c_int32, dp, C.c_int32, C.POINTER(i64)]
         L.fl_set_symmetry.argtypes = [vp, C.c_int32, i64, vp, vp, vp]
         L.fl_cluster_matvec.argtypes = [vp, vp, vp]
         L.fl_solve_cluster.argtypes = [vp, vp, vp, dp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(dp)]
@@ -335,6 +336,15 @@ class Handle:
     def cluster_build(self, m=6, eta=2.0, leaf=32):
         """Cluster approximation of the assembled matrix (order m, admissibility eta)."""
         self._check(lib().fl_cluster_build(self.h, m, eta, leaf))
+
+    def cluster_assemble(self, s: float, opts: FlOpts | None = None, m=6, eta=2.0, leaf=32) -> int:
+        """Cluster approximation assembled from the mesh, without the dense
+        matrix (near field from the pair kernels); returns n."""
+        n = C.c_int64()
+        self._check(lib().fl_cluster_assemble(self.h, s, None if opts is None else C.byref(opts), m, eta, leaf,
+                                              C.byref(n)))
+        self.n = n.value
+        return self.n
 
     def cluster_matvec(self, x, y):
         self._check(lib().fl_cluster_matvec(self.h, _ptr(x), _ptr(y)))
