@@ -67,8 +67,10 @@ def parse():
     ap.add_argument("--sur-train", type=int, default=65536, help="training pairs of the surrogate")
     ap.add_argument("--sur-steps", type=int, default=20000, help="Adam steps of the surrogate")
     ap.add_argument("--sur-tol", type=float, default=0.02, help="certified bound for the surrogate")
+    ap.add_argument("--no-cluster", action="store_true",
+                    help="skip the cluster-method leg (disks of ~3.2e4, ~2e5 and ~4e5 triangles)")
     ap.add_argument("--all-legs", action="store_true",
-                    help="also run the multigrid, a posteriori, cluster and symmetry legs")
+                    help="also run the multigrid, a posteriori and symmetry legs")
     ap.add_argument("--only-mg", action="store_true", help="run only the multigrid leg and print its object")
     ap.add_argument("--only-indicators", action="store_true",
                     help="run only the a posteriori leg and print its object")
@@ -81,17 +83,27 @@ def parse():
 
 
 def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel source changed since it was taken."""
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of the benchmark workload (scaled by a plain copy's
+    counters), per kernel group; a group's figure is dropped (None) when the
+    source file of its kernels changed since the counters were taken."""
     import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "traffic_disk8k.json")) as f:
+        with open(os.path.join(ROOT, "profiles", "traffic_disk200k.json")) as f:
             t = json.load(f)
-        with open(os.path.join(ROOT, "paper_1708_03912_amd", "csrc", "fl_kernels.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
-        return None
-    return t if t.get("source_sha256") == sha else None
+        return {}
+    out = {}
+    for key in ("cg_iteration", "separated_pairs"):
+        ent = t.get(key) or {}
+        try:
+            with open(os.path.join(ROOT, "paper_1708_03912_amd", "csrc", ent["source"]), "rb") as f:
+                sha = hashlib.sha256(f.read()).hexdigest()
+        except (OSError, KeyError):
+            continue
+        if sha == ent.get("source_sha256"):
+            out[key] = ent["bytes_per_launch"]
+    return out
 
 
 def copy_calib(mib):
@@ -202,11 +214,11 @@ def rooflines(D, svals, cache_resident):
     far_ms = mean["t_far"]
     evals_per_s = far_evals / (far_ms * 1e-3)
     far_tflops = evals_per_s * FLOPS_PER_EVAL / 1e12
-    traffic = measured_traffic()
-    rf_far = {"kernel": "far_kernel<2,2,0> + near_kernel<2,0,0> (separated element pairs, FP64)",
+    traffic = measured_traffic() if cache_resident is False else {}
+    rf_far = {"kernel": "far2_kernel<2,0,0,0> + near_kernel<2,0,0,0> (separated element pairs, FP64)",
               "bound": "alu", "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4),
-              "traffic": traffic and traffic.get("separated_pairs_bytes_per_assembly"),
+              "traffic": traffic.get("separated_pairs"),
               "per_launch_ms": round(far_ms / nsv, 4), "evals_per_launch": far_evals // nsv,
               "evals_per_s": round(evals_per_s, 1), "flops_per_eval": FLOPS_PER_EVAL,
               "transcendentals_per_eval": TRANS_PER_EVAL,
@@ -220,11 +232,11 @@ def rooflines(D, svals, cache_resident):
     vec_bytes = 12 * n * 8  # p, z, r, x, b, d and the slots' reads and writes, about
     cg_bytes = n * (n + 1) // 2 * 8 + vec_bytes
     cg_gbps = cg_bytes / (cg_ms_it * 1e-3) / 1e9
-    rf_cg = {"kernel": "cg_symv_kernel + cg_update_kernel (one Jacobi-PCG iteration, FP64 symmetric product "
-                       "from the upper triangle)",
+    rf_cg = {"kernel": "cg_symv_kernel + cg_update_kernel + cg_scalar_kernel (one Jacobi-PCG iteration, FP64 "
+                       "symmetric product from the upper triangle)",
              "bound": "hbm", "achieved": round(cg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
              "frac": round(cg_gbps / HBM_PEAK_GBPS, 4),
-             "traffic": traffic and traffic.get("cg_iteration_bytes"),
+             "traffic": traffic.get("cg_iteration"),
              "per_launch_ms": round(cg_ms_it, 4), "bytes_per_launch": cg_bytes,
              "iterations_launched_per_step": launched}
     if cache_resident:
@@ -311,8 +323,9 @@ def main():
         D2["h"].close()
         del D2
     legs = [("batch", not args.no_batch, batch_leg), ("surrogate", not args.no_surrogate, surrogate_leg),
+            ("cluster", big and not args.no_cluster, cluster_leg),
             ("multigrid", args.all_legs, mg_leg), ("indicators", args.all_legs, indicators_leg),
-            ("cluster", args.all_legs, cluster_leg), ("symmetry", args.all_legs, symmetry_leg)]
+            ("symmetry", args.all_legs, symmetry_leg)]
     for key, on, fn in legs:
         if on:
             out[key] = fn(args)
@@ -892,60 +905,76 @@ def indicators_leg(args):
 
 
 def cluster_leg(args):
-    """Cluster approximation (Sec. 6) of the assembled FP64 matrix on unit
-    disks of ~8k, 32k and 128k triangles (s = 0.75, interior DOFs), m = 6,
-    eta = 2, leaves of 32 DOFs: set-up time, device bytes against the dense
-    upper triangle, product time against the dense symmetric product, the
-    relative product error, and Jacobi-PCG to 1e-10 on both operators."""
+    """Cluster method (Sec. 6) assembled from the mesh alone
+    (fl_cluster_assemble: near field from the pair kernels, far field by
+    Chebyshev interpolation, no dense matrix) on unit disks, s = 0.75,
+    f = 1, interior DOFs, eta = 2, leaves of 32 DOFs, m = 6 and 8: assembly
+    and Jacobi-PCG (to 1e-10) times, device bytes, product time and energy
+    error against the closed form.  On the disks of ~3.2e4 and ~2e5
+    triangles the dense FP64 path runs beside it; the ~4e5-triangle disk
+    (n ~ 2e5) has a dense matrix larger than the device memory."""
     import torch
     from paper_1708_03912_amd import fraclap as F, meshgen as M
-    out = {"workload": "unit disk, s=0.75, f=1; cluster approximation m=6, eta=2, leaf 32 vs the dense FP64 matrix"}
-    for cells in (8000, 32000, 128000):
+    s = 0.75
+    fu = ball_fu(s)
+    out = {"workload": "unit disk, s=0.75, f=1, interior DOFs; cluster method assembled from the mesh, eta=2, "
+                       "leaf 32, m in {6, 8}; dense FP64 path beside it where its matrix fits",
+           "device_bytes": torch.cuda.mem_get_info()[1]}
+    o = F.make_opts(dof_mode="interior")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    for cells in (32000, 200000, 400000):
         mesh = M.disk_for_cells(cells, seed=2)
+        r = {}
         h = F.Handle(0)
         h.set_mesh(mesh)
-        n = h.assemble(0.75)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h.cluster_build(m=6, eta=2.0, leaf=32)
-        torch.cuda.synchronize()
-        t_build = (time.perf_counter() - t0) * 1e3
-        info = h.cluster_info()
-        x = torch.tensor(__import__("numpy").random.default_rng(1).standard_normal(n), device="cuda")
-        yd, yh = torch.empty_like(x), torch.empty_like(x)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        h.matvec(x, yd)
-        h.cluster_matvec(x, yh)
-        reps = 20
-        ev[0].record()
-        for _ in range(reps):
-            h.matvec(x, yd)
-        ev[1].record()
-        for _ in range(reps):
-            h.cluster_matvec(x, yh)
-        ev[2].record()
-        torch.cuda.synchronize()
-        t_dense = ev[0].elapsed_time(ev[1]) / reps
-        t_h = ev[1].elapsed_time(ev[2]) / reps
-        err = float(torch.linalg.norm(yh - yd) / torch.linalg.norm(yd))
-        b = torch.empty(n, dtype=torch.float64, device="cuda")
-        h.load_vector_one(b)
-        ud, uh = torch.zeros_like(b), torch.zeros_like(b)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        itd, _, _ = h.solve(b, ud, rtol=1e-10)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ith, _, _ = h.solve_cluster(b, uh, rtol=1e-10)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        out[f"cells{len(mesh['cells'])}"] = {
-            "n": n, "build_ms": round(t_build, 2), "clusters": info["clusters"], "far_pairs": info["far_pairs"],
-            "near_entries": info["near_entries"], "bytes": info["bytes"],
-            "dense_upper_bytes": n * (n + 1) // 2 * 8, "matvec_dense_ms": round(t_dense, 4),
-            "matvec_cluster_ms": round(t_h, 4), "rel_err": err, "cg_dense": [itd, round((t1 - t0) * 1e3, 2)],
-            "cg_cluster": [ith, round((t2 - t1) * 1e3, 2)]}
+        n = None
+        if cells <= 200000:
+            n, t_asm = timed(lambda: h.assemble(s, o))
+            b = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.load_vector_one(b)
+            u = torch.zeros_like(b)
+            (it, rel, rc), t_sol = timed(lambda: h.solve(b, u, rtol=1e-10, maxit=20000))
+            x = torch.ones(n, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            h.matvec(x, y)
+            _, t_mv = timed(lambda: [h.matvec(x, y) for _ in range(10)])
+            r["dense"] = {"assemble_ms": round(t_asm, 2), "cg_iters": it, "cg_ms": round(t_sol, 2),
+                          "matvec_ms": round(t_mv / 10, 4), "bytes": n * h.ld * 8,
+                          "energy_error": math.sqrt(max(fu - float(torch.dot(b, u)), 0.0))}
+            del b, u, x, y
+        for m in (6, 8):
+            n2, t_asm = timed(lambda: h.cluster_assemble(s, o, m=m, eta=2.0, leaf=32))
+            n = n2
+            info = h.cluster_info()
+            st = h.stats()
+            b = torch.empty(n, dtype=torch.float64, device="cuda")
+            h.load_vector_one(b)
+            u = torch.zeros_like(b)
+            (it, rel, rc), t_sol = timed(lambda: h.solve_cluster(b, u, rtol=1e-10, maxit=20000))
+            x = torch.ones(n, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            h.cluster_matvec(x, y)
+            _, t_mv = timed(lambda: [h.cluster_matvec(x, y) for _ in range(10)])
+            r["cluster_m%d" % m] = {
+                "assemble_ms": round(t_asm, 2), "near_field_kernels_ms": round(st.t_assemble_ms, 2),
+                "cg_iters": it, "cg_ms": round(t_sol, 2), "matvec_ms": round(t_mv / 10, 4),
+                "bytes": info["bytes"], "near_entries": info["near_entries"], "far_pairs": info["far_pairs"],
+                "energy_error": math.sqrt(max(fu - float(torch.dot(b, u)), 0.0))}
+            del b, u, x, y
+        r["n"] = n
+        r["cells"] = len(mesh["cells"])
+        r["dense_fp64_bytes"] = n * n * 8
+        out["cells%d" % len(mesh["cells"])] = r
         h.close()
+        torch.cuda.empty_cache()
+        print(json.dumps({"progress": "cluster leg", "cells": len(mesh["cells"])}), file=sys.stderr, flush=True)
     return out
 
 

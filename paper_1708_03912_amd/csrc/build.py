@@ -1,6 +1,6 @@
 """Build libfraclap.so (gfx950) in-tree with hipcc.
 
-Translation units: the assembly / single-system solver kernels, the
+Translation units: the assembly kernels, the single-system solver kernels, the
 batched product / solver kernels, the surrogate network kernels and the
 multigrid kernels, the strong-form kernels and the cluster kernels (default
 floating-point contraction), the host planner (no contraction, see
@@ -21,7 +21,7 @@ ARCH = os.environ.get("FRACLAP_ARCH", "gfx950")
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-UNITS = [("fl_kernels.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
+UNITS = [("fl_kernels.hip", []), ("fl_solve.hip", []), ("fl_batch.hip", []), ("fl_sur.hip", []), ("fl_mg.hip", []),
          ("fl_sf.hip", []), ("fl_cluster.hip", []), ("fl_api.hip", ["-ffp-contract=off"]),
          ("fl_batch_api.hip", []), ("fl_sur_api.hip", []), ("fl_mg_api.hip", []), ("fl_sf_api.hip", ["-ffp-contract=off"]),
          ("fl_cluster_api.hip", ["-ffp-contract=off"])]
