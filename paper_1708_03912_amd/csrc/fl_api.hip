@@ -1008,6 +1008,10 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
         launch_scatter_self(E, h->d_sc_ptr, h->d_sc_idx, h->d_sc_map, h->d_sc_vloc, h->sc_rows, dim, dS,
                             o.mass_shift, A, lda, h->stream);
     HIPCHK(hipGetLastError());
+    if (A) {
+        launch_mirror_lower(A, lda, n, h->stream);
+        HIPCHK(hipGetLastError());
+    }
     if (A32) {
         launch_to_f32(A, lda, n, A32, h->stream);
         HIPCHK(hipGetLastError());

@@ -168,6 +168,8 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
                          const double* S, double mass, double* A, long long lda, hipStream_t st);
 // y = M x, M the P1 mass matrix on the DOFs
+// A[j][i] = A[i][j] for j > i (the assembly writes the upper triangle)
+void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st);
 // the same into the cluster near field; mass as above
 void launch_scatter_self_near(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx, const int* node2dof,
                               const unsigned char* vloc, int nv, int dim, const double* S, double mass,

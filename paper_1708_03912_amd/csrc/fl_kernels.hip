@@ -26,6 +26,20 @@ hipError_t upload_rules(const RuleTables& R, hipStream_t st) {
                                   hipMemcpyHostToDevice, st);
 }
 
+// Dense assembly accumulates the upper triangle only (entry (min, max) of
+// every contribution to (i, j) and (j, i): one FP64 atomic where a
+// symmetric pair of atomics would go, which halves the traffic that limits
+// the tile flush); mirror_lower_kernel copies it to the lower triangle.
+__device__ __forceinline__ long long upper_index(int i, int j, long long lda) {
+    return i <= j ? (long long)i * lda + j : (long long)j * lda + i;
+}
+
+// an off-diagonal contribution v to (i, j) and to (j, i): once in the upper
+// triangle, twice when i = j (two vertices folded onto one DOF)
+__device__ __forceinline__ void add_pair_upper(double* A, long long lda, int i, int j, double v) {
+    atomicAdd(&A[upper_index(i, j, lda)], i == j ? 2.0 * v : v);
+}
+
 __device__ __forceinline__ int sym3(int a, int b) {
     // upper-triangular slot of (a,b), a <= b, in a 3x3 symmetric block
     return a <= b ? a * 3 - a * (a + 1) / 2 + b : b * 3 - b * (b + 1) / 2 + a;
@@ -878,8 +892,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                             nm_add(P.nm, ga, gb, v);
                             nm_add(P.nm, gb, ga, v);
                         } else {
-                            atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                            atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                            add_pair_upper(P.A, P.lda, ga, gb, v);
                         }
                     }
                 }
@@ -900,9 +913,11 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
             if constexpr (CL) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
-            } else {
+            } else if (bi != bj) {
+                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
+            } else if (vI[rr] <= vJ[cc]) {
+                // a diagonal tile's block holds both orientations already
                 atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-                if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
             }
         }
     }
@@ -1188,8 +1203,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                     } else {
                         const int ga = E.dof[sk][I0 + r], gb = E.dof[sl][J0 + l];
                         if (ga < 0 || gb < 0) continue;
-                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        add_pair_upper(P.A, P.lda, ga, gb, v);
                     }
                 }
         }
@@ -1264,8 +1278,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                             nm_add(P.nm, ga, gb, v);
                             nm_add(P.nm, gb, ga, v);
                         } else {
-                            atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                            atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                            add_pair_upper(P.A, P.lda, ga, gb, v);
                         }
                     }
                 }
@@ -1281,9 +1294,11 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
             if constexpr (CL) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
-            } else {
+            } else if (bi != bj) {
+                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
+            } else if (vI[rr] <= vJ[cc]) {
+                // a diagonal tile's block holds both orientations already
                 atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-                if (bi != bj) atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
             }
         }
     }
@@ -1527,8 +1542,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                         nm_add(P.nm, ga, gb, v);
                         nm_add(P.nm, gb, ga, v);
                     } else {
-                        atomicAdd(&P.A[(long long)ga * P.lda + gb], v);
-                        atomicAdd(&P.A[(long long)gb * P.lda + ga], v);
+                        add_pair_upper(P.A, P.lda, ga, gb, v);
                     }
                 }
             }
@@ -1554,8 +1568,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 nm_add(P.nm, vJ[cc], vI[rr], v);
             } else {
-                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
-                atomicAdd(&P.A[(long long)vJ[cc] * P.lda + vI[rr]], v);
+                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
             }
         }
     }
@@ -1964,7 +1977,7 @@ __device__ __forceinline__ void edge_acc(const double* E, const double* ap, cons
 // near field (every touching pair lies in a near block)
 __device__ __forceinline__ void touch_add(const TouchParams& P, int i, int j, double v) {
     if (P.nm.An) nm_add(P.nm, i, j, v);
-    else atomicAdd(&P.A[(long long)i * P.lda + j], v);
+    else if (i <= j) atomicAdd(&P.A[(long long)i * P.lda + j], v);  // (j, i) visits the same value
 }
 
 // Triangles sharing an edge: K = (q0,q1,a), Kt = (q0,q1,b), q0 < q1 by
@@ -2182,6 +2195,7 @@ __global__ __launch_bounds__(256) void scatter_self_kernel(ElemDev E, const int*
         for (int b = 0; b <= dim; ++b) {
             int j = E.dof[b][K];
             if (j < 0) continue;
+            if (j < i) continue;  // the lower triangle is the mirror of the upper
             double add = S[(long long)K * 6 + sym3(a, b)];
             if (mass != 0.0) add += mass_entry(mk, a, b, dim);
             row[j] += add;
@@ -2195,6 +2209,33 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
     dim3 grid((nv + 255) / 256), block(256);
     hipLaunchKernelGGL(scatter_self_kernel, grid, block, 0, st, E, v2c_ptr, v2c_idx, node2dof, vloc,
                        nv, dim, S, mass, A, lda);
+}
+
+// Lower triangle from the upper one: workgroup (J, I), I <= J, copies the
+// transpose of the 64 x 64 tile (I, J) through LDS into tile (J, I)
+// (diagonal tiles: their strictly lower part); workgroups with I > J exit.
+__global__ __launch_bounds__(256) void mirror_lower_kernel(double* A, long long lda, int n) {
+    __shared__ double t[64][65];
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (I > J) return;
+    const int r0 = I * 64, c0 = J * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int gr = r0 + r, gc = c0 + tx;
+        t[r][tx] = (gr < n && gc < n) ? A[(long long)gr * lda + gc] : 0.0;
+    }
+    __syncthreads();
+    // row c0 + r of the lower tile = column r of the upper tile
+    for (int r = ty; r < 64; r += 4) {
+        const int gr = c0 + r, gc = r0 + tx;
+        if (gr < n && gc < n && (I != J || tx < r)) A[(long long)gr * lda + gc] = t[tx][r];
+    }
+}
+
+void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st) {
+    if (n <= 1) return;
+    const unsigned nt = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(mirror_lower_kernel, dim3(nt, nt), dim3(256), 0, st, A, lda, (int)n);
 }
 
 // The same into the cluster near field (entries (i, j) of elements around
