@@ -135,6 +135,29 @@ typedef struct {
                                             (M + dt A^s) u = b, i.e.
                                             (A^s + M/dt) u = b/dt.  0
                                             (default): A^s alone           */
+    int deterministic;                   /* 0 (default): contributions are
+                                            added with FP64 atomics (the
+                                            order, and with it the last
+                                            bits, vary from run to run).
+                                            1 (fl_assemble only): bitwise
+                                            repeatable -- every contribution
+                                            that a kernel shares with others
+                                            is split exactly into two
+                                            fixed-point words (a coarse
+                                            int32 and an int64 remainder at
+                                            2^-68 of a bound on the entries,
+                                            a(phi_i, phi_i) <= C |supp_i|
+                                            |S^{d-1}| L_i^{2s} (1/(2-2s) +
+                                            1/(2s)), L_i the largest
+                                            gradient of phi_i) and summed
+                                            with integer atomics, which do
+                                            not depend on order; one pass
+                                            turns them back into FP64.
+                                            Needs n x ld x 4 more bytes of
+                                            device memory.  FL_EINVAL for
+                                            fl_assemble_batch,
+                                            fl_cluster_assemble and with
+                                            surrogate > 0               */
 } fl_opts;
 
 typedef struct {

@@ -68,6 +68,11 @@ void free_buffers(fl_handle* h) {
     if (h->dA32) (void)hipFree(h->dA32);
     h->dA32 = nullptr;
     h->A32_cap = 0;
+    if (h->dAhi) (void)hipFree(h->dAhi);
+    if (h->dSfix) (void)hipFree(h->dSfix);
+    h->dAhi = nullptr;
+    h->dSfix = nullptr;
+    h->Ahi_cap = h->Sfix_cap = 0;
     fl_batch& B = h->B;
     if (B.A64) (void)hipFree(B.A64);
     if (B.A32) (void)hipFree(B.A32);
@@ -167,6 +172,9 @@ int check_opts(fl_handle* h, const fl_opts& o) {
     if (!(o.sur_tol >= 0.0)) return fail(h, FL_EINVAL, "sur_tol must be >= 0");
     if (!(o.mass_shift >= 0.0) || !std::isfinite(o.mass_shift))
         return fail(h, FL_EINVAL, "mass_shift must be finite and >= 0");
+    if (o.deterministic != 0 && o.deterministic != 1) return fail(h, FL_EINVAL, "deterministic must be 0 or 1");
+    if (o.deterministic && o.surrogate > 0)
+        return fail(h, FL_EINVAL, "the repeatable assembly takes the exact rules (surrogate = 0)");
     for (int m = 0; m < o.n_classes; ++m) {
         if (!(o.theta[m] > 0.0) || !std::isfinite(o.theta[m]))
             return fail(h, FL_EINVAL, "theta must be positive and finite");
@@ -880,6 +888,51 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const
     return FL_OK;
 }
 
+// Bound on every partial sum the assembly accumulates.  For the hat
+// function of vertex v, with L_v its largest gradient on its cells and
+// |supp_v| their total measure, (phi(x) - phi(y))^2 <= min(L_v^2 |x-y|^2, 1)
+// on {x in supp} or {y in supp}, so
+//   a(phi_v, phi_v) <= C |supp_v| |S^{d-1}| L_v^{2s} (1/(2-2s) + 1/(2s));
+// every pair contribution to a diagonal entry is >= 0, and the absolute
+// contributions to an off-diagonal entry sum to at most the geometric mean
+// of two such bounds (Cauchy-Schwarz), and so do those to the cells'
+// diagonal blocks.  Times 2 for the quadrature, times K^2 with a K-fold
+// symmetry reduction (a DOF collects its orbit).
+double entry_bound(const fl_handle* h, double s) {
+    const int dim = h->dim, nper = dim + 1;
+    std::vector<double> supp(h->nv, 0.0), L(h->nv, 0.0);
+    for (int64_t K = 0; K < h->nc; ++K) {
+        const int32_t* c = &h->cells[nper * K];
+        if (dim == 1) {
+            const double len = std::fabs(h->verts[c[1]] - h->verts[c[0]]);
+            for (int a = 0; a < 2; ++a) {
+                supp[c[a]] += len;
+                L[c[a]] = std::max(L[c[a]], 1.0 / len);
+            }
+        } else {
+            double P[3][2];
+            for (int a = 0; a < 3; ++a)
+                for (int j = 0; j < 2; ++j) P[a][j] = h->verts[2 * c[a] + j];
+            const double area =
+                0.5 * std::fabs((P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[2][0] - P[0][0]) * (P[1][1] - P[0][1]));
+            for (int a = 0; a < 3; ++a) {
+                const double* p = P[(a + 1) % 3];
+                const double* q = P[(a + 2) % 3];
+                const double edge = std::hypot(q[0] - p[0], q[1] - p[1]);  // opposite vertex a
+                supp[c[a]] += area;
+                L[c[a]] = std::max(L[c[a]], edge / (2.0 * area));
+            }
+        }
+    }
+    const double sphere = dim == 1 ? 2.0 : 2.0 * M_PI;
+    const double rad = 1.0 / (2.0 - 2.0 * s) + 1.0 / (2.0 * s);
+    double m = 0.0;
+    for (int64_t v = 0; v < h->nv; ++v)
+        m = std::max(m, supp[v] * std::pow(L[v], 2.0 * s));
+    double k2 = h->sym_T > 0 ? (double)h->sym_order * h->sym_order : 1.0;
+    return 2.0 * k2 * cdn(dim, s) * sphere * rad * m;
+}
+
 // One assembly of A^s (Sec. 5 pair decomposition) into A (row-major, lda;
 // a_elems elements zeroed first), optional FP32 copy A32 (same lda).
 // Adds the phase times to *st and fills its pair counts.
@@ -908,6 +961,34 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     launch_zero(A, a_elems, h->stream);
     launch_zero(dS, T * 6, h->stream);
     launch_zero((double*)dcnt, 32, h->stream);
+    // repeatable accumulation: A's FP64 buffer holds the int64 remainders
+    // (zero bits are zero in both), an int32 plane the coarse words; the
+    // scale puts the entry bound just below 2^16 coarse units
+    const bool det = o.deterministic && A;
+    FixAcc fa{}, fsx{};
+    double from_hi = 0.0, from_lo = 0.0;
+    int* dflag = nullptr;
+    if (det) {
+        const size_t hi_words = ((size_t)a_elems + 1) / 2;  // int32 pairs as doubles
+        if ((rc = ensure_dev(h, &h->dAhi, &h->Ahi_cap, hi_words * 8))) return rc;
+        const size_t s_lo = (size_t)T * 6 * 8, s_hi = ((size_t)T * 6 * 4 + 7) / 8 * 8;
+        if ((rc = ensure_dev(h, &h->dSfix, &h->Sfix_cap, s_lo + s_hi + 8))) return rc;
+        launch_zero((double*)h->dAhi, (long long)hi_words, h->stream);
+        launch_zero((double*)h->dSfix, (long long)((s_lo + s_hi + 8) / 8), h->stream);
+        int e = 0;
+        (void)std::frexp(entry_bound(h, s), &e);  // bound < 2^e
+        fa.to_hi = std::ldexp(1.0, 16 - e);
+        fa.lo_per_hi = 4503599627370496.0;  // 2^52
+        from_hi = std::ldexp(1.0, e - 16);
+        from_lo = std::ldexp(1.0, e - 68);
+        dflag = (int*)(h->dSfix + s_lo + s_hi);
+        fa.flag = dflag;
+        fsx = fa;
+        fa.lo = (long long*)A;
+        fa.hi = h->dAhi;
+        fsx.lo = (long long*)h->dSfix;
+        fsx.hi = (int*)(h->dSfix + s_lo);
+    }
 
     hipEvent_t ev[5];
     for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -940,6 +1021,8 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     FP.cls_count = dcnt;
     FP.mixed = o.precision == FL_MIXED ? 1 : 0;
     if (nm) FP.nm = *nm;
+    FP.fa = fa;
+    FP.fs = fsx;
     if (o.surrogate > 0) {
         if ((rc = fl_sur_params(h, s, o, &FP.sur))) return rc;
         FP.sur.counters = dcnt + 12;
@@ -972,6 +1055,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     BP.with_boundary = o.with_boundary;
     BP.S = dS;
     BP.counters = dcnt + 10;
+    BP.fs = fsx;
     launch_self(E, BP, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[2], h->stream));
@@ -985,6 +1069,7 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     TP.A = A;
     TP.lda = lda;
     if (nm) TP.nm = *nm;
+    TP.fa = fa;
     if (dim == 2) {
         TP.npairs = P.n_edge;
         TP.pairs = (const int*)dv(o_ep);
@@ -997,6 +1082,11 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], h->stream));
 
+    if (det) {
+        launch_fix_to_double(fsx.lo, fsx.hi, from_hi, from_lo, T * 6, dS, h->stream);
+        launch_fix_to_double(fa.lo, fa.hi, from_hi, from_lo, a_elems, A, h->stream);
+        HIPCHK(hipGetLastError());
+    }
     if (before_scatter) {
         if ((rc = (*before_scatter)())) return rc;
         HIPCHK(hipGetLastError());
@@ -1019,8 +1109,12 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     HIPCHK(hipEventRecord(ev[4], h->stream));
     unsigned long long cnt[16];
     HIPCHK(hipMemcpyAsync(cnt, dcnt, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    int out_of_range = 0;
+    if (det) HIPCHK(hipMemcpyAsync(&out_of_range, dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipEventSynchronize(ev[4]));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if (out_of_range)
+        return fail(h, FL_ENONFINITE, "repeatable assembly: a contribution outside the range of its fixed-point scale");
     float ms = 0.f, ph[4] = {0, 0, 0, 0};
     HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[4]));
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ph[i], ev[i], ev[i + 1]));
@@ -1142,7 +1236,8 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
         if (h->dA) (void)hipFree(h->dA);
         h->dA = nullptr;
         h->A_cap = 0;
-        if (!fits(h, (double)A_bytes))
+        const double extra = o.deterministic ? 0.5 * (double)A_bytes : 0.0;  // coarse words
+        if (!fits(h, (double)A_bytes + extra))
             return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
     }
     Plan P;
@@ -1174,6 +1269,7 @@ int fl_assemble_batch(fl_handle* h, const double* s, int ns, const fl_opts* opts
     int rc = FL_OK;
     for (int j = 0; j < ns; ++j)
         if ((rc = check_s_opts(h, s[j], opts_in, &o))) return rc;
+    if (o.deterministic) return fail(h, FL_EINVAL, "the repeatable assembly is for fl_assemble");
     bool all_nodes = (o.dof_mode == FL_DOF_PAPER) && (s[0] < 0.5);
     for (int j = 1; j < ns; ++j)
         if (((o.dof_mode == FL_DOF_PAPER) && (s[j] < 0.5)) != all_nodes)

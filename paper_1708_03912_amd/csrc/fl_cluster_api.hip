@@ -558,6 +558,7 @@ int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t 
     if (rc) return rc;
     if (o.precision != FL_FP64) return cfail(h, FL_EINVAL, "the cluster near field is assembled in FP64");
     if (o.surrogate != 0) return cfail(h, FL_EINVAL, "the cluster near field takes the exact rules (surrogate = 0)");
+    if (o.deterministic) return cfail(h, FL_EINVAL, "the repeatable assembly is for fl_assemble");
     HIPCHK(hipSetDevice(h->device));
     if (h->stream) HIPCHK(hipStreamSynchronize(h->stream));
     hm_release(h);

@@ -173,6 +173,12 @@ struct fl_handle {
     float* dA32 = nullptr;
     size_t A32_cap = 0;
     unsigned long long* dcnt = nullptr;
+    // repeatable assembly: coarse words of A (int32, n x lda), both words of
+    // S (T x 6), the out-of-range flag
+    int* dAhi = nullptr;
+    size_t Ahi_cap = 0;
+    char* dSfix = nullptr;
+    size_t Sfix_cap = 0;
 
     // views into the plan buffer used after assembly
     fl::ElemDev E{};

@@ -102,6 +102,40 @@ __device__ __forceinline__ double* nm_slot(const NearMap& M, int i, int j) {
     return M.An + M.lpoff[p] + M.drow[i] + (long long)M.drow[j] * M.lsize[a];
 }
 
+// Repeatable accumulation (fl_opts.deterministic): a value v shared by
+// several kernels or workgroups is split exactly into v = hi 2^-F1 +
+// lo 2^-F2 (F2 = F1 + 52, hi = floor(v 2^F1), lo the rounded remainder)
+// and both parts are added with integer atomics, which do not depend on
+// order.  lo == nullptr: plain FP64 atomics.  flag[0] is set when a value
+// falls outside the range the scale was chosen for (never, given the
+// bound the host derives it from).
+struct FixAcc {
+    long long* lo = nullptr;   // same indexing as the FP64 target
+    int* hi = nullptr;
+    double to_hi = 0.0;        // 2^F1
+    double lo_per_hi = 0.0;    // 2^52
+    int* flag = nullptr;
+};
+
+__device__ __forceinline__ void fix_add(const FixAcc& F, long long idx, double v) {
+    const double th = v * F.to_hi;  // exact: a power of two
+    if (!(fabs(th) < 1073741824.0)) {
+        *F.flag = 1;
+        return;
+    }
+    const double fh = floor(th);
+    const long long lo = __double2ll_rn((th - fh) * F.lo_per_hi);  // th - fh exact, in [0, 1)
+    const int hi = (int)fh;
+    if (hi) atomicAdd(&F.hi[idx], hi);
+    if (lo) atomicAdd((unsigned long long*)&F.lo[idx], (unsigned long long)lo);
+}
+
+// v added to an FP64 accumulator, or to its fixed-point words
+__device__ __forceinline__ void acc_add(const FixAcc& F, double* D, long long idx, double v) {
+    if (F.lo) fix_add(F, idx, v);
+    else atomicAdd(&D[idx], v);
+}
+
 struct FarParams {
     int dim;
     int T;
@@ -124,6 +158,7 @@ struct FarParams {
     int mixed;              // 1: separated pairs evaluated in FP32
     SurParams sur;          // learned surrogate for the closest classes
     NearMap nm;             // cluster near field (nm.An set): output map, self-part mask
+    FixAcc fa, fs;          // repeatable accumulation of A and of S
 };
 
 struct TouchParams {
@@ -135,6 +170,7 @@ struct TouchParams {
     double* A;
     long long lda;
     NearMap nm;             // cluster near field (nm.An set): output map
+    FixAcc fa;              // repeatable accumulation of A
 };
 
 struct BndParams {
@@ -152,6 +188,7 @@ struct BndParams {
     int with_boundary;
     double* S;
     unsigned long long* counters;  // [0] touching, [1] separated
+    FixAcc fs;              // repeatable accumulation of S
 };
 
 // launch wrappers (fl_kernels.hip)
@@ -168,6 +205,9 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
                          const int* node2dof, const unsigned char* vloc, int nv, int dim,
                          const double* S, double mass, double* A, long long lda, hipStream_t st);
 // y = M x, M the P1 mass matrix on the DOFs
+// D[i] = hi[i] 2^-F1 + lo[i] 2^-F2 for i < n (D may alias lo: in place)
+void launch_fix_to_double(const long long* lo, const int* hi, double from_hi, double from_lo, long long n, double* D,
+                          hipStream_t st);
 // A[j][i] = A[i][j] for j > i (the assembly writes the upper triangle)
 void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st);
 // the same into the cluster near field; mass as above

@@ -36,8 +36,8 @@ __device__ __forceinline__ long long upper_index(int i, int j, long long lda) {
 
 // an off-diagonal contribution v to (i, j) and to (j, i): once in the upper
 // triangle, twice when i = j (two vertices folded onto one DOF)
-__device__ __forceinline__ void add_pair_upper(double* A, long long lda, int i, int j, double v) {
-    atomicAdd(&A[upper_index(i, j, lda)], i == j ? 2.0 * v : v);
+__device__ __forceinline__ void add_pair_upper(const FarParams& P, int i, int j, double v) {
+    acc_add(P.fa, P.A, upper_index(i, j, P.lda), i == j ? 2.0 * v : v);
 }
 
 __device__ __forceinline__ int sym3(int a, int b) {
@@ -731,7 +731,8 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     const int I0 = bi * BE, J0 = bj * BE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nVI = P.blk_ndof[bi], nVJ = P.blk_ndof[bj];
-    const bool direct = (nVI > MAXV) || (nVJ > MAXV);
+    const bool det = P.fa.lo != nullptr;  // repeatable: off-diagonal entries straight to the words
+    const bool direct = (nVI > MAXV) || (nVJ > MAXV) || det;
     const int T = P.T;
 
     for (int i = tid; i < BE * 3; i += 256) {
@@ -892,7 +893,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                             nm_add(P.nm, ga, gb, v);
                             nm_add(P.nm, gb, ga, v);
                         } else {
-                            add_pair_upper(P.A, P.lda, ga, gb, v);
+                            add_pair_upper(P, ga, gb, v);
                         }
                     }
                 }
@@ -901,8 +902,12 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     }
     if (okt) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m)
-            if (STacc[m] != 0.0) atomicAdd(&SJ[lane * 6 + m], STacc[m]);
+        for (int m = 0; m < 6; ++m) {
+            if (STacc[m] == 0.0) continue;
+            // four waves add into the same column sums: in LDS their order varies
+            if (det) fix_add(P.fs, (long long)Kt * 6 + m, STacc[m]);
+            else atomicAdd(&SJ[lane * 6 + m], STacc[m]);
+        }
     }
     __syncthreads();
     if (!direct) {
@@ -914,17 +919,17 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
             } else if (bi != bj) {
-                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
+                add_pair_upper(P, vI[rr], vJ[cc], v);
             } else if (vI[rr] <= vJ[cc]) {
                 // a diagonal tile's block holds both orientations already
-                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+                acc_add(P.fa, P.A, (long long)vI[rr] * P.lda + vJ[cc], v);
             }
         }
     }
     for (int i = tid; i < BE * 6; i += 256) {
         int K = I0 + i / 6, Kt2 = J0 + i / 6;
-        if (K < T && SI[i] != 0.0) atomicAdd(&P.S[(long long)K * 6 + i % 6], SI[i]);
-        if (Kt2 < T && SJ[i] != 0.0) atomicAdd(&P.S[(long long)Kt2 * 6 + i % 6], SJ[i]);
+        if (K < T && SI[i] != 0.0) acc_add(P.fs, P.S, (long long)K * 6 + i % 6, SI[i]);
+        if (Kt2 < T && SJ[i] != 0.0) acc_add(P.fs, P.S, (long long)Kt2 * 6 + i % 6, SJ[i]);
     }
     if constexpr (FARK > 0) {
         // far tile (bi != bj): every pair of its rows and columns, last class
@@ -967,7 +972,10 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     const int I0 = bi * BE, J0 = bj * BE;
     const int tid = threadIdx.x;
     const int nVI = P.blk_ndof[bi], nVJ = P.blk_ndof[bj];
-    const bool direct = (nVI > MAXV) || (nVJ > MAXV);
+    // repeatable assembly: every pair straight into the global words (the
+    // LDS sums would depend on the order of their FP64 atomics)
+    const bool det = P.fa.lo != nullptr;
+    const bool direct = (nVI > MAXV) || (nVJ > MAXV) || det;
     const int T = P.T;
 
     for (int i = tid; i < BE * 3; i += 256) {
@@ -1203,7 +1211,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                     } else {
                         const int ga = E.dof[sk][I0 + r], gb = E.dof[sl][J0 + l];
                         if (ga < 0 || gb < 0) continue;
-                        add_pair_upper(P.A, P.lda, ga, gb, v);
+                        add_pair_upper(P, ga, gb, v);
                     }
                 }
         }
@@ -1246,8 +1254,14 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
             const double fs = (CL && !nm_bit(nbits, r, l)) ? 0.0 : f;
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
-                if (SK[m] != 0.0 && fs != 0.0) atomicAdd(&SI[r * 6 + m], fs * SK[m]);
-                if (ST[m] != 0.0 && fs != 0.0) atomicAdd(&SJ[l * 6 + m], fs * ST[m]);
+                if (SK[m] == 0.0 && ST[m] == 0.0) continue;
+                if (det) {
+                    if (SK[m] != 0.0) fix_add(P.fs, (long long)(I0 + r) * 6 + m, fs * SK[m]);
+                    if (ST[m] != 0.0) fix_add(P.fs, (long long)(J0 + l) * 6 + m, fs * ST[m]);
+                } else if (fs != 0.0) {
+                    if (SK[m] != 0.0) atomicAdd(&SI[r * 6 + m], fs * SK[m]);
+                    if (ST[m] != 0.0) atomicAdd(&SJ[l * 6 + m], fs * ST[m]);
+                }
             }
             if (!direct) {
 #pragma unroll
@@ -1278,7 +1292,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                             nm_add(P.nm, ga, gb, v);
                             nm_add(P.nm, gb, ga, v);
                         } else {
-                            add_pair_upper(P.A, P.lda, ga, gb, v);
+                            add_pair_upper(P, ga, gb, v);
                         }
                     }
                 }
@@ -1295,17 +1309,17 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
             } else if (bi != bj) {
-                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
+                add_pair_upper(P, vI[rr], vJ[cc], v);
             } else if (vI[rr] <= vJ[cc]) {
                 // a diagonal tile's block holds both orientations already
-                atomicAdd(&P.A[(long long)vI[rr] * P.lda + vJ[cc]], v);
+                acc_add(P.fa, P.A, (long long)vI[rr] * P.lda + vJ[cc], v);
             }
         }
     }
     for (int i = tid; i < BE * 6; i += 256) {
         int K = I0 + i / 6, Kt2 = J0 + i / 6;
-        if (K < T && SI[i] != 0.0) atomicAdd(&P.S[(long long)K * 6 + i % 6], SI[i]);
-        if (Kt2 < T && SJ[i] != 0.0) atomicAdd(&P.S[(long long)Kt2 * 6 + i % 6], SJ[i]);
+        if (K < T && SI[i] != 0.0) acc_add(P.fs, P.S, (long long)K * 6 + i % 6, SI[i]);
+        if (Kt2 < T && SJ[i] != 0.0) acc_add(P.fs, P.S, (long long)Kt2 * 6 + i % 6, SJ[i]);
     }
     if (tid <= P.ncls && ccnt[tid]) atomicAdd(&P.cls_count[tid], (unsigned long long)ccnt[tid]);
 }
@@ -1337,13 +1351,18 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
 // vertex), so that their rounding error stays relative to the pair's
 // distance; the sums of a pair are formed in FP32 and added in FP64.
 // CL = 1: the cluster near field, as in far_kernel (the potentials take only
-// the pairs of near anchor leaves).
-template <int KO, int MIX, int W, int CL>
+// the pairs of near anchor leaves).  DET = 1 (repeatable assembly): the
+// block is summed in LDS as the fixed-point words of the global
+// accumulation (integer atomics: any order gives the same words) and its
+// words are added to A's words; the other sums of the kernel are fixed-order
+// reductions already.
+template <int KO, int MIX, int W, int CL, int DET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void far2_kernel(ElemDev E, FarParams P) {
     constexpr int Q = KO * KO;
     constexpr int LS = MAXV + 1;  // row stride of L; row / column MAXV: vertices without a DOF
     __shared__ __align__(16) double pw[MIX ? 2 : 768];
-    __shared__ __align__(16) double L[LS * LS];
+    __shared__ __align__(16) double L[LS * LS];      // DET: the int64 remainder words
+    __shared__ int Lhi[DET ? LS * LS : 1];            // DET: the int32 coarse words
     using XT = std::conditional_t<MIX, float, double>;
     __shared__ __align__(16) XT sX[BE][2 * Q];       // rows' mapped points, (x, y) per point
     __shared__ double sMK[BE];                      // |K| of the rows (0 past T)
@@ -1365,6 +1384,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
 
     if constexpr (!MIX) load_pow_tables(pw);
     for (int i = tid; i < LS * LS; i += 256) L[i] = 0.0;
+    if constexpr (DET)
+        for (int i = tid; i < LS * LS; i += 256) Lhi[i] = 0;
     if (!direct)
         for (int i = tid; i < MAXV; i += 256) {
             vI[i] = P.blk_dofs[(long long)bi * MAXV + i];
@@ -1436,7 +1457,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
     __syncthreads();
 
     for (int r = wave; r < BE; r += 4) {
-        if (I0 + r >= T) break;
+        if (I0 + r >= T) break;  // (rows past T have |K| = 0 in sMK)
         double xp[2 * Q];
 #pragma unroll
         for (int c = 0; c < 2 * Q; ++c) xp[c] = sX[r][c];
@@ -1529,8 +1550,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
             if (!direct) {
                 const int ro = sRO[r][a];
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    atomicAdd((double*)((char*)L + ro + cbo[b]), -f * o[b]);
+                for (int b = 0; b < 3; ++b) {
+                    if constexpr (DET) {
+                        const int idx = (ro + cbo[b]) >> 3;
+                        const double th = -f * o[b] * P.fa.to_hi;
+                        if (!(fabs(th) < 1073741824.0)) {
+                            *P.fa.flag = 1;
+                            continue;
+                        }
+                        const double fh = floor(th);
+                        const long long lo = __double2ll_rn((th - fh) * P.fa.lo_per_hi);
+                        if (fh != 0.0) atomicAdd(&Lhi[idx], (int)fh);
+                        if (lo) atomicAdd((unsigned long long*)&L[idx], (unsigned long long)lo);
+                    } else {
+                        atomicAdd((double*)((char*)L + ro + cbo[b]), -f * o[b]);
+                    }
+                }
             } else if (okt) {
                 const int ga = E.dof[a][I0 + r];
 #pragma unroll
@@ -1542,7 +1577,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                         nm_add(P.nm, ga, gb, v);
                         nm_add(P.nm, gb, ga, v);
                     } else {
-                        add_pair_upper(P.A, P.lda, ga, gb, v);
+                        add_pair_upper(P, ga, gb, v);
                     }
                 }
             }
@@ -1556,10 +1591,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         double v = 0.0;
 #pragma unroll
         for (int p = 0; p < Q; ++p) v += c_R.tri[off + p][6 + m] * sPhi[r][p];
-        if (v != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], v);
+        if (v != 0.0) acc_add(P.fs, P.S, (long long)K * 6 + m, v);
     }
     // off-diagonal block and its mirror into A
-    if (!direct) {
+    if (DET && !direct) {
+        // the words go to A's words (same scale), doubled on a folded diagonal
+        const long long* Llo = (const long long*)L;
+        for (int i = tid; i < nVI * nVJ; i += 256) {
+            const int rr = i / nVJ, cc = i - rr * nVJ;
+            const long long lo = Llo[rr * LS + cc];
+            const int hi = Lhi[rr * LS + cc];
+            if (lo == 0 && hi == 0) continue;
+            const int gi = vI[rr], gj = vJ[cc];
+            const long long k = gi == gj ? 2 : 1;
+            const long long at = upper_index(gi, gj, P.lda);
+            if (hi) atomicAdd(&P.fa.hi[at], (int)(k * hi));
+            if (lo) atomicAdd((unsigned long long*)&P.fa.lo[at], (unsigned long long)(k * lo));
+        }
+    } else if (!direct) {
         for (int i = tid; i < nVI * nVJ; i += 256) {
             const int rr = i / nVJ, cc = i - rr * nVJ;
             const double v = L[rr * LS + cc];
@@ -1568,7 +1617,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 nm_add(P.nm, vJ[cc], vI[rr], v);
             } else {
-                add_pair_upper(P.A, P.lda, vI[rr], vJ[cc], v);
+                add_pair_upper(P, vI[rr], vJ[cc], v);
             }
         }
     }
@@ -1594,7 +1643,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         const double* stage = L;
         const double v = ((stage[(0 * 64 + l) * 6 + m] + stage[(1 * 64 + l) * 6 + m]) +
                           stage[(2 * 64 + l) * 6 + m]) + stage[(3 * 64 + l) * 6 + m];
-        if (v != 0.0) atomicAdd(&P.S[(long long)Ktt * 6 + m], v);
+        if (v != 0.0) acc_add(P.fs, P.S, (long long)Ktt * 6 + m, v);
     }
     if (tid == 0)
         atomicAdd(&P.cls_count[P.ncls], (unsigned long long)(min(BE, T - I0) * (long long)min(BE, T - J0)));
@@ -1634,10 +1683,19 @@ void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_
     } while (0)
     if (P.dim == 2 && fark <= 2) {
         const bool w = E.w != nullptr;
-#define FL_FAR2(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W, 0>), grid, block, 0, st, E, P)
+#define FL_FAR2(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W, 0, 0>), grid, block, 0, st, E, P)
+#define FL_FAR2D(K, MX, W) hipLaunchKernelGGL((far2_kernel<K, MX, W, 0, 1>), grid, block, 0, st, E, P)
         if (P.nm.An) {
-            if (fark == 1) hipLaunchKernelGGL((far2_kernel<1, 0, 0, 1>), grid, block, 0, st, E, P);
-            else hipLaunchKernelGGL((far2_kernel<2, 0, 0, 1>), grid, block, 0, st, E, P);
+            if (fark == 1) hipLaunchKernelGGL((far2_kernel<1, 0, 0, 1, 0>), grid, block, 0, st, E, P);
+            else hipLaunchKernelGGL((far2_kernel<2, 0, 0, 1, 0>), grid, block, 0, st, E, P);
+        } else if (P.fa.lo) {
+            if (fark == 1) {
+                if (P.mixed) { if (w) FL_FAR2D(1, 1, 1); else FL_FAR2D(1, 1, 0); }
+                else { if (w) FL_FAR2D(1, 0, 1); else FL_FAR2D(1, 0, 0); }
+            } else {
+                if (P.mixed) { if (w) FL_FAR2D(2, 1, 1); else FL_FAR2D(2, 1, 0); }
+                else { if (w) FL_FAR2D(2, 0, 1); else FL_FAR2D(2, 0, 0); }
+            }
         } else if (fark == 1) {
             if (P.mixed) { if (w) FL_FAR2(1, 1, 1); else FL_FAR2(1, 1, 0); }
             else { if (w) FL_FAR2(1, 0, 1); else FL_FAR2(1, 0, 0); }
@@ -1646,6 +1704,7 @@ void launch_far_tiles(const ElemDev& E, const FarParams& P, int fark, hipStream_
             else { if (w) FL_FAR2(2, 0, 1); else FL_FAR2(2, 0, 0); }
         }
 #undef FL_FAR2
+#undef FL_FAR2D
     } else if (P.dim == 2) {
         switch (fark) {
             case 1: FL_FAR_CASE(2, 1); break;
@@ -1948,7 +2007,11 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
     }
     const double wk = E.w ? E.w[K] : 1.0;
     for (int m = 0; m < 6; ++m)
-        if (acc[m] != 0.0 && wk != 0.0) atomicAdd(&P.S[(long long)K * 6 + m], wk * acc[m]);
+        // (for s >= 1/2 the boundary term of a boundary vertex diverges; those
+        // entries never reach A, and the words of the repeatable assembly
+        // take finite values only)
+        if (acc[m] != 0.0 && wk != 0.0 && (!P.fs.lo || isfinite(acc[m])))
+            acc_add(P.fs, P.S, (long long)K * 6 + m, wk * acc[m]);
 }
 
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st) {
@@ -1977,7 +2040,7 @@ __device__ __forceinline__ void edge_acc(const double* E, const double* ap, cons
 // near field (every touching pair lies in a near block)
 __device__ __forceinline__ void touch_add(const TouchParams& P, int i, int j, double v) {
     if (P.nm.An) nm_add(P.nm, i, j, v);
-    else if (i <= j) atomicAdd(&P.A[(long long)i * P.lda + j], v);  // (j, i) visits the same value
+    else if (i <= j) acc_add(P.fa, P.A, (long long)i * P.lda + j, v);  // (j, i) visits the same value
 }
 
 // Triangles sharing an edge: K = (q0,q1,a), Kt = (q0,q1,b), q0 < q1 by
@@ -2209,6 +2272,24 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
     dim3 grid((nv + 255) / 256), block(256);
     hipLaunchKernelGGL(scatter_self_kernel, grid, block, 0, st, E, v2c_ptr, v2c_idx, node2dof, vloc,
                        nv, dim, S, mass, A, lda);
+}
+
+__global__ __launch_bounds__(256) void fix_to_double_kernel(const long long* lo, const int* hi, double from_hi,
+                                                            double from_lo, long long n, double* D) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long l = lo[i];
+        const int h = hi[i];
+        D[i] = (double)h * from_hi + (double)l * from_lo;
+    }
+}
+
+void launch_fix_to_double(const long long* lo, const int* hi, double from_hi, double from_lo, long long n, double* D,
+                          hipStream_t st) {
+    if (n <= 0) return;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fix_to_double_kernel, dim3((unsigned)blocks), dim3(256), 0, st, lo, hi, from_hi, from_lo, n, D);
 }
 
 // Lower triangle from the upper one: workgroup (J, I), I <= J, copies the

@@ -49,7 +49,8 @@ class FlOpts(C.Structure):
                 ("theta", C.c_double * FL_MAX_CLASSES),
                 ("k_far", C.c_int * (FL_MAX_CLASSES + 1)),
                 ("k_far_bnd", C.c_int * (FL_MAX_CLASSES + 1)), ("precision", C.c_int),
-                ("surrogate", C.c_int), ("sur_tol", C.c_double), ("mass_shift", C.c_double)]
+                ("surrogate", C.c_int), ("sur_tol", C.c_double), ("mass_shift", C.c_double),
+                ("deterministic", C.c_int)]
 
 
 class FlStats(C.Structure):
@@ -167,8 +168,10 @@ def default_train_opts(**kw) -> FlTrainOpts:
 
 def make_opts(k_touch=None, k_touch_bnd=None, theta=None, k_far=None, k_far_bnd=None,
               dof_mode=None, with_boundary=None, precision=None, surrogate=None, sur_tol=None,
-              mass_shift=None) -> FlOpts:
+              mass_shift=None, deterministic=None) -> FlOpts:
     o = default_opts()
+    if deterministic is not None:
+        o.deterministic = int(bool(deterministic))
     if mass_shift is not None:
         o.mass_shift = float(mass_shift)
     if surrogate is not None:

@@ -44,11 +44,11 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "fraclap.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fl_opts), offsetof(fl_opts, theta),
          offsetof(fl_opts, k_far_bnd), sizeof(fl_stats_t), offsetof(fl_stats_t, last_relres),
          sizeof(fl_tune_entry), offsetof(fl_tune_entry, gbps), offsetof(fl_opts, sur_tol),
          offsetof(fl_stats_t, pairs_fallback), sizeof(fl_train_opts), offsetof(fl_train_opts, seed),
-         (size_t)FL_SUR_BLOB, offsetof(fl_stats_t, cg_launched));
+         (size_t)FL_SUR_BLOB, offsetof(fl_stats_t, cg_launched), offsetof(fl_opts, deterministic));
   return 0; }
 """)
     exe = tmp_path / "lay"
@@ -58,7 +58,7 @@ int main(void) {
                     C.sizeof(F.FlStats), F.FlStats.last_relres.offset,
                     C.sizeof(F.FlTuneEntry), F.FlTuneEntry.gbps.offset, F.FlOpts.sur_tol.offset,
                     F.FlStats.pairs_fallback.offset, C.sizeof(F.FlTrainOpts), F.FlTrainOpts.seed.offset, F.SUR_BLOB,
-                    F.FlStats.cg_launched.offset]
+                    F.FlStats.cg_launched.offset, F.FlOpts.deterministic.offset]
 
 
 def test_surrogate_constants_match_generator():
