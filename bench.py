@@ -179,6 +179,38 @@ def dense_leg(args, mesh, svals, dof_mode, rtol, steps, warmup):
                 mean=mean, T=T, B=B, opts=opts)
 
 
+def repeatable_assembly(h, mesh, svals, dof_mode):
+    """fl_opts.deterministic = 1 on the same workload, after the timed
+    steps (not part of `value`): assembly time per s, twice, and whether the
+    two matrices agree bit for bit (compared on the device through a 64-bit
+    sum of the words of the upper triangle and a second sum weighted by a
+    fixed pattern)."""
+    import torch
+    from paper_1708_03912_amd import fraclap as F
+    out = {}
+    od = F.make_opts(dof_mode=dof_mode, deterministic=1)
+    for s in svals:
+        sums, ts = [], []
+        for _ in range(2):
+            h.set_mesh(mesh)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.assemble(s, od)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            A = h.matrix_view()
+            acc = [0, 0]
+            for r0 in range(0, h.n, 4096):
+                w = A[r0:r0 + 4096].contiguous().view(torch.int64)
+                acc[0] += int(w.sum())
+                acc[1] += int((w * (torch.arange(w.shape[1], device=w.device, dtype=torch.int64) % 7 + 1)).sum())
+            sums.append(tuple(acc))
+        st = h.stats()
+        out[str(s)] = {"assemble_ms": [round(t, 2) for t in ts], "device_ms": round(st.t_assemble_ms, 2),
+                       "separated_ms": round(st.t_far_ms, 2), "bitwise_equal": sums[0] == sums[1]}
+    return out
+
+
 def matvec_rate(h, reps=10):
     """fl_matvec (symmetric FP64 product from the upper triangle) timed with
     events on the library's stream (torch's current stream)."""
@@ -281,6 +313,7 @@ def main():
     n = res[svals[-1]]["n"]
     roof, other = rooflines(D, svals, cache_resident=n * n * 8 < 256e6)
     mv = matvec_rate(D["h"])
+    det = repeatable_assembly(D["h"], mesh, svals, dof_mode)
     wl = ("d=2 unit disk, seeded jittered-Delaunay quasi-uniform mesh T=%d B=%d, %s DOFs (n=%d), s in "
           "{0.25,0.75}, f=1: mesh ingest + FP64 assembly (all element pairs, boundary term) + load vector + "
           "Jacobi-PCG to %g + energy error, per s" % (T, B, dof_mode, n, rtol))
@@ -300,7 +333,7 @@ def main():
            "phase_ms": {str(s): {k: round(res[s][k], 4) for k in ("t_plan", "t_far", "t_self", "t_touch",
                                                                   "t_scatter", "t_solve", "t_cgk")}
                         for s in svals},
-           "roofline": roof, "roofline_other": other}
+           "roofline": roof, "roofline_other": other, "repeatable_assembly": det}
     print(json.dumps({"progress": "dense step timed", "ms_per_step": out["ms_per_step"]}), file=sys.stderr,
           flush=True)
     if not args.no_mixed:
