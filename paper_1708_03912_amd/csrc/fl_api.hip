@@ -958,7 +958,10 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
     gauss_jacobi01(2, 0.0, 1.0 - 2.0 * s, R.r1_x, R.r1_w);
     set_pow_tables(R, -(0.5 * dim + s));
     HIPCHK(upload_rules(R, h->stream));
-    launch_zero(A, a_elems, h->stream);
+    // the upper triangle only (the transpose writes the lower one at the end),
+    // unless the buffer has padding rows past n (the batched matrices)
+    if (A && a_elems == n * lda) launch_zero_upper(A, lda, n, h->stream);
+    else launch_zero(A, a_elems, h->stream);
     launch_zero(dS, T * 6, h->stream);
     launch_zero((double*)dcnt, 32, h->stream);
     // repeatable accumulation: A's FP64 buffer holds the int64 remainders

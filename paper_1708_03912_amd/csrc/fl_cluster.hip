@@ -211,10 +211,24 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
                 for (int b = 0; b < 36; ++b) acc = fma(kr[b], __shfl(xv, b, 64), acc);
             }
         } else if (a < H.M) {
+            // 16 loads of the block column in flight before their products
+            // (the sum keeps the order b = 0, 1, ...)
+            const int M = H.M;
             for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
-                const double* Kp = H.Kb + p * H.M * H.M;
-                const double* xt = H.xh + (long long)H.fdst[p] * H.M;
-                for (int b = 0; b < H.M; ++b) acc = fma(Kp[b * H.M + a], xt[b], acc);
+                const double* Kp = H.Kb + p * M * M;
+                const double* xt = H.xh + (long long)H.fdst[p] * M;
+                int b = 0;
+                for (; b + 16 <= M; b += 16) {
+                    double kr[16], xr[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        kr[k] = Kp[(b + k) * M + a];
+                        xr[k] = xt[b + k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) acc = fma(kr[k], xr[k], acc);
+                }
+                for (; b < M; ++b) acc = fma(Kp[b * M + a], xt[b], acc);
             }
         }
         red[g][lane] = acc;

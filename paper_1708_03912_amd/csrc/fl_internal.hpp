@@ -208,6 +208,8 @@ void launch_scatter_self(const ElemDev& E, const int* v2c_ptr, const int* v2c_id
 // D[i] = hi[i] 2^-F1 + lo[i] 2^-F2 for i < n (D may alias lo: in place)
 void launch_fix_to_double(const long long* lo, const int* hi, double from_hi, double from_lo, long long n, double* D,
                           hipStream_t st);
+// zero row i from column i on, i < n (the upper triangle and the padding)
+void launch_zero_upper(double* A, long long lda, long long n, hipStream_t st);
 // A[j][i] = A[i][j] for j > i (the assembly writes the upper triangle)
 void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st);
 // the same into the cluster near field; mass as above

@@ -2313,6 +2313,22 @@ __global__ __launch_bounds__(256) void mirror_lower_kernel(double* A, long long 
     }
 }
 
+// zero the upper triangle and the padding columns of every row (row i:
+// columns i .. lda-1; one workgroup per row at a time); the transpose writes
+// the strictly lower triangle
+__global__ __launch_bounds__(256) void zero_upper_kernel(double* A, long long lda, int n) {
+    for (long long i = blockIdx.x; i < n; i += gridDim.x) {
+        double* row = A + i * lda;
+        for (long long j = i + threadIdx.x; j < lda; j += 256) row[j] = 0.0;
+    }
+}
+
+void launch_zero_upper(double* A, long long lda, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned blocks = (unsigned)(n < 65536 ? n : 65536);
+    hipLaunchKernelGGL(zero_upper_kernel, dim3(blocks), dim3(256), 0, st, A, lda, (int)n);
+}
+
 void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st) {
     if (n <= 1) return;
     const unsigned nt = (unsigned)((n + 63) / 64);

@@ -41,6 +41,7 @@ def _columns(h, n):
 
 CASES = {
     "disk_interior": (lambda: M.disk_for_cells(1200, seed=2), 0.75, "paper", True, 5, 2.0, 16),
+    "disk_m8": (lambda: M.disk_for_cells(1500, seed=8), 0.4, "interior", True, 8, 2.0, 24),
     "disk_all_nodes": (lambda: M.disk_for_cells(900, seed=5), 0.3, "paper", True, 4, 1.5, 12),
     "disk_regional": (lambda: M.disk_for_cells(900, seed=5), 0.6, "interior", False, 4, 2.0, 16),
     "interval": (lambda: M.interval(256), 0.25, "paper", True, 6, 1.0, 8),
