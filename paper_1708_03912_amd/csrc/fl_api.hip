@@ -195,9 +195,11 @@ const RuleTables& base_rules() {
     static RuleTables R = [] {
         RuleTables T;
         std::memset(&T, 0, sizeof(T));
-        // kernel-power tables: 1 / m_i with m_i = 1 + (i + 1/2) / 256, the
-        // midpoint of the mantissas whose top 8 bits are i
-        for (int i = 0; i < 256; ++i) T.pw_inv[i] = (double)(1.0L / (1.0L + ((long double)i + 0.5L) / 256.0L));
+        // kernel-power tables: 2 / m_i with m_i = 1 + (i + 1/2) / 256, the
+        // midpoint of the mantissas whose top 8 bits are i (the kernels take
+        // the mantissa as m / 2 in [1/2, 1), v_frexp_mant_f64, so that
+        // (m / 2)(2 / m_i) is exactly m / m_i)
+        for (int i = 0; i < 256; ++i) T.pw_inv[i] = (double)(2.0L / (1.0L + ((long double)i + 0.5L) / 256.0L));
         for (int k = 1; k <= 16; ++k) {
             gauss_jacobi01(k, 0.0, 0.0, T.gl_x + gl_off(k), T.gl_w + gl_off(k));
             gauss_jacobi01(k, 1.0, 0.0, T.gj_x + gl_off(k), T.gj_w + gl_off(k));

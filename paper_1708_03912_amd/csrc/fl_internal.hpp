@@ -28,9 +28,10 @@ struct RuleTables {
     double r1_x[2], r1_w[2];            // 2-point rule, weight r^{1-2s} on [0,1]
     float trif[TRI_TAB][12];            // FP32 copies for the mixed-precision path
     float segf[36][8];
-    // kernel power r2^pe by tables (kpow_tab): 2^(-i/256), 2^(pe i/256),
-    // 2^(pe n) for n = -128..127, and the binomial coefficients C(pe, k),
-    // k = 0..5 (pe of the current assembly)
+    // kernel power r2^pe by tables (kpow_tab): 2 / m_i and m_i^pe for the
+    // 256 mantissa bins (m_i their midpoints), 2^(pe n) for n = -128..127,
+    // and the binomial coefficients C(pe, k), k = 0..5 (pe of the current
+    // assembly)
     double pw_inv[256], pw_fr[256], pw_ex[256], pw_c[8];
 };
 // fill the pe-dependent parts of the kernel-power tables

@@ -187,7 +187,7 @@ __device__ __forceinline__ void kpow_tab_batch(const KPowTab& kp, const double (
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         hi[p] = __double2hiint(r2[p]);
-        m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2[p]));
+        m[p] = __builtin_amdgcn_frexp_mant(r2[p]);  // mantissa / 2 (the table holds 2 / m_i)
     }
     double2 fr[N];
     double ex[N];
@@ -226,7 +226,7 @@ __device__ __forceinline__ void kpow_tab_issue(const KPowTab& kp, const double (
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         hi[p] = __double2hiint(r2[p]);
-        st.m[p] = __hiloint2double((hi[p] & 0x000FFFFF) | 0x3FF00000, __double2loint(r2[p]));
+        st.m[p] = __builtin_amdgcn_frexp_mant(r2[p]);  // mantissa / 2 (the table holds 2 / m_i)
     }
 #pragma unroll
     for (int p = 0; p < N; ++p) {

@@ -72,11 +72,11 @@ __host__ __device__ inline double kpow(double r2, double pe) {
     return ldexp(p, (int)kf);
 }
 
-// Kernel power r2^pe by tables held in LDS (pw: pairs (1/m_i, m_i^pe), m_i = 1 + (i +
+// Kernel power r2^pe by tables held in LDS (pw: pairs (2/m_i, m_i^pe), m_i = 1 + (i +
 // 1/2)/256, then 2^(pe n), n = -128..127; 768 doubles) with the
-// coefficients C(pe, k): r2 = 2^n m with m in [1, 2) read off the bits (n
-// from the exponent field, i = the top 8 mantissa bits), the remaining
-// factor m / m_i = 1 + t (|t| <= 1/512) is raised to pe by its degree-5
+// coefficients C(pe, k): r2 = 2^n m with m in [1, 2) (n from the exponent
+// field, i = the top 8 mantissa bits, m / 2 from v_frexp_mant_f64), the
+// remaining factor m / m_i = 1 + t (|t| <= 1/512) is raised to pe by its degree-5
 // Taylor polynomial.  No transcendental and ~9 FP64 operations instead of
 // ~38; relative error below 1e-15 for r2 in [2^-128, 2^128) (callers keep
 // their squared distances inside).
@@ -88,9 +88,9 @@ struct KPowTab {
         const int hi = (int)(bits >> 32);
         const int n = (hi >> 20) - 895;  // biased exponent - 1023 + 128
         const int i = (hi >> 12) & 255;
-        const double m = __longlong_as_double((bits & 0x000FFFFFFFFFFFFFLL) | 0x3FF0000000000000LL);
-        const double2 f = ((const double2*)pw)[i];  // 1/m_i, m_i^pe
-        const double t = fma(m, f.x, -1.0);
+        const double mh = __builtin_amdgcn_frexp_mant(r2);  // mantissa / 2, in [1/2, 1)
+        const double2 f = ((const double2*)pw)[i];          // 2/m_i, m_i^pe
+        const double t = fma(mh, f.x, -1.0);                 // = m / m_i - 1 exactly as with m, 1/m_i
         double p = fma(c5, t, c4);
         p = fma(p, t, c3);
         p = fma(p, t, c2);
