@@ -4,10 +4,12 @@
 Default workload (the paper's 2D test domain, Sec. 7, at the largest size
 that one GPU holds): unit disk, seeded jittered-Delaunay quasi-uniform mesh
 of 199,452 triangles, 99,205 interior DOFs (the FP64 matrix takes 80 GB),
-s in {0.25, 0.75}, f = 1.  One step = for each s: mesh ingest
-(fl_set_mesh), FP64 assembly of A^s (all element pairs and
-element/boundary-facet pairs), load vector, Jacobi-PCG to
-||r|| <= 1e-10 ||b||, energy-norm error against the closed-form solution.
+s in {0.25, 0.75}, f = 1.  One step = mesh ingest (fl_set_mesh), then for
+each s: FP64 assembly of A^s (all element pairs and element/boundary-facet
+pairs; the s-independent plan -- element order, DOF map, pair classes,
+tiles -- is made by the first assembly of the step and reused by the
+second), load vector, Jacobi-PCG to ||r|| <= 1e-10 ||b||, energy-norm
+error against the closed-form solution.
 Everything runs in libfraclap.so; inputs are resident before the timed
 region.  ``--workload disk8k`` runs the ~7.9k-triangle disk instead.
 
@@ -129,8 +131,9 @@ def ball_fu(s):
 
 
 def dense_leg(args, mesh, svals, dof_mode, rtol, steps, warmup):
-    """The dense FP64 path, timed over whole steps.  One step = for each s:
-    mesh ingest (fl_set_mesh), FP64 assembly, load vector (f = 1),
+    """The dense FP64 path, timed over whole steps.  One step = mesh ingest
+    (fl_set_mesh), then for each s: FP64 assembly (planned once per step),
+    load vector (f = 1),
     Jacobi-PCG to ||r|| <= rtol ||b||, energy-norm error against the
     closed form.  Returns the timing, per-s results, the roofline inputs
     and the handle (holding A for the last s) with the solutions."""
@@ -142,8 +145,8 @@ def dense_leg(args, mesh, svals, dof_mode, rtol, steps, warmup):
     bufs, result = {}, {}
 
     def step():
+        h.set_mesh(mesh)
         for s in svals:
-            h.set_mesh(mesh)
             n = h.assemble(s, opts)
             if s not in bufs or bufs[s][0].numel() != n:
                 bufs[s] = (torch.empty(n, dtype=torch.float64, device="cuda"),
@@ -315,8 +318,8 @@ def main():
     mv = matvec_rate(D["h"])
     det = repeatable_assembly(D["h"], mesh, svals, dof_mode)
     wl = ("d=2 unit disk, seeded jittered-Delaunay quasi-uniform mesh T=%d B=%d, %s DOFs (n=%d), s in "
-          "{0.25,0.75}, f=1: mesh ingest + FP64 assembly (all element pairs, boundary term) + load vector + "
-          "Jacobi-PCG to %g + energy error, per s" % (T, B, dof_mode, n, rtol))
+          "{0.25,0.75}, f=1: mesh ingest and the s-independent assembly plan once per step, then per s: FP64 "
+          "assembly (all element pairs, boundary term) + load vector + Jacobi-PCG to %g + energy error" % (T, B, dof_mode, n, rtol))
     out = {"metric": METRIC, "value": round(value, 1), "unit": "element-pair quadratures/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(D["ms_per_step"], 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

@@ -81,6 +81,7 @@ void free_buffers(fl_handle* h) {
     if (B.ws) (void)hipFree(B.ws);
     if (B.hflag) (void)hipHostFree(B.hflag);
     h->B = fl_batch{};
+    h->pc.valid = false;
     h->plan = h->pin = nullptr;
     h->dA = h->dS = nullptr;
     h->dcnt = nullptr;
@@ -318,6 +319,7 @@ int fl_set_mesh(fl_handle* h, int dim, int64_t nv, const double* verts, int64_t 
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     reset_assembly(h);
+    h->pc.valid = false;
     h->dim = 0;
     h->sym_T = 0;
     h->sym_order = 1;
@@ -417,6 +419,7 @@ int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const in
     if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     reset_assembly(h);
+    h->pc.valid = false;
     h->sym_pre.clear();
     h->sym_rot.clear();
     if (order == 1 && ncells_sector == 0) {
@@ -495,6 +498,7 @@ void set_dof_map(fl_handle* h, bool all_nodes) {
 // block pairs to tile (all pairs bi <= bj when null).
 int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const TileSelect* sel) {
     auto t0 = std::chrono::steady_clock::now();
+    h->pc.valid = false;  // the plan buffer is rewritten
     int rc = FL_OK;
     const int dim = h->dim, nper = dim + 1;
     const int64_t T = h->nc, nv = h->nv;
@@ -1221,6 +1225,67 @@ void set_pow_tables(RuleTables& R, double pe) {
 
 extern "C" {
 
+namespace {
+// The plan inputs besides the mesh: the DOF set and the distance classes
+// (the tiles' far / near split); the orders enter only the assembly runs.
+bool plan_key_equal(const fl_plan_cache& c, bool all_nodes, const fl_opts& o) {
+    if (c.all_nodes != all_nodes || c.n_classes != o.n_classes) return false;
+    if (c.use_far != (o.k_far[o.n_classes] <= 4)) return false;
+    for (int m = 0; m < o.n_classes; ++m)
+        if (c.theta[m] != o.theta[m]) return false;
+    return true;
+}
+
+void plan_store(fl_handle* h, bool all_nodes, const fl_opts& o, const Plan& P) {
+    fl_plan_cache& c = h->pc;
+    c.all_nodes = all_nodes;
+    c.n_classes = o.n_classes;
+    for (int m = 0; m < FL_MAX_CLASSES; ++m) c.theta[m] = m < o.n_classes ? o.theta[m] : 0.0;
+    c.use_far = o.k_far[o.n_classes] <= 4;
+    c.P = P;
+    c.E = h->E;
+    c.v2c_ptr = h->d_v2c_ptr;
+    c.v2c_idx = h->d_v2c_idx;
+    c.node2dof = h->d_node2dof;
+    c.dof_node = h->d_dof_node;
+    c.vloc = h->d_vloc;
+    c.sc_ptr = h->d_sc_ptr;
+    c.sc_idx = h->d_sc_idx;
+    c.sc_map = h->d_sc_map;
+    c.sc_vloc = h->d_sc_vloc;
+    c.sc_rows = h->sc_rows;
+    c.meas = h->d_meas;
+    c.valid = true;
+}
+
+// The kept plan when its inputs match (the handle's views restored,
+// t_plan_ms = 0), else a new one, kept for the next call.
+int plan_or_reuse(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P) {
+    const fl_plan_cache& c = h->pc;
+    if (c.valid && plan_key_equal(c, all_nodes, o)) {
+        set_dof_map(h, all_nodes);  // (host copy; other calls may have set another)
+        P = c.P;
+        P.t_plan_ms = 0.0;
+        h->E = c.E;
+        h->d_v2c_ptr = c.v2c_ptr;
+        h->d_v2c_idx = c.v2c_idx;
+        h->d_node2dof = c.node2dof;
+        h->d_dof_node = c.dof_node;
+        h->d_vloc = c.vloc;
+        h->d_sc_ptr = c.sc_ptr;
+        h->d_sc_idx = c.sc_idx;
+        h->d_sc_map = c.sc_map;
+        h->d_sc_vloc = c.sc_vloc;
+        h->sc_rows = c.sc_rows;
+        h->d_meas = c.meas;
+        return FL_OK;
+    }
+    const int rc = plan_assembly(h, all_nodes, o, P, nullptr);
+    if (rc == FL_OK) plan_store(h, all_nodes, o, P);
+    return rc;
+}
+}  // namespace
+
 int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) {
     if (!h) return FL_EINVAL;
     if (h->dim == 0) return fail(h, FL_ESTATE, "fl_set_mesh must be called first");
@@ -1246,7 +1311,7 @@ int fl_assemble(fl_handle* h, double s, const fl_opts* opts_in, int64_t* n_out) 
             return fail(h, FL_ENOMEM, "matrix of " + std::to_string(n) + " DOFs does not fit in device memory");
     }
     Plan P;
-    if ((rc = plan_assembly(h, all_nodes, o, P, nullptr))) return rc;
+    if ((rc = plan_or_reuse(h, all_nodes, o, P))) return rc;
     if ((rc = ensure_dev(h, &h->dA, &h->A_cap, A_bytes))) return rc;
     float* A32 = nullptr;
     if (o.precision == FL_MIXED) {
@@ -1298,7 +1363,7 @@ int fl_assemble_batch(fl_handle* h, const double* s, int ns, const fl_opts* opts
             return fail(h, FL_ENOMEM, "batch of " + std::to_string(ns) + " matrices does not fit in device memory");
     }
     Plan P;
-    if ((rc = plan_assembly(h, all_nodes, o, P, nullptr))) return rc;
+    if ((rc = plan_or_reuse(h, all_nodes, o, P))) return rc;
     if ((rc = ensure_dev(h, &B.A64, &B.A64_cap, bytes))) return rc;
     fl_stats_t S{};
     for (int j = 0; j < ns; ++j) {

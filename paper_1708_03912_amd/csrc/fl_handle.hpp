@@ -134,6 +134,45 @@ struct fl_hm {
     std::vector<void*> bufs;        // every device allocation above
 };
 
+namespace fl {
+// Result of the s-independent planning of an assembly: device views live in
+// the handle (plan buffer), the offsets of the per-launch lists here.
+struct Plan {
+    int64_t T = 0, nv = 0, n = 0;
+    int dim = 0, nper = 0, nblk = 0;
+    size_t o_ft = 0, o_nt = 0, o_bnd = 0, o_bdofs = 0, o_loc = 0, o_vloc = 0, o_ep = 0, o_vp = 0,
+           o_fac = 0, o_fvid = 0;
+    long long n_tiles = 0, n_far_tiles = 0, n_edge = 0, n_vert = 0;
+    double t_plan_ms = 0.0;
+};
+}  // namespace fl
+
+// The plan of the last fl_assemble / fl_assemble_batch over all element
+// pairs and the handle's views into it, kept for the next such call while
+// the mesh, the DOF set and the distance classes stay the same.  Any other
+// planning (which rewrites the plan buffer), fl_set_mesh, fl_set_symmetry
+// and the release of the buffers drop it.
+struct fl_plan_cache {
+    bool valid = false;
+    bool all_nodes = false;
+    int n_classes = 0;
+    double theta[FL_MAX_CLASSES] = {};
+    bool use_far = false;
+    fl::Plan P{};
+    fl::ElemDev E{};
+    int* v2c_ptr = nullptr;
+    int* v2c_idx = nullptr;
+    int* node2dof = nullptr;
+    int* dof_node = nullptr;
+    const unsigned char* vloc = nullptr;
+    const int* sc_ptr = nullptr;
+    const int* sc_idx = nullptr;
+    const int* sc_map = nullptr;
+    const unsigned char* sc_vloc = nullptr;
+    int sc_rows = 0;
+    double* meas = nullptr;
+};
+
 struct fl_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -207,6 +246,7 @@ struct fl_handle {
     double* w_sym = nullptr;
 
     fl_stats_t st{};
+    fl_plan_cache pc;
     fl_batch B;
     fl_sur sur;
     fl_mg mg;
@@ -215,16 +255,6 @@ struct fl_handle {
 };
 
 namespace fl {
-// Result of the s-independent planning of an assembly: device views live in
-// the handle (plan buffer), the offsets of the per-launch lists here.
-struct Plan {
-    int64_t T = 0, nv = 0, n = 0;
-    int dim = 0, nper = 0, nblk = 0;
-    size_t o_ft = 0, o_nt = 0, o_bnd = 0, o_bdofs = 0, o_loc = 0, o_vloc = 0, o_ep = 0, o_vp = 0,
-           o_fac = 0, o_fvid = 0;
-    long long n_tiles = 0, n_far_tiles = 0, n_edge = 0, n_vert = 0;
-    double t_plan_ms = 0.0;
-};
 // Chooses the element-block pairs (bi <= bj) to tile, from the internal
 // element order (perm: internal -> caller index) and the DOF of every
 // internal element's vertices (dof[a][Ki], -1: none).

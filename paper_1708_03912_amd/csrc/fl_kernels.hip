@@ -108,10 +108,12 @@ __device__ __forceinline__ double dsum_pl16(double x, double y) {
     const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
     return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
+// (a row rotation reads a valid lane for every lane, so the moves need no
+// initialised destination)
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_sum4_lanes(const double* v) {
@@ -145,6 +147,25 @@ __device__ __forceinline__ double wave_sum6(const double* v, int lane) {
     y += __shfl_xor(y, 2, 64);
     y += __shfl_xor(y, 1, 64);
     return y;
+}
+
+// Calls f(rr, cc) for the entries i = tid, tid + 256, ... of an nr x nc
+// block (i = rr nc + cc; 256 threads), the pair advanced by the fixed step
+// (256 / nc, 256 mod nc) instead of a division per entry.
+template <class F>
+__device__ __forceinline__ void for_block_entries(int nr, int nc, int tid, F&& f) {
+    if (nr <= 0 || nc <= 0) return;
+    const int dr = 256 / nc, dc = 256 - dr * nc;
+    int rr = tid / nc, cc = tid - rr * nc;
+    while (rr < nr) {
+        f(rr, cc);
+        rr += dr;
+        cc += dc;
+        if (cc >= nc) {
+            cc -= nc;
+            ++rr;
+        }
+    }
 }
 
 // ----------------------------------------------------------- separated --
@@ -237,16 +258,22 @@ __device__ __forceinline__ void kpow_tab_issue(const KPowTab& kp, const double (
 
 template <int N>
 __device__ __forceinline__ void kpow_tab_finish(const KPowTab& kp, const KPowStage<N>& st, double (&kv)[N]) {
+    // the N Horner chains advance together, one step at a time
+    double t[N], pp[N];
 #pragma unroll
-    for (int p = 0; p < N; ++p) {
-        const double t = fma(st.m[p], st.fr[p].x, -1.0);
-        double pp = fma(kp.c5, t, kp.c4);
-        pp = fma(pp, t, kp.c3);
-        pp = fma(pp, t, kp.c2);
-        pp = fma(pp, t, kp.c1);
-        pp = fma(pp, t, 1.0);
-        kv[p] = (pp * st.fr[p].y) * st.ex[p];
-    }
+    for (int p = 0; p < N; ++p) t[p] = fma(st.m[p], st.fr[p].x, -1.0);
+#pragma unroll
+    for (int p = 0; p < N; ++p) pp[p] = fma(kp.c5, t[p], kp.c4);
+#pragma unroll
+    for (int p = 0; p < N; ++p) pp[p] = fma(pp[p], t[p], kp.c3);
+#pragma unroll
+    for (int p = 0; p < N; ++p) pp[p] = fma(pp[p], t[p], kp.c2);
+#pragma unroll
+    for (int p = 0; p < N; ++p) pp[p] = fma(pp[p], t[p], kp.c1);
+#pragma unroll
+    for (int p = 0; p < N; ++p) pp[p] = fma(pp[p], t[p], 1.0);
+#pragma unroll
+    for (int p = 0; p < N; ++p) kv[p] = (pp[p] * st.fr[p].y) * st.ex[p];
 }
 
 // Fixed order KO: factorised sums.  With k_pq = k(x_p, y_q) and the rule's
@@ -911,10 +938,9 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
     }
     __syncthreads();
     if (!direct) {
-        for (int i = tid; i < nVI * nVJ; i += 256) {
-            double v = L[i];
-            if (v == 0.0) continue;
-            int rr = i / nVJ, cc = i - rr * nVJ;
+        for_block_entries(nVI, nVJ, tid, [&](int rr, int cc) {
+            const double v = L[rr * nVJ + cc];
+            if (v == 0.0) return;
             if constexpr (CL) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
@@ -924,7 +950,7 @@ __global__ __launch_bounds__(256) void far_kernel(ElemDev E, FarParams P) {
                 // a diagonal tile's block holds both orientations already
                 acc_add(P.fa, P.A, (long long)vI[rr] * P.lda + vJ[cc], v);
             }
-        }
+        });
     }
     for (int i = tid; i < BE * 6; i += 256) {
         int K = I0 + i / 6, Kt2 = J0 + i / 6;
@@ -1301,10 +1327,9 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
     }
     __syncthreads();
     if (!direct) {
-        for (int i = tid; i < nVI * nVJ; i += 256) {
-            double v = L[i];
-            if (v == 0.0) continue;
-            int rr = i / nVJ, cc = i - rr * nVJ;
+        for_block_entries(nVI, nVJ, tid, [&](int rr, int cc) {
+            const double v = L[rr * nVJ + cc];
+            if (v == 0.0) return;
             if constexpr (CL) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 if (bi != bj) nm_add(P.nm, vJ[cc], vI[rr], v);
@@ -1314,7 +1339,7 @@ __global__ __launch_bounds__(256) void near_kernel(ElemDev E, FarParams P) {
                 // a diagonal tile's block holds both orientations already
                 acc_add(P.fa, P.A, (long long)vI[rr] * P.lda + vJ[cc], v);
             }
-        }
+        });
     }
     for (int i = tid; i < BE * 6; i += 256) {
         int K = I0 + i / 6, Kt2 = J0 + i / 6;
@@ -1413,8 +1438,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         }
     }
 
-    // the lane's column element
-    const int Kt = J0 + lane;
+    // the lane's column element: lanes 16 g .. 16 g + 15 take the columns
+    // g, g + 4, .., g + 60, so that the elements a 16-lane group adds into
+    // the LDS block at once are spread over the tile and seldom share a
+    // vertex (fewer lanes on one LDS address in the atomic adds)
+    const int col = 4 * (lane & 15) + (lane >> 4);
+    const int Kt = J0 + col;
     const bool okt = Kt < T;
     const int Ktc = okt ? Kt : T - 1;
     double yq[2 * Q];
@@ -1463,7 +1492,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         for (int c = 0; c < 2 * Q; ++c) xp[c] = sX[r][c];
         double f = sMK[r] * ct;
         if constexpr (W) f *= okt ? pair_w(E, I0 + r, Kt) : 0.0;
-        const double fs = (CL && !nm_bit(nbits, r, lane)) ? 0.0 : f;
+        const double fs = (CL && !nm_bit(nbits, r, col)) ? 0.0 : f;
         double M[Q][3];
         if constexpr (MIX) {
             float xf[2 * Q], Mf[Q][3];
@@ -1597,29 +1626,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
     if (DET && !direct) {
         // the words go to A's words (same scale), doubled on a folded diagonal
         const long long* Llo = (const long long*)L;
-        for (int i = tid; i < nVI * nVJ; i += 256) {
-            const int rr = i / nVJ, cc = i - rr * nVJ;
+        for_block_entries(nVI, nVJ, tid, [&](int rr, int cc) {
             const long long lo = Llo[rr * LS + cc];
             const int hi = Lhi[rr * LS + cc];
-            if (lo == 0 && hi == 0) continue;
+            if (lo == 0 && hi == 0) return;
             const int gi = vI[rr], gj = vJ[cc];
             const long long k = gi == gj ? 2 : 1;
             const long long at = upper_index(gi, gj, P.lda);
             if (hi) atomicAdd(&P.fa.hi[at], (int)(k * hi));
             if (lo) atomicAdd((unsigned long long*)&P.fa.lo[at], (unsigned long long)(k * lo));
-        }
+        });
     } else if (!direct) {
-        for (int i = tid; i < nVI * nVJ; i += 256) {
-            const int rr = i / nVJ, cc = i - rr * nVJ;
+        for_block_entries(nVI, nVJ, tid, [&](int rr, int cc) {
             const double v = L[rr * LS + cc];
-            if (v == 0.0) continue;
+            if (v == 0.0) return;
             if constexpr (CL) {
                 nm_add(P.nm, vI[rr], vJ[cc], v);
                 nm_add(P.nm, vJ[cc], vI[rr], v);
             } else {
                 add_pair_upper(P, vI[rr], vJ[cc], v);
             }
-        }
+        });
     }
     __syncthreads();
     // diagonal blocks of the columns: each wave's part, added in wave order
@@ -1634,7 +1661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
         }
         double* stage = L;  // 4 x 64 x 6 doubles
 #pragma unroll
-        for (int m = 0; m < 6; ++m) stage[(wave * 64 + lane) * 6 + m] = st[m];
+        for (int m = 0; m < 6; ++m) stage[(wave * 64 + col) * 6 + m] = st[m];
     }
     __syncthreads();
     for (int i = tid; i < BE * 6; i += 256) {
