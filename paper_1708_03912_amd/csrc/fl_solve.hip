@@ -503,12 +503,13 @@ void sym_plan_geometry(long long n, SymPlan* P) {
     P->m = (int)std::max<long long>(3, std::min<long long>(SYM_M, tiles / 2048));
     P->nchx = (P->nb + P->m - 1) / P->m;
     P->nwg = (long long)P->nchx * P->nb;
-    // large systems: CG scalars by a one-workgroup kernel, so the
-    // reductions may use 16 lanes per element; otherwise every workgroup
-    // of the product reduces the partials itself and their count stays
-    // below 1024
+    // large systems: CG scalars by a one-workgroup kernel, and 4 lanes per
+    // element in the reductions (a load instruction then reads 4 runs of 16
+    // consecutive entries of the slot arrays, 128 B each); otherwise every
+    // workgroup of the product reduces the partials itself and their count
+    // stays below 1024
     P->sk = n > SYM_SK_N ? 1 : 0;
-    int G = 16;
+    int G = P->sk ? 4 : 16;
     if (!P->sk)
         while (G > 1 && (n * G + 255) / 256 > 1024) G >>= 1;
     P->G = G;
