@@ -250,7 +250,7 @@ def rooflines(D, svals, cache_resident):
     evals_per_s = far_evals / (far_ms * 1e-3)
     far_tflops = evals_per_s * FLOPS_PER_EVAL / 1e12
     traffic = measured_traffic() if cache_resident is False else {}
-    rf_far = {"kernel": "far2_kernel<2,0,0,0> + near_kernel<2,0,0,0> (separated element pairs, FP64)",
+    rf_far = {"kernel": "far2_kernel<2,0,0,0,0> + near_kernel<2,0,0,0> (separated element pairs, FP64)",
               "bound": "alu", "achieved": round(far_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": round(far_tflops / FP64_PEAK_TFLOPS, 4),
               "traffic": traffic.get("separated_pairs"),
