@@ -20,6 +20,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fl_handle.hpp"
@@ -690,11 +691,12 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const
         if (symm && !h->sym_pre.empty())
             for (int64_t Ki = Tw; Ki < T; ++Ki)
                 bmaxpre[Ki / BE] = std::max(bmaxpre[Ki / BE], (int)h->sym_pre[perm[Ki]]);
-        auto classify = [&](int bi, int bj) {
-            if (symm && (int64_t)bi * BE >= Tw) return;  // image blocks only: weight 0
+        // 0: no tile, 1: tile, 2: far tile
+        auto classify = [&](int bi, int bj) -> int {
+            if (symm && (int64_t)bi * BE >= Tw) return 0;  // image blocks only: weight 0
             if (symm && !h->sym_pre.empty() && (int64_t)(bi + 1) * BE <= Tw && (int64_t)bj * BE >= Tw &&
                 bmaxpre[bj] < bi * BE)
-                return;
+                return 0;
             bool far = false;
             if (use_far && bi != bj) {
                 double dx = std::max(0.0, std::max(bx0[bj] - bx1[bi], bx0[bi] - bx1[bj]));
@@ -702,15 +704,56 @@ int plan_assembly(fl_handle* h, bool all_nodes, const fl_opts& o, Plan& P, const
                 double d2 = dx * dx + dy * dy;
                 far = d2 > th_last2 * std::max(bh[bi], bh[bj]) * (1.0 + 1e-9);
             }
-            (far ? far_tiles : tiles).push_back(make_int2(bi, bj));
+            return far ? 2 : 1;
         };
         if (!sel) {
-            for (int bi = 0; bi < nblk; ++bi)
-                for (int bj = bi; bj < nblk; ++bj) classify(bi, bj);
+            // all pairs bi <= bj: block rows split over host threads in ranges
+            // of about equal pair counts, each range into lists of its own,
+            // joined in row order (the order of one sequential pass)
+            const long long npairs = (long long)nblk * (nblk + 1) / 2;
+            const int nth = (int)std::max<long long>(
+                1, std::min<long long>({(long long)std::max(1u, std::thread::hardware_concurrency()), 16LL,
+                                        npairs / 65536 + 1}));
+            std::vector<int> row0(nth + 1, nblk);
+            {
+                long long acc = 0;
+                int k = 1;
+                row0[0] = 0;
+                for (int bi = 0; bi < nblk && k < nth; ++bi) {
+                    acc += nblk - bi;
+                    if (acc * nth >= npairs * k) row0[k++] = bi + 1;
+                }
+            }
+            std::vector<std::vector<int2>> part_near(nth), part_far(nth);
+            auto work = [&](int k) {
+                for (int bi = row0[k]; bi < row0[k + 1]; ++bi)
+                    for (int bj = bi; bj < nblk; ++bj) {
+                        const int c = classify(bi, bj);
+                        if (c) (c == 2 ? part_far[k] : part_near[k]).push_back(make_int2(bi, bj));
+                    }
+            };
+            std::vector<std::thread> pool;
+            for (int k = 1; k < nth; ++k) pool.emplace_back(work, k);
+            work(0);
+            for (std::thread& t : pool) t.join();
+            size_t nn = 0, nf = 0;
+            for (int k = 0; k < nth; ++k) {
+                nn += part_near[k].size();
+                nf += part_far[k].size();
+            }
+            tiles.reserve(nn);
+            far_tiles.reserve(nf);
+            for (int k = 0; k < nth; ++k) {
+                tiles.insert(tiles.end(), part_near[k].begin(), part_near[k].end());
+                far_tiles.insert(far_tiles.end(), part_far[k].begin(), part_far[k].end());
+            }
         } else {
             std::vector<int2> pairs;
             (*sel)(perm, dof, nblk, pairs);
-            for (const int2& t : pairs) classify(t.x, t.y);
+            for (const int2& t : pairs) {
+                const int c = classify(t.x, t.y);
+                if (c) (c == 2 ? far_tiles : tiles).push_back(t);
+            }
         }
     }
     std::vector<int> blk_ndof(nblk), blk_dofs((size_t)nblk * MAXV, -1);
