@@ -187,6 +187,7 @@ struct BndParams {
     int kfb[FL_MAX_CLASSES + 1];
     int k_touch;
     int with_boundary;
+    int fchunk;             // facets per thread (set by launch_self)
     double* S;
     unsigned long long* counters;  // [0] touching, [1] separated
     FixAcc fs;              // repeatable accumulation of S

@@ -1904,26 +1904,25 @@ __device__ void bnd_vert2(const double* q, const double* b1, const double* b2, c
         for (int b = 0; b < 3; ++b) M[3 * a + b] = f * acc[sym3(a, b)];
 }
 
-constexpr int FACET_CHUNK = 4;
-
-// One thread per (element, chunk of FACET_CHUNK boundary facets): the
+// One thread per (element, chunk of P.fchunk boundary facets): the
 // boundary term sum_e a^{Kxe} over the chunk (weight C/(2s)); the thread of
 // chunk 0 adds the identical-pair term (weight C/2).  The partial 3x3 block
-// is added to the element's diagonal-block accumulator S atomically.
+// is added to the element's diagonal-block accumulator S atomically, the
+// pair counts once per wave.
 template <int DIM>
 __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
     // 2D: the kernel power of the separated element-edge pairs by the LDS
-    // tables (same exponent as the separated element pairs), loaded before
-    // any thread leaves
+    // tables (same exponent as the separated element pairs)
     __shared__ __align__(16) double pw[DIM == 2 ? 768 : 1];
     if constexpr (DIM == 2) {
         load_pow_tables(pw);
         __syncthreads();
     }
-    const int K = blockIdx.x * blockDim.x + threadIdx.x;
-    if (K >= P.T) return;
-    const int e_lo = blockIdx.y * FACET_CHUNK;
-    const int e_hi = min(P.nb, e_lo + FACET_CHUNK);
+    const int K0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = K0 < P.T;
+    const int K = live ? K0 : P.T - 1;  // (threads past T count nothing and add nothing)
+    const int e_lo = blockIdx.y * P.fchunk;
+    const int e_hi = live ? min(P.nb, e_lo + P.fchunk) : e_lo;
     constexpr int NV = DIM + 1;
     double X[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < NV * DIM; ++c) X[c] = E.x[c][K];
@@ -2029,9 +2028,17 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
                 for (int m = 0; m < 6; ++m) acc[m] += fb * M6[m];
             }
         }
-        if (ntouch) atomicAdd(&P.counters[0], ntouch);
-        if (nfar) atomicAdd(&P.counters[1], nfar);
+        // (every lane of the wave takes part in the sums)
+        for (int o = 32; o >= 1; o >>= 1) {
+            ntouch += __shfl_xor(ntouch, o, 64);
+            nfar += __shfl_xor(nfar, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (ntouch) atomicAdd(&P.counters[0], ntouch);
+            if (nfar) atomicAdd(&P.counters[1], nfar);
+        }
     }
+    if (!live) return;
     const double wk = E.w ? E.w[K] : 1.0;
     for (int m = 0; m < 6; ++m)
         // (for s >= 1/2 the boundary term of a boundary vertex diverges; those
@@ -2042,12 +2049,20 @@ __global__ __launch_bounds__(256) void self_kernel(ElemDev E, BndParams P) {
 }
 
 void launch_self(const ElemDev& E, const BndParams& P, hipStream_t st) {
-    const int chunks = P.with_boundary ? max(1, (P.nb + FACET_CHUNK - 1) / FACET_CHUNK) : 1;
-    dim3 grid((P.T + 255) / 256, chunks), block(256);
+    // facets per thread: doubled from 4 while the grid keeps about 2048
+    // workgroups or more (fewer partial blocks added into S), at most 256
+    BndParams Q = P;
+    const long long wgx = (P.T + 255) / 256;
+    int fc = 4;
+    if (P.with_boundary)
+        while (fc < 256 && wgx * ((P.nb + 2 * fc - 1) / (2 * fc)) >= 2048) fc *= 2;
+    Q.fchunk = fc;
+    const int chunks = P.with_boundary ? max(1, (P.nb + fc - 1) / fc) : 1;
+    dim3 grid((unsigned)wgx, chunks), block(256);
     if (P.dim == 2)
-        hipLaunchKernelGGL(self_kernel<2>, grid, block, 0, st, E, P);
+        hipLaunchKernelGGL(self_kernel<2>, grid, block, 0, st, E, Q);
     else
-        hipLaunchKernelGGL(self_kernel<1>, grid, block, 0, st, E, P);
+        hipLaunchKernelGGL(self_kernel<1>, grid, block, 0, st, E, Q);
 }
 
 // ----------------------------------------------------- edge and vertex --
