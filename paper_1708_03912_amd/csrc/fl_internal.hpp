@@ -231,25 +231,29 @@ void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx
 // solver kernels
 void launch_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
 
-// Symmetric dense product from the upper triangle (fl_kernels.hip): 64 x 64
-// tiles (bi <= bj); workgroup (c, bi) of a (nchx, nb) grid takes block row bi
-// and the m tiles from bj = bi + c m; partial sums in slot arrays (no
-// atomics), reduced with G lanes per element.
+// Symmetric dense product from the upper triangle (fl_solve.hip): 64 x 64
+// tiles (bi <= bj); workgroup (J, I) of an (nJ, nI) grid takes the tiles of
+// block rows I R .. I R + R - 1 and block columns J m .. J m + m - 1;
+// partial sums in slot arrays (no atomics), reduced with G lanes per
+// element.
 constexpr int SYM_TB = 64;
-constexpr int SYM_M = 16;            // longest strip of tiles per workgroup
+constexpr int SYM_M = 16;            // most block columns per workgroup
+constexpr int SYM_R = 4;             // most block rows per workgroup
 constexpr long long SYM_SK_N = 16384;  // larger systems: CG scalars by their own kernel
 constexpr int SYM_PQ_BLOCKS = 256;   // pre-reduction of the v.Av partials
 struct SymPlan {
     long long n;
     int nb;          // block rows, ceil(n / 64)
-    int m;           // tiles per workgroup along a block row (<= SYM_M)
+    int m;           // block columns per workgroup (<= SYM_M)
+    int R;           // block rows per workgroup (<= SYM_R)
     int sk;          // 1: CG scalars by cg_scalar_kernel (large n)
-    int nchx;        // chunks per block row, ceil(nb / m)
-    long long nwg;   // workgroups of a product, nchx x nb (some empty)
+    int nJ;          // workgroup columns, ceil(nb / m)
+    int nI;          // workgroup rows, ceil(nb / R)
+    long long nwg;   // workgroups of a product, nJ x nI (those below the diagonal empty)
     int G;           // lanes per element in the reductions (power of two <= 16)
     int nred;        // blocks of the reductions, ceil(n G / 256)
-    double* prow;    // nchx x n row-sum slots
-    double* pcol;    // nb x n column-sum slots
+    double* prow;    // nJ x n row-sum slots
+    double* pcol;    // nI x n column-sum slots
     double* wpart;   // nwg workgroup partials of v.Av
     double* wpart2;  // SYM_PQ_BLOCKS pre-reduced partials
     bool pre;        // pre-reduction in use

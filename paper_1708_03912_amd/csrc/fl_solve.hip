@@ -82,21 +82,25 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // Symmetric dense product from the upper triangle.  The stiffness matrix is
 // symmetric (Sec. 5: every pair adds a block and its transpose), so a
 // product reads only its 64 x 64 tiles (bi <= bj): half of the n^2 entries.
-// Workgroup (c, bi) of a (nchx, nb) grid streams the strip of tiles
-// bj = bi + c m .. bi + c m + m - 1 (< nb) of block row bi (workgroups past
-// the end of the row have nothing to do), with the next tile's loads in
-// flight while the current one is used.  It forms the row sums A_IJ v_J,
-// summed over the strip in registers, and for bi < bj the column sums
-// A_IJ^T v_I of every tile.  Partial sums go to slots that exactly one
-// workgroup writes (no atomics):
-//   prow[c n + i]  row sums of strip c of the block row of i,
-//   pcol[a n + j]  column sums of tile (a, b) for j in block b, a < b,
-// and (A v)_i is their sum over c < nch(b), then a < b (fixed order).
+// Workgroup (J, I) of an (nJ, nI) grid takes the tiles of block rows
+// I R .. I R + R - 1 and block columns J m .. J m + m - 1 on or above the
+// diagonal, row by row, with the next tile's loads in flight while the
+// current one is used.  It forms the row sums A_IJ v_J of each of its block
+// rows, summed over its tiles in registers, and the column sums A_IJ^T v_I
+// of its tiles with bi < bj, summed over its rows in LDS.  Partial sums go
+// to slots that exactly one workgroup writes (no atomics):
+//   prow[J n + i]  row sums of workgroup column J in the block row of i,
+//                  for J = b / m .. nJ - 1 (b the block of i),
+//   pcol[I n + j]  column sums of workgroup row I for j in block b,
+//                  for I = 0 .. b / R (zero where no tile lies above),
+// and (A v)_i is their sum in that order (fixed order).  Grouping R rows
+// makes an element's column slots one per R block rows instead of one per
+// tile, which keeps the slots' traffic a few percent of the matrix's.
 // Thread (wave w, lane l) holds columns 16 w + 2 (l & 7) + {0, 1} and rows
 // (l >> 3) + 8 k, k = 0..7, of each tile: one load of a wave covers eight
 // contiguous row segments of 16 entries.  A column sum is complete after
-// three exchanges inside the wave; the row sums are reduced once per strip
-// (three exchanges, then the four waves in order through LDS).
+// three exchanges inside the wave; the row sums are reduced once per block
+// row (three exchanges, then the four waves in order through LDS).
 typedef double sym_d2 __attribute__((ext_vector_type(2)));
 typedef float sym_f2 __attribute__((ext_vector_type(2)));
 template <class T>
@@ -165,20 +169,22 @@ struct SymVecP {
     __device__ __forceinline__ double val(const L& l) const { return (double)(T)(l.a + beta * l.b); }
 };
 
-// One strip of the product with the vector V.  Writes the slots; returns
-// this thread's share of the strip's part of v^T A v (diagonal tile once,
-// off-diagonal tiles twice).  red: 256 doubles of LDS.  Loads of the next
-// tile and of its vector entries (indices clamped into the arrays, so the
-// loads are unconditional and the waits count only older ones) are issued
-// before the current tile is used.
+// One block row of a workgroup's tiles: tiles bj = b0 .. b1 - 1 of block
+// row bi with the vector V.  The row sums go to the slot prow[J n + i] (the
+// caller's workgroup column J); the column sums of every tile with bj > bi
+// are added to cacc[(bj - J0) 64 + column in the tile] (LDS, one thread per
+// entry within a row; the caller's barrier between rows orders the rows'
+// additions).  Returns this thread's share of the row sums' part of v^T A v.
+// red: 256 doubles of LDS.  Loads of the next tile and of its vector entries
+// (indices clamped into the arrays, so the loads are unconditional and the
+// waits count only older ones) are issued before the current tile is used.
 template <class T, class VF>
-__device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long lda, const SymPlan& P, int bi,
-                                            int c, const VF& V, double* red) {
+__device__ __forceinline__ double sym_row(const T* __restrict__ A, long long lda, const SymPlan& P, int bi, int b0,
+                                          int b1, int J, int J0, const VF& V, double* red, double* cacc) {
     using V2 = typename Pair2<T>::type;
     using VL = typename VF::L;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, cp = lane & 7, rg = lane >> 3;
     const long long n = P.n, I0 = (long long)bi * SYM_TB;
-    const int b0 = bi + c * P.m, b1 = min(P.nb, b0 + P.m);
     const int coff = 16 * w + 2 * cp;
     double vi[8], racc[8];
     {
@@ -191,7 +197,6 @@ __device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long l
             racc[k] = 0.0;
         }
     }
-    double vd = 0.0;
     // tile bj (its entries raw, its vector entries l0, l1) into the row and
     // column sums
     auto tile = [&](int bj, long long j, const V2 (&raw)[8], const VL& l0, const VL& l1) {
@@ -212,18 +217,12 @@ __device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long l
             double y = (h5 ? c1 : c0) + __shfl_xor(h5 ? c0 : c1, 32, 64);
             y += __shfl_xor(y, 16, 64);
             y += __shfl_xor(y, 8, 64);
-            if ((lane & 0x18) == 0) {
-                const long long jj = j + h5;
-                if (jj < n) {
-                    P.pcol[(long long)bi * n + jj] = y;
-                    vd += y * (h5 ? x1 : x0);
-                }
-            }
+            if ((lane & 0x18) == 0) cacc[(bj - J0) * SYM_TB + coff + h5] += y;
         }
     };
     // two buffers in turn: the next tile's loads (and its vector entries)
     // are issued before the current tile is used, with no copy between the
-    // buffers and no branch around the loads (past the end of the strip they
+    // buffers and no branch around the loads (past the end of the row they
     // read the current tile's first row again), so the waits count only the
     // older loads
     V2 ra[8], rb[8];
@@ -265,18 +264,20 @@ __device__ __forceinline__ double sym_strip(const T* __restrict__ A, long long l
         red[w * 64 + rg + 8 * cp] = y;
     }
     __syncthreads();
+    double vd = 0.0;
     if (t < 64) {
         const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
         const long long i = I0 + t;
         if (i < n) {
-            P.prow[(long long)c * n + i] = s;
-            vd += s * V.val(V.load(i));
+            P.prow[(long long)J * n + i] = s;
+            vd = s * V.val(V.load(i));
         }
     }
+    __syncthreads();  // red is rewritten by the next row
     return vd;
 }
 
-// FP32 matrix: the same strip with 16-byte loads.  Thread (wave w, lane l)
+// FP32 matrix: the same row with 16-byte loads.  Thread (wave w, lane l)
 // holds columns 32 (w & 1) + 4 (l & 7) .. + 3 of tile b + (w >> 1) and rows
 // (l >> 3) + 8 k, so one step of the workgroup covers two tiles (waves 0, 1
 // the first, waves 2, 3 the second) with eight loads per thread.  Column
@@ -296,12 +297,11 @@ __device__ __forceinline__ void sym_load4(const float* __restrict__ A, long long
 }
 
 template <class VF>
-__device__ __forceinline__ double sym_strip4(const float* __restrict__ A, long long lda, const SymPlan& P, int bi,
-                                             int c, const VF& V, double* red) {
+__device__ __forceinline__ double sym_row4(const float* __restrict__ A, long long lda, const SymPlan& P, int bi,
+                                           int b0, int b1, int J, int J0, const VF& V, double* red, double* cacc) {
     using VL = typename VF::L;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, cq = lane & 7, rg = lane >> 3;
     const long long n = P.n, I0 = (long long)bi * SYM_TB;
-    const int b0 = bi + c * P.m, b1 = min(P.nb, b0 + P.m);
     const int half = w >> 1, coff = 32 * (w & 1) + 4 * cq;
     double vi[8], racc[8];
     {
@@ -314,9 +314,8 @@ __device__ __forceinline__ double sym_strip4(const float* __restrict__ A, long l
             racc[k] = 0.0;
         }
     }
-    double vd = 0.0;
     // this wave's tile of step s (tile b0 + 2 s + half), its first column,
-    // and whether it lies in the strip
+    // and whether it lies in the row's range
     auto col = [&](int s) { return (long long)(b0 + 2 * s + half) * SYM_TB + coff; };
     auto live = [&](int s) { return b0 + 2 * s + half < b1; };
     auto step = [&](int s, const sym_f4 (&raw)[8], const VL (&lx)[4]) {
@@ -345,13 +344,7 @@ __device__ __forceinline__ double sym_strip4(const float* __restrict__ A, long l
                 u[q] = (h5 ? cs[2 + q] : cs[q]) + __shfl_xor(h5 ? cs[q] : cs[2 + q], 32, 64);
             double y = (h4 ? u[1] : u[0]) + __shfl_xor(h4 ? u[0] : u[1], 16, 64);
             y += __shfl_xor(y, 8, 64);
-            if ((lane & 8) == 0) {
-                const int m = 2 * h5 + h4;
-                if (j + m < n) {
-                    P.pcol[(long long)bi * n + j + m] = y;
-                    vd += y * x[m];
-                }
-            }
+            if ((lane & 8) == 0) cacc[(bj - J0) * SYM_TB + coff + 2 * h5 + h4] += y;
         }
     };
     const int ns = (b1 - b0 + 1) / 2;  // steps of two tiles
@@ -400,23 +393,59 @@ __device__ __forceinline__ double sym_strip4(const float* __restrict__ A, long l
         red[w * 64 + rg + 8 * cq] = y;
     }
     __syncthreads();
+    double vd = 0.0;
     if (t < 64) {
         const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
         const long long i = I0 + t;
         if (i < n) {
-            P.prow[(long long)c * n + i] = s;
-            vd += s * V.val(V.load(i));
+            P.prow[(long long)J * n + i] = s;
+            vd = s * V.val(V.load(i));
         }
     }
+    __syncthreads();  // red is rewritten by the next row
     return vd;
 }
 
-// the strip for either matrix type
+// Workgroup (J, I) holds the tiles (bi, bj), bi <= bj, of block rows
+// bi = I R .. I R + R - 1 and block columns bj = J m .. J m + m - 1 (those
+// past the end or below the diagonal excepted; a workgroup whose columns
+// all lie left of its first row has none).
+__device__ __forceinline__ bool sym_group_live(const SymPlan& P, int I, int J) {
+    return J * P.m + P.m - 1 >= I * P.R && J * P.m < P.nb;
+}
+
+// The workgroup's part of the product, block row by block row: row sums to
+// prow[J n + i] for its rows, column sums accumulated in LDS (cacc: m x 64
+// doubles) over its rows and written to pcol[I n + j] for every column j of
+// its block columns bj >= I R (zero where no tile of the workgroup lies
+// above the diagonal in that column).  Returns this thread's share of the
+// workgroup's part of v^T A v (diagonal tiles once, the others twice).
 template <class T, class VF>
-__device__ __forceinline__ double sym_strip_any(const T* __restrict__ A, long long lda, const SymPlan& P, int bi,
-                                                int c, const VF& V, double* red) {
-    if constexpr (std::is_same<T, float>::value) return sym_strip4(A, lda, P, bi, c, V, red);
-    else return sym_strip<T>(A, lda, P, bi, c, V, red);
+__device__ __forceinline__ double sym_group_any(const T* __restrict__ A, long long lda, const SymPlan& P, int I,
+                                                int J, const VF& V, double* red, double* cacc) {
+    const int t = threadIdx.x;
+    const long long n = P.n;
+    const int J0 = J * P.m, J1 = min(P.nb, J0 + P.m);
+    for (int q = t; q < P.m * SYM_TB; q += 256) cacc[q] = 0.0;
+    __syncthreads();
+    double vd = 0.0;
+    for (int r = 0; r < P.R; ++r) {
+        const int bi = I * P.R + r;
+        const int b0 = max(J0, bi);
+        if (bi >= P.nb || b0 >= J1) break;  // (the rows below start further right still)
+        if constexpr (std::is_same<T, float>::value) vd += sym_row4(A, lda, P, bi, b0, J1, J, J0, V, red, cacc);
+        else vd += sym_row<T>(A, lda, P, bi, b0, J1, J, J0, V, red, cacc);
+    }
+    const int c0 = max(J0, I * P.R);
+    for (int q = (c0 - J0) * SYM_TB + t; q < (J1 - J0) * SYM_TB; q += 256) {
+        const long long j = (long long)J0 * SYM_TB + q;
+        if (j < n) {
+            const double y = cacc[q];
+            P.pcol[(long long)I * n + j] = y;
+            vd += y * V.val(V.load(j));
+        }
+    }
+    return vd;
 }
 
 // this lane's share of (A v)_i from the slots (lane g of an aligned group
@@ -425,11 +454,13 @@ __device__ __forceinline__ double sym_gather_share(const SymPlan& P, long long i
     const int G = P.G;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (i < P.n) {
+        // row slots of the workgroup columns J = b / m .. nJ - 1, then the
+        // column slots of the workgroup rows I = 0 .. b / R
         const int b = (int)(i / SYM_TB);
-        const int nch = (P.nb - b + P.m - 1) / P.m;
-        const int ns = nch + b;
+        const int jr0 = b / P.m, nrow = P.nJ - jr0;
+        const int ns = nrow + b / P.R + 1;
         auto slot = [&](int u) -> double {
-            return u < nch ? P.prow[(long long)u * P.n + i] : P.pcol[(long long)(u - nch) * P.n + i];
+            return u < nrow ? P.prow[(long long)(jr0 + u) * P.n + i] : P.pcol[(long long)(u - nrow) * P.n + i];
         };
         int u = g;
         for (; u + 3 * G < ns; u += 4 * G) {
@@ -455,9 +486,10 @@ template <class T>
 __global__ __launch_bounds__(256) void symv_kernel(const T* __restrict__ A, long long lda, SymPlan P,
                                                    const T* __restrict__ x) {
     __shared__ double red[256];
-    const int bi = blockIdx.y, c = blockIdx.x;
-    if (bi + c * P.m >= P.nb) return;
-    (void)sym_strip_any<T>(A, lda, P, bi, c, SymVecX<T>{x}, red);
+    __shared__ double cacc[SYM_M * SYM_TB];
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (!sym_group_live(P, I, J)) return;
+    (void)sym_group_any<T>(A, lda, P, I, J, SymVecX<T>{x}, red, cacc);
 }
 
 // y = A x from the slots
@@ -496,13 +528,19 @@ __global__ __launch_bounds__(256) void sym_smooth_kernel(SymPlan P, double* x, c
 void sym_plan_geometry(long long n, SymPlan* P) {
     P->n = n;
     P->nb = (int)((n + SYM_TB - 1) / SYM_TB);
-    // strip length: up to SYM_M tiles while the triangle still holds about
-    // 2048 strips (the chip stays filled), at least 3 (the fixed cost of a
-    // workgroup is spread over several tiles)
+    // block columns per workgroup: up to SYM_M while the triangle still holds
+    // about 2048 workgroups (the chip stays filled), at least 3 (the fixed
+    // cost of a workgroup is spread over several tiles); block rows: doubled
+    // up to SYM_R while about 4096 workgroups remain.  Each doubling of R
+    // halves the column slots an element sums (one per workgroup row above
+    // it instead of one per tile)
     const long long tiles = (long long)P->nb * (P->nb + 1) / 2;
     P->m = (int)std::max<long long>(3, std::min<long long>(SYM_M, tiles / 2048));
-    P->nchx = (P->nb + P->m - 1) / P->m;
-    P->nwg = (long long)P->nchx * P->nb;
+    P->R = 1;
+    while (P->R < SYM_R && tiles / ((long long)P->m * 2 * P->R) >= 4096) P->R *= 2;
+    P->nJ = (P->nb + P->m - 1) / P->m;
+    P->nI = (P->nb + P->R - 1) / P->R;
+    P->nwg = (long long)P->nJ * P->nI;
     // large systems: CG scalars by a one-workgroup kernel, and 4 lanes per
     // element in the reductions (a load instruction then reads 4 runs of 16
     // consecutive entries of the slot arrays, 128 B each); otherwise every
@@ -517,13 +555,13 @@ void sym_plan_geometry(long long n, SymPlan* P) {
 }
 
 size_t sym_plan_doubles(const SymPlan& P) {
-    return (size_t)(P.nchx + P.nb) * (size_t)P.n + (size_t)P.nwg + SYM_PQ_BLOCKS + 8;
+    return (size_t)(P.nJ + P.nI) * (size_t)P.n + (size_t)P.nwg + SYM_PQ_BLOCKS + 8;
 }
 
 void sym_plan_bind(SymPlan* P, double* buf) {
     P->prow = buf;
-    P->pcol = buf + (long long)P->nchx * P->n;
-    P->wpart = buf + (long long)(P->nchx + P->nb) * P->n;
+    P->pcol = buf + (long long)P->nJ * P->n;
+    P->wpart = buf + (long long)(P->nJ + P->nI) * P->n;
     P->wpart2 = P->wpart + P->nwg;
     // many workgroups: one pre-reduction pass so that every block of the
     // update sums SYM_PQ_BLOCKS partials instead of nwg
@@ -548,7 +586,7 @@ void launch_sym_pq_reduce(const SymPlan& P, hipStream_t st) {
 
 template <class T>
 void symv_launch(const SymPlan& P, const T* A, long long lda, const T* x, hipStream_t st) {
-    hipLaunchKernelGGL(symv_kernel<T>, dim3(P.nchx, P.nb), dim3(256), 0, st, A, lda, P, x);
+    hipLaunchKernelGGL(symv_kernel<T>, dim3(P.nJ, P.nI), dim3(256), 0, st, A, lda, P, x);
 }
 
 void launch_symv(const SymPlan& P, const double* A, long long lda, const double* x, double* y, hipStream_t st) {
@@ -670,14 +708,15 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     using T = cg_elem_t<ST>;
     __shared__ double sh[12];
     __shared__ double red[256];
+    __shared__ double cacc[SYM_M * SYM_TB];
     const SymPlan& P = S.sp;
-    const int bi = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
-    const long long wg = (long long)bi * gridDim.x + c;
-    if (bi + c * P.m >= P.nb) {  // beyond the triangle: an empty partial
+    const int I = blockIdx.y, J = blockIdx.x, t = threadIdx.x;
+    const long long wg = (long long)I * gridDim.x + J;
+    if (!sym_group_live(P, I, J)) {  // below the diagonal: an empty partial
         if (t == 0) P.wpart[wg] = 0.0;
         return;
     }
-    const long long n = S.n, I0 = (long long)bi * SYM_TB;
+    const long long n = S.n;
     const int par = it & 1;
     const T* pprev = S.p + (long long)(1 - par) * n;
     T* pcur = S.p + (long long)par * n;
@@ -692,7 +731,7 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
         double rzp = it > 0 ? load_partials(S.part + (1 - par) * S.nblk, S.nblk) : 0.0;
         if (*(volatile int*)&S.flag[0]) return;
         block_sum3(rz, rr, rzp, sh);
-        if (bi == 0 && c == 0 && t == 0) S.hist[it & 63] = rr;
+        if (I == 0 && J == 0 && t == 0) S.hist[it & 63] = rr;
         const double bb = S.scal[0];
         if (sqrt(rr) <= S.rtol * sqrt(bb) || it >= S.maxit || !(rr == rr)) {
             if (blockIdx.x == 0 && blockIdx.y == 0 && t == 0) {
@@ -707,9 +746,15 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     }
     const T beta = (T)beta64;
     // p_it = z + beta p_{it-1}, formed where the product needs it; the
-    // strip holding the diagonal tile stores it
-    double vd = sym_strip_any<T>(S.A, S.lda, P, bi, c, SymVecP<T>{S.z, pprev, beta}, red), u1 = 0.0, u2 = 0.0;
-    if (c == 0 && t < 64 && I0 + t < n) pcur[I0 + t] = S.z[I0 + t] + beta * pprev[I0 + t];
+    // workgroup holding a block row's diagonal tile stores it
+    double vd = sym_group_any<T>(S.A, S.lda, P, I, J, SymVecP<T>{S.z, pprev, beta}, red, cacc), u1 = 0.0,
+           u2 = 0.0;
+    for (int r = 0; r < P.R; ++r) {
+        const int bi = I * P.R + r;
+        const long long i = (long long)bi * SYM_TB + t;
+        if (bi < P.nb && bi >= J * P.m && bi < J * P.m + P.m && t < SYM_TB && i < n)
+            pcur[i] = S.z[i] + beta * pprev[i];
+    }
     block_sum3(vd, u1, u2, sh);
     if (t == 0) P.wpart[wg] = vd;
 }
@@ -840,7 +885,7 @@ void cg_init_launch(const ST& s, hipStream_t st) {
 
 template <class ST>
 void cg_iter_launch(const ST& s, int it, hipStream_t st) {
-    hipLaunchKernelGGL(cg_symv_kernel<ST>, dim3(s.sp.nchx, s.sp.nb), dim3(256), 0, st, s, it);
+    hipLaunchKernelGGL(cg_symv_kernel<ST>, dim3(s.sp.nJ, s.sp.nI), dim3(256), 0, st, s, it);
     launch_sym_pq_reduce(s.sp, st);
     hipLaunchKernelGGL(cg_update_kernel<ST>, dim3(s.nblk), dim3(256), 0, st, s, it);
     if (s.sp.sk) hipLaunchKernelGGL(cg_scalar_kernel<ST>, dim3(1), dim3(256), 0, st, s, it);
