@@ -96,6 +96,9 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
 // and (A v)_i is their sum in that order (fixed order).  Grouping R rows
 // makes an element's column slots one per R block rows instead of one per
 // tile, which keeps the slots' traffic a few percent of the matrix's.
+// Small systems (R = 1) take strips of m tiles from each block row's
+// diagonal instead (every strip but a row's last full, the column sums
+// stored per tile), which suits their few, latency-bound workgroups.
 // Thread (wave w, lane l) holds columns 16 w + 2 (l & 7) + {0, 1} and rows
 // (l >> 3) + 8 k, k = 0..7, of each tile: one load of a wave covers eight
 // contiguous row segments of 16 entries.  A column sum is complete after
@@ -173,14 +176,17 @@ struct SymVecP {
 // row bi with the vector V.  The row sums go to the slot prow[J n + i] (the
 // caller's workgroup column J); the column sums of every tile with bj > bi
 // are added to cacc[(bj - J0) 64 + column in the tile] (LDS, one thread per
-// entry within a row; the caller's barrier between rows orders the rows'
-// additions).  Returns this thread's share of the row sums' part of v^T A v.
+// entry within a row; the barrier at the end of the row orders the rows'
+// additions), or with direct (one block row per workgroup) stored to their
+// slot pcol[bi n + j] at once.  Returns this thread's share of the row's
+// part of v^T A v (with direct, the column sums' part too).
 // red: 256 doubles of LDS.  Loads of the next tile and of its vector entries
 // (indices clamped into the arrays, so the loads are unconditional and the
 // waits count only older ones) are issued before the current tile is used.
 template <class T, class VF>
 __device__ __forceinline__ double sym_row(const T* __restrict__ A, long long lda, const SymPlan& P, int bi, int b0,
-                                          int b1, int J, int J0, const VF& V, double* red, double* cacc) {
+                                          int b1, int J, int J0, bool direct, const VF& V, double* red,
+                                          double* cacc) {
     using V2 = typename Pair2<T>::type;
     using VL = typename VF::L;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, cp = lane & 7, rg = lane >> 3;
@@ -197,6 +203,7 @@ __device__ __forceinline__ double sym_row(const T* __restrict__ A, long long lda
             racc[k] = 0.0;
         }
     }
+    double vcol = 0.0;  // (direct) the column sums' part of v^T A v
     // tile bj (its entries raw, its vector entries l0, l1) into the row and
     // column sums
     auto tile = [&](int bj, long long j, const V2 (&raw)[8], const VL& l0, const VL& l1) {
@@ -217,7 +224,14 @@ __device__ __forceinline__ double sym_row(const T* __restrict__ A, long long lda
             double y = (h5 ? c1 : c0) + __shfl_xor(h5 ? c0 : c1, 32, 64);
             y += __shfl_xor(y, 16, 64);
             y += __shfl_xor(y, 8, 64);
-            if ((lane & 0x18) == 0) cacc[(bj - J0) * SYM_TB + coff + h5] += y;
+            if ((lane & 0x18) == 0) {
+                if (!direct) {
+                    cacc[(bj - J0) * SYM_TB + coff + h5] += y;
+                } else if (j + h5 < n) {
+                    P.pcol[(long long)bi * n + j + h5] = y;
+                    vcol += y * (h5 ? x1 : x0);
+                }
+            }
         }
     };
     // two buffers in turn: the next tile's loads (and its vector entries)
@@ -264,13 +278,13 @@ __device__ __forceinline__ double sym_row(const T* __restrict__ A, long long lda
         red[w * 64 + rg + 8 * cp] = y;
     }
     __syncthreads();
-    double vd = 0.0;
+    double vd = vcol;
     if (t < 64) {
         const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
         const long long i = I0 + t;
         if (i < n) {
             P.prow[(long long)J * n + i] = s;
-            vd = s * V.val(V.load(i));
+            vd += s * V.val(V.load(i));
         }
     }
     __syncthreads();  // red is rewritten by the next row
@@ -298,7 +312,8 @@ __device__ __forceinline__ void sym_load4(const float* __restrict__ A, long long
 
 template <class VF>
 __device__ __forceinline__ double sym_row4(const float* __restrict__ A, long long lda, const SymPlan& P, int bi,
-                                           int b0, int b1, int J, int J0, const VF& V, double* red, double* cacc) {
+                                           int b0, int b1, int J, int J0, bool direct, const VF& V, double* red,
+                                           double* cacc) {
     using VL = typename VF::L;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, cq = lane & 7, rg = lane >> 3;
     const long long n = P.n, I0 = (long long)bi * SYM_TB;
@@ -314,6 +329,7 @@ __device__ __forceinline__ double sym_row4(const float* __restrict__ A, long lon
             racc[k] = 0.0;
         }
     }
+    double vcol = 0.0;  // (direct) the column sums' part of v^T A v
     // this wave's tile of step s (tile b0 + 2 s + half), its first column,
     // and whether it lies in the row's range
     auto col = [&](int s) { return (long long)(b0 + 2 * s + half) * SYM_TB + coff; };
@@ -344,7 +360,15 @@ __device__ __forceinline__ double sym_row4(const float* __restrict__ A, long lon
                 u[q] = (h5 ? cs[2 + q] : cs[q]) + __shfl_xor(h5 ? cs[q] : cs[2 + q], 32, 64);
             double y = (h4 ? u[1] : u[0]) + __shfl_xor(h4 ? u[0] : u[1], 16, 64);
             y += __shfl_xor(y, 8, 64);
-            if ((lane & 8) == 0) cacc[(bj - J0) * SYM_TB + coff + 2 * h5 + h4] += y;
+            if ((lane & 8) == 0) {
+                const int m = 2 * h5 + h4;
+                if (!direct) {
+                    cacc[(bj - J0) * SYM_TB + coff + m] += y;
+                } else if (j + m < n) {
+                    P.pcol[(long long)bi * n + j + m] = y;
+                    vcol += y * x[m];
+                }
+            }
         }
     };
     const int ns = (b1 - b0 + 1) / 2;  // steps of two tiles
@@ -393,13 +417,13 @@ __device__ __forceinline__ double sym_row4(const float* __restrict__ A, long lon
         red[w * 64 + rg + 8 * cq] = y;
     }
     __syncthreads();
-    double vd = 0.0;
+    double vd = vcol;
     if (t < 64) {
         const double s = ((red[t] + red[64 + t]) + red[128 + t]) + red[192 + t];
         const long long i = I0 + t;
         if (i < n) {
             P.prow[(long long)J * n + i] = s;
-            vd = s * V.val(V.load(i));
+            vd += s * V.val(V.load(i));
         }
     }
     __syncthreads();  // red is rewritten by the next row
@@ -409,8 +433,11 @@ __device__ __forceinline__ double sym_row4(const float* __restrict__ A, long lon
 // Workgroup (J, I) holds the tiles (bi, bj), bi <= bj, of block rows
 // bi = I R .. I R + R - 1 and block columns bj = J m .. J m + m - 1 (those
 // past the end or below the diagonal excepted; a workgroup whose columns
-// all lie left of its first row has none).
+// all lie left of its first row has none).  R = 1 (small systems): block
+// row I and the strip bj = I + J m .. I + J m + m - 1 from its diagonal
+// instead, so that every strip but a row's last is full.
 __device__ __forceinline__ bool sym_group_live(const SymPlan& P, int I, int J) {
+    if (P.R == 1) return I + J * P.m < P.nb;
     return J * P.m + P.m - 1 >= I * P.R && J * P.m < P.nb;
 }
 
@@ -425,6 +452,11 @@ __device__ __forceinline__ double sym_group_any(const T* __restrict__ A, long lo
                                                 int J, const VF& V, double* red, double* cacc) {
     const int t = threadIdx.x;
     const long long n = P.n;
+    if (P.R == 1) {
+        const int b0 = I + J * P.m, b1 = min(P.nb, b0 + P.m);
+        if constexpr (std::is_same<T, float>::value) return sym_row4(A, lda, P, I, b0, b1, J, b0, true, V, red, cacc);
+        else return sym_row<T>(A, lda, P, I, b0, b1, J, b0, true, V, red, cacc);
+    }
     const int J0 = J * P.m, J1 = min(P.nb, J0 + P.m);
     for (int q = t; q < P.m * SYM_TB; q += 256) cacc[q] = 0.0;
     __syncthreads();
@@ -433,10 +465,10 @@ __device__ __forceinline__ double sym_group_any(const T* __restrict__ A, long lo
         const int bi = I * P.R + r;
         const int b0 = max(J0, bi);
         if (bi >= P.nb || b0 >= J1) break;  // (the rows below start further right still)
-        if constexpr (std::is_same<T, float>::value) vd += sym_row4(A, lda, P, bi, b0, J1, J, J0, V, red, cacc);
-        else vd += sym_row<T>(A, lda, P, bi, b0, J1, J, J0, V, red, cacc);
+        if constexpr (std::is_same<T, float>::value) vd += sym_row4(A, lda, P, bi, b0, J1, J, J0, false, V, red, cacc);
+        else vd += sym_row<T>(A, lda, P, bi, b0, J1, J, J0, false, V, red, cacc);
     }
-    const int c0 = max(J0, I * P.R);
+    const int c0 = max(J0, I * P.R + 1);  // (columns with a row of the workgroup above them)
     for (int q = (c0 - J0) * SYM_TB + t; q < (J1 - J0) * SYM_TB; q += 256) {
         const long long j = (long long)J0 * SYM_TB + q;
         if (j < n) {
@@ -454,11 +486,13 @@ __device__ __forceinline__ double sym_gather_share(const SymPlan& P, long long i
     const int G = P.G;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (i < P.n) {
-        // row slots of the workgroup columns J = b / m .. nJ - 1, then the
-        // column slots of the workgroup rows I = 0 .. b / R
+        // row slots of the workgroup columns J = b / m .. nJ - 1 (R = 1: the
+        // strips J = 0 .. of block row b), then the column slots of the
+        // workgroup rows I with I R < b
         const int b = (int)(i / SYM_TB);
-        const int jr0 = b / P.m, nrow = P.nJ - jr0;
-        const int ns = nrow + b / P.R + 1;
+        const int jr0 = P.R == 1 ? 0 : b / P.m;
+        const int nrow = P.R == 1 ? (P.nb - b + P.m - 1) / P.m : P.nJ - jr0;
+        const int ns = nrow + (b + P.R - 1) / P.R;
         auto slot = [&](int u) -> double {
             return u < nrow ? P.prow[(long long)(jr0 + u) * P.n + i] : P.pcol[(long long)(u - nrow) * P.n + i];
         };
@@ -752,7 +786,8 @@ __global__ __launch_bounds__(256) void cg_symv_kernel(ST S, int it) {
     for (int r = 0; r < P.R; ++r) {
         const int bi = I * P.R + r;
         const long long i = (long long)bi * SYM_TB + t;
-        if (bi < P.nb && bi >= J * P.m && bi < J * P.m + P.m && t < SYM_TB && i < n)
+        const bool diag = P.R == 1 ? J == 0 : (bi >= J * P.m && bi < J * P.m + P.m);
+        if (bi < P.nb && diag && t < SYM_TB && i < n)
             pcur[i] = S.z[i] + beta * pprev[i];
     }
     block_sum3(vd, u1, u2, sh);
