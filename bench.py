@@ -78,6 +78,9 @@ def parse():
                     help="run only the a posteriori leg and print its object")
     ap.add_argument("--only-cluster", action="store_true", help="run only the cluster leg and print its object")
     ap.add_argument("--only-symmetry", action="store_true", help="run only the symmetry leg and print its object")
+    ap.add_argument("--only-mixed-assembly", action="store_true",
+                    help="run only the FL_MIXED assembly of the benchmark disk (both s; the FP32 counter runs) "
+                         "and print its object")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches) and exit: the "
                          "reference for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -294,7 +297,8 @@ def main():
         return
     only = {"batch": (args.only_batch, batch_leg), "surrogate": (args.only_surrogate, surrogate_leg),
             "indicators": (args.only_indicators, indicators_leg), "symmetry": (args.only_symmetry, symmetry_leg),
-            "cluster": (args.only_cluster, cluster_leg), "multigrid": (args.only_mg, mg_leg)}
+            "cluster": (args.only_cluster, cluster_leg), "multigrid": (args.only_mg, mg_leg),
+            "mixed_assembly": (args.only_mixed_assembly, mixed_assembly_leg)}
     for key, (flag, fn) in only.items():
         if flag:
             import torch
@@ -756,6 +760,25 @@ def train_surrogate_for(mesh, args, h):
     torch.cuda.synchronize()
     return {"train_total_ms": round((time.perf_counter() - t0) * 1e3, 1), "loss_last": float(np.mean(hist[-200:])),
             "bound_at_s": {"0.25": [float(b) for b in bound[:, 1]], "0.75": [float(b) for b in bound[:, 3]]}}
+
+
+def mixed_assembly_leg(args):
+    """FL_MIXED assembly (FP32 separated pairs) of the benchmark disk,
+    interior DOFs, s in {0.25, 0.75}, once each (after one untimed
+    assembly): the workload of the FP32 counter summary."""
+    from paper_1708_03912_amd import fraclap as F, meshgen as M
+    mesh = M.disk_for_cells(200000, seed=2)
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    om = F.make_opts(dof_mode="interior", precision="mixed")
+    h.assemble(0.75, om)
+    out = {"workload": "unit disk T=%d, interior DOFs, FL_MIXED assembly" % len(mesh["cells"])}
+    for s in (0.25, 0.75):
+        n = h.assemble(s, om)
+        st = h.stats()
+        out[str(s)] = {"n": n, "assemble_ms": round(st.t_assemble_ms, 3), "separated_ms": round(st.t_far_ms, 3)}
+    h.close()
+    return out
 
 
 def mg_leg(args):

@@ -224,6 +224,7 @@ void launch_mass_matvec(const ElemDev& E, const int* dof_node, const int* v2c_pt
                         const unsigned char* vloc, int dim, long long n, const double* x, double* y,
                         hipStream_t st);
 void launch_zero(double* p, long long n, hipStream_t st);
+// FP32 copy of the tiles on and above the diagonal (what the symmetric product reads)
 void launch_to_f32(const double* A, long long lda, long long n, float* A32, hipStream_t st);
 void launch_load_one(const int* dof_node, const int* v2c_ptr, const int* v2c_idx,
                      const double* meas, int dim, long long n, double* b, hipStream_t st);

@@ -975,17 +975,32 @@ void launch_dot2(const double* a, const double* b, const double* c, long long n,
 
 // ------------------------------------------------ mixed precision --
 
-__global__ void to_f32_kernel(const double* A, long long lda, long long n, float* A32) {
-    const long long total = n * lda;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x)
-        A32[i] = (float)A[i];
+// The FP32 copy drives only the symmetric product, which reads the 64 x 64
+// tiles on and above the diagonal: row i is converted from the first column
+// of its block (64 floor(i / 64)) to n - 1, about half the matrix.  One
+// workgroup per row at a time, two entries per thread and step (16-byte
+// reads, 8-byte writes; lda is a multiple of 32, so the pairs are aligned).
+__global__ __launch_bounds__(256) void to_f32_kernel(const double* A, long long lda, long long n, float* A32) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    for (long long i = blockIdx.x; i < n; i += gridDim.x) {
+        const long long j0 = (i / SYM_TB) * SYM_TB;
+        const double* a = A + i * lda;
+        float* b = A32 + i * lda;
+        for (long long j = j0 + 2 * (long long)threadIdx.x; j < n; j += 512) {
+            if (j + 1 < n) {
+                const d2 v = *(const d2*)(a + j);
+                *(f2*)(b + j) = f2{(float)v.x, (float)v.y};
+            } else {
+                b[j] = (float)a[j];
+            }
+        }
+    }
 }
 
 void launch_to_f32(const double* A, long long lda, long long n, float* A32, hipStream_t st) {
     if (n == 0) return;
-    long long blocks = (n * lda + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    const long long blocks = n < 65536 ? n : 65536;
     hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, lda, n, A32);
 }
 
