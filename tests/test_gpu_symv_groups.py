@@ -1,8 +1,10 @@
 """The symmetric product on sizes where a workgroup takes several block rows
 (its column sums gathered over them in LDS): fl_matvec against the full
 matrix's product (torch, FP64, both triangles read), and the FP64 and
-mixed-precision CG against the true residual b - A u.  Disks of 6e4 and
-1.2e5 triangles (n ~ 3e4 and 6e4: 2 and 8 block rows per workgroup)."""
+mixed-precision CG against the true residual b - A u.  Disks of 6e4,
+1.2e5 and 1.5e5 triangles (n ~ 3e4, 6e4, 7.4e4: 2, 8 and 16 block rows per
+workgroup; the block counts 463 and 1163 leave a partial last workgroup
+row)."""
 import numpy as np
 import pytest
 
@@ -24,7 +26,7 @@ def _block_rows(n):
     return R
 
 
-@pytest.mark.parametrize("cells", [60000, 120000])
+@pytest.mark.parametrize("cells", [60000, 120000, 150000])
 def test_grouped_product_and_cg(cells):
     mesh = M.disk_for_cells(cells, seed=7)
     s = 0.6
