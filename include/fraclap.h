@@ -233,7 +233,12 @@ int fl_assemble(fl_handle *h, double s, const fl_opts *opts, int64_t *n_out);
 int64_t fl_matrix_ld(const fl_handle *h);
 
 /* Device pointer to the assembled FP64 matrix (owned by the handle, valid
- * until the next fl_set_mesh / fl_assemble / fl_destroy); NULL before. */
+ * until the next fl_set_mesh / fl_assemble / fl_destroy); NULL before.
+ * The assembly itself writes the tiles on and above the 64 x 64 diagonal
+ * tiles (all that the product and the solvers read); the first call after
+ * an assembly enqueues, on the handle's stream, the copy of the rest of the
+ * lower triangle from the upper one, so read the matrix after that stream
+ * (fl_export_matrix, fl_mg_setup and fl_cluster_build do the same). */
 const double *fl_matrix_ptr(const fl_handle *h);
 
 /* node_of_dof: host int32 array of length n receiving the vertex index of

@@ -47,6 +47,7 @@ int fail(fl_handle* h, int code, const std::string& msg) {
 
 void reset_assembly(fl_handle* h) {
     h->assembled = false;
+    h->lower_pending = false;
     h->mg.ready = false;  // the hierarchy belongs to the previous matrix
     h->sf.ready = false;  // so does the strong-form geometry (DOF map)
     h->hm.ready = false;  // and the cluster approximation
@@ -473,7 +474,12 @@ int fl_set_symmetry(fl_handle* h, int32_t order, int64_t ncells_sector, const in
 
 int64_t fl_matrix_ld(const fl_handle* h) { return (h && h->assembled) ? h->lda : 0; }
 
-const double* fl_matrix_ptr(const fl_handle* h) { return (h && h->assembled) ? h->dA : nullptr; }
+const double* fl_matrix_ptr(const fl_handle* h) {
+    if (!h || !h->assembled) return nullptr;
+    // the caller may read the whole matrix: its lower tiles are written first
+    if (fl_complete_lower(const_cast<fl_handle*>(h)) != FL_OK) return nullptr;
+    return h->dA;
+}
 
 }  // extern "C"
 
@@ -1151,8 +1157,13 @@ int run_assembly(fl_handle* h, const Plan& P, double s, const fl_opts& o, double
                             o.mass_shift, A, lda, h->stream);
     HIPCHK(hipGetLastError());
     if (A) {
-        launch_mirror_lower(A, lda, n, h->stream);
+        // the handle's own matrix: the diagonal tiles now (the symmetric
+        // product reads them whole), the rest when a reader of the full
+        // matrix asks (fl_complete_lower); other matrices: everything
+        const bool own = A == h->dA;
+        launch_mirror_lower(A, lda, n, own ? 1 : 0, h->stream);
         HIPCHK(hipGetLastError());
+        if (own) h->lower_pending = true;
     }
     if (A32) {
         launch_to_f32(A, lda, n, A32, h->stream);
@@ -1236,6 +1247,18 @@ bool fits(fl_handle* h, double bytes) {
 }  // namespace
 
 const fl::RuleTables& fl_base_rules() { return base_rules(); }
+
+int fl_complete_lower(fl_handle* h) {
+    if (!h->lower_pending || !h->dA || h->n <= 1) {
+        h->lower_pending = false;
+        return FL_OK;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    launch_mirror_lower(h->dA, h->lda, h->n, 2, h->stream);
+    HIPCHK(hipGetLastError());
+    h->lower_pending = false;
+    return FL_OK;
+}
 
 void fl_release_dense(fl_handle* h) {
     reset_assembly(h);
@@ -1445,6 +1468,7 @@ int fl_export_matrix(fl_handle* h, double* dst, int64_t ld, int on_device) {
     if (ld < h->n) return fail(h, FL_EINVAL, "ld < n");
     HIPCHK(hipSetDevice(h->device));
     if (h->n == 0) return FL_OK;
+    if (int rc = fl_complete_lower(h)) return rc;
     HIPCHK(hipMemcpy2DAsync(dst, ld * sizeof(double), h->dA, h->lda * sizeof(double),
                             h->n * sizeof(double), h->n,
                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
@@ -1461,6 +1485,7 @@ int fl_import_matrix(fl_handle* h, const double* src, int64_t ld, int on_device)
     HIPCHK(hipSetDevice(h->device));
     h->mg.ready = false;  // the hierarchy's coarse operators came from the old matrix
     h->hm.ready = false;  // so did the cluster approximation
+    h->lower_pending = false;  // the imported matrix is whole
     HIPCHK(hipMemcpy2DAsync(h->dA, h->lda * sizeof(double), src, ld * sizeof(double), h->n * sizeof(double),
                             h->n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
     if (h->opts.precision == FL_MIXED && h->dA32) launch_to_f32(h->dA, h->lda, h->n, h->dA32, h->stream);

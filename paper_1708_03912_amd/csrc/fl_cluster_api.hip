@@ -533,6 +533,7 @@ int fl_cluster_build(fl_handle* h, int32_t m, double eta, int32_t leaf) {
     HDev H{};
     if ((rc = upload_tree(h, t, m, H))) return rc;
     fl_hm& Hm = h->hm;
+    if ((rc = fl_complete_lower(h))) return rc;  // the near blocks are copied from the whole matrix
     launch_h_setup(H, h->dA, h->lda, -0.5 * (h->dim + 2.0 * h->s), h->stream);
     launch_h_diag(h->dA, h->lda, h->n, Hm.d, h->stream);
     HIPCHK(hipGetLastError());

@@ -194,6 +194,9 @@ struct fl_handle {
 
     // assembly
     bool assembled = false;   // single matrix (fl_assemble) present
+    // the single matrix's strictly lower tiles (below the diagonal tiles) are
+    // still to be written from the upper ones (fl_complete_lower)
+    bool lower_pending = false;
     bool planned = false;     // DOF map and device geometry present
     double s = 0.0;
     fl_opts opts{};
@@ -275,6 +278,11 @@ void set_dof_map(fl_handle* h, bool all_nodes);
 // Drop the dense matrix of the last assembly (and everything built on it)
 // and free its device memory.
 void fl_release_dense(fl_handle* h);
+// Write the single matrix's tiles below the diagonal tiles from the upper
+// ones if an assembly left them out (every reader of the full matrix calls
+// it first; the symmetric product reads only the tiles on and above the
+// diagonal).  Asynchronous on the handle's stream.
+int fl_complete_lower(fl_handle* h);
 
 // Quadrature tables independent of s (defined with the assembly driver).
 const fl::RuleTables& fl_base_rules();

@@ -212,8 +212,9 @@ void launch_fix_to_double(const long long* lo, const int* hi, double from_hi, do
                           hipStream_t st);
 // zero row i from column i on, i < n (the upper triangle and the padding)
 void launch_zero_upper(double* A, long long lda, long long n, hipStream_t st);
-// A[j][i] = A[i][j] for j > i (the assembly writes the upper triangle)
-void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st);
+// A[j][i] = A[i][j] for j > i (the assembly writes the upper triangle), in
+// the 64 x 64 tiles: part 0 all, 1 the diagonal tiles, 2 the others
+void launch_mirror_lower(double* A, long long lda, long long n, int part, hipStream_t st);
 // the same into the cluster near field; mass as above
 void launch_scatter_self_near(const ElemDev& E, const int* v2c_ptr, const int* v2c_idx, const int* node2dof,
                               const unsigned char* vloc, int nv, int dim, const double* S, double mass,

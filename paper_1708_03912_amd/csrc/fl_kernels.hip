@@ -2337,10 +2337,12 @@ void launch_fix_to_double(const long long* lo, const int* hi, double from_hi, do
 // Lower triangle from the upper one: workgroup (J, I), I <= J, copies the
 // transpose of the 64 x 64 tile (I, J) through LDS into tile (J, I)
 // (diagonal tiles: their strictly lower part); workgroups with I > J exit.
-__global__ __launch_bounds__(256) void mirror_lower_kernel(double* A, long long lda, int n) {
+// part 0: every tile I <= J (grid nt x nt); 1: the diagonal tiles only
+// (grid nt x 1, I = J); 2: the tiles I < J only
+__global__ __launch_bounds__(256) void mirror_lower_kernel(double* A, long long lda, int n, int part) {
     __shared__ double t[64][65];
-    const int I = blockIdx.y, J = blockIdx.x;
-    if (I > J) return;
+    const int J = blockIdx.x, I = part == 1 ? J : (int)blockIdx.y;
+    if (I > J || (part == 2 && I == J)) return;
     const int r0 = I * 64, c0 = J * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
@@ -2371,10 +2373,10 @@ void launch_zero_upper(double* A, long long lda, long long n, hipStream_t st) {
     hipLaunchKernelGGL(zero_upper_kernel, dim3(blocks), dim3(256), 0, st, A, lda, (int)n);
 }
 
-void launch_mirror_lower(double* A, long long lda, long long n, hipStream_t st) {
+void launch_mirror_lower(double* A, long long lda, long long n, int part, hipStream_t st) {
     if (n <= 1) return;
     const unsigned nt = (unsigned)((n + 63) / 64);
-    hipLaunchKernelGGL(mirror_lower_kernel, dim3(nt, nt), dim3(256), 0, st, A, lda, (int)n);
+    hipLaunchKernelGGL(mirror_lower_kernel, dim3(nt, part == 1 ? 1u : nt), dim3(256), 0, st, A, lda, (int)n, part);
 }
 
 // The same into the cluster near field (entries (i, j) of elements around

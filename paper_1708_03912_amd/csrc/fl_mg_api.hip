@@ -234,8 +234,10 @@ int fl_mg_setup(fl_handle* h, int nlevels, const int64_t* nv, const int32_t* par
             return rc;
         bmax = std::max(bmax, (size_t)n[l] * (size_t)ld_of(n[l - 1]));
     }
-    // Galerkin operators, finest to coarsest, and the diagonals
+    // Galerkin operators, finest to coarsest, and the diagonals (the finest
+    // operator is read whole)
     if ((rc = dalloc(h, &G.B, bmax))) return rc;
+    if ((rc = fl_complete_lower(h))) return rc;
     for (int l = L - 1; l >= 1; --l) {
         const fl_mg_level& V = G.lev[l];
         fl_mg_level& C = G.lev[l - 1];

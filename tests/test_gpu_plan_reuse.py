@@ -120,3 +120,33 @@ def test_plan_reused_by_batch():
         assert np.abs(A - B).max() <= 1e-14 * np.abs(B).max()
     h.close()
     g.close()
+
+
+def test_lower_triangle_on_demand():
+    """The assembly writes the tiles on and above the diagonal tiles; the
+    rest of the lower triangle is copied when a reader of the whole matrix
+    asks (export, the matrix pointer): after two assemblies on one handle
+    the whole matrix equals a fresh handle's, bit for bit, and is exactly
+    symmetric; the product, which reads only the upper tiles, agrees."""
+    mesh = M.disk_for_cells(6000, seed=9)
+    od = F.make_opts(deterministic=1, dof_mode="interior")
+    h = F.Handle(0)
+    h.set_mesh(mesh)
+    n = h.assemble(0.3, od)
+    h.assemble(0.8, od)  # the lower tiles of the s = 0.3 matrix are left in the buffer
+    A = h.export_matrix()
+    assert np.array_equal(_bits(A), _bits(A.T))
+    assert np.array_equal(_bits(A), _bits(_fresh(mesh, 0.8, od)))
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    h.matvec(x, y)
+    yr = A @ x.cpu().numpy()
+    assert np.abs(y.cpu().numpy() - yr).max() <= 1e-13 * np.abs(yr).max()
+    # the device pointer's view after a further assembly
+    h.assemble(0.5, od)
+    V = h.matrix_view()
+    torch.cuda.synchronize()
+    Av = V.cpu().numpy()
+    assert np.array_equal(_bits(Av), _bits(Av.T))
+    assert np.array_equal(_bits(Av), _bits(_fresh(mesh, 0.5, od)))
+    h.close()
