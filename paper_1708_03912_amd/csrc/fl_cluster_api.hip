@@ -24,6 +24,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -136,50 +137,67 @@ void build_host_tree(const fl_handle* h, double eta, int leaf, HostTree& t) {
             }
         }
     }
-    // tree structure (pre-order ids), perm: tree position -> DOF
+    // tree structure (pre-order ids), perm: tree position -> DOF.  A
+    // cluster's DOFs, in the order it received them, are stably sorted along
+    // the axis of largest extent and split at the middle; the shape depends
+    // on the sizes alone, so the pre-order id of every son is known before
+    // the sorts (nodes(s) clusters under one of s DOFs) and the subtrees of
+    // large clusters are built on host threads, with the same result as one
+    // recursion
     t.perm.assign(n, 0);
-    auto coord = [&](int i, int j) { return h->verts[dim * h->dof_node[i] + j]; };
-    std::function<int(std::vector<int>&, int, int, int)> make = [&](std::vector<int>& idx, int lo, int level,
-                                                                    int parent) -> int {
-        HCl c;
-        c.lo = lo;
-        c.hi = lo + (int)idx.size();
-        c.level = level;
-        c.parent = parent;
-        c.blo[0] = c.blo[1] = 0.0;
-        c.side = 0.0;
-        const int cid = (int)t.cl.size();
-        t.cl.push_back(c);
-        for (size_t k = 0; k < idx.size(); ++k) t.perm[lo + k] = idx[k];
-        if ((int)idx.size() > leaf) {
+    std::vector<double> cxy((size_t)n * dim);
+    for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < dim; ++j) cxy[(size_t)i * dim + j] = h->verts[dim * h->dof_node[i] + j];
+    std::function<int64_t(int64_t)> nodes = [&](int64_t sz) -> int64_t {
+        return sz > leaf ? 1 + nodes(sz / 2) + nodes(sz - sz / 2) : 1;
+    };
+    if (n > 0) {
+        t.cl.assign((size_t)nodes(n), HCl{});
+        for (int64_t i = 0; i < n; ++i) t.perm[i] = (int)i;
+        std::function<void(int, int, int, int, int)> make = [&](int lo, int hi, int level, int parent, int cid) {
+            HCl& c = t.cl[cid];
+            c.lo = lo;
+            c.hi = hi;
+            c.level = level;
+            c.parent = parent;
+            c.blo[0] = c.blo[1] = 0.0;
+            c.side = 0.0;
+            const int sz = hi - lo;
+            if (sz <= leaf) return;
             int ax = 0;
             double best = -1.0;
             for (int j = 0; j < dim; ++j) {
                 double lo_ = INFINITY, hi_ = -INFINITY;
-                for (int i : idx) {
-                    lo_ = std::min(lo_, coord(i, j));
-                    hi_ = std::max(hi_, coord(i, j));
+                for (int r = lo; r < hi; ++r) {
+                    const double x = cxy[(size_t)t.perm[r] * dim + j];
+                    lo_ = std::min(lo_, x);
+                    hi_ = std::max(hi_, x);
                 }
                 if (hi_ - lo_ > best) {
                     best = hi_ - lo_;
                     ax = j;
                 }
             }
-            std::vector<int> order(idx);
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return coord(a, ax) < coord(b, ax); });
-            const size_t half = order.size() / 2;
-            std::vector<int> p1(order.begin(), order.begin() + half), p2(order.begin() + half, order.end());
-            const int s1 = make(p1, lo, level + 1, cid);
-            t.cl[cid].sons.push_back(s1);
-            const int s2 = make(p2, lo + (int)half, level + 1, cid);
-            t.cl[cid].sons.push_back(s2);
-        }
-        return cid;
-    };
-    if (n > 0) {
-        std::vector<int> all(n);
-        for (int64_t i = 0; i < n; ++i) all[i] = (int)i;
-        make(all, 0, 0, -1);
+            std::vector<std::pair<double, int>> key(sz);
+            for (int r = lo; r < hi; ++r) key[r - lo] = {cxy[(size_t)t.perm[r] * dim + ax], t.perm[r]};
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                                 return a.first < b.first;
+                             });
+            for (int r = lo; r < hi; ++r) t.perm[r] = key[r - lo].second;
+            const int half = sz / 2;
+            const int s1 = cid + 1, s2 = cid + 1 + (int)nodes(half);
+            c.sons = {s1, s2};
+            if (sz >= 8192) {
+                std::thread left(make, lo, lo + half, level + 1, cid, s1);
+                make(lo + half, hi, level + 1, cid, s2);
+                left.join();
+            } else {
+                make(lo, lo + half, level + 1, cid, s1);
+                make(lo + half, hi, level + 1, cid, s2);
+            }
+        };
+        make(0, (int)n, 0, -1, 0);
     }
     // anchors
     std::vector<int> pos(n);
@@ -615,20 +633,32 @@ int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t 
                     if (dof[a][Ki] >= 0) note(dleaf[dof[a][Ki]]);
             }
         }
-        std::vector<uint64_t> keys;
+        // the block pairs (lo <= hi) as bits of an nblk x nblk map, read out
+        // row by row: the pairs in increasing (lo, hi) order, each once
+        std::vector<uint64_t> bits(((size_t)nblk * nblk + 63) / 64, 0);
         for (int l = 0; l < nleaf; ++l)
             for (int u : partners[l]) {
                 if (u < l) continue;
                 for (int b1 : bl[l])
                     for (int b2 : bl[u]) {
-                        const uint64_t lo = (uint64_t)std::min(b1, b2), hi = (uint64_t)std::max(b1, b2);
-                        keys.push_back((lo << 32) | hi);
+                        const size_t k = (size_t)std::min(b1, b2) * nblk + std::max(b1, b2);
+                        bits[k >> 6] |= 1ull << (k & 63);
                     }
             }
-        std::sort(keys.begin(), keys.end());
-        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-        pairs.resize(keys.size());
-        for (size_t i = 0; i < keys.size(); ++i) pairs[i] = make_int2((int)(keys[i] >> 32), (int)(keys[i] & 0xffffffffu));
+        pairs.clear();
+        for (int lo = 0; lo < nblk; ++lo) {
+            const size_t k0 = (size_t)lo * nblk + lo, k1 = (size_t)(lo + 1) * nblk;
+            for (size_t w = k0 >> 6; w <= (k1 - 1) >> 6; ++w) {
+                uint64_t m = bits[w];
+                if (w == (k0 >> 6)) m &= ~0ull << (k0 & 63);
+                if (w == ((k1 - 1) >> 6) && (k1 & 63)) m &= ~0ull >> (64 - (k1 & 63));
+                while (m) {
+                    const size_t k = (w << 6) + (size_t)__builtin_ctzll(m);
+                    m &= m - 1;
+                    pairs.push_back(make_int2(lo, (int)(k - (size_t)lo * nblk)));
+                }
+            }
+        }
         for (int64_t Ki = 0; Ki < T; ++Ki) aleaf_int[Ki] = aleaf_cell[perm[Ki]];
         for (int64_t Ki = 0; Ki < T; ++Ki) lc_ptr[aleaf_int[Ki] + 1]++;
         for (int l = 0; l < nleaf; ++l) lc_ptr[l + 1] += lc_ptr[l];
