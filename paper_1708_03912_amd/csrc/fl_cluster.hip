@@ -96,7 +96,9 @@ __global__ __launch_bounds__(256) void h_transfer_kernel(HDev H) {
     const int b = rem / H.M, a = rem - b * H.M;
     double x, y;
     cheb_pt(H, c, b, x, y);
-    H.T[id] = lag_box(H, H.cpar[c], a, x, y);
+    const double v = lag_box(H, H.cpar[c], a, x, y);
+    H.T[id] = v;
+    H.Tt[(long long)c * MM + (long long)a * H.M + b] = v;
 }
 
 // Kernel blocks of the admissible pairs, stored column by column:
@@ -136,51 +138,75 @@ __global__ __launch_bounds__(256) void h_gather_kernel(HDev H, const double* __r
     if (r < H.n) H.xp[r] = x[H.perm[r]];
 }
 
-// leaves: xh[c][a] = sum_r V[r][a] xp[r]; one workgroup per leaf
+// leaves: xh[c][a] = sum_r V[r][a] xp[r] (r in increasing order); one
+// workgroup per leaf, eight rows' loads in flight
 __global__ __launch_bounds__(64) void h_up_leaf_kernel(HDev H) {
     const int c = H.leaf[blockIdx.x];
-    for (int a = threadIdx.x; a < H.M; a += blockDim.x) {
+    const int M = H.M, hi = H.chi[c];
+    for (int a = threadIdx.x; a < M; a += blockDim.x) {
         double acc = 0.0;
-        for (int r = H.clo[c]; r < H.chi[c]; ++r) acc = fma(H.V[(long long)r * H.M + a], H.xp[r], acc);
-        H.xh[(long long)c * H.M + a] = acc;
+        int r = H.clo[c];
+        for (; r + 8 <= hi; r += 8) {
+            double v[8], x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                v[j] = H.V[(long long)(r + j) * M + a];
+                x[j] = H.xp[r + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc = fma(v[j], x[j], acc);
+        }
+        for (; r < hi; ++r) acc = fma(H.V[(long long)r * M + a], H.xp[r], acc);
+        H.xh[(long long)c * M + a] = acc;
     }
 }
 
+// lane l's value of v, broadcast through two scalar registers (l uniform)
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // internal clusters of one level: xh[c][a] = sum_sons sum_b T_son[b][a] xh[son][b]
+// (son 0 first, b increasing).  M <= MB <= 64: lane a loads its column of
+// both sons' shift coefficients into registers (for each b the lanes read
+// one contiguous row; every load issued before the first is used) and the
+// sons' coefficients are broadcast from the lanes that hold them; no LDS.
+// Larger M: one lane per output reads its column directly.
+template <int MB>
 __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int4* __restrict__ list) {
     const int4 e = list[blockIdx.x];  // {c, son 0, son 1, -}
-    const int c = e.x, M = H.M;
-    if (M <= 64) {
-        // both sons' shift coefficients staged in LDS (2 M^2 doubles of
-        // dynamic LDS), every load issued before the first product; the
-        // sons' coefficients travel by shuffles; son 0 is summed first
-        extern __shared__ double hdyn[];
-        const int a = threadIdx.x;
-        const double* T0 = H.T + (long long)e.y * M * M;
-        const double* T1 = H.T + (long long)e.z * M * M;
-        for (int i = a; i < M * M; i += 64) {
-            hdyn[i] = T0[i];
-            hdyn[M * M + i] = T1[i];
+    const int c = e.x, M = H.M, MM = M * M;
+    if (M <= MB) {
+        const int a = threadIdx.x, ac = min(a, M - 1);
+        const double* T0 = H.T + (long long)e.y * MM + ac;
+        const double* T1 = H.T + (long long)e.z * MM + ac;
+        // rows b >= M are loaded clamped and zeroed: their terms add exact zeros
+        const double x0 = H.xh[(long long)e.y * M + ac];
+        const double x1 = H.xh[(long long)e.z * M + ac];
+        double t0[MB], t1[MB];
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            const int bc = min(b, M - 1);
+            const double u0 = T0[bc * M], u1 = T1[bc * M];
+            t0[b] = b < M ? u0 : 0.0;
+            t1[b] = b < M ? u1 : 0.0;
         }
-        const double x0 = a < M ? H.xh[(long long)e.y * M + a] : 0.0;
-        const double x1 = a < M ? H.xh[(long long)e.z * M + a] : 0.0;
-        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the products
         double acc = 0.0;
-        for (int b = 0; b < M; ++b) {
-            const double xb = __shfl(x0, b, 64);
-            if (a < M) acc = fma(hdyn[b * M + a], xb, acc);
-        }
-        for (int b = 0; b < M; ++b) {
-            const double xb = __shfl(x1, b, 64);
-            if (a < M) acc = fma(hdyn[M * M + b * M + a], xb, acc);
-        }
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc = fma(t0[b], lane_bcast(x0, b), acc);
+#pragma unroll
+        for (int b = 0; b < MB; ++b) acc = fma(t1[b], lane_bcast(x1, b), acc);
         if (a < M) H.xh[(long long)c * M + a] = acc;
         return;
     }
     for (int a = threadIdx.x; a < M; a += blockDim.x) {
         double acc = 0.0;
         for (int sn : {e.y, e.z}) {
-            const double* Ts = H.T + (long long)sn * M * M;
+            const double* Ts = H.T + (long long)sn * MM;
             const double* xs = H.xh + (long long)sn * M;
             for (int b = 0; b < M; ++b) acc = fma(Ts[b * M + a], xs[b], acc);
         }
@@ -239,31 +265,61 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
 }
 
 // clusters of one level (>= 1): yh[c][b] += sum_a T_c[b][a] yh[parent][a]
+// (a increasing).  M <= MB <= 64: lane b loads row b of T_c from the
+// transposed copy (for each a the lanes read one contiguous row of it) into
+// registers and the parent's coefficients are broadcast; no LDS.  Larger M:
+// one lane per output reads its row directly.
+template <int MB>
 __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restrict__ list) {
     const int4 e = list[blockIdx.x];  // {c, parent, -, -}
-    const int c = e.x, M = H.M;
-    const double* Tc = H.T + (long long)c * M * M;
+    const int c = e.x, M = H.M, MM = M * M;
     const double* yp = H.yh + (long long)e.y * M;
-    if (M <= 64) {
-        extern __shared__ double hdyn[];  // M^2 doubles of dynamic LDS
-        const int b = threadIdx.x;
-        for (int i = b; i < M * M; i += 64) hdyn[i] = Tc[i];
-        const double yv = b < M ? yp[b] : 0.0;
-        __syncthreads();
-        double acc = 0.0;
-        for (int a = 0; a < M; ++a) {
-            const double ya = __shfl(yv, a, 64);
-            if (b < M) acc = fma(hdyn[b * M + a], ya, acc);
+    if (M <= MB) {
+        const int b = threadIdx.x, bc = min(b, M - 1);
+        const double* Tc = H.Tt + (long long)c * MM + bc;
+        const double yv = yp[bc];
+        double t[MB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) {
+            const double u = Tc[min(a, M - 1) * M];
+            t[a] = a < M ? u : 0.0;
         }
+        __builtin_amdgcn_sched_barrier(0);  // every load issued before the products
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < MB; ++a) acc = fma(t[a], lane_bcast(yv, a), acc);
         if (b < M) H.yh[(long long)c * M + b] += acc;
         return;
     }
+    const double* Tc = H.T + (long long)c * MM;
     for (int b = threadIdx.x; b < M; b += blockDim.x) {
         double acc = 0.0;
         for (int a = 0; a < M; ++a) acc = fma(Tc[b * M + a], yp[a], acc);
         H.yh[(long long)c * M + b] += acc;
     }
 }
+
+// a per-level pass kernel with MB = the smallest of 4, 9, 16, 25, 36, 49, 64
+// with MB >= M (64 also for M > 64, where the kernels take their direct form)
+#define FL_MB_LAUNCH(KER, GRID, ...)                                                                  \
+    do {                                                                                               \
+        const dim3 g_((unsigned)(GRID)), b_(64);                                                       \
+        if (H.M <= 4)                                                                                  \
+            hipLaunchKernelGGL(KER<4>, g_, b_, 0, st, __VA_ARGS__);                                    \
+        else if (H.M <= 9)                                                                             \
+            hipLaunchKernelGGL(KER<9>, g_, b_, 0, st, __VA_ARGS__);                                    \
+        else if (H.M <= 16)                                                                            \
+            hipLaunchKernelGGL(KER<16>, g_, b_, 0, st, __VA_ARGS__);                                   \
+        else if (H.M <= 25)                                                                            \
+            hipLaunchKernelGGL(KER<25>, g_, b_, 0, st, __VA_ARGS__);                                   \
+        else if (H.M <= 36)                                                                            \
+            hipLaunchKernelGGL(KER<36>, g_, b_, 0, st, __VA_ARGS__);                                   \
+        else if (H.M <= 49)                                                                            \
+            hipLaunchKernelGGL(KER<49>, g_, b_, 0, st, __VA_ARGS__);                                   \
+        else                                                                                           \
+            hipLaunchKernelGGL(KER<64>, g_, b_, 0, st, __VA_ARGS__);                                   \
+    } while (0)
+
 
 // leaves: y[perm[r]] = -C sum_a V[r][a] yh[c][a] + sum over near (c, t) of
 // the block row times xp[t]; one workgroup per leaf, rows in chunks of 32
@@ -403,6 +459,21 @@ __global__ __launch_bounds__(256) void h_self_far_kernel(HDev H, ElemDev E, int 
 
 inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
+// leaf coefficients (unless leaf_done), upward pass (one launch per level,
+// deepest first), far field, downward pass (one launch per level, shallowest
+// first); the lists hold four ints per cluster (device allocations: 256-byte
+// aligned)
+void h_passes(const HDev& H, const int* const* up_lists, const int* up_counts, int n_up,
+              const int* const* down_lists, const int* down_counts, int n_down, int leaf_done, hipStream_t st) {
+    if (!leaf_done) hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
+    for (int l = 0; l < n_up; ++l)
+        if (up_counts[l] > 0) FL_MB_LAUNCH(h_up_kernel, up_counts[l], H, (const int4*)up_lists[l]);
+    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
+    for (int l = 0; l < n_down; ++l)
+        if (down_counts[l] > 0) FL_MB_LAUNCH(h_down_kernel, down_counts[l], H, (const int4*)down_lists[l]);
+}
+#undef FL_MB_LAUNCH
+
 }  // namespace
 
 void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr, const int* lc_idx,
@@ -411,16 +482,7 @@ void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr
                        hipStream_t st) {
     if (H.n == 0 || T == 0) return;
     hipLaunchKernelGGL(h_density_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H, E, lc_ptr, lc_idx);
-    const size_t lds = H.M <= 64 ? sizeof(double) * H.M * H.M : 0;
-    for (int l = 0; l < n_up; ++l)
-        if (up_counts[l] > 0)
-            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, H,
-                               (const int4*)up_lists[l]);
-    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
-    for (int l = 0; l < n_down; ++l)
-        if (down_counts[l] > 0)
-            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, H,
-                               (const int4*)down_lists[l]);
+    h_passes(H, up_lists, up_counts, n_up, down_lists, down_counts, n_down, 1, st);
     hipLaunchKernelGGL(h_self_far_kernel, dim3(nb256(T)), dim3(256), 0, st, H, E, T, aleafc, C, S);
 }
 
@@ -440,18 +502,7 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
                      double* y, hipStream_t st) {
     if (H.n == 0) return;
     hipLaunchKernelGGL(h_gather_kernel, dim3(nb256(H.n)), dim3(256), 0, st, H, x);
-    hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
-    // the lists hold four ints per cluster (device allocations: 256-byte aligned)
-    const size_t lds = H.M <= 64 ? sizeof(double) * H.M * H.M : 0;
-    for (int l = 0; l < n_up; ++l)
-        if (up_counts[l] > 0)
-            hipLaunchKernelGGL(h_up_kernel, dim3((unsigned)up_counts[l]), dim3(64), 2 * lds, st, H,
-                               (const int4*)up_lists[l]);
-    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
-    for (int l = 0; l < n_down; ++l)
-        if (down_counts[l] > 0)
-            hipLaunchKernelGGL(h_down_kernel, dim3((unsigned)down_counts[l]), dim3(64), lds, st, H,
-                               (const int4*)down_lists[l]);
+    h_passes(H, up_lists, up_counts, n_up, down_lists, down_counts, n_down, 0, st);
     hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(256), 0, st, H, C, y);
 }
 

@@ -489,6 +489,7 @@ int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
     H.ndst = p_ndst;
     H.noff = p_noff;
     if ((rc = hm_alloc(h, &H.V, (size_t)n * M)) || (rc = hm_alloc(h, &H.T, (size_t)nc * M * M)) ||
+        (rc = hm_alloc(h, &H.Tt, (size_t)nc * M * M)) ||
         (rc = hm_alloc(h, &H.Kb, (size_t)H.nfar * M * M)) || (rc = hm_alloc(h, &H.An, (size_t)near_entries)) ||
         (rc = hm_alloc(h, &H.xp, (size_t)n)) || (rc = hm_alloc(h, &H.xh, (size_t)nc * M)) ||
         (rc = hm_alloc(h, &H.yh, (size_t)nc * M)) || (rc = hm_alloc(h, &Hm.d, (size_t)n)) ||

@@ -356,6 +356,7 @@ struct HDev {
     const double* qw;
     double* V;              // n x M basis coefficients (tree order)
     double* T;              // nc x M x M shift coefficients T_c[b][a]
+    double* Tt;             // the same transposed, Tt_c[a][b] = T_c[b][a]
     long long nfar;         // admissible pairs, grouped by the first cluster
     const long long* fptr;  // nc + 1
     const int* fsrc;
