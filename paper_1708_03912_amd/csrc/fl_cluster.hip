@@ -175,10 +175,10 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
 // one contiguous row; every load issued before the first is used) and the
 // sons' coefficients are broadcast from the lanes that hold them; no LDS.
 // Larger M: one lane per output reads its column directly.
-template <int MB>
+template <int MB, bool EX>
 __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int4* __restrict__ list) {
     const int4 e = list[blockIdx.x];  // {c, son 0, son 1, -}
-    const int c = e.x, M = H.M, MM = M * M;
+    const int c = e.x, M = EX ? MB : H.M, MM = M * M;
     if (M <= MB) {
         const int a = threadIdx.x, ac = min(a, M - 1);
         const double* T0 = H.T + (long long)e.y * MM + ac;
@@ -215,31 +215,58 @@ __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int4* __restrict
 }
 
 // far field: yh[s][a] = sum over admissible (s, t) of sum_b K[a][b] xh[t][b];
-// one workgroup per cluster, four groups of 64 lanes take every fourth pair,
-// their partial sums are added in group order
+// one workgroup per cluster, four groups of 64 lanes take every fourth pair
+// (pairs in increasing order, b increasing within a pair), their partial
+// sums are added in group order.  M <= MB <= 64: per pair, lane a loads its
+// block column (K[a][b] for every b; the lanes of a wave read consecutive
+// entries) and the partner's cluster vector, every load issued before the
+// first product; the partner index of the next pair is fetched with them,
+// so a pair waits for one memory latency; the cluster vector is broadcast
+// from the lanes that hold it.  Larger M: 16 loads of the block column in
+// flight before their products.
+template <int MB>
+__device__ __forceinline__ void far_fetch(const HDev& H, int M, long long p, int t, int ac, double (&k)[MB], double& x) {
+    const double* Kp = H.Kb + p * M * M + ac;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const double u = Kp[min(b, M - 1) * M];
+        k[b] = b < M ? u : 0.0;  // rows b >= M add exact zeros
+    }
+    x = H.xh[(long long)t * M + ac];
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products that follow
+}
+
+template <int MB, bool EX>
 __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
     __shared__ double red[4][64];
     const int c = blockIdx.x;
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int a0 = 0; a0 < H.M; a0 += 64) {
+    const int M = EX ? MB : H.M;
+    if (M <= MB) {
+        const int ac = min(lane, M - 1);
+        const long long pb = H.fptr[c] + g, pe = H.fptr[c + 1];
+        double acc = 0.0;
+        if (pb < pe) {
+            double k[MB], x;
+            int t = H.fdst[pb];
+            for (long long p = pb; p < pe; p += 4) {
+                const int tn = H.fdst[min(p + 4, pe - 1)];
+                far_fetch<MB>(H, M, p, t, ac, k, x);
+#pragma unroll
+                for (int b = 0; b < MB; ++b) acc = fma(k[b], lane_bcast(x, b), acc);
+                t = tn;
+            }
+        }
+        red[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && lane < M) H.yh[(long long)c * M + lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        return;
+    }
+    for (int a0 = 0; a0 < M; a0 += 64) {
         const int a = a0 + lane;
         double acc = 0.0;
-        if (H.M == 36) {
-            // m = 6 in 2D: the block column of this lane in 36 registers,
-            // every load issued before the first product
-            for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
-                const double* Kp = H.Kb + p * 36 * 36;
-                const double xv = lane < 36 ? H.xh[(long long)H.fdst[p] * 36 + lane] : 0.0;
-                double kr[36];
-#pragma unroll
-                for (int b = 0; b < 36; ++b) kr[b] = lane < 36 ? Kp[b * 36 + lane] : 0.0;
-#pragma unroll
-                for (int b = 0; b < 36; ++b) acc = fma(kr[b], __shfl(xv, b, 64), acc);
-            }
-        } else if (a < H.M) {
-            // 16 loads of the block column in flight before their products
-            // (the sum keeps the order b = 0, 1, ...)
-            const int M = H.M;
+        if (a < M) {
+            // the sum keeps the order b = 0, 1, ...
             for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
                 const double* Kp = H.Kb + p * M * M;
                 const double* xt = H.xh + (long long)H.fdst[p] * M;
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
         }
         red[g][lane] = acc;
         __syncthreads();
-        if (g == 0 && a < H.M) H.yh[(long long)c * H.M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        if (g == 0 && a < M) H.yh[(long long)c * M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
         __syncthreads();
     }
 }
@@ -269,10 +296,10 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
 // transposed copy (for each a the lanes read one contiguous row of it) into
 // registers and the parent's coefficients are broadcast; no LDS.  Larger M:
 // one lane per output reads its row directly.
-template <int MB>
+template <int MB, bool EX>
 __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restrict__ list) {
     const int4 e = list[blockIdx.x];  // {c, parent, -, -}
-    const int c = e.x, M = H.M, MM = M * M;
+    const int c = e.x, M = EX ? MB : H.M, MM = M * M;
     const double* yp = H.yh + (long long)e.y * M;
     if (M <= MB) {
         const int b = threadIdx.x, bc = min(b, M - 1);
@@ -299,25 +326,30 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restri
     }
 }
 
-// a per-level pass kernel with MB = the smallest of 4, 9, 16, 25, 36, 49, 64
-// with MB >= M (64 also for M > 64, where the kernels take their direct form)
-#define FL_MB_LAUNCH(KER, GRID, ...)                                                                  \
-    do {                                                                                               \
-        const dim3 g_((unsigned)(GRID)), b_(64);                                                       \
-        if (H.M <= 4)                                                                                  \
-            hipLaunchKernelGGL(KER<4>, g_, b_, 0, st, __VA_ARGS__);                                    \
-        else if (H.M <= 9)                                                                             \
-            hipLaunchKernelGGL(KER<9>, g_, b_, 0, st, __VA_ARGS__);                                    \
-        else if (H.M <= 16)                                                                            \
-            hipLaunchKernelGGL(KER<16>, g_, b_, 0, st, __VA_ARGS__);                                   \
-        else if (H.M <= 25)                                                                            \
-            hipLaunchKernelGGL(KER<25>, g_, b_, 0, st, __VA_ARGS__);                                   \
-        else if (H.M <= 36)                                                                            \
-            hipLaunchKernelGGL(KER<36>, g_, b_, 0, st, __VA_ARGS__);                                   \
-        else if (H.M <= 49)                                                                            \
-            hipLaunchKernelGGL(KER<49>, g_, b_, 0, st, __VA_ARGS__);                                   \
-        else                                                                                           \
-            hipLaunchKernelGGL(KER<64>, g_, b_, 0, st, __VA_ARGS__);                                   \
+// a pass kernel for M: M itself as a compile-time constant for the
+// squares 4, 9, ..., 64 (every M in 2D), else MB = the next of 4, 9, 16
+// above M (1D) or 64 (M > 64: the kernels take their direct form)
+#define FL_MB_LAUNCH(KER, GRID, BLOCK, ...)                                              \
+    do {                                                                                 \
+        const dim3 g_((unsigned)(GRID)), b_(BLOCK);                                      \
+        switch (H.M) {                                                                   \
+            case 4: hipLaunchKernelGGL((KER<4, true>), g_, b_, 0, st, __VA_ARGS__); break;   \
+            case 9: hipLaunchKernelGGL((KER<9, true>), g_, b_, 0, st, __VA_ARGS__); break;   \
+            case 16: hipLaunchKernelGGL((KER<16, true>), g_, b_, 0, st, __VA_ARGS__); break; \
+            case 25: hipLaunchKernelGGL((KER<25, true>), g_, b_, 0, st, __VA_ARGS__); break; \
+            case 36: hipLaunchKernelGGL((KER<36, true>), g_, b_, 0, st, __VA_ARGS__); break; \
+            case 49: hipLaunchKernelGGL((KER<49, true>), g_, b_, 0, st, __VA_ARGS__); break; \
+            case 64: hipLaunchKernelGGL((KER<64, true>), g_, b_, 0, st, __VA_ARGS__); break; \
+            default:                                                                     \
+                if (H.M < 4)                                                             \
+                    hipLaunchKernelGGL((KER<4, false>), g_, b_, 0, st, __VA_ARGS__);     \
+                else if (H.M < 9)                                                        \
+                    hipLaunchKernelGGL((KER<9, false>), g_, b_, 0, st, __VA_ARGS__);     \
+                else if (H.M < 16)                                                       \
+                    hipLaunchKernelGGL((KER<16, false>), g_, b_, 0, st, __VA_ARGS__);    \
+                else                                                                     \
+                    hipLaunchKernelGGL((KER<64, false>), g_, b_, 0, st, __VA_ARGS__);    \
+        }                                                                                \
     } while (0)
 
 
@@ -467,10 +499,10 @@ void h_passes(const HDev& H, const int* const* up_lists, const int* up_counts, i
               const int* const* down_lists, const int* down_counts, int n_down, int leaf_done, hipStream_t st) {
     if (!leaf_done) hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
     for (int l = 0; l < n_up; ++l)
-        if (up_counts[l] > 0) FL_MB_LAUNCH(h_up_kernel, up_counts[l], H, (const int4*)up_lists[l]);
-    hipLaunchKernelGGL(h_far_kernel, dim3((unsigned)H.nc), dim3(256), 0, st, H);
+        if (up_counts[l] > 0) FL_MB_LAUNCH(h_up_kernel, up_counts[l], 64, H, (const int4*)up_lists[l]);
+    FL_MB_LAUNCH(h_far_kernel, H.nc, 256, H);
     for (int l = 0; l < n_down; ++l)
-        if (down_counts[l] > 0) FL_MB_LAUNCH(h_down_kernel, down_counts[l], H, (const int4*)down_lists[l]);
+        if (down_counts[l] > 0) FL_MB_LAUNCH(h_down_kernel, down_counts[l], 64, H, (const int4*)down_lists[l]);
 }
 #undef FL_MB_LAUNCH
 
