@@ -354,16 +354,77 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restri
 
 
 // leaves: y[perm[r]] = -C sum_a V[r][a] yh[c][a] + sum over near (c, t) of
-// the block row times xp[t]; one workgroup per leaf, rows in chunks of 32
-// lanes, eight groups take every eighth near block (column-major blocks:
-// the lanes of a group read consecutive entries), group partials added in
-// group order
+// the block row times xp[t]; one workgroup per leaf, eight groups of 32
+// lanes take every eighth near block (column-major blocks: the lanes of a
+// group read consecutive entries), group partials added in group order.
+// Leaves of at most 32 DOFs: lane i loads its whole block row (every load
+// issued before the first product) and the partner's x, broadcast within
+// the group; the next block's range and offset are fetched with them, so a
+// block waits for one memory latency; the row sum runs over the columns in
+// order.  Larger leaves: rows in chunks of 32, four partial sums over the
+// columns.
+template <int MB, bool EX>
 __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
     __shared__ double red[8][32];
     const int li = blockIdx.x;
     const int c = H.leaf[li];
     const int lo = H.clo[c], nr = H.chi[c] - lo;
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int M = EX ? MB : H.M;
+    if (H.lmax <= 32 && M <= MB) {
+        const int ic = min(lane, nr - 1);  // lanes >= nr repeat the last row and store nothing
+        double acc = 0.0;
+        if (g == 0) {
+            // sum over a in order, every load issued before the first product
+            const double* Vr = H.V + (long long)(lo + ic) * M;
+            const double* yc = H.yh + (long long)c * M;
+            double v[MB], w[MB];
+#pragma unroll
+            for (int a = 0; a < MB; ++a) {
+                const int ac = min(a, M - 1);
+                const double u = Vr[ac];
+                v[a] = a < M ? u : 0.0;
+                w[a] = yc[ac];
+            }
+            double f = 0.0;
+#pragma unroll
+            for (int a = 0; a < MB; ++a) f = fma(v[a], w[a], f);
+            acc = -C * f;
+        }
+        const int eb = H.lnptr[li] + g, ee = H.lnptr[li + 1];
+        if (eb < ee) {
+            int2 rg = H.nrng[eb];
+            long long off = H.noff[eb];
+            for (int e = eb; e < ee; e += 8) {
+                const int en = min(e + 8, ee - 1);
+                const int2 rgn = H.nrng[en];
+                const long long offn = H.noff[en];
+                const double* blk = H.An + off + ic;
+                double b[32];
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const double u = blk[(long long)min(j, rg.y - 1) * nr];
+                    b[j] = j < rg.y ? u : 0.0;  // columns j >= nt add exact zeros
+                }
+                const double xv = H.xp[rg.x + min(lane, rg.y - 1)];
+                __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products
+                double sr = 0.0;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) sr = fma(b[j], __shfl(xv, j, 32), sr);
+                acc += sr;
+                rg = rgn;
+                off = offn;
+            }
+        }
+        red[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && lane < nr) {
+            double tot = red[0][lane];
+            for (int k = 1; k < 8; ++k) tot += red[k][lane];
+            y[H.perm[lo + lane]] = tot;
+        }
+        return;
+    }
     for (int r0 = 0; r0 < nr; r0 += 32) {
         const int i = r0 + lane;
         double acc = 0.0;
@@ -371,7 +432,7 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
             if (g == 0) {
                 const long long r = lo + i;
                 double f = 0.0;
-                for (int a = 0; a < H.M; ++a) f = fma(H.V[r * H.M + a], H.yh[(long long)c * H.M + a], f);
+                for (int a = 0; a < M; ++a) f = fma(H.V[r * M + a], H.yh[(long long)c * M + a], f);
                 acc = -C * f;
             }
             for (int e = H.lnptr[li] + g; e < H.lnptr[li + 1]; e += 8) {
@@ -504,7 +565,6 @@ void h_passes(const HDev& H, const int* const* up_lists, const int* up_counts, i
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0) FL_MB_LAUNCH(h_down_kernel, down_counts[l], 64, H, (const int4*)down_lists[l]);
 }
-#undef FL_MB_LAUNCH
 
 }  // namespace
 
@@ -535,8 +595,9 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
     if (H.n == 0) return;
     hipLaunchKernelGGL(h_gather_kernel, dim3(nb256(H.n)), dim3(256), 0, st, H, x);
     h_passes(H, up_lists, up_counts, n_up, down_lists, down_counts, n_down, 0, st);
-    hipLaunchKernelGGL(h_leaf_out_kernel, dim3((unsigned)H.nleaf), dim3(256), 0, st, H, C, y);
+    FL_MB_LAUNCH(h_leaf_out_kernel, H.nleaf, 256, H, C, y);
 }
+#undef FL_MB_LAUNCH
 
 }  // namespace fl
 

@@ -352,17 +352,21 @@ int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
     }
     for (int c = 0; c < nc; ++c) fptr[c + 1] += fptr[c];
     const int nleaf = (int)t.leaf_ids.size();
-    std::vector<int> lnptr(nleaf + 1, 0), nsrc, ndst;
+    std::vector<int> lnptr(nleaf + 1, 0), nsrc, ndst, nrng;
     std::vector<long long> noff;
     long long near_entries = 0;
     for (auto& p : t.near) {
         nsrc.push_back(p.first);
         ndst.push_back(p.second);
+        nrng.push_back(clo[p.second]);
+        nrng.push_back(chi[p.second] - clo[p.second]);
         noff.push_back(near_entries);
         near_entries += (long long)(chi[p.first] - clo[p.first]) * (chi[p.second] - clo[p.second]);
         lnptr[t.leaf_of[p.first] + 1]++;
     }
     for (int l = 0; l < nleaf; ++l) lnptr[l + 1] += lnptr[l];
+    int lmax = 0;
+    for (int c : t.leaf_ids) lmax = std::max(lmax, chi[c] - clo[c]);
     // Chebyshev points of the first kind on [0, 1] (increasing) and the
     // (m+1)-point cell rule
     std::vector<double> tnode(m);
@@ -424,7 +428,7 @@ int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
     H.nq = (int)qw.size();
     int rc;
     const int *p_clo, *p_chi, *p_cpar, *p_sptr, *p_sidx, *p_perm, *p_node, *p_rleaf, *p_leaf, *p_cells, *p_vptr,
-        *p_vidx, *p_fsrc, *p_fdst, *p_lnptr, *p_nsrc, *p_ndst;
+        *p_vidx, *p_fsrc, *p_fdst, *p_lnptr, *p_nsrc, *p_ndst, *p_nrng;
     const double *p_box, *p_tnode, *p_verts, *p_qlam, *p_qw;
     const long long *p_fptr, *p_noff;
     std::vector<int> cells(h->cells.begin(), h->cells.end());
@@ -456,6 +460,7 @@ int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
     UP(p_lnptr, lnptr);
     UP(p_nsrc, nsrc);
     UP(p_ndst, ndst);
+    UP(p_nrng, nrng);
     UP(p_box, box);
     UP(p_tnode, tnode);
     UP(p_verts, verts);
@@ -488,6 +493,8 @@ int upload_tree(fl_handle* h, const HostTree& t, int m, HDev& H) {
     H.nsrc = p_nsrc;
     H.ndst = p_ndst;
     H.noff = p_noff;
+    H.nrng = (const int2*)p_nrng;
+    H.lmax = lmax;
     if ((rc = hm_alloc(h, &H.V, (size_t)n * M)) || (rc = hm_alloc(h, &H.T, (size_t)nc * M * M)) ||
         (rc = hm_alloc(h, &H.Tt, (size_t)nc * M * M)) ||
         (rc = hm_alloc(h, &H.Kb, (size_t)H.nfar * M * M)) || (rc = hm_alloc(h, &H.An, (size_t)near_entries)) ||

@@ -367,6 +367,8 @@ struct HDev {
     const int* nsrc;
     const int* ndst;
     const long long* noff;  // offset of each block in An
+    const int2* nrng;       // per near pair: first tree position and size of its second leaf
+    int lmax;               // largest leaf (DOFs)
     double* An;             // near blocks, column by column
     double* xp;             // product workspace: x and y in tree order, cluster vectors
     double* xh;
