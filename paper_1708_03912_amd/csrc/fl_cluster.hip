@@ -85,6 +85,61 @@ __global__ __launch_bounds__(256) void h_basis_kernel(HDev H) {
     H.V[id] = acc;
 }
 
+// V in 2D with MC points per direction known at compile time: one thread
+// per r forms the whole row (MC^2 entries); at each quadrature point the 2 MC
+// one-dimensional Lagrange values are formed once (by lag, with the nodes in
+// registers) and their products taken: the same numbers and the same sums
+// (cells, then points, in order) as h_basis_kernel.
+template <int MC>
+__global__ __launch_bounds__(256) void h_basis_row_kernel(HDev H) {
+    constexpr int MM = MC * MC;
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= H.n) return;
+    double t[MC];
+#pragma unroll
+    for (int k = 0; k < MC; ++k) t[k] = H.tnode[k];
+    const int v = H.node[r];
+    const double* bx = H.box + 3 * H.rleaf[r];
+    const double bx0 = bx[0], bx1 = bx[1], bs = bx[2];
+    double acc[MM];
+#pragma unroll
+    for (int a = 0; a < MM; ++a) acc[a] = 0.0;
+    for (int e = H.vptr[v]; e < H.vptr[v + 1]; ++e) {
+        const int K = H.vidx[e];
+        const int* cv = H.cells + (long long)K * 3;
+        double P[3][2];
+        int loc = 0;
+        for (int b = 0; b < 3; ++b) {
+            P[b][0] = H.verts[(long long)cv[b] * 2];
+            P[b][1] = H.verts[(long long)cv[b] * 2 + 1];
+            if (cv[b] == v) loc = b;
+        }
+        const double meas = 0.5 * fabs((P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[2][0] - P[0][0]) * (P[1][1] - P[0][1]));
+        for (int q = 0; q < H.nq; ++q) {
+            const double* l = H.qlam + q * 3;
+            double x = 0.0, y = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                x += l[b] * P[b][0];
+                y += l[b] * P[b][1];
+            }
+            const double w = meas * H.qw[q] * l[loc];
+            const double xi = (x - bx0) / bs, eta = (y - bx1) / bs;
+            double l0[MC], l1[MC];
+#pragma unroll
+            for (int k = 0; k < MC; ++k) {
+                l0[k] = lag(t, MC, k, xi);
+                l1[k] = lag(t, MC, k, eta);
+            }
+#pragma unroll
+            for (int a0 = 0; a0 < MC; ++a0)
+#pragma unroll
+                for (int a1 = 0; a1 < MC; ++a1) acc[a0 * MC + a1] += w * (l0[a0] * l1[a1]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < MM; ++a) H.V[r * MM + a] = acc[a];
+}
+
 // T_c[b][a] = L_a^parent(xi_b^c), clusters c >= 1.  One thread per entry.
 __global__ __launch_bounds__(256) void h_transfer_kernel(HDev H) {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -500,6 +555,55 @@ __global__ __launch_bounds__(64) void h_density_kernel(HDev H, ElemDev E, const 
     }
 }
 
+// The same in 2D with MC points per direction known at compile time: the
+// leaf's quadrature points (elements in order, then points) in chunks of
+// 64; lane p of a chunk forms point p's weight and its 2 MC one-dimensional
+// Lagrange values in LDS, then lane a sums the chunk's terms in order --
+// the same numbers and sums as h_density_kernel.
+template <int MC>
+__global__ __launch_bounds__(64) void h_density_tab_kernel(HDev H, ElemDev E, const int* __restrict__ lc_ptr,
+                                                           const int* __restrict__ lc_idx) {
+    constexpr int MM = MC * MC;
+    __shared__ double Wp[64], L0[64][MC], L1[64][MC];
+    const int li = blockIdx.x;
+    const int c = H.leaf[li];
+    const int tid = threadIdx.x, a0 = tid / MC, a1 = tid - a0 * MC;
+    const int e0 = lc_ptr[li], nq = H.nq;
+    const int np = (lc_ptr[li + 1] - e0) * nq;
+    const double* bx = H.box + 3 * c;
+    double acc = 0.0;
+    for (int p0 = 0; p0 < np; p0 += 64) {
+        const int p = p0 + tid;
+        if (p < np) {
+            const int e = p / nq, q = p - e * nq;
+            const int K = lc_idx[e0 + e];
+            double P[3][2];
+            for (int b = 0; b < 3; ++b) {
+                P[b][0] = E.x[2 * b][K];
+                P[b][1] = E.x[2 * b + 1][K];
+            }
+            const double* l = H.qlam + q * 3;
+            double x = 0.0, y = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                x += l[b] * P[b][0];
+                y += l[b] * P[b][1];
+            }
+            Wp[tid] = E.meas[K] * H.qw[q];
+            const double xi = (x - bx[0]) / bx[2], eta = (y - bx[1]) / bx[2];
+            for (int k = 0; k < MC; ++k) {
+                L0[tid][k] = lag(H.tnode, MC, k, xi);
+                L1[tid][k] = lag(H.tnode, MC, k, eta);
+            }
+        }
+        __syncthreads();
+        const int cnt = min(64, np - p0);
+        if (tid < MM)
+            for (int j = 0; j < cnt; ++j) acc += Wp[j] * (L0[j][a0] * L1[j][a1]);
+        __syncthreads();
+    }
+    if (tid < MM) H.xh[(long long)c * MM + tid] = acc;
+}
+
 // S[K][ab] += C int_K l_a l_b g, g(x) = sum_a L_a^c(x) yh[c][a] (c: the leaf
 // of K's anchor), by the (m+1)-point rule; one thread per element.  The
 // tensor basis is evaluated as sum_a0 L_a0(x) sum_a1 L_a1(y) yh[a0 m + a1].
@@ -573,13 +677,37 @@ void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr
                        const int* const* down_lists, const int* down_counts, int n_down, double C, double* S,
                        hipStream_t st) {
     if (H.n == 0 || T == 0) return;
-    hipLaunchKernelGGL(h_density_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H, E, lc_ptr, lc_idx);
+    {
+        const dim3 g((unsigned)H.nleaf), b(64);
+        switch (H.dim == 2 ? H.M : 0) {
+            case 4: hipLaunchKernelGGL(h_density_tab_kernel<2>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 9: hipLaunchKernelGGL(h_density_tab_kernel<3>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 16: hipLaunchKernelGGL(h_density_tab_kernel<4>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 25: hipLaunchKernelGGL(h_density_tab_kernel<5>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 36: hipLaunchKernelGGL(h_density_tab_kernel<6>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 49: hipLaunchKernelGGL(h_density_tab_kernel<7>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            case 64: hipLaunchKernelGGL(h_density_tab_kernel<8>, g, b, 0, st, H, E, lc_ptr, lc_idx); break;
+            default: hipLaunchKernelGGL(h_density_kernel, g, b, 0, st, H, E, lc_ptr, lc_idx);
+        }
+    }
     h_passes(H, up_lists, up_counts, n_up, down_lists, down_counts, n_down, 1, st);
     hipLaunchKernelGGL(h_self_far_kernel, dim3(nb256(T)), dim3(256), 0, st, H, E, T, aleafc, C, S);
 }
 
 void launch_h_setup(const HDev& H, const double* A, long long lda, double pe, hipStream_t st) {
-    if (H.n > 0) hipLaunchKernelGGL(h_basis_kernel, dim3(nb256(H.n * H.M)), dim3(256), 0, st, H);
+    if (H.n > 0) {
+        const dim3 g(nb256(H.n)), b(256);
+        switch (H.dim == 2 ? H.M : 0) {
+            case 4: hipLaunchKernelGGL(h_basis_row_kernel<2>, g, b, 0, st, H); break;
+            case 9: hipLaunchKernelGGL(h_basis_row_kernel<3>, g, b, 0, st, H); break;
+            case 16: hipLaunchKernelGGL(h_basis_row_kernel<4>, g, b, 0, st, H); break;
+            case 25: hipLaunchKernelGGL(h_basis_row_kernel<5>, g, b, 0, st, H); break;
+            case 36: hipLaunchKernelGGL(h_basis_row_kernel<6>, g, b, 0, st, H); break;
+            case 49: hipLaunchKernelGGL(h_basis_row_kernel<7>, g, b, 0, st, H); break;
+            case 64: hipLaunchKernelGGL(h_basis_row_kernel<8>, g, b, 0, st, H); break;
+            default: hipLaunchKernelGGL(h_basis_kernel, dim3(nb256(H.n * H.M)), b, 0, st, H);
+        }
+    }
     if (H.nc > 1)
         hipLaunchKernelGGL(h_transfer_kernel, dim3(nb256((long long)H.nc * H.M * H.M)), dim3(256), 0, st, H);
     if (H.nfar > 0)
