@@ -382,8 +382,9 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restri
 }
 
 // a pass kernel for M: M itself as a compile-time constant for the
-// squares 4, 9, ..., 64 (every M in 2D), else MB = the next of 4, 9, 16
-// above M (1D) or 64 (M > 64: the kernels take their direct form)
+// squares 4, 9, ..., 64 (2D with m = 2 to 8), else MB = the next of 4, 9,
+// 16 above M (1D, and m = 1) or 64 (M > 64, 2D with m >= 9: the kernels
+// take their direct form)
 #define FL_MB_LAUNCH(KER, GRID, BLOCK, ...)                                              \
     do {                                                                                 \
         const dim3 g_((unsigned)(GRID)), b_(BLOCK);                                      \
