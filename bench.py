@@ -969,7 +969,9 @@ def cluster_leg(args):
     Chebyshev interpolation, no dense matrix) on unit disks, s = 0.75,
     f = 1, interior DOFs, eta = 2, leaves of 32 DOFs, m = 6 and 8: assembly
     and Jacobi-PCG (to 1e-10) times, device bytes, product time and energy
-    error against the closed form.  On the disks of ~3.2e4 and ~2e5
+    error against the closed form; m = 6 also with the blocks kept in FP32
+    (precision FL_MIXED: assembled in FP64, rounded once, products and sums
+    in FP64).  On the disks of ~3.2e4 and ~2e5
     triangles the dense FP64 path runs beside it; the ~4e5-triangle disk
     (n ~ 2e5) has a dense matrix larger than the device memory."""
     import torch
@@ -977,7 +979,7 @@ def cluster_leg(args):
     s = 0.75
     fu = ball_fu(s)
     out = {"workload": "unit disk, s=0.75, f=1, interior DOFs; cluster method assembled from the mesh, eta=2, "
-                       "leaf 32, m in {6, 8}; dense FP64 path beside it where its matrix fits",
+                       "leaf 32, m in {6, 8}, m = 6 also with FP32 blocks; dense FP64 path beside it where its matrix fits",
            "device_bytes": torch.cuda.mem_get_info()[1]}
     o = F.make_opts(dof_mode="interior")
 
@@ -1008,8 +1010,9 @@ def cluster_leg(args):
                           "matvec_ms": round(t_mv / 10, 4), "bytes": n * h.ld * 8,
                           "energy_error": math.sqrt(max(fu - float(torch.dot(b, u)), 0.0))}
             del b, u, x, y
-        for m in (6, 8):
-            n2, t_asm = timed(lambda: h.cluster_assemble(s, o, m=m, eta=2.0, leaf=32))
+        om = F.make_opts(dof_mode="interior", precision="mixed")
+        for m, oc, name in ((6, o, "cluster_m6"), (8, o, "cluster_m8"), (6, om, "cluster_m6_fp32")):
+            n2, t_asm = timed(lambda: h.cluster_assemble(s, oc, m=m, eta=2.0, leaf=32))
             n = n2
             info = h.cluster_info()
             st = h.stats()
@@ -1021,7 +1024,7 @@ def cluster_leg(args):
             y = torch.empty_like(x)
             h.cluster_matvec(x, y)
             _, t_mv = timed(lambda: [h.cluster_matvec(x, y) for _ in range(10)])
-            r["cluster_m%d" % m] = {
+            r[name] = {
                 "assemble_ms": round(t_asm, 2), "near_field_kernels_ms": round(st.t_assemble_ms, 2),
                 "cg_iters": it, "cg_ms": round(t_sol, 2), "matvec_ms": round(t_mv / 10, 4),
                 "bytes": info["bytes"], "near_entries": info["near_entries"], "far_pairs": info["far_pairs"],

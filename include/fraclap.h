@@ -305,8 +305,12 @@ int fl_cluster_build(fl_handle *h, int32_t m, double eta, int32_t leaf);
  * the (m+1)-point rule.  A cell's anchor is its DOF vertex first in tree
  * order; a cell without one takes the anchor of its facet neighbour of
  * smallest index that has one and widens that DOF's support box.
- * opts: as fl_assemble, but precision FL_FP64 and surrogate 0 only
- * (FL_EINVAL otherwise); no symmetry reduction (FL_EINVAL).  FL_EMESH for a
+ * opts: as fl_assemble, but surrogate 0 only (FL_EINVAL otherwise);
+ * precision FL_FP64, or FL_MIXED: the kernel and near blocks are assembled
+ * in FP64, rounded once to FP32 and kept so (the FP64 copies freed), the
+ * product multiplies and sums in FP64 -- half the bytes per product, the
+ * operator still symmetric; the Jacobi diagonal stays FP64.  No symmetry
+ * reduction (FL_EINVAL).  FL_EMESH for a
  * mesh component without any DOF.  Replaces (and frees) a dense matrix of
  * an earlier fl_assemble; afterwards fl_cluster_matvec, fl_solve_cluster,
  * fl_load_vector_one and fl_dofs work, the dense-matrix calls return

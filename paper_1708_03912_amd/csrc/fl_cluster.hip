@@ -7,6 +7,8 @@
 // fl_cluster_api.hip.  All FP64, fixed summation orders.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fl_internal.hpp"
 #include "fl_math.hpp"
 
@@ -279,9 +281,10 @@ __global__ __launch_bounds__(64) void h_up_kernel(HDev H, const int4* __restrict
 // so a pair waits for one memory latency; the cluster vector is broadcast
 // from the lanes that hold it.  Larger M: 16 loads of the block column in
 // flight before their products.
-template <int MB>
-__device__ __forceinline__ void far_fetch(const HDev& H, int M, long long p, int t, int ac, double (&k)[MB], double& x) {
-    const double* Kp = H.Kb + p * M * M + ac;
+template <int MB, typename KT>
+__device__ __forceinline__ void far_fetch(const HDev& H, const KT* __restrict__ Kb, int M, long long p, int t, int ac,
+                                          double (&k)[MB], double& x) {
+    const KT* Kp = Kb + p * M * M + ac;
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
         const double u = Kp[min(b, M - 1) * M];
@@ -291,8 +294,8 @@ __device__ __forceinline__ void far_fetch(const HDev& H, int M, long long p, int
     __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products that follow
 }
 
-template <int MB, bool EX>
-__global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
+template <int MB, bool EX, typename KT>
+__device__ __forceinline__ void far_body(const HDev& H, const KT* __restrict__ Kb) {
     __shared__ double red[4][64];
     const int c = blockIdx.x;
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
             int t = H.fdst[pb];
             for (long long p = pb; p < pe; p += 4) {
                 const int tn = H.fdst[min(p + 4, pe - 1)];
-                far_fetch<MB>(H, M, p, t, ac, k, x);
+                far_fetch<MB>(H, Kb, M, p, t, ac, k, x);
 #pragma unroll
                 for (int b = 0; b < MB; ++b) acc = fma(k[b], lane_bcast(x, b), acc);
                 t = tn;
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
         if (a < M) {
             // the sum keeps the order b = 0, 1, ...
             for (long long p = H.fptr[c] + g; p < H.fptr[c + 1]; p += 4) {
-                const double* Kp = H.Kb + p * M * M;
+                const KT* Kp = Kb + p * M * M;
                 const double* xt = H.xh + (long long)H.fdst[p] * M;
                 int b = 0;
                 for (; b + 16 <= M; b += 16) {
@@ -344,6 +347,17 @@ __global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
         if (g == 0 && a < M) H.yh[(long long)c * M + a] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
         __syncthreads();
     }
+}
+
+// the far field with the kernel blocks in FP64 or (FP32 representation) in
+// FP32, products and sums in FP64
+template <int MB, bool EX>
+__global__ __launch_bounds__(256) void h_far_kernel(HDev H) {
+    far_body<MB, EX, double>(H, H.Kb);
+}
+template <int MB, bool EX>
+__global__ __launch_bounds__(256) void h_far32_kernel(HDev H) {
+    far_body<MB, EX, float>(H, H.Kbf);
 }
 
 // clusters of one level (>= 1): yh[c][b] += sum_a T_c[b][a] yh[parent][a]
@@ -419,8 +433,8 @@ __global__ __launch_bounds__(64) void h_down_kernel(HDev H, const int4* __restri
 // block waits for one memory latency; the row sum runs over the columns in
 // order.  Larger leaves: rows in chunks of 32, four partial sums over the
 // columns.
-template <int MB, bool EX>
-__global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
+template <int MB, bool EX, typename KT>
+__device__ __forceinline__ void leaf_body(const HDev& H, const KT* __restrict__ An, double C, double* __restrict__ y) {
     __shared__ double red[8][32];
     const int li = blockIdx.x;
     const int c = H.leaf[li];
@@ -455,7 +469,7 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
                 const int en = min(e + 8, ee - 1);
                 const int2 rgn = H.nrng[en];
                 const long long offn = H.noff[en];
-                const double* blk = H.An + off + ic;
+                const KT* blk = An + off + ic;
                 double b[32];
 #pragma unroll
                 for (int j = 0; j < 32; ++j) {
@@ -494,7 +508,7 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
             for (int e = H.lnptr[li] + g; e < H.lnptr[li + 1]; e += 8) {
                 const int t = H.ndst[e];
                 const int rt = H.clo[t], nt = H.chi[t] - rt;
-                const double* blk = H.An + H.noff[e] + i;
+                const KT* blk = An + H.noff[e] + i;
                 const double* xt = H.xp + rt;
                 // four partial sums over columns j mod 4: four loads in flight
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -520,6 +534,17 @@ __global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, doubl
         }
         __syncthreads();
     }
+}
+
+// the leaves with the near blocks in FP64 or (FP32 representation) in FP32,
+// products and sums in FP64
+template <int MB, bool EX>
+__global__ __launch_bounds__(256) void h_leaf_out_kernel(HDev H, double C, double* __restrict__ y) {
+    leaf_body<MB, EX, double>(H, H.An, C, y);
+}
+template <int MB, bool EX>
+__global__ __launch_bounds__(256) void h_leaf_out32_kernel(HDev H, double C, double* __restrict__ y) {
+    leaf_body<MB, EX, float>(H, H.Anf, C, y);
 }
 
 // ------------------------------------------- far part of the self terms
@@ -666,7 +691,10 @@ void h_passes(const HDev& H, const int* const* up_lists, const int* up_counts, i
     if (!leaf_done) hipLaunchKernelGGL(h_up_leaf_kernel, dim3((unsigned)H.nleaf), dim3(64), 0, st, H);
     for (int l = 0; l < n_up; ++l)
         if (up_counts[l] > 0) FL_MB_LAUNCH(h_up_kernel, up_counts[l], 64, H, (const int4*)up_lists[l]);
-    FL_MB_LAUNCH(h_far_kernel, H.nc, 256, H);
+    if (H.Kbf)
+        FL_MB_LAUNCH(h_far32_kernel, H.nc, 256, H);
+    else
+        FL_MB_LAUNCH(h_far_kernel, H.nc, 256, H);
     for (int l = 0; l < n_down; ++l)
         if (down_counts[l] > 0) FL_MB_LAUNCH(h_down_kernel, down_counts[l], 64, H, (const int4*)down_lists[l]);
 }
@@ -724,13 +752,30 @@ void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_co
     if (H.n == 0) return;
     hipLaunchKernelGGL(h_gather_kernel, dim3(nb256(H.n)), dim3(256), 0, st, H, x);
     h_passes(H, up_lists, up_counts, n_up, down_lists, down_counts, n_down, 0, st);
-    FL_MB_LAUNCH(h_leaf_out_kernel, H.nleaf, 256, H, C, y);
+    if (H.Anf)
+        FL_MB_LAUNCH(h_leaf_out32_kernel, H.nleaf, 256, H, C, y);
+    else
+        FL_MB_LAUNCH(h_leaf_out_kernel, H.nleaf, 256, H, C, y);
 }
 #undef FL_MB_LAUNCH
 
 }  // namespace fl
 
 namespace fl {
+namespace {
+__global__ __launch_bounds__(256) void h_to_f32_kernel(const double* __restrict__ a, float* __restrict__ b,
+                                                       long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+}  // namespace
+
+void launch_h_to_f32(const double* a, float* b, long long n, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(h_to_f32_kernel, dim3((unsigned)std::min<long long>((n + 255) / 256, 1 << 20)), dim3(256), 0,
+                           st, a, b, n);
+}
+
 namespace {
 __global__ __launch_bounds__(256) void h_diag_kernel(const double* __restrict__ A, long long lda, long long n,
                                                      double* __restrict__ d) {

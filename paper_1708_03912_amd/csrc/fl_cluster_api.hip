@@ -70,6 +70,18 @@ int hm_alloc(fl_handle* h, T** p, size_t count) {
     return FL_OK;
 }
 
+// frees one device allocation of the representation before the others
+void hm_free(fl_handle* h, void* p, size_t bytes) {
+    auto& b = h->hm.bufs;
+    for (size_t i = 0; i < b.size(); ++i)
+        if (b[i] == p) {
+            (void)hipFree(p);
+            b.erase(b.begin() + (long)i);
+            h->hm.bytes -= bytes;
+            return;
+        }
+}
+
 void hm_release(fl_handle* h) {
     for (void* p : h->hm.bufs) (void)hipFree(p);
     if (h->hm.hsc) (void)hipHostFree(h->hm.hsc);
@@ -583,7 +595,11 @@ int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t 
     else fl_default_opts(&o);
     int rc = check_cluster_args(h, m, eta, leaf);
     if (rc) return rc;
-    if (o.precision != FL_FP64) return cfail(h, FL_EINVAL, "the cluster near field is assembled in FP64");
+    if (o.precision != FL_FP64 && o.precision != FL_MIXED)
+        return cfail(h, FL_EINVAL, "precision must be FL_FP64 or FL_MIXED");
+    // FL_MIXED: the blocks are assembled in FP64 and kept in FP32
+    const bool f32 = o.precision == FL_MIXED;
+    o.precision = FL_FP64;
     if (o.surrogate != 0) return cfail(h, FL_EINVAL, "the cluster near field takes the exact rules (surrogate = 0)");
     if (o.deterministic) return cfail(h, FL_EINVAL, "the repeatable assembly is for fl_assemble");
     HIPCHK(hipSetDevice(h->device));
@@ -719,6 +735,26 @@ int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t 
         launch_near_diag(nm, n, Hm.d, h->stream);
         HIPCHK(hipGetLastError());
         Hm.nm = nm;
+        if (f32) {
+            // FP32 representation: the kernel and near blocks rounded once
+            // from their FP64 assembly; the FP64 copies are released
+            float *kbf = nullptr, *anf = nullptr;
+            const long long kb_n = H.nfar * H.M * H.M;
+            if ((rc = hm_alloc(h, &kbf, (size_t)kb_n)) || (rc = hm_alloc(h, &anf, (size_t)Hm.near_entries))) {
+                hm_release(h);
+                return rc;
+            }
+            launch_h_to_f32(H.Kb, kbf, kb_n, h->stream);
+            launch_h_to_f32(H.An, anf, Hm.near_entries, h->stream);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(h->stream));
+            hm_free(h, H.Kb, sizeof(double) * (size_t)kb_n);
+            hm_free(h, H.An, sizeof(double) * (size_t)Hm.near_entries);
+            H.Kb = nullptr;
+            H.An = nullptr;
+            H.Kbf = kbf;
+            H.Anf = anf;
+        }
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     h->st = st;

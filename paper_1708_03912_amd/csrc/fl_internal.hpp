@@ -362,6 +362,8 @@ struct HDev {
     const int* fsrc;
     const int* fdst;
     double* Kb;             // nfar x M x M kernel blocks, column by column
+    const float* Kbf;       // FP32 representation: the kernel blocks and
+    const float* Anf;       // the near blocks rounded to FP32 (else null)
     long long nnear;        // near leaf pairs, grouped by the first leaf
     const int* lnptr;       // nleaf + 1 (by leaf index)
     const int* nsrc;
@@ -385,6 +387,8 @@ void launch_h_self_far(const HDev& H, const ElemDev& E, int T, const int* lc_ptr
                        const int* const* down_lists, const int* down_counts, int n_down, double C, double* S,
                        hipStream_t st);
 void launch_h_diag(const double* A, long long lda, long long n, double* d, hipStream_t st);
+// b[i] = (float)a[i], i < n (round to nearest)
+void launch_h_to_f32(const double* a, float* b, long long n, hipStream_t st);
 void launch_h_matvec(const HDev& H, const int* const* up_lists, const int* up_counts, int n_up,
                      const int* const* down_lists, const int* down_counts, int n_down, double C, const double* x,
                      double* y, hipStream_t st);
