@@ -752,6 +752,7 @@ int fl_cluster_assemble(fl_handle* h, double s, const fl_opts* opts_in, int32_t 
             hm_free(h, H.An, sizeof(double) * (size_t)Hm.near_entries);
             H.Kb = nullptr;
             H.An = nullptr;
+            Hm.nm.An = nullptr;  // the map's FP64 target is gone
             H.Kbf = kbf;
             H.Anf = anf;
         }
